@@ -1,0 +1,369 @@
+#!/usr/bin/env python3
+"""Benchmark: FP64 polar AC-OPF callback sets per second on one MI355X.
+
+One callback set = (f, grad f, c, J values, H values) at one (x, y, sigma),
+the five NLPModels callbacks an interior-point solver calls per iteration.
+
+Headline workload: the plain single-instance callbacks on a 10,000-bus
+synthetic network (13,500 branches, 2,000 generators), one step = 1,000
+callback sets at distinct seeded (x, y) pairs, launched back to back from a
+HIP graph.  Inputs rotate over 256 pre-generated pairs and outputs over 64
+buffer sets, so the working set (~0.7 GB) exceeds the 256 MB Infinity Cache
+and the roofline is the HBM one.
+
+Also measured in the same run (the "extra" object): the batched form on the
+64-scenario uneven mix (8 networks of 500 to 20,000 buses x 8 load seeds,
+one persistent launch) against the plain per-instance launches, the
+multi-period model (2,000 buses x 48 periods) and the N-1 contingency model
+(1,000 buses + 200 outage copies).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "callback sets/s (f,∇f,c,J,∇²L) FP64 batched vs plain; % of HBM roofline"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def algorithmic_bytes(cs: dict, dims, T: int = 1, K: int = 0, mp_loads: bool = False) -> int:
+    """Bytes one callback set must move at least: every input read once and
+    every output written once.  Reads: x (8n), y (8m), sigma; branch data
+    (8 admittance terms + rate^2 + two int32 buses = 80 B); bus loads and
+    shunts (32 B, loads per period when they vary); generator costs and bus
+    (28 B); adjacency (half-edges, bus pointers, generator lists); outage
+    list.  Writes: f, grad f (8n), c (8m), J (8 nnzj), H (8 nnzh)."""
+    n, m, nnzj, nnzh = dims
+    N, L, G = cs["n_bus"], cs["n_branch"], cs["n_gen"]
+    reads = 8 * n + 8 * m + 8
+    reads += 80 * L
+    reads += 16 * N * (T if mp_loads else 1) + 16 * N
+    reads += 28 * G
+    reads += 4 * 2 * L + 4 * (N + 1) * 2 + 4 * G
+    reads += 4 * K
+    writes = 8 + 8 * n + 8 * m + 8 * nnzj + 8 * nnzh
+    return int(reads + writes)
+
+
+def _cpu_model_name() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+class PlainRunner:
+    """Back-to-back plain callback sets of one model, captured in a HIP graph."""
+
+    def __init__(self, model, xs, ys, n_out: int, sets: int, torch):
+        self.torch = torch
+        self.model = model
+        dev = torch.device("cuda", model.device)
+        self.xs, self.ys = xs, ys
+        self.outs = [(torch.empty(1, dtype=torch.float64, device=dev),
+                      torch.empty(model.n, dtype=torch.float64, device=dev),
+                      torch.empty(model.m, dtype=torch.float64, device=dev),
+                      torch.empty(model.nnzj, dtype=torch.float64, device=dev),
+                      torch.empty(model.nnzh, dtype=torch.float64, device=dev)) for _ in range(n_out)]
+        self.sets = sets
+        self.graph = None
+
+    def enqueue(self, start: int = 0):
+        for k in range(self.sets):
+            j = start + k
+            x, y = self.xs[j % len(self.xs)], self.ys[j % len(self.ys)]
+            f, g, c, jv, hv = self.outs[j % len(self.outs)]
+            self.model.eval_set(x, y, 1.0, f, g, c, jv, hv)
+
+    def capture(self):
+        torch = self.torch
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.enqueue()  # warm the code path outside capture
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=s):
+            self.enqueue()
+        torch.cuda.synchronize()
+
+    def step(self):
+        self.graph.replay()
+
+
+def time_steps(torch, fn, steps: int, warmup: int):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def bench_headline(args, torch, opf, synth, log):
+    cs = synth.network(10000, 13500, 2000, 1)
+    model = opf.Model(cs, device=0)
+    dims = (model.n, model.m, model.nnzj, model.nnzh)
+    dev = torch.device("cuda", 0)
+    log(f"headline model: n={model.n} m={model.m} nnzj={model.nnzj} nnzh={model.nnzh}")
+    n_in = args.inputs
+    xs = [torch.as_tensor(synth.point(cs, (101, r)), device=dev) for r in range(n_in)]
+    ys = [torch.as_tensor(synth.multipliers(model.m, (101, r)), device=dev) for r in range(n_in)]
+    log(f"generated {n_in} seeded (x, y) pairs")
+    runner = PlainRunner(model, xs, ys, n_out=64, sets=args.sets_per_step, torch=torch)
+    runner.capture()
+    secs, wall = time_steps(torch, runner.step, args.steps, args.warmup)
+    n_sets = args.steps * args.sets_per_step
+    per_set = secs / n_sets
+    bytes_set = algorithmic_bytes(cs, dims)
+    log(f"headline: {n_sets} sets in {secs * 1e3:.2f} ms (GPU events), {wall * 1e3:.2f} ms wall")
+    return dict(cs=cs, model=model, dims=dims, xs=xs, ys=ys, secs=secs, wall=wall, n_sets=n_sets,
+                per_set=per_set, bytes_set=bytes_set)
+
+
+def bench_cpu_baseline(h, synth, oracle, budget_s: float, log):
+    cs = h["cs"]
+    xs = [synth.point(cs, (101, r)) for r in range(4)]
+    ys = [synth.multipliers(h["model"].m, (101, r)) for r in range(4)]
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.evaluate(cs, xs[done % 4], ys[done % 4], 1.0)
+        done += 1
+        el = time.perf_counter() - t0
+        if (el >= budget_s and done >= 3) or done >= 1000:
+            break
+    log(f"oracle: {done} sets in {el:.1f} s")
+    return dict(value=done / el, unit="sets/s", cores=1, kind="oracle",
+                sample=f"{done} callback sets of the 10k-bus workload (x, y seeds (101, 0..3)), "
+                       f"single-threaded C oracle, {el:.1f} s on {_cpu_model_name()}")
+
+
+def bench_batch(args, torch, opf, synth, log):
+    """The 64-scenario uneven mix: one persistent launch vs 64 plain launches."""
+    dev = torch.device("cuda", 0)
+    nets, models, plain_models, inst_model, pds, qds = [], [], [], [], [], []
+    for j, N in enumerate(synth.BATCH_SIZES):
+        cs = synth.network(N, int(round(1.35 * N)), int(round(0.2 * N)), 300 + j)
+        nets.append(cs)
+        models.append(opf.Model(cs, device=0))
+        for s in range(8):
+            pd, qd = synth.scenario_loads(cs, 3000 + 8 * j + s)
+            inst_model.append(j)
+            pds.append(pd)
+            qds.append(qd)
+            c2 = dict(cs)
+            c2["pd"], c2["qd"] = pd, qd
+            plain_models.append(opf.Model(c2, device=0))
+    batch = opf.Batch(models, inst_model, np.concatenate(pds), np.concatenate(qds))
+    n_inst = batch.n_inst
+    X = torch.empty(batch.n, dtype=torch.float64, device=dev)
+    Y = torch.empty(batch.m, dtype=torch.float64, device=dev)
+    for i in range(n_inst):
+        cs = nets[inst_model[i]]
+        X[batch.xoff[i]:batch.xoff[i + 1]] = torch.as_tensor(synth.point(cs, (103, i)), device=dev)
+        Y[batch.coff[i]:batch.coff[i + 1]] = torch.as_tensor(
+            synth.multipliers(int(batch.coff[i + 1] - batch.coff[i]), (103, i)), device=dev)
+    sig = torch.ones(n_inst, dtype=torch.float64, device=dev)
+    F = torch.empty(n_inst, dtype=torch.float64, device=dev)
+    G = torch.empty(batch.n, dtype=torch.float64, device=dev)
+    C = torch.empty(batch.m, dtype=torch.float64, device=dev)
+    J = torch.empty(batch.nnzj, dtype=torch.float64, device=dev)
+    H = torch.empty(batch.nnzh, dtype=torch.float64, device=dev)
+    sched = batch.tune()
+    log(f"batch: {n_inst} instances, n={batch.n} m={batch.m} nnzj={batch.nnzj} nnzh={batch.nnzh}, "
+        f"tuned schedule tile_cap={sched[0]} wg_per_cu={sched[1]}")
+
+    def batched():
+        batch.eval(X, Y, sig, F, G, C, J, H)
+
+    reps = args.batch_reps
+    secs_b, _ = time_steps(torch, lambda: [batched() for _ in range(reps)], 3, 1)
+    per_launch = secs_b / (3 * reps)
+
+    # plain: the same 64 instances through the single-instance API, back to
+    # back on one stream, captured in one HIP graph
+    views = []
+    for i in range(n_inst):
+        sl = lambda off, a: a[int(off[i]):int(off[i + 1])]  # noqa: E731
+        views.append((sl(batch.xoff, X), sl(batch.coff, Y), F[i:i + 1], sl(batch.xoff, G), sl(batch.coff, C),
+                      sl(batch.joff, J), sl(batch.hoff, H)))
+
+    def plain():
+        for i in range(n_inst):
+            x, y, f, g, c, jv, hv = views[i]
+            plain_models[i].eval_set(x, y, 1.0, f, g, c, jv, hv)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plain()
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (F, G, C, J, H)]
+    batched()
+    torch.cuda.synchronize()
+    bitwise = all(torch.equal(a, b) for a, b in zip(ref, (F, G, C, J, H)))
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        plain()
+    torch.cuda.synchronize()
+    secs_p, _ = time_steps(torch, lambda: [graph.replay() for _ in range(reps)], 3, 1)
+    per_plain = secs_p / (3 * reps)
+    total_bytes = sum(algorithmic_bytes(nets[inst_model[i]], (
+        int(batch.xoff[i + 1] - batch.xoff[i]), int(batch.coff[i + 1] - batch.coff[i]),
+        int(batch.joff[i + 1] - batch.joff[i]), int(batch.hoff[i + 1] - batch.hoff[i]))) for i in range(n_inst))
+    # model data is shared by the 8 scenarios of a network: count it once
+    shared = sum(80 * c["n_branch"] + 16 * c["n_bus"] + 28 * c["n_gen"] + 4 * (2 * c["n_branch"] + 2 * c["n_bus"]
+                                                                          + 2 + c["n_gen"]) for c in nets)
+    total_bytes -= 7 * shared
+    log(f"batch: batched {per_launch * 1e6:.1f} us/launch, plain {per_plain * 1e6:.1f} us/64 sets, "
+        f"bitwise equal: {bitwise}")
+    out = dict(
+        workload="64 scenarios = 8 networks (500..20000 buses, L=1.35N, G=0.2N) x 8 load seeds",
+        batched_sets_per_s=n_inst / per_launch, plain_sets_per_s=n_inst / per_plain,
+        speedup=per_plain / per_launch, us_per_launch=per_launch * 1e6, bytes_per_launch=total_bytes,
+        achieved_gbs=total_bytes / per_launch / 1e9, frac=total_bytes / per_launch / 1e9 / HBM_PEAK_GBS,
+        schedule=dict(tile_cap=sched[0], wg_per_cu=sched[1]), bitwise_equal_to_plain=bool(bitwise))
+    batch.close()
+    for mdl in models + plain_models:
+        mdl.close()
+    return out
+
+
+def bench_model(torch, opf, synth, cs, opts, n_in, n_out, sets, log, label, T=1, K=0, mp_loads=False):
+    dev = torch.device("cuda", 0)
+    model = opf.Model(cs, device=0, **opts)
+    dims = (model.n, model.m, model.nnzj, model.nnzh)
+    xs = [torch.as_tensor(synth.point(cs, (104, r), n_periods=T, n_cont=K), device=dev) for r in range(n_in)]
+    ys = [torch.as_tensor(synth.multipliers(model.m, (104, r)), device=dev) for r in range(n_in)]
+    runner = PlainRunner(model, xs, ys, n_out=n_out, sets=sets, torch=torch)
+    runner.capture()
+    secs, _ = time_steps(torch, runner.step, 3, 1)
+    per = secs / (3 * sets)
+    b = algorithmic_bytes(cs, dims, T=T, K=K, mp_loads=mp_loads)
+    log(f"{label}: {per * 1e6:.1f} us/set, {b / per / 1e9:.0f} GB/s")
+    model.close()
+    return dict(n=dims[0], m=dims[1], nnzj=dims[2], nnzh=dims[3], sets_per_s=1.0 / per, us_per_set=per * 1e6,
+                bytes_per_set=b, achieved_gbs=b / per / 1e9, frac=b / per / 1e9 / HBM_PEAK_GBS)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sets-per-step", type=int, default=1000)
+    ap.add_argument("--inputs", type=int, default=256, help="distinct pre-generated (x, y) pairs")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle timing budget (0 = skip)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched / multi-period / N-1 legs")
+    ap.add_argument("--batch-reps", type=int, default=20)
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args()
+
+    def log(*a):
+        if not args.quiet:
+            print("[bench]", *a, file=sys.stderr, flush=True)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build evaluates each model on a single MI355X "
+              "(multi-GPU sharding is a design note, not implemented); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2510_12897_amd import opf, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    opf.lib()
+    h = bench_headline(args, torch, opf, synth, log)
+    sets_per_s = h["n_sets"] / h["secs"]
+    achieved = h["bytes_set"] / h["per_set"] / 1e9
+    result = {
+        "metric": METRIC,
+        "value": sets_per_s,
+        "unit": "sets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["secs"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain polar AC-OPF callback sets, 10000-bus synthetic network "
+                        "(13500 branches, 2000 generators), 1000 sets per step at seeded (x, y)",
+            "n": h["dims"][0], "m": h["dims"][1], "nnzj": h["dims"][2], "nnzh": h["dims"][3],
+            "sets_per_step": args.sets_per_step, "launch": "HIP graph of back-to-back plain launches",
+            "inputs_rotated": args.inputs, "outputs_rotated": 64,
+        },
+        "roofline": {
+            "kernel": "eval_set_kernel",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_launch": h["bytes_set"],
+            "us_per_launch": h["per_set"] * 1e6,
+        },
+    }
+    if not args.no_extra:
+        extra = {}
+        try:
+            extra["batch64"] = bench_batch(args, torch, opf, synth, log)
+        except Exception as e:  # a failing leg must not hide the headline line
+            extra["batch64"] = {"error": repr(e)}
+        try:
+            cs = synth.network(2000, 2700, 400, 2)
+            pd_t, qd_t = synth.mp_loads(cs, 48, 202)
+            extra["multiperiod_2k_x48"] = bench_model(
+                torch, opf, synth, cs, dict(n_periods=48, pd_t=pd_t, qd_t=qd_t, ramp_ratio=0.2), 8, 4, 20,
+                log, "multi-period", T=48, mp_loads=True)
+        except Exception as e:
+            extra["multiperiod_2k_x48"] = {"error": repr(e)}
+        try:
+            cs = synth.network(1000, 1350, 200, 31)
+            out = synth.outages(cs, 200, 32)
+            extra["contingency_1k_x201"] = bench_model(
+                torch, opf, synth, cs, dict(n_cont=200, outaged=out), 4, 2, 10, log, "N-1 copies", K=200)
+        except Exception as e:
+            extra["contingency_1k_x201"] = {"error": repr(e)}
+        result["extra"] = extra
+    if args.cpu_seconds > 0:
+        from oracle import oracle
+
+        result["cpu_baseline"] = bench_cpu_baseline(h, synth, oracle, args.cpu_seconds, log)
+    h["model"].close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,248 @@
+/*
+ * opf.h -- C-ABI of the MI355X polar AC-OPF callback library (libopf.so).
+ *
+ * The library evaluates, on the GPU and in FP64, the callbacks an
+ * interior-point solver calls every iteration (the NLPModels template of
+ * the paper, Listing 1: obj, grad!, cons!, jac!, hess! with obj_weight) for
+ * the polar AC optimal power flow model the paper builds in Listing 3, its
+ * multi-period variant with generator ramp limits (Sec. III-C2) and a
+ * security-constrained variant with N-1 branch-outage copies that share
+ * generator set-points (the contingency structure of the GOC3 model,
+ * Sec. III-C4).
+ *
+ * Conventions
+ *  - Indices are 0-based int32; counts are int64; values are IEEE FP64.
+ *  - Host structures (opf_case, opf_opts) are read during the call only.
+ *  - Every per-call buffer (x, y, outputs, structure arrays) is a
+ *    caller-owned DEVICE pointer on the model's device, contiguous.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Evaluation calls
+ *    only enqueue kernels: results are valid once the stream has been
+ *    synchronised.  No call synchronises the host or copies between host
+ *    and device, except opf_model_create / opf_batch_create (one upload).
+ *  - Every function returns 0 (OPF_OK) or a negative error code; the text of
+ *    the last error on the calling thread is returned by opf_last_error().
+ *    Faults inside a kernel surface at the next synchronisation.  NaN or Inf
+ *    inside x or y propagate to the outputs and are not reported.
+ *  - One model (or batch) must not be evaluated concurrently from two
+ *    streams; different models are independent.
+ *
+ * Variable vector x (n entries), blocks in this order (Listing 3):
+ *    va [N*P] | vm [N*P] | pg [G*Pg] | qg [G*P] | p [2L*P] | q [2L*P]
+ *  P = replicas: n_periods (multi-period) or n_cont + 1 (contingency copies,
+ *  copy 0 is the base case), else 1; Pg = 1 with contingency copies (pg is
+ *  shared), else P.  Inside a block the entity index runs fastest, then the
+ *  replica.  Arc a < L is the from-side arc of branch a (at f_bus), arc L+l
+ *  the to-side arc of branch l (at t_bus).
+ *
+ * Constraint vector c (m entries), blocks in Listing 3 order, each
+ * entity-fastest over the replicas:
+ *    ref [R] | p_fr [L] | q_fr [L] | p_to [L] | q_to [L] | angle [L] |
+ *    balance_p [N] | balance_q [N] | thermal_fr [L] | thermal_to [L]
+ *  followed, for n_periods = T > 1, by ramp rows [G*(T-1)].
+ *    ref          va_r                                     = 0
+ *    flow         p_a - F_a(vm_f, vm_t, va_f - va_t)        = 0   (pi model)
+ *    angle        va_f - va_t                   in [angmin, angmax]
+ *    balance_p    pd + gs vm^2 + sum_arcs p_a - sum_gens pg = 0
+ *    balance_q    qd - bs vm^2 + sum_arcs q_a - sum_gens qg = 0
+ *    thermal      p_a^2 + q_a^2 - rate_a^2                 <= 0
+ *    ramp         pg_{k,t} - pg_{k,t-1}     in +-ramp_ratio * pmax_k
+ *  In contingency copy s >= 1 the branch outaged_branch[s-1] carries no
+ *  flow (its admittance terms are zero; its rows and pattern entries stay)
+ *  and its angle row is unbounded.
+ *
+ * Objective f = sum over pg variables of c2 pg^2 + c1 pg + c0.
+ *
+ * Sparsity patterns are structural (independent of values), fixed at model
+ * creation:
+ *  - Jacobian: COO sorted by (row, col), unique.
+ *  - Hessian of the Lagrangian obj_weight * hess f + sum_i y_i hess c_i:
+ *    lower triangle (row >= col), sorted by (row, col), unique.
+ */
+#ifndef OPF_H
+#define OPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+enum {
+    OPF_OK = 0,
+    OPF_E_ARG = -1,    /* NULL pointer, size or index out of range          */
+    OPF_E_CASE = -2,   /* the network data fails validation                 */
+    OPF_E_NOMEM = -3,  /* device or host allocation failed                  */
+    OPF_E_HIP = -4,    /* HIP runtime or kernel launch error                */
+    OPF_E_STATE = -5   /* destroyed or mismatched handle                    */
+};
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *opf_last_error(void);
+
+/* ---------------------------------------------------------------- input */
+typedef struct {
+    int32_t n_bus, n_branch, n_gen, n_ref;
+    const double *pd, *qd, *gs, *bs, *vmin, *vmax;        /* [n_bus]      */
+    const int32_t *ref_bus;                               /* [n_ref]      */
+    const int32_t *f_bus, *t_bus;                         /* [n_branch]   */
+    const double *r, *x, *b, *tap, *shift, *rate_a;       /* [n_branch]   */
+    const double *angmin, *angmax;                        /* [n_branch]   */
+    const int32_t *gen_bus;                               /* [n_gen]      */
+    const double *pmin, *pmax, *qmin, *qmax, *c2, *c1, *c0; /* [n_gen]    */
+} opf_case;
+/* Branch data is per unit with the pi model of the paper's formulation
+ * (PowerModels): series impedance r + jx, total line charging b split b/2
+ * per side, an ideal transformer of ratio tap and phase shift `shift`
+ * (radians) on the from side. */
+
+typedef struct {
+    int32_t n_periods;          /* >= 1; 1 = static model                   */
+    const double *pd_t, *qd_t;  /* [n_periods*n_bus] bus fastest; NULL =    */
+                                /* use the case loads in every period       */
+    double ramp_ratio;          /* ramp bound = ramp_ratio * pmax (T > 1)   */
+    int32_t n_cont;             /* contingency copies (0 = none); cannot be */
+                                /* combined with n_periods > 1              */
+    const int32_t *outaged_branch; /* [n_cont] branch out in copy s+1       */
+} opf_opts;
+/* opts may be NULL: static model. */
+
+/* Maximum number of branches at one bus. */
+#define OPF_MAX_DEGREE 1024
+
+/* ------------------------------------------------ host-only helpers */
+/* These run on the host only and need no GPU. */
+
+/* Validate the case and options.  OPF_E_CASE with a message naming the
+ * first offending item (bus, branch, generator, outage index, impedance,
+ * tap, bound order, degree limit, size limits); OPF_E_ARG for NULL arrays. */
+int opf_case_validate(const opf_case *cs, const opf_opts *opts);
+
+/* Sizes of the model: variables n, constraints m, Jacobian and Hessian
+ * nonzeros.  Any output pointer may be NULL. */
+int opf_case_dims(const opf_case *cs, const opf_opts *opts,
+                  int64_t *n, int64_t *m, int64_t *nnzj, int64_t *nnzh);
+
+/* The Jacobian and Hessian patterns into HOST buffers of nnzj / nnzh
+ * int32 entries (any may be NULL). */
+int opf_case_structure(const opf_case *cs, const opf_opts *opts,
+                       int32_t *jrows, int32_t *jcols, int32_t *hrows, int32_t *hcols);
+
+/* Variable bounds, constraint bounds and the starting point (vm = 1, all
+ * else 0; Listing 3) into HOST buffers of n, n, m, m, n doubles (any may be
+ * NULL).  Infinite bounds are +-INFINITY. */
+int opf_case_bounds(const opf_case *cs, const opf_opts *opts,
+                    double *lvar, double *uvar, double *lcon, double *ucon, double *x0);
+
+/* ---------------------------------------------------------------- model */
+typedef struct opf_model_s *opf_model;
+
+/* Device memory hook for model and batch storage (default hipMalloc /
+ * hipFree).  alloc returns NULL on failure, which makes create fail with
+ * OPF_E_NOMEM.  Applies to handles created afterwards; pass NULLs to
+ * restore the default. */
+void opf_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
+                       void (*release)(void *ptr, void *ctx), void *ctx);
+
+/* Validate, derive branch admittance terms, adjacency and pattern on the
+ * host, and upload everything to `device` in one copy.  The only call that
+ * moves data from host to device.  *out receives the handle. */
+int opf_model_create(const opf_case *cs, const opf_opts *opts, int device, opf_model *out);
+
+/* Free the model's device memory (synchronises the device first).  NULL is
+ * accepted.  The handle is invalid afterwards. */
+int opf_model_destroy(opf_model model);
+
+int opf_model_dims(opf_model model, int64_t *n, int64_t *m, int64_t *nnzj, int64_t *nnzh);
+
+/* Offset and length of a variable or constraint block, the named handles
+ * the paper's model builder returns (vars, cons; Sec. III-C1). */
+enum {
+    OPF_VAR_VA = 0, OPF_VAR_VM, OPF_VAR_PG, OPF_VAR_QG, OPF_VAR_P, OPF_VAR_Q,
+    OPF_CON_REF = 16, OPF_CON_P_FR, OPF_CON_Q_FR, OPF_CON_P_TO, OPF_CON_Q_TO,
+    OPF_CON_ANGLE, OPF_CON_BAL_P, OPF_CON_BAL_Q, OPF_CON_THERMAL_FR,
+    OPF_CON_THERMAL_TO, OPF_CON_RAMP
+};
+int opf_model_blocks(opf_model model, int32_t which, int64_t *offset, int64_t *len);
+
+/* Bounds and starting point into device buffers (n, n, m, m, n doubles;
+ * any may be NULL). */
+int opf_bounds(opf_model model, double *lvar, double *uvar, double *lcon, double *ucon,
+               double *x0, void *stream);
+
+/* ------------------------------------------------------------ callbacks */
+/* obj: *f (one device double) = f(x).                         (Listing 1) */
+int opf_obj(opf_model model, const double *x, double *f, void *stream);
+/* grad!: g[n] = grad f(x), dense.                                         */
+int opf_grad(opf_model model, const double *x, double *g, void *stream);
+/* cons!: c[m] = c(x).                                                     */
+int opf_cons(opf_model model, const double *x, double *c, void *stream);
+/* jac!: pattern rows/cols (int32[nnzj]) and values vals[nnzj] at x.       */
+int opf_jac_structure(opf_model model, int32_t *rows, int32_t *cols, void *stream);
+int opf_jac_coord(opf_model model, const double *x, double *vals, void *stream);
+/* hess!: lower-triangle pattern and values of
+ *   obj_weight * hess f(x) + sum_i y_i hess c_i(x),  y[m].                */
+int opf_hess_structure(opf_model model, int32_t *rows, int32_t *cols, void *stream);
+int opf_hess_coord(opf_model model, const double *x, const double *y, double obj_weight,
+                   double *vals, void *stream);
+
+/* All five callbacks in one launch; bitwise equal to the separate calls.
+ * Any output may be NULL (skipped); y may be NULL only when hvals is. */
+int opf_eval_set(opf_model model, const double *x, const double *y, double obj_weight,
+                 double *f, double *g, double *c, double *jvals, double *hvals, void *stream);
+
+/* out[n] = J(x)^T v for v[m]: the vector-Jacobian product of the
+ * constraints, each entry gathered in a fixed order (no atomics). */
+int opf_jtprod(opf_model model, const double *x, const double *v, double *out, void *stream);
+
+/* ---------------------------------------------------------------- batch */
+/* Many instances of possibly different networks evaluated by one
+ * persistent kernel launch (batched AC-OPF is the paper's stated future
+ * work, Sec. VI).  Instance j uses model inst_model[j] (static,
+ * multi-period or contingency) with its own loads: inst_pd / inst_qd hold
+ * the concatenated per-instance load arrays, n_bus entries per instance
+ * (n_periods * n_bus, bus fastest, for a multi-period model); NULL = every
+ * instance uses its model's own loads.  The models must stay alive while
+ * the batch exists. */
+typedef struct opf_batch_s *opf_batch;
+
+int opf_batch_create(const opf_model *models, int32_t n_models, const int32_t *inst_model,
+                     const double *inst_pd, const double *inst_qd, int32_t n_inst,
+                     opf_batch *out);
+int opf_batch_destroy(opf_batch batch);
+
+/* Per-instance offsets (n_inst+1 int64 each, host buffers; any may be NULL)
+ * into the concatenated X (variables), C (constraints; also Y),
+ * J and H value arrays.  Instance j's objective goes to F[j]. */
+int opf_batch_offsets(opf_batch batch, int64_t *xoff, int64_t *coff, int64_t *joff,
+                      int64_t *hoff);
+
+/* Time the candidate schedules (tile capacity, workgroups per CU) on this
+ * batch and keep the fastest in the handle.  Results of opf_batch_eval do
+ * not depend on the schedule.  Synchronises `stream`. */
+int opf_batch_tune(opf_batch batch, void *stream);
+
+/* The schedule in use: tile capacity (half-edges per bus tile) and
+ * persistent workgroups per compute unit. */
+int opf_batch_schedule(opf_batch batch, int32_t *tile_cap, int32_t *wg_per_cu);
+
+/* Force a schedule: the smallest candidate tile capacity >= tile_cap (the
+ * largest if none is) and wg_per_cu in [1, 64] (else OPF_E_ARG). */
+int opf_batch_set_schedule(opf_batch batch, int32_t tile_cap, int32_t wg_per_cu);
+
+/* All callbacks of every instance in one launch of a persistent kernel,
+ * replayed from a HIP graph.  sigma[n_inst] are the objective weights.  Any
+ * of F, G, C, J, H may be NULL (skipped); Y and sigma may be NULL when H
+ * is.  Results are bitwise equal to opf_eval_set on each instance. */
+int opf_batch_eval(opf_batch batch, const double *X, const double *Y, const double *sigma,
+                   double *F, double *G, double *C, double *J, double *H, void *stream);
+
+/* OUT = J(X)^T V for every instance (concatenated like X and C). */
+int opf_batch_jtprod(opf_batch batch, const double *X, const double *V, double *OUT,
+                     void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OPF_H */

@@ -1,0 +1,47 @@
+// Launch entry points of the callback kernels (implemented in the .hip files).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dev_model.h"
+
+namespace opf {
+
+// Work counts and LDS size of one callback set on one model.
+SetGrid plan_set(const DevModel& m, const EvalOut& o);
+size_t set_lds_bytes(const DevModel& m);
+
+// One callback set (any subset of f, g, c, J, H) on `stream`.
+hipError_t launch_eval_set(const DevModel& m, const EvalOut& o, hipStream_t stream);
+
+// out = J(x)^T v on `stream`.
+hipError_t launch_jtprod(const DevModel& m, const double* x, const double* v, double* out, hipStream_t stream);
+
+// ---- batched evaluation: a persistent kernel over a queue of work items.
+struct BatchItem {
+    int32_t inst, kind, idx, rep;
+};
+
+struct BatchInst {
+    DevModel m;
+    int64_t xoff, coff, joff, hoff;  // offsets into the concatenated arrays
+};
+
+struct BatchArgs {
+    const BatchInst* inst;   // [n_inst] device
+    const BatchItem* items;  // [n_items] device
+    int32_t n_items;
+    int32_t* counters;       // [2] device: next item, finished workgroups (self-resetting)
+    const double* X;
+    const double* Y;
+    const double* sigma;
+    double *F, *G, *C, *J, *H;
+    int32_t mode;            // 0 = callback set, 1 = J^T v (Y holds V, G holds OUT)
+};
+
+hipError_t launch_batch(const BatchArgs& a, int32_t grid, size_t lds_bytes, hipStream_t stream);
+
+// The persistent kernel's entry, for graph kernel nodes (argument: BatchArgs).
+void* batch_kernel_fn();
+
+}  // namespace opf

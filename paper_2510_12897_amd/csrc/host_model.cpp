@@ -1,0 +1,468 @@
+// Host-side model construction (see host_model.h).
+//
+// Pattern rule (structural, 0-based, sorted by (row, col), unique):
+//  Jacobian, rows in constraint order:
+//   ref        [va_r]
+//   flow row   [va_lo, va_hi, vm_lo, vm_hi, arc variable]   lo/hi = min/max(f, t)
+//   angle      [va_lo, va_hi]
+//   balance    [vm_i, generator columns ascending, arc columns ascending]
+//   thermal    [p_a, q_a]
+//   ramp       [pg_{k,t-1}, pg_{k,t}]
+//  Hessian lower triangle, per replica:
+//   va row i   [va_k for distinct neighbours k < i], va_i      (if i has a branch)
+//   vm row i   [va_k for distinct neighbours k < i], va_i, [va_k for k > i],
+//              [vm_k for distinct neighbours k < i], vm_i       (if i has a branch)
+//              vm_i only                                        (isolated bus)
+//   pg row     diagonal (objective), p row and q row: diagonal (thermal)
+//  These are exactly the variable pairs that share a nonlinear term: the four
+//  voltage variables of a branch's flow rows, vm^2 of the balance shunt term,
+//  p^2 and q^2 of a thermal row, pg^2 of a cost term.
+#include "host_model.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <limits>
+
+namespace opf {
+
+namespace {
+
+int fail(std::string& err, int code, const char* fmt, long long a = 0, long long b = 0) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, fmt, a, b);
+    err = buf;
+    return code;
+}
+
+int32_t nperiods(const opf_opts* o) { return o ? o->n_periods : 1; }
+int32_t ncont(const opf_opts* o) { return o ? o->n_cont : 0; }
+
+}  // namespace
+
+int validate(const opf_case* cs, const opf_opts* opts, std::string& err) {
+    if (!cs) return fail(err, OPF_E_ARG, "case is NULL");
+    if (cs->n_bus < 1) return fail(err, OPF_E_CASE, "n_bus must be >= 1 (got %lld)", cs->n_bus);
+    if (cs->n_branch < 0 || cs->n_gen < 0) return fail(err, OPF_E_CASE, "negative branch or generator count");
+    if (cs->n_ref < 1) return fail(err, OPF_E_CASE, "at least one reference bus is required");
+    const int32_t N = cs->n_bus, L = cs->n_branch, G = cs->n_gen;
+    if (!cs->pd || !cs->qd || !cs->gs || !cs->bs || !cs->vmin || !cs->vmax || !cs->ref_bus)
+        return fail(err, OPF_E_ARG, "a bus array is NULL");
+    if (L > 0 && (!cs->f_bus || !cs->t_bus || !cs->r || !cs->x || !cs->b || !cs->tap || !cs->shift ||
+                  !cs->rate_a || !cs->angmin || !cs->angmax))
+        return fail(err, OPF_E_ARG, "a branch array is NULL");
+    if (G > 0 && (!cs->gen_bus || !cs->pmin || !cs->pmax || !cs->qmin || !cs->qmax || !cs->c2 || !cs->c1 ||
+                  !cs->c0))
+        return fail(err, OPF_E_ARG, "a generator array is NULL");
+    for (int32_t j = 0; j < cs->n_ref; j++)
+        if (cs->ref_bus[j] < 0 || cs->ref_bus[j] >= N)
+            return fail(err, OPF_E_CASE, "reference %lld names bus %lld, out of range", j, cs->ref_bus[j]);
+    for (int32_t i = 0; i < N; i++)
+        if (!(cs->vmin[i] <= cs->vmax[i])) return fail(err, OPF_E_CASE, "bus %lld has vmin > vmax", i);
+    std::vector<int32_t> deg(N, 0);
+    for (int32_t l = 0; l < L; l++) {
+        int32_t f = cs->f_bus[l], t = cs->t_bus[l];
+        if (f < 0 || f >= N || t < 0 || t >= N)
+            return fail(err, OPF_E_CASE, "branch %lld has a bus out of range", l);
+        if (f == t) return fail(err, OPF_E_CASE, "branch %lld connects bus %lld to itself", l, f);
+        double z = cs->r[l] * cs->r[l] + cs->x[l] * cs->x[l];
+        if (!(z > 0.0) || !std::isfinite(z)) return fail(err, OPF_E_CASE, "branch %lld has zero impedance", l);
+        if (!(cs->tap[l] > 0.0) || !std::isfinite(cs->tap[l]))
+            return fail(err, OPF_E_CASE, "branch %lld has a nonpositive tap ratio", l);
+        if (!std::isfinite(cs->shift[l]) || !std::isfinite(cs->b[l]) || !std::isfinite(cs->rate_a[l]))
+            return fail(err, OPF_E_CASE, "branch %lld has a non-finite parameter", l);
+        if (++deg[f] > OPF_MAX_DEGREE || ++deg[t] > OPF_MAX_DEGREE)
+            return fail(err, OPF_E_CASE, "branch %lld takes a bus past %lld branches", l, OPF_MAX_DEGREE);
+    }
+    for (int32_t k = 0; k < G; k++) {
+        if (cs->gen_bus[k] < 0 || cs->gen_bus[k] >= N)
+            return fail(err, OPF_E_CASE, "generator %lld has a bus out of range", k);
+        if (!(cs->pmin[k] <= cs->pmax[k])) return fail(err, OPF_E_CASE, "generator %lld has pmin > pmax", k);
+        if (!(cs->qmin[k] <= cs->qmax[k])) return fail(err, OPF_E_CASE, "generator %lld has qmin > qmax", k);
+    }
+    const int32_t T = nperiods(opts), K = ncont(opts);
+    if (T < 1) return fail(err, OPF_E_CASE, "n_periods must be >= 1 (got %lld)", T);
+    if (K < 0) return fail(err, OPF_E_CASE, "n_cont must be >= 0 (got %lld)", K);
+    if (T > 1 && K > 0) return fail(err, OPF_E_CASE, "periods and contingency copies cannot be combined");
+    if (opts && T > 1 && (!(opts->ramp_ratio >= 0.0) || !std::isfinite(opts->ramp_ratio)))
+        return fail(err, OPF_E_CASE, "ramp_ratio must be finite and >= 0");
+    if (opts && (opts->pd_t == nullptr) != (opts->qd_t == nullptr))
+        return fail(err, OPF_E_ARG, "pd_t and qd_t must both be given or both be NULL");
+    if (K > 0) {
+        if (!opts->outaged_branch) return fail(err, OPF_E_ARG, "outaged_branch is NULL");
+        for (int32_t s = 0; s < K; s++)
+            if (opts->outaged_branch[s] < 0 || opts->outaged_branch[s] >= L)
+                return fail(err, OPF_E_CASE, "contingency %lld outages branch %lld, out of range", s,
+                            opts->outaged_branch[s]);
+    }
+    // sizes must fit the int32 pattern indices
+    const int64_t nrep = T > 1 ? T : (int64_t)K + 1;
+    const int64_t npg = K > 0 ? 1 : nrep;
+    const int64_t n = nrep * (2LL * N + G + 4LL * L) + npg * G;
+    const int64_t m = nrep * (cs->n_ref + 7LL * L + 2LL * N) + (T > 1 ? (int64_t)G * (T - 1) : 0);
+    const int64_t nnzj = nrep * (cs->n_ref + 30LL * L + 2LL * N + 2LL * G) + 2LL * G * (T - 1);
+    const int64_t lim = std::numeric_limits<int32_t>::max();
+    if (n >= lim || m >= lim || nnzj >= lim) return fail(err, OPF_E_CASE, "model too large for int32 indices");
+    return OPF_OK;
+}
+
+int build_host_model(const opf_case* cs, const opf_opts* opts, HostModel& hm, std::string& err) {
+    int rc = validate(cs, opts, err);
+    if (rc) return rc;
+    const int32_t N = cs->n_bus, L = cs->n_branch, G = cs->n_gen, R = cs->n_ref;
+    const int32_t T = nperiods(opts), K = ncont(opts);
+    Layout& ly = hm.ly;
+    ly.N = N; ly.L = L; ly.G = G; ly.R = R; ly.T = T; ly.K = K;
+    ly.nrep = T > 1 ? T : K + 1;
+    ly.npg = K > 0 ? 1 : ly.nrep;
+    const int64_t P = ly.nrep;
+
+    // ---- branch terms of the pi model (series g + jb, charging b/2 a side,
+    // ideal transformer tr + j ti on the from side)
+    hm.f_bus.assign(cs->f_bus, cs->f_bus + L);
+    hm.t_bus.assign(cs->t_bus, cs->t_bus + L);
+    hm.coef.assign(8 * (size_t)L, 0.0);
+    hm.rate2.resize(L);
+    for (int32_t l = 0; l < L; l++) {
+        const double z = cs->r[l] * cs->r[l] + cs->x[l] * cs->x[l];
+        const double g = cs->r[l] / z, b = -cs->x[l] / z;
+        const double tr = cs->tap[l] * std::cos(cs->shift[l]);
+        const double ti = cs->tap[l] * std::sin(cs->shift[l]);
+        const double t2 = cs->tap[l] * cs->tap[l];
+        const double bc = 0.5 * cs->b[l];
+        double* k = hm.coef.data();
+        k[0 * (size_t)L + l] = g / t2;                     // Gff
+        k[1 * (size_t)L + l] = (b + bc) / t2;              // Bff
+        k[2 * (size_t)L + l] = (-g * tr + b * ti) / t2;    // Gft
+        k[3 * (size_t)L + l] = (-b * tr - g * ti) / t2;    // Bft
+        k[4 * (size_t)L + l] = g;                          // Gtt
+        k[5 * (size_t)L + l] = b + bc;                     // Btt
+        k[6 * (size_t)L + l] = (-g * tr - b * ti) / t2;    // Gtf
+        k[7 * (size_t)L + l] = (-b * tr + g * ti) / t2;    // Btf
+        hm.rate2[l] = cs->rate_a[l] * cs->rate_a[l];
+    }
+
+    // ---- half-edges per bus, sorted by (neighbour, branch)
+    hm.adj_ptr.assign(N + 1, 0);
+    for (int32_t l = 0; l < L; l++) {
+        hm.adj_ptr[cs->f_bus[l] + 1]++;
+        hm.adj_ptr[cs->t_bus[l] + 1]++;
+    }
+    for (int32_t i = 0; i < N; i++) hm.adj_ptr[i + 1] += hm.adj_ptr[i];
+    hm.he.resize(2 * (size_t)L);
+    {
+        std::vector<int32_t> fill(hm.adj_ptr.begin(), hm.adj_ptr.end() - 1);
+        for (int32_t l = 0; l < L; l++) {
+            hm.he[fill[cs->f_bus[l]]++] = (l << 1) | 1;
+            hm.he[fill[cs->t_bus[l]]++] = (l << 1);
+        }
+    }
+    auto nbr = [&](int32_t code) {
+        const int32_t l = code >> 1;
+        return (code & 1) ? cs->t_bus[l] : cs->f_bus[l];
+    };
+    hm.he_grp.resize(2 * (size_t)L);
+    hm.nlo.assign(N, 0);
+    hm.ndist.assign(N, 0);
+    hm.max_degree = 0;
+    for (int32_t i = 0; i < N; i++) {
+        auto b = hm.he.begin() + hm.adj_ptr[i], e = hm.he.begin() + hm.adj_ptr[i + 1];
+        std::sort(b, e, [&](int32_t u, int32_t v) {
+            const int32_t nu = nbr(u), nv = nbr(v);
+            return nu != nv ? nu < nv : (u >> 1) < (v >> 1);
+        });
+        int32_t grp = -1, prev = -1;
+        for (int32_t q = hm.adj_ptr[i]; q < hm.adj_ptr[i + 1]; q++) {
+            const int32_t k = nbr(hm.he[q]);
+            if (k != prev) {
+                grp++;
+                prev = k;
+                if (k < i) hm.nlo[i]++;
+            }
+            hm.he_grp[q] = grp;
+        }
+        hm.ndist[i] = grp + 1;
+        hm.max_degree = std::max(hm.max_degree, hm.adj_ptr[i + 1] - hm.adj_ptr[i]);
+    }
+
+    // ---- generators and arcs per bus (ascending index)
+    hm.gen_ptr.assign(N + 1, 0);
+    for (int32_t k = 0; k < G; k++) hm.gen_ptr[cs->gen_bus[k] + 1]++;
+    for (int32_t i = 0; i < N; i++) hm.gen_ptr[i + 1] += hm.gen_ptr[i];
+    hm.gen_list.resize(G);
+    {
+        std::vector<int32_t> fill(hm.gen_ptr.begin(), hm.gen_ptr.end() - 1);
+        for (int32_t k = 0; k < G; k++) hm.gen_list[fill[cs->gen_bus[k]]++] = k;
+    }
+    hm.arc_ptr.assign(N + 1, 0);
+    for (int32_t a = 0; a < 2 * L; a++) hm.arc_ptr[(a < L ? cs->f_bus[a] : cs->t_bus[a - L]) + 1]++;
+    for (int32_t i = 0; i < N; i++) hm.arc_ptr[i + 1] += hm.arc_ptr[i];
+    hm.arc_list.resize(2 * (size_t)L);
+    {
+        std::vector<int32_t> fill(hm.arc_ptr.begin(), hm.arc_ptr.end() - 1);
+        for (int32_t a = 0; a < 2 * L; a++) hm.arc_list[fill[a < L ? cs->f_bus[a] : cs->t_bus[a - L]]++] = a;
+    }
+
+    // ---- per-bus offsets of the balance Jacobian rows and Hessian bus rows
+    hm.jbal_off.assign(N + 1, 0);
+    hm.hva_off.assign(N + 1, 0);
+    hm.hvm_off.assign(N + 1, 0);
+    for (int32_t i = 0; i < N; i++) {
+        const int32_t deg = hm.adj_ptr[i + 1] - hm.adj_ptr[i];
+        const int32_t ng = hm.gen_ptr[i + 1] - hm.gen_ptr[i];
+        hm.jbal_off[i + 1] = hm.jbal_off[i] + 1 + ng + deg;
+        hm.hva_off[i + 1] = hm.hva_off[i] + (deg > 0 ? hm.nlo[i] + 1 : 0);
+        hm.hvm_off[i + 1] = hm.hvm_off[i] + (deg > 0 ? hm.ndist[i] + hm.nlo[i] + 2 : 1);
+    }
+
+    // ---- bus, generator and replica data
+    hm.gs.assign(cs->gs, cs->gs + N);
+    hm.bs.assign(cs->bs, cs->bs + N);
+    if (T > 1 && opts && opts->pd_t) {
+        hm.pd.assign(opts->pd_t, opts->pd_t + (size_t)N * T);
+        hm.qd.assign(opts->qd_t, opts->qd_t + (size_t)N * T);
+        hm.load_stride = N;
+    } else {
+        hm.pd.assign(cs->pd, cs->pd + N);
+        hm.qd.assign(cs->qd, cs->qd + N);
+        hm.load_stride = 0;
+    }
+    hm.c2.assign(cs->c2, cs->c2 + G);
+    hm.c1.assign(cs->c1, cs->c1 + G);
+    hm.c0.assign(cs->c0, cs->c0 + G);
+    hm.gen_bus.assign(cs->gen_bus, cs->gen_bus + G);
+    hm.ref_bus.assign(cs->ref_bus, cs->ref_bus + R);
+    hm.ref_ptr.assign(N + 1, 0);
+    for (int32_t j = 0; j < R; j++) hm.ref_ptr[cs->ref_bus[j] + 1]++;
+    for (int32_t i = 0; i < N; i++) hm.ref_ptr[i + 1] += hm.ref_ptr[i];
+    hm.ref_list.resize(R);
+    {
+        std::vector<int32_t> fill(hm.ref_ptr.begin(), hm.ref_ptr.end() - 1);
+        for (int32_t j = 0; j < R; j++) hm.ref_list[fill[cs->ref_bus[j]]++] = j;
+    }
+    hm.outage.assign(P, -1);
+    for (int32_t s = 0; s < K; s++) hm.outage[s + 1] = opts->outaged_branch[s];
+
+    // ---- layout
+    ly.x_va = 0;
+    ly.x_vm = N * P;
+    ly.x_pg = 2LL * N * P;
+    ly.x_qg = ly.x_pg + (int64_t)G * ly.npg;
+    ly.x_p = ly.x_qg + (int64_t)G * P;
+    ly.x_q = ly.x_p + 2LL * L * P;
+    ly.n = ly.x_q + 2LL * L * P;
+    const int64_t rows[B_END] = {R * P, L * P, L * P, L * P, L * P, L * P, N * P, N * P, L * P, L * P,
+                                 T > 1 ? (int64_t)G * (T - 1) : 0};
+    ly.jbal_rep = (int64_t)N + G + 2LL * L;
+    const int64_t ents[B_END] = {R * P, 5LL * L * P, 5LL * L * P, 5LL * L * P, 5LL * L * P, 2LL * L * P,
+                                 ly.jbal_rep * P, ly.jbal_rep * P, 2LL * L * P, 2LL * L * P,
+                                 T > 1 ? 2LL * G * (T - 1) : 0};
+    ly.c_blk[0] = ly.j_blk[0] = 0;
+    for (int b = 0; b < B_END; b++) {
+        ly.c_blk[b + 1] = ly.c_blk[b] + rows[b];
+        ly.j_blk[b + 1] = ly.j_blk[b] + ents[b];
+    }
+    ly.hva_rep = hm.hva_off[N];
+    ly.hvm_rep = hm.hvm_off[N];
+    ly.h_va = 0;
+    ly.h_vm = ly.hva_rep * P;
+    ly.h_pg = ly.h_vm + ly.hvm_rep * P;
+    ly.h_p = ly.h_pg + (int64_t)G * ly.npg;
+    ly.h_q = ly.h_p + 2LL * L * P;
+    ly.nnzh = ly.h_q + 2LL * L * P;
+    if (ly.nnzh >= std::numeric_limits<int32_t>::max())
+        return fail(err, OPF_E_CASE, "model too large for int32 indices");
+    return OPF_OK;
+}
+
+std::vector<int32_t> build_tiles(const HostModel& hm, int32_t cap) {
+    cap = std::max(cap, std::max<int32_t>(hm.max_degree, 1));
+    std::vector<int32_t> tiles{0};
+    const int32_t N = hm.ly.N;
+    int32_t edges = 0, buses = 0;
+    for (int32_t i = 0; i < N; i++) {
+        const int32_t deg = hm.adj_ptr[i + 1] - hm.adj_ptr[i];
+        if (buses > 0 && (edges + deg > cap || buses + 1 > cap)) {
+            tiles.push_back(i);
+            edges = 0;
+            buses = 0;
+        }
+        edges += deg;
+        buses += 1;
+    }
+    tiles.push_back(N);
+    return tiles;
+}
+
+void fill_pattern(const HostModel& hm, int32_t* jr, int32_t* jc, int32_t* hr, int32_t* hc) {
+    const Layout& ly = hm.ly;
+    const int32_t N = ly.N, L = ly.L, G = ly.G, R = ly.R, P = ly.nrep;
+    auto va = [&](int32_t i, int32_t r) { return (int32_t)(ly.x_va + i + (int64_t)N * r); };
+    auto vm = [&](int32_t i, int32_t r) { return (int32_t)(ly.x_vm + i + (int64_t)N * r); };
+    auto pg = [&](int32_t k, int32_t r) { return (int32_t)(ly.x_pg + k + (int64_t)G * (ly.npg > 1 ? r : 0)); };
+    auto qg = [&](int32_t k, int32_t r) { return (int32_t)(ly.x_qg + k + (int64_t)G * r); };
+    auto pa = [&](int32_t a, int32_t r) { return (int32_t)(ly.x_p + a + 2LL * L * r); };
+    auto qa = [&](int32_t a, int32_t r) { return (int32_t)(ly.x_q + a + 2LL * L * r); };
+
+    if (jr || jc) {
+        int64_t e = 0;
+        int32_t row = 0;
+        auto put = [&](int32_t col) {
+            if (jr) jr[e] = row;
+            if (jc) jc[e] = col;
+            e++;
+        };
+        for (int32_t r = 0; r < P; r++)
+            for (int32_t j = 0; j < R; j++, row++) put(va(hm.ref_bus[j], r));
+        for (int b = B_PFR; b <= B_QTO; b++) {
+            const bool fr = (b == B_PFR || b == B_QFR), isp = (b == B_PFR || b == B_PTO);
+            for (int32_t r = 0; r < P; r++)
+                for (int32_t l = 0; l < L; l++, row++) {
+                    const int32_t lo = std::min(hm.f_bus[l], hm.t_bus[l]), hi = std::max(hm.f_bus[l], hm.t_bus[l]);
+                    const int32_t arc = fr ? l : L + l;
+                    put(va(lo, r)); put(va(hi, r)); put(vm(lo, r)); put(vm(hi, r));
+                    put(isp ? pa(arc, r) : qa(arc, r));
+                }
+        }
+        for (int32_t r = 0; r < P; r++)
+            for (int32_t l = 0; l < L; l++, row++) {
+                put(va(std::min(hm.f_bus[l], hm.t_bus[l]), r));
+                put(va(std::max(hm.f_bus[l], hm.t_bus[l]), r));
+            }
+        for (int isp = 1; isp >= 0; isp--)
+            for (int32_t r = 0; r < P; r++)
+                for (int32_t i = 0; i < N; i++, row++) {
+                    put(vm(i, r));
+                    for (int32_t q = hm.gen_ptr[i]; q < hm.gen_ptr[i + 1]; q++)
+                        put(isp ? pg(hm.gen_list[q], r) : qg(hm.gen_list[q], r));
+                    for (int32_t q = hm.arc_ptr[i]; q < hm.arc_ptr[i + 1]; q++)
+                        put(isp ? pa(hm.arc_list[q], r) : qa(hm.arc_list[q], r));
+                }
+        for (int side = 0; side < 2; side++)
+            for (int32_t r = 0; r < P; r++)
+                for (int32_t l = 0; l < L; l++, row++) {
+                    const int32_t arc = side == 0 ? l : L + l;
+                    put(pa(arc, r));
+                    put(qa(arc, r));
+                }
+        for (int32_t t = 1; t < ly.T; t++)
+            for (int32_t k = 0; k < G; k++, row++) {
+                put(pg(k, t - 1));
+                put(pg(k, t));
+            }
+    }
+
+    if (hr || hc) {
+        int64_t e = 0;
+        auto put = [&](int32_t row, int32_t col) {
+            if (hr) hr[e] = row;
+            if (hc) hc[e] = col;
+            e++;
+        };
+        auto nbr = [&](int32_t code) {
+            const int32_t l = code >> 1;
+            return (code & 1) ? hm.t_bus[l] : hm.f_bus[l];
+        };
+        // distinct neighbours of bus i, ascending (one per group)
+        auto distinct = [&](int32_t i, std::vector<int32_t>& out) {
+            out.clear();
+            for (int32_t q = hm.adj_ptr[i]; q < hm.adj_ptr[i + 1]; q++) {
+                const int32_t k = nbr(hm.he[q]);
+                if (out.empty() || out.back() != k) out.push_back(k);
+            }
+        };
+        std::vector<int32_t> nb;
+        for (int32_t r = 0; r < P; r++)
+            for (int32_t i = 0; i < N; i++) {
+                distinct(i, nb);
+                if (nb.empty()) continue;
+                for (int32_t k : nb)
+                    if (k < i) put(va(i, r), va(k, r));
+                put(va(i, r), va(i, r));
+            }
+        for (int32_t r = 0; r < P; r++)
+            for (int32_t i = 0; i < N; i++) {
+                distinct(i, nb);
+                if (!nb.empty()) {
+                    for (int32_t k : nb)
+                        if (k < i) put(vm(i, r), va(k, r));
+                    put(vm(i, r), va(i, r));
+                    for (int32_t k : nb)
+                        if (k > i) put(vm(i, r), va(k, r));
+                    for (int32_t k : nb)
+                        if (k < i) put(vm(i, r), vm(k, r));
+                }
+                put(vm(i, r), vm(i, r));
+            }
+        for (int32_t r = 0; r < ly.npg; r++)
+            for (int32_t k = 0; k < G; k++) put(pg(k, r), pg(k, r));
+        for (int32_t r = 0; r < P; r++)
+            for (int32_t a = 0; a < 2 * L; a++) put(pa(a, r), pa(a, r));
+        for (int32_t r = 0; r < P; r++)
+            for (int32_t a = 0; a < 2 * L; a++) put(qa(a, r), qa(a, r));
+    }
+}
+
+void fill_bounds(const opf_case* cs, const opf_opts* opts, const HostModel& hm, double* lvar, double* uvar,
+                 double* lcon, double* ucon, double* x0) {
+    const Layout& ly = hm.ly;
+    const int32_t N = ly.N, L = ly.L, G = ly.G, P = ly.nrep;
+    const double inf = std::numeric_limits<double>::infinity();
+    if (lvar || uvar || x0) {
+        for (int64_t j = 0; j < ly.n; j++) {
+            if (lvar) lvar[j] = -inf;
+            if (uvar) uvar[j] = inf;
+            if (x0) x0[j] = 0.0;
+        }
+        for (int32_t r = 0; r < P; r++) {
+            for (int32_t i = 0; i < N; i++) {
+                const int64_t c = ly.x_vm + i + (int64_t)N * r;
+                if (lvar) lvar[c] = cs->vmin[i];
+                if (uvar) uvar[c] = cs->vmax[i];
+                if (x0) x0[c] = 1.0;
+            }
+            for (int32_t k = 0; k < G; k++) {
+                const int64_t c = ly.x_qg + k + (int64_t)G * r;
+                if (lvar) lvar[c] = cs->qmin[k];
+                if (uvar) uvar[c] = cs->qmax[k];
+            }
+            for (int32_t a = 0; a < 2 * L; a++) {
+                const double rate = cs->rate_a[a < L ? a : a - L];
+                const int64_t cp = ly.x_p + a + 2LL * L * r, cq = ly.x_q + a + 2LL * L * r;
+                if (lvar) { lvar[cp] = -rate; lvar[cq] = -rate; }
+                if (uvar) { uvar[cp] = rate; uvar[cq] = rate; }
+            }
+        }
+        for (int32_t r = 0; r < ly.npg; r++)
+            for (int32_t k = 0; k < G; k++) {
+                const int64_t c = ly.x_pg + k + (int64_t)G * r;
+                if (lvar) lvar[c] = cs->pmin[k];
+                if (uvar) uvar[c] = cs->pmax[k];
+            }
+    }
+    if (lcon || ucon) {
+        const int64_t m = ly.m();
+        for (int64_t j = 0; j < m; j++) {
+            if (lcon) lcon[j] = 0.0;
+            if (ucon) ucon[j] = 0.0;
+        }
+        for (int32_t r = 0; r < P; r++)
+            for (int32_t l = 0; l < L; l++) {
+                const int64_t row = ly.c_blk[B_ANG] + l + (int64_t)L * r;
+                const bool out = hm.outage[r] == l;
+                if (lcon) lcon[row] = out ? -inf : cs->angmin[l];
+                if (ucon) ucon[row] = out ? inf : cs->angmax[l];
+            }
+        for (int64_t row = ly.c_blk[B_THF]; row < ly.c_blk[B_RAMP]; row++)
+            if (lcon) lcon[row] = -inf;
+        const double ratio = opts ? opts->ramp_ratio : 0.0;
+        for (int32_t t = 1; t < ly.T; t++)
+            for (int32_t k = 0; k < G; k++) {
+                const int64_t row = ly.c_blk[B_RAMP] + k + (int64_t)G * (t - 1);
+                if (lcon) lcon[row] = -ratio * cs->pmax[k];
+                if (ucon) ucon[row] = ratio * cs->pmax[k];
+            }
+    }
+}
+
+}  // namespace opf

@@ -1,0 +1,77 @@
+// Host-side model construction for the polar AC-OPF callbacks: validation,
+// branch admittance terms, bus adjacency, bus tiles, the sparsity pattern and
+// the bounds.  Pure C++ (no HIP); libopf uploads the result once.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "opf.h"
+
+namespace opf {
+
+// Constraint blocks in the order the paper's Listing 3 creates them, then
+// the multi-period ramp rows.
+enum Block { B_REF = 0, B_PFR, B_QFR, B_PTO, B_QTO, B_ANG, B_BALP, B_BALQ, B_THF, B_THT, B_RAMP, B_END };
+
+struct Layout {
+    int32_t N = 0, L = 0, G = 0, R = 0, T = 1, K = 0;
+    int32_t nrep = 1;   // replicas: periods or contingency copies (base + K)
+    int32_t npg = 1;    // replicas of the pg block (1 when copies share pg)
+    // variable blocks
+    int64_t x_va = 0, x_vm = 0, x_pg = 0, x_qg = 0, x_p = 0, x_q = 0, n = 0;
+    // first row of each constraint block (c_blk[B_END] = m)
+    int64_t c_blk[B_END + 1] = {};
+    // first Jacobian entry of each block (j_blk[B_END] = nnzj)
+    int64_t j_blk[B_END + 1] = {};
+    int64_t jbal_rep = 0;          // entries of one replica's balance block
+    // Hessian: va rows, vm rows, pg rows, p rows, q rows
+    int64_t h_va = 0, h_vm = 0, h_pg = 0, h_p = 0, h_q = 0, nnzh = 0;
+    int64_t hva_rep = 0, hvm_rep = 0;  // entries of one replica's va / vm rows
+
+    int64_t m() const { return c_blk[B_END]; }
+    int64_t nnzj() const { return j_blk[B_END]; }
+};
+
+struct HostModel {
+    Layout ly;
+    // branches: endpoints, 8 admittance terms (structure of arrays, term k of
+    // branch l at coef[k * L + l]: Gff Bff Gft Bft Gtt Btt Gtf Btf), rate_a^2
+    std::vector<int32_t> f_bus, t_bus;
+    std::vector<double> coef, rate2;
+    // bus adjacency: half-edges of bus i are he[adj_ptr[i] .. adj_ptr[i+1]),
+    // sorted by (neighbour bus, branch); code = branch << 1 | (bus is f_bus)
+    std::vector<int32_t> adj_ptr, he, he_grp;  // he_grp: distinct-neighbour rank
+    std::vector<int32_t> nlo, ndist;           // distinct neighbours below i / total
+    std::vector<int32_t> hva_off, hvm_off;     // first Hessian entry of bus rows (per replica)
+    std::vector<int32_t> jbal_off;             // first entry of the balance row (per replica)
+    std::vector<int32_t> gen_ptr, gen_list;    // generators per bus, ascending
+    std::vector<int32_t> arc_ptr, arc_list;    // arcs per bus, ascending (pattern only)
+    std::vector<double> gs, bs, pd, qd;        // pd, qd: N * T for multi-period, else N
+    int32_t load_stride = 0;                   // N for multi-period loads, else 0
+    std::vector<double> c2, c1, c0;
+    std::vector<int32_t> gen_bus;
+    std::vector<int32_t> ref_bus;
+    std::vector<int32_t> ref_ptr, ref_list;    // reference rows per bus, ascending
+    std::vector<int32_t> outage;               // per replica: branch out of service or -1
+    int32_t max_degree = 0;
+};
+
+// Validation; returns OPF_OK or an error code with a message.
+int validate(const opf_case* cs, const opf_opts* opts, std::string& err);
+
+// Full host model; returns OPF_OK or an error code.
+int build_host_model(const opf_case* cs, const opf_opts* opts, HostModel& hm, std::string& err);
+
+// Bus tiles: consecutive buses whose half-edges fit `cap` (cap >= max degree).
+std::vector<int32_t> build_tiles(const HostModel& hm, int32_t cap);
+
+// Pattern into host buffers (any may be null).
+void fill_pattern(const HostModel& hm, int32_t* jrows, int32_t* jcols, int32_t* hrows, int32_t* hcols);
+
+// Bounds and x0 into host buffers (any may be null).
+void fill_bounds(const opf_case* cs, const opf_opts* opts, const HostModel& hm, double* lvar, double* uvar,
+                 double* lcon, double* ucon, double* x0);
+
+}  // namespace opf

@@ -1,0 +1,192 @@
+"""Batched evaluation: one persistent launch over many uneven instances.
+
+Batched results equal the plain per-instance launches bit for bit, under
+every schedule the autotuner may pick, across graph replays, for J^T v too;
+sampled instances also match the oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2510_12897_amd import opf, synth
+
+from helpers import assert_close
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def build_mix(sizes=(40, 300, 1200), per=3, with_mp=True, with_sc=True):
+    """Instances of several networks with their own loads, plus one
+    multi-period and one contingency model."""
+    nets, models, inst_model, pds, qds, plain = [], [], [], [], [], []
+    for j, N in enumerate(sizes):
+        cs = synth.network(N, int(round(1.35 * N)), max(1, int(round(0.2 * N))), 500 + j, variant=(j % 2 == 0))
+        nets.append((cs, {}))
+        models.append(opf.Model(cs))
+        for s in range(per):
+            pd, qd = synth.scenario_loads(cs, 900 + 10 * j + s)
+            c2 = dict(cs)
+            c2["pd"], c2["qd"] = pd, qd
+            inst_model.append(len(models) - 1)
+            pds.append(pd)
+            qds.append(qd)
+            plain.append((c2, {}))
+    if with_mp:
+        cs = synth.network(50, 70, 10, 61, variant=True)
+        pd_t, qd_t = synth.mp_loads(cs, 3, 62)
+        opts = dict(n_periods=3, pd_t=pd_t, qd_t=qd_t, ramp_ratio=0.2)
+        models.append(opf.Model(cs, **opts))
+        nets.append((cs, opts))
+        for s in range(2):
+            a, b = synth.mp_loads(cs, 3, 70 + s)
+            inst_model.append(len(models) - 1)
+            pds.append(a)
+            qds.append(b)
+            plain.append((cs, dict(opts, pd_t=a, qd_t=b)))
+    if with_sc:
+        cs = synth.network(60, 85, 12, 63, variant=True)
+        opts = dict(n_cont=3, outaged=synth.outages(cs, 3, 64))
+        models.append(opf.Model(cs, **opts))
+        nets.append((cs, opts))
+        pd, qd = synth.scenario_loads(cs, 80)
+        c2 = dict(cs)
+        c2["pd"], c2["qd"] = pd, qd
+        inst_model.append(len(models) - 1)
+        pds.append(pd)
+        qds.append(qd)
+        plain.append((c2, opts))
+    batch = opf.Batch(models, inst_model, np.concatenate(pds), np.concatenate(qds))
+    return batch, models, inst_model, plain
+
+
+def fill_inputs(batch, plain):
+    X = torch.empty(batch.n, dtype=torch.float64, device=DEV)
+    Y = torch.empty(batch.m, dtype=torch.float64, device=DEV)
+    xs, ys = [], []
+    for i, (cs, opts) in enumerate(plain):
+        x = synth.point(cs, (7, i), n_periods=opts.get("n_periods", 1), n_cont=opts.get("n_cont", 0))
+        y = synth.multipliers(int(batch.coff[i + 1] - batch.coff[i]), (7, i))
+        X[batch.xoff[i]:batch.xoff[i + 1]] = torch.as_tensor(x, device=DEV)
+        Y[batch.coff[i]:batch.coff[i + 1]] = torch.as_tensor(y, device=DEV)
+        xs.append(x)
+        ys.append(y)
+    sig = torch.linspace(0.5, 1.5, batch.n_inst, dtype=torch.float64, device=DEV)
+    return X, Y, sig, xs, ys
+
+
+def outputs(batch):
+    return (torch.full((batch.n_inst,), np.nan, dtype=torch.float64, device=DEV),
+            torch.full((batch.n,), np.nan, dtype=torch.float64, device=DEV),
+            torch.full((batch.m,), np.nan, dtype=torch.float64, device=DEV),
+            torch.full((batch.nnzj,), np.nan, dtype=torch.float64, device=DEV),
+            torch.full((batch.nnzh,), np.nan, dtype=torch.float64, device=DEV))
+
+
+def plain_reference(batch, plain, X, Y, sig):
+    ref = outputs(batch)
+    F, G, C, J, H = ref
+    for i, (cs, opts) in enumerate(plain):
+        m = opf.Model(cs, **opts)
+        sl = lambda o, a: a[int(o[i]):int(o[i + 1])]  # noqa: E731
+        m.eval_set(sl(batch.xoff, X), sl(batch.coff, Y), float(sig[i].item()), F[i:i + 1], sl(batch.xoff, G),
+                   sl(batch.coff, C), sl(batch.joff, J), sl(batch.hoff, H))
+        torch.cuda.synchronize()
+        m.close()
+    return ref
+
+
+def test_batch_equals_plain_bitwise_every_schedule():
+    say("[batch] build mix")
+    batch, models, inst_model, plain = build_mix()
+    X, Y, sig, xs, ys = fill_inputs(batch, plain)
+    ref = plain_reference(batch, plain, X, Y, sig)
+    for cap, wg in ((128, 1), (256, 4), (512, 2), (1024, 8)):
+        say(f"[batch] schedule cap={cap} wg={wg}")
+        batch.set_schedule(cap, wg)
+        out = outputs(batch)
+        batch.eval(X, Y, sig, *out)
+        torch.cuda.synchronize()
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b), f"schedule ({cap}, {wg}) differs from plain"
+    say("[batch] tune")
+    sched = batch.tune()
+    out = outputs(batch)
+    batch.eval(X, Y, sig, *out)
+    torch.cuda.synchronize()
+    for a, b in zip(out, ref):
+        assert torch.equal(a, b)
+    say(f"[batch] tuned schedule {sched}")
+    batch.close()
+    for m in models:
+        m.close()
+
+
+def test_batch_graph_replays_and_partial_outputs():
+    batch, models, inst_model, plain = build_mix(sizes=(30, 200), per=2, with_mp=False)
+    X, Y, sig, xs, ys = fill_inputs(batch, plain)
+    ref = plain_reference(batch, plain, X, Y, sig)
+    out = outputs(batch)
+    for rep in range(4):
+        say(f"[batch] replay {rep}")
+        for t in out:
+            t.fill_(np.nan)  # eager work between replays
+        torch.cuda.synchronize()
+        batch.eval(X, Y, sig, *out)
+        torch.cuda.synchronize()
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b), f"replay {rep}"
+    # only constraints
+    C = torch.full((batch.m,), np.nan, dtype=torch.float64, device=DEV)
+    batch.eval(X, C=C)
+    torch.cuda.synchronize()
+    assert torch.equal(C, ref[2])
+    with pytest.raises(opf.OPFError):
+        batch.eval(X, H=out[4])
+    batch.close()
+    for m in models:
+        m.close()
+
+
+def test_batch_jtprod_equals_plain():
+    batch, models, inst_model, plain = build_mix(sizes=(25, 400), per=2)
+    X, V, _, xs, vs = fill_inputs(batch, plain)
+    out = batch.jtprod(X, V)
+    torch.cuda.synchronize()
+    for i, (cs, opts) in enumerate(plain):
+        m = opf.Model(cs, **opts)
+        r = m.jtprod(X[batch.xoff[i]:batch.xoff[i + 1]], V[batch.coff[i]:batch.coff[i + 1]])
+        torch.cuda.synchronize()
+        assert torch.equal(r, out[batch.xoff[i]:batch.xoff[i + 1]]), f"instance {i}"
+        m.close()
+    batch.close()
+    for m in models:
+        m.close()
+
+
+def test_batch_instances_match_oracle():
+    batch, models, inst_model, plain = build_mix(sizes=(35, 260), per=2)
+    X, Y, sig, xs, ys = fill_inputs(batch, plain)
+    out = outputs(batch)
+    batch.eval(X, Y, sig, *out)
+    torch.cuda.synchronize()
+    F, G, C, J, H = (t.cpu().numpy() for t in out)
+    for i, (cs, opts) in enumerate(plain):
+        say(f"[batch/oracle] instance {i}")
+        res = O.evaluate(cs, xs[i], ys[i], float(sig[i].item()), **opts)
+        sl = lambda o, a: a[int(o[i]):int(o[i + 1])]  # noqa: E731
+        assert_close([F[i]], [res["f"]], [res["fscale"]], what=f"inst {i} f")
+        assert_close(sl(batch.coff, C), res["c"], res["cscale"], what=f"inst {i} c")
+        assert_close(sl(batch.joff, J), res["jval"], res["jscale"], what=f"inst {i} J")
+        assert_close(sl(batch.hoff, H), res["hval"], res["hscale"], what=f"inst {i} H")
+        assert_close(sl(batch.xoff, G), res["g"], np.abs(res["g"]), what=f"inst {i} g")
+    batch.close()
+    for m in models:
+        m.close()
