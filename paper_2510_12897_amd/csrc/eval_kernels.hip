@@ -330,6 +330,7 @@ __device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int
 
 // ------------------------------------------------------------------ objective
 __device__ void obj_task(const DevModel& m, const EvalOut& o, double* lds) {
+    if (o.f == nullptr) return;  // uniform across the workgroup: no barrier is skipped by part of it
     const int32_t G = m.G;
     const int64_t total = (int64_t)G * m.npg;
     double acc = 0.0;
