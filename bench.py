@@ -104,7 +104,10 @@ class PlainRunner:
         torch.cuda.synchronize()
 
     def step(self):
-        self.graph.replay()
+        if self.graph is None:
+            self.enqueue()
+        else:
+            self.graph.replay()
 
 
 def time_steps(torch, fn, steps: int, warmup: int):
@@ -134,7 +137,8 @@ def bench_headline(args, torch, opf, synth, log):
     ys = [torch.as_tensor(synth.multipliers(model.m, (101, r)), device=dev) for r in range(n_in)]
     log(f"generated {n_in} seeded (x, y) pairs")
     runner = PlainRunner(model, xs, ys, n_out=64, sets=args.sets_per_step, torch=torch)
-    runner.capture()
+    if not args.eager:
+        runner.capture()
     secs, wall = time_steps(torch, runner.step, args.steps, args.warmup)
     n_sets = args.steps * args.sets_per_step
     per_set = secs / n_sets
@@ -195,7 +199,7 @@ def bench_batch(args, torch, opf, synth, log):
     H = torch.empty(batch.nnzh, dtype=torch.float64, device=dev)
     sched = batch.tune()
     log(f"batch: {n_inst} instances, n={batch.n} m={batch.m} nnzj={batch.nnzj} nnzh={batch.nnzh}, "
-        f"tuned schedule tile_cap={sched[0]} wg_per_cu={sched[1]}")
+        f"tuned schedule replica_group={sched[0]} wg_per_cu={sched[1]}")
 
     def batched():
         batch.eval(X, Y, sig, F, G, C, J, H)
@@ -246,7 +250,7 @@ def bench_batch(args, torch, opf, synth, log):
         batched_sets_per_s=n_inst / per_launch, plain_sets_per_s=n_inst / per_plain,
         speedup=per_plain / per_launch, us_per_launch=per_launch * 1e6, bytes_per_launch=total_bytes,
         achieved_gbs=total_bytes / per_launch / 1e9, frac=total_bytes / per_launch / 1e9 / HBM_PEAK_GBS,
-        schedule=dict(tile_cap=sched[0], wg_per_cu=sched[1]), bitwise_equal_to_plain=bool(bitwise))
+        schedule=dict(replica_group=sched[0], wg_per_cu=sched[1]), bitwise_equal_to_plain=bool(bitwise))
     batch.close()
     for mdl in models + plain_models:
         mdl.close()
@@ -280,6 +284,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle timing budget (0 = skip)")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / multi-period / N-1 legs")
     ap.add_argument("--batch-reps", type=int, default=20)
+    ap.add_argument("--eager", action="store_true", help="launch the headline sets without a HIP graph")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="first run a device-to-device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
 
@@ -300,6 +307,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     opf.lib()
+    if args.copy_mb > 0:
+        n = args.copy_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: 3 x {args.copy_mb} MiB device-to-device")
+        del src, dst
     h = bench_headline(args, torch, opf, synth, log)
     sets_per_s = h["n_sets"] / h["secs"]
     achieved = h["bytes_set"] / h["per_set"] / 1e9
@@ -320,7 +336,8 @@ def main():
             "workload": "plain polar AC-OPF callback sets, 10000-bus synthetic network "
                         "(13500 branches, 2000 generators), 1000 sets per step at seeded (x, y)",
             "n": h["dims"][0], "m": h["dims"][1], "nnzj": h["dims"][2], "nnzh": h["dims"][3],
-            "sets_per_step": args.sets_per_step, "launch": "HIP graph of back-to-back plain launches",
+            "sets_per_step": args.sets_per_step,
+            "launch": "eager plain launches" if args.eager else "HIP graph of back-to-back plain launches",
             "inputs_rotated": args.inputs, "outputs_rotated": 64,
         },
         "roofline": {

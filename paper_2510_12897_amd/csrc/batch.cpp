@@ -1,13 +1,13 @@
 // C-ABI of libopf: batched evaluation of many instances in one persistent
 // kernel launch replayed from a HIP graph, with a schedule autotuner.
 //
-// A schedule is (tile capacity, workgroups per compute unit).  The tile
-// capacity fixes which consecutive buses share a workgroup; the workgroup
-// count fixes how many persistent workgroups drain the queue.  Neither
-// changes any summation order (per-bus sums run over the bus's half-edges in
-// their fixed order, the objective over a fixed 256-lane tree), so every
-// schedule produces bitwise the same results as the plain per-instance
-// launch.
+// A schedule is (replica group, workgroups per compute unit): how many
+// consecutive periods or contingency copies one work item handles (its
+// descriptors are loaded once for all of them), and how many persistent
+// workgroups drain the queue.  Neither changes any summation order (segment
+// sums follow the host packing, objective partials are per generator chunk
+// and replica and are summed in index order), so every schedule produces
+// bitwise the same results as the plain per-instance launch.
 #include <map>
 #include <new>
 #include <tuple>
@@ -18,17 +18,8 @@ using namespace opf_internal;
 
 namespace {
 
-const int32_t kCaps[] = {128, 256, 512, 1024};
-const int32_t kWgPerCu[] = {1, 2, 4, 8};
-
-struct Sched {
-    int32_t cap = 0;               // effective tile capacity
-    opf::BatchInst* inst = nullptr;  // device [n_inst]
-    opf::BatchItem* items_eval = nullptr;  // device
-    opf::BatchItem* items_jt = nullptr;    // device
-    int32_t n_eval = 0, n_jt = 0;
-    size_t lds = 0;
-};
+const int32_t kGroups[] = {1, 2, 4, 8, 16};
+const int32_t kWgPerCu[] = {2, 4, 8, 16};
 
 struct GraphEntry {
     hipGraph_t graph = nullptr;
@@ -36,8 +27,14 @@ struct GraphEntry {
     opf::BatchArgs args{};
 };
 
-using GraphKey = std::tuple<int, int32_t, int32_t, const void*, const void*, const void*, const void*, const void*,
-                            const void*, const void*, const void*>;
+using GraphKey = std::tuple<int32_t, int32_t, int32_t, const void*, const void*, const void*, const void*,
+                            const void*, const void*, const void*, const void*>;
+
+struct Lists {
+    opf::BatchItem* ev = nullptr;  // device
+    opf::BatchItem* jt = nullptr;  // device
+    int32_t n_ev = 0, n_jt = 0;
+};
 
 }  // namespace
 
@@ -49,10 +46,12 @@ struct opf_batch_s {
     std::vector<int64_t> xoff, coff, joff, hoff;
     void* arena = nullptr;
     int32_t* counters = nullptr;
-    std::vector<Sched> scheds;
-    int sched = 0;
-    int32_t wg_per_cu = 4;
+    opf::BatchInst* inst = nullptr;  // device
+    std::vector<Lists> lists;        // one per candidate replica group
+    int sched = 0;                   // index into kGroups
+    int32_t wg_per_cu = 8;
     int32_t n_cu = 256;
+    size_t lds = 0;
     std::map<GraphKey, GraphEntry> graphs;
 };
 
@@ -68,42 +67,38 @@ void drop_graphs(opf_batch_s* b) {
     b->graphs.clear();
 }
 
-// Work items of one schedule: the objective reductions first (long, serial),
-// then the bus tiles, branch blocks and generator blocks of every instance.
-void make_items(const std::vector<opf::DevModel>& dms, std::vector<opf::BatchItem>& ev,
-                std::vector<opf::BatchItem>& jt) {
-    ev.clear();
-    jt.clear();
+// Work items for one replica group size: big buses first (the longest), then
+// the waves of bus segments, branch chunks and generator chunks of every
+// instance.  J^T v on a model whose copies share pg takes one generator per
+// item.
+void make_items(const std::vector<opf::DevModel>& dms, int32_t rg, int mode, std::vector<opf::BatchItem>& out) {
+    out.clear();
     const int32_t n = (int32_t)dms.size();
-    for (int32_t j = 0; j < n; j++) ev.push_back({j, opf::T_OBJ, 0, 0});
-    for (int32_t j = 0; j < n; j++)
-        for (int32_t r = 0; r < dms[j].nrep; r++)
-            for (int32_t t = 0; t < dms[j].ntiles; t++) jt.push_back({j, opf::T_BUS, t, r});
+    auto groups = [&](const opf::DevModel& d, int32_t kind, int32_t count, int32_t j) {
+        const int32_t g = std::min(std::max(rg, 1), d.nrep);
+        for (int32_t r0 = 0; r0 < d.nrep; r0 += g)
+            for (int32_t i = 0; i < count; i++) out.push_back({j, kind, i, r0, std::min(r0 + g, d.nrep), 0});
+    };
+    for (int32_t j = 0; j < n; j++) groups(dms[j], opf::T_BIG, dms[j].nbig, j);
+    for (int32_t j = 0; j < n; j++) groups(dms[j], opf::T_WAVE, dms[j].nwaves, j);
+    for (int32_t j = 0; j < n; j++) groups(dms[j], opf::T_BRANCH, dms[j].nbchunks, j);
     for (int32_t j = 0; j < n; j++) {
-        const int32_t nb = (dms[j].L + opf::kBlock - 1) / opf::kBlock;
-        for (int32_t r = 0; r < dms[j].nrep; r++)
-            for (int32_t t = 0; t < nb; t++) jt.push_back({j, opf::T_BRANCH, t, r});
+        const opf::DevModel& d = dms[j];
+        if (mode == 1 && d.npg == 1 && d.nrep > 1) {
+            for (int32_t k = 0; k < d.G; k++) out.push_back({j, opf::T_GEN, k, 0, d.nrep, 0});
+        } else {
+            groups(d, opf::T_GEN, d.ngchunks, j);
+        }
     }
-    for (int32_t j = 0; j < n; j++) {
-        const int32_t ng = (std::max(dms[j].G, dms[j].R) + opf::kBlock - 1) / opf::kBlock;
-        for (int32_t r = 0; r < dms[j].nrep; r++)
-            for (int32_t t = 0; t < ng; t++) jt.push_back({j, opf::T_GEN, t, r});
-    }
-    ev.insert(ev.end(), jt.begin(), jt.end());
 }
 
 int launch(opf_batch_s* b, const opf::BatchArgs& a0, hipStream_t stream) {
-    const Sched& s = b->scheds[b->sched];
+    const Lists& L = b->lists[b->sched];
     opf::BatchArgs a = a0;
-    a.inst = s.inst;
+    a.inst = b->inst;
     a.counters = b->counters;
-    if (a.mode == 0) {
-        a.items = s.items_eval;
-        a.n_items = s.n_eval;
-    } else {
-        a.items = s.items_jt;
-        a.n_items = s.n_jt;
-    }
+    a.items = a.mode == 0 ? L.ev : L.jt;
+    a.n_items = a.mode == 0 ? L.n_ev : L.n_jt;
     if (a.n_items == 0) return OPF_OK;
     const int32_t grid = std::max(1, std::min(a.n_items, b->n_cu * b->wg_per_cu));
     GraphKey key{b->sched, grid, a.mode, a.X, a.Y, a.sigma, a.F, a.G, a.C, a.J, a.H};
@@ -119,7 +114,7 @@ int launch(opf_batch_s* b, const opf::BatchArgs& a0, hipStream_t stream) {
         p.func = opf::batch_kernel_fn();
         p.gridDim = dim3(grid);
         p.blockDim = dim3(opf::kBlock);
-        p.sharedMemBytes = (unsigned)s.lds;
+        p.sharedMemBytes = (unsigned)b->lds;
         p.kernelParams = params;
         p.extra = nullptr;
         hipGraphNode_t node;
@@ -176,59 +171,35 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
             b->hoff[j + 1] = b->hoff[j] + ly.nnzh;
         }
 
-        // ---- pack: per-instance loads, per-(model, cap) tiles, then per
-        // schedule the instance descriptors and item lists
+        // ---- pack: queue counters, per-instance loads and objective scratch
+        // (zeroed), instance descriptors, item lists per replica group
         Packer pk;
         const size_t o_cnt = pk.reserve(2 * sizeof(int32_t));
-        std::vector<size_t> o_pd(n_inst, 0), o_qd(n_inst, 0);
+        std::vector<size_t> o_pd(n_inst, 0), o_qd(n_inst, 0), o_scr(n_inst, 0);
         std::vector<int32_t> stride(n_inst, 0);
-        if (inst_pd) {
-            int64_t off = 0;
-            for (int32_t j = 0; j < n_inst; j++) {
-                const opf::HostModel& hm = models[inst_model[j]]->hm;
+        int64_t off = 0;
+        for (int32_t j = 0; j < n_inst; j++) {
+            const opf::HostModel& hm = models[inst_model[j]]->hm;
+            if (inst_pd) {
                 const int64_t nl = (int64_t)hm.ly.N * (hm.ly.T > 1 ? hm.ly.T : 1);
                 o_pd[j] = pk.add(inst_pd + off, sizeof(double) * nl);
                 o_qd[j] = pk.add(inst_qd + off, sizeof(double) * nl);
                 stride[j] = hm.ly.T > 1 ? hm.ly.N : 0;
                 off += nl;
             }
+            o_scr[j] = pk.reserve(obj_scratch_bytes(hm));
         }
-        std::vector<int32_t> caps;
-        for (int32_t c : kCaps) {
-            int32_t eff = c;
-            for (int32_t k = 0; k < n_models; k++) eff = std::max(eff, models[k]->hm.max_degree);
-            if (std::find(caps.begin(), caps.end(), eff) == caps.end()) caps.push_back(eff);
-        }
-        struct Pending {
-            std::vector<size_t> tile_off;  // per model
-            std::vector<std::vector<int32_t>> tiles;
-            size_t inst_off, ev_off, jt_off;
-            int32_t n_ev, n_jt;
-            std::vector<opf::DevModel> dms;
-            std::vector<opf::BatchItem> ev, jt;
-        };
-        std::vector<Pending> pend(caps.size());
-        for (size_t s = 0; s < caps.size(); s++) {
-            Pending& P = pend[s];
-            P.tiles.resize(n_models);
-            P.tile_off.resize(n_models);
-            for (int32_t k = 0; k < n_models; k++) {
-                P.tiles[k] = opf::build_tiles(models[k]->hm, caps[s]);
-                P.tile_off[k] = pk.add(P.tiles[k]);
-            }
-            P.dms.resize(n_inst);
-            for (int32_t j = 0; j < n_inst; j++) {
-                opf::DevModel d = models[inst_model[j]]->dm;
-                d.ntiles = (int32_t)P.tiles[inst_model[j]].size() - 1;
-                d.tile_cap = caps[s];
-                P.dms[j] = d;
-            }
-            make_items(P.dms, P.ev, P.jt);
-            P.n_ev = (int32_t)P.ev.size();
-            P.n_jt = (int32_t)P.jt.size();
-            P.inst_off = pk.reserve(sizeof(opf::BatchInst) * n_inst);
-            P.ev_off = pk.add(P.ev);
-            P.jt_off = pk.add(P.jt);
+        const size_t o_inst = pk.reserve(sizeof(opf::BatchInst) * n_inst);
+        std::vector<opf::DevModel> dms(n_inst);
+        for (int32_t j = 0; j < n_inst; j++) dms[j] = models[inst_model[j]]->dm;
+        std::vector<std::pair<size_t, size_t>> lst_off;
+        std::vector<std::pair<int32_t, int32_t>> lst_n;
+        std::vector<opf::BatchItem> ev, jt;
+        for (int32_t g : kGroups) {
+            make_items(dms, g, 0, ev);
+            make_items(dms, g, 1, jt);
+            lst_off.push_back({pk.add(ev), pk.add(jt)});
+            lst_n.push_back({(int32_t)ev.size(), (int32_t)jt.size()});
         }
 
         DeviceGuard dg(dev);
@@ -245,38 +216,34 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
             return set_err(OPF_E_NOMEM, "device allocation of %zu bytes failed", pk.buf.size());
         }
         char* base = static_cast<char*>(b->arena);
-        // fill the instance descriptors now that device addresses are known
-        for (size_t s = 0; s < caps.size(); s++) {
-            Pending& P = pend[s];
-            opf::BatchInst* hi = reinterpret_cast<opf::BatchInst*>(pk.at(P.inst_off));
-            for (int32_t j = 0; j < n_inst; j++) {
-                opf::BatchInst bi;
-                bi.m = P.dms[j];
-                bi.m.tile_bus = reinterpret_cast<const int32_t*>(base + P.tile_off[inst_model[j]]);
-                if (inst_pd) {
-                    bi.m.pd = reinterpret_cast<const double*>(base + o_pd[j]);
-                    bi.m.qd = reinterpret_cast<const double*>(base + o_qd[j]);
-                    bi.m.load_stride = stride[j];
-                }
-                bi.xoff = b->xoff[j];
-                bi.coff = b->coff[j];
-                bi.joff = b->joff[j];
-                bi.hoff = b->hoff[j];
-                std::memcpy(&hi[j], &bi, sizeof bi);
+        opf::BatchInst* hi = reinterpret_cast<opf::BatchInst*>(pk.at(o_inst));
+        b->lds = 0;
+        for (int32_t j = 0; j < n_inst; j++) {
+            opf::BatchInst bi;
+            bi.m = dms[j];
+            if (inst_pd) {
+                bi.m.pd = reinterpret_cast<const double*>(base + o_pd[j]);
+                bi.m.qd = reinterpret_cast<const double*>(base + o_qd[j]);
+                bi.m.load_stride = stride[j];
             }
-            Sched sc;
-            sc.cap = caps[s];
-            sc.inst = reinterpret_cast<opf::BatchInst*>(base + P.inst_off);
-            sc.items_eval = reinterpret_cast<opf::BatchItem*>(base + P.ev_off);
-            sc.items_jt = reinterpret_cast<opf::BatchItem*>(base + P.jt_off);
-            sc.n_eval = P.n_ev;
-            sc.n_jt = P.n_jt;
-            opf::DevModel probe = P.dms[0];
-            probe.tile_cap = caps[s];
-            sc.lds = opf::set_lds_bytes(probe);
-            b->scheds.push_back(sc);
+            const size_t parts = sizeof(double) * (size_t)bi.m.ngchunks * bi.m.npg;
+            bi.m.obj_part = reinterpret_cast<double*>(base + o_scr[j]);
+            bi.m.obj_ticket = reinterpret_cast<int32_t*>(base + o_scr[j] + ((parts + 255) & ~size_t(255)));
+            bi.xoff = b->xoff[j];
+            bi.coff = b->coff[j];
+            bi.joff = b->joff[j];
+            bi.hoff = b->hoff[j];
+            std::memcpy(&hi[j], &bi, sizeof bi);
+            b->lds = std::max(b->lds, opf::set_lds_bytes(bi.m));
         }
-        std::memset(pk.at(o_cnt), 0, 2 * sizeof(int32_t));
+        for (size_t s = 0; s < lst_off.size(); s++) {
+            Lists L;
+            L.ev = reinterpret_cast<opf::BatchItem*>(base + lst_off[s].first);
+            L.jt = reinterpret_cast<opf::BatchItem*>(base + lst_off[s].second);
+            L.n_ev = lst_n[s].first;
+            L.n_jt = lst_n[s].second;
+            b->lists.push_back(L);
+        }
         hipError_t e = hipMemcpy(b->arena, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             dev_free(b->alloc, b->arena);
@@ -284,13 +251,8 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
             return hip_err(e, "batch upload");
         }
         b->counters = reinterpret_cast<int32_t*>(base + o_cnt);
-        // default schedule: tile capacity 256 (or the smallest that fits)
+        b->inst = reinterpret_cast<opf::BatchInst*>(base + o_inst);
         b->sched = 0;
-        for (size_t s = 0; s < b->scheds.size(); s++)
-            if (b->scheds[s].cap >= 256) {
-                b->sched = (int)s;
-                break;
-            }
     } catch (const std::bad_alloc&) {
         delete b;
         return set_err(OPF_E_NOMEM, "host allocation failed");
@@ -323,23 +285,20 @@ int opf_batch_offsets(opf_batch b, int64_t* xoff, int64_t* coff, int64_t* joff, 
     return OPF_OK;
 }
 
-int opf_batch_schedule(opf_batch b, int32_t* tile_cap, int32_t* wg_per_cu) {
+int opf_batch_schedule(opf_batch b, int32_t* replica_group, int32_t* wg_per_cu) {
     if (!valid(b)) return set_err(OPF_E_STATE, "invalid or destroyed batch handle");
-    if (tile_cap) *tile_cap = b->scheds[b->sched].cap;
+    if (replica_group) *replica_group = kGroups[b->sched];
     if (wg_per_cu) *wg_per_cu = b->wg_per_cu;
     return OPF_OK;
 }
 
-int opf_batch_set_schedule(opf_batch b, int32_t tile_cap, int32_t wg_per_cu) {
+int opf_batch_set_schedule(opf_batch b, int32_t replica_group, int32_t wg_per_cu) {
     if (!valid(b)) return set_err(OPF_E_STATE, "invalid or destroyed batch handle");
     if (wg_per_cu < 1 || wg_per_cu > 64) return set_err(OPF_E_ARG, "wg_per_cu must be in [1, 64]");
-    int found = -1;
-    for (size_t s = 0; s < b->scheds.size(); s++)
-        if (b->scheds[s].cap >= tile_cap) {
-            found = (int)s;
-            break;
-        }
-    if (found < 0) found = (int)b->scheds.size() - 1;
+    if (replica_group < 1 || replica_group > 65536) return set_err(OPF_E_ARG, "replica_group must be in [1, 65536]");
+    int found = 0;
+    for (int s = 0; s < (int)(sizeof kGroups / sizeof kGroups[0]); s++)
+        if (kGroups[s] <= replica_group) found = s;
     b->sched = found;
     b->wg_per_cu = wg_per_cu;
     return OPF_OK;
@@ -395,7 +354,9 @@ int opf_batch_tune(opf_batch b, void* stream) {
             rc = hip_err(e, "tuning setup");
             break;
         }
-        for (size_t sc = 0; sc < b->scheds.size() && rc == OPF_OK; sc++) {
+        for (size_t sc = 0; sc < b->lists.size() && rc == OPF_OK; sc++) {
+            // replica groups beyond the largest replica count are duplicates
+            if (sc > 0 && b->lists[sc].n_ev == b->lists[sc - 1].n_ev) continue;
             for (int32_t wg : kWgPerCu) {
                 b->sched = (int)sc;
                 b->wg_per_cu = wg;

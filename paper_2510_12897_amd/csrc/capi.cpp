@@ -64,12 +64,14 @@ void dev_free(const Allocator& a, void* p) {
         (void)hipFree(p);
 }
 
-ModelOffsets pack_model(Packer& pk, const opf::HostModel& hm, const std::vector<int32_t>& tiles) {
+ModelOffsets pack_model(Packer& pk, const opf::HostModel& hm) {
     ModelOffsets o{};
     o.f_bus = pk.add(hm.f_bus);
     o.t_bus = pk.add(hm.t_bus);
     o.coef = pk.add(hm.coef);
     o.rate2 = pk.add(hm.rate2);
+    o.slots = pk.add(hm.slots);
+    o.big_bus = pk.add(hm.big_bus);
     o.adj_ptr = pk.add(hm.adj_ptr);
     o.he = pk.add(hm.he);
     o.he_grp = pk.add(hm.he_grp);
@@ -92,18 +94,32 @@ ModelOffsets pack_model(Packer& pk, const opf::HostModel& hm, const std::vector<
     o.ref_ptr = pk.add(hm.ref_ptr);
     o.ref_list = pk.add(hm.ref_list);
     o.outage = pk.add(hm.outage);
-    o.tiles = pk.add(tiles);
     return o;
 }
 
-opf::DevModel make_dev(const opf::HostModel& hm, const std::vector<int32_t>& tiles, int32_t cap, char* base,
-                       const ModelOffsets& o) {
+namespace {
+int32_t gen_chunks(const opf::HostModel& hm) {
+    return (std::max(hm.ly.G, hm.ly.R) + opf::kBlock - 1) / opf::kBlock;
+}
+}  // namespace
+
+size_t obj_scratch_bytes(const opf::HostModel& hm) {
+    // partials, then the ticket on its own 256-byte line
+    const size_t parts = sizeof(double) * (size_t)gen_chunks(hm) * hm.ly.npg;
+    return ((parts + 255) & ~size_t(255)) + 256;
+}
+
+opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets& o, char* scratch) {
     const opf::Layout& ly = hm.ly;
     opf::DevModel d{};
     d.N = ly.N; d.L = ly.L; d.G = ly.G; d.R = ly.R; d.T = ly.T;
     d.nrep = ly.nrep; d.npg = ly.npg; d.load_stride = hm.load_stride;
-    d.ntiles = (int32_t)tiles.size() - 1;
-    d.tile_cap = std::max(cap, std::max<int32_t>(hm.max_degree, 1));
+    d.nwaves = hm.nwaves;
+    d.nbig = (int32_t)hm.big_bus.size();
+    d.big_cap = 0;
+    for (int32_t b : hm.big_bus) d.big_cap = std::max(d.big_cap, hm.adj_ptr[b + 1] - hm.adj_ptr[b]);
+    d.nbchunks = (ly.L + opf::kBlock - 1) / opf::kBlock;
+    d.ngchunks = gen_chunks(hm);
     d.x_va = ly.x_va; d.x_vm = ly.x_vm; d.x_pg = ly.x_pg; d.x_qg = ly.x_qg; d.x_p = ly.x_p; d.x_q = ly.x_q;
     using namespace opf;
     d.c_ref = ly.c_blk[B_REF]; d.c_pfr = ly.c_blk[B_PFR]; d.c_qfr = ly.c_blk[B_QFR];
@@ -118,13 +134,15 @@ opf::DevModel make_dev(const opf::HostModel& hm, const std::vector<int32_t>& til
     d.hva_rep = ly.hva_rep; d.hvm_rep = ly.hvm_rep;
 #define P32(name) d.name = reinterpret_cast<const int32_t*>(base + o.name)
 #define PDB(name) d.name = reinterpret_cast<const double*>(base + o.name)
-    P32(f_bus); P32(t_bus); PDB(coef); PDB(rate2);
+    P32(f_bus); P32(t_bus); PDB(coef); PDB(rate2); P32(slots); P32(big_bus);
     P32(adj_ptr); P32(he); P32(he_grp); P32(nlo); P32(ndist); P32(hva_off); P32(hvm_off); P32(jbal_off);
     P32(gen_ptr); P32(gen_list); PDB(gs); PDB(bs); PDB(pd); PDB(qd);
     PDB(c2); PDB(c1); PDB(c0); P32(gen_bus); P32(ref_bus); P32(ref_ptr); P32(ref_list); P32(outage);
 #undef P32
 #undef PDB
-    d.tile_bus = reinterpret_cast<const int32_t*>(base + o.tiles);
+    const size_t parts = sizeof(double) * (size_t)d.ngchunks * ly.npg;
+    d.obj_part = reinterpret_cast<double*>(scratch);
+    d.obj_ticket = reinterpret_cast<int32_t*>(scratch + ((parts + 255) & ~size_t(255)));
     return d;
 }
 
@@ -144,7 +162,7 @@ int check_model(opf_model m) {
 int launch_set(opf_model m, const opf::EvalOut& o, void* stream) {
     DeviceGuard dg(m->device);
     if (dg.err != hipSuccess) return hip_err(dg.err, "hipSetDevice");
-    hipError_t e = opf::launch_eval_set(m->dm, o, static_cast<hipStream_t>(stream));
+    hipError_t e = opf::launch_eval_set(m->dm, o, kPlainReplicaGroup, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_err(e, "callback kernel launch");
     return OPF_OK;
 }
@@ -227,11 +245,11 @@ int opf_model_create(const opf_case* cs, const opf_opts* opts, int device, opf_m
         }
         m->device = device;
         m->alloc = current_allocator();
-        m->tiles = opf::build_tiles(m->hm, kDefaultTileCap);
         const opf::Layout& ly = m->hm.ly;
 
         Packer pk;
-        ModelOffsets mo = pack_model(pk, m->hm, m->tiles);
+        ModelOffsets mo = pack_model(pk, m->hm);
+        const size_t o_scr = pk.reserve(obj_scratch_bytes(m->hm));  // zeroed: the ticket starts at 0
         const size_t oj_r = pk.reserve(sizeof(int32_t) * ly.nnzj());
         const size_t oj_c = pk.reserve(sizeof(int32_t) * ly.nnzj());
         const size_t oh_r = pk.reserve(sizeof(int32_t) * ly.nnzh);
@@ -262,7 +280,7 @@ int opf_model_create(const opf_case* cs, const opf_opts* opts, int device, opf_m
             return hip_err(e, "model upload");
         }
         char* base = static_cast<char*>(m->arena);
-        m->dm = make_dev(m->hm, m->tiles, kDefaultTileCap, base, mo);
+        m->dm = make_dev(m->hm, base, mo, base + o_scr);
         m->jrow = reinterpret_cast<const int32_t*>(base + oj_r);
         m->jcol = reinterpret_cast<const int32_t*>(base + oj_c);
         m->hrow = reinterpret_cast<const int32_t*>(base + oh_r);
@@ -448,7 +466,7 @@ int opf_jtprod(opf_model m, const double* x, const double* v, double* out, void*
     if (!x || !v || !out) return set_err(OPF_E_ARG, "x, v and out must be non-NULL");
     DeviceGuard dg(m->device);
     if (dg.err != hipSuccess) return hip_err(dg.err, "hipSetDevice");
-    hipError_t e = opf::launch_jtprod(m->dm, x, v, out, static_cast<hipStream_t>(stream));
+    hipError_t e = opf::launch_jtprod(m->dm, x, v, out, kPlainReplicaGroup, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_err(e, "jtprod kernel launch");
     return OPF_OK;
 }

@@ -9,18 +9,19 @@ namespace opf {
 
 // Work item kinds of one callback set.
 enum TaskKind : int32_t {
-    T_BUS = 0,     // a tile of consecutive buses: balance rows, Hessian bus rows
-    T_BRANCH = 1,  // a block of branches: flow, angle, thermal rows, arc Hessian diagonals
-    T_GEN = 2,     // a block of generators: gradient, pg Hessian diagonal, ref and ramp rows
-    T_OBJ = 3      // the objective reduction (one workgroup)
+    T_BIG = 0,     // one bus whose segment does not fit a wave (LDS tile path)
+    T_WAVE = 1,    // 64 lanes of packed bus segments: balance rows, Hessian bus rows
+    T_BRANCH = 2,  // 64 branches: flow, angle, thermal rows, arc Hessian diagonals
+    T_GEN = 3      // 64 generators: gradient, pg Hessian diagonal, objective partial, ref and ramp rows
 };
 
-constexpr int kBlock = 256;        // threads per workgroup, every task
-constexpr int kLdsPerEdge = 8;     // doubles staged in LDS per half-edge
+constexpr int kBlock = 64;          // threads per workgroup (one wave), every task
+constexpr int kLdsPerEdge = 8;      // doubles staged in LDS per lane / half-edge
 
 struct DevModel {
     int32_t N, L, G, R, T, nrep, npg, load_stride;
-    int32_t ntiles, tile_cap;
+    int32_t nwaves, nbig, big_cap;   // wave count, big-bus count, LDS half-edge capacity of the big path
+    int32_t nbchunks, ngchunks;      // branch / generator chunks of kBlock
     int64_t x_va, x_vm, x_pg, x_qg, x_p, x_q;
     int64_t c_ref, c_pfr, c_qfr, c_pto, c_qto, c_ang, c_balp, c_balq, c_thf, c_tht, c_ramp;
     int64_t j_ref, j_pfr, j_qfr, j_pto, j_qto, j_ang, j_balp, j_balq, j_thf, j_tht, j_ramp, jbal_rep;
@@ -30,7 +31,10 @@ struct DevModel {
     const int32_t* t_bus;
     const double* coef;    // [8][L]: Gff Bff Gft Bft Gtt Btt Gtf Btf
     const double* rate2;   // [L]
-    // buses
+    // wave-packed bus segments: 8 int32 per lane (kind, ref, bus, other, jpos, h0, h1, h2)
+    const int32_t* slots;  // [nwaves * kBlock * 8]
+    const int32_t* big_bus;   // [nbig]
+    // bus adjacency (the big-bus path)
     const int32_t* adj_ptr;   // [N+1]
     const int32_t* he;        // [2L] branch << 1 | from-side flag, sorted by (neighbour, branch)
     const int32_t* he_grp;    // [2L] distinct-neighbour rank within the bus
@@ -54,7 +58,10 @@ struct DevModel {
     const int32_t* ref_ptr;   // [N+1] reference rows per bus
     const int32_t* ref_list;  // [R]
     const int32_t* outage;    // [nrep] branch out of service in a replica, or -1
-    const int32_t* tile_bus;  // [ntiles+1] first bus of every tile
+    // objective scratch: one partial per (generator chunk, pg replica) and a
+    // self-resetting arrival counter
+    double* obj_part;         // [ngchunks * npg]
+    int32_t* obj_ticket;      // [1]
 };
 
 struct EvalOut {
@@ -68,14 +75,13 @@ struct EvalOut {
     double* H;
 };
 
-// Work counts of one callback set (grid decoding of the plain launch).
+// Work counts of one plain launch.  Items are ordered big buses, waves,
+// branch chunks, generator chunks; each covers `rg` consecutive replicas.
 struct SetGrid {
-    int32_t n_bus;      // bus tiles x replicas
-    int32_t n_branch;   // branch blocks x replicas
-    int32_t n_gen;      // generator blocks x replicas
-    int32_t n_obj;      // 0 or 1
-    int32_t branch_blocks, gen_blocks;  // per replica
-    int32_t total() const { return n_bus + n_branch + n_gen + n_obj; }
+    int32_t n_big, n_wave, n_branch, n_gen;  // item counts (replica groups included)
+    int32_t rg, nrg;                          // replicas per item, replica groups
+    int32_t gen_per_item;                     // 0 = chunks of kBlock generators; 1 = one generator a wave
+    int32_t total() const { return n_big + n_wave + n_branch + n_gen; }
 };
 
 }  // namespace opf

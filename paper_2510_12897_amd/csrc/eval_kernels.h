@@ -7,19 +7,21 @@
 
 namespace opf {
 
-// Work counts and LDS size of one callback set on one model.
-SetGrid plan_set(const DevModel& m, const EvalOut& o);
+// Work counts of one launch on one model (mode 0: callback set, 1: J^T v),
+// each item covering `rg` consecutive replicas, and its LDS size.
+SetGrid plan_set(const DevModel& m, const EvalOut& o, int32_t mode, int32_t rg);
 size_t set_lds_bytes(const DevModel& m);
 
 // One callback set (any subset of f, g, c, J, H) on `stream`.
-hipError_t launch_eval_set(const DevModel& m, const EvalOut& o, hipStream_t stream);
+hipError_t launch_eval_set(const DevModel& m, const EvalOut& o, int32_t rg, hipStream_t stream);
 
 // out = J(x)^T v on `stream`.
-hipError_t launch_jtprod(const DevModel& m, const double* x, const double* v, double* out, hipStream_t stream);
+hipError_t launch_jtprod(const DevModel& m, const double* x, const double* v, double* out, int32_t rg,
+                         hipStream_t stream);
 
 // ---- batched evaluation: a persistent kernel over a queue of work items.
 struct BatchItem {
-    int32_t inst, kind, idx, rep;
+    int32_t inst, kind, idx, r0, r1, pad;  // replicas [r0, r1)
 };
 
 struct BatchInst {
@@ -38,8 +40,6 @@ struct BatchArgs {
     double *F, *G, *C, *J, *H;
     int32_t mode;            // 0 = callback set, 1 = J^T v (Y holds V, G holds OUT)
 };
-
-hipError_t launch_batch(const BatchArgs& a, int32_t grid, size_t lds_bytes, hipStream_t stream);
 
 // The persistent kernel's entry, for graph kernel nodes (argument: BatchArgs).
 void* batch_kernel_fn();

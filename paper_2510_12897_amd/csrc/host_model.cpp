@@ -272,26 +272,57 @@ int build_host_model(const opf_case* cs, const opf_opts* opts, HostModel& hm, st
     ly.nnzh = ly.h_q + 2LL * L * P;
     if (ly.nnzh >= std::numeric_limits<int32_t>::max())
         return fail(err, OPF_E_CASE, "model too large for int32 indices");
+    build_slots(hm);
     return OPF_OK;
 }
 
-std::vector<int32_t> build_tiles(const HostModel& hm, int32_t cap) {
-    cap = std::max(cap, std::max<int32_t>(hm.max_degree, 1));
-    std::vector<int32_t> tiles{0};
-    const int32_t N = hm.ly.N;
-    int32_t edges = 0, buses = 0;
+void build_slots(HostModel& hm) {
+    const int32_t N = hm.ly.N, L = hm.ly.L;
+    hm.slots.clear();
+    hm.big_bus.clear();
+    int32_t lane = 0;
+    auto push = [&](int32_t kind, int32_t ref, int32_t bus, int32_t other, int32_t jpos, int32_t h0, int32_t h1,
+                    int32_t h2) {
+        const int32_t f[8] = {kind, ref, bus, other, jpos, h0, h1, h2};
+        hm.slots.insert(hm.slots.end(), f, f + 8);
+        lane = (lane + 1) % kWaveLanes;
+    };
+    auto pad_wave = [&]() {
+        while (lane != 0) push(SK_IDLE, -1, -1, -1, -1, -1, -1, -1);
+    };
     for (int32_t i = 0; i < N; i++) {
-        const int32_t deg = hm.adj_ptr[i + 1] - hm.adj_ptr[i];
-        if (buses > 0 && (edges + deg > cap || buses + 1 > cap)) {
-            tiles.push_back(i);
-            edges = 0;
-            buses = 0;
+        const int32_t e0 = hm.adj_ptr[i], e1 = hm.adj_ptr[i + 1], deg = e1 - e0;
+        const int32_t g0 = hm.gen_ptr[i], ng = hm.gen_ptr[i + 1] - g0;
+        const int32_t seg = 1 + deg + ng;
+        if (seg > kWaveLanes) {
+            hm.big_bus.push_back(i);
+            continue;
         }
-        edges += deg;
-        buses += 1;
+        if (lane + seg > kWaveLanes) pad_wave();
+        const int32_t nlo = hm.nlo[i], nd = hm.ndist[i];
+        const int32_t hva = hm.hva_off[i], hvm = hm.hvm_off[i], jrow = hm.jbal_off[i];
+        push(SK_HEAD | (seg << 8), -1, i, -1, jrow, deg > 0 ? hva + nlo : -1, deg > 0 ? hvm + nlo : -1,
+             deg > 0 ? hvm + nd + 1 + nlo : hvm);
+        for (int32_t q = e0; q < e1; q++) {
+            const int32_t code = hm.he[q], l = code >> 1, from = code & 1;
+            const int32_t k = from ? hm.t_bus[l] : hm.f_bus[l];
+            const int32_t grp = hm.he_grp[q];
+            const bool leader = (q == e0) || hm.he_grp[q - 1] != grp;
+            int32_t glen = 0;
+            if (leader)
+                for (int32_t u = q; u < e1 && hm.he_grp[u] == grp; u++) glen++;
+            // rank of this half-edge's arc among the arcs at bus i (ascending arc index)
+            const int32_t arc = from ? l : L + l;
+            const auto ab = hm.arc_list.begin() + hm.arc_ptr[i], ae = hm.arc_list.begin() + hm.arc_ptr[i + 1];
+            const int32_t arank = (int32_t)(std::lower_bound(ab, ae, arc) - ab);
+            const int32_t kind = SK_EDGE | (from << 2) | ((leader ? 1 : 0) << 3) | (glen << 8);
+            push(kind, l, i, k, jrow + 1 + ng + arank, leader && k < i ? hva + grp : -1,
+                 leader ? hvm + grp + (k > i ? 1 : 0) : -1, leader && k < i ? hvm + nd + 1 + grp : -1);
+        }
+        for (int32_t q = 0; q < ng; q++) push(SK_GEN, hm.gen_list[g0 + q], i, -1, jrow + 1 + q, -1, -1, -1);
     }
-    tiles.push_back(N);
-    return tiles;
+    pad_wave();
+    hm.nwaves = (int32_t)(hm.slots.size() / (8 * kWaveLanes));
 }
 
 void fill_pattern(const HostModel& hm, int32_t* jr, int32_t* jc, int32_t* hr, int32_t* hc) {

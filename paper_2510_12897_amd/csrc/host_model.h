@@ -56,7 +56,31 @@ struct HostModel {
     std::vector<int32_t> ref_ptr, ref_list;    // reference rows per bus, ascending
     std::vector<int32_t> outage;               // per replica: branch out of service or -1
     int32_t max_degree = 0;
+
+    // Bus segments packed into 64-lane waves.  Each bus with at most
+    // kWaveLanes - 1 incident half-edges plus generators owns a contiguous
+    // segment [head, half-edges in (neighbour, branch) order, generators]
+    // that never straddles a wave.  Every lane has 8 int32 fields (see
+    // SlotField); output positions are relative to the replica's block.
+    std::vector<int32_t> slots;                // [nwaves * kWaveLanes * 8]
+    int32_t nwaves = 0;
+    std::vector<int32_t> big_bus;              // buses whose segment does not fit a wave
 };
+
+constexpr int32_t kWaveLanes = 64;
+
+// Slot fields (int32 each): kind, ref, bus, other, jpos, h0, h1, h2.
+//  kind bits [0,2): 0 idle, 1 head, 2 half-edge, 3 generator;
+//       bit 2: half-edge at the branch's from bus; bit 3: first half-edge of
+//       its neighbour group; bits [8,16): segment length (head) or group
+//       length (group leader).
+//  head:      bus i; jpos = first entry of i's balance Jacobian rows;
+//             h0/h1/h2 = Hessian (va_i,va_i), (vm_i,va_i), (vm_i,vm_i) (-1 if absent)
+//  half-edge: ref = branch, bus = i, other = neighbour; jpos = its +1 entry;
+//             h0/h1/h2 = (va_i,va_k), (vm_i,va_k), (vm_i,vm_k) for the group
+//             leader (-1 if absent or not the leader)
+//  generator: ref = generator, bus = i; jpos = its -1 entry
+enum SlotKind { SK_IDLE = 0, SK_HEAD = 1, SK_EDGE = 2, SK_GEN = 3 };
 
 // Validation; returns OPF_OK or an error code with a message.
 int validate(const opf_case* cs, const opf_opts* opts, std::string& err);
@@ -64,8 +88,8 @@ int validate(const opf_case* cs, const opf_opts* opts, std::string& err);
 // Full host model; returns OPF_OK or an error code.
 int build_host_model(const opf_case* cs, const opf_opts* opts, HostModel& hm, std::string& err);
 
-// Bus tiles: consecutive buses whose half-edges fit `cap` (cap >= max degree).
-std::vector<int32_t> build_tiles(const HostModel& hm, int32_t cap);
+// Pack the bus segments into waves (fills hm.slots, hm.nwaves, hm.big_bus).
+void build_slots(HostModel& hm);
 
 // Pattern into host buffers (any may be null).
 void fill_pattern(const HostModel& hm, int32_t* jrows, int32_t* jcols, int32_t* hrows, int32_t* hcols);

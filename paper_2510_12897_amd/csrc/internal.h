@@ -64,17 +64,20 @@ struct Packer {
 
 constexpr uint64_t kModelMagic = 0x4f50464d4f44454cull;  // "OPFMODEL"
 constexpr uint64_t kBatchMagic = 0x4f50464241544348ull;  // "OPFBATCH"
-constexpr int32_t kDefaultTileCap = 256;
 
 // Offsets of the model arrays inside a packed arena.
 struct ModelOffsets {
-    size_t f_bus, t_bus, coef, rate2, adj_ptr, he, he_grp, nlo, ndist, hva_off, hvm_off, jbal_off, gen_ptr,
-        gen_list, gs, bs, pd, qd, c2, c1, c0, gen_bus, ref_bus, ref_ptr, ref_list, outage, tiles;
+    size_t f_bus, t_bus, coef, rate2, slots, big_bus, adj_ptr, he, he_grp, nlo, ndist, hva_off, hvm_off, jbal_off,
+        gen_ptr, gen_list, gs, bs, pd, qd, c2, c1, c0, gen_bus, ref_bus, ref_ptr, ref_list, outage;
 };
 
-ModelOffsets pack_model(Packer& pk, const opf::HostModel& hm, const std::vector<int32_t>& tiles);
-opf::DevModel make_dev(const opf::HostModel& hm, const std::vector<int32_t>& tiles, int32_t cap, char* base,
-                       const ModelOffsets& o);
+ModelOffsets pack_model(Packer& pk, const opf::HostModel& hm);
+// Objective scratch of one evaluation stream: partials and the ticket.
+size_t obj_scratch_bytes(const opf::HostModel& hm);
+opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets& o, char* scratch);
+
+// Replica grouping of plain launches: one replica per work item.
+constexpr int32_t kPlainReplicaGroup = 1;
 
 }  // namespace opf_internal
 
@@ -83,7 +86,6 @@ struct opf_model_s {
     int device = 0;
     opf_internal::Allocator alloc{};
     opf::HostModel hm;
-    std::vector<int32_t> tiles;
     void* arena = nullptr;
     opf::DevModel dm{};
     const int32_t *jrow = nullptr, *jcol = nullptr, *hrow = nullptr, *hcol = nullptr;

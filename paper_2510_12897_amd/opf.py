@@ -388,12 +388,13 @@ class Batch:
         return self.schedule()
 
     def schedule(self):
-        cap, wg = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().opf_batch_schedule(self._h, ctypes.byref(cap), ctypes.byref(wg)))
-        return cap.value, wg.value
+        """(replicas per work item, persistent workgroups per compute unit)."""
+        rg, wg = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().opf_batch_schedule(self._h, ctypes.byref(rg), ctypes.byref(wg)))
+        return rg.value, wg.value
 
-    def set_schedule(self, tile_cap: int, wg_per_cu: int):
-        _check(lib().opf_batch_set_schedule(self._h, int(tile_cap), int(wg_per_cu)))
+    def set_schedule(self, replica_group: int, wg_per_cu: int):
+        _check(lib().opf_batch_set_schedule(self._h, int(replica_group), int(wg_per_cu)))
 
     def _new(self, n):
         torch = _torch()
