@@ -243,6 +243,72 @@ int opf_batch_eval(opf_batch batch, const double *X, const double *Y, const doub
 int opf_batch_jtprod(opf_batch batch, const double *X, const double *V, double *OUT,
                      void *stream);
 
+/* Replace every instance's loads (device buffers laid out like inst_pd /
+ * inst_qd of opf_batch_create) by an asynchronous copy on `stream`.
+ * OPF_E_STATE if the batch was created without per-instance loads. */
+int opf_batch_set_loads(opf_batch batch, const double *pd, const double *qd, void *stream);
+
+/* Overwrite the arc variables p, q of every instance in X by the branch
+ * flows F(vm, va) at X's voltages (so every flow-definition row of c(X) is
+ * zero).  One launch. */
+int opf_batch_flows(opf_batch batch, double *X, void *stream);
+
+/* ------------------------------------------------ learned warm-start proxy */
+/* Kernels of a multilayer perceptron that maps loads to (vm, va, pg, qg),
+ * trained on the FP64 penalty the callbacks compute (ML proxies for OPF are
+ * the paper's related work, Sec. I; feasibility is the open issue).  All
+ * pointers are device pointers; all matrices row-major; FP32 unless noted.
+ * Matrix dimensions and leading dimensions must be multiples of 4 and the
+ * buffers 16-byte aligned (OPF_E_ARG otherwise). */
+
+/* C[M,N] = A[M,K] B[K,N] on the BF16 matrix cores: FP32 operands rounded to
+ * BF16 (nearest even), FP32 accumulation.  variant selects the storage of A
+ * and B:  0  A(i,k) = A[i*lda+k],  B(k,j) = B[j*ldb+k]   (x W^T)
+ *         1  A(i,k) = A[i*lda+k],  B(k,j) = B[k*ldb+j]   (dy W)
+ *         2  A(i,k) = A[k*lda+i],  B(k,j) = B[k*ldb+j]   (dy^T x)
+ *         3  A(i,k) = A[k*lda+i],  B(k,j) = B[j*ldb+k]
+ * bias (may be NULL) is added per column; if act is non-NULL it receives
+ * GELU(C) (exact erf form).  accumulate != 0 adds to the existing C. */
+int prox_gemm_bf16(int variant, const float *A, int lda, const float *B, int ldb, float *C, int ldc, int M, int N,
+                   int K, const float *bias, float *act, int accumulate, void *stream);
+
+/* dpre = dact * GELU'(pre), n elements. */
+int prox_gelu_bwd(const float *pre, const float *dact, float *dpre, int64_t n, void *stream);
+
+/* out[j] = scale * sum_i X[i, j] for X [M, N], summed in a fixed order;
+ * work holds ((M + 255) / 256) * N floats. */
+int prox_colsum(const float *X, int M, int N, float *work, float *out, float scale, void *stream);
+
+/* One Adam step (Kingma and Ba 2015, bias-corrected) on n parameters;
+ * step counts from 1. */
+int prox_adam(float *p, const float *g, float *m1, float *m2, int64_t n, float lr, float beta1, float beta2,
+              float eps, int step, void *stream);
+
+/* z [B, 2N+2G] (blocks vm, va, pg, qg) -> the va, vm, pg, qg entries of X
+ * [B, n] (FP64): vm, pg, qg = lower + (upper - lower) sigmoid(z); va =
+ * va_span tanh(z), 0 at reference buses; p, q set to 0.  Static models only
+ * (OPF_E_ARG otherwise). */
+int prox_squash_fwd(opf_model model, const float *z, int B, double va_span, double *X, void *stream);
+
+/* dz [B, 2N+2G] = scale * (d x / d z)^T g for the va, vm, pg, qg entries of
+ * g = gX1 + gX2 + obj_scale * gObj ([B, n] FP64 each; gX2 and gObj may be
+ * NULL). */
+int prox_squash_bwd(opf_model model, const float *z, int B, double va_span, const double *gX1, const double *gX2,
+                    const double *gObj, double obj_scale, float *dz, float scale, void *stream);
+
+/* Per instance b of C [B, m], X [B, n]: pen[b] = rho * (sum of squared
+ * constraint violations over the non-flow rows + squared bound violations of
+ * p, q); cvio[b] = largest violation over every row and the p, q bounds
+ * (the paper's Cvio, Sec. V-A); W [B, m] = d pen / d c (zero on the flow
+ * rows); gpq [B, 4L] = d pen / d (p, q). */
+int prox_penalty(opf_model model, const double *C, const double *X, double rho, int B, double *pen, double *cvio,
+                 double *W, double *gpq, void *stream);
+
+/* W2 [B, m]: minus (G1 + gpq) of each arc variable placed on its flow row,
+ * zero elsewhere, so that J^T W2 carries a gradient on p = F(vm, va) back to
+ * the voltages. */
+int prox_chain_weights(opf_model model, const double *G1, const double *gpq, int B, double *W2, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,13 +1,16 @@
 // C-ABI of libopf: batched evaluation of many instances in one persistent
 // kernel launch replayed from a HIP graph, with a schedule autotuner.
 //
-// A schedule is (replica group, workgroups per compute unit): how many
-// consecutive periods or contingency copies one work item handles (its
-// descriptors are loaded once for all of them), and how many persistent
-// workgroups drain the queue.  Neither changes any summation order (segment
-// sums follow the host packing, objective partials are per generator chunk
-// and replica and are summed in index order), so every schedule produces
-// bitwise the same results as the plain per-instance launch.
+// An evaluation is two persistent launches chained in one graph: the branch
+// phase of every instance, then the bus phase.  A schedule is (replica
+// group, workgroups per compute unit): how many consecutive periods or
+// contingency copies one work item handles (its descriptors are loaded once
+// for all of them), and how many persistent workgroups drain each queue.
+// Neither changes any summation order (segment sums follow the host
+// packing, objective partials are per generator chunk and replica and are
+// summed in index order), so every schedule produces bitwise the same
+// results as the plain per-instance launch.
+#include <array>
 #include <map>
 #include <new>
 #include <tuple>
@@ -24,16 +27,15 @@ const int32_t kWgPerCu[] = {2, 4, 8, 16};
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    opf::BatchArgs args{};
+    opf::BatchArgs args[2]{};
 };
 
 using GraphKey = std::tuple<int32_t, int32_t, int32_t, const void*, const void*, const void*, const void*,
-                            const void*, const void*, const void*, const void*>;
+                            const void*, const void*, const void*, const void*>;  // schedule, wg/CU, mode, buffers
 
 struct Lists {
-    opf::BatchItem* ev = nullptr;  // device
-    opf::BatchItem* jt = nullptr;  // device
-    int32_t n_ev = 0, n_jt = 0;
+    opf::BatchItem* items[2][2] = {};  // device, [mode][phase]
+    int32_t n[2][2] = {};
 };
 
 }  // namespace
@@ -47,11 +49,13 @@ struct opf_batch_s {
     void* arena = nullptr;
     int32_t* counters = nullptr;
     opf::BatchInst* inst = nullptr;  // device
+    double* pd_all = nullptr;        // device per-instance loads (NULL if none)
+    double* qd_all = nullptr;
+    int64_t n_loads = 0;
     std::vector<Lists> lists;        // one per candidate replica group
     int sched = 0;                   // index into kGroups
     int32_t wg_per_cu = 8;
     int32_t n_cu = 256;
-    size_t lds = 0;
     std::map<GraphKey, GraphEntry> graphs;
 };
 
@@ -67,11 +71,12 @@ void drop_graphs(opf_batch_s* b) {
     b->graphs.clear();
 }
 
-// Work items for one replica group size: big buses first (the longest), then
-// the waves of bus segments, branch chunks and generator chunks of every
-// instance.  J^T v on a model whose copies share pg takes one generator per
-// item.
-void make_items(const std::vector<opf::DevModel>& dms, int32_t rg, int mode, std::vector<opf::BatchItem>& out) {
+// Work items for one replica group size and phase.  Phase 1: the branch
+// chunks of every instance.  Phase 2: big buses first (the longest), then
+// the waves of bus segments and the generator chunks of every instance;
+// J^T v on a model whose copies share pg takes one generator per item.
+void make_items(const std::vector<opf::DevModel>& dms, int32_t rg, int mode, int phase,
+                std::vector<opf::BatchItem>& out) {
     out.clear();
     const int32_t n = (int32_t)dms.size();
     auto groups = [&](const opf::DevModel& d, int32_t kind, int32_t count, int32_t j) {
@@ -79,9 +84,12 @@ void make_items(const std::vector<opf::DevModel>& dms, int32_t rg, int mode, std
         for (int32_t r0 = 0; r0 < d.nrep; r0 += g)
             for (int32_t i = 0; i < count; i++) out.push_back({j, kind, i, r0, std::min(r0 + g, d.nrep), 0});
     };
+    if (phase == 0) {
+        for (int32_t j = 0; j < n; j++) groups(dms[j], opf::T_BRANCH, dms[j].nbchunks, j);
+        return;
+    }
     for (int32_t j = 0; j < n; j++) groups(dms[j], opf::T_BIG, dms[j].nbig, j);
     for (int32_t j = 0; j < n; j++) groups(dms[j], opf::T_WAVE, dms[j].nwaves, j);
-    for (int32_t j = 0; j < n; j++) groups(dms[j], opf::T_BRANCH, dms[j].nbchunks, j);
     for (int32_t j = 0; j < n; j++) {
         const opf::DevModel& d = dms[j];
         if (mode == 1 && d.npg == 1 && d.nrep > 1) {
@@ -94,31 +102,42 @@ void make_items(const std::vector<opf::DevModel>& dms, int32_t rg, int mode, std
 
 int launch(opf_batch_s* b, const opf::BatchArgs& a0, hipStream_t stream) {
     const Lists& L = b->lists[b->sched];
-    opf::BatchArgs a = a0;
-    a.inst = b->inst;
-    a.counters = b->counters;
-    a.items = a.mode == 0 ? L.ev : L.jt;
-    a.n_items = a.mode == 0 ? L.n_ev : L.n_jt;
-    if (a.n_items == 0) return OPF_OK;
-    const int32_t grid = std::max(1, std::min(a.n_items, b->n_cu * b->wg_per_cu));
-    GraphKey key{b->sched, grid, a.mode, a.X, a.Y, a.sigma, a.F, a.G, a.C, a.J, a.H};
+    opf::BatchArgs a[2];
+    int32_t grid[2];
+    for (int ph = 0; ph < 2; ph++) {
+        a[ph] = a0;
+        a[ph].inst = b->inst;
+        a[ph].counters = b->counters;
+        // the flows mode runs the branch items only
+        const int lm = a0.mode == 2 ? 0 : a0.mode;
+        a[ph].items = L.items[lm][ph];
+        a[ph].n_items = (a0.mode == 2 && ph == 1) ? 0 : L.n[lm][ph];
+        grid[ph] = std::max(1, std::min(a[ph].n_items, b->n_cu * b->wg_per_cu));
+    }
+    GraphKey key{b->sched, b->wg_per_cu, a0.mode, a0.X, a0.Y, a0.sigma, a0.F, a0.G, a0.C, a0.J, a0.H};
     auto it = b->graphs.find(key);
     if (it == b->graphs.end()) {
         if (b->graphs.size() >= 512) drop_graphs(b);
         GraphEntry ge;
-        ge.args = a;
+        ge.args[0] = a[0];
+        ge.args[1] = a[1];
         hipError_t e = hipGraphCreate(&ge.graph, 0);
         if (e != hipSuccess) return hip_err(e, "hipGraphCreate");
-        hipKernelNodeParams p{};
-        void* params[] = {&ge.args};
-        p.func = opf::batch_kernel_fn();
-        p.gridDim = dim3(grid);
-        p.blockDim = dim3(opf::kBlock);
-        p.sharedMemBytes = (unsigned)b->lds;
-        p.kernelParams = params;
-        p.extra = nullptr;
-        hipGraphNode_t node;
-        e = hipGraphAddKernelNode(&node, ge.graph, nullptr, 0, &p);
+        hipGraphNode_t prev = nullptr;
+        for (int ph = 0; ph < 2 && e == hipSuccess; ph++) {
+            if (ge.args[ph].n_items == 0) continue;
+            hipKernelNodeParams p{};
+            void* params[] = {&ge.args[ph]};
+            p.func = opf::batch_kernel_fn();
+            p.gridDim = dim3(grid[ph]);
+            p.blockDim = dim3(opf::kBlock);
+            p.sharedMemBytes = 0;
+            p.kernelParams = params;
+            p.extra = nullptr;
+            hipGraphNode_t node;
+            e = hipGraphAddKernelNode(&node, ge.graph, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+            prev = node;
+        }
         if (e == hipSuccess) e = hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
             if (ge.graph) (void)hipGraphDestroy(ge.graph);
@@ -175,31 +194,36 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
         // (zeroed), instance descriptors, item lists per replica group
         Packer pk;
         const size_t o_cnt = pk.reserve(2 * sizeof(int32_t));
-        std::vector<size_t> o_pd(n_inst, 0), o_qd(n_inst, 0), o_scr(n_inst, 0);
+        std::vector<int64_t> loff(n_inst + 1, 0);
+        std::vector<size_t> o_scr(n_inst, 0);
         std::vector<int32_t> stride(n_inst, 0);
-        int64_t off = 0;
         for (int32_t j = 0; j < n_inst; j++) {
             const opf::HostModel& hm = models[inst_model[j]]->hm;
-            if (inst_pd) {
-                const int64_t nl = (int64_t)hm.ly.N * (hm.ly.T > 1 ? hm.ly.T : 1);
-                o_pd[j] = pk.add(inst_pd + off, sizeof(double) * nl);
-                o_qd[j] = pk.add(inst_qd + off, sizeof(double) * nl);
-                stride[j] = hm.ly.T > 1 ? hm.ly.N : 0;
-                off += nl;
-            }
-            o_scr[j] = pk.reserve(obj_scratch_bytes(hm));
+            loff[j + 1] = loff[j] + (int64_t)hm.ly.N * (hm.ly.T > 1 ? hm.ly.T : 1);
+            stride[j] = hm.ly.T > 1 ? hm.ly.N : 0;
+            o_scr[j] = pk.reserve(opf::scratch_bytes(models[inst_model[j]]->dm));
+        }
+        size_t o_pd = 0, o_qd = 0;
+        if (inst_pd) {
+            o_pd = pk.add(inst_pd, sizeof(double) * loff[n_inst]);
+            o_qd = pk.add(inst_qd, sizeof(double) * loff[n_inst]);
         }
         const size_t o_inst = pk.reserve(sizeof(opf::BatchInst) * n_inst);
         std::vector<opf::DevModel> dms(n_inst);
         for (int32_t j = 0; j < n_inst; j++) dms[j] = models[inst_model[j]]->dm;
-        std::vector<std::pair<size_t, size_t>> lst_off;
-        std::vector<std::pair<int32_t, int32_t>> lst_n;
-        std::vector<opf::BatchItem> ev, jt;
+        std::vector<std::array<size_t, 4>> lst_off;
+        std::vector<std::array<int32_t, 4>> lst_n;
+        std::vector<opf::BatchItem> items;
         for (int32_t g : kGroups) {
-            make_items(dms, g, 0, ev);
-            make_items(dms, g, 1, jt);
-            lst_off.push_back({pk.add(ev), pk.add(jt)});
-            lst_n.push_back({(int32_t)ev.size(), (int32_t)jt.size()});
+            std::array<size_t, 4> offs{};
+            std::array<int32_t, 4> ns{};
+            for (int q = 0; q < 4; q++) {  // (mode, phase)
+                make_items(dms, g, q / 2, q % 2, items);
+                offs[q] = pk.add(items);
+                ns[q] = (int32_t)items.size();
+            }
+            lst_off.push_back(offs);
+            lst_n.push_back(ns);
         }
 
         DeviceGuard dg(dev);
@@ -217,31 +241,27 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
         }
         char* base = static_cast<char*>(b->arena);
         opf::BatchInst* hi = reinterpret_cast<opf::BatchInst*>(pk.at(o_inst));
-        b->lds = 0;
         for (int32_t j = 0; j < n_inst; j++) {
             opf::BatchInst bi;
             bi.m = dms[j];
             if (inst_pd) {
-                bi.m.pd = reinterpret_cast<const double*>(base + o_pd[j]);
-                bi.m.qd = reinterpret_cast<const double*>(base + o_qd[j]);
+                bi.m.pd = reinterpret_cast<const double*>(base + o_pd) + loff[j];
+                bi.m.qd = reinterpret_cast<const double*>(base + o_qd) + loff[j];
                 bi.m.load_stride = stride[j];
             }
-            const size_t parts = sizeof(double) * (size_t)bi.m.ngchunks * bi.m.npg;
-            bi.m.obj_part = reinterpret_cast<double*>(base + o_scr[j]);
-            bi.m.obj_ticket = reinterpret_cast<int32_t*>(base + o_scr[j] + ((parts + 255) & ~size_t(255)));
+            attach_scratch(bi.m, base + o_scr[j]);
             bi.xoff = b->xoff[j];
             bi.coff = b->coff[j];
             bi.joff = b->joff[j];
             bi.hoff = b->hoff[j];
             std::memcpy(&hi[j], &bi, sizeof bi);
-            b->lds = std::max(b->lds, opf::set_lds_bytes(bi.m));
         }
         for (size_t s = 0; s < lst_off.size(); s++) {
             Lists L;
-            L.ev = reinterpret_cast<opf::BatchItem*>(base + lst_off[s].first);
-            L.jt = reinterpret_cast<opf::BatchItem*>(base + lst_off[s].second);
-            L.n_ev = lst_n[s].first;
-            L.n_jt = lst_n[s].second;
+            for (int q = 0; q < 4; q++) {
+                L.items[q / 2][q % 2] = reinterpret_cast<opf::BatchItem*>(base + lst_off[s][q]);
+                L.n[q / 2][q % 2] = lst_n[s][q];
+            }
             b->lists.push_back(L);
         }
         hipError_t e = hipMemcpy(b->arena, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
@@ -251,6 +271,11 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
             return hip_err(e, "batch upload");
         }
         b->counters = reinterpret_cast<int32_t*>(base + o_cnt);
+        if (inst_pd) {
+            b->pd_all = reinterpret_cast<double*>(base + o_pd);
+            b->qd_all = reinterpret_cast<double*>(base + o_qd);
+            b->n_loads = loff[n_inst];
+        }
         b->inst = reinterpret_cast<opf::BatchInst*>(base + o_inst);
         b->sched = 0;
     } catch (const std::bad_alloc&) {
@@ -328,6 +353,32 @@ int opf_batch_jtprod(opf_batch b, const double* X, const double* V, double* OUT,
     return launch(b, a, static_cast<hipStream_t>(stream));
 }
 
+int opf_batch_set_loads(opf_batch b, const double* pd, const double* qd, void* stream) {
+    if (!valid(b)) return set_err(OPF_E_STATE, "invalid or destroyed batch handle");
+    if (!b->pd_all) return set_err(OPF_E_STATE, "the batch was created without per-instance loads");
+    if (!pd || !qd) return set_err(OPF_E_ARG, "pd and qd must be non-NULL");
+    DeviceGuard dg(b->device);
+    if (dg.err != hipSuccess) return hip_err(dg.err, "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t bytes = sizeof(double) * (size_t)b->n_loads;
+    hipError_t e = hipMemcpyAsync(b->pd_all, pd, bytes, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->qd_all, qd, bytes, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_err(e, "load copy");
+    return OPF_OK;
+}
+
+int opf_batch_flows(opf_batch b, double* X, void* stream) {
+    if (!valid(b)) return set_err(OPF_E_STATE, "invalid or destroyed batch handle");
+    if (!X) return set_err(OPF_E_ARG, "X must be non-NULL");
+    DeviceGuard dg(b->device);
+    if (dg.err != hipSuccess) return hip_err(dg.err, "hipSetDevice");
+    opf::BatchArgs a{};
+    a.X = X;
+    a.G = X;
+    a.mode = 2;
+    return launch(b, a, static_cast<hipStream_t>(stream));
+}
+
 int opf_batch_tune(opf_batch b, void* stream) {
     if (!valid(b)) return set_err(OPF_E_STATE, "invalid or destroyed batch handle");
     DeviceGuard dg(b->device);
@@ -356,7 +407,9 @@ int opf_batch_tune(opf_batch b, void* stream) {
         }
         for (size_t sc = 0; sc < b->lists.size() && rc == OPF_OK; sc++) {
             // replica groups beyond the largest replica count are duplicates
-            if (sc > 0 && b->lists[sc].n_ev == b->lists[sc - 1].n_ev) continue;
+            if (sc > 0 && b->lists[sc].n[0][1] == b->lists[sc - 1].n[0][1] &&
+                b->lists[sc].n[0][0] == b->lists[sc - 1].n[0][0])
+                continue;
             for (int32_t wg : kWgPerCu) {
                 b->sched = (int)sc;
                 b->wg_per_cu = wg;

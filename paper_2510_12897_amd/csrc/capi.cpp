@@ -72,6 +72,9 @@ ModelOffsets pack_model(Packer& pk, const opf::HostModel& hm) {
     o.rate2 = pk.add(hm.rate2);
     o.slots = pk.add(hm.slots);
     o.big_bus = pk.add(hm.big_bus);
+    o.big_scr = pk.add(hm.big_scr);
+    o.br_scr = pk.add(hm.br_scr);
+    o.br_hx = pk.add(hm.br_hx);
     o.adj_ptr = pk.add(hm.adj_ptr);
     o.he = pk.add(hm.he);
     o.he_grp = pk.add(hm.he_grp);
@@ -101,15 +104,17 @@ namespace {
 int32_t gen_chunks(const opf::HostModel& hm) {
     return (std::max(hm.ly.G, hm.ly.R) + opf::kBlock - 1) / opf::kBlock;
 }
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 }  // namespace
 
-size_t obj_scratch_bytes(const opf::HostModel& hm) {
-    // partials, then the ticket on its own 256-byte line
-    const size_t parts = sizeof(double) * (size_t)gen_chunks(hm) * hm.ly.npg;
-    return ((parts + 255) & ~size_t(255)) + 256;
+void attach_scratch(opf::DevModel& d, char* scratch) {
+    const size_t parts = round256(sizeof(double) * (size_t)d.ngchunks * d.npg);
+    d.obj_part = reinterpret_cast<double*>(scratch);
+    d.obj_ticket = reinterpret_cast<int32_t*>(scratch + parts);
+    d.scr = reinterpret_cast<double*>(scratch + parts + 256);
 }
 
-opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets& o, char* scratch) {
+opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets& o) {
     const opf::Layout& ly = hm.ly;
     opf::DevModel d{};
     d.N = ly.N; d.L = ly.L; d.G = ly.G; d.R = ly.R; d.T = ly.T;
@@ -118,6 +123,7 @@ opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets&
     d.nbig = (int32_t)hm.big_bus.size();
     d.big_cap = 0;
     for (int32_t b : hm.big_bus) d.big_cap = std::max(d.big_cap, hm.adj_ptr[b + 1] - hm.adj_ptr[b]);
+    d.nscr = hm.nscr;
     d.nbchunks = (ly.L + opf::kBlock - 1) / opf::kBlock;
     d.ngchunks = gen_chunks(hm);
     d.x_va = ly.x_va; d.x_vm = ly.x_vm; d.x_pg = ly.x_pg; d.x_qg = ly.x_qg; d.x_p = ly.x_p; d.x_q = ly.x_q;
@@ -134,15 +140,12 @@ opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets&
     d.hva_rep = ly.hva_rep; d.hvm_rep = ly.hvm_rep;
 #define P32(name) d.name = reinterpret_cast<const int32_t*>(base + o.name)
 #define PDB(name) d.name = reinterpret_cast<const double*>(base + o.name)
-    P32(f_bus); P32(t_bus); PDB(coef); PDB(rate2); P32(slots); P32(big_bus);
+    P32(f_bus); P32(t_bus); PDB(coef); PDB(rate2); P32(slots); P32(big_bus); P32(big_scr); P32(br_scr); P32(br_hx);
     P32(adj_ptr); P32(he); P32(he_grp); P32(nlo); P32(ndist); P32(hva_off); P32(hvm_off); P32(jbal_off);
     P32(gen_ptr); P32(gen_list); PDB(gs); PDB(bs); PDB(pd); PDB(qd);
     PDB(c2); PDB(c1); PDB(c0); P32(gen_bus); P32(ref_bus); P32(ref_ptr); P32(ref_list); P32(outage);
 #undef P32
 #undef PDB
-    const size_t parts = sizeof(double) * (size_t)d.ngchunks * ly.npg;
-    d.obj_part = reinterpret_cast<double*>(scratch);
-    d.obj_ticket = reinterpret_cast<int32_t*>(scratch + ((parts + 255) & ~size_t(255)));
     return d;
 }
 
@@ -152,7 +155,7 @@ using namespace opf_internal;
 
 namespace {
 
-bool valid(const opf_model_s* m) { return m && m->magic == kModelMagic; }
+bool valid(const opf_model_s* m) { return valid_model(m); }
 
 int check_model(opf_model m) {
     if (!valid(m)) return set_err(OPF_E_STATE, "invalid or destroyed model handle");
@@ -162,7 +165,7 @@ int check_model(opf_model m) {
 int launch_set(opf_model m, const opf::EvalOut& o, void* stream) {
     DeviceGuard dg(m->device);
     if (dg.err != hipSuccess) return hip_err(dg.err, "hipSetDevice");
-    hipError_t e = opf::launch_eval_set(m->dm, o, kPlainReplicaGroup, static_cast<hipStream_t>(stream));
+    hipError_t e = opf::launch_eval_set(m->dm, o, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_err(e, "callback kernel launch");
     return OPF_OK;
 }
@@ -249,7 +252,8 @@ int opf_model_create(const opf_case* cs, const opf_opts* opts, int device, opf_m
 
         Packer pk;
         ModelOffsets mo = pack_model(pk, m->hm);
-        const size_t o_scr = pk.reserve(obj_scratch_bytes(m->hm));  // zeroed: the ticket starts at 0
+        opf::DevModel probe = make_dev(m->hm, nullptr, mo);
+        const size_t o_scr = pk.reserve(opf::scratch_bytes(probe));  // zeroed: the ticket starts at 0
         const size_t oj_r = pk.reserve(sizeof(int32_t) * ly.nnzj());
         const size_t oj_c = pk.reserve(sizeof(int32_t) * ly.nnzj());
         const size_t oh_r = pk.reserve(sizeof(int32_t) * ly.nnzh);
@@ -259,6 +263,7 @@ int opf_model_create(const opf_case* cs, const opf_opts* opts, int device, opf_m
         const size_t ob_lv = pk.reserve(sizeof(double) * ly.n), ob_uv = pk.reserve(sizeof(double) * ly.n);
         const size_t ob_lc = pk.reserve(sizeof(double) * ly.m()), ob_uc = pk.reserve(sizeof(double) * ly.m());
         const size_t ob_x0 = pk.reserve(sizeof(double) * ly.n);
+        const size_t o_isref = pk.add(m->hm.is_ref);
         opf::fill_bounds(cs, opts, m->hm, reinterpret_cast<double*>(pk.at(ob_lv)),
                          reinterpret_cast<double*>(pk.at(ob_uv)), reinterpret_cast<double*>(pk.at(ob_lc)),
                          reinterpret_cast<double*>(pk.at(ob_uc)), reinterpret_cast<double*>(pk.at(ob_x0)));
@@ -280,7 +285,8 @@ int opf_model_create(const opf_case* cs, const opf_opts* opts, int device, opf_m
             return hip_err(e, "model upload");
         }
         char* base = static_cast<char*>(m->arena);
-        m->dm = make_dev(m->hm, base, mo, base + o_scr);
+        m->dm = make_dev(m->hm, base, mo);
+        attach_scratch(m->dm, base + o_scr);
         m->jrow = reinterpret_cast<const int32_t*>(base + oj_r);
         m->jcol = reinterpret_cast<const int32_t*>(base + oj_c);
         m->hrow = reinterpret_cast<const int32_t*>(base + oh_r);
@@ -290,6 +296,7 @@ int opf_model_create(const opf_case* cs, const opf_opts* opts, int device, opf_m
         m->lcon = reinterpret_cast<const double*>(base + ob_lc);
         m->ucon = reinterpret_cast<const double*>(base + ob_uc);
         m->x0 = reinterpret_cast<const double*>(base + ob_x0);
+        m->is_ref = reinterpret_cast<const int32_t*>(base + o_isref);
     } catch (const std::bad_alloc&) {
         delete m;
         return set_err(OPF_E_NOMEM, "host allocation failed");
@@ -466,7 +473,7 @@ int opf_jtprod(opf_model m, const double* x, const double* v, double* out, void*
     if (!x || !v || !out) return set_err(OPF_E_ARG, "x, v and out must be non-NULL");
     DeviceGuard dg(m->device);
     if (dg.err != hipSuccess) return hip_err(dg.err, "hipSetDevice");
-    hipError_t e = opf::launch_jtprod(m->dm, x, v, out, kPlainReplicaGroup, static_cast<hipStream_t>(stream));
+    hipError_t e = opf::launch_jtprod(m->dm, x, v, out, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_err(e, "jtprod kernel launch");
     return OPF_OK;
 }

@@ -7,20 +7,26 @@
 
 namespace opf {
 
-// Work item kinds of one callback set.
+// Work item kinds.  A callback set runs in two phases: branch items first
+// (they also leave each half-edge's bus-side terms in a scratch), then the
+// bus-side items.
 enum TaskKind : int32_t {
-    T_BIG = 0,     // one bus whose segment does not fit a wave (LDS tile path)
-    T_WAVE = 1,    // 64 lanes of packed bus segments: balance rows, Hessian bus rows
-    T_BRANCH = 2,  // 64 branches: flow, angle, thermal rows, arc Hessian diagonals
-    T_GEN = 3      // 64 generators: gradient, pg Hessian diagonal, objective partial, ref and ramp rows
+    T_BRANCH = 0,  // phase 1: 64 branches: flow, angle, thermal rows, arc Hessian entries, half-edge terms
+    T_BIG = 1,     // phase 2: one bus whose segment does not fit a wave
+    T_WAVE = 2,    // phase 2: 64 lanes of packed bus segments: balance rows, Hessian bus diagonals
+    T_GEN = 3      // phase 2: 64 generators: gradient, pg Hessian diagonal, objective, ref and ramp rows
 };
+
+// Scratch rows of the half-edge terms (one double per half-edge and replica).
+enum ScratchRow : int32_t { S_P = 0, S_Q, S_DAA, S_DMA, S_DMM, S_XAA, S_XMA, S_XMM, S_ROWS };
 
 constexpr int kBlock = 64;          // threads per workgroup (one wave), every task
 constexpr int kLdsPerEdge = 8;      // doubles staged in LDS per lane / half-edge
 
 struct DevModel {
     int32_t N, L, G, R, T, nrep, npg, load_stride;
-    int32_t nwaves, nbig, big_cap;   // wave count, big-bus count, LDS half-edge capacity of the big path
+    int32_t nwaves, nbig, big_cap;   // wave count, big-bus count, largest big-bus degree
+    int32_t nscr;                    // scratch entries per replica (half-edges, wave-slot order)
     int32_t nbchunks, ngchunks;      // branch / generator chunks of kBlock
     int64_t x_va, x_vm, x_pg, x_qg, x_p, x_q;
     int64_t c_ref, c_pfr, c_qfr, c_pto, c_qto, c_ang, c_balp, c_balq, c_thf, c_tht, c_ramp;
@@ -34,6 +40,9 @@ struct DevModel {
     // wave-packed bus segments: 8 int32 per lane (kind, ref, bus, other, jpos, h0, h1, h2)
     const int32_t* slots;  // [nwaves * kBlock * 8]
     const int32_t* big_bus;   // [nbig]
+    const int32_t* big_scr;   // [nbig+1] first scratch entry of each big bus
+    const int32_t* br_scr;    // [2][L] scratch entry of the from / to half-edge of each branch
+    const int32_t* br_hx;     // [4][L] off-diagonal Hessian positions, -1 for parallel branches
     // bus adjacency (the big-bus path)
     const int32_t* adj_ptr;   // [N+1]
     const int32_t* he;        // [2L] branch << 1 | from-side flag, sorted by (neighbour, branch)
@@ -62,6 +71,9 @@ struct DevModel {
     // self-resetting arrival counter
     double* obj_part;         // [ngchunks * npg]
     int32_t* obj_ticket;      // [1]
+    // half-edge terms passed from the branch phase to the bus phase:
+    // row k, replica r, entry s at scr[(k * nrep + r) * nscr + s]
+    double* scr;
 };
 
 struct EvalOut {
@@ -75,13 +87,15 @@ struct EvalOut {
     double* H;
 };
 
-// Work counts of one plain launch.  Items are ordered big buses, waves,
-// branch chunks, generator chunks; each covers `rg` consecutive replicas.
+// Work counts of one plain launch of each phase.  Phase-2 items are ordered
+// big buses, waves, generator chunks; every item covers `rg` consecutive
+// replicas.
 struct SetGrid {
-    int32_t n_big, n_wave, n_branch, n_gen;  // item counts (replica groups included)
-    int32_t rg, nrg;                          // replicas per item, replica groups
-    int32_t gen_per_item;                     // 0 = chunks of kBlock generators; 1 = one generator a wave
-    int32_t total() const { return n_big + n_wave + n_branch + n_gen; }
+    int32_t n_branch, rg1;            // phase 1 items, replicas per item
+    int32_t n_big, n_wave, n_gen;     // phase 2 items
+    int32_t rg2, nrg2;                // phase 2 replicas per item, replica groups
+    int32_t gen_per_item;             // 0 = chunks of kBlock generators; 1 = one generator a wave
+    int32_t phase2() const { return n_big + n_wave + n_gen; }
 };
 
 }  // namespace opf

@@ -7,17 +7,16 @@
 
 namespace opf {
 
-// Work counts of one launch on one model (mode 0: callback set, 1: J^T v),
-// each item covering `rg` consecutive replicas, and its LDS size.
-SetGrid plan_set(const DevModel& m, const EvalOut& o, int32_t mode, int32_t rg);
-size_t set_lds_bytes(const DevModel& m);
+// Work counts of the two launches of one model (mode 0: callback set,
+// 1: J^T v).
+SetGrid plan_set(const DevModel& m, const EvalOut& o, int32_t mode);
 
-// One callback set (any subset of f, g, c, J, H) on `stream`.
-hipError_t launch_eval_set(const DevModel& m, const EvalOut& o, int32_t rg, hipStream_t stream);
+// One callback set (any subset of f, g, c, J, H) on `stream`: the branch
+// phase, then the bus phase.
+hipError_t launch_eval_set(const DevModel& m, const EvalOut& o, hipStream_t stream);
 
 // out = J(x)^T v on `stream`.
-hipError_t launch_jtprod(const DevModel& m, const double* x, const double* v, double* out, int32_t rg,
-                         hipStream_t stream);
+hipError_t launch_jtprod(const DevModel& m, const double* x, const double* v, double* out, hipStream_t stream);
 
 // ---- batched evaluation: a persistent kernel over a queue of work items.
 struct BatchItem {
@@ -38,8 +37,13 @@ struct BatchArgs {
     const double* Y;
     const double* sigma;
     double *F, *G, *C, *J, *H;
-    int32_t mode;            // 0 = callback set, 1 = J^T v (Y holds V, G holds OUT)
+    int32_t mode;            // 0 = callback set, 1 = J^T v (Y holds V, G holds OUT),
+                             // 2 = arc flows (G is the X written in place)
 };
+
+// Scratch bytes a model needs per evaluation stream: objective partials and
+// ticket, then the half-edge terms (S_ROWS x replicas x entries doubles).
+size_t scratch_bytes(const DevModel& m);
 
 // The persistent kernel's entry, for graph kernel nodes (argument: BatchArgs).
 void* batch_kernel_fn();

@@ -236,6 +236,8 @@ int build_host_model(const opf_case* cs, const opf_opts* opts, HostModel& hm, st
     for (int32_t j = 0; j < R; j++) hm.ref_ptr[cs->ref_bus[j] + 1]++;
     for (int32_t i = 0; i < N; i++) hm.ref_ptr[i + 1] += hm.ref_ptr[i];
     hm.ref_list.resize(R);
+    hm.is_ref.assign(N, 0);
+    for (int32_t j = 0; j < R; j++) hm.is_ref[cs->ref_bus[j]] = 1;
     {
         std::vector<int32_t> fill(hm.ref_ptr.begin(), hm.ref_ptr.end() - 1);
         for (int32_t j = 0; j < R; j++) hm.ref_list[fill[cs->ref_bus[j]]++] = j;
@@ -280,6 +282,8 @@ void build_slots(HostModel& hm) {
     const int32_t N = hm.ly.N, L = hm.ly.L;
     hm.slots.clear();
     hm.big_bus.clear();
+    hm.br_scr.assign(2 * (size_t)L, -1);
+    hm.br_hx.assign(4 * (size_t)L, -1);
     int32_t lane = 0;
     auto push = [&](int32_t kind, int32_t ref, int32_t bus, int32_t other, int32_t jpos, int32_t h0, int32_t h1,
                     int32_t h2) {
@@ -289,6 +293,14 @@ void build_slots(HostModel& hm) {
     };
     auto pad_wave = [&]() {
         while (lane != 0) push(SK_IDLE, -1, -1, -1, -1, -1, -1, -1);
+    };
+    auto group_len = [&](int32_t i, int32_t q) {
+        const int32_t grp = hm.he_grp[q];
+        int32_t u = q;
+        while (u > hm.adj_ptr[i] && hm.he_grp[u - 1] == grp) u--;
+        int32_t n = 0;
+        for (; u < hm.adj_ptr[i + 1] && hm.he_grp[u] == grp; u++) n++;
+        return n;
     };
     for (int32_t i = 0; i < N; i++) {
         const int32_t e0 = hm.adj_ptr[i], e1 = hm.adj_ptr[i + 1], deg = e1 - e0;
@@ -308,14 +320,14 @@ void build_slots(HostModel& hm) {
             const int32_t k = from ? hm.t_bus[l] : hm.f_bus[l];
             const int32_t grp = hm.he_grp[q];
             const bool leader = (q == e0) || hm.he_grp[q - 1] != grp;
-            int32_t glen = 0;
-            if (leader)
-                for (int32_t u = q; u < e1 && hm.he_grp[u] == grp; u++) glen++;
+            const int32_t glen = group_len(i, q);
             // rank of this half-edge's arc among the arcs at bus i (ascending arc index)
             const int32_t arc = from ? l : L + l;
             const auto ab = hm.arc_list.begin() + hm.arc_ptr[i], ae = hm.arc_list.begin() + hm.arc_ptr[i + 1];
             const int32_t arank = (int32_t)(std::lower_bound(ab, ae, arc) - ab);
-            const int32_t kind = SK_EDGE | (from << 2) | ((leader ? 1 : 0) << 3) | (glen << 8);
+            const int32_t kind = SK_EDGE | (from << 2) | ((leader ? 1 : 0) << 3) | ((glen > 1 ? 1 : 0) << 4) |
+                                 ((leader ? glen : 0) << 8);
+            hm.br_scr[(from ? 0 : (size_t)L) + l] = (int32_t)(hm.slots.size() / 8);
             push(kind, l, i, k, jrow + 1 + ng + arank, leader && k < i ? hva + grp : -1,
                  leader ? hvm + grp + (k > i ? 1 : 0) : -1, leader && k < i ? hvm + nd + 1 + grp : -1);
         }
@@ -323,6 +335,36 @@ void build_slots(HostModel& hm) {
     }
     pad_wave();
     hm.nwaves = (int32_t)(hm.slots.size() / (8 * kWaveLanes));
+    // half-edges of big buses follow the wave slots, contiguous per bus in
+    // (neighbour, branch) order
+    int32_t s = hm.nwaves * kWaveLanes;
+    hm.big_scr.assign(1, s);
+    for (int32_t b : hm.big_bus) {
+        for (int32_t q = hm.adj_ptr[b]; q < hm.adj_ptr[b + 1]; q++, s++) {
+            const int32_t code = hm.he[q], l = code >> 1, from = code & 1;
+            hm.br_scr[(from ? 0 : (size_t)L) + l] = s;
+        }
+        hm.big_scr.push_back(s);
+    }
+    hm.nscr = s;
+    // off-diagonal Hessian positions of branches with no parallel twin
+    for (int32_t l = 0; l < L; l++) {
+        const int32_t f = hm.f_bus[l], t = hm.t_bus[l];
+        // the group of this branch at bus f (rank among f's distinct neighbours)
+        int32_t qf = -1, qt = -1;
+        for (int32_t q = hm.adj_ptr[f]; q < hm.adj_ptr[f + 1]; q++)
+            if (hm.he[q] == ((l << 1) | 1)) qf = q;
+        for (int32_t q = hm.adj_ptr[t]; q < hm.adj_ptr[t + 1]; q++)
+            if (hm.he[q] == (l << 1)) qt = q;
+        if (group_len(f, qf) > 1) continue;
+        const int32_t gf = hm.he_grp[qf], gt = hm.he_grp[qt];
+        const int32_t hi = f > t ? f : t;
+        const int32_t g_hi = f > t ? gf : gt;  // rank of the lower bus among hi's neighbours
+        hm.br_hx[0 * (size_t)L + l] = hm.hva_off[hi] + g_hi;                          // (va_hi, va_lo)
+        hm.br_hx[1 * (size_t)L + l] = hm.hvm_off[hi] + hm.ndist[hi] + 1 + g_hi;       // (vm_hi, vm_lo)
+        hm.br_hx[2 * (size_t)L + l] = hm.hvm_off[f] + gf + (t > f ? 1 : 0);           // (vm_f, va_t)
+        hm.br_hx[3 * (size_t)L + l] = hm.hvm_off[t] + gt + (f > t ? 1 : 0);           // (vm_t, va_f)
+    }
 }
 
 void fill_pattern(const HostModel& hm, int32_t* jr, int32_t* jc, int32_t* hr, int32_t* hc) {

@@ -54,6 +54,7 @@ struct HostModel {
     std::vector<int32_t> gen_bus;
     std::vector<int32_t> ref_bus;
     std::vector<int32_t> ref_ptr, ref_list;    // reference rows per bus, ascending
+    std::vector<int32_t> is_ref;               // [N] 1 at reference buses
     std::vector<int32_t> outage;               // per replica: branch out of service or -1
     int32_t max_degree = 0;
 
@@ -65,6 +66,17 @@ struct HostModel {
     std::vector<int32_t> slots;                // [nwaves * kWaveLanes * 8]
     int32_t nwaves = 0;
     std::vector<int32_t> big_bus;              // buses whose segment does not fit a wave
+    std::vector<int32_t> big_scr;              // [nbig + 1] first scratch entry of each big bus
+    // Scratch entries: one per half-edge, at its wave slot, or after the
+    // wave slots for the half-edges of big buses (contiguous per big bus).
+    int32_t nscr = 0;
+    // Per branch: scratch entry of the from- and to-side half-edge, and the
+    // Hessian positions of its four off-diagonal entries relative to the
+    // replica's va / vm row blocks: (va_hi, va_lo), (vm_hi, vm_lo),
+    // (vm_f, va_t), (vm_t, va_f); -1 when the branch shares its bus pair with
+    // a parallel branch (those entries are summed on the bus side).
+    std::vector<int32_t> br_scr;               // [2][L]
+    std::vector<int32_t> br_hx;                // [4][L]
 };
 
 constexpr int32_t kWaveLanes = 64;
@@ -72,8 +84,8 @@ constexpr int32_t kWaveLanes = 64;
 // Slot fields (int32 each): kind, ref, bus, other, jpos, h0, h1, h2.
 //  kind bits [0,2): 0 idle, 1 head, 2 half-edge, 3 generator;
 //       bit 2: half-edge at the branch's from bus; bit 3: first half-edge of
-//       its neighbour group; bits [8,16): segment length (head) or group
-//       length (group leader).
+//       its neighbour group; bit 4: its group has parallel branches;
+//       bits [8,16): segment length (head) or group length (group leader).
 //  head:      bus i; jpos = first entry of i's balance Jacobian rows;
 //             h0/h1/h2 = Hessian (va_i,va_i), (vm_i,va_i), (vm_i,vm_i) (-1 if absent)
 //  half-edge: ref = branch, bus = i, other = neighbour; jpos = its +1 entry;

@@ -67,17 +67,18 @@ constexpr uint64_t kBatchMagic = 0x4f50464241544348ull;  // "OPFBATCH"
 
 // Offsets of the model arrays inside a packed arena.
 struct ModelOffsets {
-    size_t f_bus, t_bus, coef, rate2, slots, big_bus, adj_ptr, he, he_grp, nlo, ndist, hva_off, hvm_off, jbal_off,
-        gen_ptr, gen_list, gs, bs, pd, qd, c2, c1, c0, gen_bus, ref_bus, ref_ptr, ref_list, outage;
+    size_t f_bus, t_bus, coef, rate2, slots, big_bus, big_scr, br_scr, br_hx, adj_ptr, he, he_grp, nlo, ndist,
+        hva_off, hvm_off, jbal_off, gen_ptr, gen_list, gs, bs, pd, qd, c2, c1, c0, gen_bus, ref_bus, ref_ptr,
+        ref_list, outage;
 };
 
 ModelOffsets pack_model(Packer& pk, const opf::HostModel& hm);
-// Objective scratch of one evaluation stream: partials and the ticket.
-size_t obj_scratch_bytes(const opf::HostModel& hm);
-opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets& o, char* scratch);
-
-// Replica grouping of plain launches: one replica per work item.
-constexpr int32_t kPlainReplicaGroup = 1;
+// Device descriptor of a packed model; its scratch pointers are set by
+// attach_scratch.
+opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets& o);
+// Point the descriptor's objective partials, ticket and half-edge terms at
+// `scratch` (scratch_bytes(d) bytes, the ticket zeroed).
+void attach_scratch(opf::DevModel& d, char* scratch);
 
 }  // namespace opf_internal
 
@@ -90,4 +91,7 @@ struct opf_model_s {
     opf::DevModel dm{};
     const int32_t *jrow = nullptr, *jcol = nullptr, *hrow = nullptr, *hcol = nullptr;
     const double *lvar = nullptr, *uvar = nullptr, *lcon = nullptr, *ucon = nullptr, *x0 = nullptr;
+    const int32_t* is_ref = nullptr;
 };
+
+inline bool valid_model(const opf_model_s* m) { return m && m->magic == opf_internal::kModelMagic; }

@@ -1,0 +1,130 @@
+// C-ABI of the warm-start proxy kernels (declared in include/opf.h).
+#include <cstdint>
+
+#include "internal.h"
+#include "proxy_kernels.h"
+
+using namespace opf_internal;
+
+namespace {
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+bool mult4(int v) { return v >= 0 && v % 4 == 0; }
+
+int launched(hipError_t e, const char* what) { return e == hipSuccess ? OPF_OK : hip_err(e, what); }
+
+int static_model(opf_model m) {
+    if (!valid_model(m)) return set_err(OPF_E_STATE, "invalid or destroyed model handle");
+    if (m->hm.ly.nrep != 1) return set_err(OPF_E_ARG, "the proxy kernels take a static model");
+    return OPF_OK;
+}
+
+opf::ProxBox box_of(opf_model m, double va_span) {
+    const opf::Layout& ly = m->hm.ly;
+    opf::ProxBox b{};
+    b.N = ly.N;
+    b.G = ly.G;
+    b.vmin = m->lvar + ly.x_vm;
+    b.vmax = m->uvar + ly.x_vm;
+    b.pmin = m->lvar + ly.x_pg;
+    b.pmax = m->uvar + ly.x_pg;
+    b.qmin = m->lvar + ly.x_qg;
+    b.qmax = m->uvar + ly.x_qg;
+    b.is_ref = m->is_ref;
+    b.va_span = va_span;
+    return b;
+}
+
+opf::ProxRows rows_of(opf_model m) {
+    const opf::Layout& ly = m->hm.ly;
+    opf::ProxRows r{};
+    r.m = (int32_t)ly.m();
+    r.n = (int32_t)ly.n;
+    r.L = ly.L;
+    r.flow0 = (int32_t)ly.c_blk[opf::B_PFR];
+    r.flow1 = (int32_t)ly.c_blk[opf::B_ANG];
+    r.pq0 = (int32_t)ly.x_p;
+    r.npq = 4 * ly.L;
+    r.lcon = m->lcon;
+    r.ucon = m->ucon;
+    r.lvar = m->lvar;
+    r.uvar = m->uvar;
+    return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+int prox_gemm_bf16(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N,
+                   int K, const float* bias, float* act, int accumulate, void* stream) {
+    if (variant < 0 || variant > 3) return set_err(OPF_E_ARG, "variant must be 0..3");
+    if (!A || !B || !C) return set_err(OPF_E_ARG, "A, B and C must be non-NULL");
+    if (!mult4(M) || !mult4(N) || !mult4(K) || !mult4(lda) || !mult4(ldb) || !mult4(ldc))
+        return set_err(OPF_E_ARG, "dimensions and leading dimensions must be multiples of 4");
+    if (!aligned16(A) || !aligned16(B) || !aligned16(C) || (act && !aligned16(act)))
+        return set_err(OPF_E_ARG, "buffers must be 16-byte aligned");
+    const bool a_k = variant == 0 || variant == 1, b_k = variant == 0 || variant == 3;
+    if (lda < (a_k ? K : M) || ldb < (b_k ? K : N) || ldc < N)
+        return set_err(OPF_E_ARG, "a leading dimension is smaller than its row");
+    if (M == 0 || N == 0) return OPF_OK;
+    return launched(opf::prox_gemm(variant, A, lda, B, ldb, C, ldc, M, N, K, bias, act, accumulate,
+                                   static_cast<hipStream_t>(stream)),
+                    "prox_gemm_bf16 launch");
+}
+
+int prox_gelu_bwd(const float* pre, const float* dact, float* dpre, int64_t n, void* stream) {
+    if (n < 0 || (n > 0 && (!pre || !dact || !dpre))) return set_err(OPF_E_ARG, "bad arguments");
+    return launched(opf::prox_gelu_bwd(pre, dact, dpre, n, static_cast<hipStream_t>(stream)), "prox_gelu_bwd launch");
+}
+
+int prox_colsum(const float* X, int M, int N, float* work, float* out, float scale, void* stream) {
+    if (M < 1 || N < 1 || !X || !work || !out) return set_err(OPF_E_ARG, "bad arguments");
+    return launched(opf::prox_colsum(X, M, N, work, out, scale, static_cast<hipStream_t>(stream)), "prox_colsum launch");
+}
+
+int prox_adam(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float beta1, float beta2, float eps,
+              int step, void* stream) {
+    if (n < 0 || step < 1 || (n > 0 && (!p || !g || !m1 || !m2))) return set_err(OPF_E_ARG, "bad arguments");
+    if (n == 0) return OPF_OK;
+    return launched(opf::prox_adam(p, g, m1, m2, n, lr, beta1, beta2, eps, step, static_cast<hipStream_t>(stream)),
+                    "prox_adam launch");
+}
+
+int prox_squash_fwd(opf_model model, const float* z, int B, double va_span, double* X, void* stream) {
+    if (int rc = static_model(model)) return rc;
+    if (B < 1 || !z || !X) return set_err(OPF_E_ARG, "bad arguments");
+    DeviceGuard dg(model->device);
+    return launched(opf::prox_squash_fwd(z, B, box_of(model, va_span), X, model->hm.ly.n,
+                                         static_cast<hipStream_t>(stream)),
+                    "prox_squash_fwd launch");
+}
+
+int prox_squash_bwd(opf_model model, const float* z, int B, double va_span, const double* gX1, const double* gX2,
+                    const double* gObj, double obj_scale, float* dz, float scale, void* stream) {
+    if (int rc = static_model(model)) return rc;
+    if (B < 1 || !z || !gX1 || !dz) return set_err(OPF_E_ARG, "bad arguments");
+    DeviceGuard dg(model->device);
+    return launched(opf::prox_squash_bwd(z, B, box_of(model, va_span), gX1, gX2, gObj, obj_scale, model->hm.ly.n, dz,
+                                         (float)scale, static_cast<hipStream_t>(stream)),
+                    "prox_squash_bwd launch");
+}
+
+int prox_penalty(opf_model model, const double* C, const double* X, double rho, int B, double* pen, double* cvio,
+                 double* W, double* gpq, void* stream) {
+    if (int rc = static_model(model)) return rc;
+    if (B < 1 || !C || !X || !pen || !cvio || !W || !gpq) return set_err(OPF_E_ARG, "bad arguments");
+    DeviceGuard dg(model->device);
+    return launched(opf::prox_penalty(C, X, rows_of(model), rho, B, pen, cvio, W, gpq, static_cast<hipStream_t>(stream)),
+                    "prox_penalty launch");
+}
+
+int prox_chain_weights(opf_model model, const double* G1, const double* gpq, int B, double* W2, void* stream) {
+    if (int rc = static_model(model)) return rc;
+    if (B < 1 || !G1 || !gpq || !W2) return set_err(OPF_E_ARG, "bad arguments");
+    DeviceGuard dg(model->device);
+    return launched(opf::prox_chain_weights(G1, gpq, rows_of(model), B, W2, static_cast<hipStream_t>(stream)),
+                    "prox_chain_weights launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,43 @@
+// Launchers of the warm-start proxy kernels (proxy_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace opf {
+
+// Variable boxes of one model (device pointers) for the output squashing.
+struct ProxBox {
+    int32_t N, G;
+    const double *vmin, *vmax, *pmin, *pmax, *qmin, *qmax;
+    const int32_t* is_ref;  // [N] 1 for a reference bus (its angle stays 0)
+    double va_span;         // va = va_span * tanh(z)
+};
+
+// Constraint rows and bounds of one model (device pointers) for the penalty.
+struct ProxRows {
+    int32_t m, n, L;
+    int32_t flow0, flow1;   // the flow-definition rows [flow0, flow1)
+    int32_t pq0, npq;       // the p and q variables [pq0, pq0 + npq)
+    const double *lcon, *ucon, *lvar, *uvar;
+};
+
+// variant: 0 A k-contiguous, B k-contiguous; 1 A k-contiguous, B j-contiguous;
+//          2 A i-contiguous, B j-contiguous; 3 A i-contiguous, B k-contiguous.
+hipError_t prox_gemm(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N,
+                     int K, const float* bias, float* act, int accumulate, hipStream_t s);
+hipError_t prox_gelu_bwd(const float* pre, const float* dact, float* dpre, int64_t n, hipStream_t s);
+hipError_t prox_colsum(const float* X, int M, int N, float* part, float* out, float scale, hipStream_t s);
+int prox_colsum_chunks(int M);
+hipError_t prox_adam(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2, float eps,
+                     int step, hipStream_t s);
+hipError_t prox_squash_fwd(const float* z, int B, const ProxBox& box, double* X, int64_t n, hipStream_t s);
+hipError_t prox_squash_bwd(const float* z, int B, const ProxBox& box, const double* gX1, const double* gX2,
+                           const double* gObj, double obj_scale, int64_t n, float* dz, float scale, hipStream_t s);
+hipError_t prox_penalty(const double* C, const double* X, const ProxRows& rows, double rho, int B, double* pen,
+                        double* cvio, double* W, double* gpq, hipStream_t s);
+hipError_t prox_chain_weights(const double* G1, const double* gpq, const ProxRows& rows, int B, double* W2,
+                              hipStream_t s);
+
+}  // namespace opf
