@@ -14,8 +14,9 @@ and the roofline is the HBM one.
 Also measured in the same run (the "extra" object): the batched form on the
 64-scenario uneven mix (8 networks of 500 to 20,000 buses x 8 load seeds,
 one persistent launch) against the plain per-instance launches, the
-multi-period model (2,000 buses x 48 periods) and the N-1 contingency model
-(1,000 buses + 200 outage copies).
+multi-period model (2,000 buses x 48 periods), the N-1 contingency model
+(1,000 buses + 200 outage copies) and the learned warm-start proxy (300
+buses, batches of 4,096 load samples).
 
 Prints one JSON line.
 """
@@ -274,6 +275,57 @@ def bench_model(torch, opf, synth, cs, opts, n_in, n_out, sets, log, label, T=1,
                 bytes_per_set=b, achieved_gbs=b / per / 1e9, frac=b / per / 1e9 / HBM_PEAK_GBS)
 
 
+def bench_proxy(args, torch, synth, log):
+    """The learned warm-start proxy on a 300-bus network (410 branches, 60
+    generators): MLP 600 -> 3 x 1024 (GELU) -> 720 on BF16 matrix cores,
+    batches of 4,096 load samples (+-30 % uniform), FP64 penalty from the
+    callback kernels.  Reports the training step time, the inference rate,
+    the MLP forward's matrix-core rate and, on held-out loads, the largest
+    constraint violation of the proxy against the plain starting point."""
+    from paper_2510_12897_amd import proxy as P
+
+    cs = synth.network(300, 410, 60, 41)
+    B = 4096
+    px = P.WarmStartProxy(cs, B=B, width=1024, depth=3, rho=10.0, obj_scale=1e-3, seed=1)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    steps = args.proxy_steps
+    loads, feats = px.sample(gen)
+    first = float(px.train_step(loads, feats, lr=1e-3))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps - 1):
+        loads, feats = px.sample(gen)
+        loss = px.train_step(loads, feats, lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = (time.perf_counter() - t0) / max(steps - 1, 1)
+    last = float(loss)
+    gen.manual_seed(4242)
+    loads, feats = px.sample(gen)
+    _, cvp = px.predict(loads, feats)
+    _, cvf = px.baseline(loads)
+    cvp, cvf = cvp.cpu().numpy(), cvf.cpu().numpy()
+    # inference: MLP + squashing + flows + FP64 constraint evaluation + violation
+    secs, _ = time_steps(torch, lambda: px.predict(loads, feats), 10, 2)
+    infer_s = secs / 10
+    # MLP forward alone on the matrix cores
+    with torch.no_grad():
+        secs_m, _ = time_steps(torch, lambda: px.mlp(feats), 10, 2)
+    flops = 2.0 * B * sum(a * b for a, b in zip(px.mlp.dims[:-1], px.mlp.dims[1:]))
+    mlp_tflops = flops / (secs_m / 10) / 1e12
+    log(f"proxy: loss {first:.4g} -> {last:.4g} in {steps} steps ({train_s * 1e3:.2f} ms/step); held-out "
+        f"max violation mean {cvp.mean():.4g} vs flat start {cvf.mean():.4g}; {B / infer_s:.0f} inferences/s; "
+        f"MLP forward {mlp_tflops:.1f} TFLOP/s")
+    out = dict(workload="300 buses, 410 branches, 60 generators; MLP 600-1024x3-720 GELU, BF16 MFMA; "
+                        "batches of 4096 loads (+-30 % uniform)",
+               train_steps=steps, ms_per_train_step=train_s * 1e3, loss_first=first, loss_last=last,
+               inferences_per_s=B / infer_s, mlp_forward_tflops=mlp_tflops, mlp_peak_tflops=2500.0,
+               heldout_cvio_mean=float(cvp.mean()), heldout_cvio_max=float(cvp.max()),
+               flatstart_cvio_mean=float(cvf.mean()), fallback_rate=float(np.mean(cvp > cvf)))
+    px.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,6 +336,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle timing budget (0 = skip)")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / multi-period / N-1 legs")
     ap.add_argument("--batch-reps", type=int, default=20)
+    ap.add_argument("--proxy-steps", type=int, default=150, help="training steps of the proxy leg (0 = skip)")
     ap.add_argument("--eager", action="store_true", help="launch the headline sets without a HIP graph")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run a device-to-device copy of this many MiB (HBM counter calibration)")
@@ -373,6 +426,11 @@ def main():
                 torch, opf, synth, cs, dict(n_cont=200, outaged=out), 4, 2, 10, log, "N-1 copies", K=200)
         except Exception as e:
             extra["contingency_1k_x201"] = {"error": repr(e)}
+        if args.proxy_steps > 0:
+            try:
+                extra["proxy_300bus"] = bench_proxy(args, torch, synth, log)
+            except Exception as e:
+                extra["proxy_300bus"] = {"error": repr(e)}
         result["extra"] = extra
     if args.cpu_seconds > 0:
         from oracle import oracle

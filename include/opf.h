@@ -298,16 +298,24 @@ int prox_squash_bwd(opf_model model, const float *z, int B, double va_span, cons
 
 /* Per instance b of C [B, m], X [B, n]: pen[b] = rho * (sum of squared
  * constraint violations over the non-flow rows + squared bound violations of
- * p, q); cvio[b] = largest violation over every row and the p, q bounds
- * (the paper's Cvio, Sec. V-A); W [B, m] = d pen / d c (zero on the flow
- * rows); gpq [B, 4L] = d pen / d (p, q). */
-int prox_penalty(opf_model model, const double *C, const double *X, double rho, int B, double *pen, double *cvio,
-                 double *W, double *gpq, void *stream);
+ * p, q) + obj_scale * F[b] (the objective term is skipped when F is NULL);
+ * cvio[b] = largest violation over every row and the p, q bounds (the
+ * paper's Cvio, Sec. V-A); W [B, m] = d pen / d c (zero on the flow rows);
+ * gpq [B, 4L] = d pen / d (p, q). */
+int prox_penalty(opf_model model, const double *C, const double *X, const double *F, double obj_scale, double rho,
+                 int B, double *pen, double *cvio, double *W, double *gpq, void *stream);
 
 /* W2 [B, m]: minus (G1 + gpq) of each arc variable placed on its flow row,
  * zero elsewhere, so that J^T W2 carries a gradient on p = F(vm, va) back to
  * the voltages. */
 int prox_chain_weights(opf_model model, const double *G1, const double *gpq, int B, double *W2, void *stream);
+
+/* gX [B, n] = wb[b] * (gX1 + gX2 + obj_scale * gObj) on the va, vm, pg, qg
+ * entries, zero on the arc variables p, q (which the proxy sets to the
+ * branch flows, so they are not free); wb [B] is a device vector (the
+ * incoming gradient of each instance's loss).  gX2 and gObj may be NULL. */
+int prox_vjp_sum(opf_model model, const double *gX1, const double *gX2, const double *gObj, double obj_scale,
+                 const double *wb, int B, double *gX, void *stream);
 
 #ifdef __cplusplus
 }

@@ -5,7 +5,8 @@
 // phase of every instance, then the bus phase.  A schedule is (replica
 // group, workgroups per compute unit): how many consecutive periods or
 // contingency copies one work item handles (its descriptors are loaded once
-// for all of them), and how many persistent workgroups drain each queue.
+// for all of them), and how many persistent workgroups drain each item
+// list (each XCD's workgroups stride through one contiguous range of it).
 // Neither changes any summation order (segment sums follow the host
 // packing, objective partials are per generator chunk and replica and are
 // summed in index order), so every schedule produces bitwise the same
@@ -27,11 +28,14 @@ const int32_t kWgPerCu[] = {2, 4, 8, 16};
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipGraphNode_t node[2] = {nullptr, nullptr};
     opf::BatchArgs args[2]{};
 };
 
-using GraphKey = std::tuple<int32_t, int32_t, int32_t, const void*, const void*, const void*, const void*,
-                            const void*, const void*, const void*, const void*>;  // schedule, wg/CU, mode, buffers
+// One instantiated graph per (schedule, workgroups per CU, mode); a launch
+// with other buffers rewrites the kernel arguments of the instantiated
+// graph in place instead of building a new one.
+using GraphKey = std::tuple<int32_t, int32_t, int32_t>;
 
 struct Lists {
     opf::BatchItem* items[2][2] = {};  // device, [mode][phase]
@@ -47,7 +51,6 @@ struct opf_batch_s {
     int32_t n_inst = 0;
     std::vector<int64_t> xoff, coff, joff, hoff;
     void* arena = nullptr;
-    int32_t* counters = nullptr;
     opf::BatchInst* inst = nullptr;  // device
     double* pd_all = nullptr;        // device per-instance loads (NULL if none)
     double* qd_all = nullptr;
@@ -72,9 +75,11 @@ void drop_graphs(opf_batch_s* b) {
 }
 
 // Work items for one replica group size and phase.  Phase 1: the branch
-// chunks of every instance.  Phase 2: big buses first (the longest), then
-// the waves of bus segments and the generator chunks of every instance;
-// J^T v on a model whose copies share pg takes one generator per item.
+// chunks, then (callback set) the generator chunks of every instance.
+// Phase 2: big buses first (the longest), then the waves of bus segments
+// of every instance, then one objective item per instance (callback set)
+// or the generator items (J^T v; on a model whose copies share pg, one
+// generator per item).
 void make_items(const std::vector<opf::DevModel>& dms, int32_t rg, int mode, int phase,
                 std::vector<opf::BatchItem>& out) {
     out.clear();
@@ -86,13 +91,17 @@ void make_items(const std::vector<opf::DevModel>& dms, int32_t rg, int mode, int
     };
     if (phase == 0) {
         for (int32_t j = 0; j < n; j++) groups(dms[j], opf::T_BRANCH, dms[j].nbchunks, j);
+        if (mode == 0)
+            for (int32_t j = 0; j < n; j++) groups(dms[j], opf::T_GEN, dms[j].ngchunks, j);
         return;
     }
     for (int32_t j = 0; j < n; j++) groups(dms[j], opf::T_BIG, dms[j].nbig, j);
     for (int32_t j = 0; j < n; j++) groups(dms[j], opf::T_WAVE, dms[j].nwaves, j);
     for (int32_t j = 0; j < n; j++) {
         const opf::DevModel& d = dms[j];
-        if (mode == 1 && d.npg == 1 && d.nrep > 1) {
+        if (mode == 0) {
+            out.push_back({j, opf::T_OBJ, 0, 0, 0, 0});
+        } else if (d.npg == 1 && d.nrep > 1) {
             for (int32_t k = 0; k < d.G; k++) out.push_back({j, opf::T_GEN, k, 0, d.nrep, 0});
         } else {
             groups(d, opf::T_GEN, d.ngchunks, j);
@@ -107,17 +116,27 @@ int launch(opf_batch_s* b, const opf::BatchArgs& a0, hipStream_t stream) {
     for (int ph = 0; ph < 2; ph++) {
         a[ph] = a0;
         a[ph].inst = b->inst;
-        a[ph].counters = b->counters;
         // the flows mode runs the branch items only
         const int lm = a0.mode == 2 ? 0 : a0.mode;
         a[ph].items = L.items[lm][ph];
         a[ph].n_items = (a0.mode == 2 && ph == 1) ? 0 : L.n[lm][ph];
-        grid[ph] = std::max(1, std::min(a[ph].n_items, b->n_cu * b->wg_per_cu));
+        // at least one workgroup per XCD, so every XCD's item range is drained
+        grid[ph] = std::max(opf::kXcd, std::min(a[ph].n_items, b->n_cu * b->wg_per_cu));
     }
-    GraphKey key{b->sched, b->wg_per_cu, a0.mode, a0.X, a0.Y, a0.sigma, a0.F, a0.G, a0.C, a0.J, a0.H};
+    GraphKey key{b->sched, b->wg_per_cu, a0.mode};
+    auto kernel_params = [&](int ph, opf::BatchArgs* args, void** slot) {
+        hipKernelNodeParams p{};
+        slot[0] = args;
+        p.func = opf::batch_kernel_fn(ph);
+        p.gridDim = dim3(grid[ph]);
+        p.blockDim = dim3(opf::kBlock);
+        p.sharedMemBytes = 0;
+        p.kernelParams = slot;
+        p.extra = nullptr;
+        return p;
+    };
     auto it = b->graphs.find(key);
     if (it == b->graphs.end()) {
-        if (b->graphs.size() >= 512) drop_graphs(b);
         GraphEntry ge;
         ge.args[0] = a[0];
         ge.args[1] = a[1];
@@ -126,17 +145,10 @@ int launch(opf_batch_s* b, const opf::BatchArgs& a0, hipStream_t stream) {
         hipGraphNode_t prev = nullptr;
         for (int ph = 0; ph < 2 && e == hipSuccess; ph++) {
             if (ge.args[ph].n_items == 0) continue;
-            hipKernelNodeParams p{};
-            void* params[] = {&ge.args[ph]};
-            p.func = opf::batch_kernel_fn();
-            p.gridDim = dim3(grid[ph]);
-            p.blockDim = dim3(opf::kBlock);
-            p.sharedMemBytes = 0;
-            p.kernelParams = params;
-            p.extra = nullptr;
-            hipGraphNode_t node;
-            e = hipGraphAddKernelNode(&node, ge.graph, prev ? &prev : nullptr, prev ? 1 : 0, &p);
-            prev = node;
+            void* slot[1];
+            const hipKernelNodeParams p = kernel_params(ph, &ge.args[ph], slot);
+            e = hipGraphAddKernelNode(&ge.node[ph], ge.graph, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+            prev = ge.node[ph];
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
@@ -144,6 +156,16 @@ int launch(opf_batch_s* b, const opf::BatchArgs& a0, hipStream_t stream) {
             return hip_err(e, "batch graph build");
         }
         it = b->graphs.emplace(key, ge).first;
+    } else {
+        GraphEntry& ge = it->second;
+        for (int ph = 0; ph < 2; ph++) {
+            if (!ge.node[ph] || std::memcmp(&ge.args[ph], &a[ph], sizeof a[ph]) == 0) continue;
+            ge.args[ph] = a[ph];
+            void* slot[1];
+            const hipKernelNodeParams p = kernel_params(ph, &ge.args[ph], slot);
+            hipError_t e = hipGraphExecKernelNodeSetParams(ge.exec, ge.node[ph], &p);
+            if (e != hipSuccess) return hip_err(e, "batch graph argument update");
+        }
     }
     hipError_t e = hipGraphLaunch(it->second.exec, stream);
     if (e != hipSuccess) return hip_err(e, "hipGraphLaunch");
@@ -190,10 +212,9 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
             b->hoff[j + 1] = b->hoff[j] + ly.nnzh;
         }
 
-        // ---- pack: queue counters, per-instance loads and objective scratch
-        // (zeroed), instance descriptors, item lists per replica group
+        // ---- pack: per-instance loads and scratch (zeroed), instance
+        // descriptors, item lists per replica group
         Packer pk;
-        const size_t o_cnt = pk.reserve(2 * sizeof(int32_t));
         std::vector<int64_t> loff(n_inst + 1, 0);
         std::vector<size_t> o_scr(n_inst, 0);
         std::vector<int32_t> stride(n_inst, 0);
@@ -270,7 +291,6 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
             delete b;
             return hip_err(e, "batch upload");
         }
-        b->counters = reinterpret_cast<int32_t*>(base + o_cnt);
         if (inst_pd) {
             b->pd_all = reinterpret_cast<double*>(base + o_pd);
             b->qd_all = reinterpret_cast<double*>(base + o_qd);
@@ -440,7 +460,6 @@ int opf_batch_tune(opf_batch b, void* stream) {
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(s);
-    drop_graphs(b);  // the tuning buffers are about to be freed
     dev_free(b->alloc, buf);
     if (rc) {
         b->sched = keep_sched;

@@ -72,9 +72,6 @@ ModelOffsets pack_model(Packer& pk, const opf::HostModel& hm) {
     o.rate2 = pk.add(hm.rate2);
     o.slots = pk.add(hm.slots);
     o.big_bus = pk.add(hm.big_bus);
-    o.big_scr = pk.add(hm.big_scr);
-    o.br_scr = pk.add(hm.br_scr);
-    o.br_hx = pk.add(hm.br_hx);
     o.adj_ptr = pk.add(hm.adj_ptr);
     o.he = pk.add(hm.he);
     o.he_grp = pk.add(hm.he_grp);
@@ -110,8 +107,7 @@ size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 void attach_scratch(opf::DevModel& d, char* scratch) {
     const size_t parts = round256(sizeof(double) * (size_t)d.ngchunks * d.npg);
     d.obj_part = reinterpret_cast<double*>(scratch);
-    d.obj_ticket = reinterpret_cast<int32_t*>(scratch + parts);
-    d.scr = reinterpret_cast<double*>(scratch + parts + 256);
+    d.rec = reinterpret_cast<double*>(scratch + parts);
 }
 
 opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets& o) {
@@ -123,7 +119,6 @@ opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets&
     d.nbig = (int32_t)hm.big_bus.size();
     d.big_cap = 0;
     for (int32_t b : hm.big_bus) d.big_cap = std::max(d.big_cap, hm.adj_ptr[b + 1] - hm.adj_ptr[b]);
-    d.nscr = hm.nscr;
     d.nbchunks = (ly.L + opf::kBlock - 1) / opf::kBlock;
     d.ngchunks = gen_chunks(hm);
     d.x_va = ly.x_va; d.x_vm = ly.x_vm; d.x_pg = ly.x_pg; d.x_qg = ly.x_qg; d.x_p = ly.x_p; d.x_q = ly.x_q;
@@ -140,7 +135,7 @@ opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets&
     d.hva_rep = ly.hva_rep; d.hvm_rep = ly.hvm_rep;
 #define P32(name) d.name = reinterpret_cast<const int32_t*>(base + o.name)
 #define PDB(name) d.name = reinterpret_cast<const double*>(base + o.name)
-    P32(f_bus); P32(t_bus); PDB(coef); PDB(rate2); P32(slots); P32(big_bus); P32(big_scr); P32(br_scr); P32(br_hx);
+    P32(f_bus); P32(t_bus); PDB(coef); PDB(rate2); P32(slots); P32(big_bus);
     P32(adj_ptr); P32(he); P32(he_grp); P32(nlo); P32(ndist); P32(hva_off); P32(hvm_off); P32(jbal_off);
     P32(gen_ptr); P32(gen_list); PDB(gs); PDB(bs); PDB(pd); PDB(qd);
     PDB(c2); PDB(c1); PDB(c0); P32(gen_bus); P32(ref_bus); P32(ref_ptr); P32(ref_list); P32(outage);
@@ -253,7 +248,7 @@ int opf_model_create(const opf_case* cs, const opf_opts* opts, int device, opf_m
         Packer pk;
         ModelOffsets mo = pack_model(pk, m->hm);
         opf::DevModel probe = make_dev(m->hm, nullptr, mo);
-        const size_t o_scr = pk.reserve(opf::scratch_bytes(probe));  // zeroed: the ticket starts at 0
+        const size_t o_scr = pk.reserve(opf::scratch_bytes(probe));
         const size_t oj_r = pk.reserve(sizeof(int32_t) * ly.nnzj());
         const size_t oj_c = pk.reserve(sizeof(int32_t) * ly.nnzj());
         const size_t oh_r = pk.reserve(sizeof(int32_t) * ly.nnzh);

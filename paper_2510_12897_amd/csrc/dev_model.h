@@ -7,26 +7,37 @@
 
 namespace opf {
 
-// Work item kinds.  A callback set runs in two phases: branch items first
-// (they also leave each half-edge's bus-side terms in a scratch), then the
-// bus-side items.
+// Work item kinds.  A callback set runs in two phases: branch and generator
+// items first (they also leave each half-edge's bus-side terms in a record
+// and one objective partial per generator chunk), then the bus-side items
+// and the objective sum.  No item waits for another inside a launch.
 enum TaskKind : int32_t {
-    T_BRANCH = 0,  // phase 1: 64 branches: flow, angle, thermal rows, arc Hessian entries, half-edge terms
+    T_BRANCH = 0,  // phase 1: 64 branches: flow, angle, thermal rows, arc Hessian entries, half-edge records
     T_BIG = 1,     // phase 2: one bus whose segment does not fit a wave
-    T_WAVE = 2,    // phase 2: 64 lanes of packed bus segments: balance rows, Hessian bus diagonals
-    T_GEN = 3      // phase 2: 64 generators: gradient, pg Hessian diagonal, objective, ref and ramp rows
+    T_WAVE = 2,    // phase 2: 64 lanes of packed bus segments: balance rows, bus Hessian rows
+    T_GEN = 3,     // phase 1: 64 generators: gradient, pg Hessian diagonal, objective partial, ref and
+                   // ramp rows; J^T v: phase 2, the pg / qg entries
+    T_OBJ = 4      // phase 2: the objective, summing the partials in index order
 };
 
-// Scratch rows of the half-edge terms (one double per half-edge and replica).
-enum ScratchRow : int32_t { S_P = 0, S_Q, S_DAA, S_DMA, S_DMM, S_XAA, S_XMA, S_XMM, S_ROWS };
+// Half-edge record: what the branch phase leaves for the bus phase, per
+// (replica, branch, side), side 0 at the from bus, 1 at the to bus.  For the
+// weighted flow-row Hessian W = sum_r -y_r hess F_r of the branch, with u the
+// side's own voltage magnitude:
+//   R_TT = d2W/dth2  (the bus's (va, va) term; the (va_f, va_t) entry is -R_TT)
+//   R_MA = d2W/(du dva_own)  (the (vm, va) term; the (vm_own, va_other) entry is -R_MA)
+//   R_MM = d2W/du2
+//   R_UW = d2W/(dvm_f dvm_t)
+//   R_P, R_Q = the arc's p and q (its balance-row terms)
+// The J^T v phase uses the first two fields: the side's va and vm terms.
+enum RecField : int32_t { R_TT = 0, R_MA, R_MM, R_UW, R_P, R_Q, kRec };
 
 constexpr int kBlock = 64;          // threads per workgroup (one wave), every task
-constexpr int kLdsPerEdge = 8;      // doubles staged in LDS per lane / half-edge
+constexpr int kXcd = 8;             // XCDs; workgroups are dealt to them round-robin
 
 struct DevModel {
     int32_t N, L, G, R, T, nrep, npg, load_stride;
     int32_t nwaves, nbig, big_cap;   // wave count, big-bus count, largest big-bus degree
-    int32_t nscr;                    // scratch entries per replica (half-edges, wave-slot order)
     int32_t nbchunks, ngchunks;      // branch / generator chunks of kBlock
     int64_t x_va, x_vm, x_pg, x_qg, x_p, x_q;
     int64_t c_ref, c_pfr, c_qfr, c_pto, c_qto, c_ang, c_balp, c_balq, c_thf, c_tht, c_ramp;
@@ -40,9 +51,6 @@ struct DevModel {
     // wave-packed bus segments: 8 int32 per lane (kind, ref, bus, other, jpos, h0, h1, h2)
     const int32_t* slots;  // [nwaves * kBlock * 8]
     const int32_t* big_bus;   // [nbig]
-    const int32_t* big_scr;   // [nbig+1] first scratch entry of each big bus
-    const int32_t* br_scr;    // [2][L] scratch entry of the from / to half-edge of each branch
-    const int32_t* br_hx;     // [4][L] off-diagonal Hessian positions, -1 for parallel branches
     // bus adjacency (the big-bus path)
     const int32_t* adj_ptr;   // [N+1]
     const int32_t* he;        // [2L] branch << 1 | from-side flag, sorted by (neighbour, branch)
@@ -67,13 +75,11 @@ struct DevModel {
     const int32_t* ref_ptr;   // [N+1] reference rows per bus
     const int32_t* ref_list;  // [R]
     const int32_t* outage;    // [nrep] branch out of service in a replica, or -1
-    // objective scratch: one partial per (generator chunk, pg replica) and a
-    // self-resetting arrival counter
+    // objective partials, one per (generator chunk, pg replica)
     double* obj_part;         // [ngchunks * npg]
-    int32_t* obj_ticket;      // [1]
-    // half-edge terms passed from the branch phase to the bus phase:
-    // row k, replica r, entry s at scr[(k * nrep + r) * nscr + s]
-    double* scr;
+    // half-edge records passed from the branch phase to the bus phase:
+    // replica r, branch l, side s at rec + ((r * L + l) * 2 + s) * kRec
+    double* rec;
 };
 
 struct EvalOut {
@@ -87,15 +93,20 @@ struct EvalOut {
     double* H;
 };
 
-// Work counts of one plain launch of each phase.  Phase-2 items are ordered
-// big buses, waves, generator chunks; every item covers `rg` consecutive
-// replicas.
+// Work counts of one plain launch of each phase.  Phase-1 items are branch
+// chunks then generator chunks; phase-2 items are big buses, waves, then
+// the objective item (callback set) or the generator items (J^T v).  Every
+// item covers a group of consecutive replicas.
 struct SetGrid {
-    int32_t n_branch, rg1;            // phase 1 items, replicas per item
-    int32_t n_big, n_wave, n_gen;     // phase 2 items
+    int32_t n_branch, rg1;            // phase 1 branch items, replicas per item
+    int32_t n_gen1, rgg, gen_nrep;    // phase 1 generator items, replicas per item, replicas covered
+    int32_t n_big, n_wave;            // phase 2 bus items
     int32_t rg2, nrg2;                // phase 2 replicas per item, replica groups
-    int32_t gen_per_item;             // 0 = chunks of kBlock generators; 1 = one generator a wave
-    int32_t phase2() const { return n_big + n_wave + n_gen; }
+    int32_t n_obj;                    // phase 2 objective item (0 or 1)
+    int32_t n_gen2;                   // phase 2 generator items (J^T v)
+    int32_t gen_per_item;             // J^T v: 0 = chunks of kBlock generators; 1 = one generator a wave
+    int32_t phase1() const { return n_branch + n_gen1; }
+    int32_t phase2() const { return n_big + n_wave + n_obj + n_gen2; }
 };
 
 }  // namespace opf

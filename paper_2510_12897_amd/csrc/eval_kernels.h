@@ -18,7 +18,8 @@ hipError_t launch_eval_set(const DevModel& m, const EvalOut& o, hipStream_t stre
 // out = J(x)^T v on `stream`.
 hipError_t launch_jtprod(const DevModel& m, const double* x, const double* v, double* out, hipStream_t stream);
 
-// ---- batched evaluation: a persistent kernel over a queue of work items.
+// ---- batched evaluation: one persistent kernel per phase over a list of
+// work items.
 struct BatchItem {
     int32_t inst, kind, idx, r0, r1, pad;  // replicas [r0, r1)
 };
@@ -32,7 +33,6 @@ struct BatchArgs {
     const BatchInst* inst;   // [n_inst] device
     const BatchItem* items;  // [n_items] device
     int32_t n_items;
-    int32_t* counters;       // [2] device: next item, finished workgroups (self-resetting)
     const double* X;
     const double* Y;
     const double* sigma;
@@ -41,11 +41,12 @@ struct BatchArgs {
                              // 2 = arc flows (G is the X written in place)
 };
 
-// Scratch bytes a model needs per evaluation stream: objective partials and
-// ticket, then the half-edge terms (S_ROWS x replicas x entries doubles).
+// Scratch bytes a model needs per evaluation stream: objective partials,
+// then the half-edge records (kRec doubles per replica, branch, side).
 size_t scratch_bytes(const DevModel& m);
 
-// The persistent kernel's entry, for graph kernel nodes (argument: BatchArgs).
-void* batch_kernel_fn();
+// The persistent kernel of phase 0 (branch items) or 1 (bus items), for
+// graph kernel nodes (argument: BatchArgs).
+void* batch_kernel_fn(int phase);
 
 }  // namespace opf

@@ -6,24 +6,32 @@
 // model, so every launch shape (plain grid, persistent batch, any replica
 // grouping) gives bitwise the same results.
 //
-// A callback set runs in two phases, each a 64-lane-workgroup launch:
+// A callback set runs in two phases, each a 64-lane-workgroup launch, and
+// each phase writes only outputs laid out in its own order, so every store
+// of a wave lands in a few contiguous runs (no scattered partial-line
+// writes, which the per-XCD L2s would each write back separately):
 //  phase 1, branch items (one lane per branch, branch order, so branch data,
 //    multipliers and arc variables are read coalesced; only the four bus
 //    voltages are gathered): the four flow rows, the angle row and the two
-//    thermal rows (c, J), the arc Hessian diagonals, the branch's
-//    off-diagonal Hessian entries, and for each of its two half-edges the
-//    bus-side terms (arc p and q, weighted second derivatives) written to a
-//    scratch laid out in the bus-side order;
+//    thermal rows (c, J), the arc Hessian diagonals, and one 48-byte record
+//    per half-edge (the weighted second derivatives of the branch's flow
+//    rows and the arc's p, q), written contiguously in branch order;
 //  phase 2, bus items: waves of packed bus segments [head, half-edges,
 //    generators] (the host packs them so no segment straddles a wave and
-//    precomputes every lane's output positions).  Each lane reads its own
-//    scratch entries (coalesced), stages them in LDS, and the head lane
-//    reduces its segment in order (a segmented reduction) into the balance
-//    rows and the bus's Hessian diagonal; buses wider than a wave are
-//    reduced by a whole workgroup; generator items write the gradient, the
-//    pg Hessian diagonal, reference and ramp rows, and one objective
-//    partial per (chunk, replica) -- the chunk whose arrival completes a
-//    self-resetting ticket sums the partials in index order.
+//    precomputes every lane's output positions).  Each half-edge lane reads
+//    its record (one aligned 48-byte gather), stages it in LDS, and the
+//    head lane reduces its segment in order (a segmented reduction) into the
+//    balance rows and the bus's Hessian diagonal, while the first half-edge
+//    of each neighbour group writes the group's off-diagonal Hessian
+//    entries (parallel branches summed); all of these sit in the bus's own
+//    Hessian rows.  Buses wider than a wave are reduced by a whole
+//    workgroup; generator items write the gradient, the pg Hessian
+//    diagonal, reference and ramp rows, and one objective partial per
+//    (chunk, replica) -- the chunk whose arrival completes a self-resetting
+//    ticket sums the partials in index order.
+// Workgroups are dealt to the 8 XCDs round-robin; both launches remap the
+// block index so that each XCD takes a contiguous range of work items, and
+// the cache lines that neighbouring items share meet in one L2.
 //
 // Branch flows follow the pi model of the PowerModels formulation the paper
 // uses:  F = alpha u^2 + beta w^2 + u w (a cos(th) + b sin(th)),
@@ -58,15 +66,22 @@ __device__ __forceinline__ Coef in_service(const Coef& k, const DevModel& m, int
     return m.outage[r] == l ? Coef{0, 0, 0, 0, 0, 0, 0, 0} : k;
 }
 
-__device__ __forceinline__ double* scr_at(const DevModel& m, int32_t row, int32_t r, int64_t s) {
-    return m.scr + ((int64_t)row * m.nrep + r) * m.nscr + s;
+// Half-edge record of (replica r, branch l, side s): kRec doubles, the two
+// sides of a branch adjacent, branches in order.
+__device__ __forceinline__ double* rec_at(const DevModel& m, int32_t r, int32_t l, int32_t side) {
+    return m.rec + (((int64_t)r * m.L + l) * 2 + side) * kRec;
+}
+// The J^T v record: two doubles (va term, vm term) per half-edge.
+__device__ __forceinline__ double* jt_rec_at(const DevModel& m, int32_t r, int32_t l, int32_t side) {
+    return m.rec + (((int64_t)r * m.L + l) * 2 + side) * 2;
 }
 
-__device__ __forceinline__ double coherent_load(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void coherent_store(double* p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Block index -> work item, so that each XCD (blocks b with b % kXcd equal)
+// takes one contiguous range of the nb items.
+__device__ __forceinline__ int32_t xcd_item(int32_t b, int32_t nb) {
+    const int32_t q = nb / kXcd, rem = nb % kXcd;
+    const int32_t x = b % kXcd, j = b / kXcd;
+    return x * q + min(x, rem) + j;
 }
 
 // Sum over the wave in a fixed tree order; lane 0 holds the total.
@@ -162,22 +177,11 @@ __device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, 
     const bool wantFlow = wantC || wantJ || wantH;
     const int32_t fb = m.f_bus[l], tb = m.t_bus[l];
     const bool f_lo = fb < tb;
-    int32_t s_fr = 0, s_to = 0, hx0 = -1, hx1 = -1, hx2 = -1, hx3 = -1;
-    if (wantC || wantH) {
-        s_fr = m.br_scr[l];
-        s_to = m.br_scr[L + l];
-    }
-    if (wantH) {
-        hx0 = m.br_hx[l];
-        hx1 = m.br_hx[L + l];
-        hx2 = m.br_hx[2 * L + l];
-        hx3 = m.br_hx[3 * L + l];
-    }
     Coef k0{};
     double rate2 = 0.0;
     if (wantFlow) {
         k0 = load_coef(m, l);
-        rate2 = m.rate2[l];
+        if (wantC) rate2 = m.rate2[l];
     }
     const double* x = o.x;
     for (int32_t r = r0; r < r1; r++) {
@@ -204,11 +208,6 @@ __device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, 
                 o.c[m.c_ang + rl] = vaf - vat;
                 o.c[m.c_thf + rl] = pf * pf + qf * qf - rate2;
                 o.c[m.c_tht + rl] = pt * pt + qt * qt - rate2;
-                // arc terms of the two balance rows
-                *scr_at(m, S_P, r, s_fr) = pf;
-                *scr_at(m, S_Q, r, s_fr) = qf;
-                *scr_at(m, S_P, r, s_to) = pt;
-                *scr_at(m, S_Q, r, s_to) = qt;
             }
             if (wantJ) {
                 o.J[m.j_ang + 2 * rl] = f_lo ? 1.0 : -1.0;
@@ -218,6 +217,9 @@ __device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, 
                 o.J[m.j_tht + 2 * rl] = 2.0 * pt;
                 o.J[m.j_tht + 2 * rl + 1] = 2.0 * qt;
             }
+            // the two half-edge records: [TT, MA, MM, UW, P, Q] at the from
+            // side, then at the to side (12 doubles, 16-byte aligned)
+            double2* rec = reinterpret_cast<double2*>(rec_at(m, r, l, 0));
             if (wantH) {
                 const double yf = o.y[m.c_thf + rl], yt = o.y[m.c_tht + rl];
                 o.H[m.h_p + afr] = 2.0 * yf;
@@ -226,28 +228,15 @@ __device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, 
                 o.H[m.h_q + ato] = 2.0 * yt;
                 const Hterms h = hess_terms(k, o.y[m.c_pfr + rl], o.y[m.c_qfr + rl], o.y[m.c_pto + rl],
                                             o.y[m.c_qto + rl], u, w, C, S);
-                // bus-side diagonal terms: (va_i, va_i), (vm_i, va_i), (vm_i, vm_i)
-                *scr_at(m, S_DAA, r, s_fr) = h.Stt;
-                *scr_at(m, S_DMA, r, s_fr) = h.Sut;
-                *scr_at(m, S_DMM, r, s_fr) = h.Suu;
-                *scr_at(m, S_DAA, r, s_to) = h.Stt;
-                *scr_at(m, S_DMA, r, s_to) = -h.Swt;
-                *scr_at(m, S_DMM, r, s_to) = h.Sww;
-                // off-diagonal: (va_f, va_t), (vm_f, vm_t), (vm_f, va_t), (vm_t, va_f)
-                const int64_t hva = m.h_va + m.hva_rep * r, hvm = m.h_vm + m.hvm_rep * r;
-                if (hx0 >= 0) {
-                    o.H[hva + hx0] = -h.Stt;
-                    o.H[hvm + hx1] = h.Suw;
-                    o.H[hvm + hx2] = -h.Sut;
-                    o.H[hvm + hx3] = h.Swt;
-                } else {  // parallel branches: the bus side sums the group
-                    *scr_at(m, S_XAA, r, s_fr) = -h.Stt;
-                    *scr_at(m, S_XMA, r, s_fr) = -h.Sut;
-                    *scr_at(m, S_XMM, r, s_fr) = h.Suw;
-                    *scr_at(m, S_XAA, r, s_to) = -h.Stt;
-                    *scr_at(m, S_XMA, r, s_to) = h.Swt;
-                    *scr_at(m, S_XMM, r, s_to) = h.Suw;
-                }
+                // d/dva_f = d/dth, d/dva_t = -d/dth
+                rec[0] = make_double2(h.Stt, h.Sut);
+                rec[1] = make_double2(h.Suu, h.Suw);
+                rec[3] = make_double2(h.Stt, -h.Swt);
+                rec[4] = make_double2(h.Sww, h.Suw);
+            }
+            if (wantC) {
+                rec[2] = make_double2(pf, qf);
+                rec[5] = make_double2(pt, qt);
             }
         }
         if (o.g) {
@@ -266,7 +255,6 @@ __device__ void jt_branch_task(const DevModel& m, const EvalOut& o, int32_t chun
     if (l >= m.L) return;
     const int64_t L = m.L, N = m.N;
     const int32_t fb = m.f_bus[l], tb = m.t_bus[l];
-    const int32_t s_fr = m.br_scr[l], s_to = m.br_scr[L + l];
     const Coef k0 = load_coef(m, l);
     const double* x = o.x;
     const double* v = o.y;
@@ -290,10 +278,9 @@ __device__ void jt_branch_task(const DevModel& m, const EvalOut& o, int32_t chun
         const Jterms j = jt_terms(k, v1, v2, v3, v4, u, w, C, S);
         const double va = v[m.c_ang + rl];
         // d th / d va_f = 1, d th / d va_t = -1; the angle row is va_f - va_t
-        *scr_at(m, S_P, r, s_fr) = j.Dt + va;
-        *scr_at(m, S_Q, r, s_fr) = j.Du;
-        *scr_at(m, S_P, r, s_to) = -j.Dt - va;
-        *scr_at(m, S_Q, r, s_to) = j.Dw;
+        double2* rec = reinterpret_cast<double2*>(jt_rec_at(m, r, l, 0));
+        rec[0] = make_double2(j.Dt + va, j.Du);
+        rec[1] = make_double2(-j.Dt - va, j.Dw);
     }
 }
 
@@ -331,11 +318,10 @@ __device__ __forceinline__ Slot load_slot(const DevModel& m, int32_t w) {
 
 __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_t r0, int32_t r1, double* lds) {
     const int32_t lane = threadIdx.x;
-    const int64_t sidx = (int64_t)w * kBlock + lane;  // this lane's scratch entry
     const Slot sl = load_slot(m, w);
     const int32_t type = sl.kind & 3;
+    const int32_t side = (sl.kind & 4) ? 0 : 1;  // the half-edge sits at its branch's from bus
     const bool leader = sl.kind & 8;
-    const bool grouped = sl.kind & 16;
     const int32_t len = (sl.kind >> 8) & 0xff;  // segment (head) or group (leader) length
     const bool wantC = o.c != nullptr, wantH = o.H != nullptr;
     const int64_t N = m.N, G = m.G;
@@ -346,7 +332,7 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
         bs = m.bs[sl.bus];
     }
     for (int32_t r = r0; r < r1; r++) {
-        double v[S_ROWS] = {0, 0, 0, 0, 0, 0, 0, 0};
+        double v[kRec] = {0, 0, 0, 0, 0, 0};
         double vm_i = 0.0, base_p = 0.0, base_q = 0.0, shunt = 0.0;
         if (type == SK_HEAD) {
             vm_i = x[m.x_vm + sl.bus + N * r];
@@ -357,37 +343,36 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
             }
             if (wantH) shunt = 2.0 * gs * o.y[m.c_balp + sl.bus + N * r] - 2.0 * bs * o.y[m.c_balq + sl.bus + N * r];
         } else if (type == SK_EDGE) {
-            if (wantC) {
-                v[S_P] = *scr_at(m, S_P, r, sidx);
-                v[S_Q] = *scr_at(m, S_Q, r, sidx);
-            }
+            const double2* rec = reinterpret_cast<const double2*>(rec_at(m, r, sl.ref, side));
             if (wantH) {
-                v[S_DAA] = *scr_at(m, S_DAA, r, sidx);
-                v[S_DMA] = *scr_at(m, S_DMA, r, sidx);
-                v[S_DMM] = *scr_at(m, S_DMM, r, sidx);
-                if (grouped) {
-                    v[S_XAA] = *scr_at(m, S_XAA, r, sidx);
-                    v[S_XMA] = *scr_at(m, S_XMA, r, sidx);
-                    v[S_XMM] = *scr_at(m, S_XMM, r, sidx);
-                }
+                const double2 a = rec[0], b = rec[1];
+                v[R_TT] = a.x;
+                v[R_MA] = a.y;
+                v[R_MM] = b.x;
+                v[R_UW] = b.y;
+            }
+            if (wantC) {
+                const double2 c = rec[2];
+                v[R_P] = c.x;
+                v[R_Q] = c.y;
             }
         } else if (type == SK_GEN) {
             if (wantC) {
-                v[S_P] = -x[m.x_pg + sl.ref + G * (m.npg > 1 ? r : 0)];
-                v[S_Q] = -x[m.x_qg + sl.ref + G * r];
+                v[R_P] = -x[m.x_pg + sl.ref + G * (m.npg > 1 ? r : 0)];
+                v[R_Q] = -x[m.x_qg + sl.ref + G * r];
             }
         }
         if (wantC || wantH) {
-            for (int q = 0; q < S_ROWS; q++) lds[q * kBlock + lane] = v[q];
+            for (int q = 0; q < kRec; q++) lds[q * kBlock + lane] = v[q];
             __syncthreads();
             if (type == SK_HEAD) {
                 double sp = base_p, sq = base_q, daa = 0.0, dma = 0.0, dmm = 0.0;
                 for (int32_t j = 1; j < len; j++) {  // the segment, in order
-                    sp += lds[S_P * kBlock + lane + j];
-                    sq += lds[S_Q * kBlock + lane + j];
-                    daa += lds[S_DAA * kBlock + lane + j];
-                    dma += lds[S_DMA * kBlock + lane + j];
-                    dmm += lds[S_DMM * kBlock + lane + j];
+                    sp += lds[R_P * kBlock + lane + j];
+                    sq += lds[R_Q * kBlock + lane + j];
+                    daa += lds[R_TT * kBlock + lane + j];
+                    dma += lds[R_MA * kBlock + lane + j];
+                    dmm += lds[R_MM * kBlock + lane + j];
                 }
                 if (wantC) {
                     o.c[m.c_balp + sl.bus + N * r] = sp;
@@ -399,17 +384,18 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
                     if (sl.h1 >= 0) o.H[hvm + sl.h1] = dma;
                     o.H[hvm + sl.h2] = dmm + shunt;
                 }
-            } else if (type == SK_EDGE && wantH && leader && grouped) {
-                double xaa = v[S_XAA], xma = v[S_XMA], xmm = v[S_XMM];
-                for (int32_t j = 1; j < len; j++) {  // parallel branches to one neighbour
-                    xaa += lds[S_XAA * kBlock + lane + j];
-                    xma += lds[S_XMA * kBlock + lane + j];
-                    xmm += lds[S_XMM * kBlock + lane + j];
+            } else if (type == SK_EDGE && wantH && leader) {
+                // the neighbour group (parallel branches to one bus), in order
+                double tt = v[R_TT], ma = v[R_MA], uw = v[R_UW];
+                for (int32_t j = 1; j < len; j++) {
+                    tt += lds[R_TT * kBlock + lane + j];
+                    ma += lds[R_MA * kBlock + lane + j];
+                    uw += lds[R_UW * kBlock + lane + j];
                 }
                 const int64_t hva = m.h_va + m.hva_rep * r, hvm = m.h_vm + m.hvm_rep * r;
-                if (sl.h0 >= 0) o.H[hva + sl.h0] = xaa;
-                o.H[hvm + sl.h1] = xma;
-                if (sl.h2 >= 0) o.H[hvm + sl.h2] = xmm;
+                if (sl.h0 >= 0) o.H[hva + sl.h0] = -tt;
+                o.H[hvm + sl.h1] = -ma;
+                if (sl.h2 >= 0) o.H[hvm + sl.h2] = uw;
             }
             __syncthreads();  // LDS is reused by the next replica
         }
@@ -436,9 +422,9 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
 // J^T v, phase 2: va / vm entries of the packed buses.
 __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_t r0, int32_t r1, double* lds) {
     const int32_t lane = threadIdx.x;
-    const int64_t sidx = (int64_t)w * kBlock + lane;
     const Slot sl = load_slot(m, w);
     const int32_t type = sl.kind & 3;
+    const int32_t side = (sl.kind & 4) ? 0 : 1;
     const int32_t len = (sl.kind >> 8) & 0xff;
     const int64_t N = m.N;
     const double* x = o.x;
@@ -446,8 +432,9 @@ __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int
     for (int32_t r = r0; r < r1; r++) {
         double ga = 0.0, gm = 0.0;
         if (type == SK_EDGE) {
-            ga = *scr_at(m, S_P, r, sidx);
-            gm = *scr_at(m, S_Q, r, sidx);
+            const double2 t = *reinterpret_cast<const double2*>(jt_rec_at(m, r, sl.ref, side));
+            ga = t.x;
+            gm = t.y;
         }
         lds[0 * kBlock + lane] = ga;
         lds[1 * kBlock + lane] = gm;
@@ -471,11 +458,10 @@ __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int
 }
 
 // A bus whose segment does not fit a wave: the workgroup sums its
-// half-edges' scratch entries (lane-strided, then a fixed wave tree).
+// half-edges' records (lane-strided, then a fixed wave tree).
 __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32_t r0, int32_t r1) {
     const int32_t b = m.big_bus[idx];
     const int32_t e0 = m.adj_ptr[b], e1 = m.adj_ptr[b + 1], deg = e1 - e0;
-    const int32_t s0 = m.big_scr[idx];
     const int64_t N = m.N, G = m.G;
     const double* x = o.x;
     const bool wantH = o.H != nullptr, wantC = o.c != nullptr;
@@ -487,14 +473,16 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
         if (wantC || wantH) {
             double sp = 0.0, sq = 0.0, daa = 0.0, dma = 0.0, dmm = 0.0;
             for (int32_t q = threadIdx.x; q < deg; q += kBlock) {
+                const int32_t code = m.he[e0 + q];
+                const double* rec = rec_at(m, r, code >> 1, (code & 1) ? 0 : 1);
                 if (wantC) {
-                    sp += *scr_at(m, S_P, r, s0 + q);
-                    sq += *scr_at(m, S_Q, r, s0 + q);
+                    sp += rec[R_P];
+                    sq += rec[R_Q];
                 }
                 if (wantH) {
-                    daa += *scr_at(m, S_DAA, r, s0 + q);
-                    dma += *scr_at(m, S_DMA, r, s0 + q);
-                    dmm += *scr_at(m, S_DMM, r, s0 + q);
+                    daa += rec[R_TT];
+                    dma += rec[R_MA];
+                    dmm += rec[R_MM];
                 }
             }
             sp = wave_sum(sp);
@@ -502,27 +490,28 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
             daa = wave_sum(daa);
             dma = wave_sum(dma);
             dmm = wave_sum(dmm);
-            if (wantH) {  // parallel-branch groups: the group's first half-edge sums it
+            if (wantH) {  // each neighbour group's first half-edge sums the group
                 const int64_t hva = m.h_va + m.hva_rep * r + m.hva_off[b];
                 const int64_t hvm = m.h_vm + m.hvm_rep * r + m.hvm_off[b];
                 for (int32_t e = e0 + (int32_t)threadIdx.x; e < e1; e += kBlock) {
                     const int32_t grp = m.he_grp[e];
                     if (e > e0 && m.he_grp[e - 1] == grp) continue;
-                    if (!(e + 1 < e1 && m.he_grp[e + 1] == grp)) continue;  // single branch: written in phase 1
                     const int32_t code = m.he[e], l = code >> 1;
                     const int32_t k = (code & 1) ? m.t_bus[l] : m.f_bus[l];
-                    double xaa = 0.0, xma = 0.0, xmm = 0.0;
+                    double tt = 0.0, ma = 0.0, uw = 0.0;
                     for (int32_t q = e; q < e1 && m.he_grp[q] == grp; q++) {
-                        xaa += *scr_at(m, S_XAA, r, s0 + (q - e0));
-                        xma += *scr_at(m, S_XMA, r, s0 + (q - e0));
-                        xmm += *scr_at(m, S_XMM, r, s0 + (q - e0));
+                        const int32_t cq = m.he[q];
+                        const double* rec = rec_at(m, r, cq >> 1, (cq & 1) ? 0 : 1);
+                        tt += rec[R_TT];
+                        ma += rec[R_MA];
+                        uw += rec[R_UW];
                     }
                     if (k < b) {
-                        o.H[hva + grp] = xaa;
-                        o.H[hvm + grp] = xma;
-                        o.H[hvm + m.ndist[b] + 1 + grp] = xmm;
+                        o.H[hva + grp] = -tt;
+                        o.H[hvm + grp] = -ma;
+                        o.H[hvm + m.ndist[b] + 1 + grp] = uw;
                     } else {
-                        o.H[hvm + grp + 1] = xma;
+                        o.H[hvm + grp + 1] = -ma;
                     }
                 }
             }
@@ -566,16 +555,17 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
 
 __device__ void jt_big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32_t r0, int32_t r1) {
     const int32_t b = m.big_bus[idx];
-    const int32_t deg = m.adj_ptr[b + 1] - m.adj_ptr[b];
-    const int32_t s0 = m.big_scr[idx];
+    const int32_t e0 = m.adj_ptr[b], deg = m.adj_ptr[b + 1] - e0;
     const int64_t N = m.N;
     const double* x = o.x;
     const double* v = o.y;
     for (int32_t r = r0; r < r1; r++) {
         double sa = 0.0, sm = 0.0;
         for (int32_t q = threadIdx.x; q < deg; q += kBlock) {
-            sa += *scr_at(m, S_P, r, s0 + q);
-            sm += *scr_at(m, S_Q, r, s0 + q);
+            const int32_t code = m.he[e0 + q];
+            const double* rec = jt_rec_at(m, r, code >> 1, (code & 1) ? 0 : 1);
+            sa += rec[0];
+            sm += rec[1];
         }
         sa = wave_sum(sa);
         sm = wave_sum(sm);
@@ -591,6 +581,10 @@ __device__ void jt_big_task(const DevModel& m, const EvalOut& o, int32_t idx, in
 }
 
 // ------------------------------------------------------------------ generators
+// Phase 1: per generator chunk the gradient, the pg Hessian diagonal, the
+// reference and ramp rows, and one objective partial per replica (a fixed
+// wave tree over the chunk), written with a plain store: the objective item
+// of phase 2 reads the partials after the launch boundary.
 __device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r0, int32_t r1) {
     const int32_t k = chunk * kBlock + (int32_t)threadIdx.x;
     const double* x = o.x;
@@ -601,7 +595,6 @@ __device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int
         c1 = m.c1[k];
         c0 = m.c0[k];
     }
-    int32_t parts = 0;
     for (int32_t r = r0; r < r1; r++) {
         double fk = 0.0;
         if (k < m.G) {
@@ -629,31 +622,20 @@ __device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int
         }
         if (o.f && r < m.npg) {
             const double s = wave_sum(fk);
-            if (threadIdx.x == 0) coherent_store(&m.obj_part[chunk + (int64_t)m.ngchunks * r], s);
-            parts++;
+            if (threadIdx.x == 0) m.obj_part[chunk + (int64_t)m.ngchunks * r] = s;
         }
     }
-    if (o.f && parts > 0) {
-        // the chunk that brings the count to ngchunks * npg sums every partial
-        __shared__ int32_t last;
-        if (threadIdx.x == 0) {
-            const int32_t total = m.ngchunks * m.npg;
-            const int32_t old = __hip_atomic_fetch_add(m.obj_ticket, parts, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            last = (old + parts == total) ? 1 : 0;
-        }
-        __syncthreads();
-        if (last) {
-            __atomic_thread_fence(__ATOMIC_ACQUIRE);
-            const int32_t total = m.ngchunks * m.npg;
-            double acc = 0.0;
-            for (int32_t q = threadIdx.x; q < total; q += kBlock) acc += coherent_load(&m.obj_part[q]);
-            acc = wave_sum(acc);
-            if (threadIdx.x == 0) {
-                *o.f = acc;
-                __hip_atomic_store(m.obj_ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-    }
+}
+
+// Phase 2: f = the partials summed lane-strided in index order, then a
+// fixed wave tree.
+__device__ void obj_task(const DevModel& m, const EvalOut& o) {
+    if (o.f == nullptr) return;
+    const int32_t total = m.ngchunks * m.npg;
+    double acc = 0.0;
+    for (int32_t q = threadIdx.x; q < total; q += kBlock) acc += m.obj_part[q];
+    acc = wave_sum(acc);
+    if (threadIdx.x == 0) *o.f = acc;
 }
 
 __device__ void jt_gen_task(const DevModel& m, const EvalOut& o, int32_t idx, int32_t r0, int32_t r1) {
@@ -690,24 +672,49 @@ __device__ void jt_gen_task(const DevModel& m, const EvalOut& o, int32_t idx, in
 }  // namespace
 
 // ================================================================== dispatch
-__device__ void run_task(const DevModel& m, const EvalOut& o, int32_t mode, int32_t kind, int32_t idx, int32_t r0,
-                         int32_t r1, double* lds) {
-    if (mode == 2) {
-        flows_task(m, o, idx, r0, r1);
+__device__ __forceinline__ void run_phase1(const DevModel& m, const EvalOut& o, int32_t mode, int32_t kind,
+                                           int32_t idx, int32_t r0, int32_t r1) {
+    if (kind == T_GEN) {
+        if (mode == 0) gen_task(m, o, idx, r0, r1);
     } else if (mode == 0) {
+        branch_task(m, o, idx, r0, r1);
+    } else if (mode == 1) {
+        jt_branch_task(m, o, idx, r0, r1);
+    } else {
+        flows_task(m, o, idx, r0, r1);
+    }
+}
+
+__device__ __forceinline__ void run_phase2(const DevModel& m, const EvalOut& o, int32_t mode, int32_t kind,
+                                           int32_t idx, int32_t r0, int32_t r1, double* lds) {
+    if (mode == 0) {
         switch (kind) {
-        case T_BRANCH: branch_task(m, o, idx, r0, r1); break;
         case T_BIG: big_task(m, o, idx, r0, r1); break;
         case T_WAVE: wave_task(m, o, idx, r0, r1, lds); break;
-        default: gen_task(m, o, idx, r0, r1); break;
+        default: obj_task(m, o); break;
         }
     } else {
         switch (kind) {
-        case T_BRANCH: jt_branch_task(m, o, idx, r0, r1); break;
         case T_BIG: jt_big_task(m, o, idx, r0, r1); break;
         case T_WAVE: jt_wave_task(m, o, idx, r0, r1, lds); break;
         default: jt_gen_task(m, o, idx, r0, r1); break;
         }
+    }
+}
+
+__device__ __forceinline__ void decode_phase1(const SetGrid& g, const DevModel& m, int32_t b, int32_t& kind,
+                                              int32_t& idx, int32_t& r0, int32_t& r1) {
+    if (b < g.n_branch) {
+        kind = T_BRANCH;
+        idx = b % m.nbchunks;
+        r0 = (b / m.nbchunks) * g.rg1;
+        r1 = min(r0 + g.rg1, m.nrep);
+    } else {
+        b -= g.n_branch;
+        kind = T_GEN;
+        idx = b % m.ngchunks;
+        r0 = (b / m.ngchunks) * g.rgg;
+        r1 = min(r0 + g.rgg, g.gen_nrep);
     }
 }
 
@@ -720,8 +727,12 @@ __device__ __forceinline__ void decode_phase2(const SetGrid& g, const DevModel& 
     } else if ((b -= g.n_big) < g.n_wave) {
         kind = T_WAVE;
         per = m.nwaves;
+    } else if ((b -= g.n_wave) < g.n_obj) {
+        kind = T_OBJ;
+        idx = r0 = r1 = 0;
+        return;
     } else {
-        b -= g.n_wave;
+        b -= g.n_obj;
         kind = T_GEN;
         if (g.gen_per_item) {  // one generator per wave, all replicas
             idx = b;
@@ -731,6 +742,8 @@ __device__ __forceinline__ void decode_phase2(const SetGrid& g, const DevModel& 
         }
         per = m.ngchunks;
     }
+    // replica groups outermost, so one XCD's contiguous item range covers
+    // neighbouring entities of the same replicas
     idx = b % per;
     r0 = (b / per) * g.rg2;
     r1 = min(r0 + g.rg2, m.nrep);
@@ -738,71 +751,71 @@ __device__ __forceinline__ void decode_phase2(const SetGrid& g, const DevModel& 
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) branch_kernel(DevModel m, EvalOut o, SetGrid g) {
-    const int32_t b = blockIdx.x;
-    const int32_t idx = b % m.nbchunks;
-    const int32_t r0 = (b / m.nbchunks) * g.rg1;
-    const int32_t r1 = min(r0 + g.rg1, m.nrep);
-    if (MODE == 0)
-        branch_task(m, o, idx, r0, r1);
-    else
-        jt_branch_task(m, o, idx, r0, r1);
+    int32_t kind, idx, r0, r1;
+    decode_phase1(g, m, xcd_item(blockIdx.x, gridDim.x), kind, idx, r0, r1);
+    run_phase1(m, o, MODE, kind, idx, r0, r1);
 }
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) bus_kernel(DevModel m, EvalOut o, SetGrid g) {
-    __shared__ double lds[S_ROWS * kBlock];
+    __shared__ double lds[kRec * kBlock];
     int32_t kind, idx, r0, r1;
-    decode_phase2(g, m, blockIdx.x, kind, idx, r0, r1);
-    run_task(m, o, MODE, kind, idx, r0, r1, lds);
+    decode_phase2(g, m, xcd_item(blockIdx.x, gridDim.x), kind, idx, r0, r1);
+    run_phase2(m, o, MODE, kind, idx, r0, r1, lds);
 }
 
-// Persistent kernel: every workgroup takes work items of one phase from a
-// shared queue until it is empty.  The last workgroup to leave resets the
-// queue counters, so the launch can be replayed (from a graph) with no reset
-// in between.
-__global__ void __launch_bounds__(kBlock) batch_kernel(BatchArgs a) {
-    __shared__ double lds[S_ROWS * kBlock];
-    __shared__ int32_t next;
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(&a.counters[0], 1);
-        __syncthreads();
-        const int32_t it = next;
-        __syncthreads();
-        if (it >= a.n_items) break;
+// Persistent batch kernels, one per phase: a fixed grid sized to the chip
+// drains the item list.  Items are split into kXcd contiguous ranges, one per
+// XCD, and the workgroups of an XCD stride through its range, so no queue
+// counter is needed and neighbouring items share an L2.
+__device__ __forceinline__ EvalOut batch_out(const BatchArgs& a, const BatchInst& bi, int32_t inst) {
+    EvalOut o;
+    o.x = a.X + bi.xoff;
+    if (a.mode == 0) {
+        o.y = a.Y ? a.Y + bi.coff : nullptr;
+        o.sigma = a.sigma ? a.sigma[inst] : 0.0;
+        o.f = a.F ? a.F + inst : nullptr;
+        o.g = a.G ? a.G + bi.xoff : nullptr;
+        o.c = a.C ? a.C + bi.coff : nullptr;
+        o.J = a.J ? a.J + bi.joff : nullptr;
+        o.H = a.H ? a.H + bi.hoff : nullptr;
+    } else {  // J^T v (Y holds V, G holds OUT) or flows (G is X, written in place)
+        o.y = a.mode == 1 ? a.Y + bi.coff : nullptr;
+        o.sigma = 0.0;
+        o.f = nullptr;
+        o.c = o.J = o.H = nullptr;
+        o.g = a.G + bi.xoff;
+    }
+    return o;
+}
+
+__device__ __forceinline__ void xcd_stride(int32_t n, int32_t& first, int32_t& step, int32_t& end) {
+    const int32_t P = gridDim.x, b = blockIdx.x;
+    const int32_t x = b % kXcd;
+    step = (P - x + kXcd - 1) / kXcd;  // workgroups on this XCD
+    first = (int32_t)((int64_t)n * x / kXcd) + b / kXcd;
+    end = (int32_t)((int64_t)n * (x + 1) / kXcd);
+}
+
+__global__ void __launch_bounds__(kBlock) batch_branch_kernel(BatchArgs a) {
+    int32_t it, step, end;
+    xcd_stride(a.n_items, it, step, end);
+    for (; it < end; it += step) {
         const BatchItem w = a.items[it];
         const BatchInst& bi = a.inst[w.inst];
-        EvalOut o;
-        o.x = a.X + bi.xoff;
-        if (a.mode == 0) {
-            o.y = a.Y ? a.Y + bi.coff : nullptr;
-            o.sigma = a.sigma ? a.sigma[w.inst] : 0.0;
-            o.f = a.F ? a.F + w.inst : nullptr;
-            o.g = a.G ? a.G + bi.xoff : nullptr;
-            o.c = a.C ? a.C + bi.coff : nullptr;
-            o.J = a.J ? a.J + bi.joff : nullptr;
-            o.H = a.H ? a.H + bi.hoff : nullptr;
-        } else if (a.mode == 1) {
-            o.y = a.Y + bi.coff;
-            o.sigma = 0.0;
-            o.f = o.c = o.J = o.H = nullptr;
-            o.g = a.G + bi.xoff;
-        } else {  // flows: X is read and its p, q entries rewritten
-            o.y = nullptr;
-            o.sigma = 0.0;
-            o.f = o.c = o.J = o.H = nullptr;
-            o.g = a.G + bi.xoff;
-        }
-        run_task(bi.m, o, a.mode, w.kind, w.idx, w.r0, w.r1, lds);
-        __syncthreads();
+        run_phase1(bi.m, batch_out(a, bi, w.inst), a.mode, w.kind, w.idx, w.r0, w.r1);
     }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const int32_t done = atomicAdd(&a.counters[1], 1);
-        if (done == (int32_t)gridDim.x - 1) {
-            atomicExch(&a.counters[0], 0);
-            atomicExch(&a.counters[1], 0);
-            __threadfence();
-        }
+}
+
+__global__ void __launch_bounds__(kBlock) batch_bus_kernel(BatchArgs a) {
+    __shared__ double lds[kRec * kBlock];
+    int32_t it, step, end;
+    xcd_stride(a.n_items, it, step, end);
+    for (; it < end; it += step) {
+        const BatchItem w = a.items[it];
+        const BatchInst& bi = a.inst[w.inst];
+        run_phase2(bi.m, batch_out(a, bi, w.inst), a.mode, w.kind, w.idx, w.r0, w.r1, lds);
+        __syncthreads();
     }
 }
 
@@ -820,23 +833,27 @@ SetGrid plan_set(const DevModel& m, const EvalOut& o, int32_t mode) {
     const bool any = mode == 1 || o.g || o.c || o.J || o.H;
     g.rg1 = group_for(m.nbchunks, m.nrep);
     g.n_branch = any ? m.nbchunks * ((m.nrep + g.rg1 - 1) / g.rg1) : 0;
-    g.rg2 = group_for(m.nbig + m.nwaves + m.ngchunks, m.nrep);
+    if (mode == 0 && (any || o.f)) {
+        // the objective alone needs the pg replicas only
+        g.gen_nrep = any ? m.nrep : m.npg;
+        g.rgg = group_for(m.ngchunks, g.gen_nrep);
+        g.n_gen1 = m.ngchunks * ((g.gen_nrep + g.rgg - 1) / g.rgg);
+    }
+    g.rg2 = group_for(m.nbig + m.nwaves, m.nrep);
     g.nrg2 = (m.nrep + g.rg2 - 1) / g.rg2;
     g.n_big = any ? m.nbig * g.nrg2 : 0;
     g.n_wave = any ? m.nwaves * g.nrg2 : 0;
-    if (mode == 1 && m.npg == 1 && m.nrep > 1) {
-        g.gen_per_item = 1;
-        g.n_gen = m.G;
-    } else {
-        g.gen_per_item = 0;
-        g.n_gen = (any || o.f) ? m.ngchunks * g.nrg2 : 0;
+    g.n_obj = (mode == 0 && o.f) ? 1 : 0;
+    if (mode == 1) {
+        g.gen_per_item = (m.npg == 1 && m.nrep > 1) ? 1 : 0;
+        g.n_gen2 = g.gen_per_item ? m.G : m.ngchunks * g.nrg2;
     }
     return g;
 }
 
 hipError_t launch_eval_set(const DevModel& m, const EvalOut& o, hipStream_t stream) {
     const SetGrid g = plan_set(m, o, 0);
-    if (g.n_branch > 0) hipLaunchKernelGGL(branch_kernel<0>, dim3(g.n_branch), dim3(kBlock), 0, stream, m, o, g);
+    if (g.phase1() > 0) hipLaunchKernelGGL(branch_kernel<0>, dim3(g.phase1()), dim3(kBlock), 0, stream, m, o, g);
     if (g.phase2() > 0) hipLaunchKernelGGL(bus_kernel<0>, dim3(g.phase2()), dim3(kBlock), 0, stream, m, o, g);
     return hipGetLastError();
 }
@@ -847,16 +864,18 @@ hipError_t launch_jtprod(const DevModel& m, const double* x, const double* v, do
     o.y = v;
     o.g = out;
     const SetGrid g = plan_set(m, o, 1);
-    if (g.n_branch > 0) hipLaunchKernelGGL(branch_kernel<1>, dim3(g.n_branch), dim3(kBlock), 0, stream, m, o, g);
+    if (g.phase1() > 0) hipLaunchKernelGGL(branch_kernel<1>, dim3(g.phase1()), dim3(kBlock), 0, stream, m, o, g);
     if (g.phase2() > 0) hipLaunchKernelGGL(bus_kernel<1>, dim3(g.phase2()), dim3(kBlock), 0, stream, m, o, g);
     return hipGetLastError();
 }
 
-void* batch_kernel_fn() { return reinterpret_cast<void*>(&batch_kernel); }
+void* batch_kernel_fn(int phase) {
+    return phase == 0 ? reinterpret_cast<void*>(&batch_branch_kernel) : reinterpret_cast<void*>(&batch_bus_kernel);
+}
 
 size_t scratch_bytes(const DevModel& m) {
     const size_t parts = ((sizeof(double) * (size_t)m.ngchunks * m.npg) + 255) & ~size_t(255);
-    return parts + 256 + sizeof(double) * (size_t)S_ROWS * m.nrep * m.nscr;
+    return parts + sizeof(double) * (size_t)kRec * 2 * m.nrep * m.L;
 }
 
 }  // namespace opf

@@ -282,8 +282,6 @@ void build_slots(HostModel& hm) {
     const int32_t N = hm.ly.N, L = hm.ly.L;
     hm.slots.clear();
     hm.big_bus.clear();
-    hm.br_scr.assign(2 * (size_t)L, -1);
-    hm.br_hx.assign(4 * (size_t)L, -1);
     int32_t lane = 0;
     auto push = [&](int32_t kind, int32_t ref, int32_t bus, int32_t other, int32_t jpos, int32_t h0, int32_t h1,
                     int32_t h2) {
@@ -327,7 +325,6 @@ void build_slots(HostModel& hm) {
             const int32_t arank = (int32_t)(std::lower_bound(ab, ae, arc) - ab);
             const int32_t kind = SK_EDGE | (from << 2) | ((leader ? 1 : 0) << 3) | ((glen > 1 ? 1 : 0) << 4) |
                                  ((leader ? glen : 0) << 8);
-            hm.br_scr[(from ? 0 : (size_t)L) + l] = (int32_t)(hm.slots.size() / 8);
             push(kind, l, i, k, jrow + 1 + ng + arank, leader && k < i ? hva + grp : -1,
                  leader ? hvm + grp + (k > i ? 1 : 0) : -1, leader && k < i ? hvm + nd + 1 + grp : -1);
         }
@@ -335,36 +332,6 @@ void build_slots(HostModel& hm) {
     }
     pad_wave();
     hm.nwaves = (int32_t)(hm.slots.size() / (8 * kWaveLanes));
-    // half-edges of big buses follow the wave slots, contiguous per bus in
-    // (neighbour, branch) order
-    int32_t s = hm.nwaves * kWaveLanes;
-    hm.big_scr.assign(1, s);
-    for (int32_t b : hm.big_bus) {
-        for (int32_t q = hm.adj_ptr[b]; q < hm.adj_ptr[b + 1]; q++, s++) {
-            const int32_t code = hm.he[q], l = code >> 1, from = code & 1;
-            hm.br_scr[(from ? 0 : (size_t)L) + l] = s;
-        }
-        hm.big_scr.push_back(s);
-    }
-    hm.nscr = s;
-    // off-diagonal Hessian positions of branches with no parallel twin
-    for (int32_t l = 0; l < L; l++) {
-        const int32_t f = hm.f_bus[l], t = hm.t_bus[l];
-        // the group of this branch at bus f (rank among f's distinct neighbours)
-        int32_t qf = -1, qt = -1;
-        for (int32_t q = hm.adj_ptr[f]; q < hm.adj_ptr[f + 1]; q++)
-            if (hm.he[q] == ((l << 1) | 1)) qf = q;
-        for (int32_t q = hm.adj_ptr[t]; q < hm.adj_ptr[t + 1]; q++)
-            if (hm.he[q] == (l << 1)) qt = q;
-        if (group_len(f, qf) > 1) continue;
-        const int32_t gf = hm.he_grp[qf], gt = hm.he_grp[qt];
-        const int32_t hi = f > t ? f : t;
-        const int32_t g_hi = f > t ? gf : gt;  // rank of the lower bus among hi's neighbours
-        hm.br_hx[0 * (size_t)L + l] = hm.hva_off[hi] + g_hi;                          // (va_hi, va_lo)
-        hm.br_hx[1 * (size_t)L + l] = hm.hvm_off[hi] + hm.ndist[hi] + 1 + g_hi;       // (vm_hi, vm_lo)
-        hm.br_hx[2 * (size_t)L + l] = hm.hvm_off[f] + gf + (t > f ? 1 : 0);           // (vm_f, va_t)
-        hm.br_hx[3 * (size_t)L + l] = hm.hvm_off[t] + gt + (f > t ? 1 : 0);           // (vm_t, va_f)
-    }
 }
 
 void fill_pattern(const HostModel& hm, int32_t* jr, int32_t* jc, int32_t* hr, int32_t* hc) {

@@ -66,17 +66,6 @@ struct HostModel {
     std::vector<int32_t> slots;                // [nwaves * kWaveLanes * 8]
     int32_t nwaves = 0;
     std::vector<int32_t> big_bus;              // buses whose segment does not fit a wave
-    std::vector<int32_t> big_scr;              // [nbig + 1] first scratch entry of each big bus
-    // Scratch entries: one per half-edge, at its wave slot, or after the
-    // wave slots for the half-edges of big buses (contiguous per big bus).
-    int32_t nscr = 0;
-    // Per branch: scratch entry of the from- and to-side half-edge, and the
-    // Hessian positions of its four off-diagonal entries relative to the
-    // replica's va / vm row blocks: (va_hi, va_lo), (vm_hi, vm_lo),
-    // (vm_f, va_t), (vm_t, va_f); -1 when the branch shares its bus pair with
-    // a parallel branch (those entries are summed on the bus side).
-    std::vector<int32_t> br_scr;               // [2][L]
-    std::vector<int32_t> br_hx;                // [4][L]
 };
 
 constexpr int32_t kWaveLanes = 64;
@@ -89,8 +78,9 @@ constexpr int32_t kWaveLanes = 64;
 //  head:      bus i; jpos = first entry of i's balance Jacobian rows;
 //             h0/h1/h2 = Hessian (va_i,va_i), (vm_i,va_i), (vm_i,vm_i) (-1 if absent)
 //  half-edge: ref = branch, bus = i, other = neighbour; jpos = its +1 entry;
-//             h0/h1/h2 = (va_i,va_k), (vm_i,va_k), (vm_i,vm_k) for the group
-//             leader (-1 if absent or not the leader)
+//             h0/h1/h2 = (va_i,va_k), (vm_i,va_k), (vm_i,vm_k) for the first
+//             half-edge of its neighbour group, which writes the group's
+//             off-diagonal entries (-1 if absent or not the group's first)
 //  generator: ref = generator, bus = i; jpos = its -1 entry
 enum SlotKind { SK_IDLE = 0, SK_HEAD = 1, SK_EDGE = 2, SK_GEN = 3 };
 

@@ -110,12 +110,13 @@ int prox_squash_bwd(opf_model model, const float* z, int B, double va_span, cons
                     "prox_squash_bwd launch");
 }
 
-int prox_penalty(opf_model model, const double* C, const double* X, double rho, int B, double* pen, double* cvio,
-                 double* W, double* gpq, void* stream) {
+int prox_penalty(opf_model model, const double* C, const double* X, const double* F, double obj_scale, double rho,
+                 int B, double* pen, double* cvio, double* W, double* gpq, void* stream) {
     if (int rc = static_model(model)) return rc;
     if (B < 1 || !C || !X || !pen || !cvio || !W || !gpq) return set_err(OPF_E_ARG, "bad arguments");
     DeviceGuard dg(model->device);
-    return launched(opf::prox_penalty(C, X, rows_of(model), rho, B, pen, cvio, W, gpq, static_cast<hipStream_t>(stream)),
+    return launched(opf::prox_penalty(C, X, F, obj_scale, rows_of(model), rho, B, pen, cvio, W, gpq,
+                                      static_cast<hipStream_t>(stream)),
                     "prox_penalty launch");
 }
 
@@ -125,6 +126,17 @@ int prox_chain_weights(opf_model model, const double* G1, const double* gpq, int
     DeviceGuard dg(model->device);
     return launched(opf::prox_chain_weights(G1, gpq, rows_of(model), B, W2, static_cast<hipStream_t>(stream)),
                     "prox_chain_weights launch");
+}
+
+int prox_vjp_sum(opf_model model, const double* gX1, const double* gX2, const double* gObj, double obj_scale,
+                 const double* wb, int B, double* gX, void* stream) {
+    if (int rc = static_model(model)) return rc;
+    if (B < 1 || !gX1 || !wb || !gX) return set_err(OPF_E_ARG, "bad arguments");
+    const opf::Layout& ly = model->hm.ly;
+    DeviceGuard dg(model->device);
+    return launched(opf::prox_vjp_sum(gX1, gX2, gObj, obj_scale, wb, B, ly.n, ly.x_p, gX,
+                                      static_cast<hipStream_t>(stream)),
+                    "prox_vjp_sum launch");
 }
 
 }  // extern "C"

@@ -35,9 +35,11 @@ hipError_t prox_adam(float* p, const float* g, float* m1, float* m2, int64_t n, 
 hipError_t prox_squash_fwd(const float* z, int B, const ProxBox& box, double* X, int64_t n, hipStream_t s);
 hipError_t prox_squash_bwd(const float* z, int B, const ProxBox& box, const double* gX1, const double* gX2,
                            const double* gObj, double obj_scale, int64_t n, float* dz, float scale, hipStream_t s);
-hipError_t prox_penalty(const double* C, const double* X, const ProxRows& rows, double rho, int B, double* pen,
-                        double* cvio, double* W, double* gpq, hipStream_t s);
+hipError_t prox_penalty(const double* C, const double* X, const double* F, double obj_scale, const ProxRows& rows,
+                        double rho, int B, double* pen, double* cvio, double* W, double* gpq, hipStream_t s);
 hipError_t prox_chain_weights(const double* G1, const double* gpq, const ProxRows& rows, int B, double* W2,
                               hipStream_t s);
+hipError_t prox_vjp_sum(const double* gX1, const double* gX2, const double* gObj, double obj_scale,
+                        const double* wb, int B, int64_t n, int64_t nfree, double* gX, hipStream_t s);
 
 }  // namespace opf

@@ -273,12 +273,13 @@ __global__ void squash_bwd_kernel(const float* __restrict__ z, int B, ProxBox bo
     dz[idx] = (float)(d * scale);
 }
 
-// Per instance b: the penalty rho * (sum over non-flow rows of viol^2 + sum
-// over p, q of bound viol^2), the constraint violation (max over all rows
-// and variable bounds), the weights w = d penalty / d c (zero on flow rows)
-// and d penalty / d x on the p, q entries.  One workgroup per instance,
-// fixed-order reduction.
+// Per instance b: the loss rho * (sum over non-flow rows of viol^2 + sum
+// over p, q of bound viol^2) + obj_scale * F[b] (F may be NULL), the
+// constraint violation (max over all rows and variable bounds), the weights
+// w = d penalty / d c (zero on flow rows) and d penalty / d x on the p, q
+// entries.  One workgroup per instance, fixed-order reduction.
 __global__ void __launch_bounds__(256) penalty_kernel(const double* __restrict__ C, const double* __restrict__ X,
+                                                      const double* __restrict__ F, double obj_scale,
                                                       ProxRows rows, double rho, double* __restrict__ pen,
                                                       double* __restrict__ cvio, double* __restrict__ W,
                                                       double* __restrict__ gpq) {
@@ -317,7 +318,7 @@ __global__ void __launch_bounds__(256) penalty_kernel(const double* __restrict__
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        pen[b] = rho * s_pen[0];
+        pen[b] = F ? rho * s_pen[0] + obj_scale * F[b] : rho * s_pen[0];
         cvio[b] = s_vio[0];
     }
 }
@@ -345,7 +346,33 @@ __global__ void chain_weights_kernel(const double* __restrict__ G1, const double
     W2[idx] = w;
 }
 
+// gX [B, n] = wb[b] * (gX1 + gX2 + obj_scale * gObj) on the va, vm, pg, qg
+// entries (the free variables of the proxy), zero on the arc variables.
+__global__ void vjp_sum_kernel(const double* __restrict__ gX1, const double* __restrict__ gX2,
+                               const double* __restrict__ gObj, double obj_scale, const double* __restrict__ wb,
+                               int B, int64_t n, int64_t nfree, double* __restrict__ gX) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)B * n) return;
+    const int64_t b = idx / n, e = idx % n;
+    double g = 0.0;
+    if (e < nfree) {
+        g = gX1[idx];
+        if (gX2) g += gX2[idx];
+        if (gObj) g += obj_scale * gObj[idx];
+        g *= wb[b];
+    }
+    gX[idx] = g;
+}
+
 }  // namespace
+
+hipError_t prox_vjp_sum(const double* gX1, const double* gX2, const double* gObj, double obj_scale,
+                        const double* wb, int B, int64_t n, int64_t nfree, double* gX, hipStream_t s) {
+    const int64_t tot = (int64_t)B * n;
+    hipLaunchKernelGGL(vjp_sum_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, gX1, gX2, gObj,
+                       obj_scale, wb, B, n, nfree, gX);
+    return hipGetLastError();
+}
 
 hipError_t prox_gemm(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N,
                      int K, const float* bias, float* act, int accumulate, hipStream_t s) {
@@ -396,9 +423,9 @@ hipError_t prox_squash_bwd(const float* z, int B, const ProxBox& box, const doub
     return hipGetLastError();
 }
 
-hipError_t prox_penalty(const double* C, const double* X, const ProxRows& rows, double rho, int B, double* pen,
-                        double* cvio, double* W, double* gpq, hipStream_t s) {
-    hipLaunchKernelGGL(penalty_kernel, dim3(B), dim3(256), 0, s, C, X, rows, rho, pen, cvio, W, gpq);
+hipError_t prox_penalty(const double* C, const double* X, const double* F, double obj_scale, const ProxRows& rows,
+                        double rho, int B, double* pen, double* cvio, double* W, double* gpq, hipStream_t s) {
+    hipLaunchKernelGGL(penalty_kernel, dim3(B), dim3(256), 0, s, C, X, F, obj_scale, rows, rho, pen, cvio, W, gpq);
     return hipGetLastError();
 }
 

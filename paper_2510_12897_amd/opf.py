@@ -67,7 +67,7 @@ def declared_symbols() -> list:
     """Names of every function declared in include/opf.h."""
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(opf_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b((?:opf|prox)_[a-z0-9_]+)\s*\(", text)))
 
 
 def lib():
@@ -107,6 +107,21 @@ def lib():
         "opf_batch_set_schedule": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
         "opf_batch_eval": ([_vp] + [_vp] * 8 + [_vp], ctypes.c_int),
         "opf_batch_jtprod": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+        "opf_batch_set_loads": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+        "opf_batch_flows": ([_vp, _vp, _vp], ctypes.c_int),
+        "prox_gemm_bf16": ([ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int,
+                            ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp], ctypes.c_int),
+        "prox_gelu_bwd": ([_vp, _vp, _vp, ctypes.c_int64, _vp], ctypes.c_int),
+        "prox_colsum": ([_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_float, _vp], ctypes.c_int),
+        "prox_adam": ([_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                       ctypes.c_float, ctypes.c_int, _vp], ctypes.c_int),
+        "prox_squash_fwd": ([_vp, _vp, ctypes.c_int, ctypes.c_double, _vp, _vp], ctypes.c_int),
+        "prox_squash_bwd": ([_vp, _vp, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, ctypes.c_double, _vp,
+                             ctypes.c_float, _vp], ctypes.c_int),
+        "prox_penalty": ([_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, _vp, _vp, _vp, _vp,
+                          _vp], ctypes.c_int),
+        "prox_chain_weights": ([_vp, _vp, _vp, ctypes.c_int, _vp, _vp], ctypes.c_int),
+        "prox_vjp_sum": ([_vp, _vp, _vp, _vp, ctypes.c_double, _vp, ctypes.c_int, _vp, _vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -416,3 +431,17 @@ class Batch:
         _check(lib().opf_batch_jtprod(self._h, _ptr(X, self.n, d, "X"), _ptr(V, self.m, d, "V"),
                                       _ptr(OUT, self.n, d, "OUT"), _stream()))
         return OUT
+
+    def set_loads(self, pd, qd):
+        """Replace every instance's loads (device tensors laid out like the
+        inst_pd / inst_qd given at creation)."""
+        torch = _torch()
+        _check(lib().opf_batch_set_loads(self._h, _ptr(pd, None, torch.float64, "pd"),
+                                         _ptr(qd, None, torch.float64, "qd"), _stream()))
+
+    def flows(self, X):
+        """Overwrite the arc variables of X (in place) by the branch flows at
+        X's voltages."""
+        torch = _torch()
+        _check(lib().opf_batch_flows(self._h, _ptr(X, self.n, torch.float64, "X"), _stream()))
+        return X

@@ -1,0 +1,353 @@
+"""Learned warm-start proxy: a multilayer perceptron from bus loads to
+(vm, va, pg, qg), trained self-supervised on the FP64 penalty that the
+callback kernels compute.
+
+The paper names learned proxies for OPF as related work whose feasibility is
+the open problem (Sec. I); here the FP64 constraint evaluator is the judge:
+every prediction is completed (arc flows p, q := F(vm, va)) and scored by
+the constraint kernels, and a prediction whose largest violation is worse
+than the plain starting point's falls back to it.
+
+Every step runs in libopf's kernels (argument marshalling only here):
+
+* the MLP's linear layers are BF16 matrix-core GEMMs with FP32 accumulation
+  (``prox_gemm_bf16``), the hidden activations an exact-erf GELU fused into
+  the GEMM epilogue; its backward is three more GEMM layouts, ``prox_colsum``
+  for the biases and ``prox_gelu_bwd``; the optimiser is ``prox_adam``;
+* ``Squash`` maps the network output into the variable boxes
+  (``prox_squash_fwd`` / ``prox_squash_bwd``);
+* ``OPFPenalty`` completes the arc flows (``opf_batch_flows``), evaluates f,
+  grad f and c for the whole batch in one persistent launch
+  (``opf_batch_eval``) and the penalty (``prox_penalty``); its backward is
+  the hand-written vector-Jacobian product: J^T w for the penalty weights,
+  then J^T w2 with the weights that carry the arc-flow gradient back through
+  p = F(vm, va) (``opf_batch_jtprod``, ``prox_chain_weights``,
+  ``prox_vjp_sum``).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+
+from . import opf
+from .opf import OPF_E_ARG, OPFError, _check, lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def gemm(variant, A, lda, B, ldb, C, ldc, M, N, K, bias=None, act=None, accumulate=False):
+    """C[M,N] (+)= A B on the BF16 matrix cores (layouts: see prox_gemm_bf16)."""
+    _check(lib().prox_gemm_bf16(int(variant), _p(A), int(lda), _p(B), int(ldb), _p(C), int(ldc), int(M), int(N),
+                                int(K), _p(bias), _p(act), int(bool(accumulate)), _stream()))
+
+
+# ------------------------------------------------------------------ the MLP
+class MLP:
+    """x [B, n_in] -> z [B, n_out]: `depth` hidden layers of `width` with
+    GELU, then a linear output layer.  Parameters live in one flat FP32
+    buffer (weights [out, in] row-major, then the bias, per layer)."""
+
+    def __init__(self, n_in: int, n_out: int, width: int = 1024, depth: int = 3, seed: int = 0, device: int = 0):
+        torch = _torch()
+        for d in (n_in, n_out, width):
+            if d % 4:
+                raise OPFError(OPF_E_ARG, f"layer widths must be multiples of 4 (got {d})")
+        self.dims = [n_in] + [width] * depth + [n_out]
+        self.device = torch.device("cuda", device)
+        self.layout = []  # (w_off, b_off, n_out, n_in) per layer
+        off = 0
+        for k in range(len(self.dims) - 1):
+            fi, fo = self.dims[k], self.dims[k + 1]
+            self.layout.append((off, off + fo * fi, fo, fi))
+            off += fo * fi + fo
+        self.n_params = off
+        # He-style initialisation drawn on the host from a seeded generator
+        rng = np.random.default_rng(seed)
+        host = np.zeros(off, np.float32)
+        for k, (wo, bo, fo, fi) in enumerate(self.layout):
+            gain = math.sqrt(2.0 / fi) if k < len(self.layout) - 1 else 0.5 / math.sqrt(fi)
+            host[wo:wo + fo * fi] = rng.standard_normal(fo * fi).astype(np.float32) * gain
+        self.flat = torch.from_numpy(host).to(self.device).requires_grad_(True)
+        self.m1 = torch.zeros_like(self.flat, requires_grad=False)
+        self.m2 = torch.zeros_like(self.flat, requires_grad=False)
+        self.step = 0
+
+    def weight(self, k):
+        wo, bo, fo, fi = self.layout[k]
+        return self.flat.detach()[wo:wo + fo * fi].view(fo, fi)
+
+    def bias(self, k):
+        wo, bo, fo, fi = self.layout[k]
+        return self.flat.detach()[bo:bo + fo]
+
+    def __call__(self, x):
+        return _MLPFunction.apply(x, self.flat, self)
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        if self.flat.grad is None:
+            raise OPFError(OPF_E_ARG, "no gradient: run backward first")
+        self.step += 1
+        _check(lib().prox_adam(_p(self.flat), _p(self.flat.grad), _p(self.m1), _p(self.m2), self.n_params,
+                               float(lr), float(beta1), float(beta2), float(eps), self.step, _stream()))
+        self.flat.grad = None
+
+
+class _MLPFunction:
+    """autograd.Function over the whole MLP (built lazily so that the module
+    imports without torch)."""
+    _cls = None
+
+    @classmethod
+    def apply(cls, x, flat, mlp):
+        if cls._cls is None:
+            cls._cls = _make_mlp_function()
+        return cls._cls.apply(x, flat, mlp)
+
+
+def _make_mlp_function():
+    torch = _torch()
+
+    class F(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x, flat, mlp):
+            x = x.contiguous()
+            if x.dtype != torch.float32 or x.dim() != 2 or x.shape[1] != mlp.dims[0]:
+                raise OPFError(OPF_E_ARG, f"input must be float32 [B, {mlp.dims[0]}]")
+            Bn = x.shape[0]
+            acts, pres = [x], []
+            h = x
+            nl = len(mlp.layout)
+            for k in range(nl):
+                wo, bo, fo, fi = mlp.layout[k]
+                pre = torch.empty(Bn, fo, dtype=torch.float32, device=x.device)
+                act = torch.empty_like(pre) if k < nl - 1 else None
+                gemm(0, h, fi, mlp.weight(k), fi, pre, fo, Bn, fo, fi, bias=mlp.bias(k), act=act)
+                pres.append(pre)
+                h = act if act is not None else pre
+                if act is not None:
+                    acts.append(act)
+            ctx.mlp = mlp
+            ctx.acts, ctx.pres = acts, pres
+            return h
+
+        @staticmethod
+        def backward(ctx, gz):
+            mlp = ctx.mlp
+            gz = gz.contiguous()
+            Bn = gz.shape[0]
+            gflat = torch.empty(mlp.n_params, dtype=torch.float32, device=gz.device)
+            nl = len(mlp.layout)
+            dpre = gz
+            chunks = (Bn + 255) // 256
+            work = torch.empty(chunks * max(mlp.dims), dtype=torch.float32, device=gz.device)
+            for k in range(nl - 1, -1, -1):
+                wo, bo, fo, fi = mlp.layout[k]
+                h_in = ctx.acts[k]
+                # dW [fo, fi] = dpre^T h_in; db = column sums of dpre
+                gemm(2, dpre, fo, h_in, fi, gflat[wo:wo + fo * fi], fi, fo, fi, Bn)
+                _check(lib().prox_colsum(_p(dpre), Bn, fo, _p(work), _p(gflat[bo:bo + fo]), ctypes.c_float(1.0),
+                                         _stream()))
+                if k == 0:
+                    break
+                # dh [B, fi] = dpre W, then through the GELU of layer k - 1
+                dh = torch.empty(Bn, fi, dtype=torch.float32, device=gz.device)
+                gemm(1, dpre, fo, mlp.weight(k), fi, dh, fi, Bn, fi, fo)
+                d = torch.empty_like(dh)
+                _check(lib().prox_gelu_bwd(_p(ctx.pres[k - 1]), _p(dh), _p(d), dh.numel(), _stream()))
+                dpre = d
+            return None, gflat, None
+
+    return F
+
+
+# ------------------------------------------------------------------ squashing
+def _make_squash_function():
+    torch = _torch()
+
+    class F(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, z, prox):
+            z = z.contiguous()
+            Bn = z.shape[0]
+            X = torch.empty(Bn, prox.model.n, dtype=torch.float64, device=z.device)
+            _check(lib().prox_squash_fwd(prox.model.handle, _p(z), Bn, float(prox.va_span), _p(X), _stream()))
+            ctx.save_for_backward(z)
+            ctx.prox = prox
+            return X
+
+        @staticmethod
+        def backward(ctx, gX):
+            (z,) = ctx.saved_tensors
+            gX = gX.contiguous()
+            dz = torch.empty_like(z)
+            _check(lib().prox_squash_bwd(ctx.prox.model.handle, _p(z), z.shape[0], float(ctx.prox.va_span), _p(gX),
+                                         None, None, 0.0, _p(dz), ctypes.c_float(1.0), _stream()))
+            return dz, None
+
+    return F
+
+
+def _make_penalty_function():
+    torch = _torch()
+
+    class F(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, X, pen):
+            Xf = X.detach().clone()
+            pen.batch.flows(Xf)
+            B, m = pen.B, pen.model.m
+            dev = X.device
+            Fo = torch.empty(B, dtype=torch.float64, device=dev)
+            Gf = torch.empty(B * pen.model.n, dtype=torch.float64, device=dev)
+            C = torch.empty(B * m, dtype=torch.float64, device=dev)
+            Xflat = Xf.view(-1)
+            pen.batch.eval(Xflat, F=Fo, G=Gf, C=C)
+            loss = torch.empty(B, dtype=torch.float64, device=dev)
+            cvio = torch.empty(B, dtype=torch.float64, device=dev)
+            W = torch.empty(B * m, dtype=torch.float64, device=dev)
+            gpq = torch.empty(B * 4 * pen.L, dtype=torch.float64, device=dev)
+            _check(lib().prox_penalty(pen.model.handle, _p(C), _p(Xflat), _p(Fo), float(pen.obj_scale),
+                                      float(pen.rho), B, _p(loss), _p(cvio), _p(W), _p(gpq), _stream()))
+            pen.last = {"x": Xf, "f": Fo, "c": C.view(B, m), "cvio": cvio}
+            ctx.save_for_backward(Xflat, W, gpq, Gf)
+            ctx.pen = pen
+            return loss
+
+        @staticmethod
+        def backward(ctx, gloss):
+            Xflat, W, gpq, Gf = ctx.saved_tensors
+            pen = ctx.pen
+            B, n = pen.B, pen.model.n
+            gX1 = pen.batch.jtprod(Xflat, W)
+            W2 = torch.empty_like(W)
+            _check(lib().prox_chain_weights(pen.model.handle, _p(gX1), _p(gpq), B, _p(W2), _stream()))
+            gX2 = pen.batch.jtprod(Xflat, W2)
+            gX = torch.empty(B, n, dtype=torch.float64, device=Xflat.device)
+            wb = gloss.detach().to(torch.float64).contiguous()
+            _check(lib().prox_vjp_sum(pen.model.handle, _p(gX1), _p(gX2), _p(Gf), float(pen.obj_scale), _p(wb), B,
+                                      _p(gX), _stream()))
+            return gX, None
+
+    return F
+
+
+_FUN = {}
+
+
+def _fun(name):
+    if name not in _FUN:
+        _FUN[name] = {"squash": _make_squash_function, "penalty": _make_penalty_function}[name]()
+    return _FUN[name]
+
+
+class Penalty:
+    """The FP64 penalty of B instances of one static model with per-instance
+    loads: loss_b = rho * (squared violations of the non-flow rows and of the
+    arc-variable bounds) + obj_scale * f_b at x_b with p, q := F(vm, va)."""
+
+    def __init__(self, case: dict, B: int, rho: float = 10.0, obj_scale: float = 1e-3, device: int = 0):
+        self.case = case
+        self.model = opf.Model(case, device=device)
+        self.B, self.L, self.N, self.G = int(B), int(case["n_branch"]), int(case["n_bus"]), int(case["n_gen"])
+        self.rho, self.obj_scale = float(rho), float(obj_scale)
+        pd = np.tile(np.asarray(case["pd"], np.float64), self.B)
+        qd = np.tile(np.asarray(case["qd"], np.float64), self.B)
+        self.batch = opf.Batch([self.model], np.zeros(self.B, np.int32), pd, qd)
+        self.last = None
+
+    def set_loads(self, pd, qd):
+        """pd, qd: float64 device tensors [B, N]."""
+        self.batch.set_loads(pd.contiguous().view(-1), qd.contiguous().view(-1))
+
+    def __call__(self, X):
+        """Per-instance loss [B] of X [B, n] (FP64; its p, q are ignored)."""
+        return _fun("penalty").apply(X, self)
+
+    def close(self):
+        self.batch.close()
+        self.model.close()
+
+
+class Squash:
+    def __init__(self, model, va_span: float = 1.0):
+        self.model = model
+        self.va_span = float(va_span)
+
+    def __call__(self, z):
+        return _fun("squash").apply(z, self)
+
+
+class WarmStartProxy:
+    """MLP + squashing + penalty for one network: loads (pd, qd) -> x."""
+
+    def __init__(self, case: dict, B: int, width: int = 1024, depth: int = 3, rho: float = 10.0,
+                 obj_scale: float = 1e-3, va_span: float = 1.0, seed: int = 0, device: int = 0):
+        torch = _torch()
+        N, G = int(case["n_bus"]), int(case["n_gen"])
+        if N % 2 or G % 2:
+            raise OPFError(OPF_E_ARG, "the proxy needs an even number of buses and of generators")
+        self.case, self.N, self.G, self.B = case, N, G, int(B)
+        self.pen = Penalty(case, B, rho=rho, obj_scale=obj_scale, device=device)
+        self.squash = Squash(self.pen.model, va_span)
+        self.mlp = MLP(2 * N, 2 * N + 2 * G, width=width, depth=depth, seed=seed, device=device)
+        self.dev = torch.device("cuda", device)
+        base = np.concatenate([np.asarray(case["pd"], np.float64), np.asarray(case["qd"], np.float64)])
+        self.base = torch.as_tensor(base, device=self.dev)
+        self.spread = 0.3
+        scale = self.spread / math.sqrt(3.0) * np.abs(base)
+        self.inv_scale = torch.as_tensor(np.where(scale > 0, 1.0 / np.maximum(scale, 1e-300), 0.0), device=self.dev)
+        b = self.pen.model.bounds()
+        self.x0 = b["x0"]
+
+    # -- data: seeded +-spread uniform scalings of the base loads (one factor per bus)
+    def sample(self, gen):
+        torch = _torch()
+        u = torch.rand(self.B, self.N, generator=gen, device=self.dev, dtype=torch.float64) * 2.0 - 1.0
+        fac = 1.0 + self.spread * torch.cat([u, u], dim=1)
+        loads = self.base[None, :] * fac
+        feats = ((loads - self.base[None, :]) * self.inv_scale[None, :]).to(torch.float32)
+        return loads, feats
+
+    def loss(self, loads, feats):
+        self.pen.set_loads(loads[:, :self.N], loads[:, self.N:])
+        X = self.squash(self.mlp(feats))
+        return self.pen(X)
+
+    def train_step(self, loads, feats, lr=1e-3):
+        lb = self.loss(loads, feats)
+        loss = lb.mean()
+        loss.backward()
+        self.mlp.adam_step(lr=lr)
+        return loss.detach()
+
+    def predict(self, loads, feats):
+        """(x with p, q := flows, largest violation per sample) under no grad."""
+        torch = _torch()
+        with torch.no_grad():
+            self.loss(loads, feats)
+        return self.pen.last["x"], self.pen.last["cvio"]
+
+    def baseline(self, loads):
+        """The plain starting point x0 scored on the same loads: (x, cvio)."""
+        torch = _torch()
+        with torch.no_grad():
+            self.pen.set_loads(loads[:, :self.N], loads[:, self.N:])
+            X = self.x0[None, :].expand(self.B, -1).contiguous()
+            self.pen(X)
+        return self.pen.last["x"], self.pen.last["cvio"]
+
+    def close(self):
+        self.pen.close()

@@ -1,0 +1,297 @@
+"""GPU tests of the warm-start proxy: every kernel against the CPU oracle
+(oracle/mlp_oracle.py and the C callback oracle), the hand-written VJP
+against finite differences, and the gain of the trained proxy over the plain
+starting point."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as MO
+from oracle import oracle as OR
+from paper_2510_12897_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2510_12897_amd import proxy
+    return proxy
+
+
+def _stored(variant, A, B):
+    """(A storage, lda, B storage, ldb) of the logical A [M, K], B [K, N]."""
+    a_k = variant in (0, 1)
+    b_k = variant in (0, 3)
+    As = A if a_k else A.T
+    Bs = B.T if b_k else B
+    return np.ascontiguousarray(As), As.shape[1], np.ascontiguousarray(Bs), Bs.shape[1]
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("shape", [(132, 200, 72), (256, 128, 1000), (4, 8, 4)])
+def test_gemm_vs_oracle(dev, P, variant, shape):
+    M, N, K = shape
+    rng = np.random.default_rng(10 + variant)
+    A = rng.standard_normal((M, K)).astype(np.float32)
+    B = rng.standard_normal((K, N)).astype(np.float32)
+    bias = rng.standard_normal(N).astype(np.float32)
+    C0 = rng.standard_normal((M, N)).astype(np.float32)
+    As, lda, Bs, ldb = _stored(variant, A, B)
+    tA, tB = torch.as_tensor(As, device=dev), torch.as_tensor(Bs, device=dev)
+    tb = torch.as_tensor(bias, device=dev)
+    ref = MO.gemm(A, B)
+    # FP32 accumulation of K products of BF16 values
+    bound = 2.0 * K * 2.0 ** -24 * (np.abs(MO.bf16_round(A)).astype(np.float64) @ np.abs(MO.bf16_round(B)))
+    C = torch.empty(M, N, dtype=torch.float32, device=dev)
+    act = torch.empty_like(C)
+    P.gemm(variant, tA, lda, tB, ldb, C, N, M, N, K, bias=tb, act=act)
+    torch.cuda.synchronize()
+    got = C.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - (ref + bias)) <= bound + 4e-7 * np.abs(ref + bias) + 1e-6)
+    # fused GELU epilogue on the FP32 result
+    np.testing.assert_allclose(act.cpu().numpy(), MO.gelu(got), rtol=2e-6, atol=2e-6)
+    # accumulate into an existing C
+    Ca = torch.as_tensor(C0, device=dev)
+    P.gemm(variant, tA, lda, tB, ldb, Ca, N, M, N, K, accumulate=True)
+    torch.cuda.synchronize()
+    assert np.all(np.abs(Ca.cpu().numpy() - (ref + C0)) <= bound + 4e-7 * np.abs(ref + C0) + 1e-6)
+
+
+def test_gemm_rejects_bad_shapes(dev, P):
+    from paper_2510_12897_amd.opf import OPFError
+    a = torch.zeros(8, 8, device=dev)
+    with pytest.raises(OPFError):
+        P.gemm(0, a, 8, a, 8, a, 8, 6, 8, 8)  # M not a multiple of 4
+    with pytest.raises(OPFError):
+        P.gemm(7, a, 8, a, 8, a, 8, 8, 8, 8)  # unknown variant
+
+
+def test_elementwise_kernels_vs_oracle(dev, P):
+    from paper_2510_12897_amd.opf import lib
+    rng = np.random.default_rng(3)
+    pre = rng.standard_normal(5000).astype(np.float32) * 3
+    dact = rng.standard_normal(5000).astype(np.float32)
+    tp, td = torch.as_tensor(pre, device=dev), torch.as_tensor(dact, device=dev)
+    out = torch.empty_like(tp)
+    lib().prox_gelu_bwd(P._p(tp), P._p(td), P._p(out), 5000, P._stream())
+    np.testing.assert_allclose(out.cpu().numpy(), dact * MO.gelu_grad(pre.astype(np.float64)), rtol=1e-5, atol=1e-6)
+    # column sums in a fixed order
+    X = rng.standard_normal((700, 36)).astype(np.float32)
+    tX = torch.as_tensor(X, device=dev)
+    work = torch.empty(3 * 36, device=dev)
+    cs = torch.empty(36, device=dev)
+    lib().prox_colsum(P._p(tX), 700, 36, P._p(work), P._p(cs), 0.5, P._stream())
+    np.testing.assert_allclose(cs.cpu().numpy(), 0.5 * X.astype(np.float64).sum(0), rtol=1e-5, atol=1e-5)
+    # Adam, three steps
+    p = rng.standard_normal(1000)
+    m1 = np.zeros(1000)
+    m2 = np.zeros(1000)
+    tp_ = torch.as_tensor(p.astype(np.float32), device=dev)
+    tm1, tm2 = torch.zeros(1000, device=dev), torch.zeros(1000, device=dev)
+    for t in range(1, 4):
+        g = rng.standard_normal(1000)
+        tg = torch.as_tensor(g.astype(np.float32), device=dev)
+        lib().prox_adam(P._p(tp_), P._p(tg), P._p(tm1), P._p(tm2), 1000, 1e-2, 0.9, 0.999, 1e-8, t, P._stream())
+        p, m1, m2 = MO.adam(p, g.astype(np.float32).astype(np.float64), m1, m2, t, lr=1e-2)
+    np.testing.assert_allclose(tp_.cpu().numpy(), p, rtol=1e-5, atol=1e-6)
+
+
+def _case(N=14, L=20, G=6, seed=5):
+    return synth.network(N, L, G, seed)
+
+
+def _box(case):
+    return dict(N=case["n_bus"], G=case["n_gen"], vmin=case["vmin"], vmax=case["vmax"], pmin=case["pmin"],
+                pmax=case["pmax"], qmin=case["qmin"], qmax=case["qmax"],
+                is_ref=np.isin(np.arange(case["n_bus"]), case["ref_bus"]).astype(np.float64))
+
+
+def test_squash_vs_oracle(dev, P):
+    from paper_2510_12897_amd import opf
+    case = _case()
+    N, G = case["n_bus"], case["n_gen"]
+    m = opf.Model(case)
+    sq = P.Squash(m, va_span=0.8)
+    rng = np.random.default_rng(4)
+    z = rng.standard_normal((3, 2 * N + 2 * G)).astype(np.float32)
+    tz = torch.as_tensor(z, device=dev).requires_grad_(True)
+    X = sq(tz)
+    va, vm, pg, qg = MO.squash(z.astype(np.float64), _box(case), 0.8)
+    Xc = X.detach().cpu().numpy()
+    np.testing.assert_allclose(Xc[:, :N], va, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(Xc[:, N:2 * N], vm, rtol=1e-13)
+    np.testing.assert_allclose(Xc[:, 2 * N:2 * N + G], pg, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(Xc[:, 2 * N + G:2 * N + 2 * G], qg, rtol=1e-13, atol=1e-15)
+    assert np.all(Xc[:, 2 * N + 2 * G:] == 0.0)
+    gX = rng.standard_normal(Xc.shape)
+    X.backward(torch.as_tensor(gX, device=dev))
+    ref = MO.squash_grad(z.astype(np.float64), _box(case), 0.8, gX[:, :N], gX[:, N:2 * N], gX[:, 2 * N:2 * N + G],
+                         gX[:, 2 * N + G:2 * N + 2 * G])
+    np.testing.assert_allclose(tz.grad.cpu().numpy(), ref, rtol=1e-6, atol=1e-7)  # dz is FP32
+    m.close()
+
+
+def _oracle_loss(case, pd, qd, xfree, rho, obj_scale):
+    """Oracle loss, violation and completed x of one instance: p, q := F(vm,
+    va) from the flow rows at p = q = 0, then the penalty on c(x)."""
+    N, L, G = case["n_bus"], case["n_branch"], case["n_gen"]
+    c2 = dict(case)
+    c2["pd"], c2["qd"] = pd, qd
+    n = 2 * N + 2 * G + 4 * L
+    x = np.zeros(n)
+    x[:2 * N + 2 * G] = xfree
+    r0 = OR.evaluate(c2, x, want=OR.W_CONS)
+    R = len(case["ref_bus"])
+    flows = -r0["c"][R:R + 4 * L]  # rows p_fr, q_fr, p_to, q_to; c = p_arc - F
+    x[2 * N + 2 * G:2 * N + 2 * G + L] = flows[:L]            # p_fr
+    x[2 * N + 2 * G + L:2 * N + 2 * G + 2 * L] = flows[2 * L:3 * L]  # p_to
+    x[2 * N + 2 * G + 2 * L:2 * N + 2 * G + 3 * L] = flows[L:2 * L]  # q_fr
+    x[2 * N + 2 * G + 3 * L:] = flows[3 * L:]                        # q_to
+    r = OR.evaluate(c2, x, want=OR.W_OBJ | OR.W_CONS)
+    b = OR.bounds(c2)
+    flow_rows = np.zeros(len(r["c"]), bool)
+    flow_rows[R:R + 4 * L] = True
+    pq = x[2 * N + 2 * G:]
+    pen, w, gpq, cvio = MO.penalty(r["c"], b["lcon"], b["ucon"], flow_rows, pq, b["lvar"][2 * N + 2 * G:],
+                                   b["uvar"][2 * N + 2 * G:], rho)
+    return pen + obj_scale * r["f"], cvio, x
+
+
+def _inputs(case, B, seed):
+    N, G = case["n_bus"], case["n_gen"]
+    pd, qd = synth.perturbed_loads(case, B, seed)
+    X = np.zeros((B, 2 * N + 2 * G + 4 * case["n_branch"]))
+    for b in range(B):
+        X[b] = synth.point(case, (seed, b))
+    X[:, 2 * N + 2 * G:] = 0.0
+    return pd, qd, X
+
+
+def test_penalty_vs_oracle(dev, P):
+    case = _case()
+    B = 4
+    pen = P.Penalty(case, B, rho=7.0, obj_scale=2e-3)
+    pd, qd, X = _inputs(case, B, 21)
+    pen.set_loads(torch.as_tensor(pd, device=dev), torch.as_tensor(qd, device=dev))
+    loss = pen(torch.as_tensor(X, device=dev)).cpu().numpy()
+    cvio = pen.last["cvio"].cpu().numpy()
+    xg = pen.last["x"].cpu().numpy()
+    N, G = case["n_bus"], case["n_gen"]
+    for b in range(B):
+        ref, rv, xr = _oracle_loss(case, pd[b], qd[b], X[b, :2 * N + 2 * G], 7.0, 2e-3)
+        np.testing.assert_allclose(xg[b], xr, rtol=1e-12, atol=1e-14)
+        assert loss[b] == pytest.approx(ref, rel=1e-12, abs=1e-14)
+        assert cvio[b] == pytest.approx(rv, rel=1e-12, abs=1e-14)
+    pen.close()
+
+
+def test_penalty_vjp_vs_finite_differences(dev, P):
+    """The hand-written VJP (J^T w, chained through p = F(vm, va)) against
+    central differences of the oracle's loss, and torch's gradcheck."""
+    case = _case()
+    B = 2
+    rho, osc = 3.0, 1e-2
+    pen = P.Penalty(case, B, rho=rho, obj_scale=osc)
+    pd, qd, X = _inputs(case, B, 22)
+    pen.set_loads(torch.as_tensor(pd, device=dev), torch.as_tensor(qd, device=dev))
+    tX = torch.as_tensor(X, device=dev).requires_grad_(True)
+    pen(tX).sum().backward()
+    g = tX.grad.cpu().numpy()
+    N, G = case["n_bus"], case["n_gen"]
+    nf = 2 * N + 2 * G
+    assert np.all(g[:, nf:] == 0.0)
+    h = 1e-6
+    for b in range(B):
+        for e in range(nf):
+            xp, xm = X[b, :nf].copy(), X[b, :nf].copy()
+            xp[e] += h
+            xm[e] -= h
+            fd = (_oracle_loss(case, pd[b], qd[b], xp, rho, osc)[0] - _oracle_loss(case, pd[b], qd[b], xm, rho, osc)[0])
+            fd /= 2 * h
+            assert abs(g[b, e] - fd) <= 1e-6 * max(1.0, abs(fd)), (b, e, g[b, e], fd)
+    # torch's own finite-difference check through the GPU forward
+    tX2 = torch.as_tensor(X, device=dev).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda t: pen(t), (tX2,), eps=1e-6, atol=1e-5, rtol=1e-5)
+    pen.close()
+
+
+def _mlp_oracle(x, layers):
+    """Forward and parameter gradients of sum(z * gz) with every GEMM on
+    BF16-rounded operands (as the matrix-core kernels), FP64 otherwise."""
+    acts, pres = [x.astype(np.float64)], []
+    h = x.astype(np.float64)
+    for k, (W, b) in enumerate(layers):
+        pre = MO.gemm(h.astype(np.float32), W.T) + b
+        pres.append(pre)
+        h = MO.gelu(pre) if k < len(layers) - 1 else pre
+        if k < len(layers) - 1:
+            acts.append(h)
+    return h, acts, pres
+
+
+def test_mlp_forward_backward_vs_oracle(dev, P):
+    mlp = P.MLP(8, 12, width=16, depth=2, seed=3)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((8, 8)).astype(np.float32)
+    layers = [(mlp.weight(k).cpu().numpy(), mlp.bias(k).cpu().numpy().astype(np.float64))
+              for k in range(len(mlp.layout))]
+    z_ref, acts, pres = _mlp_oracle(x, layers)
+    tz = mlp(torch.as_tensor(x, device=dev))
+    np.testing.assert_allclose(tz.detach().cpu().numpy(), z_ref, rtol=2e-2, atol=2e-2 * np.abs(z_ref).max())
+    gz = rng.standard_normal(z_ref.shape)
+    (tz * torch.as_tensor(gz.astype(np.float32), device=dev)).sum().backward()
+    gflat = mlp.flat.grad.cpu().numpy()
+    # oracle backward
+    d = gz
+    for k in range(len(layers) - 1, -1, -1):
+        W, _ = layers[k]
+        wo, bo, fo, fi = mlp.layout[k]
+        dW = MO.gemm(d.T.astype(np.float32), acts[k].astype(np.float32))
+        db = d.sum(0)
+        scale = np.abs(dW).max()
+        np.testing.assert_allclose(gflat[wo:wo + fo * fi].reshape(fo, fi), dW, atol=3e-2 * scale)
+        np.testing.assert_allclose(gflat[bo:bo + fo], db, atol=3e-2 * np.abs(db).max() + 1e-6)
+        if k:
+            dh = MO.gemm(d.astype(np.float32), W)
+            d = dh * MO.gelu_grad(pres[k - 1])
+
+
+def test_trained_proxy_gains_over_flat_start(dev, P):
+    """Self-supervised training on the FP64 penalty; on held-out loads the
+    trained proxy's largest violation must beat the plain starting point x0
+    (the method without the proxy) by a wide margin."""
+    case = synth.network(30, 41, 6, 11)
+    torch.manual_seed(0)
+    px = P.WarmStartProxy(case, B=256, width=128, depth=3, rho=10.0, obj_scale=1e-3, seed=1)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    first = None
+    for step in range(400):
+        loads, feats = px.sample(gen)
+        loss = px.train_step(loads, feats, lr=2e-3)
+        if first is None:
+            first = float(loss)
+    last = float(loss)
+    gen.manual_seed(999)  # held-out loads
+    loads, feats = px.sample(gen)
+    _, cv_proxy = px.predict(loads, feats)
+    _, cv_flat = px.baseline(loads)
+    cp, cf = cv_proxy.cpu().numpy(), cv_flat.cpu().numpy()
+    fallback = float(np.mean(cp > cf))
+    print(f"loss {first:.4g} -> {last:.4g}; held-out max violation: proxy mean {cp.mean():.4g} "
+          f"max {cp.max():.4g}, flat start mean {cf.mean():.4g}; fallback rate {fallback:.3f}")
+    assert last < 0.2 * first
+    assert cp.mean() < 0.25 * cf.mean()
+    assert fallback < 0.05
+    px.close()
