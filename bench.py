@@ -200,7 +200,7 @@ def bench_batch(args, torch, opf, synth, log):
     H = torch.empty(batch.nnzh, dtype=torch.float64, device=dev)
     sched = batch.tune()
     log(f"batch: {n_inst} instances, n={batch.n} m={batch.m} nnzj={batch.nnzj} nnzh={batch.nnzh}, "
-        f"tuned schedule replica_group={sched[0]} wg_per_cu={sched[1]}")
+        f"tuned schedule wg_per_cu={sched} (0 = one workgroup per item)")
 
     def batched():
         batch.eval(X, Y, sig, F, G, C, J, H)
@@ -251,7 +251,7 @@ def bench_batch(args, torch, opf, synth, log):
         batched_sets_per_s=n_inst / per_launch, plain_sets_per_s=n_inst / per_plain,
         speedup=per_plain / per_launch, us_per_launch=per_launch * 1e6, bytes_per_launch=total_bytes,
         achieved_gbs=total_bytes / per_launch / 1e9, frac=total_bytes / per_launch / 1e9 / HBM_PEAK_GBS,
-        schedule=dict(replica_group=sched[0], wg_per_cu=sched[1]), bitwise_equal_to_plain=bool(bitwise))
+        schedule=dict(wg_per_cu=sched), bitwise_equal_to_plain=bool(bitwise))
     batch.close()
     for mdl in models + plain_models:
         mdl.close()
@@ -336,7 +336,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle timing budget (0 = skip)")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / multi-period / N-1 legs")
     ap.add_argument("--batch-reps", type=int, default=20)
-    ap.add_argument("--proxy-steps", type=int, default=150, help="training steps of the proxy leg (0 = skip)")
+    ap.add_argument("--proxy-steps", type=int, default=500, help="training steps of the proxy leg (0 = skip)")
     ap.add_argument("--eager", action="store_true", help="launch the headline sets without a HIP graph")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run a device-to-device copy of this many MiB (HBM counter calibration)")

@@ -218,19 +218,18 @@ int opf_batch_destroy(opf_batch batch);
 int opf_batch_offsets(opf_batch batch, int64_t *xoff, int64_t *coff, int64_t *joff,
                       int64_t *hoff);
 
-/* Time the candidate schedules (replicas per work item, persistent
+/* Time the candidate schedules (flat, and persistent grids of 2 to 32
  * workgroups per compute unit) on this batch and keep the fastest in the
  * handle.  Results of opf_batch_eval do not depend on the schedule.
- * Synchronises `stream`. */
+ * Allocates tuning buffers through the allocator; synchronises `stream`. */
 int opf_batch_tune(opf_batch batch, void *stream);
 
-/* The schedule in use: replicas (periods or contingency copies) handled by
- * one work item, and persistent workgroups per compute unit. */
-int opf_batch_schedule(opf_batch batch, int32_t *replica_group, int32_t *wg_per_cu);
+/* The schedule in use: persistent workgroups per compute unit, or 0 for a
+ * flat launch (one workgroup per work item). */
+int opf_batch_schedule(opf_batch batch, int32_t *wg_per_cu);
 
-/* Force a schedule: replica_group in [1, 65536] and wg_per_cu in [1, 64]
- * (else OPF_E_ARG). */
-int opf_batch_set_schedule(opf_batch batch, int32_t replica_group, int32_t wg_per_cu);
+/* Force a schedule: wg_per_cu in [0, 64] (else OPF_E_ARG). */
+int opf_batch_set_schedule(opf_batch batch, int32_t wg_per_cu);
 
 /* All callbacks of every instance in one launch of a persistent kernel,
  * replayed from a HIP graph.  sigma[n_inst] are the objective weights.  Any

@@ -1,16 +1,16 @@
 // C-ABI of libopf: batched evaluation of many instances in one persistent
 // kernel launch replayed from a HIP graph, with a schedule autotuner.
 //
-// An evaluation is two persistent launches chained in one graph: the branch
-// phase of every instance, then the bus phase.  A schedule is (replica
-// group, workgroups per compute unit): how many consecutive periods or
-// contingency copies one work item handles (its descriptors are loaded once
-// for all of them), and how many persistent workgroups drain each item
-// list (each XCD's workgroups stride through one contiguous range of it).
-// Neither changes any summation order (segment sums follow the host
-// packing, objective partials are per generator chunk and replica and are
-// summed in index order), so every schedule produces bitwise the same
-// results as the plain per-instance launch.
+// An evaluation is two launches chained in one graph: the branch phase of
+// every instance, then the bus phase.  The schedule is the grid: with
+// wg_per_cu > 0 each launch is persistent (wg_per_cu workgroups per compute
+// unit drain the item list, each XCD's workgroups striding through one
+// contiguous range of it); with wg_per_cu = 0 it is flat (one workgroup per
+// item, the block index remapped to the same XCD ranges).  No schedule
+// changes a summation order (segment sums follow the host packing,
+// objective partials are per generator chunk and replica and are summed in
+// index order), so every schedule produces bitwise the same results as the
+// plain per-instance launch.
 #include <array>
 #include <map>
 #include <new>
@@ -22,8 +22,8 @@ using namespace opf_internal;
 
 namespace {
 
-const int32_t kGroups[] = {1, 2, 4, 8, 16};
-const int32_t kWgPerCu[] = {2, 4, 8, 16};
+// autotuner candidates: flat, then persistent grids
+const int32_t kWgPerCu[] = {0, 2, 4, 8, 16, 32};
 
 struct GraphEntry {
     hipGraph_t graph = nullptr;
@@ -32,15 +32,10 @@ struct GraphEntry {
     opf::BatchArgs args[2]{};
 };
 
-// One instantiated graph per (schedule, workgroups per CU, mode); a launch
-// with other buffers rewrites the kernel arguments of the instantiated
-// graph in place instead of building a new one.
-using GraphKey = std::tuple<int32_t, int32_t, int32_t>;
-
-struct Lists {
-    opf::BatchItem* items[2][2] = {};  // device, [mode][phase]
-    int32_t n[2][2] = {};
-};
+// One instantiated graph per (workgroups per CU, mode); a launch with other
+// buffers rewrites the kernel arguments of the instantiated graph in place
+// instead of building a new one.
+using GraphKey = std::tuple<int32_t, int32_t>;
 
 }  // namespace
 
@@ -55,8 +50,8 @@ struct opf_batch_s {
     double* pd_all = nullptr;        // device per-instance loads (NULL if none)
     double* qd_all = nullptr;
     int64_t n_loads = 0;
-    std::vector<Lists> lists;        // one per candidate replica group
-    int sched = 0;                   // index into kGroups
+    opf::BatchItem* items[2][2] = {};  // device item lists, [mode (0 set, 1 J^T v)][phase]
+    int32_t n_items[2][2] = {};
     int32_t wg_per_cu = 8;
     int32_t n_cu = 256;
     std::map<GraphKey, GraphEntry> graphs;
@@ -74,60 +69,57 @@ void drop_graphs(opf_batch_s* b) {
     b->graphs.clear();
 }
 
-// Work items for one replica group size and phase.  Phase 1: the branch
-// chunks, then (callback set) the generator chunks of every instance.
-// Phase 2: big buses first (the longest), then the waves of bus segments
-// of every instance, then one objective item per instance (callback set)
-// or the generator items (J^T v; on a model whose copies share pg, one
-// generator per item).
-void make_items(const std::vector<opf::DevModel>& dms, int32_t rg, int mode, int phase,
-                std::vector<opf::BatchItem>& out) {
+// Work items of one phase, one replica each.  Phase 1: the branch chunks,
+// then (callback set) the generator chunks of every instance.  Phase 2: big
+// buses first (the longest), then the waves of bus segments of every
+// instance, then one objective item per instance (callback set) or the
+// generator items (J^T v; on a model whose copies share pg, one generator
+// per item).  Within a kind, replicas are outermost.
+void make_items(const std::vector<opf::DevModel>& dms, int mode, int phase, std::vector<opf::BatchItem>& out) {
     out.clear();
     const int32_t n = (int32_t)dms.size();
-    auto groups = [&](const opf::DevModel& d, int32_t kind, int32_t count, int32_t j) {
-        const int32_t g = std::min(std::max(rg, 1), d.nrep);
-        for (int32_t r0 = 0; r0 < d.nrep; r0 += g)
-            for (int32_t i = 0; i < count; i++) out.push_back({j, kind, i, r0, std::min(r0 + g, d.nrep), 0});
+    auto each = [&](const opf::DevModel& d, int32_t kind, int32_t count, int32_t j) {
+        for (int32_t r = 0; r < d.nrep; r++)
+            for (int32_t i = 0; i < count; i++) out.push_back({j, kind, i, r});
     };
     if (phase == 0) {
-        for (int32_t j = 0; j < n; j++) groups(dms[j], opf::T_BRANCH, dms[j].nbchunks, j);
+        for (int32_t j = 0; j < n; j++) each(dms[j], opf::T_BRANCH, dms[j].nbchunks, j);
         if (mode == 0)
-            for (int32_t j = 0; j < n; j++) groups(dms[j], opf::T_GEN, dms[j].ngchunks, j);
+            for (int32_t j = 0; j < n; j++) each(dms[j], opf::T_GEN, dms[j].ngchunks, j);
         return;
     }
-    for (int32_t j = 0; j < n; j++) groups(dms[j], opf::T_BIG, dms[j].nbig, j);
-    for (int32_t j = 0; j < n; j++) groups(dms[j], opf::T_WAVE, dms[j].nwaves, j);
+    for (int32_t j = 0; j < n; j++) each(dms[j], opf::T_BIG, dms[j].nbig, j);
+    for (int32_t j = 0; j < n; j++) each(dms[j], opf::T_WAVE, dms[j].nwaves, j);
     for (int32_t j = 0; j < n; j++) {
         const opf::DevModel& d = dms[j];
         if (mode == 0) {
-            out.push_back({j, opf::T_OBJ, 0, 0, 0, 0});
+            out.push_back({j, opf::T_OBJ, 0, 0});
         } else if (d.npg == 1 && d.nrep > 1) {
-            for (int32_t k = 0; k < d.G; k++) out.push_back({j, opf::T_GEN, k, 0, d.nrep, 0});
+            for (int32_t k = 0; k < d.G; k++) out.push_back({j, opf::T_GEN, k, 0});
         } else {
-            groups(d, opf::T_GEN, d.ngchunks, j);
+            each(d, opf::T_GEN, d.ngchunks, j);
         }
     }
 }
 
 int launch(opf_batch_s* b, const opf::BatchArgs& a0, hipStream_t stream) {
-    const Lists& L = b->lists[b->sched];
     opf::BatchArgs a[2];
     int32_t grid[2];
+    const int lm = a0.mode == 2 ? 0 : a0.mode;  // the flows mode runs the branch items only
     for (int ph = 0; ph < 2; ph++) {
         a[ph] = a0;
         a[ph].inst = b->inst;
-        // the flows mode runs the branch items only
-        const int lm = a0.mode == 2 ? 0 : a0.mode;
-        a[ph].items = L.items[lm][ph];
-        a[ph].n_items = (a0.mode == 2 && ph == 1) ? 0 : L.n[lm][ph];
-        // at least one workgroup per XCD, so every XCD's item range is drained
-        grid[ph] = std::max(opf::kXcd, std::min(a[ph].n_items, b->n_cu * b->wg_per_cu));
+        a[ph].items = b->items[lm][ph];
+        a[ph].n_items = (a0.mode == 2 && ph == 1) ? 0 : b->n_items[lm][ph];
+        // persistent: at least one workgroup per XCD, so every XCD's range is drained
+        grid[ph] = b->wg_per_cu == 0 ? std::max(1, a[ph].n_items)
+                                      : std::max(opf::kXcd, std::min(a[ph].n_items, b->n_cu * b->wg_per_cu));
     }
-    GraphKey key{b->sched, b->wg_per_cu, a0.mode};
+    GraphKey key{b->wg_per_cu, a0.mode};
     auto kernel_params = [&](int ph, opf::BatchArgs* args, void** slot) {
         hipKernelNodeParams p{};
         slot[0] = args;
-        p.func = opf::batch_kernel_fn(ph);
+        p.func = opf::batch_kernel_fn(ph, a0.mode, b->wg_per_cu == 0);
         p.gridDim = dim3(grid[ph]);
         p.blockDim = dim3(opf::kBlock);
         p.sharedMemBytes = 0;
@@ -213,7 +205,7 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
         }
 
         // ---- pack: per-instance loads and scratch (zeroed), instance
-        // descriptors, item lists per replica group
+        // descriptors, item lists
         Packer pk;
         std::vector<int64_t> loff(n_inst + 1, 0);
         std::vector<size_t> o_scr(n_inst, 0);
@@ -232,19 +224,12 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
         const size_t o_inst = pk.reserve(sizeof(opf::BatchInst) * n_inst);
         std::vector<opf::DevModel> dms(n_inst);
         for (int32_t j = 0; j < n_inst; j++) dms[j] = models[inst_model[j]]->dm;
-        std::vector<std::array<size_t, 4>> lst_off;
-        std::vector<std::array<int32_t, 4>> lst_n;
+        size_t lst_off[2][2];
         std::vector<opf::BatchItem> items;
-        for (int32_t g : kGroups) {
-            std::array<size_t, 4> offs{};
-            std::array<int32_t, 4> ns{};
-            for (int q = 0; q < 4; q++) {  // (mode, phase)
-                make_items(dms, g, q / 2, q % 2, items);
-                offs[q] = pk.add(items);
-                ns[q] = (int32_t)items.size();
-            }
-            lst_off.push_back(offs);
-            lst_n.push_back(ns);
+        for (int q = 0; q < 4; q++) {  // (mode, phase)
+            make_items(dms, q / 2, q % 2, items);
+            lst_off[q / 2][q % 2] = pk.add(items);
+            b->n_items[q / 2][q % 2] = (int32_t)items.size();
         }
 
         DeviceGuard dg(dev);
@@ -277,14 +262,8 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
             bi.hoff = b->hoff[j];
             std::memcpy(&hi[j], &bi, sizeof bi);
         }
-        for (size_t s = 0; s < lst_off.size(); s++) {
-            Lists L;
-            for (int q = 0; q < 4; q++) {
-                L.items[q / 2][q % 2] = reinterpret_cast<opf::BatchItem*>(base + lst_off[s][q]);
-                L.n[q / 2][q % 2] = lst_n[s][q];
-            }
-            b->lists.push_back(L);
-        }
+        for (int q = 0; q < 4; q++)
+            b->items[q / 2][q % 2] = reinterpret_cast<opf::BatchItem*>(base + lst_off[q / 2][q % 2]);
         hipError_t e = hipMemcpy(b->arena, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             dev_free(b->alloc, b->arena);
@@ -297,7 +276,6 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
             b->n_loads = loff[n_inst];
         }
         b->inst = reinterpret_cast<opf::BatchInst*>(base + o_inst);
-        b->sched = 0;
     } catch (const std::bad_alloc&) {
         delete b;
         return set_err(OPF_E_NOMEM, "host allocation failed");
@@ -330,21 +308,15 @@ int opf_batch_offsets(opf_batch b, int64_t* xoff, int64_t* coff, int64_t* joff, 
     return OPF_OK;
 }
 
-int opf_batch_schedule(opf_batch b, int32_t* replica_group, int32_t* wg_per_cu) {
+int opf_batch_schedule(opf_batch b, int32_t* wg_per_cu) {
     if (!valid(b)) return set_err(OPF_E_STATE, "invalid or destroyed batch handle");
-    if (replica_group) *replica_group = kGroups[b->sched];
     if (wg_per_cu) *wg_per_cu = b->wg_per_cu;
     return OPF_OK;
 }
 
-int opf_batch_set_schedule(opf_batch b, int32_t replica_group, int32_t wg_per_cu) {
+int opf_batch_set_schedule(opf_batch b, int32_t wg_per_cu) {
     if (!valid(b)) return set_err(OPF_E_STATE, "invalid or destroyed batch handle");
-    if (wg_per_cu < 1 || wg_per_cu > 64) return set_err(OPF_E_ARG, "wg_per_cu must be in [1, 64]");
-    if (replica_group < 1 || replica_group > 65536) return set_err(OPF_E_ARG, "replica_group must be in [1, 65536]");
-    int found = 0;
-    for (int s = 0; s < (int)(sizeof kGroups / sizeof kGroups[0]); s++)
-        if (kGroups[s] <= replica_group) found = s;
-    b->sched = found;
+    if (wg_per_cu < 0 || wg_per_cu > 64) return set_err(OPF_E_ARG, "wg_per_cu must be in [0, 64]");
     b->wg_per_cu = wg_per_cu;
     return OPF_OK;
 }
@@ -412,10 +384,8 @@ int opf_batch_tune(opf_batch b, void* stream) {
     double *X = p, *G = X + n, *Y = G + n, *C = Y + m, *J = C + m, *H = J + nj, *sg = H + nh, *F = sg + b->n_inst;
     int rc = OPF_OK;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const int keep_sched = b->sched;
     const int32_t keep_wg = b->wg_per_cu;
     float best = 1e30f;
-    int best_s = keep_sched;
     int32_t best_wg = keep_wg;
     do {
         hipError_t e = hipMemsetAsync(buf, 0, bytes, s);
@@ -425,35 +395,27 @@ int opf_batch_tune(opf_batch b, void* stream) {
             rc = hip_err(e, "tuning setup");
             break;
         }
-        for (size_t sc = 0; sc < b->lists.size() && rc == OPF_OK; sc++) {
-            // replica groups beyond the largest replica count are duplicates
-            if (sc > 0 && b->lists[sc].n[0][1] == b->lists[sc - 1].n[0][1] &&
-                b->lists[sc].n[0][0] == b->lists[sc - 1].n[0][0])
-                continue;
-            for (int32_t wg : kWgPerCu) {
-                b->sched = (int)sc;
-                b->wg_per_cu = wg;
-                opf::BatchArgs a{};
-                a.X = X; a.Y = Y; a.sigma = sg; a.F = F; a.G = G; a.C = C; a.J = J; a.H = H;
-                for (int w = 0; w < 2 && rc == OPF_OK; w++) rc = launch(b, a, s);
-                if (rc) break;
-                (void)hipEventRecord(e0, s);
-                const int reps = 5;
-                for (int w = 0; w < reps && rc == OPF_OK; w++) rc = launch(b, a, s);
-                if (rc) break;
-                (void)hipEventRecord(e1, s);
-                e = hipEventSynchronize(e1);
-                if (e != hipSuccess) {
-                    rc = hip_err(e, "tuning run");
-                    break;
-                }
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (ms < best) {
-                    best = ms;
-                    best_s = (int)sc;
-                    best_wg = wg;
-                }
+        for (int32_t wg : kWgPerCu) {
+            b->wg_per_cu = wg;
+            opf::BatchArgs a{};
+            a.X = X; a.Y = Y; a.sigma = sg; a.F = F; a.G = G; a.C = C; a.J = J; a.H = H;
+            for (int w = 0; w < 2 && rc == OPF_OK; w++) rc = launch(b, a, s);
+            if (rc) break;
+            (void)hipEventRecord(e0, s);
+            const int reps = 5;
+            for (int w = 0; w < reps && rc == OPF_OK; w++) rc = launch(b, a, s);
+            if (rc) break;
+            (void)hipEventRecord(e1, s);
+            e = hipEventSynchronize(e1);
+            if (e != hipSuccess) {
+                rc = hip_err(e, "tuning run");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                best_wg = wg;
             }
         }
     } while (false);
@@ -462,11 +424,9 @@ int opf_batch_tune(opf_batch b, void* stream) {
     (void)hipStreamSynchronize(s);
     dev_free(b->alloc, buf);
     if (rc) {
-        b->sched = keep_sched;
         b->wg_per_cu = keep_wg;
         return rc;
     }
-    b->sched = best_s;
     b->wg_per_cu = best_wg;
     return OPF_OK;
 }

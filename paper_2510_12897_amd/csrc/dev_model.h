@@ -93,16 +93,13 @@ struct EvalOut {
     double* H;
 };
 
-// Work counts of one plain launch of each phase.  Phase-1 items are branch
-// chunks then generator chunks; phase-2 items are big buses, waves, then
-// the objective item (callback set) or the generator items (J^T v).  Every
-// item covers a group of consecutive replicas.
+// Work counts of one plain launch of each phase (every item covers one
+// replica).  Phase-1 items are branch chunks then generator chunks;
+// phase-2 items are big buses, waves, then the objective item (callback
+// set) or the generator items (J^T v).
 struct SetGrid {
-    int32_t n_branch, rg1;            // phase 1 branch items, replicas per item
-    int32_t n_gen1, rgg, gen_nrep;    // phase 1 generator items, replicas per item, replicas covered
-    int32_t n_big, n_wave;            // phase 2 bus items
-    int32_t rg2, nrg2;                // phase 2 replicas per item, replica groups
-    int32_t n_obj;                    // phase 2 objective item (0 or 1)
+    int32_t n_branch, n_gen1;         // phase 1 items
+    int32_t n_big, n_wave, n_obj;     // phase 2 bus items and the objective item (0 or 1)
     int32_t n_gen2;                   // phase 2 generator items (J^T v)
     int32_t gen_per_item;             // J^T v: 0 = chunks of kBlock generators; 1 = one generator a wave
     int32_t phase1() const { return n_branch + n_gen1; }

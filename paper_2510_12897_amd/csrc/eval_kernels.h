@@ -18,10 +18,10 @@ hipError_t launch_eval_set(const DevModel& m, const EvalOut& o, hipStream_t stre
 // out = J(x)^T v on `stream`.
 hipError_t launch_jtprod(const DevModel& m, const double* x, const double* v, double* out, hipStream_t stream);
 
-// ---- batched evaluation: one persistent kernel per phase over a list of
-// work items.
+// ---- batched evaluation: one kernel per phase over a list of work items
+// (persistent, or one workgroup per item).
 struct BatchItem {
-    int32_t inst, kind, idx, r0, r1, pad;  // replicas [r0, r1)
+    int32_t inst, kind, idx, r;  // instance, task kind, entity chunk / wave / bus, replica
 };
 
 struct BatchInst {
@@ -45,8 +45,9 @@ struct BatchArgs {
 // then the half-edge records (kRec doubles per replica, branch, side).
 size_t scratch_bytes(const DevModel& m);
 
-// The persistent kernel of phase 0 (branch items) or 1 (bus items), for
-// graph kernel nodes (argument: BatchArgs).
-void* batch_kernel_fn(int phase);
+// The batch kernel of phase 0 (branch items) or 1 (bus items) for mode 0
+// (callback set), 1 (J^T v) or 2 (flows, phase 0 only), persistent or flat
+// (one workgroup per item), for graph kernel nodes (argument: BatchArgs).
+void* batch_kernel_fn(int phase, int mode, bool flat);
 
 }  // namespace opf

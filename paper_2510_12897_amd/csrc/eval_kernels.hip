@@ -49,16 +49,32 @@ namespace opf {
 namespace {
 
 // slot kinds (host_model.h)
-constexpr int32_t SK_HEAD = 1, SK_EDGE = 2, SK_GEN = 3;
+constexpr int32_t SK_IDLE = 0, SK_HEAD = 1, SK_EDGE = 2, SK_GEN = 3;
 
 struct Coef {
     double Gff, Bff, Gft, Bft, Gtt, Btt, Gtf, Btf;
 };
 
-__device__ __forceinline__ Coef load_coef(const DevModel& m, int32_t l) {
-    const size_t L = (size_t)m.L;
+// Element idx of an array whose base is the same for the whole wave (a
+// kernel argument plus uniform offsets).  The byte offset is formed in 32
+// bits, so the access compiles to the scalar-base + 32-bit vector-offset
+// form and a lane keeps one offset register per index instead of a 64-bit
+// address per array.  Every per-instance array is below 4 GiB (checked when
+// the model is created).
+template <class T>
+__device__ __forceinline__ T ld(const T* base, uint32_t idx) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ void st(T* base, uint32_t idx, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T))) = v;
+}
+
+__device__ __forceinline__ Coef load_coef(const DevModel& m, uint32_t l) {
+    const int64_t L = m.L;
     const double* c = m.coef;
-    return Coef{c[l], c[L + l], c[2 * L + l], c[3 * L + l], c[4 * L + l], c[5 * L + l], c[6 * L + l], c[7 * L + l]};
+    return Coef{ld(c, l),         ld(c + L, l),     ld(c + 2 * L, l), ld(c + 3 * L, l),
+                ld(c + 4 * L, l), ld(c + 5 * L, l), ld(c + 6 * L, l), ld(c + 7 * L, l)};
 }
 
 // A branch out of service in a contingency copy has zero admittance terms.
@@ -66,14 +82,14 @@ __device__ __forceinline__ Coef in_service(const Coef& k, const DevModel& m, int
     return m.outage[r] == l ? Coef{0, 0, 0, 0, 0, 0, 0, 0} : k;
 }
 
-// Half-edge record of (replica r, branch l, side s): kRec doubles, the two
+// Half-edge records of replica r: kRec doubles per (branch, side), the two
 // sides of a branch adjacent, branches in order.
-__device__ __forceinline__ double* rec_at(const DevModel& m, int32_t r, int32_t l, int32_t side) {
-    return m.rec + (((int64_t)r * m.L + l) * 2 + side) * kRec;
+__device__ __forceinline__ double* rec_rep(const DevModel& m, int32_t r) {
+    return m.rec + (int64_t)r * m.L * 2 * kRec;
 }
-// The J^T v record: two doubles (va term, vm term) per half-edge.
-__device__ __forceinline__ double* jt_rec_at(const DevModel& m, int32_t r, int32_t l, int32_t side) {
-    return m.rec + (((int64_t)r * m.L + l) * 2 + side) * 2;
+// The J^T v records of replica r: two doubles (va term, vm term) per half-edge.
+__device__ __forceinline__ double* jt_rec_rep(const DevModel& m, int32_t r) {
+    return m.rec + (int64_t)r * m.L * 2 * 2;
 }
 
 // Block index -> work item, so that each XCD (blocks b with b % kXcd equal)
@@ -148,161 +164,163 @@ __device__ __forceinline__ Jterms jt_terms(const Coef& k, double v1, double v2, 
     return j;
 }
 
-__device__ __forceinline__ void put_flow_row(const EvalOut& o, int64_t row, int64_t jpos, double arcval,
+// One flow row: c = p_arc - F and its five Jacobian entries (columns in
+// ascending order: the lower bus's va, the higher bus's va, then the vm
+// pair, then the arc variable).
+__device__ __forceinline__ void put_flow_row(const EvalOut& o, int64_t cblk, int64_t jblk, uint32_t rl, double arcval,
                                              const Flow1& fl, bool f_lo) {
-    if (o.c) o.c[row] = arcval - fl.F;
+    if (o.c) st(o.c + cblk, rl, arcval - fl.F);
     if (o.J) {
-        double* J = o.J + jpos;
-        if (f_lo) {  // columns va_f, va_t, vm_f, vm_t, arc
-            J[0] = -fl.Ft;
-            J[1] = fl.Ft;
-            J[2] = -fl.Fu;
-            J[3] = -fl.Fw;
-        } else {     // columns va_t, va_f, vm_t, vm_f, arc
-            J[0] = fl.Ft;
-            J[1] = -fl.Ft;
-            J[2] = -fl.Fw;
-            J[3] = -fl.Fu;
-        }
-        J[4] = 1.0;
+        double* J = o.J + jblk;
+        const uint32_t j = 5 * rl;
+        st(J, j, f_lo ? -fl.Ft : fl.Ft);
+        st(J, j + 1, f_lo ? fl.Ft : -fl.Ft);
+        st(J, j + 2, f_lo ? -fl.Fu : -fl.Fw);
+        st(J, j + 3, f_lo ? -fl.Fw : -fl.Fu);
+        st(J, j + 4, 1.0);
     }
 }
 
 // ================================================================== phase 1
-__device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r0, int32_t r1) {
-    const int32_t l = chunk * kBlock + (int32_t)threadIdx.x;
-    if (l >= m.L) return;
+__device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r) {
+    const uint32_t l = (uint32_t)(chunk * kBlock) + threadIdx.x;
+    if (l >= (uint32_t)m.L) return;
     const int64_t L = m.L, N = m.N;
     const bool wantC = o.c != nullptr, wantJ = o.J != nullptr, wantH = o.H != nullptr;
     const bool wantFlow = wantC || wantJ || wantH;
-    const int32_t fb = m.f_bus[l], tb = m.t_bus[l];
+    const uint32_t fb = (uint32_t)ld(m.f_bus, l), tb = (uint32_t)ld(m.t_bus, l);
     const bool f_lo = fb < tb;
     Coef k0{};
     double rate2 = 0.0;
     if (wantFlow) {
         k0 = load_coef(m, l);
-        if (wantC) rate2 = m.rate2[l];
+        if (wantC) rate2 = ld(m.rate2, l);
     }
-    const double* x = o.x;
-    for (int32_t r = r0; r < r1; r++) {
-        const int64_t rl = l + L * r;        // row inside a branch block
-        const int64_t afr = l + 2 * L * r;   // from arc inside the p / q blocks
-        const int64_t ato = afr + L;         // to arc
+    {  // replica r
+        const int64_t ob = L * r;       // branch blocks of replica r
+        const int64_t oa = 2 * L * r;   // arc blocks of replica r (from arcs, then to arcs)
+        const int64_t on = N * r;       // bus blocks of replica r
         if (wantFlow) {
-            const double pf = x[m.x_p + afr], pt = x[m.x_p + ato];
-            const double qf = x[m.x_q + afr], qt = x[m.x_q + ato];
-            const Coef k = in_service(k0, m, l, r);
-            const double u = x[m.x_vm + fb + N * r], w = x[m.x_vm + tb + N * r];
-            const double vaf = x[m.x_va + fb + N * r], vat = x[m.x_va + tb + N * r];
+            const double* xp = o.x + m.x_p + oa;
+            const double* xq = o.x + m.x_q + oa;
+            const double pf = ld(xp, l), pt = ld(xp + L, l);
+            const double qf = ld(xq, l), qt = ld(xq + L, l);
+            const Coef k = in_service(k0, m, (int32_t)l, r);
+            const double u = ld(o.x + m.x_vm + on, fb), w = ld(o.x + m.x_vm + on, tb);
+            const double vaf = ld(o.x + m.x_va + on, fb), vat = ld(o.x + m.x_va + on, tb);
             double S, C;
             sincos(vaf - vat, &S, &C);
             if (wantC || wantJ) {
-                put_flow_row(o, m.c_pfr + rl, m.j_pfr + 5 * rl, pf, flow1(k.Gff, 0.0, k.Gft, k.Bft, u, w, C, S), f_lo);
-                put_flow_row(o, m.c_qfr + rl, m.j_qfr + 5 * rl, qf, flow1(-k.Bff, 0.0, -k.Bft, k.Gft, u, w, C, S),
+                put_flow_row(o, m.c_pfr + ob, m.j_pfr + 5 * ob, l, pf, flow1(k.Gff, 0.0, k.Gft, k.Bft, u, w, C, S),
                              f_lo);
-                put_flow_row(o, m.c_pto + rl, m.j_pto + 5 * rl, pt, flow1(0.0, k.Gtt, k.Gtf, -k.Btf, u, w, C, S), f_lo);
-                put_flow_row(o, m.c_qto + rl, m.j_qto + 5 * rl, qt, flow1(0.0, -k.Btt, -k.Btf, -k.Gtf, u, w, C, S),
+                put_flow_row(o, m.c_qfr + ob, m.j_qfr + 5 * ob, l, qf,
+                             flow1(-k.Bff, 0.0, -k.Bft, k.Gft, u, w, C, S), f_lo);
+                put_flow_row(o, m.c_pto + ob, m.j_pto + 5 * ob, l, pt, flow1(0.0, k.Gtt, k.Gtf, -k.Btf, u, w, C, S),
                              f_lo);
+                put_flow_row(o, m.c_qto + ob, m.j_qto + 5 * ob, l, qt,
+                             flow1(0.0, -k.Btt, -k.Btf, -k.Gtf, u, w, C, S), f_lo);
             }
             if (wantC) {
-                o.c[m.c_ang + rl] = vaf - vat;
-                o.c[m.c_thf + rl] = pf * pf + qf * qf - rate2;
-                o.c[m.c_tht + rl] = pt * pt + qt * qt - rate2;
+                st(o.c + m.c_ang + ob, l, vaf - vat);
+                st(o.c + m.c_thf + ob, l, pf * pf + qf * qf - rate2);
+                st(o.c + m.c_tht + ob, l, pt * pt + qt * qt - rate2);
             }
             if (wantJ) {
-                o.J[m.j_ang + 2 * rl] = f_lo ? 1.0 : -1.0;
-                o.J[m.j_ang + 2 * rl + 1] = f_lo ? -1.0 : 1.0;
-                o.J[m.j_thf + 2 * rl] = 2.0 * pf;
-                o.J[m.j_thf + 2 * rl + 1] = 2.0 * qf;
-                o.J[m.j_tht + 2 * rl] = 2.0 * pt;
-                o.J[m.j_tht + 2 * rl + 1] = 2.0 * qt;
+                // block offsets need not be even, so these pairs are stored
+                // as two 8-byte values
+                st(o.J + m.j_ang + 2 * ob, 2 * l, f_lo ? 1.0 : -1.0);
+                st(o.J + m.j_ang + 2 * ob, 2 * l + 1, f_lo ? -1.0 : 1.0);
+                st(o.J + m.j_thf + 2 * ob, 2 * l, 2.0 * pf);
+                st(o.J + m.j_thf + 2 * ob, 2 * l + 1, 2.0 * qf);
+                st(o.J + m.j_tht + 2 * ob, 2 * l, 2.0 * pt);
+                st(o.J + m.j_tht + 2 * ob, 2 * l + 1, 2.0 * qt);
             }
             // the two half-edge records: [TT, MA, MM, UW, P, Q] at the from
             // side, then at the to side (12 doubles, 16-byte aligned)
-            double2* rec = reinterpret_cast<double2*>(rec_at(m, r, l, 0));
+            double2* rec = reinterpret_cast<double2*>(rec_rep(m, r));
+            const uint32_t q = 6 * l;
             if (wantH) {
-                const double yf = o.y[m.c_thf + rl], yt = o.y[m.c_tht + rl];
-                o.H[m.h_p + afr] = 2.0 * yf;
-                o.H[m.h_p + ato] = 2.0 * yt;
-                o.H[m.h_q + afr] = 2.0 * yf;
-                o.H[m.h_q + ato] = 2.0 * yt;
-                const Hterms h = hess_terms(k, o.y[m.c_pfr + rl], o.y[m.c_qfr + rl], o.y[m.c_pto + rl],
-                                            o.y[m.c_qto + rl], u, w, C, S);
+                const double yf = ld(o.y + m.c_thf + ob, l), yt = ld(o.y + m.c_tht + ob, l);
+                st(o.H + m.h_p + oa, l, 2.0 * yf);
+                st(o.H + m.h_p + oa + L, l, 2.0 * yt);
+                st(o.H + m.h_q + oa, l, 2.0 * yf);
+                st(o.H + m.h_q + oa + L, l, 2.0 * yt);
+                const Hterms h = hess_terms(k, ld(o.y + m.c_pfr + ob, l), ld(o.y + m.c_qfr + ob, l),
+                                            ld(o.y + m.c_pto + ob, l), ld(o.y + m.c_qto + ob, l), u, w, C, S);
                 // d/dva_f = d/dth, d/dva_t = -d/dth
-                rec[0] = make_double2(h.Stt, h.Sut);
-                rec[1] = make_double2(h.Suu, h.Suw);
-                rec[3] = make_double2(h.Stt, -h.Swt);
-                rec[4] = make_double2(h.Sww, h.Suw);
+                st(rec, q, make_double2(h.Stt, h.Sut));
+                st(rec, q + 1, make_double2(h.Suu, h.Suw));
+                st(rec, q + 3, make_double2(h.Stt, -h.Swt));
+                st(rec, q + 4, make_double2(h.Sww, h.Suw));
             }
             if (wantC) {
-                rec[2] = make_double2(pf, qf);
-                rec[5] = make_double2(pt, qt);
+                st(rec, q + 2, make_double2(pf, qf));
+                st(rec, q + 5, make_double2(pt, qt));
             }
         }
         if (o.g) {
-            o.g[m.x_p + afr] = 0.0;
-            o.g[m.x_p + ato] = 0.0;
-            o.g[m.x_q + afr] = 0.0;
-            o.g[m.x_q + ato] = 0.0;
+            st(o.g + m.x_p + oa, l, 0.0);
+            st(o.g + m.x_p + oa + L, l, 0.0);
+            st(o.g + m.x_q + oa, l, 0.0);
+            st(o.g + m.x_q + oa + L, l, 0.0);
         }
     }
 }
 
 // J^T v, phase 1: the arc entries p / q (owned here) and each half-edge's
 // va / vm terms for the bus side.
-__device__ void jt_branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r0, int32_t r1) {
-    const int32_t l = chunk * kBlock + (int32_t)threadIdx.x;
-    if (l >= m.L) return;
+__device__ void jt_branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r) {
+    const uint32_t l = (uint32_t)(chunk * kBlock) + threadIdx.x;
+    if (l >= (uint32_t)m.L) return;
     const int64_t L = m.L, N = m.N;
-    const int32_t fb = m.f_bus[l], tb = m.t_bus[l];
+    const uint32_t fb = (uint32_t)ld(m.f_bus, l), tb = (uint32_t)ld(m.t_bus, l);
     const Coef k0 = load_coef(m, l);
     const double* x = o.x;
     const double* v = o.y;
-    for (int32_t r = r0; r < r1; r++) {
-        const int64_t rl = l + L * r;
-        const int64_t afr = l + 2 * L * r, ato = afr + L;
-        const int64_t bf = fb + N * r, bt = tb + N * r;
-        const double vtf = v[m.c_thf + rl], vtt = v[m.c_tht + rl];
-        const double v1 = v[m.c_pfr + rl], v2 = v[m.c_qfr + rl], v3 = v[m.c_pto + rl], v4 = v[m.c_qto + rl];
+    {  // replica r
+        const int64_t ob = L * r, oa = 2 * L * r, on = N * r;
+        const double vtf = ld(v + m.c_thf + ob, l), vtt = ld(v + m.c_tht + ob, l);
+        const double v1 = ld(v + m.c_pfr + ob, l), v2 = ld(v + m.c_qfr + ob, l);
+        const double v3 = ld(v + m.c_pto + ob, l), v4 = ld(v + m.c_qto + ob, l);
         // p_a sits in its flow row (+1), its bus's balance row (+1) and its
         // thermal row (2 p_a); q_a likewise
-        o.g[m.x_p + afr] = v1 + v[m.c_balp + bf] + 2.0 * x[m.x_p + afr] * vtf;
-        o.g[m.x_p + ato] = v3 + v[m.c_balp + bt] + 2.0 * x[m.x_p + ato] * vtt;
-        o.g[m.x_q + afr] = v2 + v[m.c_balq + bf] + 2.0 * x[m.x_q + afr] * vtf;
-        o.g[m.x_q + ato] = v4 + v[m.c_balq + bt] + 2.0 * x[m.x_q + ato] * vtt;
-        const double u = x[m.x_vm + bf], w = x[m.x_vm + bt];
-        const double th = x[m.x_va + bf] - x[m.x_va + bt];
-        const Coef k = in_service(k0, m, l, r);
+        st(o.g + m.x_p + oa, l, v1 + ld(v + m.c_balp + on, fb) + 2.0 * ld(x + m.x_p + oa, l) * vtf);
+        st(o.g + m.x_p + oa + L, l, v3 + ld(v + m.c_balp + on, tb) + 2.0 * ld(x + m.x_p + oa + L, l) * vtt);
+        st(o.g + m.x_q + oa, l, v2 + ld(v + m.c_balq + on, fb) + 2.0 * ld(x + m.x_q + oa, l) * vtf);
+        st(o.g + m.x_q + oa + L, l, v4 + ld(v + m.c_balq + on, tb) + 2.0 * ld(x + m.x_q + oa + L, l) * vtt);
+        const double u = ld(x + m.x_vm + on, fb), w = ld(x + m.x_vm + on, tb);
+        const double th = ld(x + m.x_va + on, fb) - ld(x + m.x_va + on, tb);
+        const Coef k = in_service(k0, m, (int32_t)l, r);
         double S, C;
         sincos(th, &S, &C);
         const Jterms j = jt_terms(k, v1, v2, v3, v4, u, w, C, S);
-        const double va = v[m.c_ang + rl];
+        const double va = ld(v + m.c_ang + ob, l);
         // d th / d va_f = 1, d th / d va_t = -1; the angle row is va_f - va_t
-        double2* rec = reinterpret_cast<double2*>(jt_rec_at(m, r, l, 0));
-        rec[0] = make_double2(j.Dt + va, j.Du);
-        rec[1] = make_double2(-j.Dt - va, j.Dw);
+        double2* rec = reinterpret_cast<double2*>(jt_rec_rep(m, r));
+        st(rec, 2 * l, make_double2(j.Dt + va, j.Du));
+        st(rec, 2 * l + 1, make_double2(-j.Dt - va, j.Dw));
     }
 }
 
 // Arc variables := branch flows F(vm, va) (the x rows are read from o.x,
 // the p / q entries written through o.g, which may alias it).
-__device__ void flows_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r0, int32_t r1) {
-    const int32_t l = chunk * kBlock + (int32_t)threadIdx.x;
-    if (l >= m.L) return;
+__device__ void flows_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r) {
+    const uint32_t l = (uint32_t)(chunk * kBlock) + threadIdx.x;
+    if (l >= (uint32_t)m.L) return;
     const int64_t L = m.L, N = m.N;
-    const int32_t fb = m.f_bus[l], tb = m.t_bus[l];
+    const uint32_t fb = (uint32_t)ld(m.f_bus, l), tb = (uint32_t)ld(m.t_bus, l);
     const Coef k0 = load_coef(m, l);
-    for (int32_t r = r0; r < r1; r++) {
-        const int64_t afr = l + 2 * L * r, ato = afr + L;
-        const Coef k = in_service(k0, m, l, r);
-        const double u = o.x[m.x_vm + fb + N * r], w = o.x[m.x_vm + tb + N * r];
-        const double th = o.x[m.x_va + fb + N * r] - o.x[m.x_va + tb + N * r];
+    {  // replica r
+        const int64_t oa = 2 * L * r, on = N * r;
+        const Coef k = in_service(k0, m, (int32_t)l, r);
+        const double u = ld(o.x + m.x_vm + on, fb), w = ld(o.x + m.x_vm + on, tb);
+        const double th = ld(o.x + m.x_va + on, fb) - ld(o.x + m.x_va + on, tb);
         double S, C;
         sincos(th, &S, &C);
-        o.g[m.x_p + afr] = flow1(k.Gff, 0.0, k.Gft, k.Bft, u, w, C, S).F;
-        o.g[m.x_q + afr] = flow1(-k.Bff, 0.0, -k.Bft, k.Gft, u, w, C, S).F;
-        o.g[m.x_p + ato] = flow1(0.0, k.Gtt, k.Gtf, -k.Btf, u, w, C, S).F;
-        o.g[m.x_q + ato] = flow1(0.0, -k.Btt, -k.Btf, -k.Gtf, u, w, C, S).F;
+        st(o.g + m.x_p + oa, l, flow1(k.Gff, 0.0, k.Gft, k.Bft, u, w, C, S).F);
+        st(o.g + m.x_q + oa, l, flow1(-k.Bff, 0.0, -k.Bft, k.Gft, u, w, C, S).F);
+        st(o.g + m.x_p + oa + L, l, flow1(0.0, k.Gtt, k.Gtf, -k.Btf, u, w, C, S).F);
+        st(o.g + m.x_q + oa + L, l, flow1(0.0, -k.Btt, -k.Btf, -k.Gtf, u, w, C, S).F);
     }
 }
 
@@ -311,55 +329,57 @@ struct Slot {
     int32_t kind, ref, bus, other, jpos, h0, h1, h2;
 };
 __device__ __forceinline__ Slot load_slot(const DevModel& m, int32_t w) {
-    const int4* p = reinterpret_cast<const int4*>(m.slots) + ((size_t)w * kBlock + threadIdx.x) * 2;
-    const int4 a = p[0], b = p[1];
+    const int4* p = reinterpret_cast<const int4*>(m.slots) + (size_t)w * kBlock * 2;
+    const int4 a = ld(p, 2 * threadIdx.x), b = ld(p, 2 * threadIdx.x + 1);
     return Slot{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 }
 
-__device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_t r0, int32_t r1, double* lds) {
+__device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_t r, double* lds) {
     const int32_t lane = threadIdx.x;
     const Slot sl = load_slot(m, w);
     const int32_t type = sl.kind & 3;
-    const int32_t side = (sl.kind & 4) ? 0 : 1;  // the half-edge sits at its branch's from bus
+    const uint32_t side = (sl.kind & 4) ? 0u : 1u;  // the half-edge sits at its branch's from bus
     const bool leader = sl.kind & 8;
     const int32_t len = (sl.kind >> 8) & 0xff;  // segment (head) or group (leader) length
     const bool wantC = o.c != nullptr, wantH = o.H != nullptr;
     const int64_t N = m.N, G = m.G;
-    const double* x = o.x;
+    const uint32_t bus = (uint32_t)sl.bus, ref = (uint32_t)sl.ref;
     double gs = 0.0, bs = 0.0;
     if (type == SK_HEAD) {
-        gs = m.gs[sl.bus];
-        bs = m.bs[sl.bus];
+        gs = ld(m.gs, bus);
+        bs = ld(m.bs, bus);
     }
-    for (int32_t r = r0; r < r1; r++) {
+    {  // replica r
+        const int64_t on = N * r;
         double v[kRec] = {0, 0, 0, 0, 0, 0};
         double vm_i = 0.0, base_p = 0.0, base_q = 0.0, shunt = 0.0;
         if (type == SK_HEAD) {
-            vm_i = x[m.x_vm + sl.bus + N * r];
+            vm_i = ld(o.x + m.x_vm + on, bus);
             if (wantC) {
-                const int64_t ld = sl.bus + (int64_t)m.load_stride * r;
-                base_p = m.pd[ld] + gs * vm_i * vm_i;
-                base_q = m.qd[ld] - bs * vm_i * vm_i;
+                const int64_t ol = (int64_t)m.load_stride * r;
+                base_p = ld(m.pd + ol, bus) + gs * vm_i * vm_i;
+                base_q = ld(m.qd + ol, bus) - bs * vm_i * vm_i;
             }
-            if (wantH) shunt = 2.0 * gs * o.y[m.c_balp + sl.bus + N * r] - 2.0 * bs * o.y[m.c_balq + sl.bus + N * r];
+            if (wantH) shunt = 2.0 * gs * ld(o.y + m.c_balp + on, bus) - 2.0 * bs * ld(o.y + m.c_balq + on, bus);
         } else if (type == SK_EDGE) {
-            const double2* rec = reinterpret_cast<const double2*>(rec_at(m, r, sl.ref, side));
+            const double2* rec = reinterpret_cast<const double2*>(rec_rep(m, r));
+            const uint32_t q = 3 * (2 * ref + side);
             if (wantH) {
-                const double2 a = rec[0], b = rec[1];
+                const double2 a = ld(rec, q), b = ld(rec, q + 1);
                 v[R_TT] = a.x;
                 v[R_MA] = a.y;
                 v[R_MM] = b.x;
                 v[R_UW] = b.y;
             }
             if (wantC) {
-                const double2 c = rec[2];
+                const double2 c = ld(rec, q + 2);
                 v[R_P] = c.x;
                 v[R_Q] = c.y;
             }
         } else if (type == SK_GEN) {
             if (wantC) {
-                v[R_P] = -x[m.x_pg + sl.ref + G * (m.npg > 1 ? r : 0)];
-                v[R_Q] = -x[m.x_qg + sl.ref + G * r];
+                v[R_P] = -ld(o.x + m.x_pg + G * (m.npg > 1 ? r : 0), ref);
+                v[R_Q] = -ld(o.x + m.x_qg + G * r, ref);
             }
         }
         if (wantC || wantH) {
@@ -375,14 +395,15 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
                     dmm += lds[R_MM * kBlock + lane + j];
                 }
                 if (wantC) {
-                    o.c[m.c_balp + sl.bus + N * r] = sp;
-                    o.c[m.c_balq + sl.bus + N * r] = sq;
+                    st(o.c + m.c_balp + on, bus, sp);
+                    st(o.c + m.c_balq + on, bus, sq);
                 }
                 if (wantH) {
-                    const int64_t hva = m.h_va + m.hva_rep * r, hvm = m.h_vm + m.hvm_rep * r;
-                    if (sl.h0 >= 0) o.H[hva + sl.h0] = daa;
-                    if (sl.h1 >= 0) o.H[hvm + sl.h1] = dma;
-                    o.H[hvm + sl.h2] = dmm + shunt;
+                    double* hva = o.H + m.h_va + m.hva_rep * r;
+                    double* hvm = o.H + m.h_vm + m.hvm_rep * r;
+                    if (sl.h0 >= 0) st(hva, (uint32_t)sl.h0, daa);
+                    if (sl.h1 >= 0) st(hvm, (uint32_t)sl.h1, dma);
+                    st(hvm, (uint32_t)sl.h2, dmm + shunt);
                 }
             } else if (type == SK_EDGE && wantH && leader) {
                 // the neighbour group (parallel branches to one bus), in order
@@ -392,47 +413,49 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
                     ma += lds[R_MA * kBlock + lane + j];
                     uw += lds[R_UW * kBlock + lane + j];
                 }
-                const int64_t hva = m.h_va + m.hva_rep * r, hvm = m.h_vm + m.hvm_rep * r;
-                if (sl.h0 >= 0) o.H[hva + sl.h0] = -tt;
-                o.H[hvm + sl.h1] = -ma;
-                if (sl.h2 >= 0) o.H[hvm + sl.h2] = uw;
+                double* hva = o.H + m.h_va + m.hva_rep * r;
+                double* hvm = o.H + m.h_vm + m.hvm_rep * r;
+                if (sl.h0 >= 0) st(hva, (uint32_t)sl.h0, -tt);
+                st(hvm, (uint32_t)sl.h1, -ma);
+                if (sl.h2 >= 0) st(hvm, (uint32_t)sl.h2, uw);
             }
             __syncthreads();  // LDS is reused by the next replica
         }
-        if (o.J) {
-            const int64_t jp = m.j_balp + m.jbal_rep * r + sl.jpos, jq = m.j_balq + m.jbal_rep * r + sl.jpos;
+        if (o.J && type != SK_IDLE) {
+            const uint32_t jp = (uint32_t)sl.jpos;
+            double vp, vq;
             if (type == SK_HEAD) {
-                o.J[jp] = 2.0 * gs * vm_i;
-                o.J[jq] = -2.0 * bs * vm_i;
-            } else if (type == SK_EDGE) {
-                o.J[jp] = 1.0;
-                o.J[jq] = 1.0;
-            } else if (type == SK_GEN) {
-                o.J[jp] = -1.0;
-                o.J[jq] = -1.0;
+                vp = 2.0 * gs * vm_i;
+                vq = -2.0 * bs * vm_i;
+            } else {
+                vp = vq = (type == SK_EDGE) ? 1.0 : -1.0;
             }
+            st(o.J + m.j_balp + m.jbal_rep * r, jp, vp);
+            st(o.J + m.j_balq + m.jbal_rep * r, jp, vq);
         }
         if (o.g && type == SK_HEAD) {
-            o.g[m.x_va + sl.bus + N * r] = 0.0;
-            o.g[m.x_vm + sl.bus + N * r] = 0.0;
+            st(o.g + m.x_va + on, bus, 0.0);
+            st(o.g + m.x_vm + on, bus, 0.0);
         }
     }
 }
 
 // J^T v, phase 2: va / vm entries of the packed buses.
-__device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_t r0, int32_t r1, double* lds) {
+__device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_t r, double* lds) {
     const int32_t lane = threadIdx.x;
     const Slot sl = load_slot(m, w);
     const int32_t type = sl.kind & 3;
-    const int32_t side = (sl.kind & 4) ? 0 : 1;
+    const uint32_t side = (sl.kind & 4) ? 0u : 1u;
     const int32_t len = (sl.kind >> 8) & 0xff;
     const int64_t N = m.N;
+    const uint32_t bus = (uint32_t)sl.bus;
     const double* x = o.x;
     const double* v = o.y;
-    for (int32_t r = r0; r < r1; r++) {
+    {  // replica r
+        const int64_t on = N * r;
         double ga = 0.0, gm = 0.0;
         if (type == SK_EDGE) {
-            const double2 t = *reinterpret_cast<const double2*>(jt_rec_at(m, r, sl.ref, side));
+            const double2 t = ld(reinterpret_cast<const double2*>(jt_rec_rep(m, r)), 2 * (uint32_t)sl.ref + side);
             ga = t.x;
             gm = t.y;
         }
@@ -440,18 +463,18 @@ __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int
         lds[1 * kBlock + lane] = gm;
         __syncthreads();
         if (type == SK_HEAD) {
-            const int64_t bi = sl.bus + N * r;
             double sa = 0.0, sm = 0.0;
             for (int32_t j = 1; j < len; j++) {
                 sa += lds[0 * kBlock + lane + j];
                 sm += lds[1 * kBlock + lane + j];
             }
-            for (int32_t q = m.ref_ptr[sl.bus]; q < m.ref_ptr[sl.bus + 1]; q++)
-                sa += v[m.c_ref + m.ref_list[q] + (int64_t)m.R * r];
-            const double vm = x[m.x_vm + bi];
-            sm += 2.0 * m.gs[sl.bus] * vm * v[m.c_balp + bi] - 2.0 * m.bs[sl.bus] * vm * v[m.c_balq + bi];
-            o.g[m.x_va + bi] = sa;
-            o.g[m.x_vm + bi] = sm;
+            for (int32_t q = ld(m.ref_ptr, bus); q < ld(m.ref_ptr, bus + 1); q++)
+                sa += ld(v + m.c_ref + (int64_t)m.R * r, (uint32_t)ld(m.ref_list, (uint32_t)q));
+            const double vm = ld(x + m.x_vm + on, bus);
+            sm += 2.0 * ld(m.gs, bus) * vm * ld(v + m.c_balp + on, bus) -
+                  2.0 * ld(m.bs, bus) * vm * ld(v + m.c_balq + on, bus);
+            st(o.g + m.x_va + on, bus, sa);
+            st(o.g + m.x_vm + on, bus, sm);
         }
         __syncthreads();
     }
@@ -459,7 +482,7 @@ __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int
 
 // A bus whose segment does not fit a wave: the workgroup sums its
 // half-edges' records (lane-strided, then a fixed wave tree).
-__device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32_t r0, int32_t r1) {
+__device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32_t r) {
     const int32_t b = m.big_bus[idx];
     const int32_t e0 = m.adj_ptr[b], e1 = m.adj_ptr[b + 1], deg = e1 - e0;
     const int64_t N = m.N, G = m.G;
@@ -467,14 +490,15 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
     const bool wantH = o.H != nullptr, wantC = o.c != nullptr;
     const int32_t g0 = m.gen_ptr[b], ng = m.gen_ptr[b + 1] - g0;
     const double gs = m.gs[b], bs = m.bs[b];
-    for (int32_t r = r0; r < r1; r++) {
+    {  // replica r
         const int64_t bi = b + N * r;
         const double vm = x[m.x_vm + bi];
+        const double* recs = rec_rep(m, r);
         if (wantC || wantH) {
             double sp = 0.0, sq = 0.0, daa = 0.0, dma = 0.0, dmm = 0.0;
             for (int32_t q = threadIdx.x; q < deg; q += kBlock) {
                 const int32_t code = m.he[e0 + q];
-                const double* rec = rec_at(m, r, code >> 1, (code & 1) ? 0 : 1);
+                const double* rec = recs + ((int64_t)(code >> 1) * 2 + ((code & 1) ? 0 : 1)) * kRec;
                 if (wantC) {
                     sp += rec[R_P];
                     sq += rec[R_Q];
@@ -501,7 +525,7 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
                     double tt = 0.0, ma = 0.0, uw = 0.0;
                     for (int32_t q = e; q < e1 && m.he_grp[q] == grp; q++) {
                         const int32_t cq = m.he[q];
-                        const double* rec = rec_at(m, r, cq >> 1, (cq & 1) ? 0 : 1);
+                        const double* rec = recs + ((int64_t)(cq >> 1) * 2 + ((cq & 1) ? 0 : 1)) * kRec;
                         tt += rec[R_TT];
                         ma += rec[R_MA];
                         uw += rec[R_UW];
@@ -517,8 +541,8 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
             }
             if (threadIdx.x == 0) {
                 if (wantC) {
-                    const int64_t ld = b + (int64_t)m.load_stride * r;
-                    double cp = m.pd[ld] + gs * vm * vm + sp, cq = m.qd[ld] - bs * vm * vm + sq;
+                    const int64_t ld_ = b + (int64_t)m.load_stride * r;
+                    double cp = m.pd[ld_] + gs * vm * vm + sp, cq = m.qd[ld_] - bs * vm * vm + sq;
                     const int64_t pgb = m.x_pg + G * (m.npg > 1 ? r : 0), qgb = m.x_qg + G * r;
                     for (int32_t q = 0; q < ng; q++) {
                         cp -= x[pgb + m.gen_list[g0 + q]];
@@ -553,17 +577,18 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
     }
 }
 
-__device__ void jt_big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32_t r0, int32_t r1) {
+__device__ void jt_big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32_t r) {
     const int32_t b = m.big_bus[idx];
     const int32_t e0 = m.adj_ptr[b], deg = m.adj_ptr[b + 1] - e0;
     const int64_t N = m.N;
     const double* x = o.x;
     const double* v = o.y;
-    for (int32_t r = r0; r < r1; r++) {
+    {  // replica r
+        const double* recs = jt_rec_rep(m, r);
         double sa = 0.0, sm = 0.0;
         for (int32_t q = threadIdx.x; q < deg; q += kBlock) {
             const int32_t code = m.he[e0 + q];
-            const double* rec = jt_rec_at(m, r, code >> 1, (code & 1) ? 0 : 1);
+            const double* rec = recs + ((int64_t)(code >> 1) * 2 + ((code & 1) ? 0 : 1)) * 2;
             sa += rec[0];
             sm += rec[1];
         }
@@ -585,40 +610,41 @@ __device__ void jt_big_task(const DevModel& m, const EvalOut& o, int32_t idx, in
 // reference and ramp rows, and one objective partial per replica (a fixed
 // wave tree over the chunk), written with a plain store: the objective item
 // of phase 2 reads the partials after the launch boundary.
-__device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r0, int32_t r1) {
-    const int32_t k = chunk * kBlock + (int32_t)threadIdx.x;
+__device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r) {
+    const uint32_t k = (uint32_t)(chunk * kBlock) + threadIdx.x;
     const double* x = o.x;
     const int64_t G = m.G;
+    const bool isgen = k < (uint32_t)m.G, isref = k < (uint32_t)m.R;
     double c2 = 0.0, c1 = 0.0, c0 = 0.0;
-    if (k < m.G) {
-        c2 = m.c2[k];
-        c1 = m.c1[k];
-        c0 = m.c0[k];
+    if (isgen) {
+        c2 = ld(m.c2, k);
+        c1 = ld(m.c1, k);
+        c0 = ld(m.c0, k);
     }
-    for (int32_t r = r0; r < r1; r++) {
+    const uint32_t rbus = isref ? (uint32_t)ld(m.ref_bus, k) : 0u;
+    {  // replica r
         double fk = 0.0;
-        if (k < m.G) {
+        if (isgen) {
             if (r < m.npg) {
-                const int64_t col = m.x_pg + k + G * r;
-                const double pg = x[col];
+                const double pg = ld(x + m.x_pg + G * r, k);
                 fk = c2 * pg * pg + c1 * pg + c0;
-                if (o.g) o.g[col] = 2.0 * c2 * pg + c1;
-                if (o.H) o.H[m.h_pg + k + G * r] = 2.0 * o.sigma * c2;
+                if (o.g) st(o.g + m.x_pg + G * r, k, 2.0 * c2 * pg + c1);
+                if (o.H) st(o.H + m.h_pg + G * r, k, 2.0 * o.sigma * c2);
             }
-            if (o.g) o.g[m.x_qg + k + G * r] = 0.0;
+            if (o.g) st(o.g + m.x_qg + G * r, k, 0.0);
             if (m.T > 1 && r >= 1) {
-                const int64_t row = k + G * (r - 1);
-                if (o.c) o.c[m.c_ramp + row] = x[m.x_pg + k + G * r] - x[m.x_pg + k + G * (r - 1)];
+                const int64_t row0 = G * (r - 1);
+                if (o.c) st(o.c + m.c_ramp + row0, k, ld(x + m.x_pg + G * r, k) - ld(x + m.x_pg + G * (r - 1), k));
                 if (o.J) {
-                    o.J[m.j_ramp + 2 * row] = -1.0;
-                    o.J[m.j_ramp + 2 * row + 1] = 1.0;
+                    st(o.J + m.j_ramp + 2 * row0, 2 * k, -1.0);
+                    st(o.J + m.j_ramp + 2 * row0, 2 * k + 1, 1.0);
                 }
             }
         }
-        if (k < m.R) {
-            const int64_t row = k + (int64_t)m.R * r;
-            if (o.c) o.c[m.c_ref + row] = x[m.x_va + m.ref_bus[k] + (int64_t)m.N * r];
-            if (o.J) o.J[m.j_ref + row] = 1.0;
+        if (isref) {
+            const int64_t row0 = (int64_t)m.R * r;
+            if (o.c) st(o.c + m.c_ref + row0, k, ld(x + m.x_va + (int64_t)m.N * r, rbus));
+            if (o.J) st(o.J + m.j_ref + row0, k, 1.0);
         }
         if (o.f && r < m.npg) {
             const double s = wave_sum(fk);
@@ -638,7 +664,7 @@ __device__ void obj_task(const DevModel& m, const EvalOut& o) {
     if (threadIdx.x == 0) *o.f = acc;
 }
 
-__device__ void jt_gen_task(const DevModel& m, const EvalOut& o, int32_t idx, int32_t r0, int32_t r1) {
+__device__ void jt_gen_task(const DevModel& m, const EvalOut& o, int32_t idx, int32_t r) {
     const int64_t G = m.G, N = m.N;
     const double* v = o.y;
     if (m.npg == 1 && m.nrep > 1) {
@@ -655,71 +681,76 @@ __device__ void jt_gen_task(const DevModel& m, const EvalOut& o, int32_t idx, in
         if (threadIdx.x == 0) o.g[m.x_pg + k] = acc;
         return;
     }
-    const int32_t k = idx * kBlock + (int32_t)threadIdx.x;
-    if (k >= m.G) return;
-    const int32_t bus = m.gen_bus[k];
-    for (int32_t r = r0; r < r1; r++) {
-        o.g[m.x_qg + k + G * r] = -v[m.c_balq + bus + N * r];
-        double acc = -v[m.c_balp + bus + N * r];
+    const uint32_t k = (uint32_t)(idx * kBlock) + threadIdx.x;
+    if (k >= (uint32_t)m.G) return;
+    const uint32_t bus = (uint32_t)ld(m.gen_bus, k);
+    {  // replica r
+        st(o.g + m.x_qg + G * r, k, -ld(v + m.c_balq + N * r, bus));
+        double acc = -ld(v + m.c_balp + N * r, bus);
         if (m.T > 1) {
-            if (r >= 1) acc += v[m.c_ramp + k + G * (r - 1)];
-            if (r + 1 < m.T) acc -= v[m.c_ramp + k + G * r];
+            if (r >= 1) acc += ld(v + m.c_ramp + G * (r - 1), k);
+            if (r + 1 < m.T) acc -= ld(v + m.c_ramp + G * r, k);
         }
-        o.g[m.x_pg + k + G * r] = acc;
+        st(o.g + m.x_pg + G * r, k, acc);
     }
 }
 
 }  // namespace
 
 // ================================================================== dispatch
-__device__ __forceinline__ void run_phase1(const DevModel& m, const EvalOut& o, int32_t mode, int32_t kind,
-                                           int32_t idx, int32_t r0, int32_t r1) {
-    if (kind == T_GEN) {
-        if (mode == 0) gen_task(m, o, idx, r0, r1);
-    } else if (mode == 0) {
-        branch_task(m, o, idx, r0, r1);
-    } else if (mode == 1) {
-        jt_branch_task(m, o, idx, r0, r1);
+// Every work item covers one replica: a loop over replicas inside an item
+// lets the compiler turn each output stream into its own per-lane 64-bit
+// pointer (more than doubling the branch task's registers).
+template <int MODE>
+__device__ __forceinline__ void run_phase1(const DevModel& m, const EvalOut& o, int32_t kind, int32_t idx, int32_t r) {
+    if (MODE == 0) {
+        if (kind == T_GEN)
+            gen_task(m, o, idx, r);
+        else
+            branch_task(m, o, idx, r);
+    } else if (MODE == 1) {
+        jt_branch_task(m, o, idx, r);
     } else {
-        flows_task(m, o, idx, r0, r1);
+        flows_task(m, o, idx, r);
     }
 }
 
-__device__ __forceinline__ void run_phase2(const DevModel& m, const EvalOut& o, int32_t mode, int32_t kind,
-                                           int32_t idx, int32_t r0, int32_t r1, double* lds) {
-    if (mode == 0) {
+template <int MODE>
+__device__ __forceinline__ void run_phase2(const DevModel& m, const EvalOut& o, int32_t kind, int32_t idx, int32_t r,
+                                           double* lds) {
+    if (MODE == 0) {
         switch (kind) {
-        case T_BIG: big_task(m, o, idx, r0, r1); break;
-        case T_WAVE: wave_task(m, o, idx, r0, r1, lds); break;
+        case T_BIG: big_task(m, o, idx, r); break;
+        case T_WAVE: wave_task(m, o, idx, r, lds); break;
         default: obj_task(m, o); break;
         }
     } else {
         switch (kind) {
-        case T_BIG: jt_big_task(m, o, idx, r0, r1); break;
-        case T_WAVE: jt_wave_task(m, o, idx, r0, r1, lds); break;
-        default: jt_gen_task(m, o, idx, r0, r1); break;
+        case T_BIG: jt_big_task(m, o, idx, r); break;
+        case T_WAVE: jt_wave_task(m, o, idx, r, lds); break;
+        default: jt_gen_task(m, o, idx, r); break;
         }
     }
 }
 
+// Item b of a plain launch; replicas outermost, so one XCD's contiguous
+// item range covers neighbouring entities of the same replicas.
 __device__ __forceinline__ void decode_phase1(const SetGrid& g, const DevModel& m, int32_t b, int32_t& kind,
-                                              int32_t& idx, int32_t& r0, int32_t& r1) {
+                                              int32_t& idx, int32_t& r) {
     if (b < g.n_branch) {
         kind = T_BRANCH;
         idx = b % m.nbchunks;
-        r0 = (b / m.nbchunks) * g.rg1;
-        r1 = min(r0 + g.rg1, m.nrep);
+        r = b / m.nbchunks;
     } else {
         b -= g.n_branch;
         kind = T_GEN;
         idx = b % m.ngchunks;
-        r0 = (b / m.ngchunks) * g.rgg;
-        r1 = min(r0 + g.rgg, g.gen_nrep);
+        r = b / m.ngchunks;
     }
 }
 
 __device__ __forceinline__ void decode_phase2(const SetGrid& g, const DevModel& m, int32_t b, int32_t& kind,
-                                              int32_t& idx, int32_t& r0, int32_t& r1) {
+                                              int32_t& idx, int32_t& r) {
     int32_t per;
     if (b < g.n_big) {
         kind = T_BIG;
@@ -729,45 +760,43 @@ __device__ __forceinline__ void decode_phase2(const SetGrid& g, const DevModel& 
         per = m.nwaves;
     } else if ((b -= g.n_wave) < g.n_obj) {
         kind = T_OBJ;
-        idx = r0 = r1 = 0;
+        idx = r = 0;
         return;
     } else {
         b -= g.n_obj;
         kind = T_GEN;
         if (g.gen_per_item) {  // one generator per wave, all replicas
             idx = b;
-            r0 = 0;
-            r1 = m.nrep;
+            r = 0;
             return;
         }
         per = m.ngchunks;
     }
-    // replica groups outermost, so one XCD's contiguous item range covers
-    // neighbouring entities of the same replicas
     idx = b % per;
-    r0 = (b / per) * g.rg2;
-    r1 = min(r0 + g.rg2, m.nrep);
+    r = b / per;
 }
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) branch_kernel(DevModel m, EvalOut o, SetGrid g) {
-    int32_t kind, idx, r0, r1;
-    decode_phase1(g, m, xcd_item(blockIdx.x, gridDim.x), kind, idx, r0, r1);
-    run_phase1(m, o, MODE, kind, idx, r0, r1);
+    int32_t kind, idx, r;
+    decode_phase1(g, m, xcd_item(blockIdx.x, gridDim.x), kind, idx, r);
+    run_phase1<MODE>(m, o, kind, idx, r);
 }
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) bus_kernel(DevModel m, EvalOut o, SetGrid g) {
     __shared__ double lds[kRec * kBlock];
-    int32_t kind, idx, r0, r1;
-    decode_phase2(g, m, xcd_item(blockIdx.x, gridDim.x), kind, idx, r0, r1);
-    run_phase2(m, o, MODE, kind, idx, r0, r1, lds);
+    int32_t kind, idx, r;
+    decode_phase2(g, m, xcd_item(blockIdx.x, gridDim.x), kind, idx, r);
+    run_phase2<MODE>(m, o, kind, idx, r, lds);
 }
 
-// Persistent batch kernels, one per phase: a fixed grid sized to the chip
-// drains the item list.  Items are split into kXcd contiguous ranges, one per
-// XCD, and the workgroups of an XCD stride through its range, so no queue
-// counter is needed and neighbouring items share an L2.
+// Batch kernels, one per phase and mode, in two forms.  Persistent (a grid
+// smaller than the item list): the list is split into kXcd contiguous
+// ranges, one per XCD, and the workgroups of an XCD stride through their
+// range, so no queue counter is needed and neighbouring items share an L2.
+// Flat (one workgroup per item, no loop, so fewer registers): the block
+// index is remapped to the same XCD ranges.
 __device__ __forceinline__ EvalOut batch_out(const BatchArgs& a, const BatchInst& bi, int32_t inst) {
     EvalOut o;
     o.x = a.X + bi.xoff;
@@ -797,16 +826,18 @@ __device__ __forceinline__ void xcd_stride(int32_t n, int32_t& first, int32_t& s
     end = (int32_t)((int64_t)n * (x + 1) / kXcd);
 }
 
+template <int MODE>
 __global__ void __launch_bounds__(kBlock) batch_branch_kernel(BatchArgs a) {
     int32_t it, step, end;
     xcd_stride(a.n_items, it, step, end);
     for (; it < end; it += step) {
         const BatchItem w = a.items[it];
         const BatchInst& bi = a.inst[w.inst];
-        run_phase1(bi.m, batch_out(a, bi, w.inst), a.mode, w.kind, w.idx, w.r0, w.r1);
+        run_phase1<MODE>(bi.m, batch_out(a, bi, w.inst), w.kind, w.idx, w.r);
     }
 }
 
+template <int MODE>
 __global__ void __launch_bounds__(kBlock) batch_bus_kernel(BatchArgs a) {
     __shared__ double lds[kRec * kBlock];
     int32_t it, step, end;
@@ -814,39 +845,41 @@ __global__ void __launch_bounds__(kBlock) batch_bus_kernel(BatchArgs a) {
     for (; it < end; it += step) {
         const BatchItem w = a.items[it];
         const BatchInst& bi = a.inst[w.inst];
-        run_phase2(bi.m, batch_out(a, bi, w.inst), a.mode, w.kind, w.idx, w.r0, w.r1, lds);
+        run_phase2<MODE>(bi.m, batch_out(a, bi, w.inst), w.kind, w.idx, w.r, lds);
         __syncthreads();
     }
 }
 
-namespace {
-int32_t group_for(int32_t per_rep, int32_t nrep) {
-    // enough replicas per item to keep the grid near 4096 workgroups
-    const int64_t items = (int64_t)per_rep * nrep;
-    int32_t rg = (int32_t)((items + 4095) / 4096);
-    return rg < 1 ? 1 : (rg > nrep ? nrep : rg);
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) batch_branch_flat(BatchArgs a) {
+    const int32_t it = xcd_item(blockIdx.x, gridDim.x);
+    if (it >= a.n_items) return;
+    const BatchItem w = a.items[it];
+    const BatchInst& bi = a.inst[w.inst];
+    run_phase1<MODE>(bi.m, batch_out(a, bi, w.inst), w.kind, w.idx, w.r);
 }
-}  // namespace
+
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) batch_bus_flat(BatchArgs a) {
+    __shared__ double lds[kRec * kBlock];
+    const int32_t it = xcd_item(blockIdx.x, gridDim.x);
+    if (it >= a.n_items) return;
+    const BatchItem w = a.items[it];
+    const BatchInst& bi = a.inst[w.inst];
+    run_phase2<MODE>(bi.m, batch_out(a, bi, w.inst), w.kind, w.idx, w.r, lds);
+}
 
 SetGrid plan_set(const DevModel& m, const EvalOut& o, int32_t mode) {
     SetGrid g{};
     const bool any = mode == 1 || o.g || o.c || o.J || o.H;
-    g.rg1 = group_for(m.nbchunks, m.nrep);
-    g.n_branch = any ? m.nbchunks * ((m.nrep + g.rg1 - 1) / g.rg1) : 0;
-    if (mode == 0 && (any || o.f)) {
-        // the objective alone needs the pg replicas only
-        g.gen_nrep = any ? m.nrep : m.npg;
-        g.rgg = group_for(m.ngchunks, g.gen_nrep);
-        g.n_gen1 = m.ngchunks * ((g.gen_nrep + g.rgg - 1) / g.rgg);
-    }
-    g.rg2 = group_for(m.nbig + m.nwaves, m.nrep);
-    g.nrg2 = (m.nrep + g.rg2 - 1) / g.rg2;
-    g.n_big = any ? m.nbig * g.nrg2 : 0;
-    g.n_wave = any ? m.nwaves * g.nrg2 : 0;
+    g.n_branch = any ? m.nbchunks * m.nrep : 0;
+    if (mode == 0 && (any || o.f)) g.n_gen1 = m.ngchunks * (any ? m.nrep : m.npg);  // f alone: pg replicas
+    g.n_big = any ? m.nbig * m.nrep : 0;
+    g.n_wave = any ? m.nwaves * m.nrep : 0;
     g.n_obj = (mode == 0 && o.f) ? 1 : 0;
     if (mode == 1) {
         g.gen_per_item = (m.npg == 1 && m.nrep > 1) ? 1 : 0;
-        g.n_gen2 = g.gen_per_item ? m.G : m.ngchunks * g.nrg2;
+        g.n_gen2 = g.gen_per_item ? m.G : m.ngchunks * m.nrep;
     }
     return g;
 }
@@ -869,8 +902,21 @@ hipError_t launch_jtprod(const DevModel& m, const double* x, const double* v, do
     return hipGetLastError();
 }
 
-void* batch_kernel_fn(int phase) {
-    return phase == 0 ? reinterpret_cast<void*>(&batch_branch_kernel) : reinterpret_cast<void*>(&batch_bus_kernel);
+void* batch_kernel_fn(int phase, int mode, bool flat) {
+    if (flat) {
+        if (phase == 0) {
+            if (mode == 0) return reinterpret_cast<void*>(&batch_branch_flat<0>);
+            if (mode == 1) return reinterpret_cast<void*>(&batch_branch_flat<1>);
+            return reinterpret_cast<void*>(&batch_branch_flat<2>);
+        }
+        return mode == 0 ? reinterpret_cast<void*>(&batch_bus_flat<0>) : reinterpret_cast<void*>(&batch_bus_flat<1>);
+    }
+    if (phase == 0) {
+        if (mode == 0) return reinterpret_cast<void*>(&batch_branch_kernel<0>);
+        if (mode == 1) return reinterpret_cast<void*>(&batch_branch_kernel<1>);
+        return reinterpret_cast<void*>(&batch_branch_kernel<2>);
+    }
+    return mode == 0 ? reinterpret_cast<void*>(&batch_bus_kernel<0>) : reinterpret_cast<void*>(&batch_bus_kernel<1>);
 }
 
 size_t scratch_bytes(const DevModel& m) {

@@ -103,8 +103,8 @@ def lib():
         "opf_batch_destroy": ([_vp], ctypes.c_int),
         "opf_batch_offsets": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
         "opf_batch_tune": ([_vp, _vp], ctypes.c_int),
-        "opf_batch_schedule": ([_vp, P(ctypes.c_int32), P(ctypes.c_int32)], ctypes.c_int),
-        "opf_batch_set_schedule": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+        "opf_batch_schedule": ([_vp, P(ctypes.c_int32)], ctypes.c_int),
+        "opf_batch_set_schedule": ([_vp, ctypes.c_int32], ctypes.c_int),
         "opf_batch_eval": ([_vp] + [_vp] * 8 + [_vp], ctypes.c_int),
         "opf_batch_jtprod": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
         "opf_batch_set_loads": ([_vp, _vp, _vp, _vp], ctypes.c_int),
@@ -402,14 +402,14 @@ class Batch:
         _check(lib().opf_batch_tune(self._h, _stream()))
         return self.schedule()
 
-    def schedule(self):
-        """(replicas per work item, persistent workgroups per compute unit)."""
-        rg, wg = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().opf_batch_schedule(self._h, ctypes.byref(rg), ctypes.byref(wg)))
-        return rg.value, wg.value
+    def schedule(self) -> int:
+        """Persistent workgroups per compute unit (0: one workgroup per item)."""
+        wg = ctypes.c_int32()
+        _check(lib().opf_batch_schedule(self._h, ctypes.byref(wg)))
+        return wg.value
 
-    def set_schedule(self, replica_group: int, wg_per_cu: int):
-        _check(lib().opf_batch_set_schedule(self._h, int(replica_group), int(wg_per_cu)))
+    def set_schedule(self, wg_per_cu: int):
+        _check(lib().opf_batch_set_schedule(self._h, int(wg_per_cu)))
 
     def _new(self, n):
         torch = _torch()

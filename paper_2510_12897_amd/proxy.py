@@ -74,12 +74,13 @@ class MLP:
             self.layout.append((off, off + fo * fi, fo, fi))
             off += fo * fi + fo
         self.n_params = off
-        # He-style initialisation drawn on the host from a seeded generator
+        # He-style initialisation of the hidden layers drawn on the host from
+        # a seeded generator; the output layer starts at zero, so the first
+        # prediction is the centre of every box (va = 0, vm, pg, qg mid-range)
         rng = np.random.default_rng(seed)
         host = np.zeros(off, np.float32)
-        for k, (wo, bo, fo, fi) in enumerate(self.layout):
-            gain = math.sqrt(2.0 / fi) if k < len(self.layout) - 1 else 0.5 / math.sqrt(fi)
-            host[wo:wo + fo * fi] = rng.standard_normal(fo * fi).astype(np.float32) * gain
+        for k, (wo, bo, fo, fi) in enumerate(self.layout[:-1]):
+            host[wo:wo + fo * fi] = rng.standard_normal(fo * fi).astype(np.float32) * math.sqrt(2.0 / fi)
         self.flat = torch.from_numpy(host).to(self.device).requires_grad_(True)
         self.m1 = torch.zeros_like(self.flat, requires_grad=False)
         self.m2 = torch.zeros_like(self.flat, requires_grad=False)

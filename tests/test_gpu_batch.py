@@ -108,14 +108,14 @@ def test_batch_equals_plain_bitwise_every_schedule():
     batch, models, inst_model, plain = build_mix()
     X, Y, sig, xs, ys = fill_inputs(batch, plain)
     ref = plain_reference(batch, plain, X, Y, sig)
-    for rg, wg in ((1, 1), (2, 4), (4, 2), (16, 8), (1, 16)):
-        say(f"[batch] schedule replica_group={rg} wg={wg}")
-        batch.set_schedule(rg, wg)
+    for wg in (0, 1, 2, 4, 16, 32):
+        say(f"[batch] schedule wg_per_cu={wg}")
+        batch.set_schedule(wg)
         out = outputs(batch)
         batch.eval(X, Y, sig, *out)
         torch.cuda.synchronize()
         for a, b in zip(out, ref):
-            assert torch.equal(a, b), f"schedule ({rg}, {wg}) differs from plain"
+            assert torch.equal(a, b), f"schedule {wg} differs from plain"
     say("[batch] tune")
     sched = batch.tune()
     out = outputs(batch)
