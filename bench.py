@@ -36,6 +36,36 @@ sys.path.insert(0, ROOT)
 
 METRIC = "callback sets/s (f,∇f,c,J,∇²L) FP64 batched vs plain; % of HBM roofline"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_set_10k_hbm_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_12897_amd", "csrc", f) for f in ("eval_kernels.hip", "dev_model.h")]
+
+
+def kernel_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per callback set from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, calibrated), or None when the kernel sources
+    have changed since the counters were taken."""
+    try:
+        fields = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    fields[k.strip()] = v.strip()
+        if fields.get("kernel_source_sha256") != kernel_hash():
+            return None
+        return int(float(fields["hbm_bytes_per_set"]))
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def algorithmic_bytes(cs: dict, dims, T: int = 1, K: int = 0, mp_loads: bool = False) -> int:
@@ -258,6 +288,43 @@ def bench_batch(args, torch, opf, synth, log):
     return out
 
 
+def bench_points(torch, opf, synth, log, B=16):
+    """The 10k-bus network evaluated at B independent (x, y) points per
+    launch through the batch path (what a batch of interior-point solves on
+    one network, or a sweep of evaluation points, issues)."""
+    dev = torch.device("cuda", 0)
+    cs = synth.network(10000, 13500, 2000, 1)
+    model = opf.Model(cs, device=0)
+    b = opf.Batch([model], np.zeros(B, np.int32))
+    X = torch.empty(b.n, dtype=torch.float64, device=dev)
+    Y = torch.empty(b.m, dtype=torch.float64, device=dev)
+    for i in range(B):
+        X[b.xoff[i]:b.xoff[i + 1]] = torch.as_tensor(synth.point(cs, (101, i)), device=dev)
+        Y[b.coff[i]:b.coff[i + 1]] = torch.as_tensor(synth.multipliers(model.m, (101, i)), device=dev)
+    S = torch.ones(B, dtype=torch.float64, device=dev)
+    outs = [(torch.empty(B, dtype=torch.float64, device=dev), torch.empty(b.n, dtype=torch.float64, device=dev),
+             torch.empty(b.m, dtype=torch.float64, device=dev), torch.empty(b.nnzj, dtype=torch.float64, device=dev),
+             torch.empty(b.nnzh, dtype=torch.float64, device=dev)) for _ in range(8)]
+    sched = b.tune()
+    k = [0]
+
+    def run():
+        o = outs[k[0] % len(outs)]
+        k[0] += 1
+        b.eval(X, Y, S, *o)
+
+    secs, _ = time_steps(torch, lambda: [run() for _ in range(10)], 3, 1)
+    per = secs / 30
+    shared = 80 * 13500 + 32 * 10000 + 28 * 2000 + 4 * (2 * 13500 + 2 * 10001 + 2000)
+    total = B * algorithmic_bytes(cs, (model.n, model.m, model.nnzj, model.nnzh)) - (B - 1) * shared
+    log(f"10k x {B} points: {per * 1e6:.1f} us/launch, {B / per:.0f} sets/s, {total / per / 1e9:.0f} GB/s")
+    b.close()
+    model.close()
+    return dict(workload=f"10000-bus network at {B} seeded (x, y) points per batched launch", points=B,
+                sets_per_s=B / per, us_per_launch=per * 1e6, bytes_per_launch=total,
+                achieved_gbs=total / per / 1e9, frac=total / per / 1e9 / HBM_PEAK_GBS, schedule=dict(wg_per_cu=sched))
+
+
 def bench_model(torch, opf, synth, cs, opts, n_in, n_out, sets, log, label, T=1, K=0, mp_loads=False):
     dev = torch.device("cuda", 0)
     model = opf.Model(cs, device=0, **opts)
@@ -291,12 +358,12 @@ def bench_proxy(args, torch, synth, log):
     gen.manual_seed(7)
     steps = args.proxy_steps
     loads, feats = px.sample(gen)
-    first = float(px.train_step(loads, feats, lr=1e-3))
+    first = float(px.train_step(loads, feats, lr=3e-4))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps - 1):
         loads, feats = px.sample(gen)
-        loss = px.train_step(loads, feats, lr=1e-3)
+        loss = px.train_step(loads, feats, lr=3e-4)
     torch.cuda.synchronize()
     train_s = (time.perf_counter() - t0) / max(steps - 1, 1)
     last = float(loss)
@@ -336,7 +403,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle timing budget (0 = skip)")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / multi-period / N-1 legs")
     ap.add_argument("--batch-reps", type=int, default=20)
-    ap.add_argument("--proxy-steps", type=int, default=500, help="training steps of the proxy leg (0 = skip)")
+    ap.add_argument("--proxy-steps", type=int, default=1500, help="training steps of the proxy leg (0 = skip)")
     ap.add_argument("--eager", action="store_true", help="launch the headline sets without a HIP graph")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run a device-to-device copy of this many MiB (HBM counter calibration)")
@@ -394,13 +461,14 @@ def main():
             "inputs_rotated": args.inputs, "outputs_rotated": 64,
         },
         "roofline": {
-            "kernel": "eval_set_kernel",
+            "kernel": "one callback set = branch_kernel<0> + bus_kernel<0> (two back-to-back launches)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "HBM bytes per callback set (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "bytes_per_launch": h["bytes_set"],
             "us_per_launch": h["per_set"] * 1e6,
         },
@@ -426,6 +494,10 @@ def main():
                 torch, opf, synth, cs, dict(n_cont=200, outaged=out), 4, 2, 10, log, "N-1 copies", K=200)
         except Exception as e:
             extra["contingency_1k_x201"] = {"error": repr(e)}
+        try:
+            extra["points16_10k"] = bench_points(torch, opf, synth, log, B=16)
+        except Exception as e:
+            extra["points16_10k"] = {"error": repr(e)}
         if args.proxy_steps > 0:
             try:
                 extra["proxy_300bus"] = bench_proxy(args, torch, synth, log)

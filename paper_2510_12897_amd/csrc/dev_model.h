@@ -78,7 +78,7 @@ struct DevModel {
     // objective partials, one per (generator chunk, pg replica)
     double* obj_part;         // [ngchunks * npg]
     // half-edge records passed from the branch phase to the bus phase:
-    // replica r, branch l, side s at rec + ((r * L + l) * 2 + s) * kRec
+    // side s, replica r, branch l at rec + ((s * nrep + r) * L + l) * kRec
     double* rec;
 };
 

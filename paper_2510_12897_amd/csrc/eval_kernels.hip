@@ -82,14 +82,35 @@ __device__ __forceinline__ Coef in_service(const Coef& k, const DevModel& m, int
     return m.outage[r] == l ? Coef{0, 0, 0, 0, 0, 0, 0, 0} : k;
 }
 
-// Half-edge records of replica r: kRec doubles per (branch, side), the two
-// sides of a branch adjacent, branches in order.
-__device__ __forceinline__ double* rec_rep(const DevModel& m, int32_t r) {
-    return m.rec + (int64_t)r * m.L * 2 * kRec;
+// Half-edge records of one side (0: from bus, 1: to bus) and replica r:
+// kRec doubles per branch, branches in order; the two sides are separate
+// arrays, so one wave writes each side as one contiguous run.
+__device__ __forceinline__ double* rec_side(const DevModel& m, int32_t r, int32_t side) {
+    return m.rec + ((int64_t)side * m.nrep + r) * m.L * kRec;
 }
-// The J^T v records of replica r: two doubles (va term, vm term) per half-edge.
-__device__ __forceinline__ double* jt_rec_rep(const DevModel& m, int32_t r) {
-    return m.rec + (int64_t)r * m.L * 2 * 2;
+// The J^T v records: two doubles (va term, vm term) per branch and side.
+__device__ __forceinline__ double* jt_rec_side(const DevModel& m, int32_t r, int32_t side) {
+    return m.rec + ((int64_t)side * m.nrep + r) * m.L * 2;
+}
+
+// Store PER values of every lane of a chunk as one contiguous run of
+// PER * nvalid doubles starting at dst[first]: staged through LDS, so every
+// store instruction of the wave covers consecutive addresses (a lane's own
+// values are PER doubles apart, which would touch PER times more cache
+// lines per instruction).  Every lane of the workgroup must call it.
+template <int PER>
+__device__ __forceinline__ void store_run(double* stage, double* dst, uint32_t first, uint32_t nvalid,
+                                          const double (&v)[PER]) {
+    const uint32_t lane = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < PER; k++) stage[PER * lane + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+        const uint32_t e = k * kBlock + lane;
+        if (e < PER * nvalid) st(dst, first + e, stage[e]);
+    }
+    __syncthreads();
 }
 
 // Block index -> work item, so that each XCD (blocks b with b % kXcd equal)
@@ -164,68 +185,87 @@ __device__ __forceinline__ Jterms jt_terms(const Coef& k, double v1, double v2, 
     return j;
 }
 
-// One flow row: c = p_arc - F and its five Jacobian entries (columns in
-// ascending order: the lower bus's va, the higher bus's va, then the vm
-// pair, then the arc variable).
-__device__ __forceinline__ void put_flow_row(const EvalOut& o, int64_t cblk, int64_t jblk, uint32_t rl, double arcval,
-                                             const Flow1& fl, bool f_lo) {
-    if (o.c) st(o.c + cblk, rl, arcval - fl.F);
-    if (o.J) {
-        double* J = o.J + jblk;
-        const uint32_t j = 5 * rl;
-        st(J, j, f_lo ? -fl.Ft : fl.Ft);
-        st(J, j + 1, f_lo ? fl.Ft : -fl.Ft);
-        st(J, j + 2, f_lo ? -fl.Fu : -fl.Fw);
-        st(J, j + 3, f_lo ? -fl.Fw : -fl.Fu);
-        st(J, j + 4, 1.0);
-    }
+// The five Jacobian entries of one flow row, columns in ascending order:
+// the lower bus's va, the higher bus's va, then the vm pair, then the arc
+// variable.
+__device__ __forceinline__ void flow_jrow(const Flow1& fl, bool f_lo, double (&v)[5]) {
+    v[0] = f_lo ? -fl.Ft : fl.Ft;
+    v[1] = f_lo ? fl.Ft : -fl.Ft;
+    v[2] = f_lo ? -fl.Fu : -fl.Fw;
+    v[3] = f_lo ? -fl.Fw : -fl.Fu;
+    v[4] = 1.0;
 }
 
 // ================================================================== phase 1
-__device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r) {
-    const uint32_t l = (uint32_t)(chunk * kBlock) + threadIdx.x;
-    if (l >= (uint32_t)m.L) return;
+__device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r, double* stage) {
+    const uint32_t l0 = (uint32_t)(chunk * kBlock), l = l0 + threadIdx.x;
+    const uint32_t nvalid = min((uint32_t)kBlock, (uint32_t)m.L - l0);
+    const bool act = l < (uint32_t)m.L;  // inactive lanes still join the LDS staging
     const int64_t L = m.L, N = m.N;
     const bool wantC = o.c != nullptr, wantJ = o.J != nullptr, wantH = o.H != nullptr;
-    const bool wantFlow = wantC || wantJ || wantH;
-    const uint32_t fb = (uint32_t)ld(m.f_bus, l), tb = (uint32_t)ld(m.t_bus, l);
-    const bool f_lo = fb < tb;
-    Coef k0{};
-    double rate2 = 0.0;
-    if (wantFlow) {
-        k0 = load_coef(m, l);
-        if (wantC) rate2 = ld(m.rate2, l);
-    }
-    {  // replica r
-        const int64_t ob = L * r;       // branch blocks of replica r
-        const int64_t oa = 2 * L * r;   // arc blocks of replica r (from arcs, then to arcs)
-        const int64_t on = N * r;       // bus blocks of replica r
-        if (wantFlow) {
+    const int64_t ob = L * r;       // branch blocks of replica r
+    const int64_t oa = 2 * L * r;   // arc blocks of replica r (from arcs, then to arcs)
+    const int64_t on = N * r;       // bus blocks of replica r
+    if (wantC || wantJ || wantH) {
+        // every load before the first store: loads and stores share one
+        // in-order completion counter, so a load issued after stores would
+        // also wait for all of them to complete
+        uint32_t fb = 0, tb = 0;
+        double rate2 = 0.0, pf = 0.0, pt = 0.0, qf = 0.0, qt = 0.0;
+        double yf = 0.0, yt = 0.0, y1 = 0.0, y2 = 0.0, y3 = 0.0, y4 = 0.0;
+        double u = 1.0, w = 1.0, vaf = 0.0, vat = 0.0;
+        Coef k{};
+        if (act) {
+            fb = (uint32_t)ld(m.f_bus, l);
+            tb = (uint32_t)ld(m.t_bus, l);
+            k = in_service(load_coef(m, l), m, (int32_t)l, r);
+            if (wantC) rate2 = ld(m.rate2, l);
             const double* xp = o.x + m.x_p + oa;
             const double* xq = o.x + m.x_q + oa;
-            const double pf = ld(xp, l), pt = ld(xp + L, l);
-            const double qf = ld(xq, l), qt = ld(xq + L, l);
-            const Coef k = in_service(k0, m, (int32_t)l, r);
-            const double u = ld(o.x + m.x_vm + on, fb), w = ld(o.x + m.x_vm + on, tb);
-            const double vaf = ld(o.x + m.x_va + on, fb), vat = ld(o.x + m.x_va + on, tb);
-            double S, C;
-            sincos(vaf - vat, &S, &C);
-            if (wantC || wantJ) {
-                put_flow_row(o, m.c_pfr + ob, m.j_pfr + 5 * ob, l, pf, flow1(k.Gff, 0.0, k.Gft, k.Bft, u, w, C, S),
-                             f_lo);
-                put_flow_row(o, m.c_qfr + ob, m.j_qfr + 5 * ob, l, qf,
-                             flow1(-k.Bff, 0.0, -k.Bft, k.Gft, u, w, C, S), f_lo);
-                put_flow_row(o, m.c_pto + ob, m.j_pto + 5 * ob, l, pt, flow1(0.0, k.Gtt, k.Gtf, -k.Btf, u, w, C, S),
-                             f_lo);
-                put_flow_row(o, m.c_qto + ob, m.j_qto + 5 * ob, l, qt,
-                             flow1(0.0, -k.Btt, -k.Btf, -k.Gtf, u, w, C, S), f_lo);
+            pf = ld(xp, l);
+            pt = ld(xp + L, l);
+            qf = ld(xq, l);
+            qt = ld(xq + L, l);
+            if (wantH) {
+                yf = ld(o.y + m.c_thf + ob, l);
+                yt = ld(o.y + m.c_tht + ob, l);
+                y1 = ld(o.y + m.c_pfr + ob, l);
+                y2 = ld(o.y + m.c_qfr + ob, l);
+                y3 = ld(o.y + m.c_pto + ob, l);
+                y4 = ld(o.y + m.c_qto + ob, l);
             }
-            if (wantC) {
-                st(o.c + m.c_ang + ob, l, vaf - vat);
-                st(o.c + m.c_thf + ob, l, pf * pf + qf * qf - rate2);
-                st(o.c + m.c_tht + ob, l, pt * pt + qt * qt - rate2);
-            }
-            if (wantJ) {
+            u = ld(o.x + m.x_vm + on, fb);
+            w = ld(o.x + m.x_vm + on, tb);
+            vaf = ld(o.x + m.x_va + on, fb);
+            vat = ld(o.x + m.x_va + on, tb);
+        }
+        const bool f_lo = fb < tb;
+        double S, C;
+        sincos(vaf - vat, &S, &C);
+        const Flow1 f1 = flow1(k.Gff, 0.0, k.Gft, k.Bft, u, w, C, S);
+        const Flow1 f2 = flow1(-k.Bff, 0.0, -k.Bft, k.Gft, u, w, C, S);
+        const Flow1 f3 = flow1(0.0, k.Gtt, k.Gtf, -k.Btf, u, w, C, S);
+        const Flow1 f4 = flow1(0.0, -k.Btt, -k.Btf, -k.Gtf, u, w, C, S);
+        if (wantC && act) {
+            st(o.c + m.c_pfr + ob, l, pf - f1.F);
+            st(o.c + m.c_qfr + ob, l, qf - f2.F);
+            st(o.c + m.c_pto + ob, l, pt - f3.F);
+            st(o.c + m.c_qto + ob, l, qt - f4.F);
+            st(o.c + m.c_ang + ob, l, vaf - vat);
+            st(o.c + m.c_thf + ob, l, pf * pf + qf * qf - rate2);
+            st(o.c + m.c_tht + ob, l, pt * pt + qt * qt - rate2);
+        }
+        if (wantJ) {
+            double v[5];
+            flow_jrow(f1, f_lo, v);
+            store_run<5>(stage, o.J + m.j_pfr + 5 * ob, 5 * l0, nvalid, v);
+            flow_jrow(f2, f_lo, v);
+            store_run<5>(stage, o.J + m.j_qfr + 5 * ob, 5 * l0, nvalid, v);
+            flow_jrow(f3, f_lo, v);
+            store_run<5>(stage, o.J + m.j_pto + 5 * ob, 5 * l0, nvalid, v);
+            flow_jrow(f4, f_lo, v);
+            store_run<5>(stage, o.J + m.j_qto + 5 * ob, 5 * l0, nvalid, v);
+            if (act) {
                 // block offsets need not be even, so these pairs are stored
                 // as two 8-byte values
                 st(o.J + m.j_ang + 2 * ob, 2 * l, f_lo ? 1.0 : -1.0);
@@ -235,35 +275,31 @@ __device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, 
                 st(o.J + m.j_tht + 2 * ob, 2 * l, 2.0 * pt);
                 st(o.J + m.j_tht + 2 * ob, 2 * l + 1, 2.0 * qt);
             }
-            // the two half-edge records: [TT, MA, MM, UW, P, Q] at the from
-            // side, then at the to side (12 doubles, 16-byte aligned)
-            double2* rec = reinterpret_cast<double2*>(rec_rep(m, r));
-            const uint32_t q = 6 * l;
+        }
+        if (wantH || wantC) {
+            // the half-edge records [TT, MA, MM, UW, P, Q] of each side
+            Hterms h{};
             if (wantH) {
-                const double yf = ld(o.y + m.c_thf + ob, l), yt = ld(o.y + m.c_tht + ob, l);
-                st(o.H + m.h_p + oa, l, 2.0 * yf);
-                st(o.H + m.h_p + oa + L, l, 2.0 * yt);
-                st(o.H + m.h_q + oa, l, 2.0 * yf);
-                st(o.H + m.h_q + oa + L, l, 2.0 * yt);
-                const Hterms h = hess_terms(k, ld(o.y + m.c_pfr + ob, l), ld(o.y + m.c_qfr + ob, l),
-                                            ld(o.y + m.c_pto + ob, l), ld(o.y + m.c_qto + ob, l), u, w, C, S);
-                // d/dva_f = d/dth, d/dva_t = -d/dth
-                st(rec, q, make_double2(h.Stt, h.Sut));
-                st(rec, q + 1, make_double2(h.Suu, h.Suw));
-                st(rec, q + 3, make_double2(h.Stt, -h.Swt));
-                st(rec, q + 4, make_double2(h.Sww, h.Suw));
+                if (act) {
+                    st(o.H + m.h_p + oa, l, 2.0 * yf);
+                    st(o.H + m.h_p + oa + L, l, 2.0 * yt);
+                    st(o.H + m.h_q + oa, l, 2.0 * yf);
+                    st(o.H + m.h_q + oa + L, l, 2.0 * yt);
+                }
+                h = hess_terms(k, y1, y2, y3, y4, u, w, C, S);
             }
-            if (wantC) {
-                st(rec, q + 2, make_double2(pf, qf));
-                st(rec, q + 5, make_double2(pt, qt));
-            }
+            // d/dva_f = d/dth, d/dva_t = -d/dth
+            const double rf[6] = {h.Stt, h.Sut, h.Suu, h.Suw, pf, qf};
+            store_run<6>(stage, rec_side(m, r, 0), kRec * l0, nvalid, rf);
+            const double rt[6] = {h.Stt, -h.Swt, h.Sww, h.Suw, pt, qt};
+            store_run<6>(stage, rec_side(m, r, 1), kRec * l0, nvalid, rt);
         }
-        if (o.g) {
-            st(o.g + m.x_p + oa, l, 0.0);
-            st(o.g + m.x_p + oa + L, l, 0.0);
-            st(o.g + m.x_q + oa, l, 0.0);
-            st(o.g + m.x_q + oa + L, l, 0.0);
-        }
+    }
+    if (o.g && act) {
+        st(o.g + m.x_p + oa, l, 0.0);
+        st(o.g + m.x_p + oa + L, l, 0.0);
+        st(o.g + m.x_q + oa, l, 0.0);
+        st(o.g + m.x_q + oa + L, l, 0.0);
     }
 }
 
@@ -279,26 +315,30 @@ __device__ void jt_branch_task(const DevModel& m, const EvalOut& o, int32_t chun
     const double* v = o.y;
     {  // replica r
         const int64_t ob = L * r, oa = 2 * L * r, on = N * r;
+        // every load before the first store (one in-order completion counter)
         const double vtf = ld(v + m.c_thf + ob, l), vtt = ld(v + m.c_tht + ob, l);
         const double v1 = ld(v + m.c_pfr + ob, l), v2 = ld(v + m.c_qfr + ob, l);
         const double v3 = ld(v + m.c_pto + ob, l), v4 = ld(v + m.c_qto + ob, l);
-        // p_a sits in its flow row (+1), its bus's balance row (+1) and its
-        // thermal row (2 p_a); q_a likewise
-        st(o.g + m.x_p + oa, l, v1 + ld(v + m.c_balp + on, fb) + 2.0 * ld(x + m.x_p + oa, l) * vtf);
-        st(o.g + m.x_p + oa + L, l, v3 + ld(v + m.c_balp + on, tb) + 2.0 * ld(x + m.x_p + oa + L, l) * vtt);
-        st(o.g + m.x_q + oa, l, v2 + ld(v + m.c_balq + on, fb) + 2.0 * ld(x + m.x_q + oa, l) * vtf);
-        st(o.g + m.x_q + oa + L, l, v4 + ld(v + m.c_balq + on, tb) + 2.0 * ld(x + m.x_q + oa + L, l) * vtt);
+        const double va = ld(v + m.c_ang + ob, l);
+        const double pf = ld(x + m.x_p + oa, l), pt = ld(x + m.x_p + oa + L, l);
+        const double qf = ld(x + m.x_q + oa, l), qt = ld(x + m.x_q + oa + L, l);
+        const double bpf = ld(v + m.c_balp + on, fb), bpt = ld(v + m.c_balp + on, tb);
+        const double bqf = ld(v + m.c_balq + on, fb), bqt = ld(v + m.c_balq + on, tb);
         const double u = ld(x + m.x_vm + on, fb), w = ld(x + m.x_vm + on, tb);
         const double th = ld(x + m.x_va + on, fb) - ld(x + m.x_va + on, tb);
         const Coef k = in_service(k0, m, (int32_t)l, r);
+        // p_a sits in its flow row (+1), its bus's balance row (+1) and its
+        // thermal row (2 p_a); q_a likewise
+        st(o.g + m.x_p + oa, l, v1 + bpf + 2.0 * pf * vtf);
+        st(o.g + m.x_p + oa + L, l, v3 + bpt + 2.0 * pt * vtt);
+        st(o.g + m.x_q + oa, l, v2 + bqf + 2.0 * qf * vtf);
+        st(o.g + m.x_q + oa + L, l, v4 + bqt + 2.0 * qt * vtt);
         double S, C;
         sincos(th, &S, &C);
         const Jterms j = jt_terms(k, v1, v2, v3, v4, u, w, C, S);
-        const double va = ld(v + m.c_ang + ob, l);
         // d th / d va_f = 1, d th / d va_t = -1; the angle row is va_f - va_t
-        double2* rec = reinterpret_cast<double2*>(jt_rec_rep(m, r));
-        st(rec, 2 * l, make_double2(j.Dt + va, j.Du));
-        st(rec, 2 * l + 1, make_double2(-j.Dt - va, j.Dw));
+        st(reinterpret_cast<double2*>(jt_rec_side(m, r, 0)), l, make_double2(j.Dt + va, j.Du));
+        st(reinterpret_cast<double2*>(jt_rec_side(m, r, 1)), l, make_double2(-j.Dt - va, j.Dw));
     }
 }
 
@@ -362,8 +402,8 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
             }
             if (wantH) shunt = 2.0 * gs * ld(o.y + m.c_balp + on, bus) - 2.0 * bs * ld(o.y + m.c_balq + on, bus);
         } else if (type == SK_EDGE) {
-            const double2* rec = reinterpret_cast<const double2*>(rec_rep(m, r));
-            const uint32_t q = 3 * (2 * ref + side);
+            const double2* rec = reinterpret_cast<const double2*>(rec_side(m, r, (int32_t)side));
+            const uint32_t q = 3 * ref;
             if (wantH) {
                 const double2 a = ld(rec, q), b = ld(rec, q + 1);
                 v[R_TT] = a.x;
@@ -455,7 +495,7 @@ __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int
         const int64_t on = N * r;
         double ga = 0.0, gm = 0.0;
         if (type == SK_EDGE) {
-            const double2 t = ld(reinterpret_cast<const double2*>(jt_rec_rep(m, r)), 2 * (uint32_t)sl.ref + side);
+            const double2 t = ld(reinterpret_cast<const double2*>(jt_rec_side(m, r, (int32_t)side)), (uint32_t)sl.ref);
             ga = t.x;
             gm = t.y;
         }
@@ -493,12 +533,13 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
     {  // replica r
         const int64_t bi = b + N * r;
         const double vm = x[m.x_vm + bi];
-        const double* recs = rec_rep(m, r);
+        const double* rec0 = rec_side(m, r, 0);
+        const double* rec1 = rec_side(m, r, 1);
         if (wantC || wantH) {
             double sp = 0.0, sq = 0.0, daa = 0.0, dma = 0.0, dmm = 0.0;
             for (int32_t q = threadIdx.x; q < deg; q += kBlock) {
                 const int32_t code = m.he[e0 + q];
-                const double* rec = recs + ((int64_t)(code >> 1) * 2 + ((code & 1) ? 0 : 1)) * kRec;
+                const double* rec = ((code & 1) ? rec0 : rec1) + (int64_t)(code >> 1) * kRec;
                 if (wantC) {
                     sp += rec[R_P];
                     sq += rec[R_Q];
@@ -525,7 +566,7 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
                     double tt = 0.0, ma = 0.0, uw = 0.0;
                     for (int32_t q = e; q < e1 && m.he_grp[q] == grp; q++) {
                         const int32_t cq = m.he[q];
-                        const double* rec = recs + ((int64_t)(cq >> 1) * 2 + ((cq & 1) ? 0 : 1)) * kRec;
+                        const double* rec = ((cq & 1) ? rec0 : rec1) + (int64_t)(cq >> 1) * kRec;
                         tt += rec[R_TT];
                         ma += rec[R_MA];
                         uw += rec[R_UW];
@@ -584,11 +625,12 @@ __device__ void jt_big_task(const DevModel& m, const EvalOut& o, int32_t idx, in
     const double* x = o.x;
     const double* v = o.y;
     {  // replica r
-        const double* recs = jt_rec_rep(m, r);
+        const double* rec0 = jt_rec_side(m, r, 0);
+        const double* rec1 = jt_rec_side(m, r, 1);
         double sa = 0.0, sm = 0.0;
         for (int32_t q = threadIdx.x; q < deg; q += kBlock) {
             const int32_t code = m.he[e0 + q];
-            const double* rec = recs + ((int64_t)(code >> 1) * 2 + ((code & 1) ? 0 : 1)) * 2;
+            const double* rec = ((code & 1) ? rec0 : rec1) + (int64_t)(code >> 1) * 2;
             sa += rec[0];
             sm += rec[1];
         }
@@ -622,19 +664,22 @@ __device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int
         c0 = ld(m.c0, k);
     }
     const uint32_t rbus = isref ? (uint32_t)ld(m.ref_bus, k) : 0u;
-    {  // replica r
+    {  // replica r; every load before the first store (one in-order completion counter)
+        const bool ramp = isgen && m.T > 1 && r >= 1;
+        const double pg = (isgen && r < m.npg) ? ld(x + m.x_pg + G * r, k) : 0.0;
+        const double pr = ramp ? ld(x + m.x_pg + G * r, k) - ld(x + m.x_pg + G * (r - 1), k) : 0.0;
+        const double var = (isref && o.c) ? ld(x + m.x_va + (int64_t)m.N * r, rbus) : 0.0;
         double fk = 0.0;
         if (isgen) {
             if (r < m.npg) {
-                const double pg = ld(x + m.x_pg + G * r, k);
                 fk = c2 * pg * pg + c1 * pg + c0;
                 if (o.g) st(o.g + m.x_pg + G * r, k, 2.0 * c2 * pg + c1);
                 if (o.H) st(o.H + m.h_pg + G * r, k, 2.0 * o.sigma * c2);
             }
             if (o.g) st(o.g + m.x_qg + G * r, k, 0.0);
-            if (m.T > 1 && r >= 1) {
+            if (ramp) {
                 const int64_t row0 = G * (r - 1);
-                if (o.c) st(o.c + m.c_ramp + row0, k, ld(x + m.x_pg + G * r, k) - ld(x + m.x_pg + G * (r - 1), k));
+                if (o.c) st(o.c + m.c_ramp + row0, k, pr);
                 if (o.J) {
                     st(o.J + m.j_ramp + 2 * row0, 2 * k, -1.0);
                     st(o.J + m.j_ramp + 2 * row0, 2 * k + 1, 1.0);
@@ -643,7 +688,7 @@ __device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int
         }
         if (isref) {
             const int64_t row0 = (int64_t)m.R * r;
-            if (o.c) st(o.c + m.c_ref + row0, k, ld(x + m.x_va + (int64_t)m.N * r, rbus));
+            if (o.c) st(o.c + m.c_ref + row0, k, var);
             if (o.J) st(o.J + m.j_ref + row0, k, 1.0);
         }
         if (o.f && r < m.npg) {
@@ -684,13 +729,14 @@ __device__ void jt_gen_task(const DevModel& m, const EvalOut& o, int32_t idx, in
     const uint32_t k = (uint32_t)(idx * kBlock) + threadIdx.x;
     if (k >= (uint32_t)m.G) return;
     const uint32_t bus = (uint32_t)ld(m.gen_bus, k);
-    {  // replica r
-        st(o.g + m.x_qg + G * r, k, -ld(v + m.c_balq + N * r, bus));
+    {  // replica r; both loads before the stores
+        const double yq = ld(v + m.c_balq + N * r, bus);
         double acc = -ld(v + m.c_balp + N * r, bus);
         if (m.T > 1) {
             if (r >= 1) acc += ld(v + m.c_ramp + G * (r - 1), k);
             if (r + 1 < m.T) acc -= ld(v + m.c_ramp + G * r, k);
         }
+        st(o.g + m.x_qg + G * r, k, -yq);
         st(o.g + m.x_pg + G * r, k, acc);
     }
 }
@@ -702,12 +748,13 @@ __device__ void jt_gen_task(const DevModel& m, const EvalOut& o, int32_t idx, in
 // lets the compiler turn each output stream into its own per-lane 64-bit
 // pointer (more than doubling the branch task's registers).
 template <int MODE>
-__device__ __forceinline__ void run_phase1(const DevModel& m, const EvalOut& o, int32_t kind, int32_t idx, int32_t r) {
+__device__ __forceinline__ void run_phase1(const DevModel& m, const EvalOut& o, int32_t kind, int32_t idx, int32_t r,
+                                           double* stage) {
     if (MODE == 0) {
         if (kind == T_GEN)
             gen_task(m, o, idx, r);
         else
-            branch_task(m, o, idx, r);
+            branch_task(m, o, idx, r, stage);
     } else if (MODE == 1) {
         jt_branch_task(m, o, idx, r);
     } else {
@@ -778,9 +825,10 @@ __device__ __forceinline__ void decode_phase2(const SetGrid& g, const DevModel& 
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) branch_kernel(DevModel m, EvalOut o, SetGrid g) {
+    __shared__ double stage[kRec * kBlock];
     int32_t kind, idx, r;
     decode_phase1(g, m, xcd_item(blockIdx.x, gridDim.x), kind, idx, r);
-    run_phase1<MODE>(m, o, kind, idx, r);
+    run_phase1<MODE>(m, o, kind, idx, r, stage);
 }
 
 template <int MODE>
@@ -828,12 +876,13 @@ __device__ __forceinline__ void xcd_stride(int32_t n, int32_t& first, int32_t& s
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) batch_branch_kernel(BatchArgs a) {
+    __shared__ double stage[kRec * kBlock];
     int32_t it, step, end;
     xcd_stride(a.n_items, it, step, end);
     for (; it < end; it += step) {
         const BatchItem w = a.items[it];
         const BatchInst& bi = a.inst[w.inst];
-        run_phase1<MODE>(bi.m, batch_out(a, bi, w.inst), w.kind, w.idx, w.r);
+        run_phase1<MODE>(bi.m, batch_out(a, bi, w.inst), w.kind, w.idx, w.r, stage);
     }
 }
 
@@ -852,11 +901,12 @@ __global__ void __launch_bounds__(kBlock) batch_bus_kernel(BatchArgs a) {
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) batch_branch_flat(BatchArgs a) {
+    __shared__ double stage[kRec * kBlock];
     const int32_t it = xcd_item(blockIdx.x, gridDim.x);
     if (it >= a.n_items) return;
     const BatchItem w = a.items[it];
     const BatchInst& bi = a.inst[w.inst];
-    run_phase1<MODE>(bi.m, batch_out(a, bi, w.inst), w.kind, w.idx, w.r);
+    run_phase1<MODE>(bi.m, batch_out(a, bi, w.inst), w.kind, w.idx, w.r, stage);
 }
 
 template <int MODE>

@@ -274,6 +274,13 @@ int build_host_model(const opf_case* cs, const opf_opts* opts, HostModel& hm, st
     ly.nnzh = ly.h_q + 2LL * L * P;
     if (ly.nnzh >= std::numeric_limits<int32_t>::max())
         return fail(err, OPF_E_CASE, "model too large for int32 indices");
+    // the kernels address every per-instance array with 32-bit byte offsets:
+    // x, c, J, H and the half-edge records (12 doubles per branch and
+    // replica) must each stay below 4 GiB
+    const int64_t kMaxElems = (int64_t(1) << 32) / 8;
+    if (ly.n >= kMaxElems || ly.m() >= kMaxElems || ly.nnzj() >= kMaxElems || ly.nnzh >= kMaxElems ||
+        12LL * L * P >= kMaxElems)
+        return fail(err, OPF_E_CASE, "model too large: an array of one instance exceeds 4 GiB");
     build_slots(hm);
     return OPF_OK;
 }

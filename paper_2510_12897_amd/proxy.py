@@ -283,7 +283,7 @@ class Penalty:
 
 
 class Squash:
-    def __init__(self, model, va_span: float = 1.0):
+    def __init__(self, model, va_span: float = 0.3):
         self.model = model
         self.va_span = float(va_span)
 
@@ -295,7 +295,7 @@ class WarmStartProxy:
     """MLP + squashing + penalty for one network: loads (pd, qd) -> x."""
 
     def __init__(self, case: dict, B: int, width: int = 1024, depth: int = 3, rho: float = 10.0,
-                 obj_scale: float = 1e-3, va_span: float = 1.0, seed: int = 0, device: int = 0):
+                 obj_scale: float = 1e-3, va_span: float = 0.3, seed: int = 0, device: int = 0):
         torch = _torch()
         N, G = int(case["n_bus"]), int(case["n_gen"])
         if N % 2 or G % 2:
@@ -327,7 +327,7 @@ class WarmStartProxy:
         X = self.squash(self.mlp(feats))
         return self.pen(X)
 
-    def train_step(self, loads, feats, lr=1e-3):
+    def train_step(self, loads, feats, lr=3e-4):
         lb = self.loss(loads, feats)
         loss = lb.mean()
         loss.backward()
