@@ -145,6 +145,17 @@ typedef struct opf_model_s *opf_model;
 void opf_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
                        void (*release)(void *ptr, void *ctx), void *ctx);
 
+/* Launch shape of models created afterwards.  A model whose callback set is
+ * at most `waves` 64-lane work items (summed over replicas) evaluates a set
+ * in ONE launch, its bus items recomputing the branch terms they need (a
+ * small set is latency-bound); larger models use two launches (branch items
+ * leave per-half-edge records that bus items read).  A model keeps its
+ * shape for life, and opf_eval_set and opf_batch_eval give bitwise the same
+ * results for it; the two shapes agree to rounding.  J^T v always uses two
+ * launches.  0 disables the single launch; the default is 4096.  OPF_E_ARG
+ * for a negative limit. */
+int opf_set_single_launch_limit(int64_t waves);
+
 /* Validate, derive branch admittance terms, adjacency and pattern on the
  * host, and upload everything to `device` in one copy.  The only call that
  * moves data from host to device.  *out receives the handle. */

@@ -52,7 +52,7 @@ struct opf_batch_s {
     int64_t n_loads = 0;
     opf::BatchItem* items[2][2] = {};  // device item lists, [mode (0 set, 1 J^T v)][phase]
     int32_t n_items[2][2] = {};
-    int32_t wg_per_cu = 8;
+    int32_t wg_per_cu = 0;           // flat until tuned (measured fastest on the 64-instance mix)
     int32_t n_cu = 256;
     std::map<GraphKey, GraphEntry> graphs;
 };

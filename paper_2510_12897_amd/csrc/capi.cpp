@@ -1,4 +1,5 @@
 // C-ABI of libopf (declared in include/opf.h): models and callbacks.
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <mutex>
@@ -71,6 +72,7 @@ ModelOffsets pack_model(Packer& pk, const opf::HostModel& hm) {
     o.coef = pk.add(hm.coef);
     o.rate2 = pk.add(hm.rate2);
     o.slots = pk.add(hm.slots);
+    o.slot_coef = pk.add(hm.slot_coef);
     o.big_bus = pk.add(hm.big_bus);
     o.adj_ptr = pk.add(hm.adj_ptr);
     o.he = pk.add(hm.he);
@@ -98,6 +100,8 @@ ModelOffsets pack_model(Packer& pk, const opf::HostModel& hm) {
 }
 
 namespace {
+std::atomic<int64_t> g_single_launch_limit{4096};
+int64_t single_launch_limit() { return g_single_launch_limit.load(); }
 int32_t gen_chunks(const opf::HostModel& hm) {
     return (std::max(hm.ly.G, hm.ly.R) + opf::kBlock - 1) / opf::kBlock;
 }
@@ -107,7 +111,8 @@ size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 void attach_scratch(opf::DevModel& d, char* scratch) {
     const size_t parts = round256(sizeof(double) * (size_t)d.ngchunks * d.npg);
     d.obj_part = reinterpret_cast<double*>(scratch);
-    d.rec = reinterpret_cast<double*>(scratch + parts);
+    d.obj_ticket = reinterpret_cast<int32_t*>(scratch + parts);
+    d.rec = reinterpret_cast<double*>(scratch + parts + 256);
 }
 
 opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets& o) {
@@ -121,6 +126,11 @@ opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets&
     for (int32_t b : hm.big_bus) d.big_cap = std::max(d.big_cap, hm.adj_ptr[b + 1] - hm.adj_ptr[b]);
     d.nbchunks = (ly.L + opf::kBlock - 1) / opf::kBlock;
     d.ngchunks = gen_chunks(hm);
+    // one launch per callback set when the whole set is a few waves per
+    // compute unit (the launch is latency-bound)
+    const int64_t waves = (int64_t)ly.nrep * (d.nbchunks + d.nwaves + d.nbig) + (int64_t)d.ngchunks * ly.nrep;
+    const int64_t limit = single_launch_limit();
+    d.single = (limit > 0 && waves <= limit) ? 1 : 0;
     d.x_va = ly.x_va; d.x_vm = ly.x_vm; d.x_pg = ly.x_pg; d.x_qg = ly.x_qg; d.x_p = ly.x_p; d.x_q = ly.x_q;
     using namespace opf;
     d.c_ref = ly.c_blk[B_REF]; d.c_pfr = ly.c_blk[B_PFR]; d.c_qfr = ly.c_blk[B_QFR];
@@ -135,7 +145,7 @@ opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets&
     d.hva_rep = ly.hva_rep; d.hvm_rep = ly.hvm_rep;
 #define P32(name) d.name = reinterpret_cast<const int32_t*>(base + o.name)
 #define PDB(name) d.name = reinterpret_cast<const double*>(base + o.name)
-    P32(f_bus); P32(t_bus); PDB(coef); PDB(rate2); P32(slots); P32(big_bus);
+    P32(f_bus); P32(t_bus); PDB(coef); PDB(rate2); P32(slots); PDB(slot_coef); P32(big_bus);
     P32(adj_ptr); P32(he); P32(he_grp); P32(nlo); P32(ndist); P32(hva_off); P32(hvm_off); P32(jbal_off);
     P32(gen_ptr); P32(gen_list); PDB(gs); PDB(bs); PDB(pd); PDB(qd);
     PDB(c2); PDB(c1); PDB(c0); P32(gen_bus); P32(ref_bus); P32(ref_ptr); P32(ref_list); P32(outage);
@@ -174,6 +184,12 @@ const char* opf_last_error(void) { return last_error().c_str(); }
 
 void opf_set_allocator(void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* ctx) {
     set_allocator(alloc, release, ctx);
+}
+
+int opf_set_single_launch_limit(int64_t waves) {
+    if (waves < 0) return set_err(OPF_E_ARG, "the limit must be >= 0");
+    g_single_launch_limit.store(waves);
+    return OPF_OK;
 }
 
 int opf_case_validate(const opf_case* cs, const opf_opts* opts) {
@@ -248,7 +264,7 @@ int opf_model_create(const opf_case* cs, const opf_opts* opts, int device, opf_m
         Packer pk;
         ModelOffsets mo = pack_model(pk, m->hm);
         opf::DevModel probe = make_dev(m->hm, nullptr, mo);
-        const size_t o_scr = pk.reserve(opf::scratch_bytes(probe));
+        const size_t o_scr = pk.reserve(opf::scratch_bytes(probe));  // zeroed: the ticket starts at 0
         const size_t oj_r = pk.reserve(sizeof(int32_t) * ly.nnzj());
         const size_t oj_c = pk.reserve(sizeof(int32_t) * ly.nnzj());
         const size_t oh_r = pk.reserve(sizeof(int32_t) * ly.nnzh);

@@ -17,7 +17,7 @@ enum TaskKind : int32_t {
     T_WAVE = 2,    // phase 2: 64 lanes of packed bus segments: balance rows, bus Hessian rows
     T_GEN = 3,     // phase 1: 64 generators: gradient, pg Hessian diagonal, objective partial, ref and
                    // ramp rows; J^T v: phase 2, the pg / qg entries
-    T_OBJ = 4      // phase 2: the objective, summing the partials in index order
+    T_OBJ = 4      // phase 2 (two-launch models): the objective, summing the partials in index order
 };
 
 // Half-edge record: what the branch phase leaves for the bus phase, per
@@ -31,6 +31,11 @@ enum TaskKind : int32_t {
 //   R_P, R_Q = the arc's p and q (its balance-row terms)
 // The J^T v phase uses the first two fields: the side's va and vm terms.
 enum RecField : int32_t { R_TT = 0, R_MA, R_MM, R_UW, R_P, R_Q, kRec };
+// Records are stored back to back, 48 bytes apart (16-byte aligned: three
+// 16-byte loads fetch one).  Padding them to 64-byte sectors and fetching
+// each with four cooperating lanes was measured slower (more bytes written
+// for no fewer cycles).
+constexpr int kRecStride = kRec;
 
 constexpr int kBlock = 64;          // threads per workgroup (one wave), every task
 constexpr int kXcd = 8;             // XCDs; workgroups are dealt to them round-robin
@@ -39,6 +44,8 @@ struct DevModel {
     int32_t N, L, G, R, T, nrep, npg, load_stride;
     int32_t nwaves, nbig, big_cap;   // wave count, big-bus count, largest big-bus degree
     int32_t nbchunks, ngchunks;      // branch / generator chunks of kBlock
+    int32_t single;                  // 1: small model; a plain callback set is one launch whose bus
+                                     // items recompute their half-edge terms (batches use two)
     int64_t x_va, x_vm, x_pg, x_qg, x_p, x_q;
     int64_t c_ref, c_pfr, c_qfr, c_pto, c_qto, c_ang, c_balp, c_balq, c_thf, c_tht, c_ramp;
     int64_t j_ref, j_pfr, j_qfr, j_pto, j_qto, j_ang, j_balp, j_balq, j_thf, j_tht, j_ramp, jbal_rep;
@@ -50,6 +57,7 @@ struct DevModel {
     const double* rate2;   // [L]
     // wave-packed bus segments: 8 int32 per lane (kind, ref, bus, other, jpos, h0, h1, h2)
     const int32_t* slots;  // [nwaves * kBlock * 8]
+    const double* slot_coef;  // [nwaves * kBlock * 8] admittance terms of each half-edge lane's branch
     const int32_t* big_bus;   // [nbig]
     // bus adjacency (the big-bus path)
     const int32_t* adj_ptr;   // [N+1]
@@ -75,14 +83,17 @@ struct DevModel {
     const int32_t* ref_ptr;   // [N+1] reference rows per bus
     const int32_t* ref_list;  // [R]
     const int32_t* outage;    // [nrep] branch out of service in a replica, or -1
-    // objective partials, one per (generator chunk, pg replica)
+    // objective partials, one per (generator chunk, pg replica), and the
+    // self-resetting arrival ticket of single-launch models
     double* obj_part;         // [ngchunks * npg]
+    int32_t* obj_ticket;      // [1], zero between launches
     // half-edge records passed from the branch phase to the bus phase:
-    // side s, replica r, branch l at rec + ((s * nrep + r) * L + l) * kRec
+    // side s, replica r, branch l at rec + ((s * nrep + r) * L + l) * kRecStride
     double* rec;
 };
 
 struct EvalOut {
+    int32_t single;  // this launch is the single-launch shape (bus items recompute, f by ticket)
     const double* x;
     const double* y;
     double sigma;

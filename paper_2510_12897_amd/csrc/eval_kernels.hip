@@ -83,10 +83,10 @@ __device__ __forceinline__ Coef in_service(const Coef& k, const DevModel& m, int
 }
 
 // Half-edge records of one side (0: from bus, 1: to bus) and replica r:
-// kRec doubles per branch, branches in order; the two sides are separate
-// arrays, so one wave writes each side as one contiguous run.
+// one 64-byte record per branch, branches in order; the two sides are
+// separate arrays, so one wave writes each side as one contiguous run.
 __device__ __forceinline__ double* rec_side(const DevModel& m, int32_t r, int32_t side) {
-    return m.rec + ((int64_t)side * m.nrep + r) * m.L * kRec;
+    return m.rec + ((int64_t)side * m.nrep + r) * m.L * kRecStride;
 }
 // The J^T v records: two doubles (va term, vm term) per branch and side.
 __device__ __forceinline__ double* jt_rec_side(const DevModel& m, int32_t r, int32_t side) {
@@ -196,7 +196,35 @@ __device__ __forceinline__ void flow_jrow(const Flow1& fl, bool f_lo, double (&v
     v[4] = 1.0;
 }
 
+// The half-edge record [TT, MA, MM, UW, P, Q] of branch l at one side (0:
+// from, 1: to), recomputed from x and y with the branch task's arithmetic:
+// a single launch reads nothing the branch items write.
+__device__ __forceinline__ void half_edge_record(const DevModel& m, const EvalOut& o, uint32_t l, uint32_t side,
+                                                 uint32_t fb, uint32_t tb, const Coef& k0, int32_t r,
+                                                 double (&v)[kRec]) {
+    const int64_t L = m.L, N = m.N, ob = L * r, oa = 2 * L * r + (side ? L : 0), on = N * r;
+    if (o.c) {
+        v[R_P] = ld(o.x + m.x_p + oa, l);
+        v[R_Q] = ld(o.x + m.x_q + oa, l);
+    }
+    if (o.H) {
+        const double y1 = ld(o.y + m.c_pfr + ob, l), y2 = ld(o.y + m.c_qfr + ob, l);
+        const double y3 = ld(o.y + m.c_pto + ob, l), y4 = ld(o.y + m.c_qto + ob, l);
+        const double u = ld(o.x + m.x_vm + on, fb), w = ld(o.x + m.x_vm + on, tb);
+        const double vaf = ld(o.x + m.x_va + on, fb), vat = ld(o.x + m.x_va + on, tb);
+        const Coef k = in_service(k0, m, (int32_t)l, r);
+        double S, C;
+        sincos(vaf - vat, &S, &C);
+        const Hterms h = hess_terms(k, y1, y2, y3, y4, u, w, C, S);
+        v[R_TT] = h.Stt;
+        v[R_MA] = side ? -h.Swt : h.Sut;
+        v[R_MM] = side ? h.Sww : h.Suu;
+        v[R_UW] = h.Suw;
+    }
+}
+
 // ================================================================== phase 1
+template <bool SINGLE>
 __device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r, double* stage) {
     const uint32_t l0 = (uint32_t)(chunk * kBlock), l = l0 + threadIdx.x;
     const uint32_t nvalid = min((uint32_t)kBlock, (uint32_t)m.L - l0);
@@ -257,14 +285,29 @@ __device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, 
         }
         if (wantJ) {
             double v[5];
-            flow_jrow(f1, f_lo, v);
-            store_run<5>(stage, o.J + m.j_pfr + 5 * ob, 5 * l0, nvalid, v);
-            flow_jrow(f2, f_lo, v);
-            store_run<5>(stage, o.J + m.j_qfr + 5 * ob, 5 * l0, nvalid, v);
-            flow_jrow(f3, f_lo, v);
-            store_run<5>(stage, o.J + m.j_pto + 5 * ob, 5 * l0, nvalid, v);
-            flow_jrow(f4, f_lo, v);
-            store_run<5>(stage, o.J + m.j_qto + 5 * ob, 5 * l0, nvalid, v);
+            if (SINGLE) {
+                // a small model's launch is latency-bound: store the rows
+                // directly rather than through LDS
+                if (act) {
+                    const Flow1* fl[4] = {&f1, &f2, &f3, &f4};
+                    const int64_t jb[4] = {m.j_pfr, m.j_qfr, m.j_pto, m.j_qto};
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        flow_jrow(*fl[q], f_lo, v);
+#pragma unroll
+                        for (int e = 0; e < 5; e++) st(o.J + jb[q] + 5 * ob, 5 * l + e, v[e]);
+                    }
+                }
+            } else {
+                flow_jrow(f1, f_lo, v);
+                store_run<5>(stage, o.J + m.j_pfr + 5 * ob, 5 * l0, nvalid, v);
+                flow_jrow(f2, f_lo, v);
+                store_run<5>(stage, o.J + m.j_qfr + 5 * ob, 5 * l0, nvalid, v);
+                flow_jrow(f3, f_lo, v);
+                store_run<5>(stage, o.J + m.j_pto + 5 * ob, 5 * l0, nvalid, v);
+                flow_jrow(f4, f_lo, v);
+                store_run<5>(stage, o.J + m.j_qto + 5 * ob, 5 * l0, nvalid, v);
+            }
             if (act) {
                 // block offsets need not be even, so these pairs are stored
                 // as two 8-byte values
@@ -276,23 +319,21 @@ __device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, 
                 st(o.J + m.j_tht + 2 * ob, 2 * l + 1, 2.0 * qt);
             }
         }
-        if (wantH || wantC) {
+        if (wantH && act) {
+            st(o.H + m.h_p + oa, l, 2.0 * yf);
+            st(o.H + m.h_p + oa + L, l, 2.0 * yt);
+            st(o.H + m.h_q + oa, l, 2.0 * yf);
+            st(o.H + m.h_q + oa + L, l, 2.0 * yt);
+        }
+        if ((wantH || wantC) && !SINGLE) {
             // the half-edge records [TT, MA, MM, UW, P, Q] of each side
             Hterms h{};
-            if (wantH) {
-                if (act) {
-                    st(o.H + m.h_p + oa, l, 2.0 * yf);
-                    st(o.H + m.h_p + oa + L, l, 2.0 * yt);
-                    st(o.H + m.h_q + oa, l, 2.0 * yf);
-                    st(o.H + m.h_q + oa + L, l, 2.0 * yt);
-                }
-                h = hess_terms(k, y1, y2, y3, y4, u, w, C, S);
-            }
+            if (wantH) h = hess_terms(k, y1, y2, y3, y4, u, w, C, S);
             // d/dva_f = d/dth, d/dva_t = -d/dth
-            const double rf[6] = {h.Stt, h.Sut, h.Suu, h.Suw, pf, qf};
-            store_run<6>(stage, rec_side(m, r, 0), kRec * l0, nvalid, rf);
-            const double rt[6] = {h.Stt, -h.Swt, h.Sww, h.Suw, pt, qt};
-            store_run<6>(stage, rec_side(m, r, 1), kRec * l0, nvalid, rt);
+            const double rf[kRecStride] = {h.Stt, h.Sut, h.Suu, h.Suw, pf, qf};
+            store_run<kRecStride>(stage, rec_side(m, r, 0), kRecStride * l0, nvalid, rf);
+            const double rt[kRecStride] = {h.Stt, -h.Swt, h.Sww, h.Suw, pt, qt};
+            store_run<kRecStride>(stage, rec_side(m, r, 1), kRecStride * l0, nvalid, rt);
         }
     }
     if (o.g && act) {
@@ -374,6 +415,7 @@ __device__ __forceinline__ Slot load_slot(const DevModel& m, int32_t w) {
     return Slot{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 }
 
+template <bool SINGLE>
 __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_t r, double* lds) {
     const int32_t lane = threadIdx.x;
     const Slot sl = load_slot(m, w);
@@ -401,9 +443,19 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
                 base_q = ld(m.qd + ol, bus) - bs * vm_i * vm_i;
             }
             if (wantH) shunt = 2.0 * gs * ld(o.y + m.c_balp + on, bus) - 2.0 * bs * ld(o.y + m.c_balq + on, bus);
+        } else if (type == SK_EDGE && SINGLE) {
+            Coef k{};
+            if (wantH) {
+                const double2* kc = reinterpret_cast<const double2*>(m.slot_coef) + (size_t)w * kBlock * 4;
+                const double2 c01 = ld(kc, 4 * lane), c23 = ld(kc, 4 * lane + 1);
+                const double2 c45 = ld(kc, 4 * lane + 2), c67 = ld(kc, 4 * lane + 3);
+                k = Coef{c01.x, c01.y, c23.x, c23.y, c45.x, c45.y, c67.x, c67.y};
+            }
+            const uint32_t other = (uint32_t)sl.other;
+            half_edge_record(m, o, ref, side, side ? other : bus, side ? bus : other, k, r, v);
         } else if (type == SK_EDGE) {
             const double2* rec = reinterpret_cast<const double2*>(rec_side(m, r, (int32_t)side));
-            const uint32_t q = 3 * ref;
+            const uint32_t q = (kRecStride / 2) * ref;
             if (wantH) {
                 const double2 a = ld(rec, q), b = ld(rec, q + 1);
                 v[R_TT] = a.x;
@@ -520,8 +572,25 @@ __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int
     }
 }
 
+// The record of half-edge `code` (branch << 1 | from-side flag) of a big
+// bus: recomputed in a single launch, else read from the branch phase.
+template <bool SINGLE>
+__device__ __forceinline__ void big_record(const DevModel& m, const EvalOut& o, int32_t code, int32_t r,
+                                           const double* rec0, const double* rec1, double (&v)[kRec]) {
+    const uint32_t l = (uint32_t)(code >> 1), side = (code & 1) ? 0u : 1u;
+    if (SINGLE) {
+        for (int q = 0; q < kRec; q++) v[q] = 0.0;
+        const Coef k = o.H ? load_coef(m, l) : Coef{};
+        half_edge_record(m, o, l, side, (uint32_t)ld(m.f_bus, l), (uint32_t)ld(m.t_bus, l), k, r, v);
+    } else {
+        const double* rec = (side == 0 ? rec0 : rec1) + (int64_t)l * kRecStride;
+        for (int q = 0; q < kRec; q++) v[q] = rec[q];
+    }
+}
+
 // A bus whose segment does not fit a wave: the workgroup sums its
 // half-edges' records (lane-strided, then a fixed wave tree).
+template <bool SINGLE>
 __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32_t r) {
     const int32_t b = m.big_bus[idx];
     const int32_t e0 = m.adj_ptr[b], e1 = m.adj_ptr[b + 1], deg = e1 - e0;
@@ -538,8 +607,8 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
         if (wantC || wantH) {
             double sp = 0.0, sq = 0.0, daa = 0.0, dma = 0.0, dmm = 0.0;
             for (int32_t q = threadIdx.x; q < deg; q += kBlock) {
-                const int32_t code = m.he[e0 + q];
-                const double* rec = ((code & 1) ? rec0 : rec1) + (int64_t)(code >> 1) * kRec;
+                double rec[kRec];
+                big_record<SINGLE>(m, o, m.he[e0 + q], r, rec0, rec1, rec);
                 if (wantC) {
                     sp += rec[R_P];
                     sq += rec[R_Q];
@@ -565,8 +634,8 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
                     const int32_t k = (code & 1) ? m.t_bus[l] : m.f_bus[l];
                     double tt = 0.0, ma = 0.0, uw = 0.0;
                     for (int32_t q = e; q < e1 && m.he_grp[q] == grp; q++) {
-                        const int32_t cq = m.he[q];
-                        const double* rec = ((cq & 1) ? rec0 : rec1) + (int64_t)(cq >> 1) * kRec;
+                        double rec[kRec];
+                        big_record<SINGLE>(m, o, m.he[q], r, rec0, rec1, rec);
                         tt += rec[R_TT];
                         ma += rec[R_MA];
                         uw += rec[R_UW];
@@ -652,6 +721,7 @@ __device__ void jt_big_task(const DevModel& m, const EvalOut& o, int32_t idx, in
 // reference and ramp rows, and one objective partial per replica (a fixed
 // wave tree over the chunk), written with a plain store: the objective item
 // of phase 2 reads the partials after the launch boundary.
+template <bool SINGLE>
 __device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r) {
     const uint32_t k = (uint32_t)(chunk * kBlock) + threadIdx.x;
     const double* x = o.x;
@@ -693,13 +763,38 @@ __device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int
         }
         if (o.f && r < m.npg) {
             const double s = wave_sum(fk);
-            if (threadIdx.x == 0) m.obj_part[chunk + (int64_t)m.ngchunks * r] = s;
+            const int64_t slot = chunk + (int64_t)m.ngchunks * r;
+            if (!SINGLE) {
+                if (threadIdx.x == 0) m.obj_part[slot] = s;
+            } else {
+                // single launch: the chunk whose arrival completes the
+                // self-resetting ticket sums every partial (index order)
+                __shared__ int32_t last;
+                const int32_t total = m.ngchunks * m.npg;
+                if (threadIdx.x == 0) {
+                    __hip_atomic_store(&m.obj_part[slot], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const int32_t old =
+                        __hip_atomic_fetch_add(m.obj_ticket, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                    last = (old + 1 == total) ? 1 : 0;
+                }
+                __syncthreads();
+                if (last) {
+                    double acc = 0.0;
+                    for (int32_t q = threadIdx.x; q < total; q += kBlock)
+                        acc += __hip_atomic_load(&m.obj_part[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    acc = wave_sum(acc);
+                    if (threadIdx.x == 0) {
+                        *o.f = acc;
+                        __hip_atomic_store(m.obj_ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+            }
         }
     }
 }
 
-// Phase 2: f = the partials summed lane-strided in index order, then a
-// fixed wave tree.
+// Phase 2 of a two-launch model: f = the partials summed lane-strided in
+// index order, then a fixed wave tree.
 __device__ void obj_task(const DevModel& m, const EvalOut& o) {
     if (o.f == nullptr) return;
     const int32_t total = m.ngchunks * m.npg;
@@ -752,9 +847,9 @@ __device__ __forceinline__ void run_phase1(const DevModel& m, const EvalOut& o, 
                                            double* stage) {
     if (MODE == 0) {
         if (kind == T_GEN)
-            gen_task(m, o, idx, r);
+            gen_task<false>(m, o, idx, r);
         else
-            branch_task(m, o, idx, r, stage);
+            branch_task<false>(m, o, idx, r, stage);
     } else if (MODE == 1) {
         jt_branch_task(m, o, idx, r);
     } else {
@@ -767,8 +862,8 @@ __device__ __forceinline__ void run_phase2(const DevModel& m, const EvalOut& o, 
                                            double* lds) {
     if (MODE == 0) {
         switch (kind) {
-        case T_BIG: big_task(m, o, idx, r); break;
-        case T_WAVE: wave_task(m, o, idx, r, lds); break;
+        case T_BIG: big_task<false>(m, o, idx, r); break;
+        case T_WAVE: wave_task<false>(m, o, idx, r, lds); break;
         default: obj_task(m, o); break;
         }
     } else {
@@ -824,21 +919,52 @@ __device__ __forceinline__ void decode_phase2(const SetGrid& g, const DevModel& 
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) branch_kernel(DevModel m, EvalOut o, SetGrid g) {
-    __shared__ double stage[kRec * kBlock];
+__global__ void __launch_bounds__(kBlock, 6) branch_kernel(DevModel m, EvalOut o, SetGrid g) {
+    __shared__ double stage[kRecStride * kBlock];
     int32_t kind, idx, r;
     decode_phase1(g, m, xcd_item(blockIdx.x, gridDim.x), kind, idx, r);
     run_phase1<MODE>(m, o, kind, idx, r, stage);
 }
 
+// The single launch of a small model's callback set: items ordered branch
+// chunks, generator chunks, big buses, waves (bus items recompute their
+// half-edge terms, the generator items sum the objective by ticket, so no
+// item waits for another).  Blocks are dealt to the XCDs round-robin, which
+// spreads every kind of item over all of them: a small launch is bound by
+// latency, not by the lines that neighbouring items share.
+__global__ void __launch_bounds__(kBlock) set_kernel_single(DevModel m, EvalOut o, SetGrid g) {
+    __shared__ double lds[kRecStride * kBlock];
+    int32_t b = blockIdx.x;
+    if (b < g.n_branch) {
+        branch_task<true>(m, o, b % m.nbchunks, b / m.nbchunks, lds);
+        return;
+    }
+    b -= g.n_branch;
+    if (b < g.n_gen1) {
+        gen_task<true>(m, o, b % m.ngchunks, b / m.ngchunks);
+        return;
+    }
+    b -= g.n_gen1;
+    if (b < g.n_big) {
+        big_task<true>(m, o, b % m.nbig, b / m.nbig);
+        return;
+    }
+    b -= g.n_big;
+    wave_task<true>(m, o, b % m.nwaves, b / m.nwaves, lds);
+}
+
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) bus_kernel(DevModel m, EvalOut o, SetGrid g) {
-    __shared__ double lds[kRec * kBlock];
+__global__ void __launch_bounds__(kBlock, 6) bus_kernel(DevModel m, EvalOut o, SetGrid g) {
+    __shared__ double lds[kRecStride * kBlock];
     int32_t kind, idx, r;
     decode_phase2(g, m, xcd_item(blockIdx.x, gridDim.x), kind, idx, r);
     run_phase2<MODE>(m, o, kind, idx, r, lds);
 }
 
+// Occupancy hints (second launch-bounds argument: waves per SIMD) are the
+// highest that compile without register spills; the single-launch kernel
+// keeps its registers (a small launch has few waves to hide latency with).
+//
 // Batch kernels, one per phase and mode, in two forms.  Persistent (a grid
 // smaller than the item list): the list is split into kXcd contiguous
 // ranges, one per XCD, and the workgroups of an XCD stride through their
@@ -847,6 +973,7 @@ __global__ void __launch_bounds__(kBlock) bus_kernel(DevModel m, EvalOut o, SetG
 // index is remapped to the same XCD ranges.
 __device__ __forceinline__ EvalOut batch_out(const BatchArgs& a, const BatchInst& bi, int32_t inst) {
     EvalOut o;
+    o.single = 0;  // batches always take the two-launch shape (records, objective items)
     o.x = a.X + bi.xoff;
     if (a.mode == 0) {
         o.y = a.Y ? a.Y + bi.coff : nullptr;
@@ -876,7 +1003,7 @@ __device__ __forceinline__ void xcd_stride(int32_t n, int32_t& first, int32_t& s
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) batch_branch_kernel(BatchArgs a) {
-    __shared__ double stage[kRec * kBlock];
+    __shared__ double stage[kRecStride * kBlock];
     int32_t it, step, end;
     xcd_stride(a.n_items, it, step, end);
     for (; it < end; it += step) {
@@ -888,7 +1015,7 @@ __global__ void __launch_bounds__(kBlock) batch_branch_kernel(BatchArgs a) {
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) batch_bus_kernel(BatchArgs a) {
-    __shared__ double lds[kRec * kBlock];
+    __shared__ double lds[kRecStride * kBlock];
     int32_t it, step, end;
     xcd_stride(a.n_items, it, step, end);
     for (; it < end; it += step) {
@@ -901,7 +1028,7 @@ __global__ void __launch_bounds__(kBlock) batch_bus_kernel(BatchArgs a) {
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) batch_branch_flat(BatchArgs a) {
-    __shared__ double stage[kRec * kBlock];
+    __shared__ double stage[kRecStride * kBlock];
     const int32_t it = xcd_item(blockIdx.x, gridDim.x);
     if (it >= a.n_items) return;
     const BatchItem w = a.items[it];
@@ -910,8 +1037,8 @@ __global__ void __launch_bounds__(kBlock) batch_branch_flat(BatchArgs a) {
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) batch_bus_flat(BatchArgs a) {
-    __shared__ double lds[kRec * kBlock];
+__global__ void __launch_bounds__(kBlock, 5) batch_bus_flat(BatchArgs a) {
+    __shared__ double lds[kRecStride * kBlock];
     const int32_t it = xcd_item(blockIdx.x, gridDim.x);
     if (it >= a.n_items) return;
     const BatchItem w = a.items[it];
@@ -926,7 +1053,7 @@ SetGrid plan_set(const DevModel& m, const EvalOut& o, int32_t mode) {
     if (mode == 0 && (any || o.f)) g.n_gen1 = m.ngchunks * (any ? m.nrep : m.npg);  // f alone: pg replicas
     g.n_big = any ? m.nbig * m.nrep : 0;
     g.n_wave = any ? m.nwaves * m.nrep : 0;
-    g.n_obj = (mode == 0 && o.f) ? 1 : 0;
+    g.n_obj = (mode == 0 && o.f && !o.single) ? 1 : 0;  // a single launch sums f by ticket
     if (mode == 1) {
         g.gen_per_item = (m.npg == 1 && m.nrep > 1) ? 1 : 0;
         g.n_gen2 = g.gen_per_item ? m.G : m.ngchunks * m.nrep;
@@ -934,8 +1061,15 @@ SetGrid plan_set(const DevModel& m, const EvalOut& o, int32_t mode) {
     return g;
 }
 
-hipError_t launch_eval_set(const DevModel& m, const EvalOut& o, hipStream_t stream) {
+hipError_t launch_eval_set(const DevModel& m, const EvalOut& o_in, hipStream_t stream) {
+    EvalOut o = o_in;
+    o.single = m.single;  // plain launches of small models take the single-launch shape
     const SetGrid g = plan_set(m, o, 0);
+    if (o.single) {
+        const int32_t n = g.phase1() + g.phase2();
+        if (n > 0) hipLaunchKernelGGL(set_kernel_single, dim3(n), dim3(kBlock), 0, stream, m, o, g);
+        return hipGetLastError();
+    }
     if (g.phase1() > 0) hipLaunchKernelGGL(branch_kernel<0>, dim3(g.phase1()), dim3(kBlock), 0, stream, m, o, g);
     if (g.phase2() > 0) hipLaunchKernelGGL(bus_kernel<0>, dim3(g.phase2()), dim3(kBlock), 0, stream, m, o, g);
     return hipGetLastError();
@@ -971,7 +1105,7 @@ void* batch_kernel_fn(int phase, int mode, bool flat) {
 
 size_t scratch_bytes(const DevModel& m) {
     const size_t parts = ((sizeof(double) * (size_t)m.ngchunks * m.npg) + 255) & ~size_t(255);
-    return parts + sizeof(double) * (size_t)kRec * 2 * m.nrep * m.L;
+    return parts + 256 + sizeof(double) * (size_t)kRecStride * 2 * m.nrep * m.L;
 }
 
 }  // namespace opf

@@ -339,6 +339,13 @@ void build_slots(HostModel& hm) {
     }
     pad_wave();
     hm.nwaves = (int32_t)(hm.slots.size() / (8 * kWaveLanes));
+    const size_t nslot = (size_t)hm.nwaves * kWaveLanes;
+    hm.slot_coef.assign(nslot * 8, 0.0);
+    for (size_t q = 0; q < nslot; q++) {
+        if ((hm.slots[8 * q] & 3) != SK_EDGE) continue;
+        const int32_t l = hm.slots[8 * q + 1];
+        for (int k = 0; k < 8; k++) hm.slot_coef[8 * q + k] = hm.coef[(size_t)k * L + l];
+    }
 }
 
 void fill_pattern(const HostModel& hm, int32_t* jr, int32_t* jc, int32_t* hr, int32_t* hc) {

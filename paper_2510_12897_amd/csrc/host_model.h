@@ -65,6 +65,10 @@ struct HostModel {
     // SlotField); output positions are relative to the replica's block.
     std::vector<int32_t> slots;                // [nwaves * kWaveLanes * 8]
     int32_t nwaves = 0;
+    // The 8 admittance terms of each half-edge lane's branch, in slot order
+    // (zero on other lanes): a bus wave that recomputes its half-edge terms
+    // reads them coalesced.
+    std::vector<double> slot_coef;             // [nwaves * kWaveLanes * 8]
     std::vector<int32_t> big_bus;              // buses whose segment does not fit a wave
 };
 

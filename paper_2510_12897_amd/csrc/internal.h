@@ -67,7 +67,7 @@ constexpr uint64_t kBatchMagic = 0x4f50464241544348ull;  // "OPFBATCH"
 
 // Offsets of the model arrays inside a packed arena.
 struct ModelOffsets {
-    size_t f_bus, t_bus, coef, rate2, slots, big_bus, adj_ptr, he, he_grp, nlo, ndist,
+    size_t f_bus, t_bus, coef, rate2, slots, slot_coef, big_bus, adj_ptr, he, he_grp, nlo, ndist,
         hva_off, hvm_off, jbal_off, gen_ptr, gen_list, gs, bs, pd, qd, c2, c1, c0, gen_bus, ref_bus, ref_ptr,
         ref_list, outage;
 };
@@ -76,8 +76,8 @@ ModelOffsets pack_model(Packer& pk, const opf::HostModel& hm);
 // Device descriptor of a packed model; its scratch pointers are set by
 // attach_scratch.
 opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets& o);
-// Point the descriptor's objective partials and half-edge records at
-// `scratch` (scratch_bytes(d) bytes).
+// Point the descriptor's objective partials, ticket and half-edge records
+// at `scratch` (scratch_bytes(d) bytes, the ticket zeroed).
 void attach_scratch(opf::DevModel& d, char* scratch);
 
 }  // namespace opf_internal

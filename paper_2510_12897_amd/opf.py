@@ -81,6 +81,7 @@ def lib():
     P = ctypes.POINTER
     sig = {
         "opf_last_error": ([], ctypes.c_char_p),
+        "opf_set_single_launch_limit": ([ctypes.c_int64], ctypes.c_int),
         "opf_case_validate": ([P(_Case), P(_Opts)], ctypes.c_int),
         "opf_case_dims": ([P(_Case), P(_Opts), _i64p, _i64p, _i64p, _i64p], ctypes.c_int),
         "opf_case_structure": ([P(_Case), P(_Opts), _vp, _vp, _vp, _vp], ctypes.c_int),
@@ -129,6 +130,12 @@ def lib():
         fn.restype = res
     _lib = L
     return L
+
+
+def set_single_launch_limit(waves: int):
+    """Models created afterwards evaluate a callback set in one launch when it
+    is at most `waves` work items (0: always two launches)."""
+    _check(lib().opf_set_single_launch_limit(int(waves)))
 
 
 def _check(rc: int):

@@ -44,6 +44,18 @@ def _cases():
 
 CASES = list(_cases())
 
+# launch shapes: small models evaluate a set in one launch (bus items
+# recompute the branch terms they need); limit 0 forces the two-launch
+# shape (branch items leave records) on every model
+SHAPES = {"single": 4096, "two": 0}
+
+
+@pytest.fixture(params=list(SHAPES))
+def shape(request):
+    opf.set_single_launch_limit(SHAPES[request.param])
+    yield request.param
+    opf.set_single_launch_limit(4096)
+
 
 def to_dev(a):
     return torch.as_tensor(np.ascontiguousarray(a), device=DEV)
@@ -75,19 +87,19 @@ def check_against_oracle(model, cs, opts, x, y, sigma, tag):
 
 
 @pytest.mark.parametrize("name,cs,opts", CASES, ids=[c[0] for c in CASES])
-def test_callbacks_match_oracle(name, cs, opts):
+def test_callbacks_match_oracle(name, cs, opts, shape):
     T, K = opts.get("n_periods", 1), opts.get("n_cont", 0)
     model = opf.Model(cs, **opts)
     for seed, sigma in ((100, 1.0), (101, 0.37), (102, 0.0)):
         x = synth.point(cs, seed, n_periods=T, n_cont=K)
         y = synth.multipliers(model.m, seed)
-        check_against_oracle(model, cs, opts, x, y, sigma, f"{name}/seed{seed}")
+        check_against_oracle(model, cs, opts, x, y, sigma, f"{name}/seed{seed}/{shape}")
     model.close()
 
 
 @pytest.mark.parametrize("name,cs,opts", CASES[:4] + CASES[5:8], ids=[c[0] for c in CASES[:4] + CASES[5:8]])
-def test_separate_callbacks_equal_fused_set(name, cs, opts):
-    say(f"[separate] {name}")
+def test_separate_callbacks_equal_fused_set(name, cs, opts, shape):
+    say(f"[separate] {name} ({shape} launch)")
     T, K = opts.get("n_periods", 1), opts.get("n_cont", 0)
     model = opf.Model(cs, **opts)
     x = to_dev(synth.point(cs, 7, n_periods=T, n_cont=K))
@@ -146,9 +158,9 @@ def test_jtprod_matches_oracle():
         model.close()
 
 
-def test_runs_are_bitwise_deterministic():
+def test_runs_are_bitwise_deterministic(shape):
     cs = synth.network(3000, 4050, 600, 77, variant=True)
-    say("[determinism] 3000-bus")
+    say(f"[determinism] 3000-bus ({shape} launch)")
     model = opf.Model(cs)
     x = to_dev(synth.point(cs, 1))
     y = to_dev(synth.multipliers(model.m, 1))
@@ -159,6 +171,29 @@ def test_runs_are_bitwise_deterministic():
         for u, w in zip(a, b):
             assert torch.equal(u, w)
     model.close()
+
+
+def test_launch_shapes_agree_to_rounding():
+    """The single launch (bus items recompute the branch terms) and the two
+    launches (records) agree within the tolerance on one model."""
+    name, cs, opts = CASES[-1]
+    x, y = synth.point(cs, 5), None
+    outs = []
+    for lim in (4096, 0):
+        opf.set_single_launch_limit(lim)
+        model = opf.Model(cs, **opts)
+        y = synth.multipliers(model.m, 5)
+        outs.append([t.cpu().numpy() for t in model.eval_set(to_dev(x), to_dev(y), 0.8)])
+        model.close()
+    opf.set_single_launch_limit(4096)
+    res = O.evaluate(cs, x, y, 0.8, **opts)
+    for a, b, sc in zip(outs[0][1:], outs[1][1:], (np.abs(res["g"]), res["cscale"], res["jscale"], res["hscale"])):
+        assert_close(a, b, sc, what="single vs two launches")
+
+
+def test_single_launch_limit_rejects_negative():
+    with pytest.raises(opf.OPFError):
+        opf.set_single_launch_limit(-1)
 
 
 def test_bad_arguments_raise():
