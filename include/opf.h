@@ -145,15 +145,16 @@ typedef struct opf_model_s *opf_model;
 void opf_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
                        void (*release)(void *ptr, void *ctx), void *ctx);
 
-/* Launch shape of models created afterwards.  A model whose callback set is
- * at most `waves` 64-lane work items (summed over replicas) evaluates a set
- * in ONE launch, its bus items recomputing the branch terms they need (a
- * small set is latency-bound); larger models use two launches (branch items
- * leave per-half-edge records that bus items read).  A model keeps its
- * shape for life, and opf_eval_set and opf_batch_eval give bitwise the same
- * results for it; the two shapes agree to rounding.  J^T v always uses two
- * launches.  0 disables the single launch; the default is 4096.  OPF_E_ARG
- * for a negative limit. */
+/* Launch shape of opf_eval_set for models created afterwards.  A model
+ * whose callback set is at most `waves` 64-lane work items (summed over
+ * replicas) evaluates a set in ONE launch, its bus items recomputing the
+ * branch terms they need (a small set is latency-bound); larger models use
+ * two launches (branch items leave per-half-edge records that bus items
+ * read).  A model keeps its shape for life; repeated calls are bitwise
+ * reproducible.  Batches (opf_batch_eval) and J^T v always use the two
+ * launches, so a one-launch model's plain and batched results agree to
+ * rounding, a two-launch model's bitwise.  0 disables the single launch; the
+ * default is 4096.  OPF_E_ARG for a negative limit. */
 int opf_set_single_launch_limit(int64_t waves);
 
 /* Validate, derive branch admittance terms, adjacency and pattern on the
@@ -166,6 +167,11 @@ int opf_model_create(const opf_case *cs, const opf_opts *opts, int device, opf_m
 int opf_model_destroy(opf_model model);
 
 int opf_model_dims(opf_model model, int64_t *n, int64_t *m, int64_t *nnzj, int64_t *nnzh);
+
+/* Launch shape of opf_eval_set for this model (see
+ * opf_set_single_launch_limit): *launches = 1 or 2, *items = the 64-lane
+ * work items of one set summed over replicas.  Either pointer may be NULL. */
+int opf_model_launches(opf_model model, int32_t *launches, int64_t *items);
 
 /* Offset and length of a variable or constraint block, the named handles
  * the paper's model builder returns (vars, cons; Sec. III-C1). */
@@ -282,11 +288,26 @@ int opf_batch_flows(opf_batch batch, double *X, void *stream);
 int prox_gemm_bf16(int variant, const float *A, int lda, const float *B, int ldb, float *C, int ldc, int M, int N,
                    int K, const float *bias, float *act, int accumulate, void *stream);
 
+/* prox_gemm_bf16 with the K range cut into `splits` (1..64) parts of whole
+ * 64-wide k tiles, computed by separate workgroups into work (splits * M * N
+ * floats, 16-byte aligned, caller-owned, contents overwritten), then summed
+ * part 0 first, with the bias / GELU / accumulate epilogue of prox_gemm_bf16.
+ * For products whose M x N tiles alone cannot fill the device (weight
+ * gradients, K = batch size).  splits = 1 is prox_gemm_bf16 (work unused). */
+int prox_gemm_bf16_splitk(int variant, const float *A, int lda, const float *B, int ldb, float *C, int ldc, int M,
+                          int N, int K, const float *bias, float *act, int accumulate, int splits, float *work,
+                          void *stream);
+
+/* A split count for prox_gemm_bf16_splitk: the smallest power of two (at
+ * most 16) that gives 256 or more 128 x 128 workgroups while each part keeps
+ * at least four k tiles.  Negative sizes: OPF_E_ARG. */
+int prox_gemm_splits(int M, int N, int K);
+
 /* dpre = dact * GELU'(pre), n elements. */
 int prox_gelu_bwd(const float *pre, const float *dact, float *dpre, int64_t n, void *stream);
 
 /* out[j] = scale * sum_i X[i, j] for X [M, N], summed in a fixed order;
- * work holds ((M + 255) / 256) * N floats. */
+ * work holds ((M + 127) / 128) * N floats. */
 int prox_colsum(const float *X, int M, int N, float *work, float *out, float scale, void *stream);
 
 /* One Adam step (Kingma and Ba 2015, bias-corrected) on n parameters;

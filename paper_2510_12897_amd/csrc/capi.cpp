@@ -339,6 +339,15 @@ int opf_model_dims(opf_model m, int64_t* n, int64_t* mm, int64_t* nnzj, int64_t*
     return OPF_OK;
 }
 
+int opf_model_launches(opf_model m, int32_t* launches, int64_t* items) {
+    if (int rc = check_model(m)) return rc;
+    const opf::DevModel& d = m->dm;
+    if (launches) *launches = d.single ? 1 : 2;
+    if (items)
+        *items = (int64_t)d.nrep * ((int64_t)d.nbchunks + d.nwaves + d.nbig) + (int64_t)d.ngchunks * d.nrep;
+    return OPF_OK;
+}
+
 int opf_model_blocks(opf_model m, int32_t which, int64_t* offset, int64_t* len) {
     if (int rc = check_model(m)) return rc;
     const opf::Layout& ly = m->hm.ly;

@@ -56,10 +56,13 @@ opf::ProxRows rows_of(opf_model m) {
 
 extern "C" {
 
-int prox_gemm_bf16(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N,
-                   int K, const float* bias, float* act, int accumulate, void* stream) {
+namespace {
+int gemm_checked(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N, int K,
+                 const float* bias, float* act, int accumulate, int splits, float* work, void* stream,
+                 const char* what) {
     if (variant < 0 || variant > 3) return set_err(OPF_E_ARG, "variant must be 0..3");
     if (!A || !B || !C) return set_err(OPF_E_ARG, "A, B and C must be non-NULL");
+    if (M < 0 || N < 0 || K < 0) return set_err(OPF_E_ARG, "negative dimension");
     if (!mult4(M) || !mult4(N) || !mult4(K) || !mult4(lda) || !mult4(ldb) || !mult4(ldc))
         return set_err(OPF_E_ARG, "dimensions and leading dimensions must be multiples of 4");
     if (!aligned16(A) || !aligned16(B) || !aligned16(C) || (act && !aligned16(act)))
@@ -67,10 +70,32 @@ int prox_gemm_bf16(int variant, const float* A, int lda, const float* B, int ldb
     const bool a_k = variant == 0 || variant == 1, b_k = variant == 0 || variant == 3;
     if (lda < (a_k ? K : M) || ldb < (b_k ? K : N) || ldc < N)
         return set_err(OPF_E_ARG, "a leading dimension is smaller than its row");
+    if (splits < 1 || splits > 64) return set_err(OPF_E_ARG, "splits must be 1..64");
+    if (splits > 1 && (!work || !aligned16(work)))
+        return set_err(OPF_E_ARG, "splits > 1 needs a 16-byte aligned work buffer");
     if (M == 0 || N == 0) return OPF_OK;
-    return launched(opf::prox_gemm(variant, A, lda, B, ldb, C, ldc, M, N, K, bias, act, accumulate,
+    return launched(opf::prox_gemm(variant, A, lda, B, ldb, C, ldc, M, N, K, bias, act, accumulate, splits, work,
                                    static_cast<hipStream_t>(stream)),
-                    "prox_gemm_bf16 launch");
+                    what);
+}
+}  // namespace
+
+int prox_gemm_bf16(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N,
+                   int K, const float* bias, float* act, int accumulate, void* stream) {
+    return gemm_checked(variant, A, lda, B, ldb, C, ldc, M, N, K, bias, act, accumulate, 1, nullptr, stream,
+                        "prox_gemm_bf16 launch");
+}
+
+int prox_gemm_bf16_splitk(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M,
+                          int N, int K, const float* bias, float* act, int accumulate, int splits, float* work,
+                          void* stream) {
+    return gemm_checked(variant, A, lda, B, ldb, C, ldc, M, N, K, bias, act, accumulate, splits, work, stream,
+                        "prox_gemm_bf16_splitk launch");
+}
+
+int prox_gemm_splits(int M, int N, int K) {
+    if (M < 0 || N < 0 || K < 0) return set_err(OPF_E_ARG, "negative dimension");
+    return opf::prox_gemm_splits(M, N, K);
 }
 
 int prox_gelu_bwd(const float* pre, const float* dact, float* dpre, int64_t n, void* stream) {

@@ -25,8 +25,11 @@ struct ProxRows {
 
 // variant: 0 A k-contiguous, B k-contiguous; 1 A k-contiguous, B j-contiguous;
 //          2 A i-contiguous, B j-contiguous; 3 A i-contiguous, B k-contiguous.
+// splits > 1: the k range in that many parts into work (splits * M * N
+// floats), then summed in order with the epilogue.
 hipError_t prox_gemm(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N,
-                     int K, const float* bias, float* act, int accumulate, hipStream_t s);
+                     int K, const float* bias, float* act, int accumulate, int splits, float* work, hipStream_t s);
+int prox_gemm_splits(int M, int N, int K);
 hipError_t prox_gelu_bwd(const float* pre, const float* dact, float* dpre, int64_t n, hipStream_t s);
 hipError_t prox_colsum(const float* X, int M, int N, float* part, float* out, float scale, hipStream_t s);
 int prox_colsum_chunks(int M);

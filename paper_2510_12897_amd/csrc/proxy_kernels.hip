@@ -25,9 +25,11 @@ namespace {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-constexpr int BM = 128, BN = 128, BK = 32;
-constexpr int LDK = BK + 8;  // LDS row stride (bf16) with padding against bank conflicts
+constexpr int BM = 128, BN = 128, BK = 64;
+constexpr int TILE = BM * BK;  // BF16 values of one operand tile (BM == BN)
 constexpr int GEMM_THREADS = 256;
+constexpr int kXcd = 8;  // accelerator complex dies, each with its own L2
+static_assert(BM == BN, "one tile loader serves both operands");
 
 __device__ __forceinline__ __bf16 to_bf16(float f) { return (__bf16)f; }  // round to nearest even
 
@@ -37,69 +39,104 @@ __device__ __forceinline__ float gelu_grad(float x) {
     return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
 }
 
-// Loads one BM x BK tile of A (rows i, columns k) or one BN x BK tile of B^T
-// (rows j, columns k) as 16 floats per thread, zero outside the matrix.
-// KCONT: k is the contiguous memory index (row stride ld); otherwise the row
-// index is contiguous (k stride ld).
-template <bool KCONT>
-__device__ __forceinline__ void load_tile(const float* __restrict__ P, int ld, int rows, int K, int r0, int k0,
-                                          float4 (&reg)[4]) {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        int r, k;
-        if (KCONT) {
-            r = r0 + t / 8 + 32 * q;
-            k = k0 + (t % 8) * 4;
-        } else {
-            k = k0 + t / 32 + 8 * q;
-            r = r0 + (t % 32) * 4;
-        }
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (KCONT) {
-            if (r < rows && k < K) v = *reinterpret_cast<const float4*>(P + (size_t)r * ld + k);
-        } else {
-            if (k < K && r < rows) v = *reinterpret_cast<const float4*>(P + (size_t)k * ld + r);
-        }
-        reg[q] = v;
-    }
+// LDS operand tile: 128 rows (i of A, j of B) of BK = 64 BF16 values, eight
+// 16-byte chunks of 8 k values per row.  Chunk c of row r sits at position
+// c ^ ((r >> 1) & 7): the fragment reads (16 consecutive rows, one chunk) and
+// the row-wise tile stores then fall on distinct banks.
+__device__ __forceinline__ int lds_at(int r, int c) { return r * BK + ((c ^ ((r >> 1) & 7)) << 3); }
+
+__device__ __forceinline__ bf16x8 pack8(float a0, float a1, float a2, float a3, float a4, float a5, float a6,
+                                        float a7) {
+    return (bf16x8){to_bf16(a0), to_bf16(a1), to_bf16(a2), to_bf16(a3),
+                    to_bf16(a4), to_bf16(a5), to_bf16(a6), to_bf16(a7)};
+}
+
+// Global loads of one 128 x BK operand tile (rows r0.., k0..), 32 floats per
+// thread, zero outside rows < nrows, k < kend.  Sizes are multiples of 4, so
+// each float4 is wholly inside or wholly outside.
+//  KCONT: element (r, k) at P[r * ld + k]; thread t holds row t / 8 + 32 q,
+//         k = 8 (t % 8) .. + 8 as v[2q], v[2q + 1].
+//  else:  element (r, k) at P[k * ld + r]; thread t holds rows 4 (t % 32) .. + 4
+//         at k = 8 (t / 32) + kk as v[kk] (a coalesced row segment per k).
+__device__ __forceinline__ float4 guarded_load(const float* __restrict__ base, const float* p, bool ok) {
+    // an out-of-range load reads the (valid) first element and is discarded
+    const float4 t = *reinterpret_cast<const float4*>(ok ? p : base);
+    return ok ? t : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 template <bool KCONT>
-__device__ __forceinline__ void store_tile(__bf16* S, const float4 (&reg)[4]) {
+__device__ __forceinline__ void load_tile(const float* __restrict__ P, int ld, int nrows, int kend, int r0, int k0,
+                                          float4 (&v)[8]) {
     const int t = threadIdx.x;
+    if (KCONT) {
+        const int k = k0 + (t % 8) * 8;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const float4 v = reg[q];
-        if (KCONT) {
-            const int r = t / 8 + 32 * q, k = (t % 8) * 4;
-            __bf16* d = S + r * LDK + k;
-            d[0] = to_bf16(v.x);
-            d[1] = to_bf16(v.y);
-            d[2] = to_bf16(v.z);
-            d[3] = to_bf16(v.w);
-        } else {
-            const int k = t / 32 + 8 * q, r = (t % 32) * 4;
-            S[(r + 0) * LDK + k] = to_bf16(v.x);
-            S[(r + 1) * LDK + k] = to_bf16(v.y);
-            S[(r + 2) * LDK + k] = to_bf16(v.z);
-            S[(r + 3) * LDK + k] = to_bf16(v.w);
+        for (int q = 0; q < 4; q++) {
+            const int r = r0 + t / 8 + 32 * q;
+            const float* p = P + (size_t)r * ld + k;
+            v[2 * q] = guarded_load(P, p, r < nrows && k < kend);
+            v[2 * q + 1] = guarded_load(P, p + 4, r < nrows && k + 4 < kend);
         }
+    } else {
+        const int r = r0 + (t % 32) * 4;
+#pragma unroll
+        for (int kk = 0; kk < 8; kk++) {
+            const int k = k0 + (t / 32) * 8 + kk;
+            v[kk] = guarded_load(P, P + (size_t)k * ld + r, r < nrows && k < kend);
+        }
+    }
+}
+
+// Rounds the loaded tile to BF16 and writes it to LDS as 16-byte row chunks
+// (the i-contiguous layout is transposed in registers).
+template <bool KCONT>
+__device__ __forceinline__ void store_tile(__bf16* S, const float4 (&v)[8]) {
+    const int t = threadIdx.x;
+    if (KCONT) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const float4 a = v[2 * q], b = v[2 * q + 1];
+            *reinterpret_cast<bf16x8*>(S + lds_at(t / 8 + 32 * q, t % 8)) =
+                pack8(a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w);
+        }
+    } else {
+        const int r = (t % 32) * 4, c = t / 32;
+        *reinterpret_cast<bf16x8*>(S + lds_at(r + 0, c)) =
+            pack8(v[0].x, v[1].x, v[2].x, v[3].x, v[4].x, v[5].x, v[6].x, v[7].x);
+        *reinterpret_cast<bf16x8*>(S + lds_at(r + 1, c)) =
+            pack8(v[0].y, v[1].y, v[2].y, v[3].y, v[4].y, v[5].y, v[6].y, v[7].y);
+        *reinterpret_cast<bf16x8*>(S + lds_at(r + 2, c)) =
+            pack8(v[0].z, v[1].z, v[2].z, v[3].z, v[4].z, v[5].z, v[6].z, v[7].z);
+        *reinterpret_cast<bf16x8*>(S + lds_at(r + 3, c)) =
+            pack8(v[0].w, v[1].w, v[2].w, v[3].w, v[4].w, v[5].w, v[6].w, v[7].w);
     }
 }
 
 // C[M,N] = A[M,K] B[K,N] (+ bias[N], then optionally GELU into act).
 //  A_KCONT: A(i,k) = A[i*lda + k], else A[k*lda + i]
 //  B_KCONT: B(k,j) = B[j*ldb + k], else B[k*ldb + j]
+// Workgroup (x, y, z) computes the 128 x 128 tile (y, x) over the k range
+// [z kchunk, (z + 1) kchunk); with work != NULL it writes that partial product
+// to work[z] (row-major [M, N]) instead of the epilogue.  Four waves of 64 x 64,
+// double-buffered LDS (one barrier per k tile), the next tile's global loads
+// in flight during the matrix-core work on the current one.
 template <bool A_KCONT, bool B_KCONT>
 __global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const float* __restrict__ A, int lda,
                                                             const float* __restrict__ B, int ldb, float* __restrict__ C,
-                                                            int ldc, int M, int N, int K,
+                                                            int ldc, int M, int N, int K, int kchunk,
                                                             const float* __restrict__ bias, float* __restrict__ act,
-                                                            int accumulate) {
-    __shared__ __bf16 As[BM * LDK];
-    __shared__ __bf16 Bs[BN * LDK];
-    const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
+                                                            int accumulate, float* __restrict__ work) {
+    __shared__ __bf16 lds[2][2][TILE];  // [buffer][A, B]
+    // Workgroups are dealt to the XCDs round-robin; renumber them so that
+    // each XCD takes one contiguous range of tiles (n fastest, then m, then
+    // the k part): its rows of A and the shared B stay in its own L2.
+    const int nx = gridDim.x, ny = gridDim.y, nb = nx * ny * gridDim.z;
+    const int bl = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+    const int q = nb / kXcd, rem = nb % kXcd, xcd = bl % kXcd;
+    const int tile = xcd * q + min(xcd, rem) + bl / kXcd;
+    const int i0 = (tile / nx) % ny * BM, j0 = tile % nx * BN;
+    const int kz = tile / (nx * ny);
+    const int kb = kz * kchunk, ke = min(K, kb + kchunk);
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const int wi = (wave / 2) * 64, wj = (wave % 2) * 64;
     f32x16 acc[2][2];
@@ -110,37 +147,64 @@ __global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const float* __restr
 #pragma unroll
             for (int v = 0; v < 16; v++) acc[a][b][v] = 0.f;
 
-    float4 ra[4], rb[4];
-    load_tile<A_KCONT>(A, lda, M, K, i0, 0, ra);
-    load_tile<B_KCONT>(B, ldb, N, K, j0, 0, rb);
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        __syncthreads();
-        store_tile<A_KCONT>(As, ra);
-        store_tile<B_KCONT>(Bs, rb);
-        __syncthreads();
-        if (k0 + BK < K) {  // next tile's global loads overlap the matrix-core work
-            load_tile<A_KCONT>(A, lda, M, K, i0, k0 + BK, ra);
-            load_tile<B_KCONT>(B, ldb, N, K, j0, k0 + BK, rb);
+    float4 ra[8], rb[8];
+    if (kb < ke) {
+        load_tile<A_KCONT>(A, lda, M, ke, i0, kb, ra);
+        load_tile<B_KCONT>(B, ldb, N, ke, j0, kb, rb);
+        store_tile<A_KCONT>(lds[0][0], ra);
+        store_tile<B_KCONT>(lds[0][1], rb);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+        const bool more = k0 + BK < ke;
+        if (more) {
+            load_tile<A_KCONT>(A, lda, M, ke, i0, k0 + BK, ra);
+            load_tile<B_KCONT>(B, ldb, N, ke, j0, k0 + BK, rb);
         }
+        const __bf16* As = lds[cur][0];
+        const __bf16* Bs = lds[cur][1];
 #pragma unroll
-        for (int ks = 0; ks < BK; ks += 16) {
-            const int kk = ks + (lane / 32) * 8;
+        for (int ks = 0; ks < BK / 16; ks++) {
+            const int c = ks * 2 + lane / 32;
             bf16x8 fa[2], fb[2];
 #pragma unroll
             for (int a = 0; a < 2; a++)
-                fa[a] = *reinterpret_cast<const bf16x8*>(As + (wi + a * 32 + lane % 32) * LDK + kk);
+                fa[a] = *reinterpret_cast<const bf16x8*>(As + lds_at(wi + a * 32 + lane % 32, c));
 #pragma unroll
             for (int b = 0; b < 2; b++)
-                fb[b] = *reinterpret_cast<const bf16x8*>(Bs + (wj + b * 32 + lane % 32) * LDK + kk);
+                fb[b] = *reinterpret_cast<const bf16x8*>(Bs + lds_at(wj + b * 32 + lane % 32, c));
 #pragma unroll
             for (int a = 0; a < 2; a++)
 #pragma unroll
                 for (int b = 0; b < 2; b++)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
         }
+        if (more) {  // the other buffer: every wave passed the last barrier after reading it
+            store_tile<A_KCONT>(lds[cur ^ 1][0], ra);
+            store_tile<B_KCONT>(lds[cur ^ 1][1], rb);
+        }
+        __syncthreads();
+        cur ^= 1;
     }
-    // epilogue: lane holds column j = lane % 32 of each 32x32 tile, rows
+    // lane holds column j = lane % 32 of each 32x32 tile, rows
     // (v / 4) * 8 + (lane / 32) * 4 + v % 4
+    if (work) {
+        float* W = work + (size_t)kz * M * N;
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 2; b++) {
+                const int j = j0 + wj + b * 32 + lane % 32;
+                if (j >= N) continue;
+#pragma unroll
+                for (int v = 0; v < 16; v++) {
+                    const int i = i0 + wi + a * 32 + (v / 4) * 8 + (lane / 32) * 4 + v % 4;
+                    if (i < M) W[(size_t)i * N + j] = acc[a][b][v];
+                }
+            }
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
@@ -161,31 +225,77 @@ __global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const float* __restr
         }
 }
 
+// Split-K epilogue: C = sum over the parts in order (part 0 first) + bias
+// (+ C when accumulating), GELU into act; four columns per thread.
+__global__ void splitk_sum_kernel(const float* __restrict__ work, int splits, int M, int N, float* __restrict__ C,
+                                  int ldc, const float* __restrict__ bias, float* __restrict__ act, int accumulate) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n4 = N / 4;
+    if (idx >= (int64_t)M * n4) return;
+    const int i = (int)(idx / n4), j = (int)(idx % n4) * 4;
+    const size_t mn = (size_t)M * N;
+    const float* w = work + (size_t)i * N + j;
+    float4 s = *reinterpret_cast<const float4*>(w);
+    for (int z = 1; z < splits; z++) {
+        const float4 t = *reinterpret_cast<const float4*>(w + z * mn);
+        s.x += t.x;
+        s.y += t.y;
+        s.z += t.z;
+        s.w += t.w;
+    }
+    if (bias) {
+        s.x += bias[j];
+        s.y += bias[j + 1];
+        s.z += bias[j + 2];
+        s.w += bias[j + 3];
+    }
+    float4* cp = reinterpret_cast<float4*>(C + (size_t)i * ldc + j);
+    if (accumulate) {
+        const float4 c = *cp;
+        s.x += c.x;
+        s.y += c.y;
+        s.z += c.z;
+        s.w += c.w;
+    }
+    *cp = s;
+    if (act) *reinterpret_cast<float4*>(act + (size_t)i * ldc + j) = make_float4(gelu(s.x), gelu(s.y), gelu(s.z), gelu(s.w));
+}
+
 __global__ void gelu_bwd_kernel(const float* __restrict__ pre, const float* __restrict__ dact,
                                 float* __restrict__ dpre, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dpre[i] = dact[i] * gelu_grad(pre[i]);
 }
 
-// Column sums of a row-major [M, N] matrix, deterministic: partial sums over
-// fixed 256-row chunks, then the chunks in order.
-constexpr int COLSUM_ROWS = 256;
-__global__ void colsum_partial_kernel(const float* __restrict__ X, int M, int N, float* __restrict__ part) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = blockIdx.y;
-    if (j >= N) return;
-    const int i0 = c * COLSUM_ROWS, i1 = min(i0 + COLSUM_ROWS, M);
-    float s = 0.f;
-    for (int i = i0; i < i1; i++) s += X[(size_t)i * N + j];
-    part[(size_t)c * N + j] = s;
+// Column sums of a row-major [M, N] matrix, deterministic.  Pass 1: per
+// 128-row chunk and 64-column stripe, four row groups (rows g, g + 4, ...)
+// each sum in row order, then the four groups in order.  Pass 2: the chunk
+// sums of each column the same way (chunks g, g + 4, ..., then the groups).
+constexpr int COLSUM_ROWS = 128;
+__global__ void __launch_bounds__(256) colsum_partial_kernel(const float* __restrict__ X, int M, int N,
+                                                             float* __restrict__ part) {
+    __shared__ float s[4][64];
+    const int c = threadIdx.x % 64, g = threadIdx.x / 64;
+    const int j = blockIdx.x * 64 + c;
+    const int i0 = blockIdx.y * COLSUM_ROWS, i1 = min(i0 + COLSUM_ROWS, M);
+    float acc = 0.f;
+    if (j < N)
+        for (int i = i0 + g; i < i1; i += 4) acc += X[(size_t)i * N + j];
+    s[g][c] = acc;
+    __syncthreads();
+    if (g == 0 && j < N) part[(size_t)blockIdx.y * N + j] = ((s[0][c] + s[1][c]) + s[2][c]) + s[3][c];
 }
-__global__ void colsum_final_kernel(const float* __restrict__ part, int chunks, int N, float* __restrict__ out,
-                                    float scale) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    float s = 0.f;
-    for (int c = 0; c < chunks; c++) s += part[(size_t)c * N + j];
-    out[j] = s * scale;
+__global__ void __launch_bounds__(256) colsum_final_kernel(const float* __restrict__ part, int chunks, int N,
+                                                           float* __restrict__ out, float scale) {
+    __shared__ float s[4][64];
+    const int c = threadIdx.x % 64, g = threadIdx.x / 64;
+    const int j = blockIdx.x * 64 + c;
+    float acc = 0.f;
+    if (j < N)
+        for (int k = g; k < chunks; k += 4) acc += part[(size_t)k * N + j];
+    s[g][c] = acc;
+    __syncthreads();
+    if (g == 0 && j < N) out[j] = (((s[0][c] + s[1][c]) + s[2][c]) + s[3][c]) * scale;
 }
 
 // Adam (Kingma and Ba, 2015) with bias correction; FP32 state.
@@ -374,14 +484,30 @@ hipError_t prox_vjp_sum(const double* gX1, const double* gX2, const double* gObj
     return hipGetLastError();
 }
 
+int prox_gemm_splits(int M, int N, int K) {
+    // enough workgroups for one per compute unit, each part at least 4 k tiles
+    const int64_t blocks = (int64_t)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+    int s = 1;
+    while (blocks * s < 256 && K >= 2 * s * 4 * BK && s < 16) s *= 2;
+    return s;
+}
+
 hipError_t prox_gemm(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N,
-                     int K, const float* bias, float* act, int accumulate, hipStream_t s) {
-    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM), block(GEMM_THREADS);
+                     int K, const float* bias, float* act, int accumulate, int splits, float* work, hipStream_t s) {
+    if (splits < 1) splits = 1;
+    const int kchunk = splits == 1 ? K : ((K + splits - 1) / splits + BK - 1) / BK * BK;
+    float* part = splits == 1 ? nullptr : work;
+    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, splits), block(GEMM_THREADS);
     switch (variant) {
-    case 0: hipLaunchKernelGGL((gemm_kernel<true, true>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, bias, act, accumulate); break;
-    case 1: hipLaunchKernelGGL((gemm_kernel<true, false>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, bias, act, accumulate); break;
-    case 2: hipLaunchKernelGGL((gemm_kernel<false, false>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, bias, act, accumulate); break;
-    default: hipLaunchKernelGGL((gemm_kernel<false, true>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, bias, act, accumulate); break;
+    case 0: hipLaunchKernelGGL((gemm_kernel<true, true>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
+    case 1: hipLaunchKernelGGL((gemm_kernel<true, false>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
+    case 2: hipLaunchKernelGGL((gemm_kernel<false, false>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
+    default: hipLaunchKernelGGL((gemm_kernel<false, true>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
+    }
+    if (splits > 1) {
+        const int64_t tot = (int64_t)M * (N / 4);
+        hipLaunchKernelGGL(splitk_sum_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, work, splits, M, N,
+                           C, ldc, bias, act, accumulate);
     }
     return hipGetLastError();
 }
@@ -394,8 +520,8 @@ hipError_t prox_gelu_bwd(const float* pre, const float* dact, float* dpre, int64
 
 hipError_t prox_colsum(const float* X, int M, int N, float* part, float* out, float scale, hipStream_t s) {
     const int chunks = (M + COLSUM_ROWS - 1) / COLSUM_ROWS;
-    hipLaunchKernelGGL(colsum_partial_kernel, dim3((N + 255) / 256, chunks), dim3(256), 0, s, X, M, N, part);
-    hipLaunchKernelGGL(colsum_final_kernel, dim3((N + 255) / 256), dim3(256), 0, s, part, chunks, N, out, scale);
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3((N + 63) / 64, chunks), dim3(256), 0, s, X, M, N, part);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3((N + 63) / 64), dim3(256), 0, s, part, chunks, N, out, scale);
     return hipGetLastError();
 }
 

@@ -89,6 +89,7 @@ def lib():
         "opf_model_create": ([P(_Case), P(_Opts), ctypes.c_int, P(_vp)], ctypes.c_int),
         "opf_model_destroy": ([_vp], ctypes.c_int),
         "opf_model_dims": ([_vp, _i64p, _i64p, _i64p, _i64p], ctypes.c_int),
+        "opf_model_launches": ([_vp, P(ctypes.c_int32), _i64p], ctypes.c_int),
         "opf_model_blocks": ([_vp, ctypes.c_int32, _i64p, _i64p], ctypes.c_int),
         "opf_bounds": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
         "opf_obj": ([_vp, _vp, _vp, _vp], ctypes.c_int),
@@ -112,6 +113,10 @@ def lib():
         "opf_batch_flows": ([_vp, _vp, _vp], ctypes.c_int),
         "prox_gemm_bf16": ([ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int,
                             ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp], ctypes.c_int),
+        "prox_gemm_bf16_splitk": ([ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int,
+                                   _vp, _vp], ctypes.c_int),
+        "prox_gemm_splits": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "prox_gelu_bwd": ([_vp, _vp, _vp, ctypes.c_int64, _vp], ctypes.c_int),
         "prox_colsum": ([_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_float, _vp], ctypes.c_int),
         "prox_adam": ([_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
@@ -249,6 +254,12 @@ class Model:
         v = [ctypes.c_int64() for _ in range(4)]
         _check(lib().opf_model_dims(h, *[ctypes.byref(z) for z in v]))
         self.n, self.m, self.nnzj, self.nnzh = (z.value for z in v)
+
+    def launch_shape(self):
+        """(launches per callback set: 1 or 2, 64-lane work items per set)."""
+        n, k = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().opf_model_launches(self._h, ctypes.byref(n), ctypes.byref(k)))
+        return n.value, k.value
 
     # -- lifetime
     def close(self):

@@ -48,10 +48,24 @@ def _stream():
     return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
 
 
-def gemm(variant, A, lda, B, ldb, C, ldc, M, N, K, bias=None, act=None, accumulate=False):
-    """C[M,N] (+)= A B on the BF16 matrix cores (layouts: see prox_gemm_bf16)."""
-    _check(lib().prox_gemm_bf16(int(variant), _p(A), int(lda), _p(B), int(ldb), _p(C), int(ldc), int(M), int(N),
-                                int(K), _p(bias), _p(act), int(bool(accumulate)), _stream()))
+def gemm(variant, A, lda, B, ldb, C, ldc, M, N, K, bias=None, act=None, accumulate=False, splits=1, work=None):
+    """C[M,N] (+)= A B on the BF16 matrix cores (layouts: see prox_gemm_bf16);
+    splits > 1 runs the split-K form with `work` (splits * M * N floats)."""
+    if splits == 1:
+        _check(lib().prox_gemm_bf16(int(variant), _p(A), int(lda), _p(B), int(ldb), _p(C), int(ldc), int(M), int(N),
+                                    int(K), _p(bias), _p(act), int(bool(accumulate)), _stream()))
+    else:
+        _check(lib().prox_gemm_bf16_splitk(int(variant), _p(A), int(lda), _p(B), int(ldb), _p(C), int(ldc), int(M),
+                                           int(N), int(K), _p(bias), _p(act), int(bool(accumulate)), int(splits),
+                                           _p(work), _stream()))
+
+
+def gemm_splits(M, N, K):
+    """The library's split count for an M x N x K product."""
+    s = lib().prox_gemm_splits(int(M), int(N), int(K))
+    if s < 1:
+        _check(s)
+    return s
 
 
 # ------------------------------------------------------------------ the MLP
@@ -152,13 +166,16 @@ def _make_mlp_function():
             gflat = torch.empty(mlp.n_params, dtype=torch.float32, device=gz.device)
             nl = len(mlp.layout)
             dpre = gz
-            chunks = (Bn + 255) // 256
+            chunks = (Bn + 127) // 128
             work = torch.empty(chunks * max(mlp.dims), dtype=torch.float32, device=gz.device)
+            splits = [gemm_splits(fo, fi, Bn) for (_, _, fo, fi) in mlp.layout]
+            sk = max(s * fo * fi if s > 1 else 0 for s, (_, _, fo, fi) in zip(splits, mlp.layout))
+            skw = torch.empty(max(sk, 4), dtype=torch.float32, device=gz.device)
             for k in range(nl - 1, -1, -1):
                 wo, bo, fo, fi = mlp.layout[k]
                 h_in = ctx.acts[k]
-                # dW [fo, fi] = dpre^T h_in; db = column sums of dpre
-                gemm(2, dpre, fo, h_in, fi, gflat[wo:wo + fo * fi], fi, fo, fi, Bn)
+                # dW [fo, fi] = dpre^T h_in (split over the batch); db = column sums of dpre
+                gemm(2, dpre, fo, h_in, fi, gflat[wo:wo + fo * fi], fi, fo, fi, Bn, splits=splits[k], work=skw)
                 _check(lib().prox_colsum(_p(dpre), Bn, fo, _p(work), _p(gflat[bo:bo + fo]), ctypes.c_float(1.0),
                                          _stream()))
                 if k == 0:

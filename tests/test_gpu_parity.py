@@ -196,6 +196,26 @@ def test_single_launch_limit_rejects_negative():
         opf.set_single_launch_limit(-1)
 
 
+def test_launch_shape_query():
+    """A model keeps the shape chosen at creation; the item count is the
+    closed form of the 14-bus network (1 branch chunk, 1 generator chunk,
+    its bus waves)."""
+    cs = synth.network(14, 20, 5, 0)
+    try:
+        opf.set_single_launch_limit(0)
+        two = opf.Model(cs)
+        opf.set_single_launch_limit(4096)
+        one = opf.Model(cs)
+        opf.set_single_launch_limit(1)
+        tiny = opf.Model(cs)
+    finally:
+        opf.set_single_launch_limit(4096)
+    assert two.launch_shape()[0] == 2 and one.launch_shape()[0] == 1 and tiny.launch_shape()[0] == 2
+    assert two.launch_shape()[1] == one.launch_shape()[1] >= 3
+    for mdl in (two, one, tiny):
+        mdl.close()
+
+
 def test_bad_arguments_raise():
     cs = synth.network(14, 20, 5, 0)
     model = opf.Model(cs)

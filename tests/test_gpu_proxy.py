@@ -68,6 +68,49 @@ def test_gemm_vs_oracle(dev, P, variant, shape):
     assert np.all(np.abs(Ca.cpu().numpy() - (ref + C0)) <= bound + 4e-7 * np.abs(ref + C0) + 1e-6)
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("shape,splits", [((132, 200, 1000), 3), ((256, 128, 4096), 4), ((64, 36, 200), 8)])
+def test_gemm_splitk_vs_oracle(dev, P, variant, shape, splits):
+    """Split-K: parts over whole k tiles (the last one ragged or empty), summed
+    in order with the epilogue; also bitwise repeatable."""
+    M, N, K = shape
+    rng = np.random.default_rng(20 + variant)
+    A = rng.standard_normal((M, K)).astype(np.float32)
+    B = rng.standard_normal((K, N)).astype(np.float32)
+    bias = rng.standard_normal(N).astype(np.float32)
+    C0 = rng.standard_normal((M, N)).astype(np.float32)
+    As, lda, Bs, ldb = _stored(variant, A, B)
+    tA, tB = torch.as_tensor(As, device=dev), torch.as_tensor(Bs, device=dev)
+    tb = torch.as_tensor(bias, device=dev)
+    ref = MO.gemm(A, B)
+    bound = 2.0 * K * 2.0 ** -24 * (np.abs(MO.bf16_round(A)).astype(np.float64) @ np.abs(MO.bf16_round(B)))
+    work = torch.full((splits * M * N,), float("nan"), device=dev)
+    C = torch.empty(M, N, dtype=torch.float32, device=dev)
+    act = torch.empty_like(C)
+    P.gemm(variant, tA, lda, tB, ldb, C, N, M, N, K, bias=tb, act=act, splits=splits, work=work)
+    torch.cuda.synchronize()
+    got = C.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - (ref + bias)) <= bound + 4e-7 * np.abs(ref + bias) + 1e-6)
+    np.testing.assert_allclose(act.cpu().numpy(), MO.gelu(got), rtol=2e-6, atol=2e-6)
+    C2 = torch.empty_like(C)
+    P.gemm(variant, tA, lda, tB, ldb, C2, N, M, N, K, bias=tb, splits=splits, work=work)
+    torch.cuda.synchronize()
+    assert torch.equal(C, C2)
+    Ca = torch.as_tensor(C0, device=dev)
+    P.gemm(variant, tA, lda, tB, ldb, Ca, N, M, N, K, accumulate=True, splits=splits, work=work)
+    torch.cuda.synchronize()
+    assert np.all(np.abs(Ca.cpu().numpy() - (ref + C0)) <= bound + 4e-7 * np.abs(ref + C0) + 1e-6)
+
+
+def test_gemm_splits_hint(dev, P):
+    assert P.gemm_splits(1024, 1024, 4096) == 4   # 64 tiles -> 256 workgroups
+    assert P.gemm_splits(4096, 1024, 1024) == 1   # 256 tiles already
+    assert P.gemm_splits(1024, 1024, 256) == 1    # too short to cut
+    from paper_2510_12897_amd.opf import OPFError
+    with pytest.raises(OPFError):
+        P.gemm_splits(-4, 8, 8)
+
+
 def test_gemm_rejects_bad_shapes(dev, P):
     from paper_2510_12897_amd.opf import OPFError
     a = torch.zeros(8, 8, device=dev)
@@ -75,6 +118,8 @@ def test_gemm_rejects_bad_shapes(dev, P):
         P.gemm(0, a, 8, a, 8, a, 8, 6, 8, 8)  # M not a multiple of 4
     with pytest.raises(OPFError):
         P.gemm(7, a, 8, a, 8, a, 8, 8, 8, 8)  # unknown variant
+    with pytest.raises(OPFError):
+        P.gemm(0, a, 8, a, 8, a, 8, 8, 8, 8, splits=2)  # split-K without work
 
 
 def test_elementwise_kernels_vs_oracle(dev, P):
@@ -89,10 +134,16 @@ def test_elementwise_kernels_vs_oracle(dev, P):
     # column sums in a fixed order
     X = rng.standard_normal((700, 36)).astype(np.float32)
     tX = torch.as_tensor(X, device=dev)
-    work = torch.empty(3 * 36, device=dev)
+    work = torch.empty(((700 + 127) // 128) * 36, device=dev)
     cs = torch.empty(36, device=dev)
     lib().prox_colsum(P._p(tX), 700, 36, P._p(work), P._p(cs), 0.5, P._stream())
     np.testing.assert_allclose(cs.cpu().numpy(), 0.5 * X.astype(np.float64).sum(0), rtol=1e-5, atol=1e-5)
+    # several 64-column stripes and 128-row chunks, ragged in both
+    X2 = rng.standard_normal((1000, 132)).astype(np.float32)
+    work2 = torch.empty(((1000 + 127) // 128) * 132, device=dev)
+    cs2 = torch.empty(132, device=dev)
+    lib().prox_colsum(P._p(torch.as_tensor(X2, device=dev)), 1000, 132, P._p(work2), P._p(cs2), 1.0, P._stream())
+    np.testing.assert_allclose(cs2.cpu().numpy(), X2.astype(np.float64).sum(0), rtol=1e-5, atol=2e-5)
     # Adam, three steps
     p = rng.standard_normal(1000)
     m1 = np.zeros(1000)
