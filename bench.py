@@ -411,6 +411,9 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=20)
     ap.add_argument("--proxy-steps", type=int, default=1500, help="training steps of the proxy leg (0 = skip)")
     ap.add_argument("--eager", action="store_true", help="launch the headline sets without a HIP graph")
+    ap.add_argument("--launch-limit", type=int, default=None,
+                    help="one-launch limit in work items for the models built (0 = always two launches; "
+                         "default: the library's)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run a device-to-device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--quiet", action="store_true")
@@ -433,6 +436,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     opf.lib()
+    if args.launch_limit is not None:
+        opf.set_single_launch_limit(args.launch_limit)
     if args.copy_mb > 0:
         n = args.copy_mb * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")

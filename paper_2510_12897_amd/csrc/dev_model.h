@@ -32,9 +32,10 @@ enum TaskKind : int32_t {
 // The J^T v phase uses the first two fields: the side's va and vm terms.
 enum RecField : int32_t { R_TT = 0, R_MA, R_MM, R_UW, R_P, R_Q, kRec };
 // Records are stored back to back, 48 bytes apart (16-byte aligned: three
-// 16-byte loads fetch one).  Padding them to 64-byte sectors and fetching
-// each with four cooperating lanes was measured slower (more bytes written
-// for no fewer cycles).
+// 16-byte loads fetch one).  Padding them to 64-byte sectors was measured
+// slower, with the same three loads per lane (4 % on the 64-scenario batch)
+// and with each record fetched by four cooperating lanes: the extra bytes
+// written cost more than the aligned reads save.
 constexpr int kRecStride = kRec;
 
 constexpr int kBlock = 64;          // threads per workgroup (one wave), every task

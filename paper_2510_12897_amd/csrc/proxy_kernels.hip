@@ -112,6 +112,27 @@ __device__ __forceinline__ void store_tile(__bf16* S, const float4 (&v)[8]) {
     }
 }
 
+// One BK-deep step of the four waves' 64 x 64 tiles from the LDS operands.
+__device__ __forceinline__ void mma_tile(const __bf16* As, const __bf16* Bs, int wi, int wj, int lane,
+                                         f32x16 (&acc)[2][2]) {
+#pragma unroll
+    for (int ks = 0; ks < BK / 16; ks++) {
+        const int c = ks * 2 + lane / 32;
+        bf16x8 fa[2], fb[2];
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+            fa[a] = *reinterpret_cast<const bf16x8*>(As + lds_at(wi + a * 32 + lane % 32, c));
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+            fb[b] = *reinterpret_cast<const bf16x8*>(Bs + lds_at(wj + b * 32 + lane % 32, c));
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+}
+
 // C[M,N] = A[M,K] B[K,N] (+ bias[N], then optionally GELU into act).
 //  A_KCONT: A(i,k) = A[i*lda + k], else A[k*lda + i]
 //  B_KCONT: B(k,j) = B[j*ldb + k], else B[k*ldb + j]
@@ -162,24 +183,7 @@ __global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const float* __restr
             load_tile<A_KCONT>(A, lda, M, ke, i0, k0 + BK, ra);
             load_tile<B_KCONT>(B, ldb, N, ke, j0, k0 + BK, rb);
         }
-        const __bf16* As = lds[cur][0];
-        const __bf16* Bs = lds[cur][1];
-#pragma unroll
-        for (int ks = 0; ks < BK / 16; ks++) {
-            const int c = ks * 2 + lane / 32;
-            bf16x8 fa[2], fb[2];
-#pragma unroll
-            for (int a = 0; a < 2; a++)
-                fa[a] = *reinterpret_cast<const bf16x8*>(As + lds_at(wi + a * 32 + lane % 32, c));
-#pragma unroll
-            for (int b = 0; b < 2; b++)
-                fb[b] = *reinterpret_cast<const bf16x8*>(Bs + lds_at(wj + b * 32 + lane % 32, c));
-#pragma unroll
-            for (int a = 0; a < 2; a++)
-#pragma unroll
-                for (int b = 0; b < 2; b++)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
-        }
+        mma_tile(lds[cur][0], lds[cur][1], wi, wj, lane, acc);
         if (more) {  // the other buffer: every wave passed the last barrier after reading it
             store_tile<A_KCONT>(lds[cur ^ 1][0], ra);
             store_tile<B_KCONT>(lds[cur ^ 1][1], rb);
