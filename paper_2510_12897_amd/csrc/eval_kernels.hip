@@ -768,13 +768,21 @@ __device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int
                 if (threadIdx.x == 0) m.obj_part[slot] = s;
             } else {
                 // single launch: the chunk whose arrival completes the
-                // self-resetting ticket sums every partial (index order)
+                // self-resetting ticket sums every partial (index order).
+                // Partials and ticket are device-coherent atomics; the
+                // ticket moves only after this wave's partial store has
+                // completed (s_waitcnt 0).  An acquire-release ticket would
+                // also write back and invalidate the whole XCD L2 for every
+                // chunk, which cost 1.6 us of the 10k-bus set.
                 __shared__ int32_t last;
                 const int32_t total = m.ngchunks * m.npg;
                 if (threadIdx.x == 0) {
                     __hip_atomic_store(&m.obj_part[slot], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
                     const int32_t old =
-                        __hip_atomic_fetch_add(m.obj_ticket, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_fetch_add(m.obj_ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     last = (old + 1 == total) ? 1 : 0;
                 }
                 __syncthreads();
