@@ -23,13 +23,13 @@ namespace opf {
 namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-constexpr int BM = 128, BN = 128, BK = 64;
-constexpr int TILE = BM * BK;  // BF16 values of one operand tile (BM == BN)
+constexpr int BM = 128, BK = 64;  // block tile rows (of A / C) and k depth; columns: 128 or 64
 constexpr int GEMM_THREADS = 256;
-constexpr int kXcd = 8;  // accelerator complex dies, each with its own L2
-static_assert(BM == BN, "one tile loader serves both operands");
+constexpr int kXcd = 8;       // accelerator complex dies, each with its own L2
+constexpr int kWideMin = 512; // 128-column tiles only when they give two workgroups per CU (256 CUs)
 
 __device__ __forceinline__ __bf16 to_bf16(float f) { return (__bf16)f; }  // round to nearest even
 
@@ -51,55 +51,59 @@ __device__ __forceinline__ bf16x8 pack8(float a0, float a1, float a2, float a3, 
                     to_bf16(a4), to_bf16(a5), to_bf16(a6), to_bf16(a7)};
 }
 
-// Global loads of one 128 x BK operand tile (rows r0.., k0..), 32 floats per
-// thread, zero outside rows < nrows, k < kend.  Sizes are multiples of 4, so
-// each float4 is wholly inside or wholly outside.
+// Global loads of one ROWS x BK operand tile (rows r0.., k0..; ROWS = 128 or
+// 64), ROWS / 8 floats per thread, zero outside rows < nrows, k < kend.
+// Sizes are multiples of 4, so each float4 is wholly inside or outside.
 //  KCONT: element (r, k) at P[r * ld + k]; thread t holds row t / 8 + 32 q,
 //         k = 8 (t % 8) .. + 8 as v[2q], v[2q + 1].
-//  else:  element (r, k) at P[k * ld + r]; thread t holds rows 4 (t % 32) .. + 4
-//         at k = 8 (t / 32) + kk as v[kk] (a coalesced row segment per k).
+//  else:  element (r, k) at P[k * ld + r]; thread t holds the four rows
+//         4 (t % G) .. + 4 (G = ROWS / 4 row groups) at the k values
+//         K (t / G) + kk, K = 4 G / 8 (8 for 128 rows, 4 for 64), as v[kk]:
+//         a coalesced row segment per k.
 __device__ __forceinline__ float4 guarded_load(const float* __restrict__ base, const float* p, bool ok) {
     // an out-of-range load reads the (valid) first element and is discarded
     const float4 t = *reinterpret_cast<const float4*>(ok ? p : base);
     return ok ? t : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-template <bool KCONT>
+template <bool KCONT, int ROWS>
 __device__ __forceinline__ void load_tile(const float* __restrict__ P, int ld, int nrows, int kend, int r0, int k0,
-                                          float4 (&v)[8]) {
+                                          float4 (&v)[ROWS / 16]) {
     const int t = threadIdx.x;
     if (KCONT) {
         const int k = k0 + (t % 8) * 8;
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
+        for (int q = 0; q < ROWS / 32; q++) {
             const int r = r0 + t / 8 + 32 * q;
             const float* p = P + (size_t)r * ld + k;
             v[2 * q] = guarded_load(P, p, r < nrows && k < kend);
             v[2 * q + 1] = guarded_load(P, p + 4, r < nrows && k + 4 < kend);
         }
     } else {
-        const int r = r0 + (t % 32) * 4;
+        constexpr int G = ROWS / 4, KPER = ROWS / 16;
+        const int r = r0 + (t % G) * 4;
 #pragma unroll
-        for (int kk = 0; kk < 8; kk++) {
-            const int k = k0 + (t / 32) * 8 + kk;
+        for (int kk = 0; kk < KPER; kk++) {
+            const int k = k0 + (t / G) * KPER + kk;
             v[kk] = guarded_load(P, P + (size_t)k * ld + r, r < nrows && k < kend);
         }
     }
 }
 
-// Rounds the loaded tile to BF16 and writes it to LDS as 16-byte row chunks
-// (the i-contiguous layout is transposed in registers).
-template <bool KCONT>
-__device__ __forceinline__ void store_tile(__bf16* S, const float4 (&v)[8]) {
+// Rounds the loaded tile to BF16 and writes it to LDS as row chunks (the
+// i-contiguous layout is transposed in registers: 16-byte chunks for 128
+// rows, 8-byte half chunks for 64).
+template <bool KCONT, int ROWS>
+__device__ __forceinline__ void store_tile(__bf16* S, const float4 (&v)[ROWS / 16]) {
     const int t = threadIdx.x;
     if (KCONT) {
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
+        for (int q = 0; q < ROWS / 32; q++) {
             const float4 a = v[2 * q], b = v[2 * q + 1];
             *reinterpret_cast<bf16x8*>(S + lds_at(t / 8 + 32 * q, t % 8)) =
                 pack8(a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w);
         }
-    } else {
+    } else if (ROWS == 128) {
         const int r = (t % 32) * 4, c = t / 32;
         *reinterpret_cast<bf16x8*>(S + lds_at(r + 0, c)) =
             pack8(v[0].x, v[1].x, v[2].x, v[3].x, v[4].x, v[5].x, v[6].x, v[7].x);
@@ -109,26 +113,38 @@ __device__ __forceinline__ void store_tile(__bf16* S, const float4 (&v)[8]) {
             pack8(v[0].z, v[1].z, v[2].z, v[3].z, v[4].z, v[5].z, v[6].z, v[7].z);
         *reinterpret_cast<bf16x8*>(S + lds_at(r + 3, c)) =
             pack8(v[0].w, v[1].w, v[2].w, v[3].w, v[4].w, v[5].w, v[6].w, v[7].w);
+    } else {
+        const int r = (t % 16) * 4, kq = t / 16;  // k = 4 kq .. + 4: half kq % 2 of chunk kq / 2
+        const int c = kq / 2, h = (kq % 2) * 4;
+        *reinterpret_cast<bf16x4*>(S + lds_at(r + 0, c) + h) =
+            (bf16x4){to_bf16(v[0].x), to_bf16(v[1].x), to_bf16(v[2].x), to_bf16(v[3].x)};
+        *reinterpret_cast<bf16x4*>(S + lds_at(r + 1, c) + h) =
+            (bf16x4){to_bf16(v[0].y), to_bf16(v[1].y), to_bf16(v[2].y), to_bf16(v[3].y)};
+        *reinterpret_cast<bf16x4*>(S + lds_at(r + 2, c) + h) =
+            (bf16x4){to_bf16(v[0].z), to_bf16(v[1].z), to_bf16(v[2].z), to_bf16(v[3].z)};
+        *reinterpret_cast<bf16x4*>(S + lds_at(r + 3, c) + h) =
+            (bf16x4){to_bf16(v[0].w), to_bf16(v[1].w), to_bf16(v[2].w), to_bf16(v[3].w)};
     }
 }
 
-// One BK-deep step of the four waves' 64 x 64 tiles from the LDS operands.
+// One BK-deep step of a wave's 64 x (32 NB) tile from the LDS operands.
+template <int NB>
 __device__ __forceinline__ void mma_tile(const __bf16* As, const __bf16* Bs, int wi, int wj, int lane,
-                                         f32x16 (&acc)[2][2]) {
+                                         f32x16 (&acc)[2][NB]) {
 #pragma unroll
     for (int ks = 0; ks < BK / 16; ks++) {
         const int c = ks * 2 + lane / 32;
-        bf16x8 fa[2], fb[2];
+        bf16x8 fa[2], fb[NB];
 #pragma unroll
         for (int a = 0; a < 2; a++)
             fa[a] = *reinterpret_cast<const bf16x8*>(As + lds_at(wi + a * 32 + lane % 32, c));
 #pragma unroll
-        for (int b = 0; b < 2; b++)
+        for (int b = 0; b < NB; b++)
             fb[b] = *reinterpret_cast<const bf16x8*>(Bs + lds_at(wj + b * 32 + lane % 32, c));
 #pragma unroll
         for (int a = 0; a < 2; a++)
 #pragma unroll
-            for (int b = 0; b < 2; b++)
+            for (int b = 0; b < NB; b++)
                 acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
     }
 }
@@ -136,18 +152,20 @@ __device__ __forceinline__ void mma_tile(const __bf16* As, const __bf16* Bs, int
 // C[M,N] = A[M,K] B[K,N] (+ bias[N], then optionally GELU into act).
 //  A_KCONT: A(i,k) = A[i*lda + k], else A[k*lda + i]
 //  B_KCONT: B(k,j) = B[j*ldb + k], else B[k*ldb + j]
-// Workgroup (x, y, z) computes the 128 x 128 tile (y, x) over the k range
+// A workgroup computes one 128 x BN tile (BN = 128 or 64) over the k range
 // [z kchunk, (z + 1) kchunk); with work != NULL it writes that partial product
 // to work[z] (row-major [M, N]) instead of the epilogue.  Four waves of 64 x 64,
 // double-buffered LDS (one barrier per k tile), the next tile's global loads
 // in flight during the matrix-core work on the current one.
-template <bool A_KCONT, bool B_KCONT>
+template <bool A_KCONT, bool B_KCONT, int BN>
 __global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const float* __restrict__ A, int lda,
                                                             const float* __restrict__ B, int ldb, float* __restrict__ C,
                                                             int ldc, int M, int N, int K, int kchunk,
                                                             const float* __restrict__ bias, float* __restrict__ act,
                                                             int accumulate, float* __restrict__ work) {
-    __shared__ __bf16 lds[2][2][TILE];  // [buffer][A, B]
+    constexpr int NB = BN / 64;  // 32-column MFMA tiles per wave
+    __shared__ __bf16 As[2][BM * BK];
+    __shared__ __bf16 Bs[2][BN * BK];
     // Workgroups are dealt to the XCDs round-robin; renumber them so that
     // each XCD takes one contiguous range of tiles (n fastest, then m, then
     // the k part): its rows of A and the shared B stay in its own L2.
@@ -159,34 +177,34 @@ __global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const float* __restr
     const int kz = tile / (nx * ny);
     const int kb = kz * kchunk, ke = min(K, kb + kchunk);
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    const int wi = (wave / 2) * 64, wj = (wave % 2) * 64;
-    f32x16 acc[2][2];
+    const int wi = (wave / 2) * 64, wj = (wave % 2) * (BN / 2);
+    f32x16 acc[2][NB];
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
-        for (int b = 0; b < 2; b++)
+        for (int b = 0; b < NB; b++)
 #pragma unroll
             for (int v = 0; v < 16; v++) acc[a][b][v] = 0.f;
 
-    float4 ra[8], rb[8];
+    float4 ra[BM / 16], rb[BN / 16];
     if (kb < ke) {
-        load_tile<A_KCONT>(A, lda, M, ke, i0, kb, ra);
-        load_tile<B_KCONT>(B, ldb, N, ke, j0, kb, rb);
-        store_tile<A_KCONT>(lds[0][0], ra);
-        store_tile<B_KCONT>(lds[0][1], rb);
+        load_tile<A_KCONT, BM>(A, lda, M, ke, i0, kb, ra);
+        load_tile<B_KCONT, BN>(B, ldb, N, ke, j0, kb, rb);
+        store_tile<A_KCONT, BM>(As[0], ra);
+        store_tile<B_KCONT, BN>(Bs[0], rb);
     }
     __syncthreads();
     int cur = 0;
     for (int k0 = kb; k0 < ke; k0 += BK) {
         const bool more = k0 + BK < ke;
         if (more) {
-            load_tile<A_KCONT>(A, lda, M, ke, i0, k0 + BK, ra);
-            load_tile<B_KCONT>(B, ldb, N, ke, j0, k0 + BK, rb);
+            load_tile<A_KCONT, BM>(A, lda, M, ke, i0, k0 + BK, ra);
+            load_tile<B_KCONT, BN>(B, ldb, N, ke, j0, k0 + BK, rb);
         }
-        mma_tile(lds[cur][0], lds[cur][1], wi, wj, lane, acc);
+        mma_tile<NB>(As[cur], Bs[cur], wi, wj, lane, acc);
         if (more) {  // the other buffer: every wave passed the last barrier after reading it
-            store_tile<A_KCONT>(lds[cur ^ 1][0], ra);
-            store_tile<B_KCONT>(lds[cur ^ 1][1], rb);
+            store_tile<A_KCONT, BM>(As[cur ^ 1], ra);
+            store_tile<B_KCONT, BN>(Bs[cur ^ 1], rb);
         }
         __syncthreads();
         cur ^= 1;
@@ -198,7 +216,7 @@ __global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const float* __restr
 #pragma unroll
         for (int a = 0; a < 2; a++)
 #pragma unroll
-            for (int b = 0; b < 2; b++) {
+            for (int b = 0; b < NB; b++) {
                 const int j = j0 + wj + b * 32 + lane % 32;
                 if (j >= N) continue;
 #pragma unroll
@@ -212,7 +230,7 @@ __global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const float* __restr
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
-        for (int b = 0; b < 2; b++) {
+        for (int b = 0; b < NB; b++) {
             const int j = j0 + wj + b * 32 + lane % 32;
             if (j >= N) continue;
             const float bj = bias ? bias[j] : 0.f;
@@ -489,25 +507,43 @@ hipError_t prox_vjp_sum(const double* gX1, const double* gX2, const double* gObj
 }
 
 int prox_gemm_splits(int M, int N, int K) {
-    // enough workgroups for one per compute unit, each part at least 4 k tiles
-    const int64_t blocks = (int64_t)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+    // enough 128 x 128 tiles for one per compute unit, each part at least 4 k tiles
+    const int64_t blocks = (int64_t)((M + BM - 1) / BM) * ((N + 127) / 128);
     int s = 1;
     while (blocks * s < 256 && K >= 2 * s * 4 * BK && s < 16) s *= 2;
     return s;
 }
+
+namespace {
+template <int BN>
+void launch_gemm(int variant, dim3 grid, hipStream_t s, const float* A, int lda, const float* B, int ldb, float* C,
+                 int ldc, int M, int N, int K, int kchunk, const float* bias, float* act, int accumulate,
+                 float* part) {
+    const dim3 block(GEMM_THREADS);
+    switch (variant) {
+    case 0: hipLaunchKernelGGL((gemm_kernel<true, true, BN>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
+    case 1: hipLaunchKernelGGL((gemm_kernel<true, false, BN>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
+    case 2: hipLaunchKernelGGL((gemm_kernel<false, false, BN>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
+    default: hipLaunchKernelGGL((gemm_kernel<false, true, BN>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
+    }
+}
+}  // namespace
 
 hipError_t prox_gemm(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N,
                      int K, const float* bias, float* act, int accumulate, int splits, float* work, hipStream_t s) {
     if (splits < 1) splits = 1;
     const int kchunk = splits == 1 ? K : ((K + splits - 1) / splits + BK - 1) / BK * BK;
     float* part = splits == 1 ? nullptr : work;
-    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, splits), block(GEMM_THREADS);
-    switch (variant) {
-    case 0: hipLaunchKernelGGL((gemm_kernel<true, true>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
-    case 1: hipLaunchKernelGGL((gemm_kernel<true, false>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
-    case 2: hipLaunchKernelGGL((gemm_kernel<false, false>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
-    default: hipLaunchKernelGGL((gemm_kernel<false, true>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
-    }
+    const int my = (M + BM - 1) / BM;
+    // 128-column tiles when they already give two workgroups per CU, else
+    // 64-column tiles (twice the workgroups, two resident per CU)
+    const int64_t wide = (int64_t)my * ((N + 127) / 128) * splits;
+    if (wide >= kWideMin)
+        launch_gemm<128>(variant, dim3((N + 127) / 128, my, splits), s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias,
+                         act, accumulate, part);
+    else
+        launch_gemm<64>(variant, dim3((N + 63) / 64, my, splits), s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias,
+                        act, accumulate, part);
     if (splits > 1) {
         const int64_t tot = (int64_t)M * (N / 4);
         hipLaunchKernelGGL(splitk_sum_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, work, splits, M, N,

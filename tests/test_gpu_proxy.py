@@ -39,7 +39,9 @@ def _stored(variant, A, B):
 
 
 @pytest.mark.parametrize("variant", [0, 1, 2, 3])
-@pytest.mark.parametrize("shape", [(132, 200, 72), (256, 128, 1000), (4, 8, 4)])
+# small shapes take 128 x 64 tiles; 1024 x 8192 (512 tiles of 128 x 128)
+# takes the 128-column tiles
+@pytest.mark.parametrize("shape", [(132, 200, 72), (256, 128, 1000), (4, 8, 4), (1024, 8192, 68)])
 def test_gemm_vs_oracle(dev, P, variant, shape):
     M, N, K = shape
     rng = np.random.default_rng(10 + variant)
@@ -69,7 +71,8 @@ def test_gemm_vs_oracle(dev, P, variant, shape):
 
 
 @pytest.mark.parametrize("variant", [0, 1, 2, 3])
-@pytest.mark.parametrize("shape,splits", [((132, 200, 1000), 3), ((256, 128, 4096), 4), ((64, 36, 200), 8)])
+@pytest.mark.parametrize("shape,splits", [((132, 200, 1000), 3), ((256, 128, 4096), 4), ((64, 36, 200), 8),
+                                          ((1024, 4096, 520), 2)])
 def test_gemm_splitk_vs_oracle(dev, P, variant, shape, splits):
     """Split-K: parts over whole k tiles (the last one ragged or empty), summed
     in order with the epilogue; also bitwise repeatable."""
