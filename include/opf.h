@@ -204,8 +204,9 @@ int opf_hess_structure(opf_model model, int32_t *rows, int32_t *cols, void *stre
 int opf_hess_coord(opf_model model, const double *x, const double *y, double obj_weight,
                    double *vals, void *stream);
 
-/* All five callbacks in one launch; bitwise equal to the separate calls.
- * Any output may be NULL (skipped); y may be NULL only when hvals is. */
+/* All five callbacks in one or two kernel launches (the model's launch
+ * shape, opf_model_launches); bitwise equal to the separate calls.  Any
+ * output may be NULL (skipped); y may be NULL only when hvals is. */
 int opf_eval_set(opf_model model, const double *x, const double *y, double obj_weight,
                  double *f, double *g, double *c, double *jvals, double *hvals, void *stream);
 
@@ -214,8 +215,9 @@ int opf_eval_set(opf_model model, const double *x, const double *y, double obj_w
 int opf_jtprod(opf_model model, const double *x, const double *v, double *out, void *stream);
 
 /* ---------------------------------------------------------------- batch */
-/* Many instances of possibly different networks evaluated by one
- * persistent kernel launch (batched AC-OPF is the paper's stated future
+/* Many instances of possibly different networks evaluated together: one
+ * HIP graph of two kernels (branch phase, bus phase), each covering every
+ * instance's work items (batched AC-OPF is the paper's stated future
  * work, Sec. VI).  Instance j uses model inst_model[j] (static,
  * multi-period or contingency) with its own loads: inst_pd / inst_qd hold
  * the concatenated per-instance load arrays, n_bus entries per instance
@@ -248,10 +250,13 @@ int opf_batch_schedule(opf_batch batch, int32_t *wg_per_cu);
 /* Force a schedule: wg_per_cu in [0, 64] (else OPF_E_ARG). */
 int opf_batch_set_schedule(opf_batch batch, int32_t wg_per_cu);
 
-/* All callbacks of every instance in one launch of a persistent kernel,
- * replayed from a HIP graph.  sigma[n_inst] are the objective weights.  Any
- * of F, G, C, J, H may be NULL (skipped); Y and sigma may be NULL when H
- * is.  Results are bitwise equal to opf_eval_set on each instance. */
+/* All callbacks of every instance: the batch's HIP graph (branch-phase and
+ * bus-phase kernels at the current schedule), instantiated once per
+ * schedule and relaunched with each call's buffers as kernel arguments.
+ * sigma[n_inst] are the objective weights.  Any of F, G, C, J, H may be
+ * NULL (skipped); Y and sigma may be NULL when H is.  Results are bitwise
+ * equal to opf_eval_set on each instance's model in the two-launch shape,
+ * and equal to rounding for a model in the one-launch shape. */
 int opf_batch_eval(opf_batch batch, const double *X, const double *Y, const double *sigma,
                    double *F, double *G, double *C, double *J, double *H, void *stream);
 
