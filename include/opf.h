@@ -341,10 +341,15 @@ int prox_squash_bwd(opf_model model, const float *z, int B, double va_span, cons
 int prox_penalty(opf_model model, const double *C, const double *X, const double *F, double obj_scale, double rho,
                  int B, double *pen, double *cvio, double *W, double *gpq, void *stream);
 
-/* W2 [B, m]: minus (G1 + gpq) of each arc variable placed on its flow row,
- * zero elsewhere, so that J^T W2 carries a gradient on p = F(vm, va) back to
- * the voltages. */
-int prox_chain_weights(opf_model model, const double *G1, const double *gpq, int B, double *W2, void *stream);
+/* Wt [B, m] = W + W2 for the penalty's VJP through p, q = F(vm, va): W2 is
+ * minus (G1 + gpq) of each arc variable placed on its flow row, G1 = J^T W
+ * restricted to the arc variables, which has a closed form (2 p W on the
+ * branch side's thermal row + W on the balance row of the arc's bus; W is 0
+ * on the flow rows).  J^T Wt is then the whole constraint part of the
+ * gradient (one product).  X [B, n] holds the arc flows; W, gpq as written
+ * by prox_penalty; Wt must not alias W. */
+int prox_vjp_weights(opf_model model, const double *X, const double *W, const double *gpq, int B, double *Wt,
+                     void *stream);
 
 /* gX [B, n] = wb[b] * (gX1 + gX2 + obj_scale * gObj) on the va, vm, pg, qg
  * entries, zero on the arc variables p, q (which the proxy sets to the

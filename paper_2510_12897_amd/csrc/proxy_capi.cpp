@@ -45,6 +45,12 @@ opf::ProxRows rows_of(opf_model m) {
     r.flow1 = (int32_t)ly.c_blk[opf::B_ANG];
     r.pq0 = (int32_t)ly.x_p;
     r.npq = 4 * ly.L;
+    r.thf = (int32_t)ly.c_blk[opf::B_THF];
+    r.tht = (int32_t)ly.c_blk[opf::B_THT];
+    r.balp = (int32_t)ly.c_blk[opf::B_BALP];
+    r.balq = (int32_t)ly.c_blk[opf::B_BALQ];
+    r.f_bus = m->dm.f_bus;
+    r.t_bus = m->dm.t_bus;
     r.lcon = m->lcon;
     r.ucon = m->ucon;
     r.lvar = m->lvar;
@@ -145,12 +151,14 @@ int prox_penalty(opf_model model, const double* C, const double* X, const double
                     "prox_penalty launch");
 }
 
-int prox_chain_weights(opf_model model, const double* G1, const double* gpq, int B, double* W2, void* stream) {
+int prox_vjp_weights(opf_model model, const double* X, const double* W, const double* gpq, int B, double* Wt,
+                     void* stream) {
     if (int rc = static_model(model)) return rc;
-    if (B < 1 || !G1 || !gpq || !W2) return set_err(OPF_E_ARG, "bad arguments");
+    if (B < 1 || !X || !W || !gpq || !Wt) return set_err(OPF_E_ARG, "bad arguments");
+    if (Wt == W) return set_err(OPF_E_ARG, "Wt must not alias W");
     DeviceGuard dg(model->device);
-    return launched(opf::prox_chain_weights(G1, gpq, rows_of(model), B, W2, static_cast<hipStream_t>(stream)),
-                    "prox_chain_weights launch");
+    return launched(opf::prox_vjp_weights(X, W, gpq, rows_of(model), B, Wt, static_cast<hipStream_t>(stream)),
+                    "prox_vjp_weights launch");
 }
 
 int prox_vjp_sum(opf_model model, const double* gX1, const double* gX2, const double* gObj, double obj_scale,

@@ -20,7 +20,10 @@ struct ProxRows {
     int32_t m, n, L;
     int32_t flow0, flow1;   // the flow-definition rows [flow0, flow1)
     int32_t pq0, npq;       // the p and q variables [pq0, pq0 + npq)
+    int32_t thf, tht;       // first rows of the from / to thermal blocks
+    int32_t balp, balq;     // first rows of the active / reactive balance blocks
     const double *lcon, *ucon, *lvar, *uvar;
+    const int32_t *f_bus, *t_bus;  // branch end buses
 };
 
 // variant: 0 A k-contiguous, B k-contiguous; 1 A k-contiguous, B j-contiguous;
@@ -40,8 +43,8 @@ hipError_t prox_squash_bwd(const float* z, int B, const ProxBox& box, const doub
                            const double* gObj, double obj_scale, int64_t n, float* dz, float scale, hipStream_t s);
 hipError_t prox_penalty(const double* C, const double* X, const double* F, double obj_scale, const ProxRows& rows,
                         double rho, int B, double* pen, double* cvio, double* W, double* gpq, hipStream_t s);
-hipError_t prox_chain_weights(const double* G1, const double* gpq, const ProxRows& rows, int B, double* W2,
-                              hipStream_t s);
+hipError_t prox_vjp_weights(const double* X, const double* W, const double* gpq, const ProxRows& rows, int B,
+                            double* Wt, hipStream_t s);
 hipError_t prox_vjp_sum(const double* gX1, const double* gX2, const double* gObj, double obj_scale,
                         const double* wb, int B, int64_t n, int64_t nfree, double* gX, hipStream_t s);
 

@@ -455,27 +455,38 @@ __global__ void __launch_bounds__(256) penalty_kernel(const double* __restrict__
     }
 }
 
-// The arc flows p, q are F(vm, va); a gradient g on them reaches the voltages
-// through the flow rows c = p - F: J^T w2 with w2 = -g on the flow rows
-// carries -dF^T (-g) = dF^T g to va, vm.  Writes w2 (zero off the flow rows).
-__global__ void chain_weights_kernel(const double* __restrict__ G1, const double* __restrict__ gpq, ProxRows rows,
-                                     int B, double* __restrict__ W2) {
+// The arc flows p, q are F(vm, va): a gradient on them reaches the
+// voltages through the flow rows c = p - F, whose va / vm columns are -dF.
+// With G1 = J^T W, the arc entry of the total gradient is G1 + gpq, and
+// J^T W2 with w2 = -(G1 + gpq) on the arc's flow row carries it to va, vm.
+// G1 has a closed form on the arc variables: column p_a of J holds the flow
+// row (weight 0 in W), the branch side's thermal row (2 p_a) and the active
+// balance row of the arc's bus (1); q_a likewise with the reactive row.  So
+// the total weights Wt = W + W2 need no first product, and the VJP is the
+// single product J^T Wt.  Writes Wt (W off the flow rows).
+__global__ void vjp_weights_kernel(const double* __restrict__ X, const double* __restrict__ W,
+                                   const double* __restrict__ gpq, ProxRows rows, int B, double* __restrict__ Wt) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)B * rows.m) return;
     const int64_t b = idx / rows.m;
     const int r = (int)(idx % rows.m);
-    double w = 0.0;
+    double w;
     if (r >= rows.flow0 && r < rows.flow1) {
-        // flow rows: p_fr[L], q_fr[L], p_to[L], q_to[L]; arc variable of each
+        // flow rows p_fr[L], q_fr[L], p_to[L], q_to[L]
         const int L = rows.L;
         const int rr = r - rows.flow0;
         const int blk = rr / L, l = rr % L;
-        const int arc = (blk == 0 || blk == 1) ? l : L + l;
-        const int isq = (blk == 1 || blk == 3);
-        const int q = isq * 2 * L + arc;  // index inside the p, q entries
-        w = -(G1[b * rows.n + rows.pq0 + q] + gpq[b * rows.npq + q]);
+        const bool from = blk == 0 || blk == 1, isq = blk == 1 || blk == 3;
+        const int q = (isq ? 2 * L : 0) + (from ? l : L + l);  // index inside the p, q entries
+        const double* wb = W + b * rows.m;
+        const int bus = from ? rows.f_bus[l] : rows.t_bus[l];
+        const double g1 = 2.0 * X[b * rows.n + rows.pq0 + q] * wb[(from ? rows.thf : rows.tht) + l] +
+                          wb[(isq ? rows.balq : rows.balp) + bus];
+        w = -(g1 + gpq[b * rows.npq + q]);
+    } else {
+        w = W[idx];
     }
-    W2[idx] = w;
+    Wt[idx] = w;
 }
 
 // gX [B, n] = wb[b] * (gX1 + gX2 + obj_scale * gObj) on the va, vm, pg, qg
@@ -595,11 +606,11 @@ hipError_t prox_penalty(const double* C, const double* X, const double* F, doubl
     return hipGetLastError();
 }
 
-hipError_t prox_chain_weights(const double* G1, const double* gpq, const ProxRows& rows, int B, double* W2,
-                              hipStream_t s) {
+hipError_t prox_vjp_weights(const double* X, const double* W, const double* gpq, const ProxRows& rows, int B,
+                            double* Wt, hipStream_t s) {
     const int64_t tot = (int64_t)B * rows.m;
-    hipLaunchKernelGGL(chain_weights_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, G1, gpq, rows, B,
-                       W2);
+    hipLaunchKernelGGL(vjp_weights_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, X, W, gpq, rows, B,
+                       Wt);
     return hipGetLastError();
 }
 

@@ -126,7 +126,7 @@ def lib():
                              ctypes.c_float, _vp], ctypes.c_int),
         "prox_penalty": ([_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, _vp, _vp, _vp, _vp,
                           _vp], ctypes.c_int),
-        "prox_chain_weights": ([_vp, _vp, _vp, ctypes.c_int, _vp, _vp], ctypes.c_int),
+        "prox_vjp_weights": ([_vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp], ctypes.c_int),
         "prox_vjp_sum": ([_vp, _vp, _vp, _vp, ctypes.c_double, _vp, ctypes.c_int, _vp, _vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():

@@ -17,12 +17,12 @@ Every step runs in libopf's kernels (argument marshalling only here):
 * ``Squash`` maps the network output into the variable boxes
   (``prox_squash_fwd`` / ``prox_squash_bwd``);
 * ``OPFPenalty`` completes the arc flows (``opf_batch_flows``), evaluates f,
-  grad f and c for the whole batch in one persistent launch
-  (``opf_batch_eval``) and the penalty (``prox_penalty``); its backward is
-  the hand-written vector-Jacobian product: J^T w for the penalty weights,
-  then J^T w2 with the weights that carry the arc-flow gradient back through
-  p = F(vm, va) (``opf_batch_jtprod``, ``prox_chain_weights``,
-  ``prox_vjp_sum``).
+  grad f and c for the whole batch (``opf_batch_eval``) and the penalty
+  (``prox_penalty``); its backward is the hand-written vector-Jacobian
+  product J^T (w + w2): w the penalty weights, w2 the weights on the flow
+  rows that carry the arc-flow gradient back through p = F(vm, va), built
+  in closed form (``prox_vjp_weights``), then one ``opf_batch_jtprod`` and
+  ``prox_vjp_sum``.
 """
 from __future__ import annotations
 
@@ -249,13 +249,12 @@ def _make_penalty_function():
             Xflat, W, gpq, Gf = ctx.saved_tensors
             pen = ctx.pen
             B, n = pen.B, pen.model.n
-            gX1 = pen.batch.jtprod(Xflat, W)
-            W2 = torch.empty_like(W)
-            _check(lib().prox_chain_weights(pen.model.handle, _p(gX1), _p(gpq), B, _p(W2), _stream()))
-            gX2 = pen.batch.jtprod(Xflat, W2)
+            Wt = torch.empty_like(W)
+            _check(lib().prox_vjp_weights(pen.model.handle, _p(Xflat), _p(W), _p(gpq), B, _p(Wt), _stream()))
+            gX1 = pen.batch.jtprod(Xflat, Wt)
             gX = torch.empty(B, n, dtype=torch.float64, device=Xflat.device)
             wb = gloss.detach().to(torch.float64).contiguous()
-            _check(lib().prox_vjp_sum(pen.model.handle, _p(gX1), _p(gX2), _p(Gf), float(pen.obj_scale), _p(wb), B,
+            _check(lib().prox_vjp_sum(pen.model.handle, _p(gX1), None, _p(Gf), float(pen.obj_scale), _p(wb), B,
                                       _p(gX), _stream()))
             return gX, None
 
