@@ -12,7 +12,7 @@ import torch
 from oracle import oracle as O
 from paper_2510_12897_amd import opf, synth
 
-from helpers import assert_close
+from helpers import assert_close, hub_network
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda", 0)
@@ -32,9 +32,10 @@ def shape(request):
     opf.set_single_launch_limit(4096)
 
 
-def build_mix(sizes=(40, 300, 1200), per=3, with_mp=True, with_sc=True):
+def build_mix(sizes=(40, 300, 1200), per=3, with_mp=True, with_sc=True, with_hub=True):
     """Instances of several networks with their own loads, plus one
-    multi-period and one contingency model."""
+    multi-period and one contingency model, and two load scenarios of a
+    network with hub buses (segments beyond one wave)."""
     nets, models, inst_model, pds, qds, plain = [], [], [], [], [], []
     for j, N in enumerate(sizes):
         cs = synth.network(N, int(round(1.35 * N)), max(1, int(round(0.2 * N))), 500 + j, variant=(j % 2 == 0))
@@ -72,6 +73,18 @@ def build_mix(sizes=(40, 300, 1200), per=3, with_mp=True, with_sc=True):
         pds.append(pd)
         qds.append(qd)
         plain.append((c2, opts))
+    if with_hub:
+        cs = hub_network()
+        models.append(opf.Model(cs))
+        nets.append((cs, {}))
+        for s_ in range(2):
+            pd, qd = synth.scenario_loads(cs, 90 + s_)
+            c2 = dict(cs)
+            c2["pd"], c2["qd"] = pd, qd
+            inst_model.append(len(models) - 1)
+            pds.append(pd)
+            qds.append(qd)
+            plain.append((c2, {}))
     batch = opf.Batch(models, inst_model, np.concatenate(pds), np.concatenate(qds))
     return batch, models, inst_model, plain
 

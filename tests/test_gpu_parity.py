@@ -14,7 +14,7 @@ import torch
 from oracle import oracle as O
 from paper_2510_12897_amd import opf, synth
 
-from helpers import assert_close, small_cases, strict_violations
+from helpers import assert_close, hub_network, small_cases, strict_violations
 from test_host_pattern import with_parallel_and_isolated
 
 pytestmark = pytest.mark.gpu
@@ -38,6 +38,13 @@ def _cases():
     yield "parallel_isolated", with_parallel_and_isolated(synth.network(12, 16, 4, 8, variant=True)), {}
     pc = with_parallel_and_isolated(synth.network(12, 16, 4, 9))
     yield "parallel_sc", pc, dict(n_cont=2, outaged=np.array([0, pc["n_branch"] - 1], np.int32))
+    # buses whose segments are 63, 64, 65 and 124 lanes: both sides of the
+    # one-wave limit and the workgroup-wide reduction, with replicas too
+    hub = hub_network()
+    yield "hub", hub, {}
+    pd_t, qd_t = synth.mp_loads(hub, 2, 5)
+    yield "hub_mp2", hub, dict(n_periods=2, pd_t=pd_t, qd_t=qd_t, ramp_ratio=0.2)
+    yield "hub_sc2", hub, dict(n_cont=2, outaged=hub["extra_branches"][:2])
     # several tiles and a ragged tail: 700 buses -> half-edges span many 256-wide tiles
     yield "ragged700", synth.network(700, 951, 140, 12, variant=True), {}
 

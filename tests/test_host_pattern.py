@@ -10,7 +10,7 @@ import pytest
 from oracle import oracle as O
 from paper_2510_12897_amd import opf, synth
 
-from helpers import small_cases
+from helpers import hub_network, small_cases
 
 
 def test_library_exports_every_declared_symbol():
@@ -53,6 +53,9 @@ def _cases():
     yield "parallel_isolated", with_parallel_and_isolated(synth.network(12, 16, 4, 8, variant=True)), {}
     pc = with_parallel_and_isolated(synth.network(12, 16, 4, 9))
     yield "parallel_sc", pc, dict(n_cont=2, outaged=np.array([0, pc["n_branch"] - 1], np.int32))
+    hub = hub_network()
+    yield "hub", hub, {}
+    yield "hub_sc2", hub, dict(n_cont=2, outaged=hub["extra_branches"][:2])
 
 
 CASES = list(_cases())
