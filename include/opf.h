@@ -347,7 +347,7 @@ int prox_penalty(opf_model model, const double *C, const double *X, const double
  * branch side's thermal row + W on the balance row of the arc's bus; W is 0
  * on the flow rows).  J^T Wt is then the whole constraint part of the
  * gradient (one product).  X [B, n] holds the arc flows; W, gpq as written
- * by prox_penalty; Wt must not alias W. */
+ * by prox_penalty.  Wt may be W: then only its flow rows are written. */
 int prox_vjp_weights(opf_model model, const double *X, const double *W, const double *gpq, int B, double *Wt,
                      void *stream);
 

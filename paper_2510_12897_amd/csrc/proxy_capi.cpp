@@ -155,7 +155,6 @@ int prox_vjp_weights(opf_model model, const double* X, const double* W, const do
                      void* stream) {
     if (int rc = static_model(model)) return rc;
     if (B < 1 || !X || !W || !gpq || !Wt) return set_err(OPF_E_ARG, "bad arguments");
-    if (Wt == W) return set_err(OPF_E_ARG, "Wt must not alias W");
     DeviceGuard dg(model->device);
     return launched(opf::prox_vjp_weights(X, W, gpq, rows_of(model), B, Wt, static_cast<hipStream_t>(stream)),
                     "prox_vjp_weights launch");

@@ -35,7 +35,6 @@ hipError_t prox_gemm(int variant, const float* A, int lda, const float* B, int l
 int prox_gemm_splits(int M, int N, int K);
 hipError_t prox_gelu_bwd(const float* pre, const float* dact, float* dpre, int64_t n, hipStream_t s);
 hipError_t prox_colsum(const float* X, int M, int N, float* part, float* out, float scale, hipStream_t s);
-int prox_colsum_chunks(int M);
 hipError_t prox_adam(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2, float eps,
                      int step, hipStream_t s);
 hipError_t prox_squash_fwd(const float* z, int B, const ProxBox& box, double* X, int64_t n, hipStream_t s);

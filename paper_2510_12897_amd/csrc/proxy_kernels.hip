@@ -463,30 +463,32 @@ __global__ void __launch_bounds__(256) penalty_kernel(const double* __restrict__
 // row (weight 0 in W), the branch side's thermal row (2 p_a) and the active
 // balance row of the arc's bus (1); q_a likewise with the reactive row.  So
 // the total weights Wt = W + W2 need no first product, and the VJP is the
-// single product J^T Wt.  Writes Wt (W off the flow rows).
-__global__ void vjp_weights_kernel(const double* __restrict__ X, const double* __restrict__ W,
-                                   const double* __restrict__ gpq, ProxRows rows, int B, double* __restrict__ Wt) {
+// single product J^T Wt.  One thread per flow row: the flow rows of Wt are
+// written from W's thermal and balance rows, which they never overlap, so Wt
+// may be W itself; a separate Wt also receives W's other rows.
+__global__ void vjp_weights_kernel(const double* X, const double* W, const double* __restrict__ gpq, ProxRows rows,
+                                   int B, double* Wt) {
+    const int nf = rows.flow1 - rows.flow0;  // 4 L
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)B * nf) return;
+    const int64_t b = idx / nf;
+    const int rr = (int)(idx % nf);
+    // flow rows p_fr[L], q_fr[L], p_to[L], q_to[L]
+    const int L = rows.L;
+    const int blk = rr / L, l = rr % L;
+    const bool from = blk == 0 || blk == 1, isq = blk == 1 || blk == 3;
+    const int q = (isq ? 2 * L : 0) + (from ? l : L + l);  // index inside the p, q entries
+    const double* wb = W + b * rows.m;
+    const int bus = from ? rows.f_bus[l] : rows.t_bus[l];
+    const double g1 = 2.0 * X[b * rows.n + rows.pq0 + q] * wb[(from ? rows.thf : rows.tht) + l] +
+                      wb[(isq ? rows.balq : rows.balp) + bus];
+    Wt[b * rows.m + rows.flow0 + rr] = -(g1 + gpq[b * rows.npq + q]);
+}
+__global__ void copy_off_flow_kernel(const double* __restrict__ W, ProxRows rows, int B, double* __restrict__ Wt) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)B * rows.m) return;
-    const int64_t b = idx / rows.m;
     const int r = (int)(idx % rows.m);
-    double w;
-    if (r >= rows.flow0 && r < rows.flow1) {
-        // flow rows p_fr[L], q_fr[L], p_to[L], q_to[L]
-        const int L = rows.L;
-        const int rr = r - rows.flow0;
-        const int blk = rr / L, l = rr % L;
-        const bool from = blk == 0 || blk == 1, isq = blk == 1 || blk == 3;
-        const int q = (isq ? 2 * L : 0) + (from ? l : L + l);  // index inside the p, q entries
-        const double* wb = W + b * rows.m;
-        const int bus = from ? rows.f_bus[l] : rows.t_bus[l];
-        const double g1 = 2.0 * X[b * rows.n + rows.pq0 + q] * wb[(from ? rows.thf : rows.tht) + l] +
-                          wb[(isq ? rows.balq : rows.balp) + bus];
-        w = -(g1 + gpq[b * rows.npq + q]);
-    } else {
-        w = W[idx];
-    }
-    Wt[idx] = w;
+    if (r < rows.flow0 || r >= rows.flow1) Wt[idx] = W[idx];
 }
 
 // gX [B, n] = wb[b] * (gX1 + gX2 + obj_scale * gObj) on the va, vm, pg, qg
@@ -576,7 +578,6 @@ hipError_t prox_colsum(const float* X, int M, int N, float* part, float* out, fl
     return hipGetLastError();
 }
 
-int prox_colsum_chunks(int M) { return (M + COLSUM_ROWS - 1) / COLSUM_ROWS; }
 
 hipError_t prox_adam(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2, float eps,
                      int step, hipStream_t s) {
@@ -608,9 +609,14 @@ hipError_t prox_penalty(const double* C, const double* X, const double* F, doubl
 
 hipError_t prox_vjp_weights(const double* X, const double* W, const double* gpq, const ProxRows& rows, int B,
                             double* Wt, hipStream_t s) {
-    const int64_t tot = (int64_t)B * rows.m;
-    hipLaunchKernelGGL(vjp_weights_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, X, W, gpq, rows, B,
-                       Wt);
+    if (Wt != W) {
+        const int64_t tot = (int64_t)B * rows.m;
+        hipLaunchKernelGGL(copy_off_flow_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, W, rows, B, Wt);
+    }
+    const int64_t nfl = (int64_t)B * (rows.flow1 - rows.flow0);
+    if (nfl > 0)
+        hipLaunchKernelGGL(vjp_weights_kernel, dim3((unsigned)((nfl + 255) / 256)), dim3(256), 0, s, X, W, gpq, rows,
+                           B, Wt);
     return hipGetLastError();
 }
 

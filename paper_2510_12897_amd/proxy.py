@@ -249,9 +249,9 @@ def _make_penalty_function():
             Xflat, W, gpq, Gf = ctx.saved_tensors
             pen = ctx.pen
             B, n = pen.B, pen.model.n
-            Wt = torch.empty_like(W)
-            _check(lib().prox_vjp_weights(pen.model.handle, _p(Xflat), _p(W), _p(gpq), B, _p(Wt), _stream()))
-            gX1 = pen.batch.jtprod(Xflat, Wt)
+            # w2 on the flow rows, in place (w is zero there and not needed again)
+            _check(lib().prox_vjp_weights(pen.model.handle, _p(Xflat), _p(W), _p(gpq), B, _p(W), _stream()))
+            gX1 = pen.batch.jtprod(Xflat, W)
             gX = torch.empty(B, n, dtype=torch.float64, device=Xflat.device)
             wb = gloss.detach().to(torch.float64).contiguous()
             _check(lib().prox_vjp_sum(pen.model.handle, _p(gX1), None, _p(Gf), float(pen.obj_scale), _p(wb), B,

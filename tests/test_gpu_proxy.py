@@ -250,6 +250,36 @@ def test_penalty_vs_oracle(dev, P):
     pen.close()
 
 
+def test_vjp_weights_in_place_equals_copy(dev, P):
+    """prox_vjp_weights writes the flow rows from W's thermal and balance rows:
+    in place and into a separate buffer give the same bits, the other rows
+    are W's, and a second in-place call changes nothing."""
+    from paper_2510_12897_amd.opf import lib
+    case = _case()
+    B = 3
+    pen = P.Penalty(case, B, rho=5.0, obj_scale=1e-3)
+    m, n, L = pen.model.m, pen.model.n, case["n_branch"]
+    rng = np.random.default_rng(3)
+    X = torch.as_tensor(rng.standard_normal(B * n), device=dev)
+    W = torch.as_tensor(rng.standard_normal(B * m), device=dev)
+    gpq = torch.as_tensor(rng.standard_normal(B * 4 * L), device=dev)
+    Wt = torch.full_like(W, float("nan"))
+    assert lib().prox_vjp_weights(pen.model.handle, P._p(X), P._p(W), P._p(gpq), B, P._p(Wt), P._stream()) == 0
+    W2 = W.clone()
+    assert lib().prox_vjp_weights(pen.model.handle, P._p(X), P._p(W2), P._p(gpq), B, P._p(W2), P._stream()) == 0
+    W3 = W2.clone()
+    assert lib().prox_vjp_weights(pen.model.handle, P._p(X), P._p(W3), P._p(gpq), B, P._p(W3), P._stream()) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(Wt, W2) and torch.equal(W2, W3)
+    f0, f1 = pen.model.block("p_fr")[0], pen.model.block("angle")[0]
+    off = np.ones(m, bool)
+    off[f0:f1] = False
+    for b in range(B):
+        assert torch.equal(Wt[b * m:(b + 1) * m][torch.as_tensor(off, device=dev)],
+                           W[b * m:(b + 1) * m][torch.as_tensor(off, device=dev)])
+    pen.close()
+
+
 def test_penalty_vjp_vs_finite_differences(dev, P):
     """The hand-written VJP (J^T w, chained through p = F(vm, va)) against
     central differences of the oracle's loss, and torch's gradcheck."""
