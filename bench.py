@@ -40,13 +40,28 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_set_10k_hbm_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_12897_amd", "csrc", f) for f in ("eval_kernels.hip", "dev_model.h")]
 
 
-def kernel_hash() -> str:
+def _code_only(text: str) -> str:
+    """Source text without comments and whitespace (a comment edit does not
+    change the kernels the counters were taken on)."""
+    import re
+
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return "".join(text.split())
+
+
+def kernel_hash(texts=None) -> str:
+    """sha256 of the kernel sources' code (comments and whitespace removed)."""
     import hashlib
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+    if texts is None:
+        texts = []
+        for f in KERNEL_SOURCES:
+            with open(f, encoding="utf-8") as fh:
+                texts.append(fh.read())
+    for t in texts:
+        h.update(_code_only(t).encode())
     return h.hexdigest()
 
 

@@ -3,19 +3,22 @@
 //
 // Every output entry is written exactly once by the work item that owns it,
 // with no floating-point atomics; every sum runs in an order fixed by the
-// model, so every launch shape (plain grid, persistent batch, any replica
-// grouping) gives bitwise the same results.
+// model, so a launch shape gives bitwise the same results however its items
+// are scheduled (plain grid, flat or persistent batch grid).
 //
-// A callback set runs in two phases, each a 64-lane-workgroup launch, and
-// each phase writes only outputs laid out in its own order, so every store
-// of a wave lands in a few contiguous runs (no scattered partial-line
-// writes, which the per-XCD L2s would each write back separately):
+// Two-launch shape (large models, batches, J^T v): a callback set runs in
+// two phases, each a 64-lane-workgroup launch, and each phase writes only
+// outputs laid out in its own order, so every store of a wave lands in a few
+// contiguous runs (no scattered partial-line writes, which the per-XCD L2s
+// would each write back separately):
 //  phase 1, branch items (one lane per branch, branch order, so branch data,
 //    multipliers and arc variables are read coalesced; only the four bus
 //    voltages are gathered): the four flow rows, the angle row and the two
 //    thermal rows (c, J), the arc Hessian diagonals, and one 48-byte record
 //    per half-edge (the weighted second derivatives of the branch's flow
 //    rows and the arc's p, q), written contiguously in branch order;
+//    generator items: the gradient, the pg Hessian diagonal, reference and
+//    ramp rows, and one objective partial per (chunk, replica);
 //  phase 2, bus items: waves of packed bus segments [head, half-edges,
 //    generators] (the host packs them so no segment straddles a wave and
 //    precomputes every lane's output positions).  Each half-edge lane reads
@@ -25,13 +28,17 @@
 //    of each neighbour group writes the group's off-diagonal Hessian
 //    entries (parallel branches summed); all of these sit in the bus's own
 //    Hessian rows.  Buses wider than a wave are reduced by a whole
-//    workgroup; generator items write the gradient, the pg Hessian
-//    diagonal, reference and ramp rows, and one objective partial per
-//    (chunk, replica) -- the chunk whose arrival completes a self-resetting
-//    ticket sums the partials in index order.
+//    workgroup; the objective item sums the partials in index order.
 // Workgroups are dealt to the 8 XCDs round-robin; both launches remap the
 // block index so that each XCD takes a contiguous range of work items, and
 // the cache lines that neighbouring items share meet in one L2.
+//
+// One-launch shape (plain sets of small models, which are latency-bound):
+// the same items in one launch, dealt round-robin.  Bus half-edge lanes
+// recompute their record from x, y and a slot-ordered copy of the branch
+// terms instead of reading it, so results agree with the two-launch shape to
+// rounding, not bitwise.  The generator chunk whose arrival completes a
+// self-resetting ticket sums the objective partials in index order.
 //
 // Branch flows follow the pi model of the PowerModels formulation the paper
 // uses:  F = alpha u^2 + beta w^2 + u w (a cos(th) + b sin(th)),
