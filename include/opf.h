@@ -336,10 +336,12 @@ int prox_squash_bwd(opf_model model, const float *z, int B, double va_span, cons
  * constraint violations over the non-flow rows + squared bound violations of
  * p, q) + obj_scale * F[b] (the objective term is skipped when F is NULL);
  * cvio[b] = largest violation over every row and the p, q bounds (the
- * paper's Cvio, Sec. V-A); W [B, m] = d pen / d c (zero on the flow rows);
- * gpq [B, 4L] = d pen / d (p, q). */
+ * paper's Cvio, Sec. V-A); W [B, m] = d pen / d c on the non-flow rows;
+ * gpq [B, 4L] = d pen / d (p, q).  The flow rows of W receive 0, or with
+ * vjp != 0 the weights of prox_vjp_weights (computed in the same pass), so
+ * that J^T W is the whole constraint part of the gradient. */
 int prox_penalty(opf_model model, const double *C, const double *X, const double *F, double obj_scale, double rho,
-                 int B, double *pen, double *cvio, double *W, double *gpq, void *stream);
+                 int B, int vjp, double *pen, double *cvio, double *W, double *gpq, void *stream);
 
 /* Wt [B, m] = W + W2 for the penalty's VJP through p, q = F(vm, va): W2 is
  * minus (G1 + gpq) of each arc variable placed on its flow row, G1 = J^T W
@@ -351,13 +353,13 @@ int prox_penalty(opf_model model, const double *C, const double *X, const double
 int prox_vjp_weights(opf_model model, const double *X, const double *W, const double *gpq, int B, double *Wt,
                      void *stream);
 
-/* gX [B, n] = wb[b] * (gX1 + gX2 + obj_scale * gObj) on the va, vm, pg, qg
- * entries, zero on the arc variables p, q (which the proxy sets to the
- * branch flows, so they are not free); wb [B] is a device vector (the
- * incoming gradient of each instance's loss).  gX2 and gObj may be NULL. */
-int prox_vjp_sum(opf_model model, const double *gX1, const double *gX2, const double *gObj, double obj_scale,
+/* gX [B, n] = wb[b] * (gX1 + gX2 + obj_scale * grad f(X)) on the va, vm,
+ * pg, qg entries, zero on the arc variables p, q (which the proxy sets to
+ * the branch flows, so they are not free); grad f = 2 c2 pg + c1 on the pg
+ * entries.  wb [B] is a device vector (the incoming gradient of each
+ * instance's loss).  gX2 may be NULL; X may be NULL when obj_scale is 0. */
+int prox_vjp_sum(opf_model model, const double *X, const double *gX1, const double *gX2, double obj_scale,
                  const double *wb, int B, double *gX, void *stream);
-
 #ifdef __cplusplus
 }
 #endif

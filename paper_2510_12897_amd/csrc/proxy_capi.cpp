@@ -142,11 +142,11 @@ int prox_squash_bwd(opf_model model, const float* z, int B, double va_span, cons
 }
 
 int prox_penalty(opf_model model, const double* C, const double* X, const double* F, double obj_scale, double rho,
-                 int B, double* pen, double* cvio, double* W, double* gpq, void* stream) {
+                 int B, int vjp, double* pen, double* cvio, double* W, double* gpq, void* stream) {
     if (int rc = static_model(model)) return rc;
     if (B < 1 || !C || !X || !pen || !cvio || !W || !gpq) return set_err(OPF_E_ARG, "bad arguments");
     DeviceGuard dg(model->device);
-    return launched(opf::prox_penalty(C, X, F, obj_scale, rows_of(model), rho, B, pen, cvio, W, gpq,
+    return launched(opf::prox_penalty(C, X, F, obj_scale, rows_of(model), rho, B, pen, cvio, W, gpq, vjp ? 1 : 0,
                                       static_cast<hipStream_t>(stream)),
                     "prox_penalty launch");
 }
@@ -160,13 +160,15 @@ int prox_vjp_weights(opf_model model, const double* X, const double* W, const do
                     "prox_vjp_weights launch");
 }
 
-int prox_vjp_sum(opf_model model, const double* gX1, const double* gX2, const double* gObj, double obj_scale,
+int prox_vjp_sum(opf_model model, const double* X, const double* gX1, const double* gX2, double obj_scale,
                  const double* wb, int B, double* gX, void* stream) {
     if (int rc = static_model(model)) return rc;
     if (B < 1 || !gX1 || !wb || !gX) return set_err(OPF_E_ARG, "bad arguments");
+    if (obj_scale != 0.0 && !X) return set_err(OPF_E_ARG, "X is needed for the objective term");
     const opf::Layout& ly = model->hm.ly;
+    const opf::ProxObj ob{model->dm.c2, model->dm.c1, ly.x_pg, ly.G};
     DeviceGuard dg(model->device);
-    return launched(opf::prox_vjp_sum(gX1, gX2, gObj, obj_scale, wb, B, ly.n, ly.x_p, gX,
+    return launched(opf::prox_vjp_sum(obj_scale != 0.0 ? X : nullptr, gX1, gX2, ob, obj_scale, wb, B, ly.n, ly.x_p, gX,
                                       static_cast<hipStream_t>(stream)),
                     "prox_vjp_sum launch");
 }

@@ -41,10 +41,15 @@ hipError_t prox_squash_fwd(const float* z, int B, const ProxBox& box, double* X,
 hipError_t prox_squash_bwd(const float* z, int B, const ProxBox& box, const double* gX1, const double* gX2,
                            const double* gObj, double obj_scale, int64_t n, float* dz, float scale, hipStream_t s);
 hipError_t prox_penalty(const double* C, const double* X, const double* F, double obj_scale, const ProxRows& rows,
-                        double rho, int B, double* pen, double* cvio, double* W, double* gpq, hipStream_t s);
+                        double rho, int B, double* pen, double* cvio, double* W, double* gpq, int vjp, hipStream_t s);
 hipError_t prox_vjp_weights(const double* X, const double* W, const double* gpq, const ProxRows& rows, int B,
                             double* Wt, hipStream_t s);
-hipError_t prox_vjp_sum(const double* gX1, const double* gX2, const double* gObj, double obj_scale,
+// The objective's cost coefficients (device) and pg block of a static model.
+struct ProxObj {
+    const double *c2, *c1;
+    int64_t x_pg, G;
+};
+hipError_t prox_vjp_sum(const double* X, const double* gX1, const double* gX2, const ProxObj& ob, double obj_scale,
                         const double* wb, int B, int64_t n, int64_t nfree, double* gX, hipStream_t s);
 
 }  // namespace opf

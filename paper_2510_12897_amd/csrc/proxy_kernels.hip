@@ -405,6 +405,27 @@ __global__ void squash_bwd_kernel(const float* __restrict__ z, int B, ProxBox bo
     dz[idx] = (float)(d * scale);
 }
 
+// The arc flows p, q are F(vm, va): a gradient on them reaches the
+// voltages through the flow rows c = p - F, whose va / vm columns are -dF.
+// With G1 = J^T W, the arc entry of the total gradient is G1 + gpq, and
+// J^T W2 with w2 = -(G1 + gpq) on the arc's flow row carries it to va, vm.
+// G1 has a closed form on the arc variables: column p_a of J holds the flow
+// row (weight 0 in W), the branch side's thermal row (2 p_a) and the active
+// balance row of the arc's bus (1); q_a likewise with the reactive row.  So
+// the total weights Wt = W + W2 need no first product, and the VJP is the
+// single product J^T Wt.  w2 of flow row rr (0 .. 4L) of one instance:
+__device__ __forceinline__ double flow_weight(const double* x, const double* w, const double* gq, const ProxRows& rows,
+                                              int rr) {
+    // flow rows p_fr[L], q_fr[L], p_to[L], q_to[L]
+    const int L = rows.L;
+    const int blk = rr / L, l = rr % L;
+    const bool from = blk == 0 || blk == 1, isq = blk == 1 || blk == 3;
+    const int q = (isq ? 2 * L : 0) + (from ? l : L + l);  // index inside the p, q entries
+    const int bus = from ? rows.f_bus[l] : rows.t_bus[l];
+    const double g1 = 2.0 * x[rows.pq0 + q] * w[(from ? rows.thf : rows.tht) + l] + w[(isq ? rows.balq : rows.balp) + bus];
+    return -(g1 + gq[q]);
+}
+
 // Per instance b: the loss rho * (sum over non-flow rows of viol^2 + sum
 // over p, q of bound viol^2) + obj_scale * F[b] (F may be NULL), the
 // constraint violation (max over all rows and variable bounds), the weights
@@ -413,8 +434,7 @@ __global__ void squash_bwd_kernel(const float* __restrict__ z, int B, ProxBox bo
 __global__ void __launch_bounds__(256) penalty_kernel(const double* __restrict__ C, const double* __restrict__ X,
                                                       const double* __restrict__ F, double obj_scale,
                                                       ProxRows rows, double rho, double* __restrict__ pen,
-                                                      double* __restrict__ cvio, double* __restrict__ W,
-                                                      double* __restrict__ gpq) {
+                                                      double* __restrict__ cvio, double* W, double* gpq, int vjp) {
     __shared__ double s_pen[256], s_vio[256];
     const int64_t b = blockIdx.x;
     const double* c = C + b * rows.m;
@@ -453,19 +473,16 @@ __global__ void __launch_bounds__(256) penalty_kernel(const double* __restrict__
         pen[b] = F ? rho * s_pen[0] + obj_scale * F[b] : rho * s_pen[0];
         cvio[b] = s_vio[0];
     }
+    if (vjp) {  // the workgroup's W and gpq stores are visible after the barriers above
+        for (int rr = threadIdx.x; rr < rows.flow1 - rows.flow0; rr += 256)
+            w[rows.flow0 + rr] = flow_weight(x, w, gq, rows, rr);
+    }
 }
 
-// The arc flows p, q are F(vm, va): a gradient on them reaches the
-// voltages through the flow rows c = p - F, whose va / vm columns are -dF.
-// With G1 = J^T W, the arc entry of the total gradient is G1 + gpq, and
-// J^T W2 with w2 = -(G1 + gpq) on the arc's flow row carries it to va, vm.
-// G1 has a closed form on the arc variables: column p_a of J holds the flow
-// row (weight 0 in W), the branch side's thermal row (2 p_a) and the active
-// balance row of the arc's bus (1); q_a likewise with the reactive row.  So
-// the total weights Wt = W + W2 need no first product, and the VJP is the
-// single product J^T Wt.  One thread per flow row: the flow rows of Wt are
-// written from W's thermal and balance rows, which they never overlap, so Wt
-// may be W itself; a separate Wt also receives W's other rows.
+// The VJP weights on their own (prox_vjp_weights): one thread per flow row.
+// The flow rows of Wt are written from W's thermal and balance rows, which
+// they never overlap, so Wt may be W itself; a separate Wt also receives W's
+// other rows.
 __global__ void vjp_weights_kernel(const double* X, const double* W, const double* __restrict__ gpq, ProxRows rows,
                                    int B, double* Wt) {
     const int nf = rows.flow1 - rows.flow0;  // 4 L
@@ -473,16 +490,7 @@ __global__ void vjp_weights_kernel(const double* X, const double* W, const doubl
     if (idx >= (int64_t)B * nf) return;
     const int64_t b = idx / nf;
     const int rr = (int)(idx % nf);
-    // flow rows p_fr[L], q_fr[L], p_to[L], q_to[L]
-    const int L = rows.L;
-    const int blk = rr / L, l = rr % L;
-    const bool from = blk == 0 || blk == 1, isq = blk == 1 || blk == 3;
-    const int q = (isq ? 2 * L : 0) + (from ? l : L + l);  // index inside the p, q entries
-    const double* wb = W + b * rows.m;
-    const int bus = from ? rows.f_bus[l] : rows.t_bus[l];
-    const double g1 = 2.0 * X[b * rows.n + rows.pq0 + q] * wb[(from ? rows.thf : rows.tht) + l] +
-                      wb[(isq ? rows.balq : rows.balp) + bus];
-    Wt[b * rows.m + rows.flow0 + rr] = -(g1 + gpq[b * rows.npq + q]);
+    Wt[b * rows.m + rows.flow0 + rr] = flow_weight(X + b * rows.n, W + b * rows.m, gpq + b * rows.npq, rows, rr);
 }
 __global__ void copy_off_flow_kernel(const double* __restrict__ W, ProxRows rows, int B, double* __restrict__ Wt) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -491,11 +499,13 @@ __global__ void copy_off_flow_kernel(const double* __restrict__ W, ProxRows rows
     if (r < rows.flow0 || r >= rows.flow1) Wt[idx] = W[idx];
 }
 
-// gX [B, n] = wb[b] * (gX1 + gX2 + obj_scale * gObj) on the va, vm, pg, qg
-// entries (the free variables of the proxy), zero on the arc variables.
-__global__ void vjp_sum_kernel(const double* __restrict__ gX1, const double* __restrict__ gX2,
-                               const double* __restrict__ gObj, double obj_scale, const double* __restrict__ wb,
-                               int B, int64_t n, int64_t nfree, double* __restrict__ gX) {
+// gX [B, n] = wb[b] * (gX1 + gX2 + obj_scale * grad f) on the va, vm, pg, qg
+// entries (the free variables of the proxy), zero on the arc variables;
+// grad f = 2 c2 pg + c1 on the pg entries, 0 elsewhere (static model).
+__global__ void vjp_sum_kernel(const double* __restrict__ X, const double* __restrict__ gX1,
+                               const double* __restrict__ gX2, ProxObj ob, double obj_scale,
+                               const double* __restrict__ wb, int B, int64_t n, int64_t nfree,
+                               double* __restrict__ gX) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)B * n) return;
     const int64_t b = idx / n, e = idx % n;
@@ -503,7 +513,10 @@ __global__ void vjp_sum_kernel(const double* __restrict__ gX1, const double* __r
     if (e < nfree) {
         g = gX1[idx];
         if (gX2) g += gX2[idx];
-        if (gObj) g += obj_scale * gObj[idx];
+        if (X && e >= ob.x_pg && e < ob.x_pg + ob.G) {
+            const int64_t k = e - ob.x_pg;
+            g += obj_scale * (2.0 * ob.c2[k] * X[idx] + ob.c1[k]);
+        }
         g *= wb[b];
     }
     gX[idx] = g;
@@ -511,11 +524,11 @@ __global__ void vjp_sum_kernel(const double* __restrict__ gX1, const double* __r
 
 }  // namespace
 
-hipError_t prox_vjp_sum(const double* gX1, const double* gX2, const double* gObj, double obj_scale,
+hipError_t prox_vjp_sum(const double* X, const double* gX1, const double* gX2, const ProxObj& ob, double obj_scale,
                         const double* wb, int B, int64_t n, int64_t nfree, double* gX, hipStream_t s) {
     const int64_t tot = (int64_t)B * n;
-    hipLaunchKernelGGL(vjp_sum_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, gX1, gX2, gObj,
-                       obj_scale, wb, B, n, nfree, gX);
+    hipLaunchKernelGGL(vjp_sum_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, X, gX1, gX2, ob, obj_scale,
+                       wb, B, n, nfree, gX);
     return hipGetLastError();
 }
 
@@ -602,8 +615,8 @@ hipError_t prox_squash_bwd(const float* z, int B, const ProxBox& box, const doub
 }
 
 hipError_t prox_penalty(const double* C, const double* X, const double* F, double obj_scale, const ProxRows& rows,
-                        double rho, int B, double* pen, double* cvio, double* W, double* gpq, hipStream_t s) {
-    hipLaunchKernelGGL(penalty_kernel, dim3(B), dim3(256), 0, s, C, X, F, obj_scale, rows, rho, pen, cvio, W, gpq);
+                        double rho, int B, double* pen, double* cvio, double* W, double* gpq, int vjp, hipStream_t s) {
+    hipLaunchKernelGGL(penalty_kernel, dim3(B), dim3(256), 0, s, C, X, F, obj_scale, rows, rho, pen, cvio, W, gpq, vjp);
     return hipGetLastError();
 }
 

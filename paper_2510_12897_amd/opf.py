@@ -124,8 +124,8 @@ def lib():
         "prox_squash_fwd": ([_vp, _vp, ctypes.c_int, ctypes.c_double, _vp, _vp], ctypes.c_int),
         "prox_squash_bwd": ([_vp, _vp, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, ctypes.c_double, _vp,
                              ctypes.c_float, _vp], ctypes.c_int),
-        "prox_penalty": ([_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, _vp, _vp, _vp, _vp,
-                          _vp], ctypes.c_int),
+        "prox_penalty": ([_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, _vp, _vp,
+                          _vp, _vp, _vp], ctypes.c_int),
         "prox_vjp_weights": ([_vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp], ctypes.c_int),
         "prox_vjp_sum": ([_vp, _vp, _vp, _vp, ctypes.c_double, _vp, ctypes.c_int, _vp, _vp], ctypes.c_int),
     }

@@ -21,8 +21,9 @@ Every step runs in libopf's kernels (argument marshalling only here):
   (``prox_penalty``); its backward is the hand-written vector-Jacobian
   product J^T (w + w2): w the penalty weights, w2 the weights on the flow
   rows that carry the arc-flow gradient back through p = F(vm, va), built
-  in closed form (``prox_vjp_weights``), then one ``opf_batch_jtprod`` and
-  ``prox_vjp_sum``.
+  in closed form by the penalty pass itself when a gradient will follow
+  (``prox_penalty`` with ``vjp``), then one ``opf_batch_jtprod`` and
+  ``prox_vjp_sum`` (which adds the objective gradient 2 c2 pg + c1).
 """
 from __future__ import annotations
 
@@ -229,32 +230,32 @@ def _make_penalty_function():
             B, m = pen.B, pen.model.m
             dev = X.device
             Fo = torch.empty(B, dtype=torch.float64, device=dev)
-            Gf = torch.empty(B * pen.model.n, dtype=torch.float64, device=dev)
             C = torch.empty(B * m, dtype=torch.float64, device=dev)
             Xflat = Xf.view(-1)
-            pen.batch.eval(Xflat, F=Fo, G=Gf, C=C)
+            pen.batch.eval(Xflat, F=Fo, C=C)
             loss = torch.empty(B, dtype=torch.float64, device=dev)
             cvio = torch.empty(B, dtype=torch.float64, device=dev)
             W = torch.empty(B * m, dtype=torch.float64, device=dev)
             gpq = torch.empty(B * 4 * pen.L, dtype=torch.float64, device=dev)
+            # with a gradient to come, the flow rows of W get the VJP weights
+            # in the same pass (prox_vjp_weights' closed form)
+            vjp = int(bool(ctx.needs_input_grad[0]))
             _check(lib().prox_penalty(pen.model.handle, _p(C), _p(Xflat), _p(Fo), float(pen.obj_scale),
-                                      float(pen.rho), B, _p(loss), _p(cvio), _p(W), _p(gpq), _stream()))
+                                      float(pen.rho), B, vjp, _p(loss), _p(cvio), _p(W), _p(gpq), _stream()))
             pen.last = {"x": Xf, "f": Fo, "c": C.view(B, m), "cvio": cvio}
-            ctx.save_for_backward(Xflat, W, gpq, Gf)
+            ctx.save_for_backward(Xflat, W)
             ctx.pen = pen
             return loss
 
         @staticmethod
         def backward(ctx, gloss):
-            Xflat, W, gpq, Gf = ctx.saved_tensors
+            Xflat, W = ctx.saved_tensors
             pen = ctx.pen
             B, n = pen.B, pen.model.n
-            # w2 on the flow rows, in place (w is zero there and not needed again)
-            _check(lib().prox_vjp_weights(pen.model.handle, _p(Xflat), _p(W), _p(gpq), B, _p(W), _stream()))
-            gX1 = pen.batch.jtprod(Xflat, W)
+            gX1 = pen.batch.jtprod(Xflat, W)  # W holds the VJP weights on the flow rows
             gX = torch.empty(B, n, dtype=torch.float64, device=Xflat.device)
             wb = gloss.detach().to(torch.float64).contiguous()
-            _check(lib().prox_vjp_sum(pen.model.handle, _p(gX1), None, _p(Gf), float(pen.obj_scale), _p(wb), B,
+            _check(lib().prox_vjp_sum(pen.model.handle, _p(Xflat), _p(gX1), None, float(pen.obj_scale), _p(wb), B,
                                       _p(gX), _stream()))
             return gX, None
 

@@ -280,6 +280,37 @@ def test_vjp_weights_in_place_equals_copy(dev, P):
     pen.close()
 
 
+def test_penalty_fused_vjp_weights(dev, P):
+    """prox_penalty with vjp != 0 writes on the flow rows exactly what
+    prox_vjp_weights computes from its plain output, and nothing else
+    changes."""
+    from paper_2510_12897_amd.opf import lib
+    case = _case()
+    B = 3
+    pen = P.Penalty(case, B, rho=4.0, obj_scale=1e-3)
+    m, n, L = pen.model.m, pen.model.n, case["n_branch"]
+    rng = np.random.default_rng(8)
+    C = torch.as_tensor(rng.standard_normal(B * m), device=dev)
+    X = torch.as_tensor(rng.standard_normal(B * n), device=dev)
+    F = torch.as_tensor(rng.standard_normal(B), device=dev)
+    outs = []
+    for vjp in (0, 1):
+        o = [torch.empty(B, dtype=torch.float64, device=dev) for _ in range(2)] + [
+            torch.full((B * m,), float("nan"), dtype=torch.float64, device=dev),
+            torch.full((B * 4 * L,), float("nan"), dtype=torch.float64, device=dev)]
+        assert lib().prox_penalty(pen.model.handle, P._p(C), P._p(X), P._p(F), 1e-3, 4.0, B, vjp, *[P._p(t) for t in o],
+                                  P._stream()) == 0
+        outs.append(o)
+    Wt = outs[0][2].clone()
+    assert lib().prox_vjp_weights(pen.model.handle, P._p(X), P._p(outs[0][2]), P._p(outs[0][3]), B, P._p(Wt),
+                                  P._stream()) == 0
+    torch.cuda.synchronize()
+    for a, b in zip(outs[0][:2] + outs[0][3:], outs[1][:2] + outs[1][3:]):
+        assert torch.equal(a, b)
+    assert torch.equal(outs[1][2], Wt)
+    pen.close()
+
+
 def test_penalty_vjp_vs_finite_differences(dev, P):
     """The hand-written VJP (J^T w, chained through p = F(vm, va)) against
     central differences of the oracle's loss, and torch's gradcheck."""
