@@ -37,6 +37,9 @@ enum RecField : int32_t { R_TT = 0, R_MA, R_MM, R_UW, R_P, R_Q, kRec };
 // and with each record fetched by four cooperating lanes: the extra bytes
 // written cost more than the aligned reads save.
 constexpr int kRecStride = kRec;
+// A set without the Hessian needs only the arc values of each half-edge:
+// records [P, Q], 16 bytes apart, in the same per-side arrays.
+constexpr int kRecPQ = 2;
 
 constexpr int kBlock = 64;          // threads per workgroup (one wave), every task
 constexpr int kXcd = 8;             // XCDs; workgroups are dealt to them round-robin

@@ -332,15 +332,20 @@ __device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, 
             st(o.H + m.h_q + oa, l, 2.0 * yf);
             st(o.H + m.h_q + oa + L, l, 2.0 * yt);
         }
-        if ((wantH || wantC) && !SINGLE) {
+        if (wantH && !SINGLE) {
             // the half-edge records [TT, MA, MM, UW, P, Q] of each side
-            Hterms h{};
-            if (wantH) h = hess_terms(k, y1, y2, y3, y4, u, w, C, S);
+            const Hterms h = hess_terms(k, y1, y2, y3, y4, u, w, C, S);
             // d/dva_f = d/dth, d/dva_t = -d/dth
             const double rf[kRecStride] = {h.Stt, h.Sut, h.Suu, h.Suw, pf, qf};
             store_run<kRecStride>(stage, rec_side(m, r, 0), kRecStride * l0, nvalid, rf);
             const double rt[kRecStride] = {h.Stt, -h.Swt, h.Sww, h.Suw, pt, qt};
             store_run<kRecStride>(stage, rec_side(m, r, 1), kRecStride * l0, nvalid, rt);
+        } else if (wantC && !SINGLE) {
+            // no Hessian: compact records [P, Q] (the balance rows need nothing else)
+            const double rf[kRecPQ] = {pf, qf};
+            store_run<kRecPQ>(stage, rec_side(m, r, 0), kRecPQ * l0, nvalid, rf);
+            const double rt[kRecPQ] = {pt, qt};
+            store_run<kRecPQ>(stage, rec_side(m, r, 1), kRecPQ * l0, nvalid, rt);
         }
     }
     if (o.g && act) {
@@ -462,16 +467,20 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
             half_edge_record(m, o, ref, side, side ? other : bus, side ? bus : other, k, r, v);
         } else if (type == SK_EDGE) {
             const double2* rec = reinterpret_cast<const double2*>(rec_side(m, r, (int32_t)side));
-            const uint32_t q = (kRecStride / 2) * ref;
             if (wantH) {
+                const uint32_t q = (kRecStride / 2) * ref;
                 const double2 a = ld(rec, q), b = ld(rec, q + 1);
                 v[R_TT] = a.x;
                 v[R_MA] = a.y;
                 v[R_MM] = b.x;
                 v[R_UW] = b.y;
-            }
-            if (wantC) {
-                const double2 c = ld(rec, q + 2);
+                if (wantC) {
+                    const double2 c = ld(rec, q + 2);
+                    v[R_P] = c.x;
+                    v[R_Q] = c.y;
+                }
+            } else if (wantC) {  // compact records
+                const double2 c = ld(rec, ref);
                 v[R_P] = c.x;
                 v[R_Q] = c.y;
             }
@@ -589,9 +598,14 @@ __device__ __forceinline__ void big_record(const DevModel& m, const EvalOut& o, 
         for (int q = 0; q < kRec; q++) v[q] = 0.0;
         const Coef k = o.H ? load_coef(m, l) : Coef{};
         half_edge_record(m, o, l, side, (uint32_t)ld(m.f_bus, l), (uint32_t)ld(m.t_bus, l), k, r, v);
-    } else {
+    } else if (o.H) {
         const double* rec = (side == 0 ? rec0 : rec1) + (int64_t)l * kRecStride;
         for (int q = 0; q < kRec; q++) v[q] = rec[q];
+    } else {  // compact records [P, Q]
+        const double* rec = (side == 0 ? rec0 : rec1) + (int64_t)l * kRecPQ;
+        for (int q = 0; q < kRec; q++) v[q] = 0.0;
+        v[R_P] = rec[0];
+        v[R_Q] = rec[1];
     }
 }
 
