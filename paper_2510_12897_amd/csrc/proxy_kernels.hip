@@ -449,7 +449,7 @@ __global__ void __launch_bounds__(256) penalty_kernel(const double* __restrict__
         sv = fmax(sv, fabs(dv));
         const bool flow = r >= rows.flow0 && r < rows.flow1;
         if (!flow) sp += dv * dv;
-        w[r] = flow ? 0.0 : 2.0 * rho * dv;
+        if (!(flow && vjp)) w[r] = flow ? 0.0 : 2.0 * rho * dv;  // with vjp the flow rows come below
     }
     for (int q = threadIdx.x; q < rows.npq; q += 256) {
         const double xv = x[rows.pq0 + q];
