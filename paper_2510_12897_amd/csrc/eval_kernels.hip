@@ -90,8 +90,9 @@ __device__ __forceinline__ Coef in_service(const Coef& k, const DevModel& m, int
 }
 
 // Half-edge records of one side (0: from bus, 1: to bus) and replica r:
-// one 64-byte record per branch, branches in order; the two sides are
-// separate arrays, so one wave writes each side as one contiguous run.
+// one record per branch (48 bytes, or 16 without the Hessian), branches in
+// order; the two sides are separate arrays, so one wave writes each side as
+// one contiguous run.
 __device__ __forceinline__ double* rec_side(const DevModel& m, int32_t r, int32_t side) {
     return m.rec + ((int64_t)side * m.nrep + r) * m.L * kRecStride;
 }
@@ -205,24 +206,41 @@ __device__ __forceinline__ void flow_jrow(const Flow1& fl, bool f_lo, double (&v
 
 // The half-edge record [TT, MA, MM, UW, P, Q] of branch l at one side (0:
 // from, 1: to), recomputed from x and y with the branch task's arithmetic:
-// a single launch reads nothing the branch items write.
-__device__ __forceinline__ void half_edge_record(const DevModel& m, const EvalOut& o, uint32_t l, uint32_t side,
-                                                 uint32_t fb, uint32_t tb, const Coef& k0, int32_t r,
-                                                 double (&v)[kRec]) {
+// a single launch reads nothing the branch items write.  Split into its
+// loads and its arithmetic so that a wave can issue the loads of all its
+// lane types before it waits for any.
+struct HeIn {
+    double p, q, y1, y2, y3, y4, u, w, vaf, vat;
+};
+__device__ __forceinline__ void half_edge_load(const DevModel& m, const EvalOut& o, uint32_t l, uint32_t side,
+                                               uint32_t fb, uint32_t tb, int32_t r, HeIn& e) {
     const int64_t L = m.L, N = m.N, ob = L * r, oa = 2 * L * r + (side ? L : 0), on = N * r;
     if (o.c) {
-        v[R_P] = ld(o.x + m.x_p + oa, l);
-        v[R_Q] = ld(o.x + m.x_q + oa, l);
+        e.p = ld(o.x + m.x_p + oa, l);
+        e.q = ld(o.x + m.x_q + oa, l);
     }
     if (o.H) {
-        const double y1 = ld(o.y + m.c_pfr + ob, l), y2 = ld(o.y + m.c_qfr + ob, l);
-        const double y3 = ld(o.y + m.c_pto + ob, l), y4 = ld(o.y + m.c_qto + ob, l);
-        const double u = ld(o.x + m.x_vm + on, fb), w = ld(o.x + m.x_vm + on, tb);
-        const double vaf = ld(o.x + m.x_va + on, fb), vat = ld(o.x + m.x_va + on, tb);
+        e.y1 = ld(o.y + m.c_pfr + ob, l);
+        e.y2 = ld(o.y + m.c_qfr + ob, l);
+        e.y3 = ld(o.y + m.c_pto + ob, l);
+        e.y4 = ld(o.y + m.c_qto + ob, l);
+        e.u = ld(o.x + m.x_vm + on, fb);
+        e.w = ld(o.x + m.x_vm + on, tb);
+        e.vaf = ld(o.x + m.x_va + on, fb);
+        e.vat = ld(o.x + m.x_va + on, tb);
+    }
+}
+__device__ __forceinline__ void half_edge_record(const DevModel& m, const EvalOut& o, const HeIn& e, uint32_t l,
+                                                 uint32_t side, const Coef& k0, int32_t r, double (&v)[kRec]) {
+    if (o.c) {
+        v[R_P] = e.p;
+        v[R_Q] = e.q;
+    }
+    if (o.H) {
         const Coef k = in_service(k0, m, (int32_t)l, r);
         double S, C;
-        sincos(vaf - vat, &S, &C);
-        const Hterms h = hess_terms(k, y1, y2, y3, y4, u, w, C, S);
+        sincos(e.vaf - e.vat, &S, &C);
+        const Hterms h = hess_terms(k, e.y1, e.y2, e.y3, e.y4, e.u, e.w, C, S);
         v[R_TT] = h.Stt;
         v[R_MA] = side ? -h.Swt : h.Sut;
         v[R_MM] = side ? h.Sww : h.Suu;
@@ -430,65 +448,89 @@ __device__ __forceinline__ Slot load_slot(const DevModel& m, int32_t w) {
 template <bool SINGLE>
 __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_t r, double* lds) {
     const int32_t lane = threadIdx.x;
+    const bool wantC = o.c != nullptr, wantH = o.H != nullptr;
+    // one launch: a half-edge lane's branch terms depend only on the lane,
+    // so they load together with the descriptor
+    Coef k{};
+    if (SINGLE && wantH) {
+        const double2* kc = reinterpret_cast<const double2*>(m.slot_coef) + (size_t)w * kBlock * 4;
+        const double2 c01 = ld(kc, 4 * lane), c23 = ld(kc, 4 * lane + 1);
+        const double2 c45 = ld(kc, 4 * lane + 2), c67 = ld(kc, 4 * lane + 3);
+        k = Coef{c01.x, c01.y, c23.x, c23.y, c45.x, c45.y, c67.x, c67.y};
+    }
     const Slot sl = load_slot(m, w);
     const int32_t type = sl.kind & 3;
     const uint32_t side = (sl.kind & 4) ? 0u : 1u;  // the half-edge sits at its branch's from bus
     const bool leader = sl.kind & 8;
     const int32_t len = (sl.kind >> 8) & 0xff;  // segment (head) or group (leader) length
-    const bool wantC = o.c != nullptr, wantH = o.H != nullptr;
     const int64_t N = m.N, G = m.G;
     const uint32_t bus = (uint32_t)sl.bus, ref = (uint32_t)sl.ref;
-    double gs = 0.0, bs = 0.0;
-    if (type == SK_HEAD) {
-        gs = ld(m.gs, bus);
-        bs = ld(m.bs, bus);
-    }
     {  // replica r
         const int64_t on = N * r;
-        double v[kRec] = {0, 0, 0, 0, 0, 0};
-        double vm_i = 0.0, base_p = 0.0, base_q = 0.0, shunt = 0.0;
+        // every lane type issues its loads before any arithmetic: the lane
+        // types of a wave run one after another, and a type that used its
+        // loads before the next type's branch would cost the wave one
+        // memory round trip per lane type.  The loaded values are read only
+        // under their own lane type and get no default: writing a default
+        // into a register another type's load is still filling would make
+        // the wave wait for that load.
+        double gs, bs, vm_i, pd, qd, yp, yq, gp, gq;
+        double2 ra, rb, rc;
+        HeIn e;
         if (type == SK_HEAD) {
+            gs = ld(m.gs, bus);
+            bs = ld(m.bs, bus);
             vm_i = ld(o.x + m.x_vm + on, bus);
             if (wantC) {
                 const int64_t ol = (int64_t)m.load_stride * r;
-                base_p = ld(m.pd + ol, bus) + gs * vm_i * vm_i;
-                base_q = ld(m.qd + ol, bus) - bs * vm_i * vm_i;
+                pd = ld(m.pd + ol, bus);
+                qd = ld(m.qd + ol, bus);
             }
-            if (wantH) shunt = 2.0 * gs * ld(o.y + m.c_balp + on, bus) - 2.0 * bs * ld(o.y + m.c_balq + on, bus);
-        } else if (type == SK_EDGE && SINGLE) {
-            Coef k{};
             if (wantH) {
-                const double2* kc = reinterpret_cast<const double2*>(m.slot_coef) + (size_t)w * kBlock * 4;
-                const double2 c01 = ld(kc, 4 * lane), c23 = ld(kc, 4 * lane + 1);
-                const double2 c45 = ld(kc, 4 * lane + 2), c67 = ld(kc, 4 * lane + 3);
-                k = Coef{c01.x, c01.y, c23.x, c23.y, c45.x, c45.y, c67.x, c67.y};
+                yp = ld(o.y + m.c_balp + on, bus);
+                yq = ld(o.y + m.c_balq + on, bus);
             }
+        } else if (type == SK_EDGE && SINGLE) {
             const uint32_t other = (uint32_t)sl.other;
-            half_edge_record(m, o, ref, side, side ? other : bus, side ? bus : other, k, r, v);
+            half_edge_load(m, o, ref, side, side ? other : bus, side ? bus : other, r, e);
         } else if (type == SK_EDGE) {
             const double2* rec = reinterpret_cast<const double2*>(rec_side(m, r, (int32_t)side));
             if (wantH) {
                 const uint32_t q = (kRecStride / 2) * ref;
-                const double2 a = ld(rec, q), b = ld(rec, q + 1);
-                v[R_TT] = a.x;
-                v[R_MA] = a.y;
-                v[R_MM] = b.x;
-                v[R_UW] = b.y;
-                if (wantC) {
-                    const double2 c = ld(rec, q + 2);
-                    v[R_P] = c.x;
-                    v[R_Q] = c.y;
-                }
-            } else if (wantC) {  // compact records
-                const double2 c = ld(rec, ref);
-                v[R_P] = c.x;
-                v[R_Q] = c.y;
+                ra = ld(rec, q);
+                rb = ld(rec, q + 1);
+                if (wantC) rc = ld(rec, q + 2);
+            } else if (wantC) {  // compact records [P, Q]
+                rc = ld(rec, ref);
             }
-        } else if (type == SK_GEN) {
+        } else if (type == SK_GEN && wantC) {
+            gp = ld(o.x + m.x_pg + G * (m.npg > 1 ? r : 0), ref);
+            gq = ld(o.x + m.x_qg + G * r, ref);
+        }
+        double v[kRec] = {0, 0, 0, 0, 0, 0};
+        double base_p = 0.0, base_q = 0.0, shunt = 0.0;
+        if (type == SK_HEAD) {
             if (wantC) {
-                v[R_P] = -ld(o.x + m.x_pg + G * (m.npg > 1 ? r : 0), ref);
-                v[R_Q] = -ld(o.x + m.x_qg + G * r, ref);
+                base_p = pd + gs * vm_i * vm_i;
+                base_q = qd - bs * vm_i * vm_i;
             }
+            if (wantH) shunt = 2.0 * gs * yp - 2.0 * bs * yq;
+        } else if (type == SK_EDGE && SINGLE) {
+            half_edge_record(m, o, e, ref, side, k, r, v);
+        } else if (type == SK_EDGE) {
+            if (wantH) {
+                v[R_TT] = ra.x;
+                v[R_MA] = ra.y;
+                v[R_MM] = rb.x;
+                v[R_UW] = rb.y;
+            }
+            if (wantC) {
+                v[R_P] = rc.x;
+                v[R_Q] = rc.y;
+            }
+        } else if (type == SK_GEN && wantC) {
+            v[R_P] = -gp;
+            v[R_Q] = -gq;
         }
         if (wantC || wantH) {
             for (int q = 0; q < kRec; q++) lds[q * kBlock + lane] = v[q];
@@ -561,14 +603,25 @@ __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int
     const double* v = o.y;
     {  // replica r
         const int64_t on = N * r;
-        double ga = 0.0, gm = 0.0;
+        // the head lanes' loads go out with the half-edge lanes' records
+        // (one memory round trip); loaded values get no default (see
+        // wave_task)
+        double2 t;
+        double vm, gs, bs, vp, vq;
+        int32_t q0, q1;
         if (type == SK_EDGE) {
-            const double2 t = ld(reinterpret_cast<const double2*>(jt_rec_side(m, r, (int32_t)side)), (uint32_t)sl.ref);
-            ga = t.x;
-            gm = t.y;
+            t = ld(reinterpret_cast<const double2*>(jt_rec_side(m, r, (int32_t)side)), (uint32_t)sl.ref);
+        } else if (type == SK_HEAD) {
+            vm = ld(x + m.x_vm + on, bus);
+            gs = ld(m.gs, bus);
+            bs = ld(m.bs, bus);
+            vp = ld(v + m.c_balp + on, bus);
+            vq = ld(v + m.c_balq + on, bus);
+            q0 = ld(m.ref_ptr, bus);
+            q1 = ld(m.ref_ptr, bus + 1);
         }
-        lds[0 * kBlock + lane] = ga;
-        lds[1 * kBlock + lane] = gm;
+        lds[0 * kBlock + lane] = type == SK_EDGE ? t.x : 0.0;
+        lds[1 * kBlock + lane] = type == SK_EDGE ? t.y : 0.0;
         __syncthreads();
         if (type == SK_HEAD) {
             double sa = 0.0, sm = 0.0;
@@ -576,11 +629,9 @@ __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int
                 sa += lds[0 * kBlock + lane + j];
                 sm += lds[1 * kBlock + lane + j];
             }
-            for (int32_t q = ld(m.ref_ptr, bus); q < ld(m.ref_ptr, bus + 1); q++)
+            for (int32_t q = q0; q < q1; q++)  // the reference row (one bus)
                 sa += ld(v + m.c_ref + (int64_t)m.R * r, (uint32_t)ld(m.ref_list, (uint32_t)q));
-            const double vm = ld(x + m.x_vm + on, bus);
-            sm += 2.0 * ld(m.gs, bus) * vm * ld(v + m.c_balp + on, bus) -
-                  2.0 * ld(m.bs, bus) * vm * ld(v + m.c_balq + on, bus);
+            sm += 2.0 * gs * vm * vp - 2.0 * bs * vm * vq;
             st(o.g + m.x_va + on, bus, sa);
             st(o.g + m.x_vm + on, bus, sm);
         }
@@ -597,7 +648,9 @@ __device__ __forceinline__ void big_record(const DevModel& m, const EvalOut& o, 
     if (SINGLE) {
         for (int q = 0; q < kRec; q++) v[q] = 0.0;
         const Coef k = o.H ? load_coef(m, l) : Coef{};
-        half_edge_record(m, o, l, side, (uint32_t)ld(m.f_bus, l), (uint32_t)ld(m.t_bus, l), k, r, v);
+        HeIn e{};
+        half_edge_load(m, o, l, side, (uint32_t)ld(m.f_bus, l), (uint32_t)ld(m.t_bus, l), r, e);
+        half_edge_record(m, o, e, l, side, k, r, v);
     } else if (o.H) {
         const double* rec = (side == 0 ? rec0 : rec1) + (int64_t)l * kRecStride;
         for (int q = 0; q < kRec; q++) v[q] = rec[q];
