@@ -309,30 +309,20 @@ __device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, 
             st(o.c + m.c_tht + ob, l, pt * pt + qt * qt - rate2);
         }
         if (wantJ) {
+            // the flow-row blocks (5 values per lane) go through LDS so that
+            // each store instruction of the wave covers consecutive addresses
+            // (in the one-launch shape too: 9.75 -> 9.41 us on the 10k-bus
+            // set); the 2-value pairs are stored directly, since staging them
+            // as well cost more in barriers than it saved (10.4 us)
             double v[5];
-            if (SINGLE) {
-                // a small model's launch is latency-bound: store the rows
-                // directly rather than through LDS
-                if (act) {
-                    const Flow1* fl[4] = {&f1, &f2, &f3, &f4};
-                    const int64_t jb[4] = {m.j_pfr, m.j_qfr, m.j_pto, m.j_qto};
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        flow_jrow(*fl[q], f_lo, v);
-#pragma unroll
-                        for (int e = 0; e < 5; e++) st(o.J + jb[q] + 5 * ob, 5 * l + e, v[e]);
-                    }
-                }
-            } else {
-                flow_jrow(f1, f_lo, v);
-                store_run<5>(stage, o.J + m.j_pfr + 5 * ob, 5 * l0, nvalid, v);
-                flow_jrow(f2, f_lo, v);
-                store_run<5>(stage, o.J + m.j_qfr + 5 * ob, 5 * l0, nvalid, v);
-                flow_jrow(f3, f_lo, v);
-                store_run<5>(stage, o.J + m.j_pto + 5 * ob, 5 * l0, nvalid, v);
-                flow_jrow(f4, f_lo, v);
-                store_run<5>(stage, o.J + m.j_qto + 5 * ob, 5 * l0, nvalid, v);
-            }
+            flow_jrow(f1, f_lo, v);
+            store_run<5>(stage, o.J + m.j_pfr + 5 * ob, 5 * l0, nvalid, v);
+            flow_jrow(f2, f_lo, v);
+            store_run<5>(stage, o.J + m.j_qfr + 5 * ob, 5 * l0, nvalid, v);
+            flow_jrow(f3, f_lo, v);
+            store_run<5>(stage, o.J + m.j_pto + 5 * ob, 5 * l0, nvalid, v);
+            flow_jrow(f4, f_lo, v);
+            store_run<5>(stage, o.J + m.j_qto + 5 * ob, 5 * l0, nvalid, v);
             if (act) {
                 // block offsets need not be even, so these pairs are stored
                 // as two 8-byte values
