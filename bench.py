@@ -338,7 +338,7 @@ def bench_points(torch, opf, synth, log, B=16):
     per = secs / 30
     shared = 80 * 13500 + 32 * 10000 + 28 * 2000 + 4 * (2 * 13500 + 2 * 10001 + 2000)
     total = B * algorithmic_bytes(cs, (model.n, model.m, model.nnzj, model.nnzh)) - (B - 1) * shared
-    log(f"10k x {B} points: {per * 1e6:.1f} us/launch, {B / per:.0f} sets/s, {total / per / 1e9:.0f} GB/s")
+    log(f"10k x {B} points (wg_per_cu={sched}): {per * 1e6:.1f} us/launch, {B / per:.0f} sets/s, {total / per / 1e9:.0f} GB/s")
     b.close()
     model.close()
     return dict(workload=f"10000-bus network at {B} seeded (x, y) points per batched launch", points=B,
