@@ -180,19 +180,24 @@ def test_runs_are_bitwise_deterministic(shape):
     model.close()
 
 
-def test_launch_shapes_agree_to_rounding():
+@pytest.mark.parametrize("which", ["ragged700", "hub_sc2"])
+def test_launch_shapes_agree_to_rounding(which):
     """The single launch (bus items recompute the branch terms) and the two
-    launches (records) agree within the tolerance on one model."""
-    name, cs, opts = CASES[-1]
-    x, y = synth.point(cs, 5), None
-    outs = []
+    launches (records) agree within the tolerance on one model (hub_sc2:
+    buses wider than a wave, contingency copies)."""
+    name, cs, opts = [c for c in CASES if c[0] == which][0]
+    T, K = opts.get("n_periods", 1), opts.get("n_cont", 0)
+    x, y = synth.point(cs, 5, n_periods=T, n_cont=K), None
+    outs, shapes = [], []
     for lim in (4096, 0):
         opf.set_single_launch_limit(lim)
         model = opf.Model(cs, **opts)
+        shapes.append(model.launch_shape()[0])
         y = synth.multipliers(model.m, 5)
         outs.append([t.cpu().numpy() for t in model.eval_set(to_dev(x), to_dev(y), 0.8)])
         model.close()
     opf.set_single_launch_limit(4096)
+    assert shapes == [1, 2]
     res = O.evaluate(cs, x, y, 0.8, **opts)
     for a, b, sc in zip(outs[0][1:], outs[1][1:], (np.abs(res["g"]), res["cscale"], res["jscale"], res["hscale"])):
         assert_close(a, b, sc, what="single vs two launches")
