@@ -1080,11 +1080,16 @@ __global__ void __launch_bounds__(kBlock, 6) bus_kernel(DevModel m, EvalOut o, S
 // range, so no queue counter is needed and neighbouring items share an L2.
 // Flat (one workgroup per item, no loop, so fewer registers): the block
 // index is remapped to the same XCD ranges.
+// The kernel's MODE equals a.mode for every launch that runs items (the bus
+// phase of the flows mode has none).  Taking the mode from the template
+// leaves one assignment per field: a branch on a.mode made the compiler
+// keep this struct in private (scratch) memory.
+template <int MODE>
 __device__ __forceinline__ EvalOut batch_out(const BatchArgs& a, const BatchInst& bi, int32_t inst) {
     EvalOut o;
     o.single = 0;  // batches always take the two-launch shape (records, objective items)
     o.x = a.X + bi.xoff;
-    if (a.mode == 0) {
+    if constexpr (MODE == 0) {
         o.y = a.Y ? a.Y + bi.coff : nullptr;
         o.sigma = a.sigma ? a.sigma[inst] : 0.0;
         o.f = a.F ? a.F + inst : nullptr;
@@ -1093,10 +1098,12 @@ __device__ __forceinline__ EvalOut batch_out(const BatchArgs& a, const BatchInst
         o.J = a.J ? a.J + bi.joff : nullptr;
         o.H = a.H ? a.H + bi.hoff : nullptr;
     } else {  // J^T v (Y holds V, G holds OUT) or flows (G is X, written in place)
-        o.y = a.mode == 1 ? a.Y + bi.coff : nullptr;
+        o.y = MODE == 1 ? a.Y + bi.coff : nullptr;
         o.sigma = 0.0;
         o.f = nullptr;
-        o.c = o.J = o.H = nullptr;
+        o.c = nullptr;
+        o.J = nullptr;
+        o.H = nullptr;
         o.g = a.G + bi.xoff;
     }
     return o;
@@ -1118,7 +1125,7 @@ __global__ void __launch_bounds__(kBlock) batch_branch_kernel(BatchArgs a) {
     for (; it < end; it += step) {
         const BatchItem w = a.items[it];
         const BatchInst& bi = a.inst[w.inst];
-        run_phase1<MODE>(bi.m, batch_out(a, bi, w.inst), w.kind, w.idx, w.r, stage);
+        run_phase1<MODE>(bi.m, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, stage);
     }
 }
 
@@ -1130,7 +1137,7 @@ __global__ void __launch_bounds__(kBlock) batch_bus_kernel(BatchArgs a) {
     for (; it < end; it += step) {
         const BatchItem w = a.items[it];
         const BatchInst& bi = a.inst[w.inst];
-        run_phase2<MODE>(bi.m, batch_out(a, bi, w.inst), w.kind, w.idx, w.r, lds);
+        run_phase2<MODE>(bi.m, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, lds);
         __syncthreads();
     }
 }
@@ -1142,7 +1149,7 @@ __global__ void __launch_bounds__(kBlock) batch_branch_flat(BatchArgs a) {
     if (it >= a.n_items) return;
     const BatchItem w = a.items[it];
     const BatchInst& bi = a.inst[w.inst];
-    run_phase1<MODE>(bi.m, batch_out(a, bi, w.inst), w.kind, w.idx, w.r, stage);
+    run_phase1<MODE>(bi.m, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, stage);
 }
 
 template <int MODE>
@@ -1152,7 +1159,7 @@ __global__ void __launch_bounds__(kBlock, 5) batch_bus_flat(BatchArgs a) {
     if (it >= a.n_items) return;
     const BatchItem w = a.items[it];
     const BatchInst& bi = a.inst[w.inst];
-    run_phase2<MODE>(bi.m, batch_out(a, bi, w.inst), w.kind, w.idx, w.r, lds);
+    run_phase2<MODE>(bi.m, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, lds);
 }
 
 SetGrid plan_set(const DevModel& m, const EvalOut& o, int32_t mode) {
