@@ -96,6 +96,7 @@ ModelOffsets pack_model(Packer& pk, const opf::HostModel& hm) {
     o.ref_ptr = pk.add(hm.ref_ptr);
     o.ref_list = pk.add(hm.ref_list);
     o.outage = pk.add(hm.outage);
+    o.slots_c = pk.add(hm.slots_c);
     return o;
 }
 
@@ -148,7 +149,7 @@ opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets&
     P32(f_bus); P32(t_bus); PDB(coef); PDB(rate2); P32(slots); PDB(slot_coef); P32(big_bus);
     P32(adj_ptr); P32(he); P32(he_grp); P32(nlo); P32(ndist); P32(hva_off); P32(hvm_off); P32(jbal_off);
     P32(gen_ptr); P32(gen_list); PDB(gs); PDB(bs); PDB(pd); PDB(qd);
-    PDB(c2); PDB(c1); PDB(c0); P32(gen_bus); P32(ref_bus); P32(ref_ptr); P32(ref_list); P32(outage);
+    PDB(c2); PDB(c1); PDB(c0); P32(gen_bus); P32(ref_bus); P32(ref_ptr); P32(ref_list); P32(outage); P32(slots_c);
 #undef P32
 #undef PDB
     return d;

@@ -94,6 +94,9 @@ struct DevModel {
     // half-edge records passed from the branch phase to the bus phase:
     // side s, replica r, branch l at rec + ((s * nrep + r) * L + l) * kRecStride
     double* rec;
+    // the wave-packed bus segments again, 2 int32 per lane (kind word,
+    // index): the compact form the two-launch bus waves read
+    const int32_t* slots_c;   // [nwaves * kBlock * 2]
 };
 
 struct EvalOut {

@@ -467,6 +467,12 @@ __device__ __forceinline__ Slot load_slot(const DevModel& m, int32_t w) {
     return Slot{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 }
 
+// Output positions in the bus wave: the full slot's fields (one launch) or
+// those formed from the compact slot (two launches).
+#define H0 (SINGLE ? sl.h0 : h0)
+#define H1 (SINGLE ? sl.h1 : h1)
+#define H2 (SINGLE ? sl.h2 : h2)
+#define JP (SINGLE ? sl.jpos : jp)
 template <bool SINGLE>
 __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_t r, double* lds) {
     const int32_t lane = threadIdx.x;
@@ -480,13 +486,28 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
         const double2 c45 = ld(kc, 4 * lane + 2), c67 = ld(kc, 4 * lane + 3);
         k = Coef{c01.x, c01.y, c23.x, c23.y, c45.x, c45.y, c67.x, c67.y};
     }
-    const Slot sl = load_slot(m, w);
-    const int32_t type = sl.kind & 3;
-    const uint32_t side = (sl.kind & 4) ? 0u : 1u;  // the half-edge sits at its branch's from bus
-    const bool leader = sl.kind & 8;
-    const int32_t len = (sl.kind >> 8) & 0xff;  // segment (head) or group (leader) length
+    // the descriptor: the full slot (one launch, which also needs the
+    // neighbour bus), else the compact 8-byte slot, whose output positions
+    // come from the head lane's per-bus offsets
+    Slot sl;
+    int32_t kind, len;
+    uint32_t bus, ref;
+    if (SINGLE) {
+        sl = load_slot(m, w);
+        kind = sl.kind;
+        len = (kind >> 8) & 0xff;
+        bus = (uint32_t)sl.bus;
+        ref = (uint32_t)sl.ref;
+    } else {
+        const int2 c = ld(reinterpret_cast<const int2*>(m.slots_c) + (size_t)w * kBlock, (uint32_t)lane);
+        kind = c.x;
+        len = ((kind >> 8) & 63) + 1;
+        bus = ref = (uint32_t)c.y;
+    }
+    const int32_t type = kind & 3;
+    const uint32_t side = (kind & 4) ? 0u : 1u;  // the half-edge sits at its branch's from bus
+    const bool leader = kind & 8;               // len: segment (head) or group (leader) length
     const int64_t N = m.N, G = m.G;
-    const uint32_t bus = (uint32_t)sl.bus, ref = (uint32_t)sl.ref;
     {  // replica r
         const int64_t on = N * r;
         // every lane type issues its loads before any arithmetic: the lane
@@ -499,10 +520,20 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
         double gs, bs, vm_i, pd, qd, yp, yq, gp, gq;
         double2 ra, rb, rc;
         HeIn e;
+        int32_t jrow, hva0, hvm0, nlo, nd;  // the head's per-bus offsets (compact slots)
         if (type == SK_HEAD) {
             gs = ld(m.gs, bus);
             bs = ld(m.bs, bus);
             vm_i = ld(o.x + m.x_vm + on, bus);
+            if (!SINGLE) {
+                if (o.J) jrow = ld(m.jbal_off, bus);
+                if (wantH) {
+                    hva0 = ld(m.hva_off, bus);
+                    hvm0 = ld(m.hvm_off, bus);
+                    nlo = ld(m.nlo, bus);
+                    nd = ld(m.ndist, bus);
+                }
+            }
             if (wantC) {
                 const int64_t ol = (int64_t)m.load_stride * r;
                 pd = ld(m.pd + ol, bus);
@@ -554,17 +585,50 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
             v[R_P] = -gp;
             v[R_Q] = -gq;
         }
+        // output positions: balance Jacobian entry, Hessian entries of the
+        // bus (-1: absent).  With compact slots every lane joins the
+        // shuffles; only heads and leaders use the Hessian positions.  They
+        // are formed here, once all loads have landed, so that the offsets
+        // are not live through the reductions below.
+        // (The full slot holds them; it is read at the stores.)
+        int32_t jp = 0, h0, h1, h2;
+        if constexpr (!SINGLE) {
+            const int32_t hl = (kind >> 14) & 63;
+            if (o.J) jp = __shfl(jrow, hl, kBlock) + ((kind >> 20) & 63);
+            if (wantH) {
+                const int32_t hva_b = __shfl(hva0, hl, kBlock), hvm_b = __shfl(hvm0, hl, kBlock);
+                const int32_t nd_b = __shfl(nd, hl, kBlock);
+                if (type == SK_HEAD) {  // (va_i, va_i), (vm_i, va_i), (vm_i, vm_i)
+                    const bool nodeg = kind & 64;
+                    h0 = nodeg ? -1 : hva_b + nlo;
+                    h1 = nodeg ? -1 : hvm_b + nlo;
+                    h2 = nodeg ? hvm_b : hvm_b + nd_b + 1 + nlo;
+                } else {  // (va_i, va_k), (vm_i, va_k), (vm_i, vm_k) of the group
+                    const int32_t grp = (int32_t)((uint32_t)kind >> 26);
+                    const bool klo = kind & 16, khi = kind & 32;
+                    h0 = klo ? hva_b + grp : -1;
+                    h1 = hvm_b + grp + (khi ? 1 : 0);
+                    h2 = klo ? hvm_b + nd_b + 1 + grp : -1;
+                }
+            }
+        }
         if (wantC || wantH) {
             for (int q = 0; q < kRec; q++) lds[q * kBlock + lane] = v[q];
             __syncthreads();
             if (type == SK_HEAD) {
                 double sp = base_p, sq = base_q, daa = 0.0, dma = 0.0, dmm = 0.0;
-                for (int32_t j = 1; j < len; j++) {  // the segment, in order
+                auto add = [&](int32_t j) {  // the segment, in order
                     sp += lds[R_P * kBlock + lane + j];
                     sq += lds[R_Q * kBlock + lane + j];
                     daa += lds[R_TT * kBlock + lane + j];
                     dma += lds[R_MA * kBlock + lane + j];
                     dmm += lds[R_MM * kBlock + lane + j];
+                };
+                if constexpr (SINGLE) {
+                    for (int32_t j = 1; j < len; j++) add(j);
+                } else {
+#pragma unroll 4  // the compiler's deeper unrolling spills in the two-launch bus kernel
+                    for (int32_t j = 1; j < len; j++) add(j);
                 }
                 if (wantC) {
                     st(o.c + m.c_balp + on, bus, sp);
@@ -578,9 +642,9 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
                 if (wantH) {
                     double* hva = o.H + m.h_va + m.hva_rep * r;
                     double* hvm = o.H + m.h_vm + m.hvm_rep * r;
-                    if (sl.h0 >= 0) st_sel<SINGLE>(hva, (uint32_t)sl.h0, daa);
-                    if (sl.h1 >= 0) st_sel<SINGLE>(hvm, (uint32_t)sl.h1, dma);
-                    st_sel<SINGLE>(hvm, (uint32_t)sl.h2, dmm + shunt);
+                    if (H0 >= 0) st_sel<SINGLE>(hva, (uint32_t)H0, daa);
+                    if (H1 >= 0) st_sel<SINGLE>(hvm, (uint32_t)H1, dma);
+                    st_sel<SINGLE>(hvm, (uint32_t)H2, dmm + shunt);
                 }
             } else if (type == SK_EDGE && wantH && leader) {
                 // the neighbour group (parallel branches to one bus), in order
@@ -592,14 +656,13 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
                 }
                 double* hva = o.H + m.h_va + m.hva_rep * r;
                 double* hvm = o.H + m.h_vm + m.hvm_rep * r;
-                if (sl.h0 >= 0) st_sel<SINGLE>(hva, (uint32_t)sl.h0, -tt);
-                st_sel<SINGLE>(hvm, (uint32_t)sl.h1, -ma);
-                if (sl.h2 >= 0) st_sel<SINGLE>(hvm, (uint32_t)sl.h2, uw);
+                if (H0 >= 0) st_sel<SINGLE>(hva, (uint32_t)H0, -tt);
+                st_sel<SINGLE>(hvm, (uint32_t)H1, -ma);
+                if (H2 >= 0) st_sel<SINGLE>(hvm, (uint32_t)H2, uw);
             }
             __syncthreads();  // LDS is reused by the next replica
         }
         if (o.J && type != SK_IDLE) {
-            const uint32_t jp = (uint32_t)sl.jpos;
             double vp, vq;
             if (type == SK_HEAD) {
                 vp = 2.0 * gs * vm_i;
@@ -607,8 +670,8 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
             } else {
                 vp = vq = (type == SK_EDGE) ? 1.0 : -1.0;
             }
-            st(o.J + m.j_balp + m.jbal_rep * r, jp, vp);
-            st(o.J + m.j_balq + m.jbal_rep * r, jp, vq);
+            st(o.J + m.j_balp + m.jbal_rep * r, (uint32_t)JP, vp);
+            st(o.J + m.j_balq + m.jbal_rep * r, (uint32_t)JP, vq);
         }
         if (o.g && type == SK_HEAD) {
             st(o.g + m.x_va + on, bus, 0.0);
@@ -616,6 +679,10 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
         }
     }
 }
+#undef H0
+#undef H1
+#undef H2
+#undef JP
 
 // J^T v, phase 2: va / vm entries of the packed buses.
 __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_t r, double* lds) {

@@ -288,16 +288,24 @@ int build_host_model(const opf_case* cs, const opf_opts* opts, HostModel& hm, st
 void build_slots(HostModel& hm) {
     const int32_t N = hm.ly.N, L = hm.ly.L;
     hm.slots.clear();
+    hm.slots_c.clear();
     hm.big_bus.clear();
     int32_t lane = 0;
     auto push = [&](int32_t kind, int32_t ref, int32_t bus, int32_t other, int32_t jpos, int32_t h0, int32_t h1,
-                    int32_t h2) {
+                    int32_t h2, uint32_t ckind, int32_t cidx) {
         const int32_t f[8] = {kind, ref, bus, other, jpos, h0, h1, h2};
         hm.slots.insert(hm.slots.end(), f, f + 8);
+        hm.slots_c.push_back((int32_t)ckind);
+        hm.slots_c.push_back(cidx);
         lane = (lane + 1) % kWaveLanes;
     };
     auto pad_wave = [&]() {
-        while (lane != 0) push(SK_IDLE, -1, -1, -1, -1, -1, -1, -1);
+        while (lane != 0) push(SK_IDLE, -1, -1, -1, -1, -1, -1, -1, SK_IDLE, 0);
+    };
+    // compact kind word (SlotCompact); every field below is < 64 because a
+    // segment fits one wave
+    auto ck = [](uint32_t low, uint32_t len1, uint32_t head_lane, uint32_t joff, uint32_t grp) {
+        return low | (len1 << 8) | (head_lane << 14) | (joff << 20) | (grp << 26);
     };
     auto group_len = [&](int32_t i, int32_t q) {
         const int32_t grp = hm.he_grp[q];
@@ -318,8 +326,9 @@ void build_slots(HostModel& hm) {
         if (lane + seg > kWaveLanes) pad_wave();
         const int32_t nlo = hm.nlo[i], nd = hm.ndist[i];
         const int32_t hva = hm.hva_off[i], hvm = hm.hvm_off[i], jrow = hm.jbal_off[i];
+        const uint32_t head_lane = (uint32_t)lane;
         push(SK_HEAD | (seg << 8), -1, i, -1, jrow, deg > 0 ? hva + nlo : -1, deg > 0 ? hvm + nlo : -1,
-             deg > 0 ? hvm + nd + 1 + nlo : hvm);
+             deg > 0 ? hvm + nd + 1 + nlo : hvm, ck(SK_HEAD | (deg == 0 ? 64u : 0u), seg - 1, head_lane, 0, 0), i);
         for (int32_t q = e0; q < e1; q++) {
             const int32_t code = hm.he[q], l = code >> 1, from = code & 1;
             const int32_t k = from ? hm.t_bus[l] : hm.f_bus[l];
@@ -332,10 +341,15 @@ void build_slots(HostModel& hm) {
             const int32_t arank = (int32_t)(std::lower_bound(ab, ae, arc) - ab);
             const int32_t kind = SK_EDGE | (from << 2) | ((leader ? 1 : 0) << 3) | ((glen > 1 ? 1 : 0) << 4) |
                                  ((leader ? glen : 0) << 8);
+            const uint32_t clow = SK_EDGE | (from << 2) | ((leader ? 1u : 0u) << 3) | ((k < i ? 1u : 0u) << 4) |
+                                  ((k > i ? 1u : 0u) << 5);
             push(kind, l, i, k, jrow + 1 + ng + arank, leader && k < i ? hva + grp : -1,
-                 leader ? hvm + grp + (k > i ? 1 : 0) : -1, leader && k < i ? hvm + nd + 1 + grp : -1);
+                 leader ? hvm + grp + (k > i ? 1 : 0) : -1, leader && k < i ? hvm + nd + 1 + grp : -1,
+                 ck(clow, leader ? glen - 1 : 0, head_lane, 1 + ng + arank, grp), l);
         }
-        for (int32_t q = 0; q < ng; q++) push(SK_GEN, hm.gen_list[g0 + q], i, -1, jrow + 1 + q, -1, -1, -1);
+        for (int32_t q = 0; q < ng; q++)
+            push(SK_GEN, hm.gen_list[g0 + q], i, -1, jrow + 1 + q, -1, -1, -1, ck(SK_GEN, 0, head_lane, 1 + q, 0),
+                 hm.gen_list[g0 + q]);
     }
     pad_wave();
     hm.nwaves = (int32_t)(hm.slots.size() / (8 * kWaveLanes));

@@ -64,6 +64,9 @@ struct HostModel {
     // that never straddles a wave.  Every lane has 8 int32 fields (see
     // SlotField); output positions are relative to the replica's block.
     std::vector<int32_t> slots;                // [nwaves * kWaveLanes * 8]
+    // The same lanes in the compact form the two-launch bus waves read:
+    // 2 int32 per lane (kind word, index), see SlotCompact.
+    std::vector<int32_t> slots_c;              // [nwaves * kWaveLanes * 2]
     int32_t nwaves = 0;
     // The 8 admittance terms of each half-edge lane's branch, in slot order
     // (zero on other lanes): a bus wave that recomputes its half-edge terms
@@ -87,6 +90,21 @@ constexpr int32_t kWaveLanes = 64;
 //             off-diagonal entries (-1 if absent or not the group's first)
 //  generator: ref = generator, bus = i; jpos = its -1 entry
 enum SlotKind { SK_IDLE = 0, SK_HEAD = 1, SK_EDGE = 2, SK_GEN = 3 };
+
+// Compact slot (two launches; 8 bytes per lane instead of 32): the index is
+// the bus (head) or the branch / generator (other lanes); the kind word
+// holds
+//   bits [0,4): as in the full kind (lane type, from side, group leader);
+//   bit 4: neighbour k < i; bit 5: k > i (half-edge); bit 6: the head's bus
+//          has no branches;
+//   bits [8,14): segment length - 1 (head) or group length - 1 (leader);
+//   bits [14,20): lane of the segment's head in the wave;
+//   bits [20,26): offset of the lane's balance Jacobian entry from the
+//                 head's (0 head, 1 + q generator q, 1 + ng + arc rank);
+//   bits [26,32): neighbour group of a half-edge.
+// A head lane reads its bus's Hessian and Jacobian row offsets (hva_off,
+// hvm_off, nlo, ndist, jbal_off); the other lanes of the segment take them
+// from the head lane and form their positions from the fields above.
 
 // Validation; returns OPF_OK or an error code with a message.
 int validate(const opf_case* cs, const opf_opts* opts, std::string& err);
