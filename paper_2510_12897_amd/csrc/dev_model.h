@@ -50,10 +50,14 @@ struct DevModel {
     int32_t nbchunks, ngchunks;      // branch / generator chunks of kBlock
     int32_t single;                  // 1: small model; a plain callback set is one launch whose bus
                                      // items recompute their half-edge terms (batches use two)
-    int64_t x_va, x_vm, x_pg, x_qg, x_p, x_q;
-    int64_t c_ref, c_pfr, c_qfr, c_pto, c_qto, c_ang, c_balp, c_balq, c_thf, c_tht, c_ramp;
-    int64_t j_ref, j_pfr, j_qfr, j_pto, j_qto, j_ang, j_balp, j_balq, j_thf, j_tht, j_ramp, jbal_rep;
-    int64_t h_va, h_vm, h_pg, h_p, h_q, hva_rep, hvm_rep;
+    // block offsets and per-replica strides of x, c, J and H: 32 bits, since
+    // every per-instance array stays below 2^29 elements (checked when the
+    // model is created); 64-bit fields would double the scalar registers the
+    // kernels spend on them
+    int32_t x_va, x_vm, x_pg, x_qg, x_p, x_q;
+    int32_t c_ref, c_pfr, c_qfr, c_pto, c_qto, c_ang, c_balp, c_balq, c_thf, c_tht, c_ramp;
+    int32_t j_ref, j_pfr, j_qfr, j_pto, j_qto, j_ang, j_balp, j_balq, j_thf, j_tht, j_ramp, jbal_rep;
+    int32_t h_va, h_vm, h_pg, h_p, h_q, hva_rep, hvm_rep;
     // branches
     const int32_t* f_bus;
     const int32_t* t_bus;

@@ -1216,7 +1216,11 @@ __global__ void __launch_bounds__(kBlock) batch_branch_flat(BatchArgs a) {
     if (it >= a.n_items) return;
     const BatchItem w = a.items[it];
     const BatchInst& bi = a.inst[w.inst];
-    run_phase1<MODE>(bi.m, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, stage);
+    // a local copy: the instance's fields load together at the start instead
+    // of one dependent scalar round trip per branch that first uses them
+    // (64-scenario batch: 97.5 -> 95.4 us)
+    const DevModel mloc = bi.m;
+    run_phase1<MODE>(mloc, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, stage);
 }
 
 template <int MODE>
@@ -1226,7 +1230,11 @@ __global__ void __launch_bounds__(kBlock, 5) batch_bus_flat(BatchArgs a) {
     if (it >= a.n_items) return;
     const BatchItem w = a.items[it];
     const BatchInst& bi = a.inst[w.inst];
-    run_phase2<MODE>(bi.m, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, lds);
+    // a local copy: the instance's fields load together at the start instead
+    // of one dependent scalar round trip per branch that first uses them
+    // (64-scenario batch: 97.5 -> 95.4 us)
+    const DevModel mloc = bi.m;
+    run_phase2<MODE>(mloc, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, lds);
 }
 
 SetGrid plan_set(const DevModel& m, const EvalOut& o, int32_t mode) {
