@@ -687,12 +687,14 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
 // J^T v, phase 2: va / vm entries of the packed buses.
 __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_t r, double* lds) {
     const int32_t lane = threadIdx.x;
-    const Slot sl = load_slot(m, w);
-    const int32_t type = sl.kind & 3;
-    const uint32_t side = (sl.kind & 4) ? 0u : 1u;
-    const int32_t len = (sl.kind >> 8) & 0xff;
+    // the compact slot: lane type, side, segment length; the index is the
+    // bus (head) or the branch (half-edge)
+    const int2 sc = ld(reinterpret_cast<const int2*>(m.slots_c) + (size_t)w * kBlock, (uint32_t)lane);
+    const int32_t type = sc.x & 3;
+    const uint32_t side = (sc.x & 4) ? 0u : 1u;
+    const int32_t len = ((sc.x >> 8) & 63) + 1;
     const int64_t N = m.N;
-    const uint32_t bus = (uint32_t)sl.bus;
+    const uint32_t bus = (uint32_t)sc.y, ref = (uint32_t)sc.y;
     const double* x = o.x;
     const double* v = o.y;
     {  // replica r
@@ -704,7 +706,7 @@ __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int
         double vm, gs, bs, vp, vq;
         int32_t q0, q1;
         if (type == SK_EDGE) {
-            t = ld(reinterpret_cast<const double2*>(jt_rec_side(m, r, (int32_t)side)), (uint32_t)sl.ref);
+            t = ld(reinterpret_cast<const double2*>(jt_rec_side(m, r, (int32_t)side)), ref);
         } else if (type == SK_HEAD) {
             vm = ld(x + m.x_vm + on, bus);
             gs = ld(m.gs, bus);
