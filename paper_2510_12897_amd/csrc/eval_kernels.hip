@@ -20,9 +20,11 @@
 //    generator items: the gradient, the pg Hessian diagonal, reference and
 //    ramp rows, and one objective partial per (chunk, replica);
 //  phase 2, bus items: waves of packed bus segments [head, half-edges,
-//    generators] (the host packs them so no segment straddles a wave and
-//    precomputes every lane's output positions).  Each half-edge lane reads
-//    its record (one aligned 48-byte gather), stages it in LDS, and the
+//    generators] (the host packs them so no segment straddles a wave; an
+//    8-byte descriptor per lane, and the head lane's per-bus row offsets,
+//    shared with its segment by shuffle, give every output position).  Each
+//    half-edge lane reads its record (one aligned 48-byte gather), stages it
+//    in LDS, and the
 //    head lane reduces its segment in order (a segmented reduction) into the
 //    balance rows and the bus's Hessian diagonal, while the first half-edge
 //    of each neighbour group writes the group's off-diagonal Hessian
