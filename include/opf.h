@@ -215,9 +215,9 @@ int opf_eval_set(opf_model model, const double *x, const double *y, double obj_w
 int opf_jtprod(opf_model model, const double *x, const double *v, double *out, void *stream);
 
 /* ---------------------------------------------------------------- batch */
-/* Many instances of possibly different networks evaluated together: one
- * HIP graph of two kernels (branch phase, bus phase), each covering every
- * instance's work items (batched AC-OPF is the paper's stated future
+/* Many instances of possibly different networks evaluated together: two
+ * kernel launches (branch phase, bus phase) on the caller's stream, each
+ * covering every instance's work items (batched AC-OPF is the paper's stated future
  * work, Sec. VI).  Instance j uses model inst_model[j] (static,
  * multi-period or contingency) with its own loads: inst_pd / inst_qd hold
  * the concatenated per-instance load arrays, n_bus entries per instance
@@ -250,11 +250,11 @@ int opf_batch_schedule(opf_batch batch, int32_t *wg_per_cu);
 /* Force a schedule: wg_per_cu in [0, 64] (else OPF_E_ARG). */
 int opf_batch_set_schedule(opf_batch batch, int32_t wg_per_cu);
 
-/* All callbacks of every instance: the batch's HIP graph (branch-phase and
- * bus-phase kernels at the current schedule), instantiated once per
- * schedule and relaunched with each call's buffers as kernel arguments.
- * sigma[n_inst] are the objective weights.  Any of F, G, C, J, H may be
- * NULL (skipped); Y and sigma may be NULL when H is.  Results are bitwise
+/* All callbacks of every instance: the branch-phase and bus-phase kernels
+ * at the current schedule, launched on `stream` with this call's buffers
+ * as kernel arguments (no allocation; the launches can be captured into a
+ * HIP graph).  sigma[n_inst] are the objective weights.  Any of F, G, C,
+ * J, H may be NULL (skipped); Y and sigma may be NULL when H is.  Results are bitwise
  * equal to opf_eval_set on each instance's model in the two-launch shape,
  * and equal to rounding for a model in the one-launch shape. */
 int opf_batch_eval(opf_batch batch, const double *X, const double *Y, const double *sigma,

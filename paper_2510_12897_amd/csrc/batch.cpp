@@ -1,20 +1,22 @@
-// C-ABI of libopf: batched evaluation of many instances in one persistent
-// kernel launch replayed from a HIP graph, with a schedule autotuner.
+// C-ABI of libopf: batched evaluation of many instances, with a schedule
+// autotuner.
 //
-// An evaluation is two launches chained in one graph: the branch phase of
-// every instance, then the bus phase.  The schedule is the grid: with
-// wg_per_cu > 0 each launch is persistent (wg_per_cu workgroups per compute
-// unit drain the item list, each XCD's workgroups striding through one
-// contiguous range of it); with wg_per_cu = 0 it is flat (one workgroup per
-// item, the block index remapped to the same XCD ranges).  No schedule
+// An evaluation is two kernel launches on the caller's stream: the branch
+// phase of every instance, then the bus phase.  (Launching them from an
+// instantiated HIP graph instead cost 4.6 us more per evaluation on the
+// 64-scenario mix and on 16 points of the 10k-bus network; the direct
+// launches can still be captured into a caller's graph.)  The schedule is
+// the grid: with wg_per_cu > 0 each launch is persistent (wg_per_cu
+// workgroups per compute unit drain the item list, each XCD's workgroups
+// striding through one contiguous range of it); with wg_per_cu = 0 it is
+// flat (one workgroup per item, the block index remapped to the same XCD
+// ranges).  No schedule
 // changes a summation order (segment sums follow the host packing,
 // objective partials are per generator chunk and replica and are summed in
 // index order), so every schedule produces bitwise the same results as the
 // plain per-instance launch.
 #include <array>
-#include <map>
 #include <new>
-#include <tuple>
 
 #include "internal.h"
 
@@ -24,18 +26,6 @@ namespace {
 
 // autotuner candidates: flat, then persistent grids
 const int32_t kWgPerCu[] = {0, 2, 4, 8, 16, 32};
-
-struct GraphEntry {
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipGraphNode_t node[2] = {nullptr, nullptr};
-    opf::BatchArgs args[2]{};
-};
-
-// One instantiated graph per (workgroups per CU, mode); a launch with other
-// buffers rewrites the kernel arguments of the instantiated graph in place
-// instead of building a new one.
-using GraphKey = std::tuple<int32_t, int32_t>;
 
 }  // namespace
 
@@ -54,20 +44,11 @@ struct opf_batch_s {
     int32_t n_items[2][2] = {};
     int32_t wg_per_cu = 0;           // flat until tuned (measured fastest on the 64-instance mix)
     int32_t n_cu = 256;
-    std::map<GraphKey, GraphEntry> graphs;
 };
 
 namespace {
 
 bool valid(const opf_batch_s* b) { return b && b->magic == kBatchMagic; }
-
-void drop_graphs(opf_batch_s* b) {
-    for (auto& kv : b->graphs) {
-        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
-    }
-    b->graphs.clear();
-}
 
 // Work items of one phase, one replica each.  Phase 1: the branch chunks,
 // then (callback set) the generator chunks of every instance.  Phase 2: big
@@ -115,52 +96,13 @@ int launch(opf_batch_s* b, const opf::BatchArgs& a0, hipStream_t stream) {
         grid[ph] = b->wg_per_cu == 0 ? std::max(1, a[ph].n_items)
                                       : std::max(opf::kXcd, std::min(a[ph].n_items, b->n_cu * b->wg_per_cu));
     }
-    GraphKey key{b->wg_per_cu, a0.mode};
-    auto kernel_params = [&](int ph, opf::BatchArgs* args, void** slot) {
-        hipKernelNodeParams p{};
-        slot[0] = args;
-        p.func = opf::batch_kernel_fn(ph, a0.mode, b->wg_per_cu == 0);
-        p.gridDim = dim3(grid[ph]);
-        p.blockDim = dim3(opf::kBlock);
-        p.sharedMemBytes = 0;
-        p.kernelParams = slot;
-        p.extra = nullptr;
-        return p;
-    };
-    auto it = b->graphs.find(key);
-    if (it == b->graphs.end()) {
-        GraphEntry ge;
-        ge.args[0] = a[0];
-        ge.args[1] = a[1];
-        hipError_t e = hipGraphCreate(&ge.graph, 0);
-        if (e != hipSuccess) return hip_err(e, "hipGraphCreate");
-        hipGraphNode_t prev = nullptr;
-        for (int ph = 0; ph < 2 && e == hipSuccess; ph++) {
-            if (ge.args[ph].n_items == 0) continue;
-            void* slot[1];
-            const hipKernelNodeParams p = kernel_params(ph, &ge.args[ph], slot);
-            e = hipGraphAddKernelNode(&ge.node[ph], ge.graph, prev ? &prev : nullptr, prev ? 1 : 0, &p);
-            prev = ge.node[ph];
-        }
-        if (e == hipSuccess) e = hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            if (ge.graph) (void)hipGraphDestroy(ge.graph);
-            return hip_err(e, "batch graph build");
-        }
-        it = b->graphs.emplace(key, ge).first;
-    } else {
-        GraphEntry& ge = it->second;
-        for (int ph = 0; ph < 2; ph++) {
-            if (!ge.node[ph] || std::memcmp(&ge.args[ph], &a[ph], sizeof a[ph]) == 0) continue;
-            ge.args[ph] = a[ph];
-            void* slot[1];
-            const hipKernelNodeParams p = kernel_params(ph, &ge.args[ph], slot);
-            hipError_t e = hipGraphExecKernelNodeSetParams(ge.exec, ge.node[ph], &p);
-            if (e != hipSuccess) return hip_err(e, "batch graph argument update");
-        }
+    for (int ph = 0; ph < 2; ph++) {
+        if (a[ph].n_items == 0) continue;
+        void* args[1] = {&a[ph]};
+        const hipError_t e = hipLaunchKernel(opf::batch_kernel_fn(ph, a0.mode, b->wg_per_cu == 0), dim3(grid[ph]),
+                                             dim3(opf::kBlock), args, 0, stream);
+        if (e != hipSuccess) return hip_err(e, ph == 0 ? "batch branch-phase launch" : "batch bus-phase launch");
     }
-    hipError_t e = hipGraphLaunch(it->second.exec, stream);
-    if (e != hipSuccess) return hip_err(e, "hipGraphLaunch");
     return OPF_OK;
 }
 
@@ -290,7 +232,6 @@ int opf_batch_destroy(opf_batch b) {
     {
         DeviceGuard dg(b->device);
         (void)hipDeviceSynchronize();
-        drop_graphs(b);
         dev_free(b->alloc, b->arena);
     }
     b->magic = 0;

@@ -1,8 +1,9 @@
 """Batched evaluation: one persistent launch over many uneven instances.
 
 Batched results equal the plain per-instance launches bit for bit, under
-every schedule the autotuner may pick, across graph replays, for J^T v too;
-sampled instances also match the oracle."""
+every schedule the autotuner may pick, across repeated evaluations and
+replays of a captured HIP graph, for J^T v too; sampled instances also
+match the oracle."""
 import sys
 
 import numpy as np
@@ -173,7 +174,7 @@ def test_batch_equals_plain_bitwise_every_schedule(shape):
         m.close()
 
 
-def test_batch_graph_replays_and_partial_outputs():
+def test_batch_repeated_evals_and_partial_outputs():
     opf.set_single_launch_limit(0)  # plain references in the batch's (two-launch) shape
     batch, models, inst_model, plain = build_mix(sizes=(30, 200), per=2, with_mp=False)
     X, Y, sig, xs, ys = fill_inputs(batch, plain)
@@ -199,6 +200,38 @@ def test_batch_graph_replays_and_partial_outputs():
     for m in models:
         m.close()
     opf.set_single_launch_limit(4096)
+
+
+@pytest.mark.parametrize("wg_per_cu", [0, 4])
+def test_batch_eval_captured_in_graph(wg_per_cu):
+    """The batch's two launches captured into a HIP graph: every replay, with
+    eager work in between, is bitwise the eager evaluation."""
+    batch, models, inst_model, plain = build_mix(sizes=(30, 200), per=2, with_mp=False)
+    batch.set_schedule(wg_per_cu)
+    X, Y, sig, xs, ys = fill_inputs(batch, plain)
+    ref = outputs(batch)
+    batch.eval(X, Y, sig, *ref)
+    torch.cuda.synchronize()
+    out = outputs(batch)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        batch.eval(X, Y, sig, *out)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        say(f"[batch] captured graph replay {rep} (wg_per_cu={wg_per_cu})")
+        for t in out:
+            t.fill_(np.nan)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b), f"replay {rep}"
+    del graph
+    batch.close()
+    for m in models:
+        m.close()
 
 
 def test_batch_jtprod_equals_plain():
