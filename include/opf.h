@@ -238,8 +238,8 @@ int opf_batch_offsets(opf_batch batch, int64_t *xoff, int64_t *coff, int64_t *jo
                       int64_t *hoff);
 
 /* Time the candidate schedules (flat, and persistent grids of 2 to 32
- * workgroups per compute unit) on this batch and keep the fastest in the
- * handle.  Results of opf_batch_eval do not depend on the schedule.
+ * workgroups per compute unit) on this batch, each the best of three rounds
+ * interleaved over the candidates, and keep the fastest in the handle.  Results of opf_batch_eval do not depend on the schedule.
  * Allocates tuning buffers through the allocator; synchronises `stream`. */
 int opf_batch_tune(opf_batch batch, void *stream);
 

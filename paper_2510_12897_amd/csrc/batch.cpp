@@ -326,8 +326,12 @@ int opf_batch_tune(opf_batch b, void* stream) {
     int rc = OPF_OK;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const int32_t keep_wg = b->wg_per_cu;
-    float best = 1e30f;
-    int32_t best_wg = keep_wg;
+    constexpr int kCand = (int)(sizeof(kWgPerCu) / sizeof(kWgPerCu[0]));
+    // each candidate's best of three rounds, the rounds interleaved over the
+    // candidates: a transient slowdown (another process, a profiler starting)
+    // then cannot decide the choice
+    std::array<float, kCand> best_ms;
+    best_ms.fill(1e30f);
     do {
         hipError_t e = hipMemsetAsync(buf, 0, bytes, s);
         if (e == hipSuccess) e = hipEventCreate(&e0);
@@ -336,7 +340,9 @@ int opf_batch_tune(opf_batch b, void* stream) {
             rc = hip_err(e, "tuning setup");
             break;
         }
-        for (int32_t wg : kWgPerCu) {
+        for (int round = 0; round < 3 * kCand && rc == OPF_OK; round++) {
+            const int ci = round % kCand;
+            const int32_t wg = kWgPerCu[ci];
             b->wg_per_cu = wg;
             opf::BatchArgs a{};
             a.X = X; a.Y = Y; a.sigma = sg; a.F = F; a.G = G; a.C = C; a.J = J; a.H = H;
@@ -354,10 +360,7 @@ int opf_batch_tune(opf_batch b, void* stream) {
             }
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best) {
-                best = ms;
-                best_wg = wg;
-            }
+            best_ms[ci] = std::min(best_ms[ci], ms);
         }
     } while (false);
     if (e0) (void)hipEventDestroy(e0);
@@ -368,7 +371,10 @@ int opf_batch_tune(opf_batch b, void* stream) {
         b->wg_per_cu = keep_wg;
         return rc;
     }
-    b->wg_per_cu = best_wg;
+    int ci_best = 0;
+    for (int ci = 1; ci < kCand; ci++)
+        if (best_ms[ci] < best_ms[ci_best]) ci_best = ci;
+    b->wg_per_cu = kWgPerCu[ci_best];
     return OPF_OK;
 }
 
