@@ -243,3 +243,26 @@ def test_bad_arguments_raise():
     model.close()
     with pytest.raises(opf.OPFError):
         model.cons(x)
+
+
+@pytest.mark.parametrize("name,cs,opts", [c for c in CASES if c[0] in ("mp4", "sc3", "hub", "ragged700")],
+                         ids=["mp4", "sc3", "hub", "ragged700"])
+def test_every_output_entry_written(name, cs, opts, shape):
+    """Outputs pre-filled with NaN: one evaluation (fused set and separate
+    callbacks) leaves none of them unwritten."""
+    T, K = opts.get("n_periods", 1), opts.get("n_cont", 0)
+    model = opf.Model(cs, **opts)
+    x = to_dev(synth.point(cs, 9, n_periods=T, n_cont=K))
+    y = to_dev(synth.multipliers(model.m, 9))
+
+    def nan(n):
+        return torch.full((n,), float("nan"), dtype=torch.float64, device=DEV)
+
+    fused = model.eval_set(x, y, 0.5, nan(1), nan(model.n), nan(model.m), nan(model.nnzj), nan(model.nnzh))
+    sep = (model.obj(x, nan(1)), model.grad(x, nan(model.n)), model.cons(x, nan(model.m)),
+           model.jac_coord(x, nan(model.nnzj)), model.hess_coord(x, y, 0.5, nan(model.nnzh)))
+    torch.cuda.synchronize()
+    for what, outs in (("fused", fused), ("separate", sep)):
+        left = [int(torch.isnan(t).sum()) for t in outs]
+        assert left == [0] * 5, f"{name} ({shape} launch) {what}: NaN entries left in f, g, c, J, H: {left}"
+    model.close()
