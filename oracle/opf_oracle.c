@@ -131,21 +131,20 @@ static hd hd_scale(double s, hd x) {
     return z;
 }
 /* g(x) for g = sin or cos: g(a) + g'(a)(b e1 + c e2) + (g'(a) d + g''(a) b c) e1 e2.
- * Magnitudes: first-order propagation of the argument's magnitude through
- * g, g', g'' (each bounded by |g| + |g'| ma etc.). */
+ * Magnitudes: sin and cos are single terms of the rows they enter, so each
+ * part's companion is the absolute value of the term itself, |g(a)|,
+ * |g'(a)| |b|, ... carried through the chain rule term by term (the literal
+ * sum of |contributions|; the argument's own magnitude plays no part). */
 static hd hd_trig(hd x, double g0, double g1, double g2) {
     hd z;
     z.a = g0;
     z.b = g1 * x.b;
     z.c = g1 * x.c;
     z.d = g1 * x.d + g2 * x.b * x.c;
-    double m0 = fabs(g0) + fabs(g1) * x.ma;
-    double m1 = fabs(g1) + fabs(g2) * x.ma;
-    double m2 = fabs(g2) + fabs(g1) * x.ma;
-    z.ma = m0;
-    z.mb = m1 * x.mb;
-    z.mc = m1 * x.mc;
-    z.md = m1 * x.md + m2 * x.mb * x.mc;
+    z.ma = fabs(g0);
+    z.mb = fabs(g1) * x.mb;
+    z.mc = fabs(g1) * x.mc;
+    z.md = fabs(g1) * x.md + fabs(g2) * x.mb * x.mc;
     return z;
 }
 static hd hd_sin(hd x) { return hd_trig(x, sin(x.a), cos(x.a), -sin(x.a)); }
