@@ -218,7 +218,7 @@ int opf_jtprod(opf_model model, const double *x, const double *v, double *out, v
 /* Many instances of possibly different networks evaluated together: two
  * kernel launches (branch phase, bus phase) on the caller's stream, each
  * covering every instance's work items (batched AC-OPF is the paper's stated future
- * work, Sec. VI).  Instance j uses model inst_model[j] (static,
+ * work, Sec. V).  Instance j uses model inst_model[j] (static,
  * multi-period or contingency) with its own loads: inst_pd / inst_qd hold
  * the concatenated per-instance load arrays, n_bus entries per instance
  * (n_periods * n_bus, bus fastest, for a multi-period model); NULL = every
@@ -336,7 +336,7 @@ int prox_squash_bwd(opf_model model, const float *z, int B, double va_span, cons
  * constraint violations over the non-flow rows + squared bound violations of
  * p, q) + obj_scale * F[b] (the objective term is skipped when F is NULL);
  * cvio[b] = largest violation over every row and the p, q bounds (the
- * paper's Cvio, Sec. V-A); W [B, m] = d pen / d c on the non-flow rows;
+ * paper's Cvio, Sec. IV-A5); W [B, m] = d pen / d c on the non-flow rows;
  * gpq [B, 4L] = d pen / d (p, q).  The flow rows of W receive 0, or with
  * vjp != 0 the weights of prox_vjp_weights (computed in the same pass), so
  * that J^T W is the whole constraint part of the gradient. */

@@ -14,7 +14,7 @@ library never loads it and it imports nothing from the HIP package.
   derivative.
 * The penalty on the constraint values: squared violations of the non-flow
   rows and of the arc-variable bounds, its gradient with respect to c, and
-  the largest violation (the paper's Cvio, Sec. V-A).
+  the largest violation (the paper's Cvio, Sec. IV-A5).
 """
 from __future__ import annotations
 

@@ -5,8 +5,8 @@
 //  - prox_gemm: C[M,N] = A[M,K] B[K,N] on the matrix cores
 //    (v_mfma_f32_32x32x16_bf16): operands are FP32 in memory, rounded to
 //    BF16 (nearest even) when staged into LDS, accumulated in FP32; optional
-//    fused epilogue bias + exact GELU.  128x128 block tile, BK = 32, four
-//    waves of 64x64, global loads of the next K tile overlapped with the
+//    fused epilogue bias + exact GELU.  128x128 or 128x64 block tile, BK = 64, four
+//    waves of 64x64 or 64x32, global loads of the next K tile overlapped with the
 //    matrix-core work on the current one.
 //  - elementwise / reduction kernels: GELU backward, deterministic column
 //    sums (bias gradient), Adam, output squashing into the variable bounds

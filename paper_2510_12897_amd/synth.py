@@ -5,7 +5,7 @@ oracle.  It draws networks, loads, evaluation points and multipliers; it holds
 none of the model's arithmetic (no flows, no derivatives, no pattern rules).
 
 Networks stand in for the PGLib-OPF / GOC3 / epigrids cases the paper
-benchmarks on (Sec. V, Tables I-III), which are not available here.  Sizes
+benchmarks on (Sec. IV, Tables I-III), which are not available here.  Sizes
 follow the paper's "Large" classes (static nvar > 75k, multi-period
 nvar > 500k).  Recipe:
 

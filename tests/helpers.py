@@ -89,3 +89,13 @@ def strict_violations(v, ref, rtol=RTOL, atol=ATOL) -> int:
     v = np.asarray(v, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     return int((np.abs(v - ref) > rtol * np.abs(ref) + atol).sum())
+
+
+# Strict-form counts of the parity checks of this session, by case tag:
+# written to gpurun_out/parity_strict_counts.json at the end of the session
+# when that folder exists (tests/conftest.py).
+STRICT_COUNTS = {}
+
+
+def record_strict(tag, n_strict, n_total):
+    STRICT_COUNTS[tag] = dict(strict_violations=int(n_strict), compared=int(n_total))

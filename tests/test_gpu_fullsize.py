@@ -21,7 +21,7 @@ import torch
 from oracle import oracle as O
 from paper_2510_12897_amd import opf, synth
 
-from helpers import assert_close
+from helpers import assert_close, record_strict, strict_violations
 
 pytestmark = pytest.mark.gpu
 
@@ -44,6 +44,9 @@ def check_set(res, out, tag):
     assert_close(c, res["c"], res["cscale"], what=f"{tag} c")
     assert_close(jv, res["jval"], res["jscale"], what=f"{tag} J")
     assert_close(hv, res["hval"], res["hscale"], what=f"{tag} H")
+    n_strict = sum(strict_violations(a, b) for a, b in ((c, res["c"]), (jv, res["jval"]), (hv, res["hval"])))
+    record_strict(tag, n_strict, len(c) + len(jv) + len(hv))
+    say(f"[fullsize] {tag}: strict-form violations {n_strict}")
 
 
 def check_patterns(model, res, tag):

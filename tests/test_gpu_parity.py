@@ -14,7 +14,7 @@ import torch
 from oracle import oracle as O
 from paper_2510_12897_amd import opf, synth
 
-from helpers import assert_close, hub_network, small_cases, strict_violations
+from helpers import assert_close, hub_network, record_strict, small_cases, strict_violations
 from test_host_pattern import with_parallel_and_isolated
 
 pytestmark = pytest.mark.gpu
@@ -89,6 +89,7 @@ def check_against_oracle(model, cs, opts, x, y, sigma, tag):
     assert_close(hv.cpu().numpy(), res["hval"], res["hscale"], what=f"{tag} H")
     n_strict = sum(strict_violations(a, b) for a, b in (
         (c.cpu().numpy(), res["c"]), (jvh, res["jval"]), (hv.cpu().numpy(), res["hval"])))
+    record_strict(tag, n_strict, c.numel() + jv.numel() + hv.numel())
     say(f"[parity] {tag}: ok (strict-form violations: {n_strict})")
     return f, g, c, jv, hv
 
