@@ -1,5 +1,6 @@
 /*
- * CPU ORACLE for the polar AC-OPF NLP callbacks.  TEST INFRASTRUCTURE ONLY:
+ * CPU ORACLE for the AC-OPF NLP callbacks, polar and rectangular forms.
+ * TEST INFRASTRUCTURE ONLY:
  * only the test suite, the smoke check and the benchmark's CPU-baseline leg
  * load this library; the product path never does.
  *
@@ -17,6 +18,9 @@
  *                 example in Sec. III-D) and append generator ramp rows
  *                 pg_t - pg_{t-1} (the mpopf ramp limit, Sec. III-C2);
  *                 contingency copies repeat every block except pg.
+ *                 The rectangular form (form = :rect, Sec. III-C1) takes
+ *                 bus variables (vr, vi) for (va, vm) and rows of
+ *                 PowerModels' ACR formulation (see row_value_rect).
  *   J(x)          sparse Jacobian values, sorted by (row, col)
  *   H(x, y, s)    lower triangle of s * hess f + sum_i y_i hess c_i, sorted by
  *                 (row, col), duplicates merged (hess! with obj_weight,
@@ -65,6 +69,7 @@ typedef struct {
     double ramp_ratio;
     int32_t n_cont;             /* contingency copies (0 = none) */
     const int32_t *outaged;     /* [n_cont] */
+    int32_t form;               /* 0 = polar (va, vm), 1 = rectangular (vr, vi) */
 } or_case;
 
 typedef struct {
@@ -153,10 +158,13 @@ static hd hd_cos(hd x) { return hd_trig(x, cos(x.a), -sin(x.a), -cos(x.a)); }
 /* ------------------------------------------------------------------ */
 /* layout: variable and constraint blocks                              */
 /* ------------------------------------------------------------------ */
-enum { R_REF, R_PFR, R_QFR, R_PTO, R_QTO, R_ANG, R_BALP, R_BALQ, R_THF, R_THT, R_RAMP, R_NBLK };
+/* R_ANGL (the lower angle-difference row) and R_VMAG (voltage magnitude)
+ * exist in the rectangular form only; in the polar form they are empty. */
+enum { R_REF, R_PFR, R_QFR, R_PTO, R_QTO, R_ANG, R_ANGL, R_BALP, R_BALQ, R_THF, R_THT, R_VMAG, R_RAMP,
+       R_NBLK };
 
 typedef struct {
-    int N, L, G, R, T, K, nrep, npg;
+    int N, L, G, R, T, K, nrep, npg, rect;
     int64_t xva, xvm, xpg, xqg, xp, xq, n;
     int64_t cblk[R_NBLK + 1]; /* start row of every constraint block; cblk[R_NBLK] = m */
 } layout;
@@ -168,6 +176,8 @@ static int make_layout(const or_case *cs, layout *ly) {
     if (cs->n_cont < 0) return fail("n_cont must be >= 0");
     if (cs->n_periods > 1 && cs->n_cont > 0)
         return fail("periods and contingency copies are not combined");
+    if (cs->form != 0 && cs->form != 1) return fail("form must be 0 (polar) or 1 (rectangular)");
+    ly->rect = cs->form;
     ly->N = cs->n_bus; ly->L = cs->n_branch; ly->G = cs->n_gen; ly->R = cs->n_ref;
     ly->T = cs->n_periods; ly->K = cs->n_cont;
     ly->nrep = cs->n_periods > 1 ? cs->n_periods : cs->n_cont + 1;
@@ -180,15 +190,20 @@ static int make_layout(const or_case *cs, layout *ly) {
     ly->xp = ly->xqg + G * nr;
     ly->xq = ly->xp + 2 * L * nr;
     ly->n = ly->xq + 2 * L * nr;
-    int64_t sizes[R_NBLK] = {R * nr, L * nr, L * nr, L * nr, L * nr, L * nr,
-                             N * nr, N * nr, L * nr, L * nr,
+    int64_t rc = ly->rect;
+    int64_t sizes[R_NBLK] = {R * nr, L * nr, L * nr, L * nr, L * nr, L * nr, rc * L * nr,
+                             N * nr, N * nr, L * nr, L * nr, rc * N * nr,
                              (ly->T > 1) ? G * (ly->T - 1) : 0};
     ly->cblk[0] = 0;
     for (int k = 0; k < R_NBLK; k++) ly->cblk[k + 1] = ly->cblk[k] + sizes[k];
     return 0;
 }
+/* The two bus blocks: (va, vm) in the polar form, (vr, vi) in the
+ * rectangular form (same positions). */
 static int64_t col_va(const layout *l, int i, int r) { return l->xva + i + (int64_t)l->N * r; }
 static int64_t col_vm(const layout *l, int i, int r) { return l->xvm + i + (int64_t)l->N * r; }
+static int64_t col_vr(const layout *l, int i, int r) { return col_va(l, i, r); }
+static int64_t col_vi(const layout *l, int i, int r) { return col_vm(l, i, r); }
 static int64_t col_pg(const layout *l, int k, int r) {
     return l->xpg + k + (int64_t)l->G * (l->npg == 1 ? 0 : r);
 }
@@ -233,6 +248,7 @@ typedef struct {
     int blk, ent, rep;   /* block, entity (ref index / branch / bus / gen), replica */
     int nsup;
     int narc;            /* balance rows: number of arc terms */
+    int nbv;             /* balance rows: leading bus variables (1 polar: vm; 2 rect: vr, vi) */
     int64_t sup[64 + 16]; /* variable columns, in term order (filled by row_support) */
     int64_t *big;         /* used instead of sup when a balance row is long */
 } row_t;
@@ -283,32 +299,49 @@ static int row_support(const or_case *cs, const layout *ly, const adjacency *adj
     int64_t *s = rw->sup;
     rw->big = NULL;
     rw->narc = 0;
+    rw->nbv = ly->rect ? 2 : 1;
     switch (rw->blk) {
     case R_REF:
+        /* polar: va_r; rectangular: vi_r (a zero angle with vr > 0) */
         rw->nsup = 1;
-        s[0] = col_va(ly, cs->ref_bus[e], r);
+        s[0] = ly->rect ? col_vi(ly, cs->ref_bus[e], r) : col_va(ly, cs->ref_bus[e], r);
         break;
     case R_PFR: case R_QFR: case R_PTO: case R_QTO: {
         int arc = (rw->blk == R_PFR || rw->blk == R_QFR) ? e : L + e;
         int isp = (rw->blk == R_PFR || rw->blk == R_PTO);
         rw->nsup = 5;
         s[0] = isp ? col_p(ly, arc, r) : col_q(ly, arc, r);
-        s[1] = col_vm(ly, cs->f_bus[e], r);
-        s[2] = col_vm(ly, cs->t_bus[e], r);
-        s[3] = col_va(ly, cs->f_bus[e], r);
-        s[4] = col_va(ly, cs->t_bus[e], r);
+        if (ly->rect) { /* (vr_f, vr_t, vi_f, vi_t) */
+            s[1] = col_vr(ly, cs->f_bus[e], r);
+            s[2] = col_vr(ly, cs->t_bus[e], r);
+            s[3] = col_vi(ly, cs->f_bus[e], r);
+            s[4] = col_vi(ly, cs->t_bus[e], r);
+        } else {        /* (vm_f, vm_t, va_f, va_t) */
+            s[1] = col_vm(ly, cs->f_bus[e], r);
+            s[2] = col_vm(ly, cs->t_bus[e], r);
+            s[3] = col_va(ly, cs->f_bus[e], r);
+            s[4] = col_va(ly, cs->t_bus[e], r);
+        }
         break;
     }
-    case R_ANG:
-        rw->nsup = 2;
-        s[0] = col_va(ly, cs->f_bus[e], r);
-        s[1] = col_va(ly, cs->t_bus[e], r);
+    case R_ANG: case R_ANGL:
+        if (ly->rect) { /* (vr_f, vr_t, vi_f, vi_t) */
+            rw->nsup = 4;
+            s[0] = col_vr(ly, cs->f_bus[e], r);
+            s[1] = col_vr(ly, cs->t_bus[e], r);
+            s[2] = col_vi(ly, cs->f_bus[e], r);
+            s[3] = col_vi(ly, cs->t_bus[e], r);
+        } else {
+            rw->nsup = 2;
+            s[0] = col_va(ly, cs->f_bus[e], r);
+            s[1] = col_va(ly, cs->t_bus[e], r);
+        }
         break;
     case R_BALP: case R_BALQ: {
         int isp = rw->blk == R_BALP;
         int na = adj->arc_ptr[e + 1] - adj->arc_ptr[e];
         int ng = adj->gen_ptr[e + 1] - adj->gen_ptr[e];
-        rw->nsup = 1 + na + ng;
+        rw->nsup = rw->nbv + na + ng;
         rw->narc = na;
         if (rw->nsup > (int)(sizeof rw->sup / sizeof rw->sup[0])) {
             rw->big = malloc(sizeof(int64_t) * (size_t)rw->nsup);
@@ -316,7 +349,12 @@ static int row_support(const or_case *cs, const layout *ly, const adjacency *adj
             s = rw->big;
         }
         int q = 0;
-        s[q++] = col_vm(ly, e, r);
+        if (ly->rect) {
+            s[q++] = col_vr(ly, e, r);
+            s[q++] = col_vi(ly, e, r);
+        } else {
+            s[q++] = col_vm(ly, e, r);
+        }
         for (int j = adj->arc_ptr[e]; j < adj->arc_ptr[e + 1]; j++)
             s[q++] = isp ? col_p(ly, adj->arc_idx[j], r) : col_q(ly, adj->arc_idx[j], r);
         for (int j = adj->gen_ptr[e]; j < adj->gen_ptr[e + 1]; j++)
@@ -330,6 +368,11 @@ static int row_support(const or_case *cs, const layout *ly, const adjacency *adj
         s[1] = col_q(ly, arc, r);
         break;
     }
+    case R_VMAG:
+        rw->nsup = 2;
+        s[0] = col_vr(ly, e, r);
+        s[1] = col_vi(ly, e, r);
+        break;
     case R_RAMP:
         rw->nsup = 2;
         s[0] = col_pg(ly, e, r);      /* pg_{k,t} */
@@ -344,6 +387,75 @@ static double bus_pd(const or_case *cs, int i, int r) {
 }
 static double bus_qd(const or_case *cs, int i, int r) {
     return (cs->n_periods > 1 && cs->qd_t) ? cs->qd_t[i + (int64_t)cs->n_bus * r] : cs->qd[i];
+}
+
+/* The value of one row of the rectangular form (PowerModels' ACR
+ * formulation) as a function of its variables v[0..nsup).  With
+ * V = vr + j vi the polar terms become polynomials: vm^2 = vr^2 + vi^2,
+ * vm_f vm_t cos(th) = vr_f vr_t + vi_f vi_t (CR) and vm_f vm_t sin(th) =
+ * vi_f vr_t - vr_f vi_t (SI), so every flow is
+ * alpha |V_f|^2 + beta |V_t|^2 + a CR + b SI with the polar coefficients.
+ * The angle-difference limits are the two tangent rows
+ * SI - tan(angmax) CR <= 0 and SI - tan(angmin) CR >= 0, the voltage
+ * magnitude limits the rows vr^2 + vi^2 in [vmin^2, vmax^2], and the
+ * reference row fixes vi_r = 0. */
+static hd row_value_rect(const or_case *cs, const row_t *rw, const hd *v) {
+    int e = rw->ent, r = rw->rep;
+    switch (rw->blk) {
+    case R_REF:
+        return v[0];
+    case R_PFR: case R_QFR: case R_PTO: case R_QTO: {
+        /* v = (arc variable, vr_f, vr_t, vi_f, vi_t) */
+        bcoef k = branch_coef(cs, e, r);
+        hd vrf = v[1], vrt = v[2], vif = v[3], vit = v[4];
+        hd CR = hd_add(hd_mul(vrf, vrt), hd_mul(vif, vit));
+        hd SI = hd_sub(hd_mul(vif, vrt), hd_mul(vrf, vit));
+        hd Uf = hd_add(hd_mul(vrf, vrf), hd_mul(vif, vif));
+        hd Ut = hd_add(hd_mul(vrt, vrt), hd_mul(vit, vit));
+        hd F;
+        switch (rw->blk) {
+        case R_PFR:
+            F = hd_add(hd_scale(k.Gff, Uf), hd_add(hd_scale(k.Gft, CR), hd_scale(k.Bft, SI)));
+            break;
+        case R_QFR:
+            F = hd_add(hd_scale(-k.Bff, Uf), hd_add(hd_scale(-k.Bft, CR), hd_scale(k.Gft, SI)));
+            break;
+        case R_PTO:
+            F = hd_add(hd_scale(k.Gtt, Ut), hd_sub(hd_scale(k.Gtf, CR), hd_scale(k.Btf, SI)));
+            break;
+        default:
+            F = hd_add(hd_scale(-k.Btt, Ut), hd_sub(hd_scale(-k.Btf, CR), hd_scale(k.Gtf, SI)));
+            break;
+        }
+        return hd_sub(v[0], F);
+    }
+    case R_ANG: case R_ANGL: {
+        /* v = (vr_f, vr_t, vi_f, vi_t) */
+        double t = tan(rw->blk == R_ANG ? cs->angmax[e] : cs->angmin[e]);
+        hd CR = hd_add(hd_mul(v[0], v[1]), hd_mul(v[2], v[3]));
+        hd SI = hd_sub(hd_mul(v[2], v[1]), hd_mul(v[0], v[3]));
+        return hd_sub(SI, hd_scale(t, CR));
+    }
+    case R_BALP: case R_BALQ: {
+        int isp = rw->blk == R_BALP;
+        double load = isp ? bus_pd(cs, e, r) : bus_qd(cs, e, r);
+        double shunt = isp ? cs->gs[e] : -cs->bs[e];
+        hd v2 = hd_add(hd_mul(v[0], v[0]), hd_mul(v[1], v[1]));
+        hd acc = hd_add(hd_cst(load), hd_scale(shunt, v2));
+        for (int q = 2; q < 2 + rw->narc; q++) acc = hd_add(acc, v[q]);
+        for (int q = 2 + rw->narc; q < rw->nsup; q++) acc = hd_sub(acc, v[q]);
+        return acc;
+    }
+    case R_VMAG:
+        return hd_add(hd_mul(v[0], v[0]), hd_mul(v[1], v[1]));
+    case R_THF: case R_THT: {
+        double rate = cs->rate_a[e];
+        return hd_sub(hd_add(hd_mul(v[0], v[0]), hd_mul(v[1], v[1])), hd_cst(rate * rate));
+    }
+    case R_RAMP:
+        return hd_sub(v[0], v[1]);
+    }
+    return hd_cst(NAN);
 }
 
 /* The value of one row as a function of its variables v[0..nsup). */
@@ -404,12 +516,35 @@ static hd row_value(const or_case *cs, const row_t *rw, const hd *v) {
 }
 
 static hd eval_row(const or_case *cs, const row_t *rw, const hd *v) {
-    return row_value(cs, rw, v);
+    return cs->form ? row_value_rect(cs, rw, v) : row_value(cs, rw, v);
 }
 
 /* Hessian support: pairs (i, j) of support positions, i >= j by position
  * order (the caller orders them by column). */
-static int row_hess_pairs(const row_t *rw, int pairs[][2]) {
+static int row_hess_pairs_rect(const row_t *rw, int pairs[][2]) {
+    /* flow rows (positions 1..4 = vr_f, vr_t, vi_f, vi_t): the squares of
+     * |V_f|^2 and |V_t|^2, the products of CR and SI; angle rows
+     * (positions 0..3): the products of CR and SI */
+    static const int flow[8][2] = {{1, 1}, {2, 2}, {3, 3}, {4, 4}, {2, 1}, {4, 3}, {3, 2}, {4, 1}};
+    static const int ang[4][2] = {{1, 0}, {3, 2}, {2, 1}, {3, 0}};
+    switch (rw->blk) {
+    case R_PFR: case R_QFR: case R_PTO: case R_QTO:
+        memcpy(pairs, flow, sizeof flow);
+        return 8;
+    case R_ANG: case R_ANGL:
+        memcpy(pairs, ang, sizeof ang);
+        return 4;
+    case R_BALP: case R_BALQ: case R_VMAG: case R_THF: case R_THT:
+        pairs[0][0] = 0; pairs[0][1] = 0;
+        pairs[1][0] = 1; pairs[1][1] = 1;
+        return 2;
+    default:
+        return 0;
+    }
+}
+
+static int row_hess_pairs(const row_t *rw, int rect, int pairs[][2]) {
+    if (rect) return row_hess_pairs_rect(rw, pairs);
     switch (rw->blk) {
     case R_PFR: case R_QFR: case R_PTO: case R_QTO: {
         int n = 0;
@@ -439,7 +574,7 @@ static void row_of(const layout *ly, int64_t row, row_t *rw) {
     int64_t per;
     switch (blk) {
     case R_REF: per = ly->R; break;
-    case R_BALP: case R_BALQ: per = ly->N; break;
+    case R_BALP: case R_BALQ: case R_VMAG: per = ly->N; break;
     case R_RAMP: per = ly->G; break;
     default: per = ly->L; break;
     }
@@ -511,8 +646,15 @@ int or_bounds(const or_case *cs, double *lvar, double *uvar, double *lcon, doubl
     for (int64_t j = 0; j < ly.n; j++) { lvar[j] = -INFINITY; uvar[j] = INFINITY; x0[j] = 0.0; }
     for (int r = 0; r < ly.nrep; r++) {
         for (int i = 0; i < N; i++) {
-            int64_t c = col_vm(&ly, i, r);
-            lvar[c] = cs->vmin[i]; uvar[c] = cs->vmax[i]; x0[c] = 1.0;
+            if (ly.rect) {
+                /* |vr|, |vi| <= vmax; start vr = 1, vi = 0 */
+                int64_t cr = col_vr(&ly, i, r), ci = col_vi(&ly, i, r);
+                lvar[cr] = -cs->vmax[i]; uvar[cr] = cs->vmax[i]; x0[cr] = 1.0;
+                lvar[ci] = -cs->vmax[i]; uvar[ci] = cs->vmax[i];
+            } else {
+                int64_t c = col_vm(&ly, i, r);
+                lvar[c] = cs->vmin[i]; uvar[c] = cs->vmax[i]; x0[c] = 1.0;
+            }
         }
         for (int k = 0; k < G; k++) {
             if (r < ly.npg) { int64_t c = col_pg(&ly, k, r); lvar[c] = cs->pmin[k]; uvar[c] = cs->pmax[k]; }
@@ -530,10 +672,19 @@ int or_bounds(const or_case *cs, double *lvar, double *uvar, double *lcon, doubl
         row_t rw;
         row_of(&ly, row, &rw);
         double lo = 0.0, hi = 0.0;
-        if (rw.blk == R_ANG) {
-            int out = cs->n_cont > 0 && rw.rep >= 1 && cs->outaged[rw.rep - 1] == rw.ent;
-            lo = out ? -INFINITY : cs->angmin[rw.ent];
-            hi = out ? INFINITY : cs->angmax[rw.ent];
+        int out = (rw.blk == R_ANG || rw.blk == R_ANGL) && cs->n_cont > 0 && rw.rep >= 1 &&
+                  cs->outaged[rw.rep - 1] == rw.ent;
+        if (out) {
+            lo = -INFINITY; hi = INFINITY;
+        } else if (rw.blk == R_ANG && !ly.rect) {
+            lo = cs->angmin[rw.ent]; hi = cs->angmax[rw.ent];
+        } else if (rw.blk == R_ANG) {   /* SI - tan(angmax) CR <= 0 */
+            lo = -INFINITY; hi = 0.0;
+        } else if (rw.blk == R_ANGL) {  /* SI - tan(angmin) CR >= 0 */
+            lo = 0.0; hi = INFINITY;
+        } else if (rw.blk == R_VMAG) {
+            lo = cs->vmin[rw.ent] * cs->vmin[rw.ent];
+            hi = cs->vmax[rw.ent] * cs->vmax[rw.ent];
         } else if (rw.blk == R_THF || rw.blk == R_THT) {
             lo = -INFINITY; hi = 0.0;
         } else if (rw.blk == R_RAMP) {
@@ -580,7 +731,7 @@ or_result *or_eval(const or_case *cs, const double *x, const double *y, double s
     res->n = n; res->m = m;
     int maxsup = 1;
     for (int i = 0; i < ly.N; i++) {
-        int s = 1 + (adj.arc_ptr[i + 1] - adj.arc_ptr[i]) + (adj.gen_ptr[i + 1] - adj.gen_ptr[i]);
+        int s = 2 + (adj.arc_ptr[i + 1] - adj.arc_ptr[i]) + (adj.gen_ptr[i + 1] - adj.gen_ptr[i]);
         if (s > maxsup) maxsup = s;
     }
     if (maxsup < 5) maxsup = 5;
@@ -635,7 +786,7 @@ or_result *or_eval(const or_case *cs, const double *x, const double *y, double s
             }
             if (want & W_HESS) {
                 int pairs[16][2];
-                int np = row_hess_pairs(&rw, pairs);
+                int np = row_hess_pairs(&rw, ly.rect, pairs);
                 for (int p = 0; p < np; p++) {
                     int s1 = pairs[p][0], s2 = pairs[p][1];
                     hd v = seeded(cs, &rw, x, buf, s1, s2);

@@ -6,7 +6,8 @@ imports nothing from the HIP package.
 
 Cases are dicts of numpy arrays with the field names of the network
 generator; options are keyword arguments ``n_periods``, ``pd_t``, ``qd_t``,
-``ramp_ratio``, ``n_cont``, ``outaged``.
+``ramp_ratio``, ``n_cont``, ``outaged`` and ``form`` ("polar", the default,
+or "rect": bus variables (vr, vi) in place of (va, vm)).
 """
 from __future__ import annotations
 
@@ -50,6 +51,7 @@ class _Case(ctypes.Structure):
         ("n_periods", ctypes.c_int32), ("pd_t", _dp), ("qd_t", _dp),
         ("ramp_ratio", ctypes.c_double),
         ("n_cont", ctypes.c_int32), ("outaged", _ip),
+        ("form", ctypes.c_int32),
     ]
 
 
@@ -88,8 +90,11 @@ class OracleError(RuntimeError):
     pass
 
 
+FORMS = {"polar": 0, "rect": 1}
+
+
 def _make_case(case: dict, n_periods=1, pd_t=None, qd_t=None, ramp_ratio=0.0,
-               n_cont=0, outaged=None):
+               n_cont=0, outaged=None, form="polar"):
     keep = []
 
     def d(a):
@@ -116,6 +121,7 @@ def _make_case(case: dict, n_periods=1, pd_t=None, qd_t=None, ramp_ratio=0.0,
     c.ramp_ratio = float(ramp_ratio)
     c.n_cont = int(n_cont)
     c.outaged = i(outaged if outaged is not None else np.zeros(1, np.int32))
+    c.form = FORMS[form]
     return c, keep
 
 

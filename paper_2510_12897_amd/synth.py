@@ -155,14 +155,15 @@ def network(n_bus: int, n_branch: int, n_gen: int, seed, variant: bool = False) 
     )
 
 
-def point(case: dict, seed, n_periods: int = 1, n_cont: int = 0) -> np.ndarray:
+def point(case: dict, seed, n_periods: int = 1, n_cont: int = 0, form: str = "polar") -> np.ndarray:
     """An evaluation point drawn inside the variable bounds.
 
     Blocks are concatenated in the model's variable order (va, vm, pg, qg,
     p, q), each block entity-fastest over its replicas (periods or copies);
     with contingency copies the pg block is shared (one replica).  va, which
     is unbounded, is drawn from U(-pi/6, pi/6); p and q of an arc from
-    U(-rate_a, rate_a) of its branch.
+    U(-rate_a, rate_a) of its branch.  For the rectangular form the same
+    draws give the bus blocks (vr, vi) = (vm cos va, vm sin va).
     """
     rng = _rng(seed)
     nrep = n_periods if n_periods > 1 else n_cont + 1
@@ -176,6 +177,10 @@ def point(case: dict, seed, n_periods: int = 1, n_cont: int = 0) -> np.ndarray:
     p = rng.uniform(-np.tile(rate_arc, nrep), np.tile(rate_arc, nrep))
     q = rng.uniform(-np.tile(rate_arc, nrep), np.tile(rate_arc, nrep))
     assert p.size == 2 * L * nrep and pg.size == G * npg
+    if form == "rect":
+        va, vm = vm * np.cos(va), vm * np.sin(va)
+    elif form != "polar":
+        raise ValueError(f"unknown form {form!r}")
     return np.concatenate([va, vm, pg, qg, p, q])
 
 
