@@ -214,6 +214,23 @@ int opf_eval_set(opf_model model, const double *x, const double *y, double obj_w
  * constraints, each entry gathered in a fixed order (no atomics). */
 int opf_jtprod(opf_model model, const double *x, const double *v, double *out, void *stream);
 
+/* opf_eval_set for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and bitwise the same results, with their scratch (objective
+ * partials, the one-launch arrival ticket, the half-edge records) taken
+ * from one fixed device array of OPF_NOALLOC_SCRATCH_BYTES per GPU, held
+ * from the first call on that GPU until the process ends, instead of the
+ * model's own.  The call allocates nothing and enqueues at most one more
+ * launch (it zeroes the ticket).  Every call on one GPU shares that array:
+ * calls that overlap in time on one GPU (two streams, two threads) race and
+ * give wrong results; calls ordered on one stream are safe.  OPF_E_ARG if
+ * the model needs more scratch than the array holds (48 bytes per branch,
+ * side and replica plus the partials: about 340k branch replicas), or for
+ * a NULL x, or a NULL y with hvals. */
+#define OPF_NOALLOC_SCRATCH_BYTES (32u << 20)
+int opf_eval_set_noalloc(opf_model model, const double *x, const double *y, double obj_weight, double *f,
+                         double *g, double *c, double *jvals, double *hvals, void *stream);
+
 /* ---------------------------------------------------------------- batch */
 /* Many instances of possibly different networks evaluated together: two
  * kernel launches (branch phase, bus phase) on the caller's stream, each

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libopf.so")
-SOURCES = ["host_model.cpp", "capi.cpp", "batch.cpp", "proxy_capi.cpp", "eval_kernels.hip", "proxy_kernels.hip"]
+SOURCES = ["host_model.cpp", "capi.cpp", "batch.cpp", "proxy_capi.cpp", "eval_kernels.hip", "proxy_kernels.hip", "noalloc.hip"]
 ARCH = os.environ.get("OPF_OFFLOAD_ARCH", "gfx950")
 
 

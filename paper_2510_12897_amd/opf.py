@@ -101,6 +101,7 @@ def lib():
         "opf_hess_coord": ([_vp, _vp, _vp, ctypes.c_double, _vp, _vp], ctypes.c_int),
         "opf_eval_set": ([_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
         "opf_jtprod": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+        "opf_eval_set_noalloc": ([_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
         "opf_batch_create": ([P(_vp), ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, P(_vp)], ctypes.c_int),
         "opf_batch_destroy": ([_vp], ctypes.c_int),
         "opf_batch_offsets": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
@@ -363,6 +364,18 @@ class Model:
             jvals = self._new(self.nnzj) if jvals is None else jvals
             hvals = self._new(self.nnzh) if hvals is None else hvals
         _check(lib().opf_eval_set(
+            self._h, _ptr(x, self.n, torch.float64, "x"), _ptr(y, self.m, torch.float64, "y"),
+            float(obj_weight), _ptr(f, 1, torch.float64, "f"), _ptr(g, self.n, torch.float64, "g"),
+            _ptr(c, self.m, torch.float64, "c"), _ptr(jvals, self.nnzj, torch.float64, "jvals"),
+            _ptr(hvals, self.nnzh, torch.float64, "hvals"), _stream()))
+        return f, g, c, jvals, hvals
+
+    def eval_set_noalloc(self, x, y, obj_weight: float = 1.0, f=None, g=None, c=None, jvals=None, hvals=None):
+        """eval_set through the entry point that allocates nothing (its
+        scratch is the library's fixed per-device array); only the given
+        outputs are computed."""
+        torch = _torch()
+        _check(lib().opf_eval_set_noalloc(
             self._h, _ptr(x, self.n, torch.float64, "x"), _ptr(y, self.m, torch.float64, "y"),
             float(obj_weight), _ptr(f, 1, torch.float64, "f"), _ptr(g, self.n, torch.float64, "g"),
             _ptr(c, self.m, torch.float64, "c"), _ptr(jvals, self.nnzj, torch.float64, "jvals"),
