@@ -105,8 +105,27 @@ typedef struct {
     int32_t n_cont;             /* contingency copies (0 = none); cannot be */
                                 /* combined with n_periods > 1              */
     const int32_t *outaged_branch; /* [n_cont] branch out in copy s+1       */
+    int32_t form;               /* OPF_FORM_POLAR (0) or OPF_FORM_RECT (1)  */
 } opf_opts;
-/* opts may be NULL: static model. */
+/* opts may be NULL: static polar model.
+ *
+ * form = OPF_FORM_RECT is the rectangular form (Sec. III-C1, form = :rect):
+ * the two bus blocks hold vr, vi (V = vr + j vi) in place of va, vm, and
+ * the rows are those of the ACR formulation of the cited PowerModels:
+ *    ref          vi_r                                        = 0
+ *    flow         p_a - F_a(V_f, V_t)                         = 0
+ *                 F = alpha |V_f|^2 + beta |V_t|^2 + a CR + b SI with the
+ *                 polar coefficients, CR = vr_f vr_t + vi_f vi_t,
+ *                 SI = vi_f vr_t - vr_f vi_t (= vm_f vm_t cos / sin th)
+ *    angle        SI - tan(angmax) CR   <= 0
+ *    angle_lo     SI - tan(angmin) CR   >= 0     (a second row per branch)
+ *    balance      as polar with vm^2 = vr^2 + vi^2
+ *    thermal      as polar
+ *    vmag         vr^2 + vi^2              in [vmin^2, vmax^2]  (per bus)
+ *  Constraint blocks: ref | p_fr | q_fr | p_to | q_to | angle | angle_lo |
+ *  balance_p | balance_q | thermal_fr | thermal_to | vmag | (ramp).
+ *  Bounds: vr, vi in [-vmax, vmax]; start point vr = 1, all else 0. */
+enum { OPF_FORM_POLAR = 0, OPF_FORM_RECT = 1 };
 
 /* Maximum number of branches at one bus. */
 #define OPF_MAX_DEGREE 1024
@@ -179,7 +198,9 @@ enum {
     OPF_VAR_VA = 0, OPF_VAR_VM, OPF_VAR_PG, OPF_VAR_QG, OPF_VAR_P, OPF_VAR_Q,
     OPF_CON_REF = 16, OPF_CON_P_FR, OPF_CON_Q_FR, OPF_CON_P_TO, OPF_CON_Q_TO,
     OPF_CON_ANGLE, OPF_CON_BAL_P, OPF_CON_BAL_Q, OPF_CON_THERMAL_FR,
-    OPF_CON_THERMAL_TO, OPF_CON_RAMP
+    OPF_CON_THERMAL_TO, OPF_CON_RAMP,
+    OPF_CON_ANGLE_LO, OPF_CON_VMAG,         /* rectangular form (empty in polar) */
+    OPF_VAR_VR = OPF_VAR_VA, OPF_VAR_VI = OPF_VAR_VM  /* rectangular bus blocks */
 };
 int opf_model_blocks(opf_model model, int32_t which, int64_t *offset, int64_t *len);
 

@@ -44,6 +44,7 @@ struct opf_batch_s {
     int32_t n_items[2][2] = {};
     int32_t wg_per_cu = 0;           // flat until tuned (measured fastest on the 64-instance mix)
     int32_t n_cu = 256;
+    bool rect = false;               // every model is of the rectangular form (else all polar)
 };
 
 namespace {
@@ -99,8 +100,8 @@ int launch(opf_batch_s* b, const opf::BatchArgs& a0, hipStream_t stream) {
     for (int ph = 0; ph < 2; ph++) {
         if (a[ph].n_items == 0) continue;
         void* args[1] = {&a[ph]};
-        const hipError_t e = hipLaunchKernel(opf::batch_kernel_fn(ph, a0.mode, b->wg_per_cu == 0), dim3(grid[ph]),
-                                             dim3(opf::kBlock), args, 0, stream);
+        const hipError_t e = hipLaunchKernel(opf::batch_kernel_fn(ph, a0.mode, b->wg_per_cu == 0, b->rect),
+                                             dim3(grid[ph]), dim3(opf::kBlock), args, 0, stream);
         if (e != hipSuccess) return hip_err(e, ph == 0 ? "batch branch-phase launch" : "batch bus-phase launch");
     }
     return OPF_OK;
@@ -124,6 +125,9 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
     const int dev = models[0]->device;
     for (int32_t k = 1; k < n_models; k++)
         if (models[k]->device != dev) return set_err(OPF_E_ARG, "all models must live on one device");
+    for (int32_t k = 1; k < n_models; k++)
+        if (models[k]->hm.ly.rect != models[0]->hm.ly.rect)
+            return set_err(OPF_E_ARG, "all models of a batch must be of one form (polar or rectangular)");
     for (int32_t j = 0; j < n_inst; j++)
         if (inst_model[j] < 0 || inst_model[j] >= n_models)
             return set_err(OPF_E_ARG, "instance %d names model %d, out of range", j, inst_model[j]);
@@ -132,6 +136,7 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
     try {
         b = new opf_batch_s();
         b->device = dev;
+        b->rect = models[0]->hm.ly.rect != 0;
         b->alloc = current_allocator();
         b->n_inst = n_inst;
         b->xoff.assign(n_inst + 1, 0);
@@ -303,6 +308,7 @@ int opf_batch_set_loads(opf_batch b, const double* pd, const double* qd, void* s
 int opf_batch_flows(opf_batch b, double* X, void* stream) {
     if (!valid(b)) return set_err(OPF_E_STATE, "invalid or destroyed batch handle");
     if (!X) return set_err(OPF_E_ARG, "X must be non-NULL");
+    if (b->rect) return set_err(OPF_E_ARG, "opf_batch_flows takes polar models only");
     DeviceGuard dg(b->device);
     if (dg.err != hipSuccess) return hip_err(dg.err, "hipSetDevice");
     opf::BatchArgs a{};

@@ -97,6 +97,7 @@ ModelOffsets pack_model(Packer& pk, const opf::HostModel& hm) {
     o.ref_list = pk.add(hm.ref_list);
     o.outage = pk.add(hm.outage);
     o.slots_c = pk.add(hm.slots_c);
+    o.tan_lim = pk.add(hm.tan_lim);
     return o;
 }
 
@@ -150,6 +151,10 @@ opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets&
     P32(adj_ptr); P32(he); P32(he_grp); P32(nlo); P32(ndist); P32(hva_off); P32(hvm_off); P32(jbal_off);
     P32(gen_ptr); P32(gen_list); PDB(gs); PDB(bs); PDB(pd); PDB(qd);
     PDB(c2); PDB(c1); PDB(c0); P32(gen_bus); P32(ref_bus); P32(ref_ptr); P32(ref_list); P32(outage); P32(slots_c);
+    PDB(tan_lim);
+    d.rect = ly.rect;
+    d.c_angl = ly.c_blk[B_ANGL]; d.c_vmag = ly.c_blk[B_VMAG];
+    d.j_angl = ly.j_blk[B_ANGL]; d.j_vmag = ly.j_blk[B_VMAG];
 #undef P32
 #undef PDB
     return d;
@@ -361,14 +366,19 @@ int opf_model_blocks(opf_model m, int32_t which, int64_t* offset, int64_t* len) 
     case OPF_VAR_QG: o = ly.x_qg; l = ly.G * P; break;
     case OPF_VAR_P: o = ly.x_p; l = 2LL * ly.L * P; break;
     case OPF_VAR_Q: o = ly.x_q; l = 2LL * ly.L * P; break;
-    default:
-        if (which >= OPF_CON_REF && which <= OPF_CON_RAMP) {
-            const int b = which - OPF_CON_REF;
+    default: {
+        using namespace opf;
+        // OPF_CON_* ids in header order -> constraint blocks
+        static const int kBlk[] = {B_REF, B_PFR, B_QFR, B_PTO, B_QTO, B_ANG, B_BALP, B_BALQ,
+                                   B_THF, B_THT, B_RAMP, B_ANGL, B_VMAG};
+        if (which >= OPF_CON_REF && which <= OPF_CON_VMAG) {
+            const int b = kBlk[which - OPF_CON_REF];
             o = ly.c_blk[b];
             l = ly.c_blk[b + 1] - ly.c_blk[b];
         } else {
             return set_err(OPF_E_ARG, "unknown block id %d", which);
         }
+    }
     }
     if (offset) *offset = o;
     if (len) *len = l;

@@ -101,6 +101,13 @@ struct DevModel {
     // the wave-packed bus segments again, 2 int32 per lane (kind word,
     // index): the compact form the two-launch bus waves read
     const int32_t* slots_c;   // [nwaves * kBlock * 2]
+    // rectangular form (Sec. III-C1): the bus blocks at x_va, x_vm hold
+    // vr, vi; each branch has a second angle row (block c_angl) and each bus
+    // a voltage-magnitude row (block c_vmag).  Kept last, so that the polar
+    // kernels' argument offsets do not move.
+    int32_t rect;
+    int32_t c_angl, c_vmag, j_angl, j_vmag;
+    const double* tan_lim;    // [2][L]: tan(angmax), tan(angmin)
 };
 
 struct EvalOut {

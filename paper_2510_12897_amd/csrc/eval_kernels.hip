@@ -282,6 +282,111 @@ __device__ __forceinline__ void half_edge_record(const DevModel& m, const EvalOu
     }
 }
 
+// ------------------------------------------------------- rectangular form
+// With V = vr + j vi (Sec. III-C1, form = :rect) the branch rows are
+// polynomials: CR = vr_f vr_t + vi_f vi_t and SI = vi_f vr_t - vr_f vi_t
+// stand for vm_f vm_t cos(th) and vm_f vm_t sin(th), Uf = |V_f|^2 and
+// Ut = |V_t|^2 for vm_f^2 and vm_t^2, so every flow is
+//   F = al Uf + be Ut + a CR + b SI
+// with the polar (al, be, a, b), and the two angle rows are SI - tan(lim) CR
+// (al = be = 0, a = -tan(lim), b = 1).  No trigonometry.
+struct RVolt {
+    double rf, rt, jf, jt;  // vr_f, vr_t, vi_f, vi_t
+};
+struct RTerm {
+    double F, Drf, Drt, Djf, Djt;  // value and d/d(vr_f, vr_t, vi_f, vi_t)
+};
+__device__ __forceinline__ RTerm rterm(double al, double be, double a, double b, const RVolt& v, double CR,
+                                       double SI, double Uf, double Ut) {
+    RTerm r;
+    r.F = al * Uf + be * Ut + a * CR + b * SI;
+    r.Drf = 2.0 * al * v.rf + a * v.rt - b * v.jt;
+    r.Drt = 2.0 * be * v.rt + a * v.rf + b * v.jf;
+    r.Djf = 2.0 * al * v.jf + a * v.jt + b * v.rt;
+    r.Djt = 2.0 * be * v.jt + a * v.jf - b * v.rf;
+    return r;
+}
+// Jacobian entries of a row with partials t, columns ascending (vr_lo,
+// vr_hi, vi_lo, vi_hi, then the arc variable's 1 when NV = 5), scaled by sg
+// (-1 for a flow row p - F).
+template <int NV>
+__device__ __forceinline__ void rect_jrow(const RTerm& t, bool f_lo, double sg, double (&v)[NV]) {
+    v[0] = sg * (f_lo ? t.Drf : t.Drt);
+    v[1] = sg * (f_lo ? t.Drt : t.Drf);
+    v[2] = sg * (f_lo ? t.Djf : t.Djt);
+    v[3] = sg * (f_lo ? t.Djt : t.Djf);
+    if constexpr (NV == 5) v[4] = 1.0;
+}
+// The multiplier-weighted sum W = sum_r y_r c_r over a branch's six voltage
+// rows (four flows p - F, two angle rows) as W = al Uf + be Ut + A CR + B SI
+// (+ the linear arc terms): its second derivatives are d2W/dvr_f2 =
+// d2W/dvi_f2 = 2 al, d2W/dvr_t2 = d2W/dvi_t2 = 2 be, d2W/(dvr_f dvr_t) =
+// d2W/(dvi_f dvi_t) = A, d2W/(dvi_f dvr_t) = B, d2W/(dvr_f dvi_t) = -B.
+struct RW {
+    double al, be, A, B;
+};
+__device__ __forceinline__ RW rect_w(const Coef& k, double t5, double t6, double y1, double y2, double y3, double y4,
+                                     double y5, double y6) {
+    RW w;
+    w.al = -(y1 * k.Gff - y2 * k.Bff);
+    w.be = -(y3 * k.Gtt - y4 * k.Btt);
+    w.A = -(y1 * k.Gft - y2 * k.Bft + y3 * k.Gtf - y4 * k.Btf) - y5 * t5 - y6 * t6;
+    w.B = -(y1 * k.Bft + y2 * k.Gft - y3 * k.Btf - y4 * k.Gtf) + y5 + y6;
+    return w;
+}
+// The rectangular half-edge record [D, Bs, D, A, P, Q] of one side (own
+// bus i, other bus k): D = the (vr_i, vr_i) and (vi_i, vi_i) term, Bs = the
+// (vi_i, vr_k) term, A = the (vr_i, vr_k) and (vi_i, vi_k) term; the fields
+// sit where the bus phase sums the polar record's (TT, MA, MM, UW).
+__device__ __forceinline__ void rect_record(const RW& w, uint32_t side, double p, double q, double (&v)[kRec]) {
+    v[R_TT] = side ? 2.0 * w.be : 2.0 * w.al;
+    v[R_MA] = side ? -w.B : w.B;
+    v[R_MM] = v[R_TT];
+    v[R_UW] = w.A;
+    v[R_P] = p;
+    v[R_Q] = q;
+}
+
+// The rectangular record of branch l at one side, recomputed from x and y
+// (one launch).  Loads first, arithmetic second (as half_edge_load / _record).
+struct RHeIn {
+    double p, q, y1, y2, y3, y4, y5, y6, t5, t6;
+    RVolt v;
+};
+__device__ __forceinline__ void rect_edge_load(const DevModel& m, const EvalOut& o, uint32_t l, uint32_t side,
+                                               uint32_t fb, uint32_t tb, int32_t r, RHeIn& e) {
+    const int64_t L = m.L, N = m.N, ob = L * r, oa = 2 * L * r + (side ? L : 0), on = N * r;
+    if (o.c) {
+        e.p = ld(o.x + m.x_p + oa, l);
+        e.q = ld(o.x + m.x_q + oa, l);
+    }
+    if (o.H) {
+        e.y1 = ld(o.y + m.c_pfr + ob, l);
+        e.y2 = ld(o.y + m.c_qfr + ob, l);
+        e.y3 = ld(o.y + m.c_pto + ob, l);
+        e.y4 = ld(o.y + m.c_qto + ob, l);
+        e.y5 = ld(o.y + m.c_ang + ob, l);
+        e.y6 = ld(o.y + m.c_angl + ob, l);
+        e.t5 = ld(m.tan_lim, l);
+        e.t6 = ld(m.tan_lim + L, l);
+        e.v.rf = ld(o.x + m.x_va + on, fb);
+        e.v.rt = ld(o.x + m.x_va + on, tb);
+        e.v.jf = ld(o.x + m.x_vm + on, fb);
+        e.v.jt = ld(o.x + m.x_vm + on, tb);
+    }
+}
+__device__ __forceinline__ void rect_edge_record(const DevModel& m, const EvalOut& o, const RHeIn& e, uint32_t l,
+                                                 uint32_t side, const Coef& k0, int32_t r, double (&v)[kRec]) {
+    if (o.H) {
+        const Coef k = in_service(k0, m, (int32_t)l, r);
+        rect_record(rect_w(k, e.t5, e.t6, e.y1, e.y2, e.y3, e.y4, e.y5, e.y6), side, 0.0, 0.0, v);
+    }
+    if (o.c) {
+        v[R_P] = e.p;
+        v[R_Q] = e.q;
+    }
+}
+
 // ================================================================== phase 1
 template <bool SINGLE>
 __device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r, double* stage) {
@@ -398,6 +503,159 @@ __device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, 
     }
 }
 
+// Phase 1 of the rectangular form: one lane per branch, as branch_task;
+// writes the four flow rows, the two angle rows, the two thermal rows, the
+// arc Hessian diagonals and the half-edge records [D, Bs, D, A, P, Q].
+template <bool SINGLE>
+__device__ void rbranch_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r, double* stage) {
+    const uint32_t l0 = (uint32_t)(chunk * kBlock), l = l0 + threadIdx.x;
+    const uint32_t nvalid = min((uint32_t)kBlock, (uint32_t)m.L - l0);
+    const bool act = l < (uint32_t)m.L;  // inactive lanes still join the LDS staging
+    const int64_t L = m.L, N = m.N;
+    const bool wantC = o.c != nullptr, wantJ = o.J != nullptr, wantH = o.H != nullptr;
+    const int64_t ob = L * r, oa = 2 * L * r, on = N * r;
+    if (wantC || wantJ || wantH) {
+        uint32_t fb = 0, tb = 0;
+        double rate2 = 0.0, pf = 0.0, pt = 0.0, qf = 0.0, qt = 0.0, t5 = 0.0, t6 = 0.0;
+        double yf = 0.0, yt = 0.0, y1 = 0.0, y2 = 0.0, y3 = 0.0, y4 = 0.0, y5 = 0.0, y6 = 0.0;
+        RVolt v{1.0, 1.0, 0.0, 0.0};
+        Coef k{};
+        if (act) {
+            fb = (uint32_t)ld(m.f_bus, l);
+            tb = (uint32_t)ld(m.t_bus, l);
+            k = in_service(load_coef(m, l), m, (int32_t)l, r);
+            if (wantC) rate2 = ld(m.rate2, l);
+            t5 = ld(m.tan_lim, l);
+            t6 = ld(m.tan_lim + L, l);
+            const double* xp = o.x + m.x_p + oa;
+            const double* xq = o.x + m.x_q + oa;
+            pf = ld(xp, l);
+            pt = ld(xp + L, l);
+            qf = ld(xq, l);
+            qt = ld(xq + L, l);
+            if (wantH) {
+                yf = ld(o.y + m.c_thf + ob, l);
+                yt = ld(o.y + m.c_tht + ob, l);
+                y1 = ld(o.y + m.c_pfr + ob, l);
+                y2 = ld(o.y + m.c_qfr + ob, l);
+                y3 = ld(o.y + m.c_pto + ob, l);
+                y4 = ld(o.y + m.c_qto + ob, l);
+                y5 = ld(o.y + m.c_ang + ob, l);
+                y6 = ld(o.y + m.c_angl + ob, l);
+            }
+            v.rf = ld(o.x + m.x_va + on, fb);
+            v.rt = ld(o.x + m.x_va + on, tb);
+            v.jf = ld(o.x + m.x_vm + on, fb);
+            v.jt = ld(o.x + m.x_vm + on, tb);
+        }
+        const bool f_lo = fb < tb;
+        const double CR = v.rf * v.rt + v.jf * v.jt, SI = v.jf * v.rt - v.rf * v.jt;
+        const double Uf = v.rf * v.rf + v.jf * v.jf, Ut = v.rt * v.rt + v.jt * v.jt;
+        const RTerm f1 = rterm(k.Gff, 0.0, k.Gft, k.Bft, v, CR, SI, Uf, Ut);
+        const RTerm f2 = rterm(-k.Bff, 0.0, -k.Bft, k.Gft, v, CR, SI, Uf, Ut);
+        const RTerm f3 = rterm(0.0, k.Gtt, k.Gtf, -k.Btf, v, CR, SI, Uf, Ut);
+        const RTerm f4 = rterm(0.0, -k.Btt, -k.Btf, -k.Gtf, v, CR, SI, Uf, Ut);
+        const RTerm a5 = rterm(0.0, 0.0, -t5, 1.0, v, CR, SI, Uf, Ut);
+        const RTerm a6 = rterm(0.0, 0.0, -t6, 1.0, v, CR, SI, Uf, Ut);
+        if (wantC && act) {
+            st(o.c + m.c_pfr + ob, l, pf - f1.F);
+            st(o.c + m.c_qfr + ob, l, qf - f2.F);
+            st(o.c + m.c_pto + ob, l, pt - f3.F);
+            st(o.c + m.c_qto + ob, l, qt - f4.F);
+            st(o.c + m.c_ang + ob, l, a5.F);
+            st(o.c + m.c_angl + ob, l, a6.F);
+            st(o.c + m.c_thf + ob, l, pf * pf + qf * qf - rate2);
+            st(o.c + m.c_tht + ob, l, pt * pt + qt * qt - rate2);
+        }
+        if (wantJ) {
+            // flow rows (vr_lo, vr_hi, vi_lo, vi_hi, arc) and angle rows
+            // (vr_lo, vr_hi, vi_lo, vi_hi), staged through LDS
+            double v5[5], v4[4];
+            rect_jrow(f1, f_lo, -1.0, v5);
+            store_run<5>(stage, o.J + m.j_pfr + 5 * ob, 5 * l0, nvalid, v5);
+            rect_jrow(f2, f_lo, -1.0, v5);
+            store_run<5>(stage, o.J + m.j_qfr + 5 * ob, 5 * l0, nvalid, v5);
+            rect_jrow(f3, f_lo, -1.0, v5);
+            store_run<5>(stage, o.J + m.j_pto + 5 * ob, 5 * l0, nvalid, v5);
+            rect_jrow(f4, f_lo, -1.0, v5);
+            store_run<5>(stage, o.J + m.j_qto + 5 * ob, 5 * l0, nvalid, v5);
+            rect_jrow(a5, f_lo, 1.0, v4);
+            store_run<4>(stage, o.J + m.j_ang + 4 * ob, 4 * l0, nvalid, v4);
+            rect_jrow(a6, f_lo, 1.0, v4);
+            store_run<4>(stage, o.J + m.j_angl + 4 * ob, 4 * l0, nvalid, v4);
+            if (act) {
+                st(o.J + m.j_thf + 2 * ob, 2 * l, 2.0 * pf);
+                st(o.J + m.j_thf + 2 * ob, 2 * l + 1, 2.0 * qf);
+                st(o.J + m.j_tht + 2 * ob, 2 * l, 2.0 * pt);
+                st(o.J + m.j_tht + 2 * ob, 2 * l + 1, 2.0 * qt);
+            }
+        }
+        if (wantH && act) {
+            st(o.H + m.h_p + oa, l, 2.0 * yf);
+            st(o.H + m.h_p + oa + L, l, 2.0 * yt);
+            st(o.H + m.h_q + oa, l, 2.0 * yf);
+            st(o.H + m.h_q + oa + L, l, 2.0 * yt);
+        }
+        if (wantH && !SINGLE) {
+            const RW w = rect_w(k, t5, t6, y1, y2, y3, y4, y5, y6);
+            double rf[kRec], rt[kRec];
+            rect_record(w, 0, pf, qf, rf);
+            rect_record(w, 1, pt, qt, rt);
+            store_run<kRecStride, true>(stage, rec_side(m, r, 0), kRecStride * l0, nvalid, rf);
+            store_run<kRecStride, true>(stage, rec_side(m, r, 1), kRecStride * l0, nvalid, rt);
+        } else if (wantC && !SINGLE) {
+            const double rf[kRecPQ] = {pf, qf};
+            store_run<kRecPQ, true>(stage, rec_side(m, r, 0), kRecPQ * l0, nvalid, rf);
+            const double rt[kRecPQ] = {pt, qt};
+            store_run<kRecPQ, true>(stage, rec_side(m, r, 1), kRecPQ * l0, nvalid, rt);
+        }
+    }
+    if (o.g && act) {
+        st(o.g + m.x_p + oa, l, 0.0);
+        st(o.g + m.x_p + oa + L, l, 0.0);
+        st(o.g + m.x_q + oa, l, 0.0);
+        st(o.g + m.x_q + oa + L, l, 0.0);
+    }
+}
+
+// J^T v of the rectangular form, phase 1: the arc entries (as polar) and
+// each half-edge's (vr, vi) terms: the gradient of W = sum_r v_r c_r over
+// the branch's six voltage rows at the side's own bus.
+__device__ void rjt_branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r) {
+    const uint32_t l = (uint32_t)(chunk * kBlock) + threadIdx.x;
+    if (l >= (uint32_t)m.L) return;
+    const int64_t L = m.L, N = m.N;
+    const uint32_t fb = (uint32_t)ld(m.f_bus, l), tb = (uint32_t)ld(m.t_bus, l);
+    const Coef k0 = load_coef(m, l);
+    const double t5 = ld(m.tan_lim, l), t6 = ld(m.tan_lim + L, l);
+    const double* x = o.x;
+    const double* v = o.y;
+    const int64_t ob = L * r, oa = 2 * L * r, on = N * r;
+    const double vtf = ld(v + m.c_thf + ob, l), vtt = ld(v + m.c_tht + ob, l);
+    const double v1 = ld(v + m.c_pfr + ob, l), v2 = ld(v + m.c_qfr + ob, l);
+    const double v3 = ld(v + m.c_pto + ob, l), v4 = ld(v + m.c_qto + ob, l);
+    const double v5 = ld(v + m.c_ang + ob, l), v6 = ld(v + m.c_angl + ob, l);
+    const double pf = ld(x + m.x_p + oa, l), pt = ld(x + m.x_p + oa + L, l);
+    const double qf = ld(x + m.x_q + oa, l), qt = ld(x + m.x_q + oa + L, l);
+    const double bpf = ld(v + m.c_balp + on, fb), bpt = ld(v + m.c_balp + on, tb);
+    const double bqf = ld(v + m.c_balq + on, fb), bqt = ld(v + m.c_balq + on, tb);
+    RVolt e;
+    e.rf = ld(x + m.x_va + on, fb);
+    e.rt = ld(x + m.x_va + on, tb);
+    e.jf = ld(x + m.x_vm + on, fb);
+    e.jt = ld(x + m.x_vm + on, tb);
+    const Coef k = in_service(k0, m, (int32_t)l, r);
+    st(o.g + m.x_p + oa, l, v1 + bpf + 2.0 * pf * vtf);
+    st(o.g + m.x_p + oa + L, l, v3 + bpt + 2.0 * pt * vtt);
+    st(o.g + m.x_q + oa, l, v2 + bqf + 2.0 * qf * vtf);
+    st(o.g + m.x_q + oa + L, l, v4 + bqt + 2.0 * qt * vtt);
+    const RW w = rect_w(k, t5, t6, v1, v2, v3, v4, v5, v6);
+    const double CR = 0.0, SI = 0.0;
+    const RTerm d = rterm(w.al, w.be, w.A, w.B, e, CR, SI, 0.0, 0.0);
+    st_keep(reinterpret_cast<double2*>(jt_rec_side(m, r, 0)), l, make_double2(d.Drf, d.Djf));
+    st_keep(reinterpret_cast<double2*>(jt_rec_side(m, r, 1)), l, make_double2(d.Drt, d.Djt));
+}
+
 // J^T v, phase 1: the arc entries p / q (owned here) and each half-edge's
 // va / vm terms for the bus side.
 __device__ void jt_branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r) {
@@ -475,7 +733,9 @@ __device__ __forceinline__ Slot load_slot(const DevModel& m, int32_t w) {
 #define H1 (SINGLE ? sl.h1 : h1)
 #define H2 (SINGLE ? sl.h2 : h2)
 #define JP (SINGLE ? sl.jpos : jp)
-template <bool SINGLE>
+// RECT: the rectangular form (bus blocks vr, vi; records [D, Bs, D, A, P, Q];
+// a voltage-magnitude row per head).
+template <bool SINGLE, bool RECT = false>
 __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_t r, double* lds) {
     const int32_t lane = threadIdx.x;
     const bool wantC = o.c != nullptr, wantH = o.H != nullptr;
@@ -519,14 +779,19 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
         // under their own lane type and get no default: writing a default
         // into a register another type's load is still filling would make
         // the wave wait for that load.
-        double gs, bs, vm_i, pd, qd, yp, yq, gp, gq;
+        double gs, bs, vm_i, vr_i, pd, qd, yp, yq, ymag, gp, gq;
         double2 ra, rb, rc;
         HeIn e;
+        RHeIn re;
         int32_t jrow, hva0, hvm0, nlo, nd;  // the head's per-bus offsets (compact slots)
         if (type == SK_HEAD) {
             gs = ld(m.gs, bus);
             bs = ld(m.bs, bus);
-            vm_i = ld(o.x + m.x_vm + on, bus);
+            vm_i = ld(o.x + m.x_vm + on, bus);  // rectangular: vi_i
+            if (RECT) {
+                vr_i = ld(o.x + m.x_va + on, bus);
+                if (wantH) ymag = ld(o.y + m.c_vmag + on, bus);
+            }
             if (!SINGLE) {
                 if (o.J) jrow = ld(m.jbal_off, bus);
                 if (wantH) {
@@ -547,7 +812,10 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
             }
         } else if (type == SK_EDGE && SINGLE) {
             const uint32_t other = (uint32_t)sl.other;
-            half_edge_load(m, o, ref, side, side ? other : bus, side ? bus : other, r, e);
+            if (RECT)
+                rect_edge_load(m, o, ref, side, side ? other : bus, side ? bus : other, r, re);
+            else
+                half_edge_load(m, o, ref, side, side ? other : bus, side ? bus : other, r, e);
         } else if (type == SK_EDGE) {
             const double2* rec = reinterpret_cast<const double2*>(rec_side(m, r, (int32_t)side));
             if (wantH) {
@@ -565,13 +833,18 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
         double v[kRec] = {0, 0, 0, 0, 0, 0};
         double base_p = 0.0, base_q = 0.0, shunt = 0.0;
         if (type == SK_HEAD) {
+            // vm^2 (rectangular: vr^2 + vi^2)
+            const double v2 = RECT ? vr_i * vr_i + vm_i * vm_i : vm_i * vm_i;
             if (wantC) {
-                base_p = pd + gs * vm_i * vm_i;
-                base_q = qd - bs * vm_i * vm_i;
+                base_p = pd + gs * v2;
+                base_q = qd - bs * v2;
             }
-            if (wantH) shunt = 2.0 * gs * yp - 2.0 * bs * yq;
+            if (wantH) shunt = 2.0 * gs * yp - 2.0 * bs * yq + (RECT ? 2.0 * ymag : 0.0);
         } else if (type == SK_EDGE && SINGLE) {
-            half_edge_record(m, o, e, ref, side, k, r, v);
+            if (RECT)
+                rect_edge_record(m, o, re, ref, side, k, r, v);
+            else
+                half_edge_record(m, o, e, ref, side, k, r, v);
         } else if (type == SK_EDGE) {
             if (wantH) {
                 v[R_TT] = ra.x;
@@ -596,8 +869,23 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
         int32_t jp = 0, h0, h1, h2;
         if constexpr (!SINGLE) {
             const int32_t hl = (kind >> 14) & 63;
-            if (o.J) jp = __shfl(jrow, hl, kBlock) + ((kind >> 20) & 63);
-            if (wantH) {
+            // the rectangular balance rows lead with two bus entries
+            if (o.J) jp = __shfl(jrow, hl, kBlock) + ((kind >> 20) & 63) + (RECT && type != SK_HEAD ? 1 : 0);
+            if (wantH && RECT) {
+                const int32_t hva_b = __shfl(hva0, hl, kBlock), hvm_b = __shfl(hvm0, hl, kBlock);
+                const int32_t nd_b = __shfl(nd, hl, kBlock);
+                if (type == SK_HEAD) {  // (vr_i, vr_i), (vi_i, vi_i)
+                    h0 = hva_b + nlo;
+                    h1 = -1;
+                    h2 = hvm_b + nd_b + nlo;
+                } else {  // (vr_i, vr_k), (vi_i, vr_k), (vi_i, vi_k) of the group
+                    const int32_t grp = (int32_t)((uint32_t)kind >> 26);
+                    const bool klo = kind & 16;
+                    h0 = klo ? hva_b + grp : -1;
+                    h1 = hvm_b + grp;
+                    h2 = klo ? hvm_b + nd_b + grp : -1;
+                }
+            } else if (wantH) {
                 const int32_t hva_b = __shfl(hva0, hl, kBlock), hvm_b = __shfl(hvm0, hl, kBlock);
                 const int32_t nd_b = __shfl(nd, hl, kBlock);
                 if (type == SK_HEAD) {  // (va_i, va_i), (vm_i, va_i), (vm_i, vm_i)
@@ -635,13 +923,19 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
                 if (wantC) {
                     st(o.c + m.c_balp + on, bus, sp);
                     st(o.c + m.c_balq + on, bus, sq);
+                    if (RECT) st(o.c + m.c_vmag + on, bus, vr_i * vr_i + vm_i * vm_i);
                 }
                 // The Hessian entries of a bus are single scattered values;
                 // in the two-launch shape they merge into whole lines in L2
                 // before they are written back (streaming them: 16-point
                 // batch 55 -> 60 us, 64-scenario batch 114 -> 128 us), while
                 // in the one launch streaming them is faster.
-                if (wantH) {
+                if (wantH && RECT) {  // the two diagonals; no (vi_i, vr_i) entry
+                    double* hva = o.H + m.h_va + m.hva_rep * r;
+                    double* hvm = o.H + m.h_vm + m.hvm_rep * r;
+                    st_sel<SINGLE>(hva, (uint32_t)H0, daa + shunt);
+                    st_sel<SINGLE>(hvm, (uint32_t)H2, dmm + shunt);
+                } else if (wantH) {
                     double* hva = o.H + m.h_va + m.hva_rep * r;
                     double* hvm = o.H + m.h_vm + m.hvm_rep * r;
                     if (H0 >= 0) st_sel<SINGLE>(hva, (uint32_t)H0, daa);
@@ -658,8 +952,10 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
                 }
                 double* hva = o.H + m.h_va + m.hva_rep * r;
                 double* hvm = o.H + m.h_vm + m.hvm_rep * r;
-                if (H0 >= 0) st_sel<SINGLE>(hva, (uint32_t)H0, -tt);
-                st_sel<SINGLE>(hvm, (uint32_t)H1, -ma);
+                // polar: (va_i, va_k) = -TT, (vm_i, va_k) = -MA, (vm_i, vm_k) = UW;
+                // rectangular: (vr_i, vr_k) = A, (vi_i, vr_k) = Bs, (vi_i, vi_k) = A
+                if (H0 >= 0) st_sel<SINGLE>(hva, (uint32_t)H0, RECT ? uw : -tt);
+                st_sel<SINGLE>(hvm, (uint32_t)H1, RECT ? ma : -ma);
                 if (H2 >= 0) st_sel<SINGLE>(hvm, (uint32_t)H2, uw);
             }
             __syncthreads();  // LDS is reused by the next replica
@@ -672,8 +968,18 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
             } else {
                 vp = vq = (type == SK_EDGE) ? 1.0 : -1.0;
             }
-            st(o.J + m.j_balp + m.jbal_rep * r, (uint32_t)JP, vp);
-            st(o.J + m.j_balq + m.jbal_rep * r, (uint32_t)JP, vq);
+            if (RECT && type == SK_HEAD) {
+                // (vr_i, vi_i) of both balance rows, then the magnitude row
+                st(o.J + m.j_balp + m.jbal_rep * r, (uint32_t)JP, 2.0 * gs * vr_i);
+                st(o.J + m.j_balq + m.jbal_rep * r, (uint32_t)JP, -2.0 * bs * vr_i);
+                st(o.J + m.j_balp + m.jbal_rep * r, (uint32_t)JP + 1, vp);
+                st(o.J + m.j_balq + m.jbal_rep * r, (uint32_t)JP + 1, vq);
+                st(o.J + m.j_vmag + 2 * on, 2 * bus, 2.0 * vr_i);
+                st(o.J + m.j_vmag + 2 * on, 2 * bus + 1, 2.0 * vm_i);
+            } else {
+                st(o.J + m.j_balp + m.jbal_rep * r, (uint32_t)JP, vp);
+                st(o.J + m.j_balq + m.jbal_rep * r, (uint32_t)JP, vq);
+            }
         }
         if (o.g && type == SK_HEAD) {
             st(o.g + m.x_va + on, bus, 0.0);
@@ -686,7 +992,8 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
 #undef H2
 #undef JP
 
-// J^T v, phase 2: va / vm entries of the packed buses.
+// J^T v, phase 2: va / vm (rectangular: vr / vi) entries of the packed buses.
+template <bool RECT = false>
 __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_t r, double* lds) {
     const int32_t lane = threadIdx.x;
     // the compact slot: lane type, side, segment length; the index is the
@@ -705,12 +1012,16 @@ __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int
         // (one memory round trip); loaded values get no default (see
         // wave_task)
         double2 t;
-        double vm, gs, bs, vp, vq;
+        double vm, vr, gs, bs, vp, vq, vg;
         int32_t q0, q1;
         if (type == SK_EDGE) {
             t = ld(reinterpret_cast<const double2*>(jt_rec_side(m, r, (int32_t)side)), ref);
         } else if (type == SK_HEAD) {
-            vm = ld(x + m.x_vm + on, bus);
+            vm = ld(x + m.x_vm + on, bus);  // rectangular: vi
+            if (RECT) {
+                vr = ld(x + m.x_va + on, bus);
+                vg = ld(v + m.c_vmag + on, bus);
+            }
             gs = ld(m.gs, bus);
             bs = ld(m.bs, bus);
             vp = ld(v + m.c_balp + on, bus);
@@ -727,9 +1038,16 @@ __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int
                 sa += lds[0 * kBlock + lane + j];
                 sm += lds[1 * kBlock + lane + j];
             }
+            double sref = 0.0;
             for (int32_t q = q0; q < q1; q++)  // the reference row (one bus)
-                sa += ld(v + m.c_ref + (int64_t)m.R * r, (uint32_t)ld(m.ref_list, (uint32_t)q));
-            sm += 2.0 * gs * vm * vp - 2.0 * bs * vm * vq;
+                sref += ld(v + m.c_ref + (int64_t)m.R * r, (uint32_t)ld(m.ref_list, (uint32_t)q));
+            if (RECT) {  // balance rows' shunt terms and the magnitude row; ref row on vi
+                sa += 2.0 * gs * vr * vp - 2.0 * bs * vr * vq + 2.0 * vr * vg;
+                sm += 2.0 * gs * vm * vp - 2.0 * bs * vm * vq + 2.0 * vm * vg + sref;
+            } else {
+                sa += sref;
+                sm += 2.0 * gs * vm * vp - 2.0 * bs * vm * vq;
+            }
             st(o.g + m.x_va + on, bus, sa);
             st(o.g + m.x_vm + on, bus, sm);
         }
@@ -739,16 +1057,22 @@ __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int
 
 // The record of half-edge `code` (branch << 1 | from-side flag) of a big
 // bus: recomputed in a single launch, else read from the branch phase.
-template <bool SINGLE>
+template <bool SINGLE, bool RECT>
 __device__ __forceinline__ void big_record(const DevModel& m, const EvalOut& o, int32_t code, int32_t r,
                                            const double* rec0, const double* rec1, double (&v)[kRec]) {
     const uint32_t l = (uint32_t)(code >> 1), side = (code & 1) ? 0u : 1u;
     if (SINGLE) {
         for (int q = 0; q < kRec; q++) v[q] = 0.0;
         const Coef k = o.H ? load_coef(m, l) : Coef{};
-        HeIn e{};
-        half_edge_load(m, o, l, side, (uint32_t)ld(m.f_bus, l), (uint32_t)ld(m.t_bus, l), r, e);
-        half_edge_record(m, o, e, l, side, k, r, v);
+        if (RECT) {
+            RHeIn e{};
+            rect_edge_load(m, o, l, side, (uint32_t)ld(m.f_bus, l), (uint32_t)ld(m.t_bus, l), r, e);
+            rect_edge_record(m, o, e, l, side, k, r, v);
+        } else {
+            HeIn e{};
+            half_edge_load(m, o, l, side, (uint32_t)ld(m.f_bus, l), (uint32_t)ld(m.t_bus, l), r, e);
+            half_edge_record(m, o, e, l, side, k, r, v);
+        }
     } else if (o.H) {
         const double* rec = (side == 0 ? rec0 : rec1) + (int64_t)l * kRecStride;
         for (int q = 0; q < kRec; q++) v[q] = rec[q];
@@ -762,7 +1086,7 @@ __device__ __forceinline__ void big_record(const DevModel& m, const EvalOut& o, 
 
 // A bus whose segment does not fit a wave: the workgroup sums its
 // half-edges' records (lane-strided, then a fixed wave tree).
-template <bool SINGLE>
+template <bool SINGLE, bool RECT = false>
 __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32_t r) {
     const int32_t b = m.big_bus[idx];
     const int32_t e0 = m.adj_ptr[b], e1 = m.adj_ptr[b + 1], deg = e1 - e0;
@@ -773,14 +1097,16 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
     const double gs = m.gs[b], bs = m.bs[b];
     {  // replica r
         const int64_t bi = b + N * r;
-        const double vm = x[m.x_vm + bi];
+        const double vm = x[m.x_vm + bi];             // rectangular: vi
+        const double vr = RECT ? x[m.x_va + bi] : 0.0;
+        const double v2 = RECT ? vr * vr + vm * vm : vm * vm;
         const double* rec0 = rec_side(m, r, 0);
         const double* rec1 = rec_side(m, r, 1);
         if (wantC || wantH) {
             double sp = 0.0, sq = 0.0, daa = 0.0, dma = 0.0, dmm = 0.0;
             for (int32_t q = threadIdx.x; q < deg; q += kBlock) {
                 double rec[kRec];
-                big_record<SINGLE>(m, o, m.he[e0 + q], r, rec0, rec1, rec);
+                big_record<SINGLE, RECT>(m, o, m.he[e0 + q], r, rec0, rec1, rec);
                 if (wantC) {
                     sp += rec[R_P];
                     sq += rec[R_Q];
@@ -807,12 +1133,18 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
                     double tt = 0.0, ma = 0.0, uw = 0.0;
                     for (int32_t q = e; q < e1 && m.he_grp[q] == grp; q++) {
                         double rec[kRec];
-                        big_record<SINGLE>(m, o, m.he[q], r, rec0, rec1, rec);
+                        big_record<SINGLE, RECT>(m, o, m.he[q], r, rec0, rec1, rec);
                         tt += rec[R_TT];
                         ma += rec[R_MA];
                         uw += rec[R_UW];
                     }
-                    if (k < b) {
+                    if (RECT) {  // (vr_i, vr_k) = A, (vi_i, vr_k) = Bs, (vi_i, vi_k) = A
+                        o.H[hvm + grp] = ma;
+                        if (k < b) {
+                            o.H[hva + grp] = uw;
+                            o.H[hvm + m.ndist[b] + grp] = uw;
+                        }
+                    } else if (k < b) {
                         o.H[hva + grp] = -tt;
                         o.H[hvm + grp] = -ma;
                         o.H[hvm + m.ndist[b] + 1 + grp] = uw;
@@ -824,7 +1156,7 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
             if (threadIdx.x == 0) {
                 if (wantC) {
                     const int64_t ld_ = b + (int64_t)m.load_stride * r;
-                    double cp = m.pd[ld_] + gs * vm * vm + sp, cq = m.qd[ld_] - bs * vm * vm + sq;
+                    double cp = m.pd[ld_] + gs * v2 + sp, cq = m.qd[ld_] - bs * v2 + sq;
                     const int64_t pgb = m.x_pg + G * (m.npg > 1 ? r : 0), qgb = m.x_qg + G * r;
                     for (int32_t q = 0; q < ng; q++) {
                         cp -= x[pgb + m.gen_list[g0 + q]];
@@ -832,24 +1164,42 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
                     }
                     o.c[m.c_balp + bi] = cp;
                     o.c[m.c_balq + bi] = cq;
+                    if (RECT) o.c[m.c_vmag + bi] = v2;
                 }
                 if (wantH) {
-                    const double shunt = 2.0 * gs * o.y[m.c_balp + bi] - 2.0 * bs * o.y[m.c_balq + bi];
+                    const double shunt = 2.0 * gs * o.y[m.c_balp + bi] - 2.0 * bs * o.y[m.c_balq + bi] +
+                                         (RECT ? 2.0 * o.y[m.c_vmag + bi] : 0.0);
                     const int64_t hva = m.h_va + m.hva_rep * r + m.hva_off[b];
                     const int64_t hvm = m.h_vm + m.hvm_rep * r + m.hvm_off[b];
                     const int32_t nlo = m.nlo[b];
-                    o.H[hva + nlo] = daa;
-                    o.H[hvm + nlo] = dma;
-                    o.H[hvm + m.ndist[b] + 1 + nlo] = dmm + shunt;
+                    if (RECT) {
+                        o.H[hva + nlo] = daa + shunt;
+                        o.H[hvm + m.ndist[b] + nlo] = dmm + shunt;
+                    } else {
+                        o.H[hva + nlo] = daa;
+                        o.H[hvm + nlo] = dma;
+                        o.H[hvm + m.ndist[b] + 1 + nlo] = dmm + shunt;
+                    }
                 }
             }
         }
         if (o.J) {
             double* Jp = o.J + m.j_balp + m.jbal_rep * r + m.jbal_off[b];
             double* Jq = o.J + m.j_balq + m.jbal_rep * r + m.jbal_off[b];
-            for (int32_t q = threadIdx.x; q < 1 + ng + deg; q += kBlock) {
-                Jp[q] = q == 0 ? 2.0 * gs * vm : (q <= ng ? -1.0 : 1.0);
-                Jq[q] = q == 0 ? -2.0 * bs * vm : (q <= ng ? -1.0 : 1.0);
+            if (RECT) {  // (vr_i, vi_i), generators, arcs; then the magnitude row
+                for (int32_t q = threadIdx.x; q < 2 + ng + deg; q += kBlock) {
+                    Jp[q] = q == 0 ? 2.0 * gs * vr : q == 1 ? 2.0 * gs * vm : (q <= ng + 1 ? -1.0 : 1.0);
+                    Jq[q] = q == 0 ? -2.0 * bs * vr : q == 1 ? -2.0 * bs * vm : (q <= ng + 1 ? -1.0 : 1.0);
+                }
+                if (threadIdx.x == 0) {
+                    o.J[m.j_vmag + 2 * bi] = 2.0 * vr;
+                    o.J[m.j_vmag + 2 * bi + 1] = 2.0 * vm;
+                }
+            } else {
+                for (int32_t q = threadIdx.x; q < 1 + ng + deg; q += kBlock) {
+                    Jp[q] = q == 0 ? 2.0 * gs * vm : (q <= ng ? -1.0 : 1.0);
+                    Jq[q] = q == 0 ? -2.0 * bs * vm : (q <= ng ? -1.0 : 1.0);
+                }
             }
         }
         if (o.g && threadIdx.x == 0) {
@@ -859,6 +1209,7 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
     }
 }
 
+template <bool RECT = false>
 __device__ void jt_big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32_t r) {
     const int32_t b = m.big_bus[idx];
     const int32_t e0 = m.adj_ptr[b], deg = m.adj_ptr[b + 1] - e0;
@@ -879,9 +1230,19 @@ __device__ void jt_big_task(const DevModel& m, const EvalOut& o, int32_t idx, in
         sm = wave_sum(sm);
         if (threadIdx.x == 0) {
             const int64_t bi = b + N * r;
-            for (int32_t q = m.ref_ptr[b]; q < m.ref_ptr[b + 1]; q++) sa += v[m.c_ref + m.ref_list[q] + (int64_t)m.R * r];
-            const double vm = x[m.x_vm + bi];
-            sm += 2.0 * m.gs[b] * vm * v[m.c_balp + bi] - 2.0 * m.bs[b] * vm * v[m.c_balq + bi];
+            double sref = 0.0;
+            for (int32_t q = m.ref_ptr[b]; q < m.ref_ptr[b + 1]; q++)
+                sref += v[m.c_ref + m.ref_list[q] + (int64_t)m.R * r];
+            const double vm = x[m.x_vm + bi];  // rectangular: vi
+            const double vp = v[m.c_balp + bi], vq = v[m.c_balq + bi];
+            if (RECT) {
+                const double vr = x[m.x_va + bi], vg = v[m.c_vmag + bi];
+                sa += 2.0 * m.gs[b] * vr * vp - 2.0 * m.bs[b] * vr * vq + 2.0 * vr * vg;
+                sm += 2.0 * m.gs[b] * vm * vp - 2.0 * m.bs[b] * vm * vq + 2.0 * vm * vg + sref;
+            } else {
+                sa += sref;
+                sm += 2.0 * m.gs[b] * vm * vp - 2.0 * m.bs[b] * vm * vq;
+            }
             o.g[m.x_va + bi] = sa;
             o.g[m.x_vm + bi] = sm;
         }
@@ -893,7 +1254,7 @@ __device__ void jt_big_task(const DevModel& m, const EvalOut& o, int32_t idx, in
 // reference and ramp rows, and one objective partial per replica (a fixed
 // wave tree over the chunk), written with a plain store: the objective item
 // of phase 2 reads the partials after the launch boundary.
-template <bool SINGLE>
+template <bool SINGLE, bool RECT = false>
 __device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r) {
     const uint32_t k = (uint32_t)(chunk * kBlock) + threadIdx.x;
     const double* x = o.x;
@@ -910,7 +1271,8 @@ __device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int
         const bool ramp = isgen && m.T > 1 && r >= 1;
         const double pg = (isgen && r < m.npg) ? ld(x + m.x_pg + G * r, k) : 0.0;
         const double pr = ramp ? ld(x + m.x_pg + G * r, k) - ld(x + m.x_pg + G * (r - 1), k) : 0.0;
-        const double var = (isref && o.c) ? ld(x + m.x_va + (int64_t)m.N * r, rbus) : 0.0;
+        // the reference row: va_r (rectangular: vi_r)
+        const double var = (isref && o.c) ? ld(x + (RECT ? m.x_vm : m.x_va) + (int64_t)m.N * r, rbus) : 0.0;
         double fk = 0.0;
         if (isgen) {
             if (r < m.npg) {
@@ -1022,34 +1384,41 @@ __device__ void jt_gen_task(const DevModel& m, const EvalOut& o, int32_t idx, in
 // Every work item covers one replica: a loop over replicas inside an item
 // lets the compiler turn each output stream into its own per-lane 64-bit
 // pointer (more than doubling the branch task's registers).
-template <int MODE>
+// RECT selects the rectangular form's tasks (every kernel is instantiated
+// for both forms; a launch takes the model's).
+template <int MODE, bool RECT>
 __device__ __forceinline__ void run_phase1(const DevModel& m, const EvalOut& o, int32_t kind, int32_t idx, int32_t r,
                                            double* stage) {
     if (MODE == 0) {
         if (kind == T_GEN)
-            gen_task<false>(m, o, idx, r);
+            gen_task<false, RECT>(m, o, idx, r);
+        else if (RECT)
+            rbranch_task<false>(m, o, idx, r, stage);
         else
             branch_task<false>(m, o, idx, r, stage);
     } else if (MODE == 1) {
-        jt_branch_task(m, o, idx, r);
+        if (RECT)
+            rjt_branch_task(m, o, idx, r);
+        else
+            jt_branch_task(m, o, idx, r);
     } else {
         flows_task(m, o, idx, r);
     }
 }
 
-template <int MODE>
+template <int MODE, bool RECT>
 __device__ __forceinline__ void run_phase2(const DevModel& m, const EvalOut& o, int32_t kind, int32_t idx, int32_t r,
                                            double* lds) {
     if (MODE == 0) {
         switch (kind) {
-        case T_BIG: big_task<false>(m, o, idx, r); break;
-        case T_WAVE: wave_task<false>(m, o, idx, r, lds); break;
+        case T_BIG: big_task<false, RECT>(m, o, idx, r); break;
+        case T_WAVE: wave_task<false, RECT>(m, o, idx, r, lds); break;
         default: obj_task(m, o); break;
         }
     } else {
         switch (kind) {
-        case T_BIG: jt_big_task(m, o, idx, r); break;
-        case T_WAVE: jt_wave_task(m, o, idx, r, lds); break;
+        case T_BIG: jt_big_task<RECT>(m, o, idx, r); break;
+        case T_WAVE: jt_wave_task<RECT>(m, o, idx, r, lds); break;
         default: jt_gen_task(m, o, idx, r); break;
         }
     }
@@ -1098,12 +1467,12 @@ __device__ __forceinline__ void decode_phase2(const SetGrid& g, const DevModel& 
     r = b / per;
 }
 
-template <int MODE>
+template <int MODE, bool RECT>
 __global__ void __launch_bounds__(kBlock, 6) branch_kernel(DevModel m, EvalOut o, SetGrid g) {
     __shared__ double stage[kRecStride * kBlock];
     int32_t kind, idx, r;
     decode_phase1(g, m, xcd_item(blockIdx.x, gridDim.x), kind, idx, r);
-    run_phase1<MODE>(m, o, kind, idx, r, stage);
+    run_phase1<MODE, RECT>(m, o, kind, idx, r, stage);
 }
 
 // The single launch of a small model's callback set: items ordered branch
@@ -1112,33 +1481,37 @@ __global__ void __launch_bounds__(kBlock, 6) branch_kernel(DevModel m, EvalOut o
 // item waits for another).  Blocks are dealt to the XCDs round-robin, which
 // spreads every kind of item over all of them: a small launch is bound by
 // latency, not by the lines that neighbouring items share.
+template <bool RECT>
 __global__ void __launch_bounds__(kBlock) set_kernel_single(DevModel m, EvalOut o, SetGrid g) {
     __shared__ double lds[kRecStride * kBlock];
     int32_t b = blockIdx.x;
     if (b < g.n_branch) {
-        branch_task<true>(m, o, b % m.nbchunks, b / m.nbchunks, lds);
+        if (RECT)
+            rbranch_task<true>(m, o, b % m.nbchunks, b / m.nbchunks, lds);
+        else
+            branch_task<true>(m, o, b % m.nbchunks, b / m.nbchunks, lds);
         return;
     }
     b -= g.n_branch;
     if (b < g.n_gen1) {
-        gen_task<true>(m, o, b % m.ngchunks, b / m.ngchunks);
+        gen_task<true, RECT>(m, o, b % m.ngchunks, b / m.ngchunks);
         return;
     }
     b -= g.n_gen1;
     if (b < g.n_big) {
-        big_task<true>(m, o, b % m.nbig, b / m.nbig);
+        big_task<true, RECT>(m, o, b % m.nbig, b / m.nbig);
         return;
     }
     b -= g.n_big;
-    wave_task<true>(m, o, b % m.nwaves, b / m.nwaves, lds);
+    wave_task<true, RECT>(m, o, b % m.nwaves, b / m.nwaves, lds);
 }
 
-template <int MODE>
+template <int MODE, bool RECT>
 __global__ void __launch_bounds__(kBlock, 6) bus_kernel(DevModel m, EvalOut o, SetGrid g) {
     __shared__ double lds[kRecStride * kBlock];
     int32_t kind, idx, r;
     decode_phase2(g, m, xcd_item(blockIdx.x, gridDim.x), kind, idx, r);
-    run_phase2<MODE>(m, o, kind, idx, r, lds);
+    run_phase2<MODE, RECT>(m, o, kind, idx, r, lds);
 }
 
 // Occupancy hints (second launch-bounds argument: waves per SIMD) are the
@@ -1188,7 +1561,7 @@ __device__ __forceinline__ void xcd_stride(int32_t n, int32_t& first, int32_t& s
     end = (int32_t)((int64_t)n * (x + 1) / kXcd);
 }
 
-template <int MODE>
+template <int MODE, bool RECT>
 __global__ void __launch_bounds__(kBlock) batch_branch_kernel(BatchArgs a) {
     __shared__ double stage[kRecStride * kBlock];
     int32_t it, step, end;
@@ -1196,11 +1569,11 @@ __global__ void __launch_bounds__(kBlock) batch_branch_kernel(BatchArgs a) {
     for (; it < end; it += step) {
         const BatchItem w = a.items[it];
         const BatchInst& bi = a.inst[w.inst];
-        run_phase1<MODE>(bi.m, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, stage);
+        run_phase1<MODE, RECT>(bi.m, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, stage);
     }
 }
 
-template <int MODE>
+template <int MODE, bool RECT>
 __global__ void __launch_bounds__(kBlock) batch_bus_kernel(BatchArgs a) {
     __shared__ double lds[kRecStride * kBlock];
     int32_t it, step, end;
@@ -1208,12 +1581,12 @@ __global__ void __launch_bounds__(kBlock) batch_bus_kernel(BatchArgs a) {
     for (; it < end; it += step) {
         const BatchItem w = a.items[it];
         const BatchInst& bi = a.inst[w.inst];
-        run_phase2<MODE>(bi.m, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, lds);
+        run_phase2<MODE, RECT>(bi.m, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, lds);
         __syncthreads();
     }
 }
 
-template <int MODE>
+template <int MODE, bool RECT>
 __global__ void __launch_bounds__(kBlock) batch_branch_flat(BatchArgs a) {
     __shared__ double stage[kRecStride * kBlock];
     const int32_t it = xcd_item(blockIdx.x, gridDim.x);
@@ -1224,10 +1597,10 @@ __global__ void __launch_bounds__(kBlock) batch_branch_flat(BatchArgs a) {
     // of one dependent scalar round trip per branch that first uses them
     // (64-scenario batch: 97.5 -> 95.4 us)
     const DevModel mloc = bi.m;
-    run_phase1<MODE>(mloc, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, stage);
+    run_phase1<MODE, RECT>(mloc, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, stage);
 }
 
-template <int MODE>
+template <int MODE, bool RECT>
 __global__ void __launch_bounds__(kBlock, 5) batch_bus_flat(BatchArgs a) {
     __shared__ double lds[kRecStride * kBlock];
     const int32_t it = xcd_item(blockIdx.x, gridDim.x);
@@ -1238,7 +1611,7 @@ __global__ void __launch_bounds__(kBlock, 5) batch_bus_flat(BatchArgs a) {
     // of one dependent scalar round trip per branch that first uses them
     // (64-scenario batch: 97.5 -> 95.4 us)
     const DevModel mloc = bi.m;
-    run_phase2<MODE>(mloc, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, lds);
+    run_phase2<MODE, RECT>(mloc, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, lds);
 }
 
 SetGrid plan_set(const DevModel& m, const EvalOut& o, int32_t mode) {
@@ -1256,17 +1629,34 @@ SetGrid plan_set(const DevModel& m, const EvalOut& o, int32_t mode) {
     return g;
 }
 
-hipError_t launch_eval_set(const DevModel& m, const EvalOut& o_in, hipStream_t stream) {
-    EvalOut o = o_in;
-    o.single = m.single;  // plain launches of small models take the single-launch shape
+template <bool RECT>
+hipError_t launch_set_form(const DevModel& m, const EvalOut& o, hipStream_t stream) {
     const SetGrid g = plan_set(m, o, 0);
     if (o.single) {
         const int32_t n = g.phase1() + g.phase2();
-        if (n > 0) hipLaunchKernelGGL(set_kernel_single, dim3(n), dim3(kBlock), 0, stream, m, o, g);
+        if (n > 0) hipLaunchKernelGGL(set_kernel_single<RECT>, dim3(n), dim3(kBlock), 0, stream, m, o, g);
         return hipGetLastError();
     }
-    if (g.phase1() > 0) hipLaunchKernelGGL(branch_kernel<0>, dim3(g.phase1()), dim3(kBlock), 0, stream, m, o, g);
-    if (g.phase2() > 0) hipLaunchKernelGGL(bus_kernel<0>, dim3(g.phase2()), dim3(kBlock), 0, stream, m, o, g);
+    if (g.phase1() > 0)
+        hipLaunchKernelGGL((branch_kernel<0, RECT>), dim3(g.phase1()), dim3(kBlock), 0, stream, m, o, g);
+    if (g.phase2() > 0)
+        hipLaunchKernelGGL((bus_kernel<0, RECT>), dim3(g.phase2()), dim3(kBlock), 0, stream, m, o, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_set(const DevModel& m, const EvalOut& o_in, hipStream_t stream) {
+    EvalOut o = o_in;
+    o.single = m.single;  // plain launches of small models take the single-launch shape
+    return m.rect ? launch_set_form<true>(m, o, stream) : launch_set_form<false>(m, o, stream);
+}
+
+template <bool RECT>
+hipError_t launch_jt_form(const DevModel& m, const EvalOut& o, hipStream_t stream) {
+    const SetGrid g = plan_set(m, o, 1);
+    if (g.phase1() > 0)
+        hipLaunchKernelGGL((branch_kernel<1, RECT>), dim3(g.phase1()), dim3(kBlock), 0, stream, m, o, g);
+    if (g.phase2() > 0)
+        hipLaunchKernelGGL((bus_kernel<1, RECT>), dim3(g.phase2()), dim3(kBlock), 0, stream, m, o, g);
     return hipGetLastError();
 }
 
@@ -1275,27 +1665,31 @@ hipError_t launch_jtprod(const DevModel& m, const double* x, const double* v, do
     o.x = x;
     o.y = v;
     o.g = out;
-    const SetGrid g = plan_set(m, o, 1);
-    if (g.phase1() > 0) hipLaunchKernelGGL(branch_kernel<1>, dim3(g.phase1()), dim3(kBlock), 0, stream, m, o, g);
-    if (g.phase2() > 0) hipLaunchKernelGGL(bus_kernel<1>, dim3(g.phase2()), dim3(kBlock), 0, stream, m, o, g);
-    return hipGetLastError();
+    return m.rect ? launch_jt_form<true>(m, o, stream) : launch_jt_form<false>(m, o, stream);
 }
 
-void* batch_kernel_fn(int phase, int mode, bool flat) {
+template <bool RECT>
+void* batch_kernel_form(int phase, int mode, bool flat) {
     if (flat) {
         if (phase == 0) {
-            if (mode == 0) return reinterpret_cast<void*>(&batch_branch_flat<0>);
-            if (mode == 1) return reinterpret_cast<void*>(&batch_branch_flat<1>);
-            return reinterpret_cast<void*>(&batch_branch_flat<2>);
+            if (mode == 0) return reinterpret_cast<void*>(&batch_branch_flat<0, RECT>);
+            if (mode == 1) return reinterpret_cast<void*>(&batch_branch_flat<1, RECT>);
+            return reinterpret_cast<void*>(&batch_branch_flat<2, RECT>);
         }
-        return mode == 0 ? reinterpret_cast<void*>(&batch_bus_flat<0>) : reinterpret_cast<void*>(&batch_bus_flat<1>);
+        return mode == 0 ? reinterpret_cast<void*>(&batch_bus_flat<0, RECT>)
+                         : reinterpret_cast<void*>(&batch_bus_flat<1, RECT>);
     }
     if (phase == 0) {
-        if (mode == 0) return reinterpret_cast<void*>(&batch_branch_kernel<0>);
-        if (mode == 1) return reinterpret_cast<void*>(&batch_branch_kernel<1>);
-        return reinterpret_cast<void*>(&batch_branch_kernel<2>);
+        if (mode == 0) return reinterpret_cast<void*>(&batch_branch_kernel<0, RECT>);
+        if (mode == 1) return reinterpret_cast<void*>(&batch_branch_kernel<1, RECT>);
+        return reinterpret_cast<void*>(&batch_branch_kernel<2, RECT>);
     }
-    return mode == 0 ? reinterpret_cast<void*>(&batch_bus_kernel<0>) : reinterpret_cast<void*>(&batch_bus_kernel<1>);
+    return mode == 0 ? reinterpret_cast<void*>(&batch_bus_kernel<0, RECT>)
+                     : reinterpret_cast<void*>(&batch_bus_kernel<1, RECT>);
+}
+
+void* batch_kernel_fn(int phase, int mode, bool flat, bool rect) {
+    return rect ? batch_kernel_form<true>(phase, mode, flat) : batch_kernel_form<false>(phase, mode, flat);
 }
 
 size_t scratch_bytes(const DevModel& m) {

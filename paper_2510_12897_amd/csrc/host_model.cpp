@@ -1,4 +1,6 @@
-// Host-side model construction (see host_model.h).
+// Host-side model construction (see host_model.h).  The rule below is the
+// polar form's; the rectangular form's (bus blocks vr, vi) follows it in
+// fill_pattern.
 //
 // Pattern rule (structural, 0-based, sorted by (row, col), unique):
 //  Jacobian, rows in constraint order:
@@ -37,6 +39,7 @@ int fail(std::string& err, int code, const char* fmt, long long a = 0, long long
 
 int32_t nperiods(const opf_opts* o) { return o ? o->n_periods : 1; }
 int32_t ncont(const opf_opts* o) { return o ? o->n_cont : 0; }
+int32_t form(const opf_opts* o) { return o ? o->form : OPF_FORM_POLAR; }
 
 }  // namespace
 
@@ -84,6 +87,8 @@ int validate(const opf_case* cs, const opf_opts* opts, std::string& err) {
     if (T < 1) return fail(err, OPF_E_CASE, "n_periods must be >= 1 (got %lld)", T);
     if (K < 0) return fail(err, OPF_E_CASE, "n_cont must be >= 0 (got %lld)", K);
     if (T > 1 && K > 0) return fail(err, OPF_E_CASE, "periods and contingency copies cannot be combined");
+    if (form(opts) != OPF_FORM_POLAR && form(opts) != OPF_FORM_RECT)
+        return fail(err, OPF_E_CASE, "form must be OPF_FORM_POLAR or OPF_FORM_RECT (got %lld)", form(opts));
     if (opts && T > 1 && (!(opts->ramp_ratio >= 0.0) || !std::isfinite(opts->ramp_ratio)))
         return fail(err, OPF_E_CASE, "ramp_ratio must be finite and >= 0");
     if (opts && (opts->pd_t == nullptr) != (opts->qd_t == nullptr))
@@ -99,8 +104,11 @@ int validate(const opf_case* cs, const opf_opts* opts, std::string& err) {
     const int64_t nrep = T > 1 ? T : (int64_t)K + 1;
     const int64_t npg = K > 0 ? 1 : nrep;
     const int64_t n = nrep * (2LL * N + G + 4LL * L) + npg * G;
-    const int64_t m = nrep * (cs->n_ref + 7LL * L + 2LL * N) + (T > 1 ? (int64_t)G * (T - 1) : 0);
-    const int64_t nnzj = nrep * (cs->n_ref + 30LL * L + 2LL * N + 2LL * G) + 2LL * G * (T - 1);
+    const bool rect = form(opts) == OPF_FORM_RECT;
+    const int64_t m = nrep * (cs->n_ref + (rect ? 8LL : 7LL) * L + (rect ? 3LL : 2LL) * N) +
+                      (T > 1 ? (int64_t)G * (T - 1) : 0);
+    const int64_t nnzj = nrep * (cs->n_ref + (rect ? 36LL : 30LL) * L + (rect ? 6LL : 2LL) * N + 2LL * G) +
+                         2LL * G * (T - 1);
     const int64_t lim = std::numeric_limits<int32_t>::max();
     if (n >= lim || m >= lim || nnzj >= lim) return fail(err, OPF_E_CASE, "model too large for int32 indices");
     return OPF_OK;
@@ -115,6 +123,7 @@ int build_host_model(const opf_case* cs, const opf_opts* opts, HostModel& hm, st
     ly.N = N; ly.L = L; ly.G = G; ly.R = R; ly.T = T; ly.K = K;
     ly.nrep = T > 1 ? T : K + 1;
     ly.npg = K > 0 ? 1 : ly.nrep;
+    ly.rect = form(opts) == OPF_FORM_RECT ? 1 : 0;
     const int64_t P = ly.nrep;
 
     // ---- branch terms of the pi model (series g + jb, charging b/2 a side,
@@ -140,6 +149,13 @@ int build_host_model(const opf_case* cs, const opf_opts* opts, HostModel& hm, st
         k[6 * (size_t)L + l] = (-g * tr - b * ti) / t2;    // Gtf
         k[7 * (size_t)L + l] = (-b * tr + g * ti) / t2;    // Btf
         hm.rate2[l] = cs->rate_a[l] * cs->rate_a[l];
+    }
+    if (ly.rect) {
+        hm.tan_lim.resize(2 * (size_t)L);
+        for (int32_t l = 0; l < L; l++) {
+            hm.tan_lim[l] = std::tan(cs->angmax[l]);
+            hm.tan_lim[(size_t)L + l] = std::tan(cs->angmin[l]);
+        }
     }
 
     // ---- half-edges per bus, sorted by (neighbour, branch)
@@ -210,9 +226,19 @@ int build_host_model(const opf_case* cs, const opf_opts* opts, HostModel& hm, st
     for (int32_t i = 0; i < N; i++) {
         const int32_t deg = hm.adj_ptr[i + 1] - hm.adj_ptr[i];
         const int32_t ng = hm.gen_ptr[i + 1] - hm.gen_ptr[i];
-        hm.jbal_off[i + 1] = hm.jbal_off[i] + 1 + ng + deg;
-        hm.hva_off[i + 1] = hm.hva_off[i] + (deg > 0 ? hm.nlo[i] + 1 : 0);
-        hm.hvm_off[i + 1] = hm.hvm_off[i] + (deg > 0 ? hm.ndist[i] + hm.nlo[i] + 2 : 1);
+        if (ly.rect) {
+            // balance rows lead with vr_i, vi_i; the vr row holds (vr_i, vr_k)
+            // for k < i and the diagonal, the vi row (vi_i, vr_k) for every
+            // neighbour, (vi_i, vi_k) for k < i and the diagonal (no
+            // (vi_i, vr_i) term exists)
+            hm.jbal_off[i + 1] = hm.jbal_off[i] + 2 + ng + deg;
+            hm.hva_off[i + 1] = hm.hva_off[i] + hm.nlo[i] + 1;
+            hm.hvm_off[i + 1] = hm.hvm_off[i] + hm.ndist[i] + hm.nlo[i] + 1;
+        } else {
+            hm.jbal_off[i + 1] = hm.jbal_off[i] + 1 + ng + deg;
+            hm.hva_off[i + 1] = hm.hva_off[i] + (deg > 0 ? hm.nlo[i] + 1 : 0);
+            hm.hvm_off[i + 1] = hm.hvm_off[i] + (deg > 0 ? hm.ndist[i] + hm.nlo[i] + 2 : 1);
+        }
     }
 
     // ---- bus, generator and replica data
@@ -253,11 +279,13 @@ int build_host_model(const opf_case* cs, const opf_opts* opts, HostModel& hm, st
     ly.x_p = ly.x_qg + (int64_t)G * P;
     ly.x_q = ly.x_p + 2LL * L * P;
     ly.n = ly.x_q + 2LL * L * P;
-    const int64_t rows[B_END] = {R * P, L * P, L * P, L * P, L * P, L * P, N * P, N * P, L * P, L * P,
-                                 T > 1 ? (int64_t)G * (T - 1) : 0};
-    ly.jbal_rep = (int64_t)N + G + 2LL * L;
-    const int64_t ents[B_END] = {R * P, 5LL * L * P, 5LL * L * P, 5LL * L * P, 5LL * L * P, 2LL * L * P,
-                                 ly.jbal_rep * P, ly.jbal_rep * P, 2LL * L * P, 2LL * L * P,
+    const int64_t rk = ly.rect;
+    const int64_t rows[B_END] = {R * P, L * P, L * P, L * P, L * P, L * P, rk * L * P, N * P, N * P, L * P, L * P,
+                                 rk * N * P, T > 1 ? (int64_t)G * (T - 1) : 0};
+    ly.jbal_rep = (1 + rk) * N + G + 2LL * L;
+    const int64_t angj = (2 + 2 * rk) * L * P;  // polar (va_f, va_t); rectangular (vr_f, vr_t, vi_f, vi_t)
+    const int64_t ents[B_END] = {R * P, 5LL * L * P, 5LL * L * P, 5LL * L * P, 5LL * L * P, angj, rk * angj,
+                                 ly.jbal_rep * P, ly.jbal_rep * P, 2LL * L * P, 2LL * L * P, rk * 2 * N * P,
                                  T > 1 ? 2LL * G * (T - 1) : 0};
     ly.c_blk[0] = ly.j_blk[0] = 0;
     for (int b = 0; b < B_END; b++) {
@@ -287,6 +315,7 @@ int build_host_model(const opf_case* cs, const opf_opts* opts, HostModel& hm, st
 
 void build_slots(HostModel& hm) {
     const int32_t N = hm.ly.N, L = hm.ly.L;
+    const bool rect = hm.ly.rect != 0;
     hm.slots.clear();
     hm.slots_c.clear();
     hm.big_bus.clear();
@@ -327,8 +356,14 @@ void build_slots(HostModel& hm) {
         const int32_t nlo = hm.nlo[i], nd = hm.ndist[i];
         const int32_t hva = hm.hva_off[i], hvm = hm.hvm_off[i], jrow = hm.jbal_off[i];
         const uint32_t head_lane = (uint32_t)lane;
-        push(SK_HEAD | (seg << 8), -1, i, -1, jrow, deg > 0 ? hva + nlo : -1, deg > 0 ? hvm + nlo : -1,
-             deg > 0 ? hvm + nd + 1 + nlo : hvm, ck(SK_HEAD | (deg == 0 ? 64u : 0u), seg - 1, head_lane, 0, 0), i);
+        const int32_t nbv = rect ? 2 : 1;  // leading bus entries of the balance rows
+        if (rect)  // (vr_i, vr_i), no (vi_i, vr_i), (vi_i, vi_i)
+            push(SK_HEAD | (seg << 8), -1, i, -1, jrow, hva + nlo, -1, hvm + nd + nlo,
+                 ck(SK_HEAD | (deg == 0 ? 64u : 0u), seg - 1, head_lane, 0, 0), i);
+        else
+            push(SK_HEAD | (seg << 8), -1, i, -1, jrow, deg > 0 ? hva + nlo : -1, deg > 0 ? hvm + nlo : -1,
+                 deg > 0 ? hvm + nd + 1 + nlo : hvm, ck(SK_HEAD | (deg == 0 ? 64u : 0u), seg - 1, head_lane, 0, 0),
+                 i);
         for (int32_t q = e0; q < e1; q++) {
             const int32_t code = hm.he[q], l = code >> 1, from = code & 1;
             const int32_t k = from ? hm.t_bus[l] : hm.f_bus[l];
@@ -343,12 +378,17 @@ void build_slots(HostModel& hm) {
                                  ((leader ? glen : 0) << 8);
             const uint32_t clow = SK_EDGE | (from << 2) | ((leader ? 1u : 0u) << 3) | ((k < i ? 1u : 0u) << 4) |
                                   ((k > i ? 1u : 0u) << 5);
-            push(kind, l, i, k, jrow + 1 + ng + arank, leader && k < i ? hva + grp : -1,
-                 leader ? hvm + grp + (k > i ? 1 : 0) : -1, leader && k < i ? hvm + nd + 1 + grp : -1,
-                 ck(clow, leader ? glen - 1 : 0, head_lane, 1 + ng + arank, grp), l);
+            if (rect)  // (vr_i, vr_k) for k < i, (vi_i, vr_k), (vi_i, vi_k) for k < i
+                push(kind, l, i, k, jrow + nbv + ng + arank, leader && k < i ? hva + grp : -1,
+                     leader ? hvm + grp : -1, leader && k < i ? hvm + nd + grp : -1,
+                     ck(clow, leader ? glen - 1 : 0, head_lane, 1 + ng + arank, grp), l);
+            else
+                push(kind, l, i, k, jrow + 1 + ng + arank, leader && k < i ? hva + grp : -1,
+                     leader ? hvm + grp + (k > i ? 1 : 0) : -1, leader && k < i ? hvm + nd + 1 + grp : -1,
+                     ck(clow, leader ? glen - 1 : 0, head_lane, 1 + ng + arank, grp), l);
         }
         for (int32_t q = 0; q < ng; q++)
-            push(SK_GEN, hm.gen_list[g0 + q], i, -1, jrow + 1 + q, -1, -1, -1, ck(SK_GEN, 0, head_lane, 1 + q, 0),
+            push(SK_GEN, hm.gen_list[g0 + q], i, -1, jrow + nbv + q, -1, -1, -1, ck(SK_GEN, 0, head_lane, 1 + q, 0),
                  hm.gen_list[g0 + q]);
     }
     pad_wave();
@@ -380,8 +420,10 @@ void fill_pattern(const HostModel& hm, int32_t* jr, int32_t* jc, int32_t* hr, in
             if (jc) jc[e] = col;
             e++;
         };
+        // the rectangular form reads va, vm as vr, vi (same block positions)
+        const bool rect = ly.rect != 0;
         for (int32_t r = 0; r < P; r++)
-            for (int32_t j = 0; j < R; j++, row++) put(va(hm.ref_bus[j], r));
+            for (int32_t j = 0; j < R; j++, row++) put(rect ? vm(hm.ref_bus[j], r) : va(hm.ref_bus[j], r));
         for (int b = B_PFR; b <= B_QTO; b++) {
             const bool fr = (b == B_PFR || b == B_QFR), isp = (b == B_PFR || b == B_PTO);
             for (int32_t r = 0; r < P; r++)
@@ -392,14 +434,21 @@ void fill_pattern(const HostModel& hm, int32_t* jr, int32_t* jc, int32_t* hr, in
                     put(isp ? pa(arc, r) : qa(arc, r));
                 }
         }
-        for (int32_t r = 0; r < P; r++)
-            for (int32_t l = 0; l < L; l++, row++) {
-                put(va(std::min(hm.f_bus[l], hm.t_bus[l]), r));
-                put(va(std::max(hm.f_bus[l], hm.t_bus[l]), r));
-            }
+        for (int blk = 0; blk < (rect ? 2 : 1); blk++)  // angle rows (rectangular: two blocks)
+            for (int32_t r = 0; r < P; r++)
+                for (int32_t l = 0; l < L; l++, row++) {
+                    const int32_t lo = std::min(hm.f_bus[l], hm.t_bus[l]), hi = std::max(hm.f_bus[l], hm.t_bus[l]);
+                    put(va(lo, r));
+                    put(va(hi, r));
+                    if (rect) {
+                        put(vm(lo, r));
+                        put(vm(hi, r));
+                    }
+                }
         for (int isp = 1; isp >= 0; isp--)
             for (int32_t r = 0; r < P; r++)
                 for (int32_t i = 0; i < N; i++, row++) {
+                    if (rect) put(va(i, r));
                     put(vm(i, r));
                     for (int32_t q = hm.gen_ptr[i]; q < hm.gen_ptr[i + 1]; q++)
                         put(isp ? pg(hm.gen_list[q], r) : qg(hm.gen_list[q], r));
@@ -412,6 +461,12 @@ void fill_pattern(const HostModel& hm, int32_t* jr, int32_t* jc, int32_t* hr, in
                     const int32_t arc = side == 0 ? l : L + l;
                     put(pa(arc, r));
                     put(qa(arc, r));
+                }
+        if (rect)  // voltage-magnitude rows
+            for (int32_t r = 0; r < P; r++)
+                for (int32_t i = 0; i < N; i++, row++) {
+                    put(va(i, r));
+                    put(vm(i, r));
                 }
         for (int32_t t = 1; t < ly.T; t++)
             for (int32_t k = 0; k < G; k++, row++) {
@@ -440,7 +495,26 @@ void fill_pattern(const HostModel& hm, int32_t* jr, int32_t* jc, int32_t* hr, in
             }
         };
         std::vector<int32_t> nb;
-        for (int32_t r = 0; r < P; r++)
+        if (ly.rect) {
+            // vr row i: (vr_i, vr_k) for k < i, diagonal; vi row i: (vi_i, vr_k)
+            // for every distinct neighbour, (vi_i, vi_k) for k < i, diagonal
+            for (int32_t r = 0; r < P; r++)
+                for (int32_t i = 0; i < N; i++) {
+                    distinct(i, nb);
+                    for (int32_t k : nb)
+                        if (k < i) put(va(i, r), va(k, r));
+                    put(va(i, r), va(i, r));
+                }
+            for (int32_t r = 0; r < P; r++)
+                for (int32_t i = 0; i < N; i++) {
+                    distinct(i, nb);
+                    for (int32_t k : nb) put(vm(i, r), va(k, r));
+                    for (int32_t k : nb)
+                        if (k < i) put(vm(i, r), vm(k, r));
+                    put(vm(i, r), vm(i, r));
+                }
+        }
+        for (int32_t r = 0; r < P && !ly.rect; r++)
             for (int32_t i = 0; i < N; i++) {
                 distinct(i, nb);
                 if (nb.empty()) continue;
@@ -448,7 +522,7 @@ void fill_pattern(const HostModel& hm, int32_t* jr, int32_t* jc, int32_t* hr, in
                     if (k < i) put(va(i, r), va(k, r));
                 put(va(i, r), va(i, r));
             }
-        for (int32_t r = 0; r < P; r++)
+        for (int32_t r = 0; r < P && !ly.rect; r++)
             for (int32_t i = 0; i < N; i++) {
                 distinct(i, nb);
                 if (!nb.empty()) {
@@ -485,6 +559,13 @@ void fill_bounds(const opf_case* cs, const opf_opts* opts, const HostModel& hm, 
         for (int32_t r = 0; r < P; r++) {
             for (int32_t i = 0; i < N; i++) {
                 const int64_t c = ly.x_vm + i + (int64_t)N * r;
+                if (ly.rect) {  // vr, vi in [-vmax, vmax]; start vr = 1, vi = 0
+                    const int64_t cr = ly.x_va + i + (int64_t)N * r;
+                    if (lvar) lvar[cr] = lvar[c] = -cs->vmax[i];
+                    if (uvar) uvar[cr] = uvar[c] = cs->vmax[i];
+                    if (x0) x0[cr] = 1.0;
+                    continue;
+                }
                 if (lvar) lvar[c] = cs->vmin[i];
                 if (uvar) uvar[c] = cs->vmax[i];
                 if (x0) x0[c] = 1.0;
@@ -518,11 +599,25 @@ void fill_bounds(const opf_case* cs, const opf_opts* opts, const HostModel& hm, 
             for (int32_t l = 0; l < L; l++) {
                 const int64_t row = ly.c_blk[B_ANG] + l + (int64_t)L * r;
                 const bool out = hm.outage[r] == l;
+                if (ly.rect) {  // SI - tan(angmax) CR <= 0, SI - tan(angmin) CR >= 0
+                    const int64_t rlo = ly.c_blk[B_ANGL] + l + (int64_t)L * r;
+                    if (lcon) lcon[row] = -inf;
+                    if (ucon) ucon[row] = out ? inf : 0.0;
+                    if (lcon) lcon[rlo] = out ? -inf : 0.0;
+                    if (ucon) ucon[rlo] = inf;
+                    continue;
+                }
                 if (lcon) lcon[row] = out ? -inf : cs->angmin[l];
                 if (ucon) ucon[row] = out ? inf : cs->angmax[l];
             }
-        for (int64_t row = ly.c_blk[B_THF]; row < ly.c_blk[B_RAMP]; row++)
+        for (int64_t row = ly.c_blk[B_THF]; row < ly.c_blk[B_VMAG]; row++)
             if (lcon) lcon[row] = -inf;
+        for (int32_t r = 0; r < P && ly.rect; r++)
+            for (int32_t i = 0; i < N; i++) {
+                const int64_t row = ly.c_blk[B_VMAG] + i + (int64_t)N * r;
+                if (lcon) lcon[row] = cs->vmin[i] * cs->vmin[i];
+                if (ucon) ucon[row] = cs->vmax[i] * cs->vmax[i];
+            }
         const double ratio = opts ? opts->ramp_ratio : 0.0;
         for (int32_t t = 1; t < ly.T; t++)
             for (int32_t k = 0; k < G; k++) {

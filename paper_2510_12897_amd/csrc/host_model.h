@@ -12,11 +12,16 @@
 namespace opf {
 
 // Constraint blocks in the order the paper's Listing 3 creates them, then
-// the multi-period ramp rows.
-enum Block { B_REF = 0, B_PFR, B_QFR, B_PTO, B_QTO, B_ANG, B_BALP, B_BALQ, B_THF, B_THT, B_RAMP, B_END };
+// the multi-period ramp rows.  B_ANGL (the second angle-difference row) and
+// B_VMAG (the voltage-magnitude row) are rows of the rectangular form only
+// (Sec. III-C1); they are empty in the polar form.
+enum Block {
+    B_REF = 0, B_PFR, B_QFR, B_PTO, B_QTO, B_ANG, B_ANGL, B_BALP, B_BALQ, B_THF, B_THT, B_VMAG, B_RAMP, B_END
+};
 
 struct Layout {
     int32_t N = 0, L = 0, G = 0, R = 0, T = 1, K = 0;
+    int32_t rect = 0;   // 0: polar (va, vm); 1: rectangular (vr, vi) in the same two bus blocks
     int32_t nrep = 1;   // replicas: periods or contingency copies (base + K)
     int32_t npg = 1;    // replicas of the pg block (1 when copies share pg)
     // variable blocks
@@ -26,9 +31,9 @@ struct Layout {
     // first Jacobian entry of each block (j_blk[B_END] = nnzj)
     int64_t j_blk[B_END + 1] = {};
     int64_t jbal_rep = 0;          // entries of one replica's balance block
-    // Hessian: va rows, vm rows, pg rows, p rows, q rows
+    // Hessian: va (vr) rows, vm (vi) rows, pg rows, p rows, q rows
     int64_t h_va = 0, h_vm = 0, h_pg = 0, h_p = 0, h_q = 0, nnzh = 0;
-    int64_t hva_rep = 0, hvm_rep = 0;  // entries of one replica's va / vm rows
+    int64_t hva_rep = 0, hvm_rep = 0;  // entries of one replica's va / vm (vr / vi) rows
 
     int64_t m() const { return c_blk[B_END]; }
     int64_t nnzj() const { return j_blk[B_END]; }
@@ -40,6 +45,8 @@ struct HostModel {
     // branch l at coef[k * L + l]: Gff Bff Gft Bft Gtt Btt Gtf Btf), rate_a^2
     std::vector<int32_t> f_bus, t_bus;
     std::vector<double> coef, rate2;
+    // rectangular form: tan(angmax) [L], then tan(angmin) [L]
+    std::vector<double> tan_lim;
     // bus adjacency: half-edges of bus i are he[adj_ptr[i] .. adj_ptr[i+1]),
     // sorted by (neighbour bus, branch); code = branch << 1 | (bus is f_bus)
     std::vector<int32_t> adj_ptr, he, he_grp;  // he_grp: distinct-neighbour rank
@@ -89,6 +96,10 @@ constexpr int32_t kWaveLanes = 64;
 //             half-edge of its neighbour group, which writes the group's
 //             off-diagonal entries (-1 if absent or not the group's first)
 //  generator: ref = generator, bus = i; jpos = its -1 entry
+// In the rectangular form va, vm read vr, vi: the head's h0/h2 are
+// (vr_i,vr_i), (vi_i,vi_i) and h1 is absent (-1); a group's h0/h1/h2 are
+// (vr_i,vr_k), (vi_i,vr_k), (vi_i,vi_k); the balance rows lead with two bus
+// entries (vr_i, vi_i), so every other lane's jpos is one further on.
 enum SlotKind { SK_IDLE = 0, SK_HEAD = 1, SK_EDGE = 2, SK_GEN = 3 };
 
 // Compact slot (two launches; 8 bytes per lane instead of 32): the index is
@@ -100,7 +111,9 @@ enum SlotKind { SK_IDLE = 0, SK_HEAD = 1, SK_EDGE = 2, SK_GEN = 3 };
 //   bits [8,14): segment length - 1 (head) or group length - 1 (leader);
 //   bits [14,20): lane of the segment's head in the wave;
 //   bits [20,26): offset of the lane's balance Jacobian entry from the
-//                 head's (0 head, 1 + q generator q, 1 + ng + arc rank);
+//                 head's (0 head, 1 + q generator q, 1 + ng + arc rank; the
+//                 rectangular form adds 1 to the non-head offsets in the
+//                 kernel, so that the field stays below 64);
 //   bits [26,32): neighbour group of a half-edge.
 // A head lane reads its bus's Hessian and Jacobian row offsets (hva_off,
 // hvm_off, nlo, ndist, jbal_off); the other lanes of the segment take them

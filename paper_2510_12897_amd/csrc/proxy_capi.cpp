@@ -16,6 +16,7 @@ int launched(hipError_t e, const char* what) { return e == hipSuccess ? OPF_OK :
 int static_model(opf_model m) {
     if (!valid_model(m)) return set_err(OPF_E_STATE, "invalid or destroyed model handle");
     if (m->hm.ly.nrep != 1) return set_err(OPF_E_ARG, "the proxy kernels take a static model");
+    if (m->hm.ly.rect) return set_err(OPF_E_ARG, "the proxy kernels take a polar model");
     return OPF_OK;
 }
 

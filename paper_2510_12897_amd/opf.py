@@ -7,7 +7,8 @@ of a Model fails with OPFError.
 
 Cases are dicts of numpy arrays with the field names of ``opf_case``
 (``synth.network`` produces them); options are the keyword arguments
-``n_periods``, ``pd_t``, ``qd_t``, ``ramp_ratio``, ``n_cont``, ``outaged``.
+``n_periods``, ``pd_t``, ``qd_t``, ``ramp_ratio``, ``n_cont``, ``outaged`` and
+``form`` ("polar", the default, or "rect" for bus variables (vr, vi)).
 """
 from __future__ import annotations
 
@@ -23,9 +24,12 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "opf.h")
 
 OPF_OK, OPF_E_ARG, OPF_E_CASE, OPF_E_NOMEM, OPF_E_HIP, OPF_E_STATE = 0, -1, -2, -3, -4, -5
 
-VAR_BLOCKS = {"va": 0, "vm": 1, "pg": 2, "qg": 3, "p": 4, "q": 5}
+# bus blocks: va, vm (polar) or vr, vi (rectangular form), same positions
+VAR_BLOCKS = {"va": 0, "vm": 1, "pg": 2, "qg": 3, "p": 4, "q": 5, "vr": 0, "vi": 1}
 CON_BLOCKS = {name: 16 + k for k, name in enumerate(
-    ["ref", "p_fr", "q_fr", "p_to", "q_to", "angle", "bal_p", "bal_q", "thermal_fr", "thermal_to", "ramp"])}
+    ["ref", "p_fr", "q_fr", "p_to", "q_to", "angle", "bal_p", "bal_q", "thermal_fr", "thermal_to", "ramp",
+     "angle_lo", "vmag"])}
+FORMS = {"polar": 0, "rect": 1}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -57,6 +61,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [
         ("n_periods", ctypes.c_int32), ("pd_t", _dp), ("qd_t", _dp),
         ("ramp_ratio", ctypes.c_double), ("n_cont", ctypes.c_int32), ("outaged_branch", _ip),
+        ("form", ctypes.c_int32),
     ]
 
 
@@ -150,7 +155,8 @@ def _check(rc: int):
 
 
 # ---------------------------------------------------------------- marshalling
-def _case_struct(case: dict, n_periods=1, pd_t=None, qd_t=None, ramp_ratio=0.0, n_cont=0, outaged=None):
+def _case_struct(case: dict, n_periods=1, pd_t=None, qd_t=None, ramp_ratio=0.0, n_cont=0, outaged=None,
+                 form="polar"):
     keep = []
 
     def d(a):
@@ -178,6 +184,9 @@ def _case_struct(case: dict, n_periods=1, pd_t=None, qd_t=None, ramp_ratio=0.0, 
     o.ramp_ratio = float(ramp_ratio)
     o.n_cont = int(n_cont)
     o.outaged_branch = i(outaged) if outaged is not None else _ip()
+    if form not in FORMS:
+        raise OPFError(OPF_E_ARG, f"unknown form {form!r} (polar or rect)")
+    o.form = FORMS[form]
     return c, o, keep
 
 

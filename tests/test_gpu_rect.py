@@ -1,0 +1,261 @@
+"""GPU parity of the rectangular form (form = :rect, Sec. III-C1) against
+the oracle: bus variables (vr, vi), polynomial flows, two tangent angle
+rows per branch and a voltage-magnitude row per bus.
+
+Same bar as the polar parity tests: patterns bit-exact; values within
+|v - v*| <= 1e-12 max(|v*|, S) + 1e-14 (S = the oracle's sum of |terms|);
+constant Jacobian entries bit-exact; both launch shapes; separate callbacks,
+the fused set and repeated runs bitwise equal; J^T v against the oracle's
+dense product; the batch bitwise equal to two-launch plain sets; the
+10,000-bus network at full size.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2510_12897_amd import opf, synth
+
+from helpers import assert_close, hub_network, record_strict, small_cases, strict_violations
+from test_host_pattern import with_parallel_and_isolated
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+RECT = dict(form="rect")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _cases():
+    for name, cs in small_cases():
+        yield name, cs, dict(RECT)
+    cs = synth.network(30, 44, 12, 3, variant=True)
+    pd_t, qd_t = synth.mp_loads(cs, 4, 1)
+    yield "mp4", cs, dict(n_periods=4, pd_t=pd_t, qd_t=qd_t, ramp_ratio=0.2, **RECT)
+    yield "sc3", cs, dict(n_cont=3, outaged=synth.outages(cs, 3, 2), **RECT)
+    yield "parallel_isolated", with_parallel_and_isolated(synth.network(12, 16, 4, 8, variant=True)), dict(RECT)
+    pc = with_parallel_and_isolated(synth.network(12, 16, 4, 9))
+    yield "parallel_sc", pc, dict(n_cont=2, outaged=np.array([0, pc["n_branch"] - 1], np.int32), **RECT)
+    hub = hub_network()
+    yield "hub", hub, dict(RECT)
+    pd_t, qd_t = synth.mp_loads(hub, 2, 5)
+    yield "hub_mp2", hub, dict(n_periods=2, pd_t=pd_t, qd_t=qd_t, ramp_ratio=0.2, **RECT)
+    yield "hub_sc2", hub, dict(n_cont=2, outaged=hub["extra_branches"][:2], **RECT)
+    yield "ragged700", synth.network(700, 951, 140, 12, variant=True), dict(RECT)
+
+
+CASES = list(_cases())
+SHAPES = {"single": 4096, "two": 0}
+
+
+@pytest.fixture(params=list(SHAPES))
+def shape(request):
+    opf.set_single_launch_limit(SHAPES[request.param])
+    yield request.param
+    opf.set_single_launch_limit(4096)
+
+
+def to_dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV)
+
+
+def point(cs, seed, opts):
+    return synth.point(cs, seed, n_periods=opts.get("n_periods", 1), n_cont=opts.get("n_cont", 0), form="rect")
+
+
+def check(res, out, tag):
+    f, g, c, jv, hv = (np.atleast_1d(t.cpu().numpy()) if torch.is_tensor(t) else np.atleast_1d(t) for t in out)
+    assert_close(f[:1], [res["f"]], [res["fscale"]], what=f"{tag} f")
+    assert_close(g, res["g"], np.abs(res["g"]), what=f"{tag} grad")
+    assert_close(c, res["c"], res["cscale"], what=f"{tag} c")
+    assert_close(jv, res["jval"], res["jscale"], what=f"{tag} J")
+    lin = np.isin(res["jval"], [-1.0, 1.0])
+    np.testing.assert_array_equal(jv[lin], res["jval"][lin])
+    assert_close(hv, res["hval"], res["hscale"], what=f"{tag} H")
+    n_strict = sum(strict_violations(a, b) for a, b in ((c, res["c"]), (jv, res["jval"]), (hv, res["hval"])))
+    record_strict(tag, n_strict, len(c) + len(jv) + len(hv))
+    say(f"[rect] {tag}: ok (strict-form violations: {n_strict})")
+
+
+def check_patterns(model, res, tag):
+    jr, jc = model.jac_structure()
+    hr, hc = model.hess_structure()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(jr.cpu().numpy(), res["jrow"], err_msg=f"{tag} J rows")
+    np.testing.assert_array_equal(jc.cpu().numpy(), res["jcol"], err_msg=f"{tag} J cols")
+    np.testing.assert_array_equal(hr.cpu().numpy(), res["hrow"], err_msg=f"{tag} H rows")
+    np.testing.assert_array_equal(hc.cpu().numpy(), res["hcol"], err_msg=f"{tag} H cols")
+
+
+@pytest.mark.parametrize("name,cs,opts", CASES, ids=[c[0] for c in CASES])
+def test_rect_callbacks_match_oracle(name, cs, opts, shape):
+    model = opf.Model(cs, **opts)
+    say(f"[rect] {name} ({shape}): n={model.n} m={model.m} nnzj={model.nnzj} nnzh={model.nnzh}")
+    for seed, sigma in ((100, 1.0), (101, 0.37), (102, 0.0)):
+        x = point(cs, seed, opts)
+        y = synth.multipliers(model.m, seed)
+        res = O.evaluate(cs, x, y, sigma, **opts)
+        if seed == 100:
+            check_patterns(model, res, name)
+        out = model.eval_set(to_dev(x), to_dev(y), sigma)
+        torch.cuda.synchronize()
+        check(res, out, f"rect {name}/seed{seed}/{shape}")
+    model.close()
+
+
+@pytest.mark.parametrize("name", ["c0v", "mp4", "sc3", "hub"])
+def test_rect_separate_callbacks_and_every_entry_written(name, shape):
+    """Outputs pre-filled with NaN: the fused set and the separate callbacks
+    write every entry and agree bitwise; a partial set computes only what
+    is asked for."""
+    _, cs, opts = [c for c in CASES if c[0] == name][0]
+    model = opf.Model(cs, **opts)
+    x = to_dev(point(cs, 7, opts))
+    y = to_dev(synth.multipliers(model.m, 7))
+
+    def nan(n):
+        return torch.full((n,), float("nan"), dtype=torch.float64, device=DEV)
+
+    fused = model.eval_set(x, y, 0.6, nan(1), nan(model.n), nan(model.m), nan(model.nnzj), nan(model.nnzh))
+    sep = (model.obj(x, nan(1)), model.grad(x, nan(model.n)), model.cons(x, nan(model.m)),
+           model.jac_coord(x, nan(model.nnzj)), model.hess_coord(x, y, 0.6, nan(model.nnzh)))
+    again = model.eval_set(x, y, 0.6)
+    c4 = torch.full((model.m,), 7.0, dtype=torch.float64, device=DEV)
+    model.eval_set(x, None, 1.0, c=c4, alloc=False)
+    torch.cuda.synchronize()
+    left = [int(torch.isnan(t).sum()) for t in fused]
+    assert left == [0] * 5, f"{name} ({shape}): NaN entries left in f, g, c, J, H: {left}"
+    for a, b, d in zip(fused, sep, again):
+        assert torch.equal(a.view(-1), b.view(-1)) and torch.equal(a.view(-1), d.view(-1))
+    assert torch.equal(c4, fused[2])
+    model.close()
+
+
+def test_rect_bounds_and_blocks_on_device():
+    cs = synth.network(30, 44, 12, 3, variant=True)
+    for opts in (dict(RECT), dict(n_periods=3, ramp_ratio=0.2, **RECT),
+                 dict(n_cont=2, outaged=synth.outages(cs, 2, 5), **RECT)):
+        say(f"[rect bounds] {sorted(opts)}")
+        model = opf.Model(cs, **opts)
+        b = model.bounds()
+        ref = O.bounds(cs, **opts)
+        torch.cuda.synchronize()
+        for k in ("lvar", "uvar", "lcon", "ucon", "x0"):
+            np.testing.assert_array_equal(b[k].cpu().numpy(), ref[k], err_msg=k)
+        P = opts.get("n_periods", 1) if opts.get("n_periods", 1) > 1 else opts.get("n_cont", 0) + 1
+        o, ln = model.block("vr")
+        assert (o, ln) == (0, 30 * P) and np.all(ref["x0"][o:o + ln] == 1.0)
+        assert model.block("angle_lo")[1] == 44 * P and model.block("vmag")[1] == 30 * P
+        assert model.block("bal_p")[0] == model.block("angle_lo")[0] + 44 * P
+        model.close()
+
+
+def test_rect_jtprod_matches_oracle():
+    for name, cs, opts in CASES:
+        say(f"[rect jtprod] {name}")
+        model = opf.Model(cs, **opts)
+        x = point(cs, 11, opts)
+        v = synth.multipliers(model.m, 11)
+        res = O.evaluate(cs, x, want=O.W_JAC, **opts)
+        ref = np.zeros(model.n)
+        np.add.at(ref, res["jcol"], res["jval"] * v[res["jrow"]])
+        scale = np.zeros(model.n)
+        np.add.at(scale, res["jcol"], (np.abs(res["jval"]) + res["jscale"]) * np.abs(v[res["jrow"]]))
+        out = model.jtprod(to_dev(x), to_dev(v))
+        torch.cuda.synchronize()
+        assert_close(out.cpu().numpy(), ref, scale, what=f"rect {name} J^T v")
+        model.close()
+
+
+def test_rect_batch_bitwise_equal_to_two_launch_plain():
+    """A batch of rectangular instances (uneven networks, own loads, both
+    schedules) equals the two-launch plain sets bitwise; mixing forms in
+    one batch is refused."""
+    opf.set_single_launch_limit(0)
+    try:
+        nets = [synth.network(n, int(round(1.35 * n)), int(round(0.2 * n)), 600 + n, variant=True)
+                for n in (40, 300, 1000)]
+        models = [opf.Model(cs, **RECT) for cs in nets]
+    finally:
+        opf.set_single_launch_limit(4096)
+    inst = [0, 1, 2, 1, 0, 2]
+    pds, qds = zip(*[synth.scenario_loads(nets[j], 700 + i) for i, j in enumerate(inst)])
+    batch = opf.Batch(models, inst, np.concatenate(pds), np.concatenate(qds))
+    xs = [point(nets[j], (105, i), {}) for i, j in enumerate(inst)]
+    ys = [synth.multipliers(models[j].m, (105, i)) for i, j in enumerate(inst)]
+    X, Y = to_dev(np.concatenate(xs)), to_dev(np.concatenate(ys))
+    S = torch.linspace(0.5, 1.5, len(inst), dtype=torch.float64, device=DEV)
+    for wg in (0, 4):
+        batch.set_schedule(wg)
+        say(f"[rect batch] schedule {wg}")
+        out = (torch.empty(len(inst), dtype=torch.float64, device=DEV),) + tuple(
+            torch.empty(k, dtype=torch.float64, device=DEV) for k in (batch.n, batch.m, batch.nnzj, batch.nnzh))
+        batch.eval(X, Y, S, *out)
+        for i, j in enumerate(inst):
+            c2 = dict(nets[j])
+            c2["pd"], c2["qd"] = pds[i], qds[i]
+            plain_model = None
+            opf.set_single_launch_limit(0)
+            try:
+                plain_model = opf.Model(c2, **RECT)
+            finally:
+                opf.set_single_launch_limit(4096)
+            ref = plain_model.eval_set(to_dev(xs[i]), to_dev(ys[i]), float(S[i]))
+            torch.cuda.synchronize()
+            sl = [(batch.xoff, 1), (batch.coff, 2), (batch.joff, 3), (batch.hoff, 4)]
+            assert torch.equal(out[0][i:i + 1], ref[0].view(1))
+            for off, k in sl:
+                assert torch.equal(out[k][int(off[i]):int(off[i + 1])], ref[k]), f"instance {i} output {k}"
+            plain_model.close()
+            if wg == 0 and i < 2:
+                res = O.evaluate(c2, xs[i], ys[i], float(S[i]), **RECT)
+                check(res, ref, f"rect batch instance {i}")
+    V = Y.clone()
+    out_b = batch.jtprod(X, V)
+    torch.cuda.synchronize()
+    for i, j in enumerate(inst[:3]):
+        ref = models[j].jtprod(to_dev(xs[i]), to_dev(ys[i]))
+        torch.cuda.synchronize()
+        assert torch.equal(out_b[int(batch.xoff[i]):int(batch.xoff[i + 1])], ref)
+    batch.close()
+    polar = opf.Model(nets[0])
+    with pytest.raises(opf.OPFError):
+        opf.Batch([models[0], polar], [0, 1])
+    polar.close()
+    for m in models:
+        m.close()
+
+
+def test_rect_proxy_kernels_refuse_rect_models():
+    cs = synth.network(14, 20, 5, 0)
+    model = opf.Model(cs, **RECT)
+    z = torch.zeros((1, 2 * 14 + 2 * 5), dtype=torch.float32, device=DEV)
+    X = torch.zeros((1, model.n), dtype=torch.float64, device=DEV)
+    rc = opf.lib().opf_batch_flows(None, None, None)
+    assert rc == opf.OPF_E_STATE
+    rc = opf.lib().prox_squash_fwd(model.handle, z.data_ptr(), 1, 0.3, X.data_ptr(), None)
+    assert rc == opf.OPF_E_ARG
+    model.close()
+
+
+def test_rect_10k_full_size_matches_oracle(shape):
+    """The 10,000-bus network in the rectangular form: every output of one
+    set at the benchmark's seeded inputs, in both launch shapes."""
+    cs = synth.network(10000, 13500, 2000, 1)
+    model = opf.Model(cs, **RECT)
+    say(f"[rect] 10k ({shape}): n={model.n} m={model.m} nnzj={model.nnzj} nnzh={model.nnzh}, "
+        f"{model.launch_shape()[0]} launches")
+    x = synth.point(cs, (101, 0), form="rect")
+    y = synth.multipliers(model.m, (101, 0))
+    out = model.eval_set(to_dev(x), to_dev(y), 1.0)
+    torch.cuda.synchronize()
+    res = O.evaluate(cs, x, y, 1.0, **RECT)
+    check_patterns(model, res, "rect 10k")
+    check(res, out, f"rect 10k/{shape}")
+    model.close()

@@ -58,7 +58,14 @@ def _cases():
     yield "hub_sc2", hub, dict(n_cont=2, outaged=hub["extra_branches"][:2])
 
 
+def _rect(cases):
+    """The rectangular form of every case."""
+    for name, cs, opts in cases:
+        yield name + "_rect", cs, dict(opts, form="rect")
+
+
 CASES = list(_cases())
+CASES += list(_rect(CASES))
 
 
 @pytest.mark.parametrize("name,cs,opts", CASES, ids=[c[0] for c in CASES])
@@ -66,7 +73,7 @@ def test_host_pattern_matches_oracle_bit_exact(name, cs, opts):
     n, m, nnzj, nnzh = opf.case_dims(cs, **opts)
     assert (n, m) == O.dims(cs, **opts)
     T, K = opts.get("n_periods", 1), opts.get("n_cont", 0)
-    x = synth.point(cs, 3, n_periods=T, n_cont=K)
+    x = synth.point(cs, 3, n_periods=T, n_cont=K, form=opts.get("form", "polar"))
     res = O.evaluate(cs, x, synth.multipliers(m, 3), 1.0, want=O.W_JAC | O.W_HESS, **opts)
     jr, jc, hr, hc = opf.case_structure(cs, **opts)
     assert jr.dtype == np.int32 and hr.dtype == np.int32
@@ -96,6 +103,23 @@ def test_closed_form_sizes_full_configs():
     cs = synth.network(1000, 1350, 200, 31)
     out = synth.outages(cs, 200, 32)
     assert opf.case_dims(cs, n_cont=200, outaged=out) == (1527800, 2301651, 8623101, 2774000)
+
+
+def test_closed_form_sizes_rect():
+    """Rectangular form (simple graph, every bus on a branch): n as polar,
+    m = R + 8L + 3N, nnzJ = R + 36L + 6N + 2G, nnzH = G + 2N + 8L."""
+    cs = synth.network(10000, 13500, 2000, 1)
+    assert opf.case_dims(cs, form="rect") == (78000, 1 + 8 * 13500 + 3 * 10000,
+                                              1 + 36 * 13500 + 6 * 10000 + 2 * 2000, 2000 + 2 * 10000 + 8 * 13500)
+    _err(cs, opf.OPF_E_ARG, form="cartesian")
+
+
+def test_form_out_of_range_rejected():
+    cs = synth.network(5, 6, 2, 1)
+    c, o, keep = opf._case_struct(cs)
+    o.form = 7
+    assert opf.lib().opf_case_validate(ctypes.byref(c), ctypes.byref(o)) == opf.OPF_E_CASE
+    assert b"form" in opf.lib().opf_last_error()
 
 
 def _err(cs, code, **opts):
