@@ -83,23 +83,31 @@ def measured_traffic():
         return None
 
 
-def algorithmic_bytes(cs: dict, dims, T: int = 1, K: int = 0, mp_loads: bool = False) -> int:
+def algorithmic_bytes(cs: dict, dims, T: int = 1, K: int = 0, mp_loads: bool = False, rect: bool = False) -> int:
     """Bytes one callback set must move at least: every input read once and
     every output written once.  Reads: x (8n), y (8m), sigma; branch data
-    (8 admittance terms + rate^2 + two int32 buses = 80 B); bus loads and
+    (8 admittance terms + rate^2 + two int32 buses = 80 B; the rectangular
+    form also reads the two angle-limit tangents, 16 B); bus loads and
     shunts (32 B, loads per period when they vary); generator costs and bus
     (28 B); adjacency (half-edges, bus pointers, generator lists); outage
     list.  Writes: f, grad f (8n), c (8m), J (8 nnzj), H (8 nnzh)."""
     n, m, nnzj, nnzh = dims
     N, L, G = cs["n_bus"], cs["n_branch"], cs["n_gen"]
     reads = 8 * n + 8 * m + 8
-    reads += 80 * L
+    reads += (96 if rect else 80) * L
     reads += 16 * N * (T if mp_loads else 1) + 16 * N
     reads += 28 * G
     reads += 4 * 2 * L + 4 * (N + 1) * 2 + 4 * G
     reads += 4 * K
     writes = 8 + 8 * n + 8 * m + 8 * nnzj + 8 * nnzh
     return int(reads + writes)
+
+
+def _nproc() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
 
 
 def _cpu_model_name() -> str:
@@ -210,9 +218,66 @@ def bench_cpu_baseline(h, synth, oracle, budget_s: float, log):
         if (el >= budget_s and done >= 3) or done >= 1000:
             break
     log(f"oracle: {done} sets in {el:.1f} s")
-    return dict(value=done / el, unit="sets/s", cores=1, kind="oracle",
+    return dict(value=done / el, unit="sets/s", cores=1, kind="oracle", threads=1, nproc=_nproc(),
+                cpu_model=_cpu_model_name(),
                 sample=f"{done} callback sets of the 10k-bus workload (x, y seeds (101, 0..3)), "
                        f"single-threaded C oracle, {el:.1f} s on {_cpu_model_name()}")
+
+
+def bench_cpu_batch64(synth, oracle, log):
+    """The oracle over the 64-scenario mix: every scenario once on one
+    thread, then once with one scenario per thread on every host core (the
+    oracle is a C library called through ctypes, which releases the
+    interpreter lock, so the threads run in parallel)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    cases = []
+    for j, N in enumerate(synth.BATCH_SIZES):
+        cs = synth.network(N, int(round(1.35 * N)), int(round(0.2 * N)), 300 + j)
+        n, m = oracle.dims(cs)
+        for s in range(8):
+            pd, qd = synth.scenario_loads(cs, 3000 + 8 * j + s)
+            c2 = dict(cs)
+            c2["pd"], c2["qd"] = pd, qd
+            i = len(cases)
+            cases.append((c2, synth.point(cs, (103, i)), synth.multipliers(m, (103, i))))
+
+    def one(k):
+        c2, x, y = cases[k]
+        oracle.evaluate(c2, x, y, 1.0)
+
+    t0 = time.perf_counter()
+    for k in range(len(cases)):
+        one(k)
+    t1 = time.perf_counter() - t0
+    threads = _nproc()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, range(len(cases))))
+    tn = time.perf_counter() - t0
+    log(f"oracle on the 64-scenario mix: {t1:.1f} s on 1 thread, {tn:.1f} s on {threads} threads")
+    return dict(kind="oracle", unit="sets/s", sets=len(cases), one_thread_sets_per_s=len(cases) / t1,
+                all_cores_sets_per_s=len(cases) / tn, threads=threads, nproc=_nproc(), cpu_model=_cpu_model_name(),
+                sample="every scenario of the 64-scenario mix once, one thread, then one scenario per thread")
+
+
+def measure_copy_gbs(torch, mib: int = 1024, reps: int = 5) -> float:
+    """Device-to-device copy rate (bytes read + written per second) of a
+    plain copy of `mib` MiB: the HBM rate a streaming kernel reaches here."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2.0 * n * 8 / secs / 1e9
 
 
 def bench_batch(args, torch, opf, synth, log):
@@ -234,42 +299,52 @@ def bench_batch(args, torch, opf, synth, log):
             plain_models.append(opf.Model(c2, device=0))
     batch = opf.Batch(models, inst_model, np.concatenate(pds), np.concatenate(qds))
     n_inst = batch.n_inst
-    X = torch.empty(batch.n, dtype=torch.float64, device=dev)
-    Y = torch.empty(batch.m, dtype=torch.float64, device=dev)
-    for i in range(n_inst):
-        cs = nets[inst_model[i]]
-        X[batch.xoff[i]:batch.xoff[i + 1]] = torch.as_tensor(synth.point(cs, (103, i)), device=dev)
-        Y[batch.coff[i]:batch.coff[i + 1]] = torch.as_tensor(
-            synth.multipliers(int(batch.coff[i + 1] - batch.coff[i]), (103, i)), device=dev)
+    # n_xy input sets (63 MB each) and n_o output sets (250 MB each), rotated
+    # per evaluation: about 1 GB, past the 256 MB Infinity Cache
+    n_xy, n_o = 4, 3
+    XS = [torch.empty(batch.n, dtype=torch.float64, device=dev) for _ in range(n_xy)]
+    YS = [torch.empty(batch.m, dtype=torch.float64, device=dev) for _ in range(n_xy)]
+    for q in range(n_xy):
+        for i in range(n_inst):
+            cs = nets[inst_model[i]]
+            XS[q][batch.xoff[i]:batch.xoff[i + 1]] = torch.as_tensor(synth.point(cs, (103 + 1000 * q, i)), device=dev)
+            YS[q][batch.coff[i]:batch.coff[i + 1]] = torch.as_tensor(
+                synth.multipliers(int(batch.coff[i + 1] - batch.coff[i]), (103 + 1000 * q, i)), device=dev)
     sig = torch.ones(n_inst, dtype=torch.float64, device=dev)
-    F = torch.empty(n_inst, dtype=torch.float64, device=dev)
-    G = torch.empty(batch.n, dtype=torch.float64, device=dev)
-    C = torch.empty(batch.m, dtype=torch.float64, device=dev)
-    J = torch.empty(batch.nnzj, dtype=torch.float64, device=dev)
-    H = torch.empty(batch.nnzh, dtype=torch.float64, device=dev)
+    OUTS = [(torch.empty(n_inst, dtype=torch.float64, device=dev),
+             torch.empty(batch.n, dtype=torch.float64, device=dev),
+             torch.empty(batch.m, dtype=torch.float64, device=dev),
+             torch.empty(batch.nnzj, dtype=torch.float64, device=dev),
+             torch.empty(batch.nnzh, dtype=torch.float64, device=dev)) for _ in range(n_o)]
+    X, Y = XS[0], YS[0]
+    F, G, C, J, H = OUTS[0]
     sched = batch.tune()
     log(f"batch: {n_inst} instances, n={batch.n} m={batch.m} nnzj={batch.nnzj} nnzh={batch.nnzh}, "
         f"tuned schedule wg_per_cu={sched} (0 = one workgroup per item)")
 
-    def batched():
-        batch.eval(X, Y, sig, F, G, C, J, H)
+    def batched(k=0):
+        batch.eval(XS[k % n_xy], YS[k % n_xy], sig, *OUTS[k % n_o])
 
     reps = args.batch_reps
     # eager: one evaluation call after another (two kernel launches each)
-    secs_e, _ = time_steps(torch, lambda: [batched() for _ in range(reps)], 3, 1)
+    secs_e, _ = time_steps(torch, lambda: [batched(k) for k in range(reps)], 3, 1)
     per_eager = secs_e / (3 * reps)
 
     # plain: the same 64 instances through the single-instance API, back to
-    # back on one stream, captured in one HIP graph
-    views = []
-    for i in range(n_inst):
-        sl = lambda off, a: a[int(off[i]):int(off[i + 1])]  # noqa: E731
-        views.append((sl(batch.xoff, X), sl(batch.coff, Y), F[i:i + 1], sl(batch.xoff, G), sl(batch.coff, C),
-                      sl(batch.joff, J), sl(batch.hoff, H)))
-
-    def plain():
+    # back on one stream, captured in one HIP graph, rotating the same sets
+    def views_of(k):
+        Xk, Yk, (Fk, Gk, Ck, Jk, Hk) = XS[k % n_xy], YS[k % n_xy], OUTS[k % n_o]
+        v = []
         for i in range(n_inst):
-            x, y, f, g, c, jv, hv = views[i]
+            sl = lambda off, a: a[int(off[i]):int(off[i + 1])]  # noqa: E731
+            v.append((sl(batch.xoff, Xk), sl(batch.coff, Yk), Fk[i:i + 1], sl(batch.xoff, Gk), sl(batch.coff, Ck),
+                      sl(batch.joff, Jk), sl(batch.hoff, Hk)))
+        return v
+
+    views_k = [views_of(k) for k in range(n_xy * n_o)]
+
+    def plain(k=0):
+        for i, (x, y, f, g, c, jv, hv) in enumerate(views_k[k % len(views_k)]):
             plain_models[i].eval_set(x, y, 1.0, f, g, c, jv, hv)
 
     s = torch.cuda.Stream()
@@ -288,12 +363,12 @@ def bench_batch(args, torch, opf, synth, log):
     # the mix (batched: two launches per pass; plain: 64), replayed
     graph_b = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph_b, stream=s):
-        for _ in range(reps):
-            batched()
+        for k in range(reps):
+            batched(k)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph, stream=s):
-        for _ in range(reps):
-            plain()
+        for k in range(reps):
+            plain(k)
     torch.cuda.synchronize()
     secs_b, _ = time_steps(torch, graph_b.replay, 3, 1)
     per_launch = secs_b / (3 * reps)
@@ -313,7 +388,8 @@ def bench_batch(args, torch, opf, synth, log):
         workload="64 scenarios = 8 networks (500..20000 buses, L=1.35N, G=0.2N) x 8 load seeds",
         batched_sets_per_s=n_inst / per_launch, plain_sets_per_s=n_inst / per_plain,
         speedup=per_plain / per_launch, us_per_launch=per_launch * 1e6, bytes_per_launch=total_bytes,
-        timing=f"both forms captured in a HIP graph of {reps} passes over the mix and replayed",
+        timing=f"both forms captured in a HIP graph of {reps} passes over the mix and replayed, rotating "
+               f"{n_xy} input and {n_o} output sets (about 1 GB, past the Infinity Cache)",
         us_per_eval_eager=per_eager * 1e6, speedup_eager=per_plain / per_eager,
         achieved_gbs=total_bytes / per_launch / 1e9, frac=total_bytes / per_launch / 1e9 / HBM_PEAK_GBS,
         schedule=dict(wg_per_cu=sched), bitwise_equal_to_plain=bool(bitwise), max_rel_diff_to_plain=max_rel)
@@ -331,11 +407,13 @@ def bench_points(torch, opf, synth, log, B=16):
     cs = synth.network(10000, 13500, 2000, 1)
     model = opf.Model(cs, device=0)
     b = opf.Batch([model], np.zeros(B, np.int32))
-    X = torch.empty(b.n, dtype=torch.float64, device=dev)
-    Y = torch.empty(b.m, dtype=torch.float64, device=dev)
-    for i in range(B):
-        X[b.xoff[i]:b.xoff[i + 1]] = torch.as_tensor(synth.point(cs, (101, i)), device=dev)
-        Y[b.coff[i]:b.coff[i + 1]] = torch.as_tensor(synth.multipliers(model.m, (101, i)), device=dev)
+    n_xy = 8  # input sets of 24 MB rotated with the 8 output sets (114 MB each)
+    XS = [torch.empty(b.n, dtype=torch.float64, device=dev) for _ in range(n_xy)]
+    YS = [torch.empty(b.m, dtype=torch.float64, device=dev) for _ in range(n_xy)]
+    for q in range(n_xy):
+        for i in range(B):
+            XS[q][b.xoff[i]:b.xoff[i + 1]] = torch.as_tensor(synth.point(cs, (101, i + B * q)), device=dev)
+            YS[q][b.coff[i]:b.coff[i + 1]] = torch.as_tensor(synth.multipliers(model.m, (101, i + B * q)), device=dev)
     S = torch.ones(B, dtype=torch.float64, device=dev)
     outs = [(torch.empty(B, dtype=torch.float64, device=dev), torch.empty(b.n, dtype=torch.float64, device=dev),
              torch.empty(b.m, dtype=torch.float64, device=dev), torch.empty(b.nnzj, dtype=torch.float64, device=dev),
@@ -345,6 +423,7 @@ def bench_points(torch, opf, synth, log, B=16):
 
     def run():
         o = outs[k[0] % len(outs)]
+        X, Y = XS[k[0] % n_xy], YS[k[0] % n_xy]
         k[0] += 1
         b.eval(X, Y, S, *o)
 
@@ -372,21 +451,31 @@ def bench_points(torch, opf, synth, log, B=16):
                 achieved_gbs=total / per / 1e9, frac=total / per / 1e9 / HBM_PEAK_GBS, schedule=dict(wg_per_cu=sched))
 
 
-def bench_model(torch, opf, synth, cs, opts, n_in, n_out, sets, log, label, T=1, K=0, mp_loads=False):
+def bench_model(torch, opf, synth, cs, opts, n_in, n_out, sets, log, label, T=1, K=0, mp_loads=False, seed=104,
+                steps=3):
+    """Plain sets of one model from a HIP graph, n_in input pairs and n_out
+    output sets rotated (sized past the 256 MB Infinity Cache)."""
     dev = torch.device("cuda", 0)
     model = opf.Model(cs, device=0, **opts)
+    rect = opts.get("form") == "rect"
     dims = (model.n, model.m, model.nnzj, model.nnzh)
-    xs = [torch.as_tensor(synth.point(cs, (104, r), n_periods=T, n_cont=K), device=dev) for r in range(n_in)]
-    ys = [torch.as_tensor(synth.multipliers(model.m, (104, r)), device=dev) for r in range(n_in)]
+    form = "rect" if rect else "polar"
+    xs = [torch.as_tensor(synth.point(cs, (seed, r), n_periods=T, n_cont=K, form=form), device=dev)
+          for r in range(n_in)]
+    ys = [torch.as_tensor(synth.multipliers(model.m, (seed, r)), device=dev) for r in range(n_in)]
     runner = PlainRunner(model, xs, ys, n_out=n_out, sets=sets, torch=torch)
     runner.capture()
-    secs, _ = time_steps(torch, runner.step, 3, 1)
-    per = secs / (3 * sets)
-    b = algorithmic_bytes(cs, dims, T=T, K=K, mp_loads=mp_loads)
-    log(f"{label}: {per * 1e6:.1f} us/set, {b / per / 1e9:.0f} GB/s")
+    secs, _ = time_steps(torch, runner.step, steps, 1)
+    per = secs / (steps * sets)
+    b = algorithmic_bytes(cs, dims, T=T, K=K, mp_loads=mp_loads, rect=rect)
+    ws = n_in * 8 * (dims[0] + dims[1]) + n_out * 8 * (1 + sum(dims))
+    log(f"{label}: {per * 1e6:.2f} us/set, {b / per / 1e9:.0f} GB/s (working set {ws / 2**20:.0f} MiB)")
+    launches, items = model.launch_shape()
     model.close()
     return dict(n=dims[0], m=dims[1], nnzj=dims[2], nnzh=dims[3], sets_per_s=1.0 / per, us_per_set=per * 1e6,
-                bytes_per_set=b, achieved_gbs=b / per / 1e9, frac=b / per / 1e9 / HBM_PEAK_GBS)
+                bytes_per_set=b, achieved_gbs=b / per / 1e9, frac=b / per / 1e9 / HBM_PEAK_GBS,
+                launches_per_set=launches, work_items=items, inputs_rotated=n_in, outputs_rotated=n_out,
+                working_set_mib=ws / 2**20)
 
 
 def bench_proxy(args, torch, synth, log):
@@ -417,8 +506,10 @@ def bench_proxy(args, torch, synth, log):
     gen.manual_seed(4242)
     loads, feats = px.sample(gen)
     _, cvp = px.predict(loads, feats)
-    _, cvf = px.baseline(loads)
-    cvp, cvf = cvp.cpu().numpy(), cvf.cpu().numpy()
+    _, cv0 = px.baseline(loads)
+    _, cvf = px.flat_start(loads)
+    cvp, cv0, cvf = cvp.cpu().numpy(), cv0.cpu().numpy(), cvf.cpu().numpy()
+    curve = P.fallback_curve(cvp)
     # inference: MLP + squashing + flows + FP64 constraint evaluation + violation
     secs, _ = time_steps(torch, lambda: px.predict(loads, feats), 10, 2)
     infer_s = secs / 10
@@ -428,14 +519,19 @@ def bench_proxy(args, torch, synth, log):
     flops = 2.0 * B * sum(a * b for a, b in zip(px.mlp.dims[:-1], px.mlp.dims[1:]))
     mlp_tflops = flops / (secs_m / 10) / 1e12
     log(f"proxy: loss {first:.4g} -> {last:.4g} in {steps} steps ({train_s * 1e3:.2f} ms/step); held-out "
-        f"max violation mean {cvp.mean():.4g} vs flat start {cvf.mean():.4g}; {B / infer_s:.0f} inferences/s; "
-        f"MLP forward {mlp_tflops:.1f} TFLOP/s")
+        f"Cvio mean {cvp.mean():.4g} vs x0 {cv0.mean():.4g} and flat start {cvf.mean():.4g}; fallback rate at "
+        f"tau 0.05: {curve[0.05]:.3f}; {B / infer_s:.0f} inferences/s; MLP forward {mlp_tflops:.1f} TFLOP/s")
     out = dict(workload="300 buses, 410 branches, 60 generators; MLP 600-1024x3-720 GELU, BF16 MFMA; "
                         "batches of 4096 loads (+-30 % uniform)",
                train_steps=steps, ms_per_train_step=train_s * 1e3, loss_first=first, loss_last=last,
                inferences_per_s=B / infer_s, mlp_forward_tflops=mlp_tflops, mlp_peak_tflops=2500.0,
                heldout_cvio_mean=float(cvp.mean()), heldout_cvio_max=float(cvp.max()),
-               flatstart_cvio_mean=float(cvf.mean()), fallback_rate=float(np.mean(cvp > cvf)))
+               x0_cvio_mean=float(cv0.mean()), flatstart_cvio_mean=float(cvf.mean()),
+               fallback_tau=0.05, fallback_rate=curve[0.05],
+               fallback_curve={str(k): v for k, v in curve.items()},
+               fallback_definition="share of held-out samples whose Cvio (largest violation over every row and "
+                                   "bound, p.u.) exceeds tau",
+               beats_flatstart_rate=float(np.mean(cvp < cvf)), beats_x0_rate=float(np.mean(cvp < cv0)))
     px.close()
     return out
 
@@ -491,6 +587,8 @@ def main():
     h = bench_headline(args, torch, opf, synth, log)
     sets_per_s = h["n_sets"] / h["secs"]
     achieved = h["bytes_set"] / h["per_set"] / 1e9
+    copy_gbs = measure_copy_gbs(torch)
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
     result = {
         "metric": METRIC,
         "value": sets_per_s,
@@ -523,6 +621,8 @@ def main():
             "traffic_unit": "HBM bytes per callback set (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "bytes_per_launch": h["bytes_set"],
             "us_per_launch": h["per_set"] * 1e6,
+            "copy_gbs": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs,
         },
     }
     if not args.no_extra:
@@ -535,7 +635,7 @@ def main():
             cs = synth.network(2000, 2700, 400, 2)
             pd_t, qd_t = synth.mp_loads(cs, 48, 202)
             extra["multiperiod_2k_x48"] = bench_model(
-                torch, opf, synth, cs, dict(n_periods=48, pd_t=pd_t, qd_t=qd_t, ramp_ratio=0.2), 8, 4, 20,
+                torch, opf, synth, cs, dict(n_periods=48, pd_t=pd_t, qd_t=qd_t, ramp_ratio=0.2), 24, 8, 24,
                 log, "multi-period", T=48, mp_loads=True)
         except Exception as e:
             extra["multiperiod_2k_x48"] = {"error": repr(e)}
@@ -543,9 +643,17 @@ def main():
             cs = synth.network(1000, 1350, 200, 31)
             out = synth.outages(cs, 200, 32)
             extra["contingency_1k_x201"] = bench_model(
-                torch, opf, synth, cs, dict(n_cont=200, outaged=out), 4, 2, 10, log, "N-1 copies", K=200)
+                torch, opf, synth, cs, dict(n_cont=200, outaged=out), 16, 6, 24, log, "N-1 copies", K=200)
         except Exception as e:
             extra["contingency_1k_x201"] = {"error": repr(e)}
+        try:
+            cs = synth.network(10000, 13500, 2000, 1)
+            extra["rect_10k"] = bench_model(torch, opf, synth, cs, dict(form="rect"), 256, 64, 500, log,
+                                            "rectangular 10k", seed=101)
+            extra["rect_10k"]["workload"] = ("plain rectangular-form callback sets, 10000-bus network, "
+                                             "HIP graph of back-to-back launches")
+        except Exception as e:
+            extra["rect_10k"] = {"error": repr(e)}
         try:
             extra["points16_10k"] = bench_points(torch, opf, synth, log, B=16)
         except Exception as e:
@@ -560,6 +668,11 @@ def main():
         from oracle import oracle
 
         result["cpu_baseline"] = bench_cpu_baseline(h, synth, oracle, args.cpu_seconds, log)
+        if not args.no_extra:
+            try:
+                result.setdefault("extra", {})["cpu_oracle_batch64"] = bench_cpu_batch64(synth, oracle, log)
+            except Exception as e:
+                result.setdefault("extra", {})["cpu_oracle_batch64"] = {"error": repr(e)}
     h["model"].close()
     print(json.dumps(result), flush=True)
 

@@ -1321,6 +1321,11 @@ __device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int
                 }
                 __syncthreads();
                 if (last) {
+                    // acquire at agent scope, once per launch (the last chunk
+                    // only): the partials below are read after every other
+                    // chunk's ticket increment, which each issued only once
+                    // its own partial store had completed
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     double acc = 0.0;
                     for (int32_t q = threadIdx.x; q < total; q += kBlock)
                         acc += __hip_atomic_load(&m.obj_part[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -271,6 +271,18 @@ def _fun(name):
     return _FUN[name]
 
 
+# thresholds (p.u.) of the fallback curve: a prediction whose Cvio exceeds
+# tau is discarded and the solver starts without it
+FALLBACK_TAUS = (0.01, 0.02, 0.05, 0.1, 0.2, 0.5)
+
+
+def fallback_curve(cvio, taus=FALLBACK_TAUS) -> dict:
+    """{tau: share of samples whose Cvio (the largest violation over every
+    row and bound, Sec. IV-A5) exceeds tau}."""
+    cvio = np.asarray(cvio, dtype=np.float64)
+    return {float(t): float(np.mean(cvio > t)) for t in taus}
+
+
 class Penalty:
     """The FP64 penalty of B instances of one static model with per-instance
     loads: loss_b = rho * (squared violations of the non-flow rows and of the
@@ -360,10 +372,25 @@ class WarmStartProxy:
 
     def baseline(self, loads):
         """The plain starting point x0 scored on the same loads: (x, cvio)."""
+        return self._score(loads, self.x0)
+
+    def flat_start(self, loads):
+        """The flat start scored on the same loads: vm = 1, va = 0, pg and qg
+        at the middle of their bounds, p and q the branch flows: (x, cvio)."""
+        torch = _torch()
+        b = self.pen.model.bounds()
+        x = self.x0.clone()
+        for blk in ("pg", "qg"):
+            o, n = self.pen.model.block(blk)
+            x[o:o + n] = 0.5 * (b["lvar"][o:o + n] + b["uvar"][o:o + n])
+        torch.cuda.synchronize()
+        return self._score(loads, x)
+
+    def _score(self, loads, x):
         torch = _torch()
         with torch.no_grad():
             self.pen.set_loads(loads[:, :self.N], loads[:, self.N:])
-            X = self.x0[None, :].expand(self.B, -1).contiguous()
+            X = x[None, :].expand(self.B, -1).contiguous()
             self.pen(X)
         return self.pen.last["x"], self.pen.last["cvio"]
 

@@ -388,30 +388,40 @@ def test_mlp_forward_backward_vs_oracle(dev, P):
 
 
 def test_trained_proxy_gains_over_flat_start(dev, P):
-    """Self-supervised training on the FP64 penalty; on held-out loads the
-    trained proxy's largest violation must beat the plain starting point x0
-    (the method without the proxy) by a wide margin."""
-    case = synth.network(30, 41, 6, 11)
+    """Self-supervised training of the benchmarked proxy (300 buses, 410
+    branches, 60 generators; MLP 600 -> 3 x 1024 -> 720; batches of 4,096)
+    on the FP64 penalty.  On held-out loads its largest violation (Cvio,
+    Sec. IV-A5) must beat both the model's starting point x0 and the flat
+    start (vm = 1, va = 0, pg, qg at mid-bounds, p, q = flows) by a wide
+    margin.  The fallback rate is the share of samples whose Cvio exceeds
+    tau = 0.05 p.u. (a solver would discard those predictions)."""
+    case = synth.network(300, 410, 60, 41)
     torch.manual_seed(0)
-    px = P.WarmStartProxy(case, B=256, width=128, depth=3, rho=10.0, obj_scale=1e-3, seed=1)
+    px = P.WarmStartProxy(case, B=4096, width=1024, depth=3, rho=10.0, obj_scale=1e-3, seed=1)
     gen = torch.Generator(device=dev)
-    gen.manual_seed(5)
+    gen.manual_seed(7)
     first = None
-    for step in range(600):
+    for step in range(1500):
         loads, feats = px.sample(gen)
-        loss = px.train_step(loads, feats, lr=1e-3)
+        loss = px.train_step(loads, feats, lr=3e-4)
         if first is None:
             first = float(loss)
     last = float(loss)
-    gen.manual_seed(999)  # held-out loads
+    gen.manual_seed(4242)  # held-out loads
     loads, feats = px.sample(gen)
     _, cv_proxy = px.predict(loads, feats)
-    _, cv_flat = px.baseline(loads)
-    cp, cf = cv_proxy.cpu().numpy(), cv_flat.cpu().numpy()
-    fallback = float(np.mean(cp > cf))
-    print(f"loss {first:.4g} -> {last:.4g}; held-out max violation: proxy mean {cp.mean():.4g} "
-          f"max {cp.max():.4g}, flat start mean {cf.mean():.4g}; fallback rate {fallback:.3f}")
-    assert last < 0.5 * first
-    assert cp.mean() < 0.5 * cf.mean()
-    assert fallback < 0.05
+    cp = cv_proxy.cpu().numpy()
+    _, cv_x0 = px.baseline(loads)
+    c0 = cv_x0.cpu().numpy()
+    _, cv_flat = px.flat_start(loads)
+    cf = cv_flat.cpu().numpy()
+    curve = P.fallback_curve(cp)
+    print(f"loss {first:.4g} -> {last:.4g}; held-out Cvio: proxy mean {cp.mean():.4g} max {cp.max():.4g}, "
+          f"x0 mean {c0.mean():.4g}, flat start mean {cf.mean():.4g}; fallback rate by tau {curve}")
+    assert last < 0.05 * first
+    assert cp.mean() < 0.5 * c0.mean() and cp.mean() < 0.5 * cf.mean()
+    assert np.mean(cp < cf) > 0.95
+    # the fallback rate is the share of samples above tau
+    assert curve[0.05] == float(np.mean(cp > 0.05))
+    assert all(a >= b for a, b in zip(list(curve.values()), list(curve.values())[1:]))
     px.close()
