@@ -21,6 +21,11 @@
  *                 The rectangular form (form = :rect, Sec. III-C1) takes
  *                 bus variables (vr, vi) for (va, vm) and rows of
  *                 PowerModels' ACR formulation (see row_value_rect).
+ *                 Storage units (Sec. III-C3, the storage model of Geth,
+ *                 Coffrin and Fobes 2020 that the paper cites) and linear
+ *                 user-extension devices (Sec. III-D, Listing 10) add
+ *                 their variable and row blocks after the others and their
+ *                 terms to the balance rows (see row_value_ext).
  *   J(x)          sparse Jacobian values, sorted by (row, col)
  *   H(x, y, s)    lower triangle of s * hess f + sum_i y_i hess c_i, sorted by
  *                 (row, col), duplicates merged (hess! with obj_weight,
@@ -70,6 +75,17 @@ typedef struct {
     int32_t n_cont;             /* contingency copies (0 = none) */
     const int32_t *outaged;     /* [n_cont] */
     int32_t form;               /* 0 = polar (va, vm), 1 = rectangular (vr, vi) */
+    /* storage units (polar form, no contingency copies) */
+    int32_t n_stor;
+    const int32_t *stor_bus;
+    const double *stor_emax, *stor_chmax, *stor_dismax, *stor_rating, *stor_qmin, *stor_qmax;
+    const double *stor_eta_c, *stor_eta_d, *stor_r, *stor_x, *stor_ploss, *stor_qloss, *stor_e0;
+    double stor_dt;             /* duration of a period */
+    int32_t stor_comp;          /* 1: add the complementarity rows sc * sd */
+    /* linear user-extension devices (no contingency copies) */
+    int32_t n_dev;
+    const int32_t *dev_bus, *dev_mask;  /* mask bit 0: active balance, bit 1: reactive balance */
+    const double *dev_cp, *dev_cq, *dev_cost, *dev_lo, *dev_hi, *dev_ramp, *dev_init_lo, *dev_init_hi;
 } or_case;
 
 typedef struct {
@@ -129,6 +145,22 @@ static hd hd_mul(hd x, hd y) {
     z.md = x.ma * y.md + x.mb * y.mc + x.mc * y.mb + x.md * y.ma;
     return z;
 }
+/* 1 / x: value 1/a, first parts -b/a^2, -c/a^2, second part
+ * 2 b c / a^3 - d / a^2 (the Taylor expansion of 1/(a + h) to second order
+ * in the two directions).  Magnitudes: the same expressions on |parts|. */
+static hd hd_inv(hd x) {
+    hd r;
+    double a = x.a, a2 = a * a, a3 = a2 * a, aa = fabs(a);
+    r.a = 1.0 / a;
+    r.b = -x.b / a2;
+    r.c = -x.c / a2;
+    r.d = 2.0 * x.b * x.c / a3 - x.d / a2;
+    r.ma = 1.0 / aa;
+    r.mb = x.mb / a2;
+    r.mc = x.mc / a2;
+    r.md = 2.0 * x.mb * x.mc / (a2 * aa) + x.md / a2;
+    return r;
+}
 static hd hd_scale(double s, hd x) {
     double as = fabs(s);
     hd z = {s * x.a, s * x.b, s * x.c, s * x.d,
@@ -160,12 +192,19 @@ static hd hd_cos(hd x) { return hd_trig(x, cos(x.a), -sin(x.a), -cos(x.a)); }
 /* ------------------------------------------------------------------ */
 /* R_ANGL (the lower angle-difference row) and R_VMAG (voltage magnitude)
  * exist in the rectangular form only; in the polar form they are empty. */
+/* Storage rows (per unit and period): R_SOC state of charge, R_SLP / R_SLQ
+ * active and reactive loss rows, R_STH thermal limit, R_SCMP the optional
+ * complementarity row; device rows: R_DRAMP ramp (periods 1..T-1), R_DINIT
+ * initial value (period 0). */
 enum { R_REF, R_PFR, R_QFR, R_PTO, R_QTO, R_ANG, R_ANGL, R_BALP, R_BALQ, R_THF, R_THT, R_VMAG, R_RAMP,
-       R_NBLK };
+       R_SOC, R_SLP, R_SLQ, R_STH, R_SCMP, R_DRAMP, R_DINIT, R_NBLK };
 
 typedef struct {
-    int N, L, G, R, T, K, nrep, npg, rect;
+    int N, L, G, R, T, K, nrep, npg, rect, S, D;
     int64_t xva, xvm, xpg, xqg, xp, xq, n;
+    /* storage blocks ps, qs, qsc, se, sc, sd and the device block u, each
+     * S * nrep (D * nrep), unit fastest */
+    int64_t xps, xqs, xqsc, xse, xsc, xsd, xu;
     int64_t cblk[R_NBLK + 1]; /* start row of every constraint block; cblk[R_NBLK] = m */
 } layout;
 
@@ -177,7 +216,13 @@ static int make_layout(const or_case *cs, layout *ly) {
     if (cs->n_periods > 1 && cs->n_cont > 0)
         return fail("periods and contingency copies are not combined");
     if (cs->form != 0 && cs->form != 1) return fail("form must be 0 (polar) or 1 (rectangular)");
+    if (cs->n_stor < 0 || cs->n_dev < 0) return fail("negative storage or device count");
+    if ((cs->n_stor > 0 || cs->n_dev > 0) && cs->n_cont > 0)
+        return fail("storage and devices are not combined with contingency copies");
+    if (cs->n_stor > 0 && cs->form != 0) return fail("storage units take the polar form");
     ly->rect = cs->form;
+    ly->S = cs->n_stor;
+    ly->D = cs->n_dev;
     ly->N = cs->n_bus; ly->L = cs->n_branch; ly->G = cs->n_gen; ly->R = cs->n_ref;
     ly->T = cs->n_periods; ly->K = cs->n_cont;
     ly->nrep = cs->n_periods > 1 ? cs->n_periods : cs->n_cont + 1;
@@ -189,11 +234,20 @@ static int make_layout(const or_case *cs, layout *ly) {
     ly->xqg = ly->xpg + G * ly->npg;
     ly->xp = ly->xqg + G * nr;
     ly->xq = ly->xp + 2 * L * nr;
-    ly->n = ly->xq + 2 * L * nr;
-    int64_t rc = ly->rect;
+    int64_t S = ly->S, D = ly->D;
+    ly->xps = ly->xq + 2 * L * nr;
+    ly->xqs = ly->xps + S * nr;
+    ly->xqsc = ly->xqs + S * nr;
+    ly->xse = ly->xqsc + S * nr;
+    ly->xsc = ly->xse + S * nr;
+    ly->xsd = ly->xsc + S * nr;
+    ly->xu = ly->xsd + S * nr;
+    ly->n = ly->xu + D * nr;
+    int64_t rc = ly->rect, T1 = ly->T - 1;
     int64_t sizes[R_NBLK] = {R * nr, L * nr, L * nr, L * nr, L * nr, L * nr, rc * L * nr,
                              N * nr, N * nr, L * nr, L * nr, rc * N * nr,
-                             (ly->T > 1) ? G * (ly->T - 1) : 0};
+                             G * T1, S * nr, S * nr, S * nr, S * nr, (cs->stor_comp ? S : 0) * nr,
+                             D * T1, D};
     ly->cblk[0] = 0;
     for (int k = 0; k < R_NBLK; k++) ly->cblk[k + 1] = ly->cblk[k] + sizes[k];
     return 0;
@@ -210,6 +264,14 @@ static int64_t col_pg(const layout *l, int k, int r) {
 static int64_t col_qg(const layout *l, int k, int r) { return l->xqg + k + (int64_t)l->G * r; }
 static int64_t col_p(const layout *l, int a, int r) { return l->xp + a + 2 * (int64_t)l->L * r; }
 static int64_t col_q(const layout *l, int a, int r) { return l->xq + a + 2 * (int64_t)l->L * r; }
+/* storage unit u and device d in period r */
+static int64_t col_ps(const layout *l, int u, int r) { return l->xps + u + (int64_t)l->S * r; }
+static int64_t col_qs(const layout *l, int u, int r) { return l->xqs + u + (int64_t)l->S * r; }
+static int64_t col_qsc(const layout *l, int u, int r) { return l->xqsc + u + (int64_t)l->S * r; }
+static int64_t col_se(const layout *l, int u, int r) { return l->xse + u + (int64_t)l->S * r; }
+static int64_t col_sc(const layout *l, int u, int r) { return l->xsc + u + (int64_t)l->S * r; }
+static int64_t col_sd(const layout *l, int u, int r) { return l->xsd + u + (int64_t)l->S * r; }
+static int64_t col_u(const layout *l, int d, int r) { return l->xu + d + (int64_t)l->D * r; }
 
 /* ------------------------------------------------------------------ */
 /* branch admittance terms of the pi model                             */
@@ -249,14 +311,36 @@ typedef struct {
     int nsup;
     int narc;            /* balance rows: number of arc terms */
     int nbv;             /* balance rows: leading bus variables (1 polar: vm; 2 rect: vr, vi) */
+    int ngen, nstor;     /* balance rows: generator and storage terms */
+    const int32_t *devs; /* balance rows: the devices of the device terms (the rest of the row) */
     int64_t sup[64 + 16]; /* variable columns, in term order (filled by row_support) */
     int64_t *big;         /* used instead of sup when a balance row is long */
 } row_t;
 
 typedef struct {
-    /* arcs and generators incident to each bus, for the balance rows */
-    int32_t *arc_ptr, *arc_idx, *gen_ptr, *gen_idx;
+    /* arcs, generators, storage units and devices (active and reactive
+     * balance lists by mask) at each bus, for the balance rows */
+    int32_t *arc_ptr, *arc_idx, *gen_ptr, *gen_idx, *st_ptr, *st_idx;
+    int32_t *dp_ptr, *dp_idx, *dq_ptr, *dq_idx;
 } adjacency;
+
+/* Entities e with bus(e) listed per bus in increasing index: ptr [N+1],
+ * idx [count]; keep(e) selects which. */
+static int bus_lists(int N, int count, const int32_t *bus, const int32_t *mask, int bit, int32_t **ptr,
+                     int32_t **idx) {
+    *ptr = calloc((size_t)N + 1, sizeof(int32_t));
+    *idx = malloc(sizeof(int32_t) * (size_t)(count + 1));
+    if (!*ptr || !*idx) return fail("out of memory");
+    for (int e = 0; e < count; e++)
+        if (!mask || (mask[e] & bit)) (*ptr)[bus[e] + 1]++;
+    for (int i = 0; i < N; i++) (*ptr)[i + 1] += (*ptr)[i];
+    int32_t *fill = calloc((size_t)N + 1, sizeof(int32_t));
+    if (!fill) return fail("out of memory");
+    for (int e = 0; e < count; e++)
+        if (!mask || (mask[e] & bit)) (*idx)[(*ptr)[bus[e]] + fill[bus[e]]++] = e;
+    free(fill);
+    return 0;
+}
 
 static int build_adjacency(const or_case *cs, adjacency *adj) {
     int N = cs->n_bus, L = cs->n_branch, G = cs->n_gen;
@@ -285,10 +369,15 @@ static int build_adjacency(const or_case *cs, adjacency *adj) {
         adj->gen_idx[adj->gen_ptr[bus] + fill[bus]++] = k;
     }
     free(fill);
+    if (bus_lists(N, cs->n_stor, cs->stor_bus, NULL, 0, &adj->st_ptr, &adj->st_idx)) return -1;
+    if (bus_lists(N, cs->n_dev, cs->dev_bus, cs->dev_mask, 1, &adj->dp_ptr, &adj->dp_idx)) return -1;
+    if (bus_lists(N, cs->n_dev, cs->dev_bus, cs->dev_mask, 2, &adj->dq_ptr, &adj->dq_idx)) return -1;
     return 0;
 }
 static void free_adjacency(adjacency *adj) {
     free(adj->arc_ptr); free(adj->arc_idx); free(adj->gen_ptr); free(adj->gen_idx);
+    free(adj->st_ptr); free(adj->st_idx);
+    free(adj->dp_ptr); free(adj->dp_idx); free(adj->dq_ptr); free(adj->dq_idx);
 }
 
 static int64_t *row_sup(row_t *rw) { return rw->big ? rw->big : rw->sup; }
@@ -341,8 +430,14 @@ static int row_support(const or_case *cs, const layout *ly, const adjacency *adj
         int isp = rw->blk == R_BALP;
         int na = adj->arc_ptr[e + 1] - adj->arc_ptr[e];
         int ng = adj->gen_ptr[e + 1] - adj->gen_ptr[e];
-        rw->nsup = rw->nbv + na + ng;
+        int ns = adj->st_ptr[e + 1] - adj->st_ptr[e];
+        const int32_t *dptr = isp ? adj->dp_ptr : adj->dq_ptr, *didx = isp ? adj->dp_idx : adj->dq_idx;
+        int nd = dptr[e + 1] - dptr[e];
+        rw->nsup = rw->nbv + na + ng + ns + nd;
         rw->narc = na;
+        rw->ngen = ng;
+        rw->nstor = ns;
+        rw->devs = didx + dptr[e];
         if (rw->nsup > (int)(sizeof rw->sup / sizeof rw->sup[0])) {
             rw->big = malloc(sizeof(int64_t) * (size_t)rw->nsup);
             if (!rw->big) return fail("out of memory");
@@ -359,8 +454,52 @@ static int row_support(const or_case *cs, const layout *ly, const adjacency *adj
             s[q++] = isp ? col_p(ly, adj->arc_idx[j], r) : col_q(ly, adj->arc_idx[j], r);
         for (int j = adj->gen_ptr[e]; j < adj->gen_ptr[e + 1]; j++)
             s[q++] = isp ? col_pg(ly, adj->gen_idx[j], r) : col_qg(ly, adj->gen_idx[j], r);
+        for (int j = adj->st_ptr[e]; j < adj->st_ptr[e + 1]; j++)
+            s[q++] = isp ? col_ps(ly, adj->st_idx[j], r) : col_qs(ly, adj->st_idx[j], r);
+        for (int j = dptr[e]; j < dptr[e + 1]; j++) s[q++] = col_u(ly, didx[j], r);
         break;
     }
+    case R_SOC:  /* se_t, se_{t-1} (periods t >= 1), sc_t, sd_t */
+        rw->nsup = 0;
+        s[rw->nsup++] = col_se(ly, e, r);
+        if (r >= 1) s[rw->nsup++] = col_se(ly, e, r - 1);
+        s[rw->nsup++] = col_sc(ly, e, r);
+        s[rw->nsup++] = col_sd(ly, e, r);
+        break;
+    case R_SLP:  /* ps, qs, vm of the unit's bus, sd, sc */
+        rw->nsup = 5;
+        s[0] = col_ps(ly, e, r);
+        s[1] = col_qs(ly, e, r);
+        s[2] = col_vm(ly, cs->stor_bus[e], r);
+        s[3] = col_sd(ly, e, r);
+        s[4] = col_sc(ly, e, r);
+        break;
+    case R_SLQ:  /* ps, qs, vm, qsc */
+        rw->nsup = 4;
+        s[0] = col_ps(ly, e, r);
+        s[1] = col_qs(ly, e, r);
+        s[2] = col_vm(ly, cs->stor_bus[e], r);
+        s[3] = col_qsc(ly, e, r);
+        break;
+    case R_STH:  /* ps, qs */
+        rw->nsup = 2;
+        s[0] = col_ps(ly, e, r);
+        s[1] = col_qs(ly, e, r);
+        break;
+    case R_SCMP: /* sc, sd */
+        rw->nsup = 2;
+        s[0] = col_sc(ly, e, r);
+        s[1] = col_sd(ly, e, r);
+        break;
+    case R_DRAMP: /* u_t, u_{t-1} */
+        rw->nsup = 2;
+        s[0] = col_u(ly, e, r);
+        s[1] = col_u(ly, e, r - 1);
+        break;
+    case R_DINIT:
+        rw->nsup = 1;
+        s[0] = col_u(ly, e, 0);
+        break;
     case R_THF: case R_THT: {
         int arc = rw->blk == R_THF ? e : L + e;
         rw->nsup = 2;
@@ -380,6 +519,23 @@ static int row_support(const or_case *cs, const layout *ly, const adjacency *adj
         break;
     }
     return 0;
+}
+
+/* The terms a balance row adds after its arc terms, in the order of its
+ * support: -pg (-qg) of every generator at the bus, +ps (+qs) of every
+ * storage unit (the power it draws from the grid), and the device terms
+ * cp u (cq u) of the devices whose mask names this row (Listing 10 adds the
+ * electrolyzer load p_elec to the active balance with constraint!). */
+static hd balance_tail(const or_case *cs, const row_t *rw, const hd *v, int first, hd acc) {
+    int isp = rw->blk == R_BALP;
+    int q = first;
+    for (int j = 0; j < rw->ngen; j++, q++) acc = hd_sub(acc, v[q]);
+    for (int j = 0; j < rw->nstor; j++, q++) acc = hd_add(acc, v[q]);
+    for (int j = 0; q < rw->nsup; j++, q++) {
+        int d = rw->devs[j];
+        acc = hd_add(acc, hd_scale(isp ? cs->dev_cp[d] : cs->dev_cq[d], v[q]));
+    }
+    return acc;
 }
 
 static double bus_pd(const or_case *cs, int i, int r) {
@@ -443,8 +599,7 @@ static hd row_value_rect(const or_case *cs, const row_t *rw, const hd *v) {
         hd v2 = hd_add(hd_mul(v[0], v[0]), hd_mul(v[1], v[1]));
         hd acc = hd_add(hd_cst(load), hd_scale(shunt, v2));
         for (int q = 2; q < 2 + rw->narc; q++) acc = hd_add(acc, v[q]);
-        for (int q = 2 + rw->narc; q < rw->nsup; q++) acc = hd_sub(acc, v[q]);
-        return acc;
+        return balance_tail(cs, rw, v, 2 + rw->narc, acc);
     }
     case R_VMAG:
         return hd_add(hd_mul(v[0], v[0]), hd_mul(v[1], v[1]));
@@ -502,8 +657,7 @@ static hd row_value(const or_case *cs, const row_t *rw, const hd *v) {
         double shunt = isp ? cs->gs[e] : -cs->bs[e];
         hd acc = hd_add(hd_cst(load), hd_scale(shunt, hd_mul(v[0], v[0])));
         for (int q = 1; q < 1 + rw->narc; q++) acc = hd_add(acc, v[q]);
-        for (int q = 1 + rw->narc; q < rw->nsup; q++) acc = hd_sub(acc, v[q]);
-        return acc;
+        return balance_tail(cs, rw, v, 1 + rw->narc, acc);
     }
     case R_THF: case R_THT: {
         double rate = cs->rate_a[e];
@@ -515,7 +669,60 @@ static hd row_value(const or_case *cs, const row_t *rw, const hd *v) {
     return hd_cst(NAN);
 }
 
+/* Rows of the storage units and the user-extension devices.
+ * Storage, per unit u at bus i and period t (the model of Geth, Coffrin and
+ * Fobes 2020 that the paper cites for its storage formulation):
+ *   state of charge  se_t - se_{t-1} - dt (eta_c sc_t - sd_t / eta_d) = 0,
+ *                    se_{-1} = the initial energy e0 (a constant)
+ *   active losses    ps + sd - sc - p_loss - r (ps^2 + qs^2) / vm_i^2 = 0
+ *   reactive losses  qs - qsc - q_loss - x (ps^2 + qs^2) / vm_i^2 = 0
+ *                    ((ps^2 + qs^2) / vm^2 is the squared converter current)
+ *   thermal          ps^2 + qs^2 - rating^2 <= 0
+ *   complementarity  sc sd <= 0 (with sc, sd >= 0: sc sd = 0), when asked
+ * ps, qs: the power the unit draws from the grid (a load in the balance
+ * rows); qsc: the converter's reactive set-point; se: stored energy;
+ * sc, sd: charging and discharging power.
+ * Devices, per device d (Listing 10's electrolyzer generalised to linear
+ * devices):  ramp u_t - u_{t-1} (t >= 1) and the initial row u_0. */
+static hd row_value_ext(const or_case *cs, const row_t *rw, const hd *v) {
+    int e = rw->ent;
+    switch (rw->blk) {
+    case R_SOC: {
+        double dt = cs->stor_dt, ec = cs->stor_eta_c[e], ed = cs->stor_eta_d[e];
+        int q = 0;
+        hd se = v[q++];
+        hd prev = rw->rep >= 1 ? v[q++] : hd_cst(cs->stor_e0[e]);
+        hd sc = v[q++], sd = v[q++];
+        hd flow = hd_sub(hd_scale(ec, sc), hd_scale(1.0 / ed, sd));
+        return hd_sub(hd_sub(se, prev), hd_scale(dt, flow));
+    }
+    case R_SLP: case R_SLQ: {
+        hd ps = v[0], qs = v[1], vm = v[2];
+        hd i2 = hd_mul(hd_add(hd_mul(ps, ps), hd_mul(qs, qs)), hd_inv(hd_mul(vm, vm)));
+        if (rw->blk == R_SLP) {
+            hd sd = v[3], sc = v[4];
+            hd lhs = hd_sub(hd_add(ps, sd), sc);
+            return hd_sub(hd_sub(lhs, hd_cst(cs->stor_ploss[e])), hd_scale(cs->stor_r[e], i2));
+        }
+        hd qsc = v[3];
+        return hd_sub(hd_sub(hd_sub(qs, qsc), hd_cst(cs->stor_qloss[e])), hd_scale(cs->stor_x[e], i2));
+    }
+    case R_STH: {
+        double rt = cs->stor_rating[e];
+        return hd_sub(hd_add(hd_mul(v[0], v[0]), hd_mul(v[1], v[1])), hd_cst(rt * rt));
+    }
+    case R_SCMP:
+        return hd_mul(v[0], v[1]);
+    case R_DRAMP:
+        return hd_sub(v[0], v[1]);
+    case R_DINIT:
+        return v[0];
+    }
+    return hd_cst(NAN);
+}
+
 static hd eval_row(const or_case *cs, const row_t *rw, const hd *v) {
+    if (rw->blk >= R_SOC) return row_value_ext(cs, rw, v);
     return cs->form ? row_value_rect(cs, rw, v) : row_value(cs, rw, v);
 }
 
@@ -543,7 +750,29 @@ static int row_hess_pairs_rect(const row_t *rw, int pairs[][2]) {
     }
 }
 
+/* Storage and device rows: the loss rows pair ps, qs and vm (positions
+ * 0, 1, 2) inside (ps^2 + qs^2) / vm^2 (no ps-qs product), the thermal row
+ * squares ps and qs, the complementarity row multiplies sc and sd. */
+static int row_hess_pairs_ext(const row_t *rw, int pairs[][2]) {
+    static const int loss[5][2] = {{0, 0}, {1, 1}, {2, 2}, {2, 0}, {2, 1}};
+    switch (rw->blk) {
+    case R_SLP: case R_SLQ:
+        memcpy(pairs, loss, sizeof loss);
+        return 5;
+    case R_STH:
+        pairs[0][0] = 0; pairs[0][1] = 0;
+        pairs[1][0] = 1; pairs[1][1] = 1;
+        return 2;
+    case R_SCMP:
+        pairs[0][0] = 1; pairs[0][1] = 0;
+        return 1;
+    default:
+        return 0;
+    }
+}
+
 static int row_hess_pairs(const row_t *rw, int rect, int pairs[][2]) {
+    if (rw->blk >= R_SOC) return row_hess_pairs_ext(rw, pairs);
     if (rect) return row_hess_pairs_rect(rw, pairs);
     switch (rw->blk) {
     case R_PFR: case R_QFR: case R_PTO: case R_QTO: {
@@ -576,12 +805,14 @@ static void row_of(const layout *ly, int64_t row, row_t *rw) {
     case R_REF: per = ly->R; break;
     case R_BALP: case R_BALQ: case R_VMAG: per = ly->N; break;
     case R_RAMP: per = ly->G; break;
+    case R_SOC: case R_SLP: case R_SLQ: case R_STH: case R_SCMP: per = ly->S; break;
+    case R_DRAMP: case R_DINIT: per = ly->D; break;
     default: per = ly->L; break;
     }
     rw->blk = blk;
     rw->ent = (int)(loc % per);
     rw->rep = (int)(loc / per);
-    if (blk == R_RAMP) rw->rep += 1; /* ramp rows start at period 1 */
+    if (blk == R_RAMP || blk == R_DRAMP) rw->rep += 1; /* ramp rows start at period 1 */
 }
 
 /* ------------------------------------------------------------------ */
@@ -625,6 +856,10 @@ static int check_case(const or_case *cs) {
         if (cs->ref_bus[j] < 0 || cs->ref_bus[j] >= cs->n_bus) return fail("reference bus out of range");
     for (int s = 0; s < cs->n_cont; s++)
         if (cs->outaged[s] < 0 || cs->outaged[s] >= cs->n_branch) return fail("outaged branch out of range");
+    for (int u = 0; u < cs->n_stor; u++)
+        if (cs->stor_bus[u] < 0 || cs->stor_bus[u] >= cs->n_bus) return fail("storage bus out of range");
+    for (int d = 0; d < cs->n_dev; d++)
+        if (cs->dev_bus[d] < 0 || cs->dev_bus[d] >= cs->n_bus) return fail("device bus out of range");
     return 0;
 }
 
@@ -666,6 +901,18 @@ int or_bounds(const or_case *cs, double *lvar, double *uvar, double *lcon, doubl
             lvar[col_p(&ly, a, r)] = -rate; uvar[col_p(&ly, a, r)] = rate;
             lvar[col_q(&ly, a, r)] = -rate; uvar[col_q(&ly, a, r)] = rate;
         }
+        for (int u = 0; u < ly.S; u++) {
+            double rt = cs->stor_rating[u];
+            lvar[col_ps(&ly, u, r)] = -rt; uvar[col_ps(&ly, u, r)] = rt;
+            lvar[col_qs(&ly, u, r)] = cs->stor_qmin[u]; uvar[col_qs(&ly, u, r)] = cs->stor_qmax[u];
+            lvar[col_qsc(&ly, u, r)] = -rt; uvar[col_qsc(&ly, u, r)] = rt;
+            lvar[col_se(&ly, u, r)] = 0.0; uvar[col_se(&ly, u, r)] = cs->stor_emax[u];
+            lvar[col_sc(&ly, u, r)] = 0.0; uvar[col_sc(&ly, u, r)] = cs->stor_chmax[u];
+            lvar[col_sd(&ly, u, r)] = 0.0; uvar[col_sd(&ly, u, r)] = cs->stor_dismax[u];
+        }
+        for (int d = 0; d < ly.D; d++) {
+            lvar[col_u(&ly, d, r)] = cs->dev_lo[d]; uvar[col_u(&ly, d, r)] = cs->dev_hi[d];
+        }
     }
     int64_t m = ly.cblk[R_NBLK];
     for (int64_t row = 0; row < m; row++) {
@@ -690,6 +937,12 @@ int or_bounds(const or_case *cs, double *lvar, double *uvar, double *lcon, doubl
         } else if (rw.blk == R_RAMP) {
             lo = -cs->ramp_ratio * cs->pmax[rw.ent];
             hi = cs->ramp_ratio * cs->pmax[rw.ent];
+        } else if (rw.blk == R_STH || rw.blk == R_SCMP) {
+            lo = -INFINITY; hi = 0.0;
+        } else if (rw.blk == R_DRAMP) {
+            lo = -cs->dev_ramp[rw.ent]; hi = cs->dev_ramp[rw.ent];
+        } else if (rw.blk == R_DINIT) {
+            lo = cs->dev_init_lo[rw.ent]; hi = cs->dev_init_hi[rw.ent];
         }
         lcon[row] = lo; ucon[row] = hi;
     }
@@ -731,7 +984,9 @@ or_result *or_eval(const or_case *cs, const double *x, const double *y, double s
     res->n = n; res->m = m;
     int maxsup = 1;
     for (int i = 0; i < ly.N; i++) {
-        int s = 2 + (adj.arc_ptr[i + 1] - adj.arc_ptr[i]) + (adj.gen_ptr[i + 1] - adj.gen_ptr[i]);
+        int s = 2 + (adj.arc_ptr[i + 1] - adj.arc_ptr[i]) + (adj.gen_ptr[i + 1] - adj.gen_ptr[i]) +
+                (adj.st_ptr[i + 1] - adj.st_ptr[i]) + (adj.dp_ptr[i + 1] - adj.dp_ptr[i]) +
+                (adj.dq_ptr[i + 1] - adj.dq_ptr[i]);
         if (s > maxsup) maxsup = s;
     }
     if (maxsup < 5) maxsup = 5;
@@ -758,6 +1013,15 @@ or_result *or_eval(const or_case *cs, const double *x, const double *y, double s
                     if (tv_push(&H, col, col, sigma * term.d, fabs(sigma) * term.md)) { err = 1; goto done; }
             }
         }
+        /* the devices' secondary objective (Listing 10): cost_d u_{d,t} */
+        for (int r = 0; r < ly.nrep; r++)
+            for (int d = 0; d < ly.D; d++) {
+                int64_t col = col_u(&ly, d, r);
+                hd term = hd_scale(cs->dev_cost[d], hd_var(x[col], 1.0, 1.0));
+                f += term.a;
+                fs += term.ma;
+                res->g[col] = term.b;
+            }
         res->f = f;
         res->fscale = fs;
     }

@@ -6,8 +6,11 @@ imports nothing from the HIP package.
 
 Cases are dicts of numpy arrays with the field names of the network
 generator; options are keyword arguments ``n_periods``, ``pd_t``, ``qd_t``,
-``ramp_ratio``, ``n_cont``, ``outaged`` and ``form`` ("polar", the default,
-or "rect": bus variables (vr, vi) in place of (va, vm)).
+``ramp_ratio``, ``n_cont``, ``outaged``, ``form`` ("polar", the default,
+or "rect": bus variables (vr, vi) in place of (va, vm)), ``storage`` (a dict
+of per-unit arrays: bus, emax, chmax, dismax, rating, qmin, qmax, eta_c,
+eta_d, r, x, ploss, qloss, e0), ``stor_dt``, ``stor_comp`` and ``devices``
+(per-device arrays: bus, mask, cp, cq, cost, lo, hi, ramp, init_lo, init_hi).
 """
 from __future__ import annotations
 
@@ -52,7 +55,20 @@ class _Case(ctypes.Structure):
         ("ramp_ratio", ctypes.c_double),
         ("n_cont", ctypes.c_int32), ("outaged", _ip),
         ("form", ctypes.c_int32),
+        ("n_stor", ctypes.c_int32), ("stor_bus", _ip),
+        ("stor_emax", _dp), ("stor_chmax", _dp), ("stor_dismax", _dp), ("stor_rating", _dp),
+        ("stor_qmin", _dp), ("stor_qmax", _dp), ("stor_eta_c", _dp), ("stor_eta_d", _dp),
+        ("stor_r", _dp), ("stor_x", _dp), ("stor_ploss", _dp), ("stor_qloss", _dp), ("stor_e0", _dp),
+        ("stor_dt", ctypes.c_double), ("stor_comp", ctypes.c_int32),
+        ("n_dev", ctypes.c_int32), ("dev_bus", _ip), ("dev_mask", _ip),
+        ("dev_cp", _dp), ("dev_cq", _dp), ("dev_cost", _dp), ("dev_lo", _dp), ("dev_hi", _dp),
+        ("dev_ramp", _dp), ("dev_init_lo", _dp), ("dev_init_hi", _dp),
     ]
+
+
+STOR_FIELDS = ("emax", "chmax", "dismax", "rating", "qmin", "qmax", "eta_c", "eta_d", "r", "x", "ploss", "qloss",
+               "e0")
+DEV_FIELDS = ("cp", "cq", "cost", "lo", "hi", "ramp", "init_lo", "init_hi")
 
 
 class _Result(ctypes.Structure):
@@ -94,7 +110,7 @@ FORMS = {"polar": 0, "rect": 1}
 
 
 def _make_case(case: dict, n_periods=1, pd_t=None, qd_t=None, ramp_ratio=0.0,
-               n_cont=0, outaged=None, form="polar"):
+               n_cont=0, outaged=None, form="polar", storage=None, stor_dt=1.0, stor_comp=False, devices=None):
     keep = []
 
     def d(a):
@@ -122,6 +138,19 @@ def _make_case(case: dict, n_periods=1, pd_t=None, qd_t=None, ramp_ratio=0.0,
     c.n_cont = int(n_cont)
     c.outaged = i(outaged if outaged is not None else np.zeros(1, np.int32))
     c.form = FORMS[form]
+    if storage is not None and len(storage["bus"]) > 0:
+        c.n_stor = len(storage["bus"])
+        c.stor_bus = i(storage["bus"])
+        for k in STOR_FIELDS:
+            setattr(c, "stor_" + k, d(storage[k]))
+    c.stor_dt = float(stor_dt)
+    c.stor_comp = int(bool(stor_comp))
+    if devices is not None and len(devices["bus"]) > 0:
+        c.n_dev = len(devices["bus"])
+        c.dev_bus = i(devices["bus"])
+        c.dev_mask = i(devices["mask"])
+        for k in DEV_FIELDS:
+            setattr(c, "dev_" + k, d(devices[k]))
     return c, keep
 
 

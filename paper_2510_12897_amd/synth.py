@@ -42,6 +42,8 @@ __all__ = [
     "outages",
     "scenario_loads",
     "perturbed_loads",
+    "storage",
+    "devices",
     "BATCH_SIZES",
 ]
 
@@ -155,7 +157,8 @@ def network(n_bus: int, n_branch: int, n_gen: int, seed, variant: bool = False) 
     )
 
 
-def point(case: dict, seed, n_periods: int = 1, n_cont: int = 0, form: str = "polar") -> np.ndarray:
+def point(case: dict, seed, n_periods: int = 1, n_cont: int = 0, form: str = "polar", storage=None,
+          devices=None) -> np.ndarray:
     """An evaluation point drawn inside the variable bounds.
 
     Blocks are concatenated in the model's variable order (va, vm, pg, qg,
@@ -181,7 +184,16 @@ def point(case: dict, seed, n_periods: int = 1, n_cont: int = 0, form: str = "po
         va, vm = vm * np.cos(va), vm * np.sin(va)
     elif form != "polar":
         raise ValueError(f"unknown form {form!r}")
-    return np.concatenate([va, vm, pg, qg, p, q])
+    blocks = [va, vm, pg, qg, p, q]
+    if storage is not None:  # ps, qs, qsc, se, sc, sd inside their bounds
+        st = storage
+        rt = np.tile(st["rating"], nrep)
+        blocks += [rng.uniform(-rt, rt), rng.uniform(np.tile(st["qmin"], nrep), np.tile(st["qmax"], nrep)),
+                   rng.uniform(-rt, rt), rng.uniform(0.0, np.tile(st["emax"], nrep)),
+                   rng.uniform(0.0, np.tile(st["chmax"], nrep)), rng.uniform(0.0, np.tile(st["dismax"], nrep))]
+    if devices is not None:
+        blocks.append(rng.uniform(np.tile(devices["lo"], nrep), np.tile(devices["hi"], nrep)))
+    return np.concatenate(blocks)
 
 
 def multipliers(m: int, seed) -> np.ndarray:
@@ -229,3 +241,41 @@ def perturbed_loads(case: dict, n_samples: int, seed, spread: float = 0.3):
     rng = _rng(seed)
     fac = rng.uniform(1.0 - spread, 1.0 + spread, size=(n_samples, case["n_bus"]))
     return case["pd"][None, :] * fac, case["qd"][None, :] * fac
+
+
+def storage(case: dict, seed, frac: float = 0.1, loads=None) -> dict:
+    """Storage units at the buses with the largest active loads (the top
+    `frac` of buses, at least one), as the paper places them for its
+    multi-period benchmarks with storage (Sec. IV-C), each with an energy
+    rating of 1.5 times its bus's load there.  The paper gives no other
+    parameter; drawn here: charge and discharge ratings 0.5 emax, thermal
+    rating 0.6 emax, reactive range +-0.5 rating, efficiencies
+    ~ U(0.9, 0.95), converter r ~ U(0, 0.02), x ~ U(0, 0.05), standby losses
+    ~ U(0, 1e-3) and an initial energy of 0.5 emax.  `loads` (default the
+    case's pd) picks the buses."""
+    rng = _rng(seed)
+    pd = np.asarray(case["pd"] if loads is None else loads, np.float64)
+    n = max(1, int(round(frac * case["n_bus"])))
+    bus = np.sort(np.argsort(-pd, kind="stable")[:n]).astype(np.int32)
+    emax = np.maximum(1.5 * pd[bus], 1e-3)
+    rating = 0.6 * emax
+    return dict(bus=bus, emax=emax, chmax=0.5 * emax, dismax=0.5 * emax, rating=rating, qmin=-0.5 * rating,
+                qmax=0.5 * rating, eta_c=rng.uniform(0.9, 0.95, n), eta_d=rng.uniform(0.9, 0.95, n),
+                r=rng.uniform(0.0, 0.02, n), x=rng.uniform(0.0, 0.05, n), ploss=rng.uniform(0.0, 1e-3, n),
+                qloss=rng.uniform(0.0, 1e-3, n), e0=0.5 * emax)
+
+
+def devices(case: dict, n_dev: int, seed) -> dict:
+    """Linear user-extension devices shaped like the electrolyzers of the
+    paper's user-extension example (Sec. III-D): buses uniform with
+    replacement, a load on the active balance (cp = 1, mask 1), every third
+    device also on the reactive balance (mask 3, cq ~ U(0.1, 0.3)), a
+    negative cost ~ U(-50, -10) (hydrogen revenue), power in [0, 0.5],
+    ramp limit 0.1 and an initial power of 0."""
+    rng = _rng(seed)
+    bus = rng.integers(0, case["n_bus"], n_dev).astype(np.int32)
+    mask = np.where(np.arange(n_dev) % 3 == 2, 3, 1).astype(np.int32)
+    cq = np.where(mask == 3, rng.uniform(0.1, 0.3, n_dev), 0.0)
+    return dict(bus=bus, mask=mask, cp=np.ones(n_dev), cq=cq, cost=rng.uniform(-50.0, -10.0, n_dev),
+                lo=np.zeros(n_dev), hi=np.full(n_dev, 0.5), ramp=np.full(n_dev, 0.1), init_lo=np.zeros(n_dev),
+                init_hi=np.zeros(n_dev))
