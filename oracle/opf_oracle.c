@@ -84,7 +84,7 @@ typedef struct {
     int32_t stor_comp;          /* 1: add the complementarity rows sc * sd */
     /* linear user-extension devices (no contingency copies) */
     int32_t n_dev;
-    const int32_t *dev_bus, *dev_mask;  /* mask bit 0: active balance, bit 1: reactive balance */
+    const int32_t *dev_bus;     /* every device enters both balance rows of its bus */
     const double *dev_cp, *dev_cq, *dev_cost, *dev_lo, *dev_hi, *dev_ramp, *dev_init_lo, *dev_init_hi;
 } or_case;
 
@@ -318,26 +318,22 @@ typedef struct {
 } row_t;
 
 typedef struct {
-    /* arcs, generators, storage units and devices (active and reactive
-     * balance lists by mask) at each bus, for the balance rows */
-    int32_t *arc_ptr, *arc_idx, *gen_ptr, *gen_idx, *st_ptr, *st_idx;
-    int32_t *dp_ptr, *dp_idx, *dq_ptr, *dq_idx;
+    /* arcs, generators, storage units and devices at each bus, for the
+     * balance rows */
+    int32_t *arc_ptr, *arc_idx, *gen_ptr, *gen_idx, *st_ptr, *st_idx, *dv_ptr, *dv_idx;
 } adjacency;
 
 /* Entities e with bus(e) listed per bus in increasing index: ptr [N+1],
- * idx [count]; keep(e) selects which. */
-static int bus_lists(int N, int count, const int32_t *bus, const int32_t *mask, int bit, int32_t **ptr,
-                     int32_t **idx) {
+ * idx [count]. */
+static int bus_lists(int N, int count, const int32_t *bus, int32_t **ptr, int32_t **idx) {
     *ptr = calloc((size_t)N + 1, sizeof(int32_t));
     *idx = malloc(sizeof(int32_t) * (size_t)(count + 1));
     if (!*ptr || !*idx) return fail("out of memory");
-    for (int e = 0; e < count; e++)
-        if (!mask || (mask[e] & bit)) (*ptr)[bus[e] + 1]++;
+    for (int e = 0; e < count; e++) (*ptr)[bus[e] + 1]++;
     for (int i = 0; i < N; i++) (*ptr)[i + 1] += (*ptr)[i];
     int32_t *fill = calloc((size_t)N + 1, sizeof(int32_t));
     if (!fill) return fail("out of memory");
-    for (int e = 0; e < count; e++)
-        if (!mask || (mask[e] & bit)) (*idx)[(*ptr)[bus[e]] + fill[bus[e]]++] = e;
+    for (int e = 0; e < count; e++) (*idx)[(*ptr)[bus[e]] + fill[bus[e]]++] = e;
     free(fill);
     return 0;
 }
@@ -369,15 +365,13 @@ static int build_adjacency(const or_case *cs, adjacency *adj) {
         adj->gen_idx[adj->gen_ptr[bus] + fill[bus]++] = k;
     }
     free(fill);
-    if (bus_lists(N, cs->n_stor, cs->stor_bus, NULL, 0, &adj->st_ptr, &adj->st_idx)) return -1;
-    if (bus_lists(N, cs->n_dev, cs->dev_bus, cs->dev_mask, 1, &adj->dp_ptr, &adj->dp_idx)) return -1;
-    if (bus_lists(N, cs->n_dev, cs->dev_bus, cs->dev_mask, 2, &adj->dq_ptr, &adj->dq_idx)) return -1;
+    if (bus_lists(N, cs->n_stor, cs->stor_bus, &adj->st_ptr, &adj->st_idx)) return -1;
+    if (bus_lists(N, cs->n_dev, cs->dev_bus, &adj->dv_ptr, &adj->dv_idx)) return -1;
     return 0;
 }
 static void free_adjacency(adjacency *adj) {
     free(adj->arc_ptr); free(adj->arc_idx); free(adj->gen_ptr); free(adj->gen_idx);
-    free(adj->st_ptr); free(adj->st_idx);
-    free(adj->dp_ptr); free(adj->dp_idx); free(adj->dq_ptr); free(adj->dq_idx);
+    free(adj->st_ptr); free(adj->st_idx); free(adj->dv_ptr); free(adj->dv_idx);
 }
 
 static int64_t *row_sup(row_t *rw) { return rw->big ? rw->big : rw->sup; }
@@ -431,7 +425,7 @@ static int row_support(const or_case *cs, const layout *ly, const adjacency *adj
         int na = adj->arc_ptr[e + 1] - adj->arc_ptr[e];
         int ng = adj->gen_ptr[e + 1] - adj->gen_ptr[e];
         int ns = adj->st_ptr[e + 1] - adj->st_ptr[e];
-        const int32_t *dptr = isp ? adj->dp_ptr : adj->dq_ptr, *didx = isp ? adj->dp_idx : adj->dq_idx;
+        const int32_t *dptr = adj->dv_ptr, *didx = adj->dv_idx;
         int nd = dptr[e + 1] - dptr[e];
         rw->nsup = rw->nbv + na + ng + ns + nd;
         rw->narc = na;
@@ -524,8 +518,9 @@ static int row_support(const or_case *cs, const layout *ly, const adjacency *adj
 /* The terms a balance row adds after its arc terms, in the order of its
  * support: -pg (-qg) of every generator at the bus, +ps (+qs) of every
  * storage unit (the power it draws from the grid), and the device terms
- * cp u (cq u) of the devices whose mask names this row (Listing 10 adds the
- * electrolyzer load p_elec to the active balance with constraint!). */
+ * cp u (cq u) of every device at the bus (Listing 10 adds the electrolyzer
+ * load p_elec to the active balance with constraint!: cp = 1, cq = 0).
+ * Devices enter both rows structurally, zero coefficients included. */
 static hd balance_tail(const or_case *cs, const row_t *rw, const hd *v, int first, hd acc) {
     int isp = rw->blk == R_BALP;
     int q = first;
@@ -985,8 +980,7 @@ or_result *or_eval(const or_case *cs, const double *x, const double *y, double s
     int maxsup = 1;
     for (int i = 0; i < ly.N; i++) {
         int s = 2 + (adj.arc_ptr[i + 1] - adj.arc_ptr[i]) + (adj.gen_ptr[i + 1] - adj.gen_ptr[i]) +
-                (adj.st_ptr[i + 1] - adj.st_ptr[i]) + (adj.dp_ptr[i + 1] - adj.dp_ptr[i]) +
-                (adj.dq_ptr[i + 1] - adj.dq_ptr[i]);
+                (adj.st_ptr[i + 1] - adj.st_ptr[i]) + (adj.dv_ptr[i + 1] - adj.dv_ptr[i]);
         if (s > maxsup) maxsup = s;
     }
     if (maxsup < 5) maxsup = 5;

@@ -10,7 +10,7 @@ generator; options are keyword arguments ``n_periods``, ``pd_t``, ``qd_t``,
 or "rect": bus variables (vr, vi) in place of (va, vm)), ``storage`` (a dict
 of per-unit arrays: bus, emax, chmax, dismax, rating, qmin, qmax, eta_c,
 eta_d, r, x, ploss, qloss, e0), ``stor_dt``, ``stor_comp`` and ``devices``
-(per-device arrays: bus, mask, cp, cq, cost, lo, hi, ramp, init_lo, init_hi).
+(per-device arrays: bus, cp, cq, cost, lo, hi, ramp, init_lo, init_hi).
 """
 from __future__ import annotations
 
@@ -60,7 +60,7 @@ class _Case(ctypes.Structure):
         ("stor_qmin", _dp), ("stor_qmax", _dp), ("stor_eta_c", _dp), ("stor_eta_d", _dp),
         ("stor_r", _dp), ("stor_x", _dp), ("stor_ploss", _dp), ("stor_qloss", _dp), ("stor_e0", _dp),
         ("stor_dt", ctypes.c_double), ("stor_comp", ctypes.c_int32),
-        ("n_dev", ctypes.c_int32), ("dev_bus", _ip), ("dev_mask", _ip),
+        ("n_dev", ctypes.c_int32), ("dev_bus", _ip),
         ("dev_cp", _dp), ("dev_cq", _dp), ("dev_cost", _dp), ("dev_lo", _dp), ("dev_hi", _dp),
         ("dev_ramp", _dp), ("dev_init_lo", _dp), ("dev_init_hi", _dp),
     ]
@@ -148,7 +148,6 @@ def _make_case(case: dict, n_periods=1, pd_t=None, qd_t=None, ramp_ratio=0.0,
     if devices is not None and len(devices["bus"]) > 0:
         c.n_dev = len(devices["bus"])
         c.dev_bus = i(devices["bus"])
-        c.dev_mask = i(devices["mask"])
         for k in DEV_FIELDS:
             setattr(c, "dev_" + k, d(devices[k]))
     return c, keep

@@ -268,14 +268,13 @@ def storage(case: dict, seed, frac: float = 0.1, loads=None) -> dict:
 def devices(case: dict, n_dev: int, seed) -> dict:
     """Linear user-extension devices shaped like the electrolyzers of the
     paper's user-extension example (Sec. III-D): buses uniform with
-    replacement, a load on the active balance (cp = 1, mask 1), every third
-    device also on the reactive balance (mask 3, cq ~ U(0.1, 0.3)), a
-    negative cost ~ U(-50, -10) (hydrogen revenue), power in [0, 0.5],
-    ramp limit 0.1 and an initial power of 0."""
+    replacement, a load on the active balance (cp = 1; cq = 0, except every
+    third device draws reactive power too, cq ~ U(0.1, 0.3)), a negative
+    cost ~ U(-50, -10) (hydrogen revenue), power in [0, 0.5], ramp limit
+    0.1 and an initial power of 0."""
     rng = _rng(seed)
     bus = rng.integers(0, case["n_bus"], n_dev).astype(np.int32)
-    mask = np.where(np.arange(n_dev) % 3 == 2, 3, 1).astype(np.int32)
-    cq = np.where(mask == 3, rng.uniform(0.1, 0.3, n_dev), 0.0)
-    return dict(bus=bus, mask=mask, cp=np.ones(n_dev), cq=cq, cost=rng.uniform(-50.0, -10.0, n_dev),
+    cq = np.where(np.arange(n_dev) % 3 == 2, rng.uniform(0.1, 0.3, n_dev), 0.0)
+    return dict(bus=bus, cp=np.ones(n_dev), cq=cq, cost=rng.uniform(-50.0, -10.0, n_dev),
                 lo=np.zeros(n_dev), hi=np.full(n_dev, 0.5), ramp=np.full(n_dev, 0.1), init_lo=np.zeros(n_dev),
                 init_hi=np.zeros(n_dev))

@@ -134,12 +134,11 @@ def test_balance_gains_storage_and_device_terms():
     xb0, cb0, _ = _layout(cs, base_opts)
     st, dv = opts["storage"], opts["devices"]
     ps, qs, u = (_blk(x, xb, k).reshape(T, -1) for k in ("ps", "qs", "u"))
-    for row, draw, coef, bit in (("balp", ps, dv["cp"], 1), ("balq", qs, dv["cq"], 2)):
+    for row, draw, coef in (("balp", ps, dv["cp"]), ("balq", qs, dv["cq"])):
         add = np.zeros((T, N))
         for t in range(T):
             np.add.at(add[t], st["bus"], draw[t])
-            on = (dv["mask"] & bit) != 0
-            np.add.at(add[t], dv["bus"][on], coef[on] * u[t, on])
+            np.add.at(add[t], dv["bus"], coef * u[t])
         got = _blk(r_ext["c"], cb, row).reshape(T, N) - _blk(r_base["c"], cb0, row).reshape(T, N)
         np.testing.assert_allclose(got, add, rtol=1e-12, atol=1e-14, err_msg=row)
     # device rows and objective
@@ -208,9 +207,11 @@ def test_ext_hessian_matches_finite_differences(kw):
 
 def test_ext_pattern_closed_form():
     """Added to the base counts per period: storage J 4 (soc; 3 at t = 0)
-    + 5 + 4 + 2 (+ 2 complementarity) per unit and 1 per balance row it
-    enters; H 5 + 2 (ps, qs, vm diagonals merged) ... written out below;
-    devices J 1 per balance row they enter, 2 per ramp row, 1 initial row."""
+    + 5 + 4 + 2 (+ 2 complementarity) per unit and 1 in each balance row;
+    H 5 per unit ((ps, ps), (qs, qs), (ps, vm), (qs, vm), (sd, sc); the
+    (vm, vm) term merges into the bus diagonal); devices J 1 in each balance
+    row (structural, zero coefficients included), 2 per ramp row, 1 per
+    initial row."""
     cs, opts = _ext_case(T=4)
     T, S, D = 4, len(opts["storage"]["bus"]), len(opts["devices"]["bus"])
     base = {k: v for k, v in opts.items() if k not in ("storage", "stor_dt", "stor_comp", "devices")}
@@ -218,8 +219,7 @@ def test_ext_pattern_closed_form():
     m = O.dims(cs, **opts)[1]
     r = O.evaluate(cs, x, synth.multipliers(m, 9), 1.0, **opts)
     r0 = O.evaluate(cs, x[:O.dims(cs, **base)[0]], synth.multipliers(O.dims(cs, **base)[1], 9), 1.0, **base)
-    nmask = int(((opts["devices"]["mask"] & 1) != 0).sum() + ((opts["devices"]["mask"] & 2) != 0).sum())
-    dj = T * S * (4 + 5 + 4 + 2 + 2 + 2) - S + T * nmask + 2 * D * (T - 1) + D
+    dj = T * S * (4 + 5 + 4 + 2 + 2 + 2) - S + T * 2 * D + 2 * D * (T - 1) + D
     assert r["jrow"].size - r0["jrow"].size == dj
     # H: per unit and period (ps,ps) (qs,qs) (ps,vm) (qs,vm) (sd,sc); (vm,vm) merges with the bus diagonal
     assert r["hrow"].size - r0["hrow"].size == T * S * 5
