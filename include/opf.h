@@ -46,6 +46,11 @@
  *    balance_q    qd - bs vm^2 + sum_arcs q_a - sum_gens qg = 0
  *    thermal      p_a^2 + q_a^2 - rate_a^2                 <= 0
  *    ramp         pg_{k,t} - pg_{k,t-1}     in +-ramp_ratio * pmax_k
+ *  and then the storage rows soc | loss_p | loss_q | thermal | (comp) and
+ *  the device rows ramp [D*(T-1)] | init [D] (opf_storage, opf_devices),
+ *  each entity-fastest over the periods.  Storage units and devices add
+ *  the variable blocks ps | qs | qsc | se | sc | sd | u after q, and their
+ *  terms +ps, +cp u (+qs, +cq u) to the balance rows of their bus.
  *  In contingency copy s >= 1 the branch outaged_branch[s-1] carries no
  *  flow (its admittance terms are zero; its rows and pattern entries stay)
  *  and its angle row is unbounded.
@@ -97,6 +102,42 @@ typedef struct {
  * per side, an ideal transformer of ratio tap and phase shift `shift`
  * (radians) on the from side. */
 
+/* Storage units (Sec. III-C3: the multi-period model with storage; its
+ * formulation is the storage model of Geth, Coffrin and Fobes 2020 that the
+ * paper cites).  Per unit u at bus i and period t the variables are ps, qs
+ * (the power the unit draws from the grid, a load in the balance rows),
+ * qsc (the converter's reactive set-point), se (stored energy), sc, sd
+ * (charging and discharging power), with bounds ps, qsc in +-rating,
+ * qs in [qmin, qmax], se in [0, emax], sc in [0, chmax], sd in [0, dismax];
+ * and the rows
+ *   soc     se_t - se_{t-1} - dt (eta_c sc_t - sd_t / eta_d) = 0
+ *           (se_{-1} = e0, the initial energy)
+ *   loss_p  ps + sd - sc - ploss - r (ps^2 + qs^2) / vm_i^2   = 0
+ *   loss_q  qs - qsc - qloss - x (ps^2 + qs^2) / vm_i^2       = 0
+ *   thermal ps^2 + qs^2 - rating^2                           <= 0
+ *   comp    sc sd <= 0 (with sc, sd >= 0: sc sd = 0)  only if comp != 0
+ * Polar form only; not combined with contingency copies. */
+typedef struct {
+    int32_t n;                  /* units                                    */
+    const int32_t *bus;         /* [n]                                      */
+    const double *emax, *chmax, *dismax, *rating, *qmin, *qmax;    /* [n]   */
+    const double *eta_c, *eta_d, *r, *x, *ploss, *qloss, *e0;      /* [n]   */
+    double dt;                  /* duration of one period                   */
+    int32_t comp;               /* 1: add the complementarity rows          */
+} opf_storage;
+
+/* User-extension devices (Sec. III-D: components a user adds to a built
+ * model, the electrolyzer example of Listing 10), linear: per device d at
+ * bus i and period t one variable u in [lo, hi]; the objective gains
+ * cost u; the balance rows of bus i gain cp u (active) and cq u (reactive),
+ * both entries structural; rows ramp u_t - u_{t-1} in +-ramp (t >= 1) and
+ * init u_0 in [init_lo, init_hi].  Not combined with contingency copies. */
+typedef struct {
+    int32_t n;                  /* devices                                  */
+    const int32_t *bus;         /* [n]                                      */
+    const double *cp, *cq, *cost, *lo, *hi, *ramp, *init_lo, *init_hi; /* [n] */
+} opf_devices;
+
 typedef struct {
     int32_t n_periods;          /* >= 1; 1 = static model                   */
     const double *pd_t, *qd_t;  /* [n_periods*n_bus] bus fastest; NULL =    */
@@ -106,6 +147,8 @@ typedef struct {
                                 /* combined with n_periods > 1              */
     const int32_t *outaged_branch; /* [n_cont] branch out in copy s+1       */
     int32_t form;               /* OPF_FORM_POLAR (0) or OPF_FORM_RECT (1)  */
+    const opf_storage *storage; /* NULL = none                              */
+    const opf_devices *devices; /* NULL = none                              */
 } opf_opts;
 /* opts may be NULL: static polar model.
  *
@@ -200,7 +243,10 @@ enum {
     OPF_CON_ANGLE, OPF_CON_BAL_P, OPF_CON_BAL_Q, OPF_CON_THERMAL_FR,
     OPF_CON_THERMAL_TO, OPF_CON_RAMP,
     OPF_CON_ANGLE_LO, OPF_CON_VMAG,         /* rectangular form (empty in polar) */
-    OPF_VAR_VR = OPF_VAR_VA, OPF_VAR_VI = OPF_VAR_VM  /* rectangular bus blocks */
+    OPF_VAR_VR = OPF_VAR_VA, OPF_VAR_VI = OPF_VAR_VM,  /* rectangular bus blocks */
+    OPF_VAR_PS = 6, OPF_VAR_QS, OPF_VAR_QSC, OPF_VAR_SE, OPF_VAR_SC, OPF_VAR_SD, OPF_VAR_U,
+    OPF_CON_SOC = 29, OPF_CON_STOR_LOSS_P, OPF_CON_STOR_LOSS_Q, OPF_CON_STOR_THERMAL, OPF_CON_STOR_COMP,
+    OPF_CON_DEV_RAMP, OPF_CON_DEV_INIT
 };
 int opf_model_blocks(opf_model model, int32_t which, int64_t *offset, int64_t *len);
 

@@ -52,7 +52,8 @@ namespace {
 bool valid(const opf_batch_s* b) { return b && b->magic == kBatchMagic; }
 
 // Work items of one phase, one replica each.  Phase 1: the branch chunks,
-// then (callback set) the generator chunks of every instance.  Phase 2: big
+// then (callback set) the generator chunks, then the storage and device
+// chunks of every instance.  Phase 2: big
 // buses first (the longest), then the waves of bus segments of every
 // instance, then one objective item per instance (callback set) or the
 // generator items (J^T v; on a model whose copies share pg, one generator
@@ -68,6 +69,9 @@ void make_items(const std::vector<opf::DevModel>& dms, int mode, int phase, std:
         for (int32_t j = 0; j < n; j++) each(dms[j], opf::T_BRANCH, dms[j].nbchunks, j);
         if (mode == 0)
             for (int32_t j = 0; j < n; j++) each(dms[j], opf::T_GEN, dms[j].ngchunks, j);
+        // storage units and devices (their own rows; J^T v: their entries)
+        for (int32_t j = 0; j < n; j++) each(dms[j], opf::T_STOR, dms[j].nschunks, j);
+        for (int32_t j = 0; j < n; j++) each(dms[j], opf::T_DEV, dms[j].ndchunks, j);
         return;
     }
     for (int32_t j = 0; j < n; j++) each(dms[j], opf::T_BIG, dms[j].nbig, j);

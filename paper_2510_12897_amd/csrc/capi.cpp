@@ -98,6 +98,14 @@ ModelOffsets pack_model(Packer& pk, const opf::HostModel& hm) {
     o.outage = pk.add(hm.outage);
     o.slots_c = pk.add(hm.slots_c);
     o.tan_lim = pk.add(hm.tan_lim);
+    o.stor_bus = pk.add(hm.stor_bus);
+    o.stor_par = pk.add(hm.stor_par);
+    o.dev_bus = pk.add(hm.dev_bus);
+    o.dev_par = pk.add(hm.dev_par);
+    o.st_ptr = pk.add(hm.st_ptr);
+    o.st_list = pk.add(hm.st_list);
+    o.dv_ptr = pk.add(hm.dv_ptr);
+    o.dv_list = pk.add(hm.dv_list);
     return o;
 }
 
@@ -111,7 +119,7 @@ size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 }  // namespace
 
 void attach_scratch(opf::DevModel& d, char* scratch) {
-    const size_t parts = round256(sizeof(double) * (size_t)d.ngchunks * d.npg);
+    const size_t parts = round256(sizeof(double) * (size_t)opf::obj_slots(d));
     d.obj_part = reinterpret_cast<double*>(scratch);
     d.obj_ticket = reinterpret_cast<int32_t*>(scratch + parts);
     d.rec = reinterpret_cast<double*>(scratch + parts + 256);
@@ -130,7 +138,12 @@ opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets&
     d.ngchunks = gen_chunks(hm);
     // one launch per callback set when the whole set is a few waves per
     // compute unit (the launch is latency-bound)
-    const int64_t waves = (int64_t)ly.nrep * (d.nbchunks + d.nwaves + d.nbig) + (int64_t)d.ngchunks * ly.nrep;
+    d.S = ly.S;
+    d.D = ly.D;
+    d.nschunks = (ly.S + opf::kBlock - 1) / opf::kBlock;
+    d.ndchunks = (ly.D + opf::kBlock - 1) / opf::kBlock;
+    d.comp = ly.comp;
+    const int64_t waves = (int64_t)ly.nrep * (d.nbchunks + d.nwaves + d.nbig + d.ngchunks + d.nschunks + d.ndchunks);
     const int64_t limit = single_launch_limit();
     d.single = (limit > 0 && waves <= limit) ? 1 : 0;
     d.x_va = ly.x_va; d.x_vm = ly.x_vm; d.x_pg = ly.x_pg; d.x_qg = ly.x_qg; d.x_p = ly.x_p; d.x_q = ly.x_q;
@@ -152,6 +165,15 @@ opf::DevModel make_dev(const opf::HostModel& hm, char* base, const ModelOffsets&
     P32(gen_ptr); P32(gen_list); PDB(gs); PDB(bs); PDB(pd); PDB(qd);
     PDB(c2); PDB(c1); PDB(c0); P32(gen_bus); P32(ref_bus); P32(ref_ptr); P32(ref_list); P32(outage); P32(slots_c);
     PDB(tan_lim);
+    P32(stor_bus); PDB(stor_par); P32(dev_bus); PDB(dev_par); P32(st_ptr); P32(st_list); P32(dv_ptr); P32(dv_list);
+    d.x_ps = ly.x_ps; d.x_qs = ly.x_qs; d.x_qsc = ly.x_qsc; d.x_se = ly.x_se; d.x_sc = ly.x_sc; d.x_sd = ly.x_sd;
+    d.x_u = ly.x_u;
+    d.c_soc = ly.c_blk[B_SOC]; d.c_slp = ly.c_blk[B_SLP]; d.c_slq = ly.c_blk[B_SLQ]; d.c_sth = ly.c_blk[B_STH];
+    d.c_scmp = ly.c_blk[B_SCMP]; d.c_dramp = ly.c_blk[B_DRAMP]; d.c_dinit = ly.c_blk[B_DINIT];
+    d.j_soc = ly.j_blk[B_SOC]; d.j_slp = ly.j_blk[B_SLP]; d.j_slq = ly.j_blk[B_SLQ]; d.j_sth = ly.j_blk[B_STH];
+    d.j_scmp = ly.j_blk[B_SCMP]; d.j_dramp = ly.j_blk[B_DRAMP]; d.j_dinit = ly.j_blk[B_DINIT];
+    d.h_ps = ly.h_ps; d.h_qs = ly.h_qs; d.h_sd = ly.h_sd;
+    d.stor_dt = hm.stor_dt;
     d.rect = ly.rect;
     d.c_angl = ly.c_blk[B_ANGL]; d.c_vmag = ly.c_blk[B_VMAG];
     d.j_angl = ly.j_blk[B_ANGL]; d.j_vmag = ly.j_blk[B_VMAG];
@@ -350,7 +372,7 @@ int opf_model_launches(opf_model m, int32_t* launches, int64_t* items) {
     const opf::DevModel& d = m->dm;
     if (launches) *launches = d.single ? 1 : 2;
     if (items)
-        *items = (int64_t)d.nrep * ((int64_t)d.nbchunks + d.nwaves + d.nbig) + (int64_t)d.ngchunks * d.nrep;
+        *items = (int64_t)d.nrep * ((int64_t)d.nbchunks + d.nwaves + d.nbig + d.ngchunks + d.nschunks + d.ndchunks);
     return OPF_OK;
 }
 
@@ -366,12 +388,19 @@ int opf_model_blocks(opf_model m, int32_t which, int64_t* offset, int64_t* len) 
     case OPF_VAR_QG: o = ly.x_qg; l = ly.G * P; break;
     case OPF_VAR_P: o = ly.x_p; l = 2LL * ly.L * P; break;
     case OPF_VAR_Q: o = ly.x_q; l = 2LL * ly.L * P; break;
+    case OPF_VAR_PS: o = ly.x_ps; l = (int64_t)ly.S * P; break;
+    case OPF_VAR_QS: o = ly.x_qs; l = (int64_t)ly.S * P; break;
+    case OPF_VAR_QSC: o = ly.x_qsc; l = (int64_t)ly.S * P; break;
+    case OPF_VAR_SE: o = ly.x_se; l = (int64_t)ly.S * P; break;
+    case OPF_VAR_SC: o = ly.x_sc; l = (int64_t)ly.S * P; break;
+    case OPF_VAR_SD: o = ly.x_sd; l = (int64_t)ly.S * P; break;
+    case OPF_VAR_U: o = ly.x_u; l = (int64_t)ly.D * P; break;
     default: {
         using namespace opf;
         // OPF_CON_* ids in header order -> constraint blocks
-        static const int kBlk[] = {B_REF, B_PFR, B_QFR, B_PTO, B_QTO, B_ANG, B_BALP, B_BALQ,
-                                   B_THF, B_THT, B_RAMP, B_ANGL, B_VMAG};
-        if (which >= OPF_CON_REF && which <= OPF_CON_VMAG) {
+        static const int kBlk[] = {B_REF, B_PFR, B_QFR, B_PTO, B_QTO, B_ANG, B_BALP, B_BALQ, B_THF, B_THT, B_RAMP,
+                                   B_ANGL, B_VMAG, B_SOC, B_SLP, B_SLQ, B_STH, B_SCMP, B_DRAMP, B_DINIT};
+        if (which >= OPF_CON_REF && which <= OPF_CON_DEV_INIT) {
             const int b = kBlk[which - OPF_CON_REF];
             o = ly.c_blk[b];
             l = ly.c_blk[b + 1] - ly.c_blk[b];

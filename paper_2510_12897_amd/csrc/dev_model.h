@@ -17,7 +17,9 @@ enum TaskKind : int32_t {
     T_WAVE = 2,    // phase 2: 64 lanes of packed bus segments: balance rows, bus Hessian rows
     T_GEN = 3,     // phase 1: 64 generators: gradient, pg Hessian diagonal, objective partial, ref and
                    // ramp rows; J^T v: phase 2, the pg / qg entries
-    T_OBJ = 4      // phase 2 (two-launch models): the objective, summing the partials in index order
+    T_OBJ = 4,     // phase 2 (two-launch models): the objective, summing the partials in index order
+    T_STOR = 5,    // phase 1: 64 storage units: their rows, Jacobian and Hessian entries
+    T_DEV = 6      // phase 1: 64 devices: their rows, gradient and objective partial
 };
 
 // Half-edge record: what the branch phase leaves for the bus phase, per
@@ -40,6 +42,12 @@ constexpr int kRecStride = kRec;
 // A set without the Hessian needs only the arc values of each half-edge:
 // records [P, Q], 16 bytes apart, in the same per-side arrays.
 constexpr int kRecPQ = 2;
+
+// Storage parameters, stored [kStorPar][S] (structure of arrays).
+enum StorPar : int32_t { SP_EMAX = 0, SP_CHMAX, SP_DISMAX, SP_RATING, SP_QMIN, SP_QMAX, SP_ETAC, SP_ETAD, SP_R,
+                         SP_X, SP_PLOSS, SP_QLOSS, SP_E0, kStorPar };
+// Device parameters the kernels read, stored [kDevPar][D].
+enum DevPar : int32_t { DP_CP = 0, DP_CQ, DP_COST, kDevPar };
 
 constexpr int kBlock = 64;          // threads per workgroup (one wave), every task
 constexpr int kXcd = 8;             // XCDs; workgroups are dealt to them round-robin
@@ -108,7 +116,34 @@ struct DevModel {
     int32_t rect;
     int32_t c_angl, c_vmag, j_angl, j_vmag;
     const double* tan_lim;    // [2][L]: tan(angmax), tan(angmin)
+    // storage units and user-extension devices (S, D; their blocks of x, c,
+    // J, H; per-bus lists for the wide-bus task).  Objective partials: the
+    // generator chunks' (ngchunks * npg), then the device chunks'
+    // (ndchunks * nrep).
+    int32_t S, D, nschunks, ndchunks, comp;
+    int32_t x_ps, x_qs, x_qsc, x_se, x_sc, x_sd, x_u;
+    int32_t c_soc, c_slp, c_slq, c_sth, c_scmp, c_dramp, c_dinit;
+    int32_t j_soc, j_slp, j_slq, j_sth, j_scmp, j_dramp, j_dinit;
+    int32_t h_ps, h_qs, h_sd;
+    double stor_dt;
+    const int32_t* stor_bus;  // [S]
+    const double* stor_par;   // [kStorPar][S]
+    const int32_t* dev_bus;   // [D]
+    const double* dev_par;    // [kDevPar][D]
+    const int32_t* st_ptr;    // [N+1] storage units per bus, ascending
+    const int32_t* st_list;
+    const int32_t* dv_ptr;    // [N+1] devices per bus, ascending
+    const int32_t* dv_list;
 };
+
+// Objective partials of a model: one per generator chunk and pg replica,
+// then one per device chunk and replica.
+#if defined(__HIP__)
+__attribute__((host, device))
+#endif
+inline int32_t obj_slots(const DevModel& m) {
+    return m.ngchunks * m.npg + m.ndchunks * m.nrep;
+}
 
 struct EvalOut {
     int32_t single;  // this launch is the single-launch shape (bus items recompute, f by ticket)
@@ -128,10 +163,11 @@ struct EvalOut {
 // set) or the generator items (J^T v).
 struct SetGrid {
     int32_t n_branch, n_gen1;         // phase 1 items
+    int32_t n_stor, n_dev;            // phase 1 items (after the generators)
     int32_t n_big, n_wave, n_obj;     // phase 2 bus items and the objective item (0 or 1)
     int32_t n_gen2;                   // phase 2 generator items (J^T v)
     int32_t gen_per_item;             // J^T v: 0 = chunks of kBlock generators; 1 = one generator a wave
-    int32_t phase1() const { return n_branch + n_gen1; }
+    int32_t phase1() const { return n_branch + n_gen1 + n_stor + n_dev; }
     int32_t phase2() const { return n_big + n_wave + n_obj + n_gen2; }
 };
 

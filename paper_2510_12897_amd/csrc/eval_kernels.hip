@@ -387,6 +387,21 @@ __device__ __forceinline__ void rect_edge_record(const DevModel& m, const EvalOu
     }
 }
 
+// The (vm, vm) Hessian term of a storage unit's loss rows at its bus:
+// -(y_lp r + y_lq x) d2 i2 / dvm2 with d2 i2 / dvm2 = 6 S2 / vm^4.
+__device__ __forceinline__ double stor_vmvm(double ps, double qs, double vm, double ylp, double ylq, double rr,
+                                            double xx) {
+    const double iv2 = 1.0 / (vm * vm);
+    return -(ylp * rr + ylq * xx) * 6.0 * (ps * ps + qs * qs) * iv2 * iv2;
+}
+
+// The vm entry of J^T v from a storage unit's loss rows:
+// (v_lp r + v_lq x) 2 S2 / vm^3.
+__device__ __forceinline__ double jt_stor_vm(double ps, double qs, double vm, double vlp, double vlq, double rr,
+                                             double xx) {
+    return (vlp * rr + vlq * xx) * 2.0 * (ps * ps + qs * qs) / (vm * vm * vm);
+}
+
 // ================================================================== phase 1
 template <bool SINGLE>
 __device__ void branch_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r, double* stage) {
@@ -826,10 +841,37 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
             } else if (wantC) {  // compact records [P, Q]
                 rc = ld(rec, ref);
             }
+        } else if (type == SK_GEN && (kind & 4)) {
+            // a storage unit: ps, qs (and for its (vm, vm) term the loss
+            // rows' multipliers and r, x), held in the generator / head
+            // registers (gp, gq, yp, yq, gs, bs), which a lane of another
+            // type does not use
+            const int64_t S = m.S;
+            if (wantC || wantH) {
+                gp = ld(o.x + m.x_ps + S * r, ref);
+                gq = ld(o.x + m.x_qs + S * r, ref);
+            }
+            if (wantH) {
+                yp = ld(o.y + m.c_slp + S * r, ref);
+                yq = ld(o.y + m.c_slq + S * r, ref);
+                gs = ld(m.stor_par + SP_R * S, ref);
+                bs = ld(m.stor_par + SP_X * S, ref);
+            }
+        } else if (type == SK_GEN && (kind & 16)) {
+            // a device: u and its balance coefficients cp, cq
+            const int64_t D = m.D;
+            if (wantC) gp = ld(o.x + m.x_u + D * r, ref);
+            if (wantC || o.J) {
+                gs = ld(m.dev_par + DP_CP * D, ref);
+                bs = ld(m.dev_par + DP_CQ * D, ref);
+            }
         } else if (type == SK_GEN && wantC) {
             gp = ld(o.x + m.x_pg + G * (m.npg > 1 ? r : 0), ref);
             gq = ld(o.x + m.x_qg + G * r, ref);
         }
+        // a storage lane's (vm, vm) term needs its bus's vm: the head's
+        double vm_h = 0.0;
+        if (wantH && m.S > 0) vm_h = __shfl(vm_i, SINGLE ? (sl.other & 63) : ((kind >> 14) & 63), kBlock);
         double v[kRec] = {0, 0, 0, 0, 0, 0};
         double base_p = 0.0, base_q = 0.0, shunt = 0.0;
         if (type == SK_HEAD) {
@@ -855,6 +897,17 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
             if (wantC) {
                 v[R_P] = rc.x;
                 v[R_Q] = rc.y;
+            }
+        } else if (type == SK_GEN && (kind & 4)) {  // storage: +ps, +qs
+            if (wantC) {
+                v[R_P] = gp;
+                v[R_Q] = gq;
+            }
+            if (wantH) v[R_MM] = stor_vmvm(gp, gq, vm_h, yp, yq, gs, bs);
+        } else if (type == SK_GEN && (kind & 16)) {  // device: +cp u, +cq u
+            if (wantC) {
+                v[R_P] = gs * gp;
+                v[R_Q] = bs * gp;
             }
         } else if (type == SK_GEN && wantC) {
             v[R_P] = -gp;
@@ -965,8 +1018,11 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
             if (type == SK_HEAD) {
                 vp = 2.0 * gs * vm_i;
                 vq = -2.0 * bs * vm_i;
-            } else {
-                vp = vq = (type == SK_EDGE) ? 1.0 : -1.0;
+            } else if (type == SK_GEN && (kind & 16)) {  // device: cp, cq
+                vp = gs;
+                vq = bs;
+            } else {  // arcs and storage units +1, generators -1
+                vp = vq = (type == SK_EDGE || (kind & 4)) ? 1.0 : -1.0;
             }
             if (RECT && type == SK_HEAD) {
                 // (vr_i, vi_i) of both balance rows, then the magnitude row
@@ -1016,6 +1072,16 @@ __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int
         int32_t q0, q1;
         if (type == SK_EDGE) {
             t = ld(reinterpret_cast<const double2*>(jt_rec_side(m, r, (int32_t)side)), ref);
+        } else if (type == SK_GEN && (sc.x & 4)) {
+            // a storage unit's loss rows: ps, qs, their multipliers, r, x
+            // (in the registers of the head's loads)
+            const int64_t S = m.S;
+            vr = ld(x + m.x_ps + S * r, ref);
+            vg = ld(x + m.x_qs + S * r, ref);
+            vp = ld(v + m.c_slp + S * r, ref);
+            vq = ld(v + m.c_slq + S * r, ref);
+            gs = ld(m.stor_par + SP_R * S, ref);
+            bs = ld(m.stor_par + SP_X * S, ref);
         } else if (type == SK_HEAD) {
             vm = ld(x + m.x_vm + on, bus);  // rectangular: vi
             if (RECT) {
@@ -1029,8 +1095,11 @@ __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int
             q0 = ld(m.ref_ptr, bus);
             q1 = ld(m.ref_ptr, bus + 1);
         }
+        double vm_h = 0.0;
+        if (m.S > 0) vm_h = __shfl(vm, (sc.x >> 14) & 63, kBlock);
+        const bool stor = type == SK_GEN && (sc.x & 4);
         lds[0 * kBlock + lane] = type == SK_EDGE ? t.x : 0.0;
-        lds[1 * kBlock + lane] = type == SK_EDGE ? t.y : 0.0;
+        lds[1 * kBlock + lane] = type == SK_EDGE ? t.y : stor ? jt_stor_vm(vr, vg, vm_h, vp, vq, gs, bs) : 0.0;
         __syncthreads();
         if (type == SK_HEAD) {
             double sa = 0.0, sm = 0.0;
@@ -1162,13 +1231,30 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
                         cp -= x[pgb + m.gen_list[g0 + q]];
                         cq -= x[qgb + m.gen_list[g0 + q]];
                     }
+                    for (int32_t q = m.st_ptr[b]; q < m.st_ptr[b + 1]; q++) {  // storage draws
+                        const int64_t e = m.st_list[q] + (int64_t)m.S * r;
+                        cp += x[m.x_ps + e];
+                        cq += x[m.x_qs + e];
+                    }
+                    for (int32_t q = m.dv_ptr[b]; q < m.dv_ptr[b + 1]; q++) {  // devices
+                        const int32_t d = m.dv_list[q];
+                        const double u = x[m.x_u + d + (int64_t)m.D * r];
+                        cp += m.dev_par[DP_CP * (int64_t)m.D + d] * u;
+                        cq += m.dev_par[DP_CQ * (int64_t)m.D + d] * u;
+                    }
                     o.c[m.c_balp + bi] = cp;
                     o.c[m.c_balq + bi] = cq;
                     if (RECT) o.c[m.c_vmag + bi] = v2;
                 }
                 if (wantH) {
-                    const double shunt = 2.0 * gs * o.y[m.c_balp + bi] - 2.0 * bs * o.y[m.c_balq + bi] +
-                                         (RECT ? 2.0 * o.y[m.c_vmag + bi] : 0.0);
+                    double shunt = 2.0 * gs * o.y[m.c_balp + bi] - 2.0 * bs * o.y[m.c_balq + bi] +
+                                   (RECT ? 2.0 * o.y[m.c_vmag + bi] : 0.0);
+                    for (int32_t q = m.st_ptr[b]; q < m.st_ptr[b + 1]; q++) {  // storage (vm, vm) terms
+                        const int32_t u = m.st_list[q];
+                        const int64_t e = u + (int64_t)m.S * r;
+                        shunt += stor_vmvm(x[m.x_ps + e], x[m.x_qs + e], vm, o.y[m.c_slp + e], o.y[m.c_slq + e],
+                                           m.stor_par[SP_R * (int64_t)m.S + u], m.stor_par[SP_X * (int64_t)m.S + u]);
+                    }
                     const int64_t hva = m.h_va + m.hva_rep * r + m.hva_off[b];
                     const int64_t hvm = m.h_vm + m.hvm_rep * r + m.hvm_off[b];
                     const int32_t nlo = m.nlo[b];
@@ -1200,6 +1286,19 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
                     Jp[q] = q == 0 ? 2.0 * gs * vm : (q <= ng ? -1.0 : 1.0);
                     Jq[q] = q == 0 ? -2.0 * bs * vm : (q <= ng ? -1.0 : 1.0);
                 }
+            }
+            // storage units (+1) and devices (cp, cq) follow the arcs
+            const int32_t nbv = RECT ? 2 : 1, ns = m.st_ptr[b + 1] - m.st_ptr[b];
+            const int32_t nd = m.dv_ptr[b + 1] - m.dv_ptr[b], q0 = nbv + ng + deg;
+            for (int32_t q = threadIdx.x; q < ns + nd; q += kBlock) {
+                double vp = 1.0, vq = 1.0;
+                if (q >= ns) {
+                    const int32_t d = m.dv_list[m.dv_ptr[b] + q - ns];
+                    vp = m.dev_par[DP_CP * (int64_t)m.D + d];
+                    vq = m.dev_par[DP_CQ * (int64_t)m.D + d];
+                }
+                Jp[q0 + q] = vp;
+                Jq[q0 + q] = vq;
             }
         }
         if (o.g && threadIdx.x == 0) {
@@ -1242,9 +1341,59 @@ __device__ void jt_big_task(const DevModel& m, const EvalOut& o, int32_t idx, in
             } else {
                 sa += sref;
                 sm += 2.0 * m.gs[b] * vm * vp - 2.0 * m.bs[b] * vm * vq;
+                for (int32_t q = m.st_ptr[b]; q < m.st_ptr[b + 1]; q++) {  // storage loss rows
+                    const int32_t u = m.st_list[q];
+                    const int64_t e = u + (int64_t)m.S * r;
+                    sm += jt_stor_vm(x[m.x_ps + e], x[m.x_qs + e], vm, v[m.c_slp + e], v[m.c_slq + e],
+                                     m.stor_par[SP_R * (int64_t)m.S + u], m.stor_par[SP_X * (int64_t)m.S + u]);
+                }
             }
             o.g[m.x_va + bi] = sa;
             o.g[m.x_vm + bi] = sm;
+        }
+    }
+}
+
+// One objective partial: the wave's terms summed in a fixed tree into
+// slot `slot` (generator chunks first, then device chunks; obj_slots).  Two
+// launches: a plain store, summed by the objective item after the launch
+// boundary.  One launch: the chunk whose arrival completes a self-resetting
+// ticket sums every partial in index order.  Partials and ticket are
+// device-coherent atomics; the ticket moves only after this wave's partial
+// store has completed (s_waitcnt 0).  An acquire-release ticket would also
+// write back and invalidate the whole XCD L2 for every chunk, which cost
+// 1.6 us of the 10k-bus set.
+template <bool SINGLE>
+__device__ __forceinline__ void obj_partial(const DevModel& m, const EvalOut& o, int64_t slot, double fk) {
+    const double s = wave_sum(fk);
+    if (!SINGLE) {
+        if (threadIdx.x == 0) m.obj_part[slot] = s;
+        return;
+    }
+    __shared__ int32_t last;
+    const int32_t total = obj_slots(m);
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&m.obj_part[slot], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const int32_t old = __hip_atomic_fetch_add(m.obj_ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = (old + 1 == total) ? 1 : 0;
+    }
+    __syncthreads();
+    if (last) {
+        // acquire at agent scope, once per launch (the last chunk only): the
+        // partials below are read after every other chunk's ticket
+        // increment, which each issued only once its own partial store had
+        // completed
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        double acc = 0.0;
+        for (int32_t q = threadIdx.x; q < total; q += kBlock)
+            acc += __hip_atomic_load(&m.obj_part[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        acc = wave_sum(acc);
+        if (threadIdx.x == 0) {
+            *o.f = acc;
+            __hip_atomic_store(m.obj_ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -1295,48 +1444,7 @@ __device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int
             if (o.c) st(o.c + m.c_ref + row0, k, var);
             if (o.J) st(o.J + m.j_ref + row0, k, 1.0);
         }
-        if (o.f && r < m.npg) {
-            const double s = wave_sum(fk);
-            const int64_t slot = chunk + (int64_t)m.ngchunks * r;
-            if (!SINGLE) {
-                if (threadIdx.x == 0) m.obj_part[slot] = s;
-            } else {
-                // single launch: the chunk whose arrival completes the
-                // self-resetting ticket sums every partial (index order).
-                // Partials and ticket are device-coherent atomics; the
-                // ticket moves only after this wave's partial store has
-                // completed (s_waitcnt 0).  An acquire-release ticket would
-                // also write back and invalidate the whole XCD L2 for every
-                // chunk, which cost 1.6 us of the 10k-bus set.
-                __shared__ int32_t last;
-                const int32_t total = m.ngchunks * m.npg;
-                if (threadIdx.x == 0) {
-                    __hip_atomic_store(&m.obj_part[slot], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                    __builtin_amdgcn_s_waitcnt(0);
-                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                    const int32_t old =
-                        __hip_atomic_fetch_add(m.obj_ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    last = (old + 1 == total) ? 1 : 0;
-                }
-                __syncthreads();
-                if (last) {
-                    // acquire at agent scope, once per launch (the last chunk
-                    // only): the partials below are read after every other
-                    // chunk's ticket increment, which each issued only once
-                    // its own partial store had completed
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    double acc = 0.0;
-                    for (int32_t q = threadIdx.x; q < total; q += kBlock)
-                        acc += __hip_atomic_load(&m.obj_part[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    acc = wave_sum(acc);
-                    if (threadIdx.x == 0) {
-                        *o.f = acc;
-                        __hip_atomic_store(m.obj_ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                }
-            }
-        }
+        if (o.f && r < m.npg) obj_partial<SINGLE>(m, o, chunk + (int64_t)m.ngchunks * r, fk);
     }
 }
 
@@ -1344,7 +1452,7 @@ __device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int
 // index order, then a fixed wave tree.
 __device__ void obj_task(const DevModel& m, const EvalOut& o) {
     if (o.f == nullptr) return;
-    const int32_t total = m.ngchunks * m.npg;
+    const int32_t total = obj_slots(m);
     double acc = 0.0;
     for (int32_t q = threadIdx.x; q < total; q += kBlock) acc += m.obj_part[q];
     acc = wave_sum(acc);
@@ -1383,6 +1491,178 @@ __device__ void jt_gen_task(const DevModel& m, const EvalOut& o, int32_t idx, in
     }
 }
 
+// ----------------------------------------------------- storage and devices
+// Storage units (the storage model of Geth, Coffrin and Fobes 2020 that the
+// paper cites, Sec. III-C3), one lane per unit and replica (period).  With
+// S2 = ps^2 + qs^2 and the squared converter current i2 = S2 / vm^2:
+//   soc     se - se_prev - dt (eta_c sc - sd / eta_d)     (se_prev = e0 at t = 0)
+//   loss_p  ps + sd - sc - ploss - r i2
+//   loss_q  qs - qsc - qloss - x i2
+//   thermal S2 - rating^2;  comp  sc sd
+// The unit's own rows, their Jacobian entries, its Hessian rows (ps, qs,
+// sd) and the zero gradient of its variables are written here; its
+// balance-row entries and its (vm, vm) Hessian term belong to its bus's
+// segment (a storage lane there).
+__device__ void stor_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r) {
+    const uint32_t u = (uint32_t)(chunk * kBlock) + threadIdx.x;
+    if (u >= (uint32_t)m.S) return;
+    const int64_t S = m.S, so = S * r;
+    const double* P = m.stor_par;
+    const double* x = o.x;
+    // every load before the first store
+    const uint32_t bus = (uint32_t)ld(m.stor_bus, u);
+    const double ps = ld(x + m.x_ps + so, u), qs = ld(x + m.x_qs + so, u);
+    const double qsc = ld(x + m.x_qsc + so, u), se = ld(x + m.x_se + so, u);
+    const double sc = ld(x + m.x_sc + so, u), sd = ld(x + m.x_sd + so, u);
+    const double se0 = r >= 1 ? ld(x + m.x_se + so - S, u) : ld(P + SP_E0 * S, u);
+    const double vm = ld(x + m.x_vm + (int64_t)m.N * r, bus);
+    const double etac = ld(P + SP_ETAC * S, u), etad = ld(P + SP_ETAD * S, u);
+    const double rr = ld(P + SP_R * S, u), xx = ld(P + SP_X * S, u);
+    const double pls = ld(P + SP_PLOSS * S, u), qls = ld(P + SP_QLOSS * S, u), rat = ld(P + SP_RATING * S, u);
+    double ylp = 0.0, ylq = 0.0, yth = 0.0, ycm = 0.0;
+    if (o.H) {
+        ylp = ld(o.y + m.c_slp + so, u);
+        ylq = ld(o.y + m.c_slq + so, u);
+        yth = ld(o.y + m.c_sth + so, u);
+        if (m.comp) ycm = ld(o.y + m.c_scmp + so, u);
+    }
+    const double dt = m.stor_dt;
+    const double iv2 = 1.0 / (vm * vm), iv3 = iv2 / vm;
+    const double S2 = ps * ps + qs * qs, i2 = S2 * iv2;
+    const uint32_t e = (uint32_t)so + u;
+    if (o.c) {
+        st(o.c + m.c_soc, e, se - se0 - dt * (etac * sc - sd / etad));
+        st(o.c + m.c_slp, e, ps + sd - sc - pls - rr * i2);
+        st(o.c + m.c_slq, e, qs - qsc - qls - xx * i2);
+        st(o.c + m.c_sth, e, S2 - rat * rat);
+        if (m.comp) st(o.c + m.c_scmp, e, sc * sd);
+    }
+    if (o.J) {
+        // columns ascending: soc [se_prev], se, sc, sd; loss_p vm, ps, qs, sc,
+        // sd; loss_q vm, ps, qs, qsc; thermal ps, qs; comp sc, sd
+        if (r >= 1) {
+            const uint32_t j = (uint32_t)(3 * S + 4 * S * (r - 1)) + 4 * u;
+            st(o.J + m.j_soc, j, -1.0);
+            st(o.J + m.j_soc, j + 1, 1.0);
+            st(o.J + m.j_soc, j + 2, -dt * etac);
+            st(o.J + m.j_soc, j + 3, dt / etad);
+        } else {
+            st(o.J + m.j_soc, 3 * u, 1.0);
+            st(o.J + m.j_soc, 3 * u + 1, -dt * etac);
+            st(o.J + m.j_soc, 3 * u + 2, dt / etad);
+        }
+        const double dvm = 2.0 * S2 * iv3;  // d i2 / d vm = -dvm
+        st(o.J + m.j_slp, 5 * e, rr * dvm);
+        st(o.J + m.j_slp, 5 * e + 1, 1.0 - 2.0 * rr * ps * iv2);
+        st(o.J + m.j_slp, 5 * e + 2, -2.0 * rr * qs * iv2);
+        st(o.J + m.j_slp, 5 * e + 3, -1.0);
+        st(o.J + m.j_slp, 5 * e + 4, 1.0);
+        st(o.J + m.j_slq, 4 * e, xx * dvm);
+        st(o.J + m.j_slq, 4 * e + 1, -2.0 * xx * ps * iv2);
+        st(o.J + m.j_slq, 4 * e + 2, 1.0 - 2.0 * xx * qs * iv2);
+        st(o.J + m.j_slq, 4 * e + 3, -1.0);
+        st(o.J + m.j_sth, 2 * e, 2.0 * ps);
+        st(o.J + m.j_sth, 2 * e + 1, 2.0 * qs);
+        if (m.comp) {
+            st(o.J + m.j_scmp, 2 * e, sd);
+            st(o.J + m.j_scmp, 2 * e + 1, sc);
+        }
+    }
+    if (o.H) {
+        // the loss rows weigh -i2 by w; d2 i2 / dps2 = 2 / vm^2,
+        // d2 i2 / (dps dvm) = -4 ps / vm^3
+        const double w = ylp * rr + ylq * xx;
+        st(o.H + m.h_ps, 2 * e, 4.0 * w * ps * iv3);
+        st(o.H + m.h_ps, 2 * e + 1, -2.0 * w * iv2 + 2.0 * yth);
+        st(o.H + m.h_qs, 2 * e, 4.0 * w * qs * iv3);
+        st(o.H + m.h_qs, 2 * e + 1, -2.0 * w * iv2 + 2.0 * yth);
+        if (m.comp) st(o.H + m.h_sd, e, ycm);
+    }
+    if (o.g) {
+        st(o.g + m.x_ps + so, u, 0.0);
+        st(o.g + m.x_qs + so, u, 0.0);
+        st(o.g + m.x_qsc + so, u, 0.0);
+        st(o.g + m.x_se + so, u, 0.0);
+        st(o.g + m.x_sc + so, u, 0.0);
+        st(o.g + m.x_sd + so, u, 0.0);
+    }
+}
+
+// User-extension devices (Sec. III-D), one lane per device and replica:
+// the gradient (cost), the ramp row (t >= 1) or the initial row (t = 0) and
+// the device chunk's objective partial.  Balance entries: the bus segment.
+template <bool SINGLE>
+__device__ void dev_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r) {
+    const uint32_t d = (uint32_t)(chunk * kBlock) + threadIdx.x;
+    const bool act = d < (uint32_t)m.D;
+    const int64_t D = m.D, od = D * r;
+    double fk = 0.0;
+    if (act) {
+        const double u = ld(o.x + m.x_u + od, d);
+        const double cost = ld(m.dev_par + DP_COST * D, d);
+        const double up = r >= 1 ? ld(o.x + m.x_u + od - D, d) : 0.0;
+        fk = cost * u;
+        if (o.g) st(o.g + m.x_u + od, d, cost);
+        if (r >= 1) {
+            const uint32_t e = (uint32_t)(D * (r - 1)) + d;
+            if (o.c) st(o.c + m.c_dramp, e, u - up);
+            if (o.J) {
+                st(o.J + m.j_dramp, 2 * e, -1.0);
+                st(o.J + m.j_dramp, 2 * e + 1, 1.0);
+            }
+        } else {
+            if (o.c) st(o.c + m.c_dinit, d, u);
+            if (o.J) st(o.J + m.j_dinit, d, 1.0);
+        }
+    }
+    if (o.f) obj_partial<SINGLE>(m, o, (int64_t)m.ngchunks * m.npg + chunk + (int64_t)m.ndchunks * r, fk);
+}
+
+// J^T v of the storage units: each unit's six variable entries (its rows
+// and its balance-row entries +1 on ps, qs).
+__device__ void jt_stor_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r) {
+    const uint32_t u = (uint32_t)(chunk * kBlock) + threadIdx.x;
+    if (u >= (uint32_t)m.S) return;
+    const int64_t S = m.S, so = S * r, on = (int64_t)m.N * r;
+    const double* P = m.stor_par;
+    const double* x = o.x;
+    const double* v = o.y;
+    const uint32_t bus = (uint32_t)ld(m.stor_bus, u);
+    const double ps = ld(x + m.x_ps + so, u), qs = ld(x + m.x_qs + so, u);
+    const double sc = ld(x + m.x_sc + so, u), sd = ld(x + m.x_sd + so, u);
+    const double vm = ld(x + m.x_vm + on, bus);
+    const double etac = ld(P + SP_ETAC * S, u), etad = ld(P + SP_ETAD * S, u);
+    const double rr = ld(P + SP_R * S, u), xx = ld(P + SP_X * S, u);
+    const double vsoc = ld(v + m.c_soc + so, u);
+    const double vsoc1 = (r + 1 < m.nrep) ? ld(v + m.c_soc + so + S, u) : 0.0;
+    const double vlp = ld(v + m.c_slp + so, u), vlq = ld(v + m.c_slq + so, u), vth = ld(v + m.c_sth + so, u);
+    const double vcm = m.comp ? ld(v + m.c_scmp + so, u) : 0.0;
+    const double vbp = ld(v + m.c_balp + on, bus), vbq = ld(v + m.c_balq + on, bus);
+    const double iv2 = 1.0 / (vm * vm), dt = m.stor_dt;
+    st(o.g + m.x_ps + so, u, vlp * (1.0 - 2.0 * rr * ps * iv2) - vlq * 2.0 * xx * ps * iv2 + 2.0 * ps * vth + vbp);
+    st(o.g + m.x_qs + so, u, -vlp * 2.0 * rr * qs * iv2 + vlq * (1.0 - 2.0 * xx * qs * iv2) + 2.0 * qs * vth + vbq);
+    st(o.g + m.x_qsc + so, u, -vlq);
+    st(o.g + m.x_se + so, u, vsoc - vsoc1);
+    st(o.g + m.x_sc + so, u, -dt * etac * vsoc - vlp + vcm * sd);
+    st(o.g + m.x_sd + so, u, dt / etad * vsoc + vlp + vcm * sc);
+}
+
+// J^T v of the devices: balance coefficients, ramp and initial rows.
+__device__ void jt_dev_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r) {
+    const uint32_t d = (uint32_t)(chunk * kBlock) + threadIdx.x;
+    if (d >= (uint32_t)m.D) return;
+    const int64_t D = m.D, od = D * r, on = (int64_t)m.N * r;
+    const double* v = o.y;
+    const uint32_t bus = (uint32_t)ld(m.dev_bus, d);
+    const double cp = ld(m.dev_par + DP_CP * D, d), cq = ld(m.dev_par + DP_CQ * D, d);
+    const double vbp = ld(v + m.c_balp + on, bus), vbq = ld(v + m.c_balq + on, bus);
+    // u_r enters the ramp row of period r (+1), of period r + 1 (-1) and,
+    // at r = 0, the initial row
+    const double own = r >= 1 ? ld(v + m.c_dramp + od - D, d) : ld(v + m.c_dinit, d);
+    const double next = (r + 1 < m.nrep) ? ld(v + m.c_dramp + od, d) : 0.0;
+    st(o.g + m.x_u + od, d, cp * vbp + cq * vbq + own - next);
+}
+
 }  // namespace
 
 // ================================================================== dispatch
@@ -1397,16 +1677,24 @@ __device__ __forceinline__ void run_phase1(const DevModel& m, const EvalOut& o, 
     if (MODE == 0) {
         if (kind == T_GEN)
             gen_task<false, RECT>(m, o, idx, r);
+        else if (kind == T_STOR)
+            stor_task(m, o, idx, r);
+        else if (kind == T_DEV)
+            dev_task<false>(m, o, idx, r);
         else if (RECT)
             rbranch_task<false>(m, o, idx, r, stage);
         else
             branch_task<false>(m, o, idx, r, stage);
     } else if (MODE == 1) {
-        if (RECT)
+        if (kind == T_STOR)
+            jt_stor_task(m, o, idx, r);
+        else if (kind == T_DEV)
+            jt_dev_task(m, o, idx, r);
+        else if (RECT)
             rjt_branch_task(m, o, idx, r);
         else
             jt_branch_task(m, o, idx, r);
-    } else {
+    } else if (kind == T_BRANCH) {
         flows_task(m, o, idx, r);
     }
 }
@@ -1437,11 +1725,19 @@ __device__ __forceinline__ void decode_phase1(const SetGrid& g, const DevModel& 
         kind = T_BRANCH;
         idx = b % m.nbchunks;
         r = b / m.nbchunks;
-    } else {
-        b -= g.n_branch;
+    } else if ((b -= g.n_branch) < g.n_gen1) {
         kind = T_GEN;
         idx = b % m.ngchunks;
         r = b / m.ngchunks;
+    } else if ((b -= g.n_gen1) < g.n_stor) {
+        kind = T_STOR;
+        idx = b % m.nschunks;
+        r = b / m.nschunks;
+    } else {
+        b -= g.n_stor;
+        kind = T_DEV;
+        idx = b % m.ndchunks;
+        r = b / m.ndchunks;
     }
 }
 
@@ -1503,6 +1799,16 @@ __global__ void __launch_bounds__(kBlock) set_kernel_single(DevModel m, EvalOut 
         return;
     }
     b -= g.n_gen1;
+    if (b < g.n_stor) {
+        stor_task(m, o, b % m.nschunks, b / m.nschunks);
+        return;
+    }
+    b -= g.n_stor;
+    if (b < g.n_dev) {
+        dev_task<true>(m, o, b % m.ndchunks, b / m.ndchunks);
+        return;
+    }
+    b -= g.n_dev;
     if (b < g.n_big) {
         big_task<true, RECT>(m, o, b % m.nbig, b / m.nbig);
         return;
@@ -1624,6 +1930,8 @@ SetGrid plan_set(const DevModel& m, const EvalOut& o, int32_t mode) {
     const bool any = mode == 1 || o.g || o.c || o.J || o.H;
     g.n_branch = any ? m.nbchunks * m.nrep : 0;
     if (mode == 0 && (any || o.f)) g.n_gen1 = m.ngchunks * (any ? m.nrep : m.npg);  // f alone: pg replicas
+    g.n_stor = any ? m.nschunks * m.nrep : 0;
+    g.n_dev = (any || (mode == 0 && o.f)) ? m.ndchunks * m.nrep : 0;  // f alone: the devices' cost terms
     g.n_big = any ? m.nbig * m.nrep : 0;
     g.n_wave = any ? m.nwaves * m.nrep : 0;
     g.n_obj = (mode == 0 && o.f && !o.single) ? 1 : 0;  // a single launch sums f by ticket
@@ -1698,7 +2006,7 @@ void* batch_kernel_fn(int phase, int mode, bool flat, bool rect) {
 }
 
 size_t scratch_bytes(const DevModel& m) {
-    const size_t parts = ((sizeof(double) * (size_t)m.ngchunks * m.npg) + 255) & ~size_t(255);
+    const size_t parts = ((sizeof(double) * (size_t)obj_slots(m)) + 255) & ~size_t(255);
     return parts + 256 + sizeof(double) * (size_t)kRecStride * 2 * m.nrep * m.L;
 }
 

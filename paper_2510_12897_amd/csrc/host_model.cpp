@@ -40,6 +40,8 @@ int fail(std::string& err, int code, const char* fmt, long long a = 0, long long
 int32_t nperiods(const opf_opts* o) { return o ? o->n_periods : 1; }
 int32_t ncont(const opf_opts* o) { return o ? o->n_cont : 0; }
 int32_t form(const opf_opts* o) { return o ? o->form : OPF_FORM_POLAR; }
+int32_t nstor(const opf_opts* o) { return (o && o->storage) ? o->storage->n : 0; }
+int32_t ndev(const opf_opts* o) { return (o && o->devices) ? o->devices->n : 0; }
 
 }  // namespace
 
@@ -100,15 +102,48 @@ int validate(const opf_case* cs, const opf_opts* opts, std::string& err) {
                 return fail(err, OPF_E_CASE, "contingency %lld outages branch %lld, out of range", s,
                             opts->outaged_branch[s]);
     }
+    const int32_t S = nstor(opts), D = ndev(opts);
+    if (S < 0 || D < 0) return fail(err, OPF_E_CASE, "negative storage or device count");
+    if ((S > 0 || D > 0) && K > 0)
+        return fail(err, OPF_E_CASE, "storage units and devices cannot be combined with contingency copies");
+    if (S > 0) {
+        const opf_storage* st = opts->storage;
+        if (form(opts) != OPF_FORM_POLAR) return fail(err, OPF_E_CASE, "storage units take the polar form");
+        if (!st->bus || !st->emax || !st->chmax || !st->dismax || !st->rating || !st->qmin || !st->qmax ||
+            !st->eta_c || !st->eta_d || !st->r || !st->x || !st->ploss || !st->qloss || !st->e0)
+            return fail(err, OPF_E_ARG, "a storage array is NULL");
+        if (!(st->dt > 0.0) || !std::isfinite(st->dt)) return fail(err, OPF_E_CASE, "storage dt must be > 0");
+        for (int32_t u = 0; u < S; u++) {
+            if (st->bus[u] < 0 || st->bus[u] >= N)
+                return fail(err, OPF_E_CASE, "storage unit %lld has a bus out of range", u);
+            if (!(st->eta_c[u] > 0.0) || !(st->eta_d[u] > 0.0))
+                return fail(err, OPF_E_CASE, "storage unit %lld has a nonpositive efficiency", u);
+            if (!(st->qmin[u] <= st->qmax[u]) || !(st->emax[u] >= 0.0) || !(st->chmax[u] >= 0.0) ||
+                !(st->dismax[u] >= 0.0) || !(st->rating[u] >= 0.0))
+                return fail(err, OPF_E_CASE, "storage unit %lld has inconsistent ratings", u);
+        }
+    }
+    if (D > 0) {
+        const opf_devices* dv = opts->devices;
+        if (!dv->bus || !dv->cp || !dv->cq || !dv->cost || !dv->lo || !dv->hi || !dv->ramp || !dv->init_lo ||
+            !dv->init_hi)
+            return fail(err, OPF_E_ARG, "a device array is NULL");
+        for (int32_t d = 0; d < D; d++) {
+            if (dv->bus[d] < 0 || dv->bus[d] >= N)
+                return fail(err, OPF_E_CASE, "device %lld has a bus out of range", d);
+            if (!(dv->lo[d] <= dv->hi[d]) || !(dv->init_lo[d] <= dv->init_hi[d]))
+                return fail(err, OPF_E_CASE, "device %lld has lo > hi", d);
+        }
+    }
     // sizes must fit the int32 pattern indices
     const int64_t nrep = T > 1 ? T : (int64_t)K + 1;
     const int64_t npg = K > 0 ? 1 : nrep;
-    const int64_t n = nrep * (2LL * N + G + 4LL * L) + npg * G;
+    const int64_t n = nrep * (2LL * N + G + 4LL * L + 6LL * S + D) + npg * G;
     const bool rect = form(opts) == OPF_FORM_RECT;
     const int64_t m = nrep * (cs->n_ref + (rect ? 8LL : 7LL) * L + (rect ? 3LL : 2LL) * N) +
                       (T > 1 ? (int64_t)G * (T - 1) : 0);
     const int64_t nnzj = nrep * (cs->n_ref + (rect ? 36LL : 30LL) * L + (rect ? 6LL : 2LL) * N + 2LL * G) +
-                         2LL * G * (T - 1);
+                         2LL * G * (T - 1) + nrep * (19LL * S + 2LL * D) + 2LL * D * (T - 1) + D;
     const int64_t lim = std::numeric_limits<int32_t>::max();
     if (n >= lim || m >= lim || nnzj >= lim) return fail(err, OPF_E_CASE, "model too large for int32 indices");
     return OPF_OK;
@@ -271,6 +306,45 @@ int build_host_model(const opf_case* cs, const opf_opts* opts, HostModel& hm, st
     hm.outage.assign(P, -1);
     for (int32_t s = 0; s < K; s++) hm.outage[s + 1] = opts->outaged_branch[s];
 
+    // ---- storage units and devices
+    const int32_t S = nstor(opts), D = ndev(opts);
+    ly.S = S;
+    ly.D = D;
+    ly.comp = (S > 0 && opts->storage->comp) ? 1 : 0;
+    auto per_bus = [&](int32_t count, const std::vector<int32_t>& bus, std::vector<int32_t>& ptr,
+                       std::vector<int32_t>& list) {
+        ptr.assign(N + 1, 0);
+        for (int32_t e = 0; e < count; e++) ptr[bus[e] + 1]++;
+        for (int32_t i = 0; i < N; i++) ptr[i + 1] += ptr[i];
+        list.resize(count);
+        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        for (int32_t e = 0; e < count; e++) list[fill[bus[e]]++] = e;
+    };
+    if (S > 0) {
+        const opf_storage* st = opts->storage;
+        hm.stor_bus.assign(st->bus, st->bus + S);
+        const double* par[kStorPar] = {st->emax, st->chmax, st->dismax, st->rating, st->qmin, st->qmax, st->eta_c,
+                                       st->eta_d, st->r, st->x, st->ploss, st->qloss, st->e0};
+        hm.stor_par.resize((size_t)kStorPar * S);
+        for (int k = 0; k < kStorPar; k++)
+            std::copy(par[k], par[k] + S, hm.stor_par.begin() + (size_t)k * S);
+        hm.stor_dt = st->dt;
+    }
+    if (D > 0) {
+        const opf_devices* dv = opts->devices;
+        hm.dev_bus.assign(dv->bus, dv->bus + D);
+        const double* par[kDevPar] = {dv->cp, dv->cq, dv->cost};
+        hm.dev_par.resize((size_t)kDevPar * D);
+        for (int k = 0; k < kDevPar; k++) std::copy(par[k], par[k] + D, hm.dev_par.begin() + (size_t)k * D);
+    }
+    per_bus(S, hm.stor_bus, hm.st_ptr, hm.st_list);
+    per_bus(D, hm.dev_bus, hm.dv_ptr, hm.dv_list);
+    // balance rows also hold one entry per storage unit and device at the bus
+    for (int32_t i = N - 1; i >= 0; i--) {
+        const int32_t extra = (hm.st_ptr[i + 1] + hm.dv_ptr[i + 1]);
+        hm.jbal_off[i + 1] += extra;
+    }
+
     // ---- layout
     ly.x_va = 0;
     ly.x_vm = N * P;
@@ -278,15 +352,26 @@ int build_host_model(const opf_case* cs, const opf_opts* opts, HostModel& hm, st
     ly.x_qg = ly.x_pg + (int64_t)G * ly.npg;
     ly.x_p = ly.x_qg + (int64_t)G * P;
     ly.x_q = ly.x_p + 2LL * L * P;
-    ly.n = ly.x_q + 2LL * L * P;
-    const int64_t rk = ly.rect;
+    ly.x_ps = ly.x_q + 2LL * L * P;
+    ly.x_qs = ly.x_ps + (int64_t)S * P;
+    ly.x_qsc = ly.x_qs + (int64_t)S * P;
+    ly.x_se = ly.x_qsc + (int64_t)S * P;
+    ly.x_sc = ly.x_se + (int64_t)S * P;
+    ly.x_sd = ly.x_sc + (int64_t)S * P;
+    ly.x_u = ly.x_sd + (int64_t)S * P;
+    ly.n = ly.x_u + (int64_t)D * P;
+    const int64_t rk = ly.rect, T1 = T - 1;
     const int64_t rows[B_END] = {R * P, L * P, L * P, L * P, L * P, L * P, rk * L * P, N * P, N * P, L * P, L * P,
-                                 rk * N * P, T > 1 ? (int64_t)G * (T - 1) : 0};
-    ly.jbal_rep = (1 + rk) * N + G + 2LL * L;
+                                 rk * N * P, (int64_t)G * T1, (int64_t)S * P, (int64_t)S * P, (int64_t)S * P,
+                                 (int64_t)S * P, (int64_t)ly.comp * S * P, (int64_t)D * T1, (int64_t)D};
+    ly.jbal_rep = (1 + rk) * N + G + 2LL * L + S + D;
     const int64_t angj = (2 + 2 * rk) * L * P;  // polar (va_f, va_t); rectangular (vr_f, vr_t, vi_f, vi_t)
+    // state of charge: 3 entries in period 0 (se, sc, sd), 4 after (se_{t-1} too)
+    const int64_t socj = (int64_t)S * (3 + 4 * (P - 1));
     const int64_t ents[B_END] = {R * P, 5LL * L * P, 5LL * L * P, 5LL * L * P, 5LL * L * P, angj, rk * angj,
                                  ly.jbal_rep * P, ly.jbal_rep * P, 2LL * L * P, 2LL * L * P, rk * 2 * N * P,
-                                 T > 1 ? 2LL * G * (T - 1) : 0};
+                                 2LL * G * T1, socj, 5LL * S * P, 4LL * S * P, 2LL * S * P, 2LL * ly.comp * S * P,
+                                 2LL * D * T1, (int64_t)D};
     ly.c_blk[0] = ly.j_blk[0] = 0;
     for (int b = 0; b < B_END; b++) {
         ly.c_blk[b + 1] = ly.c_blk[b] + rows[b];
@@ -299,7 +384,10 @@ int build_host_model(const opf_case* cs, const opf_opts* opts, HostModel& hm, st
     ly.h_pg = ly.h_vm + ly.hvm_rep * P;
     ly.h_p = ly.h_pg + (int64_t)G * ly.npg;
     ly.h_q = ly.h_p + 2LL * L * P;
-    ly.nnzh = ly.h_q + 2LL * L * P;
+    ly.h_ps = ly.h_q + 2LL * L * P;
+    ly.h_qs = ly.h_ps + 2LL * S * P;
+    ly.h_sd = ly.h_qs + 2LL * S * P;
+    ly.nnzh = ly.h_sd + (int64_t)ly.comp * S * P;
     if (ly.nnzh >= std::numeric_limits<int32_t>::max())
         return fail(err, OPF_E_CASE, "model too large for int32 indices");
     // the kernels address every per-instance array with 32-bit byte offsets:
@@ -347,22 +435,24 @@ void build_slots(HostModel& hm) {
     for (int32_t i = 0; i < N; i++) {
         const int32_t e0 = hm.adj_ptr[i], e1 = hm.adj_ptr[i + 1], deg = e1 - e0;
         const int32_t g0 = hm.gen_ptr[i], ng = hm.gen_ptr[i + 1] - g0;
-        const int32_t seg = 1 + deg + ng;
+        const int32_t s0 = hm.st_ptr[i], ns = hm.st_ptr[i + 1] - s0;
+        const int32_t d0 = hm.dv_ptr[i], nd = hm.dv_ptr[i + 1] - d0;
+        const int32_t seg = 1 + deg + ng + ns + nd;
         if (seg > kWaveLanes) {
             hm.big_bus.push_back(i);
             continue;
         }
         if (lane + seg > kWaveLanes) pad_wave();
-        const int32_t nlo = hm.nlo[i], nd = hm.ndist[i];
+        const int32_t nlo = hm.nlo[i], ndst = hm.ndist[i];
         const int32_t hva = hm.hva_off[i], hvm = hm.hvm_off[i], jrow = hm.jbal_off[i];
         const uint32_t head_lane = (uint32_t)lane;
         const int32_t nbv = rect ? 2 : 1;  // leading bus entries of the balance rows
         if (rect)  // (vr_i, vr_i), no (vi_i, vr_i), (vi_i, vi_i)
-            push(SK_HEAD | (seg << 8), -1, i, -1, jrow, hva + nlo, -1, hvm + nd + nlo,
+            push(SK_HEAD | (seg << 8), -1, i, -1, jrow, hva + nlo, -1, hvm + ndst + nlo,
                  ck(SK_HEAD | (deg == 0 ? 64u : 0u), seg - 1, head_lane, 0, 0), i);
         else
             push(SK_HEAD | (seg << 8), -1, i, -1, jrow, deg > 0 ? hva + nlo : -1, deg > 0 ? hvm + nlo : -1,
-                 deg > 0 ? hvm + nd + 1 + nlo : hvm, ck(SK_HEAD | (deg == 0 ? 64u : 0u), seg - 1, head_lane, 0, 0),
+                 deg > 0 ? hvm + ndst + 1 + nlo : hvm, ck(SK_HEAD | (deg == 0 ? 64u : 0u), seg - 1, head_lane, 0, 0),
                  i);
         for (int32_t q = e0; q < e1; q++) {
             const int32_t code = hm.he[q], l = code >> 1, from = code & 1;
@@ -380,16 +470,24 @@ void build_slots(HostModel& hm) {
                                   ((k > i ? 1u : 0u) << 5);
             if (rect)  // (vr_i, vr_k) for k < i, (vi_i, vr_k), (vi_i, vi_k) for k < i
                 push(kind, l, i, k, jrow + nbv + ng + arank, leader && k < i ? hva + grp : -1,
-                     leader ? hvm + grp : -1, leader && k < i ? hvm + nd + grp : -1,
+                     leader ? hvm + grp : -1, leader && k < i ? hvm + ndst + grp : -1,
                      ck(clow, leader ? glen - 1 : 0, head_lane, 1 + ng + arank, grp), l);
             else
                 push(kind, l, i, k, jrow + 1 + ng + arank, leader && k < i ? hva + grp : -1,
-                     leader ? hvm + grp + (k > i ? 1 : 0) : -1, leader && k < i ? hvm + nd + 1 + grp : -1,
+                     leader ? hvm + grp + (k > i ? 1 : 0) : -1, leader && k < i ? hvm + ndst + 1 + grp : -1,
                      ck(clow, leader ? glen - 1 : 0, head_lane, 1 + ng + arank, grp), l);
         }
         for (int32_t q = 0; q < ng; q++)
             push(SK_GEN, hm.gen_list[g0 + q], i, -1, jrow + nbv + q, -1, -1, -1, ck(SK_GEN, 0, head_lane, 1 + q, 0),
                  hm.gen_list[g0 + q]);
+        // storage units (bit 2) and devices (bit 4): their balance entries
+        // follow the arcs'; `other` is the head's lane (they read its vm)
+        for (int32_t q = 0; q < ns; q++)
+            push(SK_GEN | 4, hm.st_list[s0 + q], i, (int32_t)head_lane, jrow + nbv + ng + deg + q, -1, -1, -1,
+                 ck(SK_GEN | 4, 0, head_lane, 1 + ng + deg + q, 0), hm.st_list[s0 + q]);
+        for (int32_t q = 0; q < nd; q++)
+            push(SK_GEN | 16, hm.dv_list[d0 + q], i, (int32_t)head_lane, jrow + nbv + ng + deg + ns + q, -1, -1, -1,
+                 ck(SK_GEN | 16, 0, head_lane, 1 + ng + deg + ns + q, 0), hm.dv_list[d0 + q]);
     }
     pad_wave();
     hm.nwaves = (int32_t)(hm.slots.size() / (8 * kWaveLanes));
@@ -411,6 +509,9 @@ void fill_pattern(const HostModel& hm, int32_t* jr, int32_t* jc, int32_t* hr, in
     auto qg = [&](int32_t k, int32_t r) { return (int32_t)(ly.x_qg + k + (int64_t)G * r); };
     auto pa = [&](int32_t a, int32_t r) { return (int32_t)(ly.x_p + a + 2LL * L * r); };
     auto qa = [&](int32_t a, int32_t r) { return (int32_t)(ly.x_q + a + 2LL * L * r); };
+    const int32_t S = ly.S, D = ly.D;
+    auto sv = [&](int64_t base, int32_t u, int32_t r) { return (int32_t)(base + u + (int64_t)S * r); };
+    auto uv = [&](int32_t d, int32_t r) { return (int32_t)(ly.x_u + d + (int64_t)D * r); };
 
     if (jr || jc) {
         int64_t e = 0;
@@ -454,6 +555,9 @@ void fill_pattern(const HostModel& hm, int32_t* jr, int32_t* jc, int32_t* hr, in
                         put(isp ? pg(hm.gen_list[q], r) : qg(hm.gen_list[q], r));
                     for (int32_t q = hm.arc_ptr[i]; q < hm.arc_ptr[i + 1]; q++)
                         put(isp ? pa(hm.arc_list[q], r) : qa(hm.arc_list[q], r));
+                    for (int32_t q = hm.st_ptr[i]; q < hm.st_ptr[i + 1]; q++)
+                        put(sv(isp ? ly.x_ps : ly.x_qs, hm.st_list[q], r));
+                    for (int32_t q = hm.dv_ptr[i]; q < hm.dv_ptr[i + 1]; q++) put(uv(hm.dv_list[q], r));
                 }
         for (int side = 0; side < 2; side++)
             for (int32_t r = 0; r < P; r++)
@@ -473,6 +577,47 @@ void fill_pattern(const HostModel& hm, int32_t* jr, int32_t* jc, int32_t* hr, in
                 put(pg(k, t - 1));
                 put(pg(k, t));
             }
+        // storage rows, columns ascending: soc [se_{t-1}], se, sc, sd; loss_p
+        // vm, ps, qs, sc, sd; loss_q vm, ps, qs, qsc; thermal ps, qs; comp sc, sd
+        for (int32_t r = 0; r < P; r++)
+            for (int32_t u = 0; u < S; u++, row++) {
+                if (r >= 1) put(sv(ly.x_se, u, r - 1));
+                put(sv(ly.x_se, u, r));
+                put(sv(ly.x_sc, u, r));
+                put(sv(ly.x_sd, u, r));
+            }
+        for (int32_t r = 0; r < P; r++)
+            for (int32_t u = 0; u < S; u++, row++) {
+                put(vm(hm.stor_bus[u], r));
+                put(sv(ly.x_ps, u, r));
+                put(sv(ly.x_qs, u, r));
+                put(sv(ly.x_sc, u, r));
+                put(sv(ly.x_sd, u, r));
+            }
+        for (int32_t r = 0; r < P; r++)
+            for (int32_t u = 0; u < S; u++, row++) {
+                put(vm(hm.stor_bus[u], r));
+                put(sv(ly.x_ps, u, r));
+                put(sv(ly.x_qs, u, r));
+                put(sv(ly.x_qsc, u, r));
+            }
+        for (int32_t r = 0; r < P; r++)
+            for (int32_t u = 0; u < S; u++, row++) {
+                put(sv(ly.x_ps, u, r));
+                put(sv(ly.x_qs, u, r));
+            }
+        for (int32_t r = 0; r < P && ly.comp; r++)
+            for (int32_t u = 0; u < S; u++, row++) {
+                put(sv(ly.x_sc, u, r));
+                put(sv(ly.x_sd, u, r));
+            }
+        // device rows: ramp u_{t-1}, u_t; init u_0
+        for (int32_t t = 1; t < ly.T; t++)
+            for (int32_t d = 0; d < D; d++, row++) {
+                put(uv(d, t - 1));
+                put(uv(d, t));
+            }
+        for (int32_t d = 0; d < D; d++, row++) put(uv(d, 0));
     }
 
     if (hr || hc) {
@@ -542,6 +687,19 @@ void fill_pattern(const HostModel& hm, int32_t* jr, int32_t* jc, int32_t* hr, in
             for (int32_t a = 0; a < 2 * L; a++) put(pa(a, r), pa(a, r));
         for (int32_t r = 0; r < P; r++)
             for (int32_t a = 0; a < 2 * L; a++) put(qa(a, r), qa(a, r));
+        // storage rows: (ps, vm), (ps, ps); (qs, vm), (qs, qs); (sd, sc)
+        for (int32_t r = 0; r < P; r++)
+            for (int32_t u = 0; u < S; u++) {
+                put(sv(ly.x_ps, u, r), vm(hm.stor_bus[u], r));
+                put(sv(ly.x_ps, u, r), sv(ly.x_ps, u, r));
+            }
+        for (int32_t r = 0; r < P; r++)
+            for (int32_t u = 0; u < S; u++) {
+                put(sv(ly.x_qs, u, r), vm(hm.stor_bus[u], r));
+                put(sv(ly.x_qs, u, r), sv(ly.x_qs, u, r));
+            }
+        for (int32_t r = 0; r < P && ly.comp; r++)
+            for (int32_t u = 0; u < S; u++) put(sv(ly.x_sd, u, r), sv(ly.x_sc, u, r));
     }
 }
 
@@ -588,6 +746,26 @@ void fill_bounds(const opf_case* cs, const opf_opts* opts, const HostModel& hm, 
                 if (lvar) lvar[c] = cs->pmin[k];
                 if (uvar) uvar[c] = cs->pmax[k];
             }
+        const int32_t S = ly.S, D = ly.D;
+        for (int32_t r = 0; r < P; r++) {
+            for (int32_t u = 0; u < S; u++) {
+                const opf_storage* st = opts->storage;
+                const int64_t o = u + (int64_t)S * r;
+                const double lo[6] = {-st->rating[u], st->qmin[u], -st->rating[u], 0.0, 0.0, 0.0};
+                const double hi[6] = {st->rating[u], st->qmax[u], st->rating[u], st->emax[u], st->chmax[u],
+                                      st->dismax[u]};
+                const int64_t base[6] = {ly.x_ps, ly.x_qs, ly.x_qsc, ly.x_se, ly.x_sc, ly.x_sd};
+                for (int k = 0; k < 6; k++) {
+                    if (lvar) lvar[base[k] + o] = lo[k];
+                    if (uvar) uvar[base[k] + o] = hi[k];
+                }
+            }
+            for (int32_t d = 0; d < D; d++) {
+                const int64_t c = ly.x_u + d + (int64_t)D * r;
+                if (lvar) lvar[c] = opts->devices->lo[d];
+                if (uvar) uvar[c] = opts->devices->hi[d];
+            }
+        }
     }
     if (lcon || ucon) {
         const int64_t m = ly.m();
@@ -612,6 +790,20 @@ void fill_bounds(const opf_case* cs, const opf_opts* opts, const HostModel& hm, 
             }
         for (int64_t row = ly.c_blk[B_THF]; row < ly.c_blk[B_VMAG]; row++)
             if (lcon) lcon[row] = -inf;
+        // storage thermal and complementarity rows: (-inf, 0]; device rows
+        for (int64_t row = ly.c_blk[B_STH]; row < ly.c_blk[B_DRAMP]; row++)
+            if (lcon) lcon[row] = -inf;
+        for (int32_t t = 1; t < ly.T; t++)
+            for (int32_t d = 0; d < ly.D; d++) {
+                const int64_t row = ly.c_blk[B_DRAMP] + d + (int64_t)ly.D * (t - 1);
+                if (lcon) lcon[row] = -opts->devices->ramp[d];
+                if (ucon) ucon[row] = opts->devices->ramp[d];
+            }
+        for (int32_t d = 0; d < ly.D; d++) {
+            const int64_t row = ly.c_blk[B_DINIT] + d;
+            if (lcon) lcon[row] = opts->devices->init_lo[d];
+            if (ucon) ucon[row] = opts->devices->init_hi[d];
+        }
         for (int32_t r = 0; r < P && ly.rect; r++)
             for (int32_t i = 0; i < N; i++) {
                 const int64_t row = ly.c_blk[B_VMAG] + i + (int64_t)N * r;

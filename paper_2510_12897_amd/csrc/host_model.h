@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "dev_model.h"
 #include "opf.h"
 
 namespace opf {
@@ -15,17 +16,26 @@ namespace opf {
 // the multi-period ramp rows.  B_ANGL (the second angle-difference row) and
 // B_VMAG (the voltage-magnitude row) are rows of the rectangular form only
 // (Sec. III-C1); they are empty in the polar form.
+// B_SOC .. B_SCMP are the storage rows (state of charge, active and
+// reactive losses, thermal, complementarity), B_DRAMP / B_DINIT the device
+// rows (opf_storage, opf_devices); empty without units and devices.
 enum Block {
-    B_REF = 0, B_PFR, B_QFR, B_PTO, B_QTO, B_ANG, B_ANGL, B_BALP, B_BALQ, B_THF, B_THT, B_VMAG, B_RAMP, B_END
+    B_REF = 0, B_PFR, B_QFR, B_PTO, B_QTO, B_ANG, B_ANGL, B_BALP, B_BALQ, B_THF, B_THT, B_VMAG, B_RAMP,
+    B_SOC, B_SLP, B_SLQ, B_STH, B_SCMP, B_DRAMP, B_DINIT, B_END
 };
+
 
 struct Layout {
     int32_t N = 0, L = 0, G = 0, R = 0, T = 1, K = 0;
     int32_t rect = 0;   // 0: polar (va, vm); 1: rectangular (vr, vi) in the same two bus blocks
+    int32_t S = 0, D = 0;  // storage units, user-extension devices
+    int32_t comp = 0;      // storage complementarity rows present
     int32_t nrep = 1;   // replicas: periods or contingency copies (base + K)
     int32_t npg = 1;    // replicas of the pg block (1 when copies share pg)
     // variable blocks
     int64_t x_va = 0, x_vm = 0, x_pg = 0, x_qg = 0, x_p = 0, x_q = 0, n = 0;
+    // storage blocks ps, qs, qsc, se, sc, sd and the device block u
+    int64_t x_ps = 0, x_qs = 0, x_qsc = 0, x_se = 0, x_sc = 0, x_sd = 0, x_u = 0;
     // first row of each constraint block (c_blk[B_END] = m)
     int64_t c_blk[B_END + 1] = {};
     // first Jacobian entry of each block (j_blk[B_END] = nnzj)
@@ -33,6 +43,9 @@ struct Layout {
     int64_t jbal_rep = 0;          // entries of one replica's balance block
     // Hessian: va (vr) rows, vm (vi) rows, pg rows, p rows, q rows
     int64_t h_va = 0, h_vm = 0, h_pg = 0, h_p = 0, h_q = 0, nnzh = 0;
+    // storage rows of the Hessian: ps rows [(ps, vm), (ps, ps)], qs rows
+    // [(qs, vm), (qs, qs)], sd rows [(sd, sc)] (complementarity only)
+    int64_t h_ps = 0, h_qs = 0, h_sd = 0;
     int64_t hva_rep = 0, hvm_rep = 0;  // entries of one replica's va / vm (vr / vi) rows
 
     int64_t m() const { return c_blk[B_END]; }
@@ -64,6 +77,12 @@ struct HostModel {
     std::vector<int32_t> is_ref;               // [N] 1 at reference buses
     std::vector<int32_t> outage;               // per replica: branch out of service or -1
     int32_t max_degree = 0;
+    // storage units and devices: bus, parameters, per-bus lists (ascending)
+    std::vector<int32_t> stor_bus, dev_bus;
+    std::vector<double> stor_par;              // [kStorPar][S]
+    std::vector<double> dev_par;               // [kDevPar][D]
+    std::vector<int32_t> st_ptr, st_list, dv_ptr, dv_list;
+    double stor_dt = 0.0;
 
     // Bus segments packed into 64-lane waves.  Each bus with at most
     // kWaveLanes - 1 incident half-edges plus generators owns a contiguous
@@ -96,6 +115,10 @@ constexpr int32_t kWaveLanes = 64;
 //             half-edge of its neighbour group, which writes the group's
 //             off-diagonal entries (-1 if absent or not the group's first)
 //  generator: ref = generator, bus = i; jpos = its -1 entry
+//  storage unit (generator lane type, kind bit 2): ref = unit, bus = i,
+//             other = the lane of its segment's head; jpos = its +1 entry
+//  device (generator lane type, kind bit 4): ref = device, bus = i,
+//             other = the head's lane; jpos = its entry (cp / cq)
 // In the rectangular form va, vm read vr, vi: the head's h0/h2 are
 // (vr_i,vr_i), (vi_i,vi_i) and h1 is absent (-1); a group's h0/h1/h2 are
 // (vr_i,vr_k), (vi_i,vr_k), (vi_i,vi_k); the balance rows lead with two bus
@@ -105,13 +128,15 @@ enum SlotKind { SK_IDLE = 0, SK_HEAD = 1, SK_EDGE = 2, SK_GEN = 3 };
 // Compact slot (two launches; 8 bytes per lane instead of 32): the index is
 // the bus (head) or the branch / generator (other lanes); the kind word
 // holds
-//   bits [0,4): as in the full kind (lane type, from side, group leader);
-//   bit 4: neighbour k < i; bit 5: k > i (half-edge); bit 6: the head's bus
-//          has no branches;
+//   bits [0,4): as in the full kind (lane type, from side or storage unit,
+//               group leader);
+//   bit 4: neighbour k < i (half-edge), device (generator lane type);
+//   bit 5: k > i (half-edge); bit 6: the head's bus has no branches;
 //   bits [8,14): segment length - 1 (head) or group length - 1 (leader);
 //   bits [14,20): lane of the segment's head in the wave;
 //   bits [20,26): offset of the lane's balance Jacobian entry from the
-//                 head's (0 head, 1 + q generator q, 1 + ng + arc rank; the
+//                 head's (0 head, 1 + q generator q, 1 + ng + arc rank,
+//                 1 + ng + deg + q storage unit q, then the devices; the
 //                 rectangular form adds 1 to the non-head offsets in the
 //                 kernel, so that the field stays below 64);
 //   bits [26,32): neighbour group of a half-edge.

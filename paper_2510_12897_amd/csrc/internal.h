@@ -69,7 +69,7 @@ constexpr uint64_t kBatchMagic = 0x4f50464241544348ull;  // "OPFBATCH"
 struct ModelOffsets {
     size_t f_bus, t_bus, coef, rate2, slots, slot_coef, big_bus, adj_ptr, he, he_grp, nlo, ndist,
         hva_off, hvm_off, jbal_off, gen_ptr, gen_list, gs, bs, pd, qd, c2, c1, c0, gen_bus, ref_bus, ref_ptr,
-        ref_list, outage, slots_c, tan_lim;
+        ref_list, outage, slots_c, tan_lim, stor_bus, stor_par, dev_bus, dev_par, st_ptr, st_list, dv_ptr, dv_list;
 };
 
 ModelOffsets pack_model(Packer& pk, const opf::HostModel& hm);

@@ -8,7 +8,10 @@ of a Model fails with OPFError.
 Cases are dicts of numpy arrays with the field names of ``opf_case``
 (``synth.network`` produces them); options are the keyword arguments
 ``n_periods``, ``pd_t``, ``qd_t``, ``ramp_ratio``, ``n_cont``, ``outaged`` and
-``form`` ("polar", the default, or "rect" for bus variables (vr, vi)).
+``form`` ("polar", the default, or "rect" for bus variables (vr, vi)),
+``storage`` (a dict of per-unit arrays named as the fields of opf_storage),
+``stor_dt``, ``stor_comp`` and ``devices`` (per-device arrays named as the
+fields of opf_devices).
 """
 from __future__ import annotations
 
@@ -25,10 +28,11 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "opf.h")
 OPF_OK, OPF_E_ARG, OPF_E_CASE, OPF_E_NOMEM, OPF_E_HIP, OPF_E_STATE = 0, -1, -2, -3, -4, -5
 
 # bus blocks: va, vm (polar) or vr, vi (rectangular form), same positions
-VAR_BLOCKS = {"va": 0, "vm": 1, "pg": 2, "qg": 3, "p": 4, "q": 5, "vr": 0, "vi": 1}
+VAR_BLOCKS = {"va": 0, "vm": 1, "pg": 2, "qg": 3, "p": 4, "q": 5, "vr": 0, "vi": 1,
+              "ps": 6, "qs": 7, "qsc": 8, "se": 9, "sc": 10, "sd": 11, "u": 12}
 CON_BLOCKS = {name: 16 + k for k, name in enumerate(
     ["ref", "p_fr", "q_fr", "p_to", "q_to", "angle", "bal_p", "bal_q", "thermal_fr", "thermal_to", "ramp",
-     "angle_lo", "vmag"])}
+     "angle_lo", "vmag", "soc", "stor_loss_p", "stor_loss_q", "stor_thermal", "stor_comp", "dev_ramp", "dev_init"])}
 FORMS = {"polar": 0, "rect": 1}
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -57,11 +61,25 @@ class _Case(ctypes.Structure):
     ]
 
 
+STOR_FIELDS = ("emax", "chmax", "dismax", "rating", "qmin", "qmax", "eta_c", "eta_d", "r", "x", "ploss", "qloss",
+               "e0")
+DEV_FIELDS = ("cp", "cq", "cost", "lo", "hi", "ramp", "init_lo", "init_hi")
+
+
+class _Storage(ctypes.Structure):
+    _fields_ = ([("n", ctypes.c_int32), ("bus", _ip)] + [(k, _dp) for k in STOR_FIELDS]
+                + [("dt", ctypes.c_double), ("comp", ctypes.c_int32)])
+
+
+class _Devices(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("bus", _ip)] + [(k, _dp) for k in DEV_FIELDS]
+
+
 class _Opts(ctypes.Structure):
     _fields_ = [
         ("n_periods", ctypes.c_int32), ("pd_t", _dp), ("qd_t", _dp),
         ("ramp_ratio", ctypes.c_double), ("n_cont", ctypes.c_int32), ("outaged_branch", _ip),
-        ("form", ctypes.c_int32),
+        ("form", ctypes.c_int32), ("storage", ctypes.POINTER(_Storage)), ("devices", ctypes.POINTER(_Devices)),
     ]
 
 
@@ -156,7 +174,7 @@ def _check(rc: int):
 
 # ---------------------------------------------------------------- marshalling
 def _case_struct(case: dict, n_periods=1, pd_t=None, qd_t=None, ramp_ratio=0.0, n_cont=0, outaged=None,
-                 form="polar"):
+                 form="polar", storage=None, stor_dt=1.0, stor_comp=False, devices=None):
     keep = []
 
     def d(a):
@@ -187,6 +205,24 @@ def _case_struct(case: dict, n_periods=1, pd_t=None, qd_t=None, ramp_ratio=0.0, 
     if form not in FORMS:
         raise OPFError(OPF_E_ARG, f"unknown form {form!r} (polar or rect)")
     o.form = FORMS[form]
+    if storage is not None:
+        st = _Storage()
+        st.n = len(storage["bus"])
+        st.bus = i(storage["bus"])
+        for k in STOR_FIELDS:
+            setattr(st, k, d(storage[k]))
+        st.dt = float(stor_dt)
+        st.comp = int(bool(stor_comp))
+        keep.append(st)
+        o.storage = ctypes.pointer(st)
+    if devices is not None:
+        dv = _Devices()
+        dv.n = len(devices["bus"])
+        dv.bus = i(devices["bus"])
+        for k in DEV_FIELDS:
+            setattr(dv, k, d(devices[k]))
+        keep.append(dv)
+        o.devices = ctypes.pointer(dv)
     return c, o, keep
 
 

@@ -64,8 +64,28 @@ def _rect(cases):
         yield name + "_rect", cs, dict(opts, form="rect")
 
 
+def _ext_cases():
+    """Storage units and devices (multi-period and static), devices in the
+    rectangular form, and a hub bus whose segment overflows a wave only
+    because of its units and devices."""
+    cs = synth.network(30, 44, 12, 3, variant=True)
+    pd_t, qd_t = synth.mp_loads(cs, 4, 1)
+    st, dv = synth.storage(cs, 7, frac=0.2), synth.devices(cs, 9, 8)
+    yield "stor_dev_mp4", cs, dict(n_periods=4, pd_t=pd_t, qd_t=qd_t, ramp_ratio=0.2, storage=st, stor_dt=0.5,
+                                   stor_comp=True, devices=dv)
+    yield "stor_static", cs, dict(storage=st, stor_dt=1.0)
+    yield "dev_rect_mp2", cs, dict(n_periods=2, ramp_ratio=0.2, devices=dv, form="rect")
+    hub = hub_network()
+    hst = synth.storage(hub, 3, frac=0.05)
+    hst["bus"] = np.sort(np.r_[hst["bus"][:-2], [200, 200]]).astype(np.int32)  # two units at the 63-lane hub
+    hdv = synth.devices(hub, 6, 4)
+    hdv["bus"][:3] = 100  # three devices at the 64-lane hub
+    yield "hub_stor_dev_mp2", hub, dict(n_periods=2, ramp_ratio=0.2, storage=hst, stor_dt=0.5, devices=hdv)
+
+
 CASES = list(_cases())
 CASES += list(_rect(CASES))
+CASES += list(_ext_cases())
 
 
 @pytest.mark.parametrize("name,cs,opts", CASES, ids=[c[0] for c in CASES])
@@ -73,7 +93,8 @@ def test_host_pattern_matches_oracle_bit_exact(name, cs, opts):
     n, m, nnzj, nnzh = opf.case_dims(cs, **opts)
     assert (n, m) == O.dims(cs, **opts)
     T, K = opts.get("n_periods", 1), opts.get("n_cont", 0)
-    x = synth.point(cs, 3, n_periods=T, n_cont=K, form=opts.get("form", "polar"))
+    x = synth.point(cs, 3, n_periods=T, n_cont=K, form=opts.get("form", "polar"), storage=opts.get("storage"),
+                    devices=opts.get("devices"))
     res = O.evaluate(cs, x, synth.multipliers(m, 3), 1.0, want=O.W_JAC | O.W_HESS, **opts)
     jr, jc, hr, hc = opf.case_structure(cs, **opts)
     assert jr.dtype == np.int32 and hr.dtype == np.int32
