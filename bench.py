@@ -83,14 +83,17 @@ def measured_traffic():
         return None
 
 
-def algorithmic_bytes(cs: dict, dims, T: int = 1, K: int = 0, mp_loads: bool = False, rect: bool = False) -> int:
+def algorithmic_bytes(cs: dict, dims, T: int = 1, K: int = 0, mp_loads: bool = False, rect: bool = False,
+                      S: int = 0, D: int = 0) -> int:
     """Bytes one callback set must move at least: every input read once and
     every output written once.  Reads: x (8n), y (8m), sigma; branch data
     (8 admittance terms + rate^2 + two int32 buses = 80 B; the rectangular
     form also reads the two angle-limit tangents, 16 B); bus loads and
     shunts (32 B, loads per period when they vary); generator costs and bus
     (28 B); adjacency (half-edges, bus pointers, generator lists); outage
-    list.  Writes: f, grad f (8n), c (8m), J (8 nnzj), H (8 nnzh)."""
+    list; storage units (13 parameters and a bus, 108 B) and devices (3
+    coefficients and a bus, 28 B) with their per-bus lists.  Writes: f,
+    grad f (8n), c (8m), J (8 nnzj), H (8 nnzh)."""
     n, m, nnzj, nnzh = dims
     N, L, G = cs["n_bus"], cs["n_branch"], cs["n_gen"]
     reads = 8 * n + 8 * m + 8
@@ -99,6 +102,8 @@ def algorithmic_bytes(cs: dict, dims, T: int = 1, K: int = 0, mp_loads: bool = F
     reads += 28 * G
     reads += 4 * 2 * L + 4 * (N + 1) * 2 + 4 * G
     reads += 4 * K
+    if S or D:
+        reads += 108 * S + 28 * D + 4 * (S + D) + 8 * (N + 1)
     writes = 8 + 8 * n + 8 * m + 8 * nnzj + 8 * nnzh
     return int(reads + writes)
 
@@ -460,14 +465,16 @@ def bench_model(torch, opf, synth, cs, opts, n_in, n_out, sets, log, label, T=1,
     rect = opts.get("form") == "rect"
     dims = (model.n, model.m, model.nnzj, model.nnzh)
     form = "rect" if rect else "polar"
-    xs = [torch.as_tensor(synth.point(cs, (seed, r), n_periods=T, n_cont=K, form=form), device=dev)
-          for r in range(n_in)]
+    st, dv = opts.get("storage"), opts.get("devices")
+    xs = [torch.as_tensor(synth.point(cs, (seed, r), n_periods=T, n_cont=K, form=form, storage=st, devices=dv),
+                          device=dev) for r in range(n_in)]
     ys = [torch.as_tensor(synth.multipliers(model.m, (seed, r)), device=dev) for r in range(n_in)]
     runner = PlainRunner(model, xs, ys, n_out=n_out, sets=sets, torch=torch)
     runner.capture()
     secs, _ = time_steps(torch, runner.step, steps, 1)
     per = secs / (steps * sets)
-    b = algorithmic_bytes(cs, dims, T=T, K=K, mp_loads=mp_loads, rect=rect)
+    b = algorithmic_bytes(cs, dims, T=T, K=K, mp_loads=mp_loads, rect=rect, S=len(st["bus"]) if st else 0,
+                          D=len(dv["bus"]) if dv else 0)
     ws = n_in * 8 * (dims[0] + dims[1]) + n_out * 8 * (1 + sum(dims))
     log(f"{label}: {per * 1e6:.2f} us/set, {b / per / 1e9:.0f} GB/s (working set {ws / 2**20:.0f} MiB)")
     launches, items = model.launch_shape()
@@ -639,6 +646,20 @@ def main():
                 log, "multi-period", T=48, mp_loads=True)
         except Exception as e:
             extra["multiperiod_2k_x48"] = {"error": repr(e)}
+        try:
+            # storage at the largest 10 % of loads (1.5x energy ratings) and
+            # 100 electrolyzer-like devices, 30-minute periods
+            cs = synth.network(2000, 2700, 400, 2)
+            pd_t, qd_t = synth.mp_loads(cs, 48, 202)
+            extra["multiperiod_storage_2k_x48"] = bench_model(
+                torch, opf, synth, cs, dict(n_periods=48, pd_t=pd_t, qd_t=qd_t, ramp_ratio=0.2,
+                                            storage=synth.storage(cs, 203), stor_dt=0.5,
+                                            devices=synth.devices(cs, 100, 204)), 24, 8, 24,
+                log, "multi-period with storage and devices", T=48, mp_loads=True)
+            extra["multiperiod_storage_2k_x48"]["workload"] = (
+                "2000 buses x 48 periods, 200 storage units at the largest loads, 100 devices")
+        except Exception as e:
+            extra["multiperiod_storage_2k_x48"] = {"error": repr(e)}
         try:
             cs = synth.network(1000, 1350, 200, 31)
             out = synth.outages(cs, 200, 32)

@@ -45,6 +45,7 @@ struct opf_batch_s {
     int32_t wg_per_cu = 0;           // flat until tuned (measured fastest on the 64-instance mix)
     int32_t n_cu = 256;
     bool rect = false;               // every model is of the rectangular form (else all polar)
+    bool ext = false;                // some model has storage units or devices
 };
 
 namespace {
@@ -104,7 +105,7 @@ int launch(opf_batch_s* b, const opf::BatchArgs& a0, hipStream_t stream) {
     for (int ph = 0; ph < 2; ph++) {
         if (a[ph].n_items == 0) continue;
         void* args[1] = {&a[ph]};
-        const hipError_t e = hipLaunchKernel(opf::batch_kernel_fn(ph, a0.mode, b->wg_per_cu == 0, b->rect),
+        const hipError_t e = hipLaunchKernel(opf::batch_kernel_fn(ph, a0.mode, b->wg_per_cu == 0, b->rect, b->ext),
                                              dim3(grid[ph]), dim3(opf::kBlock), args, 0, stream);
         if (e != hipSuccess) return hip_err(e, ph == 0 ? "batch branch-phase launch" : "batch bus-phase launch");
     }
@@ -141,6 +142,8 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
         b = new opf_batch_s();
         b->device = dev;
         b->rect = models[0]->hm.ly.rect != 0;
+        for (int32_t k = 0; k < n_models; k++)
+            if (models[k]->hm.ly.S > 0 || models[k]->hm.ly.D > 0) b->ext = true;
         b->alloc = current_allocator();
         b->n_inst = n_inst;
         b->xoff.assign(n_inst + 1, 0);

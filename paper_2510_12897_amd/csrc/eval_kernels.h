@@ -48,7 +48,8 @@ size_t scratch_bytes(const DevModel& m);
 // The batch kernel of phase 0 (branch items) or 1 (bus items) for mode 0
 // (callback set), 1 (J^T v) or 2 (flows, phase 0 only, polar only),
 // persistent or flat (one workgroup per item), of the polar or the
-// rectangular form (argument: BatchArgs).
-void* batch_kernel_fn(int phase, int mode, bool flat, bool rect);
+// rectangular form, with or without storage units and devices in any
+// instance (argument: BatchArgs).
+void* batch_kernel_fn(int phase, int mode, bool flat, bool rect, bool ext);
 
 }  // namespace opf

@@ -749,8 +749,10 @@ __device__ __forceinline__ Slot load_slot(const DevModel& m, int32_t w) {
 #define H2 (SINGLE ? sl.h2 : h2)
 #define JP (SINGLE ? sl.jpos : jp)
 // RECT: the rectangular form (bus blocks vr, vi; records [D, Bs, D, A, P, Q];
-// a voltage-magnitude row per head).
-template <bool SINGLE, bool RECT = false>
+// a voltage-magnitude row per head).  EXT: the model has storage units or
+// devices (lanes of the generator type with kind bit 2 or 4); without them
+// the kernel holds none of their code or kernel arguments.
+template <bool SINGLE, bool RECT = false, bool EXT = false>
 __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_t r, double* lds) {
     const int32_t lane = threadIdx.x;
     const bool wantC = o.c != nullptr, wantH = o.H != nullptr;
@@ -841,7 +843,7 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
             } else if (wantC) {  // compact records [P, Q]
                 rc = ld(rec, ref);
             }
-        } else if (type == SK_GEN && (kind & 4)) {
+        } else if (EXT && type == SK_GEN && (kind & 4)) {
             // a storage unit: ps, qs (and for its (vm, vm) term the loss
             // rows' multipliers and r, x), held in the generator / head
             // registers (gp, gq, yp, yq, gs, bs), which a lane of another
@@ -857,7 +859,7 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
                 gs = ld(m.stor_par + SP_R * S, ref);
                 bs = ld(m.stor_par + SP_X * S, ref);
             }
-        } else if (type == SK_GEN && (kind & 16)) {
+        } else if (EXT && type == SK_GEN && (kind & 16)) {
             // a device: u and its balance coefficients cp, cq
             const int64_t D = m.D;
             if (wantC) gp = ld(o.x + m.x_u + D * r, ref);
@@ -871,7 +873,7 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
         }
         // a storage lane's (vm, vm) term needs its bus's vm: the head's
         double vm_h = 0.0;
-        if (wantH && m.S > 0) vm_h = __shfl(vm_i, SINGLE ? (sl.other & 63) : ((kind >> 14) & 63), kBlock);
+        if (EXT && wantH && m.S > 0) vm_h = __shfl(vm_i, SINGLE ? (sl.other & 63) : ((kind >> 14) & 63), kBlock);
         double v[kRec] = {0, 0, 0, 0, 0, 0};
         double base_p = 0.0, base_q = 0.0, shunt = 0.0;
         if (type == SK_HEAD) {
@@ -898,13 +900,13 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
                 v[R_P] = rc.x;
                 v[R_Q] = rc.y;
             }
-        } else if (type == SK_GEN && (kind & 4)) {  // storage: +ps, +qs
+        } else if (EXT && type == SK_GEN && (kind & 4)) {  // storage: +ps, +qs
             if (wantC) {
                 v[R_P] = gp;
                 v[R_Q] = gq;
             }
             if (wantH) v[R_MM] = stor_vmvm(gp, gq, vm_h, yp, yq, gs, bs);
-        } else if (type == SK_GEN && (kind & 16)) {  // device: +cp u, +cq u
+        } else if (EXT && type == SK_GEN && (kind & 16)) {  // device: +cp u, +cq u
             if (wantC) {
                 v[R_P] = gs * gp;
                 v[R_Q] = bs * gp;
@@ -1018,11 +1020,11 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
             if (type == SK_HEAD) {
                 vp = 2.0 * gs * vm_i;
                 vq = -2.0 * bs * vm_i;
-            } else if (type == SK_GEN && (kind & 16)) {  // device: cp, cq
+            } else if (EXT && type == SK_GEN && (kind & 16)) {  // device: cp, cq
                 vp = gs;
                 vq = bs;
             } else {  // arcs and storage units +1, generators -1
-                vp = vq = (type == SK_EDGE || (kind & 4)) ? 1.0 : -1.0;
+                vp = vq = (type == SK_EDGE || (EXT && (kind & 4))) ? 1.0 : -1.0;
             }
             if (RECT && type == SK_HEAD) {
                 // (vr_i, vi_i) of both balance rows, then the magnitude row
@@ -1049,7 +1051,7 @@ __device__ void wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_
 #undef JP
 
 // J^T v, phase 2: va / vm (rectangular: vr / vi) entries of the packed buses.
-template <bool RECT = false>
+template <bool RECT = false, bool EXT = false>
 __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int32_t r, double* lds) {
     const int32_t lane = threadIdx.x;
     // the compact slot: lane type, side, segment length; the index is the
@@ -1072,7 +1074,7 @@ __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int
         int32_t q0, q1;
         if (type == SK_EDGE) {
             t = ld(reinterpret_cast<const double2*>(jt_rec_side(m, r, (int32_t)side)), ref);
-        } else if (type == SK_GEN && (sc.x & 4)) {
+        } else if (EXT && type == SK_GEN && (sc.x & 4)) {
             // a storage unit's loss rows: ps, qs, their multipliers, r, x
             // (in the registers of the head's loads)
             const int64_t S = m.S;
@@ -1096,8 +1098,8 @@ __device__ void jt_wave_task(const DevModel& m, const EvalOut& o, int32_t w, int
             q1 = ld(m.ref_ptr, bus + 1);
         }
         double vm_h = 0.0;
-        if (m.S > 0) vm_h = __shfl(vm, (sc.x >> 14) & 63, kBlock);
-        const bool stor = type == SK_GEN && (sc.x & 4);
+        if (EXT && m.S > 0) vm_h = __shfl(vm, (sc.x >> 14) & 63, kBlock);
+        const bool stor = EXT && type == SK_GEN && (sc.x & 4);
         lds[0 * kBlock + lane] = type == SK_EDGE ? t.x : 0.0;
         lds[1 * kBlock + lane] = type == SK_EDGE ? t.y : stor ? jt_stor_vm(vr, vg, vm_h, vp, vq, gs, bs) : 0.0;
         __syncthreads();
@@ -1155,7 +1157,7 @@ __device__ __forceinline__ void big_record(const DevModel& m, const EvalOut& o, 
 
 // A bus whose segment does not fit a wave: the workgroup sums its
 // half-edges' records (lane-strided, then a fixed wave tree).
-template <bool SINGLE, bool RECT = false>
+template <bool SINGLE, bool RECT = false, bool EXT = false>
 __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32_t r) {
     const int32_t b = m.big_bus[idx];
     const int32_t e0 = m.adj_ptr[b], e1 = m.adj_ptr[b + 1], deg = e1 - e0;
@@ -1231,12 +1233,12 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
                         cp -= x[pgb + m.gen_list[g0 + q]];
                         cq -= x[qgb + m.gen_list[g0 + q]];
                     }
-                    for (int32_t q = m.st_ptr[b]; q < m.st_ptr[b + 1]; q++) {  // storage draws
+                    for (int32_t q = EXT ? m.st_ptr[b] : 0; q < (EXT ? m.st_ptr[b + 1] : 0); q++) {  // storage
                         const int64_t e = m.st_list[q] + (int64_t)m.S * r;
                         cp += x[m.x_ps + e];
                         cq += x[m.x_qs + e];
                     }
-                    for (int32_t q = m.dv_ptr[b]; q < m.dv_ptr[b + 1]; q++) {  // devices
+                    for (int32_t q = EXT ? m.dv_ptr[b] : 0; q < (EXT ? m.dv_ptr[b + 1] : 0); q++) {  // devices
                         const int32_t d = m.dv_list[q];
                         const double u = x[m.x_u + d + (int64_t)m.D * r];
                         cp += m.dev_par[DP_CP * (int64_t)m.D + d] * u;
@@ -1249,7 +1251,7 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
                 if (wantH) {
                     double shunt = 2.0 * gs * o.y[m.c_balp + bi] - 2.0 * bs * o.y[m.c_balq + bi] +
                                    (RECT ? 2.0 * o.y[m.c_vmag + bi] : 0.0);
-                    for (int32_t q = m.st_ptr[b]; q < m.st_ptr[b + 1]; q++) {  // storage (vm, vm) terms
+                    for (int32_t q = EXT ? m.st_ptr[b] : 0; q < (EXT ? m.st_ptr[b + 1] : 0); q++) {  // storage (vm, vm)
                         const int32_t u = m.st_list[q];
                         const int64_t e = u + (int64_t)m.S * r;
                         shunt += stor_vmvm(x[m.x_ps + e], x[m.x_qs + e], vm, o.y[m.c_slp + e], o.y[m.c_slq + e],
@@ -1288,8 +1290,8 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
                 }
             }
             // storage units (+1) and devices (cp, cq) follow the arcs
-            const int32_t nbv = RECT ? 2 : 1, ns = m.st_ptr[b + 1] - m.st_ptr[b];
-            const int32_t nd = m.dv_ptr[b + 1] - m.dv_ptr[b], q0 = nbv + ng + deg;
+            const int32_t nbv = RECT ? 2 : 1, ns = EXT ? m.st_ptr[b + 1] - m.st_ptr[b] : 0;
+            const int32_t nd = EXT ? m.dv_ptr[b + 1] - m.dv_ptr[b] : 0, q0 = nbv + ng + deg;
             for (int32_t q = threadIdx.x; q < ns + nd; q += kBlock) {
                 double vp = 1.0, vq = 1.0;
                 if (q >= ns) {
@@ -1308,7 +1310,7 @@ __device__ void big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32
     }
 }
 
-template <bool RECT = false>
+template <bool RECT = false, bool EXT = false>
 __device__ void jt_big_task(const DevModel& m, const EvalOut& o, int32_t idx, int32_t r) {
     const int32_t b = m.big_bus[idx];
     const int32_t e0 = m.adj_ptr[b], deg = m.adj_ptr[b + 1] - e0;
@@ -1341,7 +1343,7 @@ __device__ void jt_big_task(const DevModel& m, const EvalOut& o, int32_t idx, in
             } else {
                 sa += sref;
                 sm += 2.0 * m.gs[b] * vm * vp - 2.0 * m.bs[b] * vm * vq;
-                for (int32_t q = m.st_ptr[b]; q < m.st_ptr[b + 1]; q++) {  // storage loss rows
+                for (int32_t q = EXT ? m.st_ptr[b] : 0; q < (EXT ? m.st_ptr[b + 1] : 0); q++) {  // storage
                     const int32_t u = m.st_list[q];
                     const int64_t e = u + (int64_t)m.S * r;
                     sm += jt_stor_vm(x[m.x_ps + e], x[m.x_qs + e], vm, v[m.c_slp + e], v[m.c_slq + e],
@@ -1363,7 +1365,7 @@ __device__ void jt_big_task(const DevModel& m, const EvalOut& o, int32_t idx, in
 // store has completed (s_waitcnt 0).  An acquire-release ticket would also
 // write back and invalidate the whole XCD L2 for every chunk, which cost
 // 1.6 us of the 10k-bus set.
-template <bool SINGLE>
+template <bool SINGLE, bool EXT>
 __device__ __forceinline__ void obj_partial(const DevModel& m, const EvalOut& o, int64_t slot, double fk) {
     const double s = wave_sum(fk);
     if (!SINGLE) {
@@ -1371,7 +1373,7 @@ __device__ __forceinline__ void obj_partial(const DevModel& m, const EvalOut& o,
         return;
     }
     __shared__ int32_t last;
-    const int32_t total = obj_slots(m);
+    const int32_t total = EXT ? obj_slots(m) : m.ngchunks * m.npg;
     if (threadIdx.x == 0) {
         __hip_atomic_store(&m.obj_part[slot], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -1403,7 +1405,7 @@ __device__ __forceinline__ void obj_partial(const DevModel& m, const EvalOut& o,
 // reference and ramp rows, and one objective partial per replica (a fixed
 // wave tree over the chunk), written with a plain store: the objective item
 // of phase 2 reads the partials after the launch boundary.
-template <bool SINGLE, bool RECT = false>
+template <bool SINGLE, bool RECT = false, bool EXT = false>
 __device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int32_t r) {
     const uint32_t k = (uint32_t)(chunk * kBlock) + threadIdx.x;
     const double* x = o.x;
@@ -1444,15 +1446,16 @@ __device__ void gen_task(const DevModel& m, const EvalOut& o, int32_t chunk, int
             if (o.c) st(o.c + m.c_ref + row0, k, var);
             if (o.J) st(o.J + m.j_ref + row0, k, 1.0);
         }
-        if (o.f && r < m.npg) obj_partial<SINGLE>(m, o, chunk + (int64_t)m.ngchunks * r, fk);
+        if (o.f && r < m.npg) obj_partial<SINGLE, EXT>(m, o, chunk + (int64_t)m.ngchunks * r, fk);
     }
 }
 
 // Phase 2 of a two-launch model: f = the partials summed lane-strided in
 // index order, then a fixed wave tree.
+template <bool EXT>
 __device__ void obj_task(const DevModel& m, const EvalOut& o) {
     if (o.f == nullptr) return;
-    const int32_t total = obj_slots(m);
+    const int32_t total = EXT ? obj_slots(m) : m.ngchunks * m.npg;
     double acc = 0.0;
     for (int32_t q = threadIdx.x; q < total; q += kBlock) acc += m.obj_part[q];
     acc = wave_sum(acc);
@@ -1615,7 +1618,7 @@ __device__ void dev_task(const DevModel& m, const EvalOut& o, int32_t chunk, int
             if (o.J) st(o.J + m.j_dinit, d, 1.0);
         }
     }
-    if (o.f) obj_partial<SINGLE>(m, o, (int64_t)m.ngchunks * m.npg + chunk + (int64_t)m.ndchunks * r, fk);
+    if (o.f) obj_partial<SINGLE, true>(m, o, (int64_t)m.ngchunks * m.npg + chunk + (int64_t)m.ndchunks * r, fk);
 }
 
 // J^T v of the storage units: each unit's six variable entries (its rows
@@ -1671,24 +1674,24 @@ __device__ void jt_dev_task(const DevModel& m, const EvalOut& o, int32_t chunk, 
 // pointer (more than doubling the branch task's registers).
 // RECT selects the rectangular form's tasks (every kernel is instantiated
 // for both forms; a launch takes the model's).
-template <int MODE, bool RECT>
+template <int MODE, bool RECT, bool EXT>
 __device__ __forceinline__ void run_phase1(const DevModel& m, const EvalOut& o, int32_t kind, int32_t idx, int32_t r,
                                            double* stage) {
     if (MODE == 0) {
         if (kind == T_GEN)
-            gen_task<false, RECT>(m, o, idx, r);
-        else if (kind == T_STOR)
+            gen_task<false, RECT, EXT>(m, o, idx, r);
+        else if (EXT && kind == T_STOR)
             stor_task(m, o, idx, r);
-        else if (kind == T_DEV)
+        else if (EXT && kind == T_DEV)
             dev_task<false>(m, o, idx, r);
         else if (RECT)
             rbranch_task<false>(m, o, idx, r, stage);
         else
             branch_task<false>(m, o, idx, r, stage);
     } else if (MODE == 1) {
-        if (kind == T_STOR)
+        if (EXT && kind == T_STOR)
             jt_stor_task(m, o, idx, r);
-        else if (kind == T_DEV)
+        else if (EXT && kind == T_DEV)
             jt_dev_task(m, o, idx, r);
         else if (RECT)
             rjt_branch_task(m, o, idx, r);
@@ -1699,19 +1702,19 @@ __device__ __forceinline__ void run_phase1(const DevModel& m, const EvalOut& o, 
     }
 }
 
-template <int MODE, bool RECT>
+template <int MODE, bool RECT, bool EXT>
 __device__ __forceinline__ void run_phase2(const DevModel& m, const EvalOut& o, int32_t kind, int32_t idx, int32_t r,
                                            double* lds) {
     if (MODE == 0) {
         switch (kind) {
-        case T_BIG: big_task<false, RECT>(m, o, idx, r); break;
-        case T_WAVE: wave_task<false, RECT>(m, o, idx, r, lds); break;
-        default: obj_task(m, o); break;
+        case T_BIG: big_task<false, RECT, EXT>(m, o, idx, r); break;
+        case T_WAVE: wave_task<false, RECT, EXT>(m, o, idx, r, lds); break;
+        default: obj_task<EXT>(m, o); break;
         }
     } else {
         switch (kind) {
-        case T_BIG: jt_big_task<RECT>(m, o, idx, r); break;
-        case T_WAVE: jt_wave_task<RECT>(m, o, idx, r, lds); break;
+        case T_BIG: jt_big_task<RECT, EXT>(m, o, idx, r); break;
+        case T_WAVE: jt_wave_task<RECT, EXT>(m, o, idx, r, lds); break;
         default: jt_gen_task(m, o, idx, r); break;
         }
     }
@@ -1719,13 +1722,14 @@ __device__ __forceinline__ void run_phase2(const DevModel& m, const EvalOut& o, 
 
 // Item b of a plain launch; replicas outermost, so one XCD's contiguous
 // item range covers neighbouring entities of the same replicas.
+template <bool EXT>
 __device__ __forceinline__ void decode_phase1(const SetGrid& g, const DevModel& m, int32_t b, int32_t& kind,
                                               int32_t& idx, int32_t& r) {
     if (b < g.n_branch) {
         kind = T_BRANCH;
         idx = b % m.nbchunks;
         r = b / m.nbchunks;
-    } else if ((b -= g.n_branch) < g.n_gen1) {
+    } else if ((b -= g.n_branch) < g.n_gen1 || !EXT) {
         kind = T_GEN;
         idx = b % m.ngchunks;
         r = b / m.ngchunks;
@@ -1768,12 +1772,12 @@ __device__ __forceinline__ void decode_phase2(const SetGrid& g, const DevModel& 
     r = b / per;
 }
 
-template <int MODE, bool RECT>
+template <int MODE, bool RECT, bool EXT>
 __global__ void __launch_bounds__(kBlock, 6) branch_kernel(DevModel m, EvalOut o, SetGrid g) {
     __shared__ double stage[kRecStride * kBlock];
     int32_t kind, idx, r;
-    decode_phase1(g, m, xcd_item(blockIdx.x, gridDim.x), kind, idx, r);
-    run_phase1<MODE, RECT>(m, o, kind, idx, r, stage);
+    decode_phase1<EXT>(g, m, xcd_item(blockIdx.x, gridDim.x), kind, idx, r);
+    run_phase1<MODE, RECT, EXT>(m, o, kind, idx, r, stage);
 }
 
 // The single launch of a small model's callback set: items ordered branch
@@ -1782,7 +1786,7 @@ __global__ void __launch_bounds__(kBlock, 6) branch_kernel(DevModel m, EvalOut o
 // item waits for another).  Blocks are dealt to the XCDs round-robin, which
 // spreads every kind of item over all of them: a small launch is bound by
 // latency, not by the lines that neighbouring items share.
-template <bool RECT>
+template <bool RECT, bool EXT>
 __global__ void __launch_bounds__(kBlock) set_kernel_single(DevModel m, EvalOut o, SetGrid g) {
     __shared__ double lds[kRecStride * kBlock];
     int32_t b = blockIdx.x;
@@ -1795,34 +1799,36 @@ __global__ void __launch_bounds__(kBlock) set_kernel_single(DevModel m, EvalOut 
     }
     b -= g.n_branch;
     if (b < g.n_gen1) {
-        gen_task<true, RECT>(m, o, b % m.ngchunks, b / m.ngchunks);
+        gen_task<true, RECT, EXT>(m, o, b % m.ngchunks, b / m.ngchunks);
         return;
     }
     b -= g.n_gen1;
-    if (b < g.n_stor) {
-        stor_task(m, o, b % m.nschunks, b / m.nschunks);
-        return;
+    if constexpr (EXT) {
+        if (b < g.n_stor) {
+            stor_task(m, o, b % m.nschunks, b / m.nschunks);
+            return;
+        }
+        b -= g.n_stor;
+        if (b < g.n_dev) {
+            dev_task<true>(m, o, b % m.ndchunks, b / m.ndchunks);
+            return;
+        }
+        b -= g.n_dev;
     }
-    b -= g.n_stor;
-    if (b < g.n_dev) {
-        dev_task<true>(m, o, b % m.ndchunks, b / m.ndchunks);
-        return;
-    }
-    b -= g.n_dev;
     if (b < g.n_big) {
-        big_task<true, RECT>(m, o, b % m.nbig, b / m.nbig);
+        big_task<true, RECT, EXT>(m, o, b % m.nbig, b / m.nbig);
         return;
     }
     b -= g.n_big;
-    wave_task<true, RECT>(m, o, b % m.nwaves, b / m.nwaves, lds);
+    wave_task<true, RECT, EXT>(m, o, b % m.nwaves, b / m.nwaves, lds);
 }
 
-template <int MODE, bool RECT>
+template <int MODE, bool RECT, bool EXT>
 __global__ void __launch_bounds__(kBlock, 6) bus_kernel(DevModel m, EvalOut o, SetGrid g) {
     __shared__ double lds[kRecStride * kBlock];
     int32_t kind, idx, r;
     decode_phase2(g, m, xcd_item(blockIdx.x, gridDim.x), kind, idx, r);
-    run_phase2<MODE, RECT>(m, o, kind, idx, r, lds);
+    run_phase2<MODE, RECT, EXT>(m, o, kind, idx, r, lds);
 }
 
 // Occupancy hints (second launch-bounds argument: waves per SIMD) are the
@@ -1872,7 +1878,7 @@ __device__ __forceinline__ void xcd_stride(int32_t n, int32_t& first, int32_t& s
     end = (int32_t)((int64_t)n * (x + 1) / kXcd);
 }
 
-template <int MODE, bool RECT>
+template <int MODE, bool RECT, bool EXT>
 __global__ void __launch_bounds__(kBlock) batch_branch_kernel(BatchArgs a) {
     __shared__ double stage[kRecStride * kBlock];
     int32_t it, step, end;
@@ -1880,11 +1886,11 @@ __global__ void __launch_bounds__(kBlock) batch_branch_kernel(BatchArgs a) {
     for (; it < end; it += step) {
         const BatchItem w = a.items[it];
         const BatchInst& bi = a.inst[w.inst];
-        run_phase1<MODE, RECT>(bi.m, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, stage);
+        run_phase1<MODE, RECT, EXT>(bi.m, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, stage);
     }
 }
 
-template <int MODE, bool RECT>
+template <int MODE, bool RECT, bool EXT>
 __global__ void __launch_bounds__(kBlock) batch_bus_kernel(BatchArgs a) {
     __shared__ double lds[kRecStride * kBlock];
     int32_t it, step, end;
@@ -1892,12 +1898,12 @@ __global__ void __launch_bounds__(kBlock) batch_bus_kernel(BatchArgs a) {
     for (; it < end; it += step) {
         const BatchItem w = a.items[it];
         const BatchInst& bi = a.inst[w.inst];
-        run_phase2<MODE, RECT>(bi.m, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, lds);
+        run_phase2<MODE, RECT, EXT>(bi.m, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, lds);
         __syncthreads();
     }
 }
 
-template <int MODE, bool RECT>
+template <int MODE, bool RECT, bool EXT>
 __global__ void __launch_bounds__(kBlock) batch_branch_flat(BatchArgs a) {
     __shared__ double stage[kRecStride * kBlock];
     const int32_t it = xcd_item(blockIdx.x, gridDim.x);
@@ -1908,10 +1914,10 @@ __global__ void __launch_bounds__(kBlock) batch_branch_flat(BatchArgs a) {
     // of one dependent scalar round trip per branch that first uses them
     // (64-scenario batch: 97.5 -> 95.4 us)
     const DevModel mloc = bi.m;
-    run_phase1<MODE, RECT>(mloc, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, stage);
+    run_phase1<MODE, RECT, EXT>(mloc, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, stage);
 }
 
-template <int MODE, bool RECT>
+template <int MODE, bool RECT, bool EXT>
 __global__ void __launch_bounds__(kBlock, 5) batch_bus_flat(BatchArgs a) {
     __shared__ double lds[kRecStride * kBlock];
     const int32_t it = xcd_item(blockIdx.x, gridDim.x);
@@ -1922,7 +1928,7 @@ __global__ void __launch_bounds__(kBlock, 5) batch_bus_flat(BatchArgs a) {
     // of one dependent scalar round trip per branch that first uses them
     // (64-scenario batch: 97.5 -> 95.4 us)
     const DevModel mloc = bi.m;
-    run_phase2<MODE, RECT>(mloc, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, lds);
+    run_phase2<MODE, RECT, EXT>(mloc, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, lds);
 }
 
 SetGrid plan_set(const DevModel& m, const EvalOut& o, int32_t mode) {
@@ -1942,34 +1948,40 @@ SetGrid plan_set(const DevModel& m, const EvalOut& o, int32_t mode) {
     return g;
 }
 
-template <bool RECT>
+// The form (RECT) and the presence of storage units or devices (EXT) pick
+// the kernel instantiation.
+bool has_ext(const DevModel& m) { return m.S > 0 || m.D > 0; }
+
+template <bool RECT, bool EXT>
 hipError_t launch_set_form(const DevModel& m, const EvalOut& o, hipStream_t stream) {
     const SetGrid g = plan_set(m, o, 0);
     if (o.single) {
         const int32_t n = g.phase1() + g.phase2();
-        if (n > 0) hipLaunchKernelGGL(set_kernel_single<RECT>, dim3(n), dim3(kBlock), 0, stream, m, o, g);
+        if (n > 0) hipLaunchKernelGGL((set_kernel_single<RECT, EXT>), dim3(n), dim3(kBlock), 0, stream, m, o, g);
         return hipGetLastError();
     }
     if (g.phase1() > 0)
-        hipLaunchKernelGGL((branch_kernel<0, RECT>), dim3(g.phase1()), dim3(kBlock), 0, stream, m, o, g);
+        hipLaunchKernelGGL((branch_kernel<0, RECT, EXT>), dim3(g.phase1()), dim3(kBlock), 0, stream, m, o, g);
     if (g.phase2() > 0)
-        hipLaunchKernelGGL((bus_kernel<0, RECT>), dim3(g.phase2()), dim3(kBlock), 0, stream, m, o, g);
+        hipLaunchKernelGGL((bus_kernel<0, RECT, EXT>), dim3(g.phase2()), dim3(kBlock), 0, stream, m, o, g);
     return hipGetLastError();
 }
 
 hipError_t launch_eval_set(const DevModel& m, const EvalOut& o_in, hipStream_t stream) {
     EvalOut o = o_in;
     o.single = m.single;  // plain launches of small models take the single-launch shape
-    return m.rect ? launch_set_form<true>(m, o, stream) : launch_set_form<false>(m, o, stream);
+    if (has_ext(m))
+        return m.rect ? launch_set_form<true, true>(m, o, stream) : launch_set_form<false, true>(m, o, stream);
+    return m.rect ? launch_set_form<true, false>(m, o, stream) : launch_set_form<false, false>(m, o, stream);
 }
 
-template <bool RECT>
+template <bool RECT, bool EXT>
 hipError_t launch_jt_form(const DevModel& m, const EvalOut& o, hipStream_t stream) {
     const SetGrid g = plan_set(m, o, 1);
     if (g.phase1() > 0)
-        hipLaunchKernelGGL((branch_kernel<1, RECT>), dim3(g.phase1()), dim3(kBlock), 0, stream, m, o, g);
+        hipLaunchKernelGGL((branch_kernel<1, RECT, EXT>), dim3(g.phase1()), dim3(kBlock), 0, stream, m, o, g);
     if (g.phase2() > 0)
-        hipLaunchKernelGGL((bus_kernel<1, RECT>), dim3(g.phase2()), dim3(kBlock), 0, stream, m, o, g);
+        hipLaunchKernelGGL((bus_kernel<1, RECT, EXT>), dim3(g.phase2()), dim3(kBlock), 0, stream, m, o, g);
     return hipGetLastError();
 }
 
@@ -1978,31 +1990,34 @@ hipError_t launch_jtprod(const DevModel& m, const double* x, const double* v, do
     o.x = x;
     o.y = v;
     o.g = out;
-    return m.rect ? launch_jt_form<true>(m, o, stream) : launch_jt_form<false>(m, o, stream);
+    if (has_ext(m))
+        return m.rect ? launch_jt_form<true, true>(m, o, stream) : launch_jt_form<false, true>(m, o, stream);
+    return m.rect ? launch_jt_form<true, false>(m, o, stream) : launch_jt_form<false, false>(m, o, stream);
 }
 
-template <bool RECT>
+template <bool RECT, bool EXT>
 void* batch_kernel_form(int phase, int mode, bool flat) {
     if (flat) {
         if (phase == 0) {
-            if (mode == 0) return reinterpret_cast<void*>(&batch_branch_flat<0, RECT>);
-            if (mode == 1) return reinterpret_cast<void*>(&batch_branch_flat<1, RECT>);
-            return reinterpret_cast<void*>(&batch_branch_flat<2, RECT>);
+            if (mode == 0) return reinterpret_cast<void*>(&batch_branch_flat<0, RECT, EXT>);
+            if (mode == 1) return reinterpret_cast<void*>(&batch_branch_flat<1, RECT, EXT>);
+            return reinterpret_cast<void*>(&batch_branch_flat<2, RECT, EXT>);
         }
-        return mode == 0 ? reinterpret_cast<void*>(&batch_bus_flat<0, RECT>)
-                         : reinterpret_cast<void*>(&batch_bus_flat<1, RECT>);
+        return mode == 0 ? reinterpret_cast<void*>(&batch_bus_flat<0, RECT, EXT>)
+                         : reinterpret_cast<void*>(&batch_bus_flat<1, RECT, EXT>);
     }
     if (phase == 0) {
-        if (mode == 0) return reinterpret_cast<void*>(&batch_branch_kernel<0, RECT>);
-        if (mode == 1) return reinterpret_cast<void*>(&batch_branch_kernel<1, RECT>);
-        return reinterpret_cast<void*>(&batch_branch_kernel<2, RECT>);
+        if (mode == 0) return reinterpret_cast<void*>(&batch_branch_kernel<0, RECT, EXT>);
+        if (mode == 1) return reinterpret_cast<void*>(&batch_branch_kernel<1, RECT, EXT>);
+        return reinterpret_cast<void*>(&batch_branch_kernel<2, RECT, EXT>);
     }
-    return mode == 0 ? reinterpret_cast<void*>(&batch_bus_kernel<0, RECT>)
-                     : reinterpret_cast<void*>(&batch_bus_kernel<1, RECT>);
+    return mode == 0 ? reinterpret_cast<void*>(&batch_bus_kernel<0, RECT, EXT>)
+                     : reinterpret_cast<void*>(&batch_bus_kernel<1, RECT, EXT>);
 }
 
-void* batch_kernel_fn(int phase, int mode, bool flat, bool rect) {
-    return rect ? batch_kernel_form<true>(phase, mode, flat) : batch_kernel_form<false>(phase, mode, flat);
+void* batch_kernel_fn(int phase, int mode, bool flat, bool rect, bool ext) {
+    if (ext) return rect ? batch_kernel_form<true, true>(phase, mode, flat) : batch_kernel_form<false, true>(phase, mode, flat);
+    return rect ? batch_kernel_form<true, false>(phase, mode, flat) : batch_kernel_form<false, false>(phase, mode, flat);
 }
 
 size_t scratch_bytes(const DevModel& m) {
