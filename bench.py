@@ -361,7 +361,8 @@ def bench_batch(args, torch, opf, synth, log):
     batched()
     torch.cuda.synchronize()
     # plain launches of these models take the one-launch shape (recomputed
-    # branch terms), batches the two-launch shape: equal up to rounding
+    # branch terms), batches the two-launch shape: bitwise equal (the
+    # kernels contract no floating-point operation)
     bitwise = all(torch.equal(a, b) for a, b in zip(ref, (F, G, C, J, H)))
     max_rel = max(float(((a - b).abs() / b.abs().clamp(min=1.0)).max()) for a, b in zip((F, G, C, J, H), ref))
     # both forms captured the same way: one HIP graph of `reps` passes over

@@ -53,6 +53,13 @@
 #include "dev_model.h"
 #include "eval_kernels.h"
 
+// No floating-point contraction anywhere in these kernels: every multiply
+// and add rounds on its own, so an expression gives bitwise the same value
+// in every kernel that inlines it (a one-launch set, whose bus lanes
+// recompute the branch terms, equals the two-launch set and the batch bit
+// for bit), and each operation rounds as in the oracle.
+#pragma clang fp contract(off)
+
 namespace opf {
 
 namespace {
@@ -188,7 +195,8 @@ __device__ __forceinline__ Flow1 flow1(double al, double be, double a, double b,
 
 // Second-order terms of sum_r (-y_r) F_r over the four flow rows of a branch
 // (each row is p_arc - F_r).  hess F is linear in (alpha, beta, a, b), so the
-// weighted sum needs one trig evaluation.
+// weighted sum needs one trig evaluation.  The branch items (records) and
+// the one-launch bus lanes (recompute) both call it.
 struct Hterms {
     double Suu, Sww, Suw, Stt, Sut, Swt;  // d2/du2, dw2, du dw, dth2, du dth, dw dth
 };
