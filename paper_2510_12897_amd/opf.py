@@ -161,6 +161,44 @@ def lib():
     return L
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+# every callback pair ever installed: a model calls its creation-time hook
+# again when it is destroyed, so none may be freed
+_hooks = []
+
+
+def set_allocator(alloc=None, release=None):
+    """Device memory hook for models and batches created afterwards:
+    alloc(nbytes) -> int device address (0 on failure, which makes create
+    fail with OPF_E_NOMEM), release(address).  None, None restores hipMalloc
+    / hipFree."""
+    L = lib()
+    L.opf_set_allocator.argtypes = [_ALLOC_FN, _RELEASE_FN, ctypes.c_void_p]
+    L.opf_set_allocator.restype = None
+    if alloc is None:
+        L.opf_set_allocator(_ALLOC_FN(), _RELEASE_FN(), None)
+        return
+    a = _ALLOC_FN(lambda n, ctx: int(alloc(int(n)) or 0) or None)
+    r = _RELEASE_FN(lambda p, ctx: release(int(p)) if p else None)
+    L.opf_set_allocator(a, r, None)
+    _hooks.append((a, r))
+
+
+def use_torch_allocator(device: int = 0):
+    """Route model and batch storage through torch's caching allocator on
+    `device` (its current stream at allocation time)."""
+    torch = _torch()
+
+    def alloc(n):
+        return torch.cuda.caching_allocator_alloc(n, device)
+
+    def release(p):
+        torch.cuda.caching_allocator_delete(p)
+
+    set_allocator(alloc, release)
+
+
 def set_single_launch_limit(waves: int):
     """Models created afterwards evaluate a callback set in one launch when it
     is at most `waves` work items (0: always two launches)."""
