@@ -380,6 +380,20 @@ def bench_batch(args, torch, opf, synth, log):
     per_launch = secs_b / (3 * reps)
     secs_p, _ = time_steps(torch, graph.replay, 3, 1)
     per_plain = secs_p / (3 * reps)
+    # every schedule the tuner chooses from, the same way (a graph of `reps`
+    # evaluations), so the choice can be read off the record
+    sched_us = {}
+    for wg in (-1, 0, 4, 16):
+        batch.set_schedule(wg)
+        g_s = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g_s, stream=s):
+            for k in range(reps):
+                batched(k)
+        torch.cuda.synchronize()
+        secs_s, _ = time_steps(torch, g_s.replay, 2, 1)
+        sched_us[str(wg)] = secs_s / (2 * reps) * 1e6
+        del g_s
+    batch.set_schedule(sched)
     total_bytes = sum(algorithmic_bytes(nets[inst_model[i]], (
         int(batch.xoff[i + 1] - batch.xoff[i]), int(batch.coff[i + 1] - batch.coff[i]),
         int(batch.joff[i + 1] - batch.joff[i]), int(batch.hoff[i + 1] - batch.hoff[i]))) for i in range(n_inst))
@@ -389,7 +403,8 @@ def bench_batch(args, torch, opf, synth, log):
     total_bytes -= 7 * shared
     log(f"batch: batched {per_launch * 1e6:.1f} us/evaluation in a graph ({per_eager * 1e6:.1f} us issued eagerly), "
         f"plain {per_plain * 1e6:.1f} us/64 sets, "
-        f"bitwise equal: {bitwise}, max |diff| / max(|plain|, 1): {max_rel:.3g}")
+        f"bitwise equal: {bitwise}, max |diff| / max(|plain|, 1): {max_rel:.3g}; by schedule (us): "
+        + ", ".join(f"{k}: {v:.1f}" for k, v in sched_us.items()))
     out = dict(
         workload="64 scenarios = 8 networks (500..20000 buses, L=1.35N, G=0.2N) x 8 load seeds",
         batched_sets_per_s=n_inst / per_launch, plain_sets_per_s=n_inst / per_plain,
@@ -398,7 +413,10 @@ def bench_batch(args, torch, opf, synth, log):
                f"{n_xy} input and {n_o} output sets (about 1 GB, past the Infinity Cache)",
         us_per_eval_eager=per_eager * 1e6, speedup_eager=per_plain / per_eager,
         achieved_gbs=total_bytes / per_launch / 1e9, frac=total_bytes / per_launch / 1e9 / HBM_PEAK_GBS,
-        schedule=dict(wg_per_cu=sched), bitwise_equal_to_plain=bool(bitwise), max_rel_diff_to_plain=max_rel)
+        schedule=dict(wg_per_cu=sched, us_per_eval_by_schedule=sched_us,
+                      legend="-1 one launch (bus lanes recompute the branch terms); 0 two flat launches; "
+                             "k > 0 two persistent launches of k workgroups per CU"),
+        bitwise_equal_to_plain=bool(bitwise), max_rel_diff_to_plain=max_rel)
     batch.close()
     for mdl in models + plain_models:
         mdl.close()

@@ -212,11 +212,11 @@ void opf_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
  * replicas) evaluates a set in ONE launch, its bus items recomputing the
  * branch terms they need (a small set is latency-bound); larger models use
  * two launches (branch items leave per-half-edge records that bus items
- * read).  A model keeps its shape for life; repeated calls are bitwise
- * reproducible.  Batches (opf_batch_eval) and J^T v always use the two
- * launches, so a one-launch model's plain and batched results agree to
- * rounding, a two-launch model's bitwise.  0 disables the single launch; the
- * default is 4096.  OPF_E_ARG for a negative limit. */
+ * read).  A model keeps its shape for life.  Both shapes give bitwise the
+ * same results (no floating-point contraction in the kernels), and so do
+ * batches (opf_batch_eval) in either of their shapes.  J^T v always uses
+ * two launches.  0 disables the single launch; the default is 4096.
+ * OPF_E_ARG for a negative limit. */
 int opf_set_single_launch_limit(int64_t waves);
 
 /* Validate, derive branch admittance terms, adjacency and pattern on the
@@ -321,26 +321,31 @@ int opf_batch_destroy(opf_batch batch);
 int opf_batch_offsets(opf_batch batch, int64_t *xoff, int64_t *coff, int64_t *joff,
                       int64_t *hoff);
 
-/* Time the candidate schedules (flat, and persistent grids of 2 to 32
- * workgroups per compute unit) on this batch, each the best of three rounds
- * interleaved over the candidates, and keep the fastest in the handle.  Results of opf_batch_eval do not depend on the schedule.
- * Allocates tuning buffers through the allocator; synchronises `stream`. */
+/* Time the candidate schedules on this batch, each the best of three
+ * rounds interleaved over the candidates, and keep the fastest in the
+ * handle: the launch shape (one launch whose bus lanes recompute the branch
+ * terms, or two launches passing records) and, for two launches, the grid
+ * (flat, or persistent with 2 to 32 workgroups per compute unit).  Results
+ * of opf_batch_eval do not depend on the schedule (bitwise).  Allocates
+ * tuning buffers through the allocator; synchronises `stream`. */
 int opf_batch_tune(opf_batch batch, void *stream);
 
-/* The schedule in use: persistent workgroups per compute unit, or 0 for a
- * flat launch (one workgroup per work item). */
+/* The schedule in use: -1 for the one-launch shape, 0 for two flat
+ * launches (one workgroup per work item), else two persistent launches of
+ * wg_per_cu workgroups per compute unit.  J^T v (opf_batch_jtprod) always
+ * takes two launches, flat when the schedule is -1 or 0. */
 int opf_batch_schedule(opf_batch batch, int32_t *wg_per_cu);
 
-/* Force a schedule: wg_per_cu in [0, 64] (else OPF_E_ARG). */
+/* Force a schedule: wg_per_cu in [-1, 64] (else OPF_E_ARG). */
 int opf_batch_set_schedule(opf_batch batch, int32_t wg_per_cu);
 
-/* All callbacks of every instance: the branch-phase and bus-phase kernels
- * at the current schedule, launched on `stream` with this call's buffers
- * as kernel arguments (no allocation; the launches can be captured into a
- * HIP graph).  sigma[n_inst] are the objective weights.  Any of F, G, C,
- * J, H may be NULL (skipped); Y and sigma may be NULL when H is.  Results are bitwise
- * equal to opf_eval_set on each instance's model in the two-launch shape,
- * and equal to rounding for a model in the one-launch shape. */
+/* All callbacks of every instance in one or two kernel launches (the
+ * schedule), launched on `stream` with this call's buffers as kernel
+ * arguments (no allocation; the launches can be captured into a HIP
+ * graph).  sigma[n_inst] are the objective weights.  Any of F, G, C, J, H
+ * may be NULL (skipped); Y and sigma may be NULL when H is.  Results are
+ * bitwise equal to opf_eval_set on each instance's model, in either launch
+ * shape. */
 int opf_batch_eval(opf_batch batch, const double *X, const double *Y, const double *sigma,
                    double *F, double *G, double *C, double *J, double *H, void *stream);
 

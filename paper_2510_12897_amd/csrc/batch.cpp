@@ -24,8 +24,9 @@ using namespace opf_internal;
 
 namespace {
 
-// autotuner candidates: flat, then persistent grids
-const int32_t kWgPerCu[] = {0, 2, 4, 8, 16, 32};
+// autotuner candidates: the one-launch shape (-1), flat two launches (0),
+// then persistent two-launch grids
+const int32_t kWgPerCu[] = {-1, 0, 2, 4, 8, 16, 32};
 
 }  // namespace
 
@@ -42,7 +43,9 @@ struct opf_batch_s {
     int64_t n_loads = 0;
     opf::BatchItem* items[2][2] = {};  // device item lists, [mode (0 set, 1 J^T v)][phase]
     int32_t n_items[2][2] = {};
-    int32_t wg_per_cu = 0;           // flat until tuned (measured fastest on the 64-instance mix)
+    opf::BatchItem* items_single = nullptr;  // the one-launch shape's list (callback sets)
+    int32_t n_items_single = 0;
+    int32_t wg_per_cu = 0;           // -1: one launch; 0: flat two launches; > 0: persistent two launches
     int32_t n_cu = 256;
     bool rect = false;               // every model is of the rectangular form (else all polar)
     bool ext = false;                // some model has storage units or devices
@@ -90,6 +93,19 @@ void make_items(const std::vector<opf::DevModel>& dms, int mode, int phase, std:
 }
 
 int launch(opf_batch_s* b, const opf::BatchArgs& a0, hipStream_t stream) {
+    if (a0.mode == 0 && b->wg_per_cu < 0) {
+        // one launch: every item of every instance, bus lanes recomputing the
+        // branch terms, the objective by each instance's arrival ticket
+        opf::BatchArgs a = a0;
+        a.inst = b->inst;
+        a.items = b->items_single;
+        a.n_items = b->n_items_single;
+        if (a.n_items == 0) return OPF_OK;
+        void* args[1] = {&a};
+        const hipError_t e = hipLaunchKernel(opf::batch_single_fn(b->rect, b->ext), dim3(a.n_items),
+                                             dim3(opf::kBlock), args, 0, stream);
+        return e == hipSuccess ? OPF_OK : hip_err(e, "batch one-launch");
+    }
     opf::BatchArgs a[2];
     int32_t grid[2];
     const int lm = a0.mode == 2 ? 0 : a0.mode;  // the flows mode runs the branch items only
@@ -99,13 +115,13 @@ int launch(opf_batch_s* b, const opf::BatchArgs& a0, hipStream_t stream) {
         a[ph].items = b->items[lm][ph];
         a[ph].n_items = (a0.mode == 2 && ph == 1) ? 0 : b->n_items[lm][ph];
         // persistent: at least one workgroup per XCD, so every XCD's range is drained
-        grid[ph] = b->wg_per_cu == 0 ? std::max(1, a[ph].n_items)
+        grid[ph] = b->wg_per_cu <= 0 ? std::max(1, a[ph].n_items)
                                       : std::max(opf::kXcd, std::min(a[ph].n_items, b->n_cu * b->wg_per_cu));
     }
     for (int ph = 0; ph < 2; ph++) {
         if (a[ph].n_items == 0) continue;
         void* args[1] = {&a[ph]};
-        const hipError_t e = hipLaunchKernel(opf::batch_kernel_fn(ph, a0.mode, b->wg_per_cu == 0, b->rect, b->ext),
+        const hipError_t e = hipLaunchKernel(opf::batch_kernel_fn(ph, a0.mode, b->wg_per_cu <= 0, b->rect, b->ext),
                                              dim3(grid[ph]), dim3(opf::kBlock), args, 0, stream);
         if (e != hipSuccess) return hip_err(e, ph == 0 ? "batch branch-phase launch" : "batch bus-phase launch");
     }
@@ -178,12 +194,24 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
         const size_t o_inst = pk.reserve(sizeof(opf::BatchInst) * n_inst);
         std::vector<opf::DevModel> dms(n_inst);
         for (int32_t j = 0; j < n_inst; j++) dms[j] = models[inst_model[j]]->dm;
-        size_t lst_off[2][2];
+        size_t lst_off[2][2], lst_single = 0;
         std::vector<opf::BatchItem> items;
         for (int q = 0; q < 4; q++) {  // (mode, phase)
             make_items(dms, q / 2, q % 2, items);
             lst_off[q / 2][q % 2] = pk.add(items);
             b->n_items[q / 2][q % 2] = (int32_t)items.size();
+        }
+        // the one-launch shape: the callback set's phase-1 items, then its
+        // phase-2 items without the objective items (each instance sums its
+        // objective by ticket)
+        {
+            std::vector<opf::BatchItem> all, p2;
+            make_items(dms, 0, 0, all);
+            make_items(dms, 0, 1, p2);
+            for (const opf::BatchItem& w : p2)
+                if (w.kind != opf::T_OBJ) all.push_back(w);
+            lst_single = pk.add(all);
+            b->n_items_single = (int32_t)all.size();
         }
 
         DeviceGuard dg(dev);
@@ -218,6 +246,7 @@ int opf_batch_create(const opf_model* models, int32_t n_models, const int32_t* i
         }
         for (int q = 0; q < 4; q++)
             b->items[q / 2][q % 2] = reinterpret_cast<opf::BatchItem*>(base + lst_off[q / 2][q % 2]);
+        b->items_single = reinterpret_cast<opf::BatchItem*>(base + lst_single);
         hipError_t e = hipMemcpy(b->arena, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             dev_free(b->alloc, b->arena);
@@ -269,7 +298,7 @@ int opf_batch_schedule(opf_batch b, int32_t* wg_per_cu) {
 
 int opf_batch_set_schedule(opf_batch b, int32_t wg_per_cu) {
     if (!valid(b)) return set_err(OPF_E_STATE, "invalid or destroyed batch handle");
-    if (wg_per_cu < 0 || wg_per_cu > 64) return set_err(OPF_E_ARG, "wg_per_cu must be in [0, 64]");
+    if (wg_per_cu < -1 || wg_per_cu > 64) return set_err(OPF_E_ARG, "wg_per_cu must be in [-1, 64]");
     b->wg_per_cu = wg_per_cu;
     return OPF_OK;
 }

@@ -52,4 +52,9 @@ size_t scratch_bytes(const DevModel& m);
 // instance (argument: BatchArgs).
 void* batch_kernel_fn(int phase, int mode, bool flat, bool rect, bool ext);
 
+// The one-launch batch kernel of callback sets (one workgroup per item:
+// branch, generator, storage, device, wide-bus and wave items of every
+// instance; bus lanes recompute the branch terms; objective by ticket).
+void* batch_single_fn(bool rect, bool ext);
+
 }  // namespace opf

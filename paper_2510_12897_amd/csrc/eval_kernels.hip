@@ -1939,6 +1939,38 @@ __global__ void __launch_bounds__(kBlock, 5) batch_bus_flat(BatchArgs a) {
     run_phase2<MODE, RECT, EXT>(mloc, batch_out<MODE>(a, bi, w.inst), w.kind, w.idx, w.r, lds);
 }
 
+// The one-launch shape over a batch: one workgroup per item (in list order,
+// dealt round-robin to the XCDs like the plain one-launch kernel), every
+// task in its one-launch form.
+template <bool RECT, bool EXT>
+__global__ void __launch_bounds__(kBlock) batch_single_flat(BatchArgs a) {
+    __shared__ double lds[kRecStride * kBlock];
+    const int32_t it = blockIdx.x;
+    if (it >= a.n_items) return;
+    const BatchItem w = a.items[it];
+    const BatchInst& bi = a.inst[w.inst];
+    const DevModel m = bi.m;
+    EvalOut o = batch_out<0>(a, bi, w.inst);
+    o.single = 1;
+    switch (w.kind) {
+    case T_BRANCH:
+        if (RECT)
+            rbranch_task<true>(m, o, w.idx, w.r, lds);
+        else
+            branch_task<true>(m, o, w.idx, w.r, lds);
+        break;
+    case T_GEN: gen_task<true, RECT, EXT>(m, o, w.idx, w.r); break;
+    case T_STOR:
+        if (EXT) stor_task(m, o, w.idx, w.r);
+        break;
+    case T_DEV:
+        if (EXT) dev_task<true>(m, o, w.idx, w.r);
+        break;
+    case T_BIG: big_task<true, RECT, EXT>(m, o, w.idx, w.r); break;
+    default: wave_task<true, RECT, EXT>(m, o, w.idx, w.r, lds); break;
+    }
+}
+
 SetGrid plan_set(const DevModel& m, const EvalOut& o, int32_t mode) {
     SetGrid g{};
     const bool any = mode == 1 || o.g || o.c || o.J || o.H;
@@ -2021,6 +2053,14 @@ void* batch_kernel_form(int phase, int mode, bool flat) {
     }
     return mode == 0 ? reinterpret_cast<void*>(&batch_bus_kernel<0, RECT, EXT>)
                      : reinterpret_cast<void*>(&batch_bus_kernel<1, RECT, EXT>);
+}
+
+void* batch_single_fn(bool rect, bool ext) {
+    if (ext)
+        return rect ? reinterpret_cast<void*>(&batch_single_flat<true, true>)
+                    : reinterpret_cast<void*>(&batch_single_flat<false, true>);
+    return rect ? reinterpret_cast<void*>(&batch_single_flat<true, false>)
+                : reinterpret_cast<void*>(&batch_single_flat<false, false>);
 }
 
 void* batch_kernel_fn(int phase, int mode, bool flat, bool rect, bool ext) {

@@ -517,7 +517,8 @@ class Batch:
         return self.schedule()
 
     def schedule(self) -> int:
-        """Persistent workgroups per compute unit (0: one workgroup per item)."""
+        """-1: one launch; 0: two flat launches (one workgroup per item);
+        else two persistent launches of this many workgroups per CU."""
         wg = ctypes.c_int32()
         _check(lib().opf_batch_schedule(self._h, ctypes.byref(wg)))
         return wg.value

@@ -141,7 +141,7 @@ def test_batch_equals_plain_bitwise_every_schedule(shape):
     X, Y, sig, xs, ys = fill_inputs(batch, plain)
     ref = plain_reference(batch, plain, X, Y, sig)
     first = None
-    for wg in (0, 1, 2, 4, 16, 32):
+    for wg in (0, -1, 1, 2, 4, 16, 32):
         say(f"[batch] schedule wg_per_cu={wg}")
         batch.set_schedule(wg)
         out = outputs(batch)
@@ -193,7 +193,7 @@ def test_batch_repeated_evals_and_partial_outputs():
     opf.set_single_launch_limit(4096)
 
 
-@pytest.mark.parametrize("wg_per_cu", [0, 4])
+@pytest.mark.parametrize("wg_per_cu", [0, 4, -1])
 def test_batch_eval_captured_in_graph(wg_per_cu):
     """The batch's two launches captured into a HIP graph: every replay, with
     eager work in between, is bitwise the eager evaluation."""

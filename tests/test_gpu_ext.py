@@ -183,7 +183,7 @@ def test_ext_batch_bitwise_equal_to_two_launch_plain():
     ys = [synth.multipliers(models[j].m, (106, i)) for i, j in enumerate(inst)]
     X, Y = to_dev(np.concatenate(xs)), to_dev(np.concatenate(ys))
     S = torch.linspace(0.5, 1.5, len(inst), dtype=torch.float64, device=DEV)
-    for wg in (0, 4):
+    for wg in (0, 4, -1):
         batch.set_schedule(wg)
         say(f"[ext batch] schedule {wg}")
         out = (torch.empty(len(inst), dtype=torch.float64, device=DEV),) + tuple(
