@@ -1,0 +1,334 @@
+"""A GPU-resident interior-point solver that consumes the callbacks: the
+solver configuration of Sec. IV-A3 that runs MadNLP with the LiftedKKT
+condensed system on the GPU.
+
+Every callback (f, grad f, c, J, H of the Lagrangian) is one call into the
+model (for an ``opf.Model``: libopf's kernels), and every solver vector stays
+on the model's device.  The linear algebra is dense: the condensed matrix
+
+    K = W + Sigma_x + J^T Sigma_s J  (+ delta I)
+
+is assembled on the device (the J^T Sigma_s J products are scattered through
+a pair list built once from the Jacobian pattern) and factored by torch's
+dense Cholesky (rocSOLVER on ROCm).  The paper's GPU configuration factors K
+with a sparse direct solver; without one, this solver is meant for networks
+up to a few thousand buses (``max_dense_n`` variables), and it reports where
+its time goes (callbacks, linear algebra, the rest), the split of the
+paper's Fig. 5.
+
+The algorithm is a primal-dual barrier method in the form of Waechter and
+Biegler's Ipopt, with the LiftedKKT treatment of equalities (Pacaud and
+Shin, condensed-space interior-point methods):
+
+* every constraint row gets a slack s with c(x) - s = 0 and lcon <= s <=
+  ucon; an equality row's bounds are relaxed by ``relax`` (default: the
+  tolerance) on each side, so every slack has an interior and the
+  condensed K is positive definite once W is regularised;
+* the Newton step of the barrier KKT system condenses onto dx:
+      K dx = -r_x - J^T (Sigma_s r_c + r_s),  ds = J dx + r_c,
+      dlam = Sigma_s ds + r_s,
+  with r_x = grad f + J^T lam - mu/(x - l) + mu/(u - x),
+  r_s = -lam - mu/(s - lcon) + mu/(ucon - s), r_c = c(x) - s, and the
+  Sigma the bound-dual over distance ratios; delta grows (1e-8, then x 8)
+  until the Cholesky factorization succeeds;
+* fraction-to-the-boundary rule with tau = max(0.99, 1 - mu), separate
+  primal and bound-dual step lengths, backtracking on the l1 merit function
+  f - mu sum log(distances) + nu |c(x) - s|_1 with an Armijo condition;
+* monotone barrier update mu <- max(tol / 10, min(0.2 mu, mu^1.5)) once the
+  barrier problem is solved to 10 mu; bound duals are kept within a factor
+  1e10 of mu / distance; stop when the scaled KKT error is at most tol.
+
+``model`` is anything with the ``opf.Model`` callback surface: ``n``, ``m``,
+``bounds()``, ``jac_structure()``, ``hess_structure()``,
+``eval_set(x, y, w)``, ``obj(x)`` and ``cons(x)`` returning tensors on one
+device.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class InteriorPoint:
+    """Solve min f(x) s.t. lcon <= c(x) <= ucon, lvar <= x <= uvar."""
+
+    def __init__(self, model, tol: float = 1e-6, relax: float | None = None, max_iter: int = 300,
+                 mu0: float = 0.1, max_dense_n: int = 40000, verbose: bool = False):
+        torch = _torch()
+        self.model = model
+        self.tol = float(tol)
+        self.relax = self.tol if relax is None else float(relax)
+        self.max_iter, self.mu0, self.verbose = int(max_iter), float(mu0), verbose
+        n, m = int(model.n), int(model.m)
+        if n > max_dense_n:
+            raise ValueError(f"ipm: {n} variables exceed the dense limit max_dense_n = {max_dense_n}")
+        self.n, self.m = n, m
+        b = model.bounds()
+        self.lv, self.uv, self.x0 = b["lvar"], b["uvar"], b["x0"]
+        self.lc0, self.uc0 = b["lcon"], b["ucon"]
+        self.dev = self.lv.device
+        eq = self.lc0 == self.uc0
+        self.lc = torch.where(eq, self.lc0 - self.relax, self.lc0)
+        self.uc = torch.where(eq, self.uc0 + self.relax, self.uc0)
+        self.hxl, self.hxu = torch.isfinite(self.lv), torch.isfinite(self.uv)
+        self.hsl, self.hsu = torch.isfinite(self.lc), torch.isfinite(self.uc)
+        jr, jc = (t.long() for t in model.jac_structure())
+        hr, hc = (t.long() for t in model.hess_structure())
+        self.jr, self.jc = jr, jc
+        # K index of every Hessian value, both triangles
+        off = hr != hc
+        self.h_src = torch.cat([torch.arange(hr.numel(), device=self.dev), torch.nonzero(off)[:, 0]])
+        self.h_dst = torch.cat([hr * n + hc, (hc * n + hr)[off]])
+        # ordered pairs (a, b) of Jacobian entries in one row r:
+        # K[col a, col b] += Sigma_s[r] J_a J_b
+        self.p_a, self.p_b, self.p_row, self.p_dst = self._pairs(jr.cpu().numpy(), jc.cpu().numpy(), n)
+        self.K = torch.empty(n * n, dtype=torch.float64, device=self.dev)
+        self.times = {"callbacks": 0.0, "linear_algebra": 0.0, "other": 0.0}
+        self.counts = {"eval_set": 0, "obj_cons": 0, "factorizations": 0}
+
+    def _pairs(self, jr, jc, n):
+        torch = _torch()
+        order = np.argsort(jr, kind="stable")
+        starts = np.searchsorted(jr[order], np.arange(self.m + 1))
+        cnt = np.diff(starts)
+        tot = int((cnt.astype(np.int64) ** 2).sum())
+        a = np.empty(tot, np.int64)
+        b = np.empty(tot, np.int64)
+        r = np.empty(tot, np.int64)
+        pos = 0
+        for c in np.unique(cnt):
+            if c == 0:
+                continue
+            sel = np.nonzero(cnt == c)[0]
+            ent = order[starts[sel][:, None] + np.arange(c)[None, :]]      # (rows, c) entry indices
+            w = ent.shape[0] * c * c
+            a[pos:pos + w] = np.repeat(ent, c, axis=1).ravel()
+            b[pos:pos + w] = np.tile(ent, (1, c)).ravel()
+            r[pos:pos + w] = np.repeat(sel, c * c)
+            pos += w
+        dst = jc[a].astype(np.int64) * n + jc[b]
+
+        def dev(v):
+            return torch.from_numpy(v).to(self.dev)
+        return dev(a), dev(b), dev(r), dev(dst)
+
+    # ---------------------------------------------------------------- helpers
+    def _sync(self):
+        if self.dev.type == "cuda":
+            _torch().cuda.synchronize(self.dev)
+
+    def _timed(self, part, fn, *a):
+        self._sync()
+        t0 = time.perf_counter()
+        out = fn(*a)
+        self._sync()
+        self.times[part] += time.perf_counter() - t0
+        return out
+
+    def _eval(self, x, lam):
+        self.counts["eval_set"] += 1
+        return self.model.eval_set(x, lam, 1.0)
+
+    def _obj_cons(self, x):
+        self.counts["obj_cons"] += 1
+        return self.model.obj(x), self.model.cons(x)
+
+    def _interior(self, v, lo, hi, hl, hu, k1=1e-2, k2=1e-2):
+        """Move v into the interior of [lo, hi] (Ipopt's initial-point
+        push: at least k1 max(1, |bound|) from a bound, at most k2 of the
+        gap)."""
+        torch = _torch()
+        lo0 = torch.where(hl, lo, torch.zeros_like(lo))
+        hi0 = torch.where(hu, hi, torch.zeros_like(hi))
+        both = hl & hu
+        pl = k1 * torch.clamp(lo0.abs(), min=1.0)
+        pu = k1 * torch.clamp(hi0.abs(), min=1.0)
+        pl = torch.where(both, torch.minimum(pl, k2 * (hi0 - lo0)), pl)
+        pu = torch.where(both, torch.minimum(pu, k2 * (hi0 - lo0)), pu)
+        v = torch.where(hl, torch.maximum(v, lo0 + pl), v)
+        v = torch.where(hu, torch.minimum(v, hi0 - pu), v)
+        return v
+
+    def _dist(self, x, s):
+        """Distances to the four bound sets (1 where a bound is absent)."""
+        torch = _torch()
+        one = torch.ones((), dtype=torch.float64, device=self.dev)
+        return (torch.where(self.hxl, x - self.lv, one), torch.where(self.hxu, self.uv - x, one),
+                torch.where(self.hsl, s - self.lc, one), torch.where(self.hsu, self.uc - s, one))
+
+    def _jt(self, jv, v):
+        torch = _torch()
+        return torch.zeros(self.n, dtype=torch.float64, device=self.dev).index_add_(0, self.jc, jv * v[self.jr])
+
+    def _kkt(self, mu, g, c, jv, x, s, lam, z):
+        """Scaled KKT error of the barrier problem at mu (Ipopt's E_mu with
+        s_max = 100)."""
+        torch = _torch()
+        zl, zu, vl, vu = z
+        dlx, dux, dls, dus = self._dist(x, s)
+        rdx = g + self._jt(jv, lam) - zl + zu
+        rds = -lam - vl + vu
+        comp = torch.cat([(dlx * zl - mu)[self.hxl], (dux * zu - mu)[self.hxu],
+                          (dls * vl - mu)[self.hsl], (dus * vu - mu)[self.hsu]])
+        nz = comp.numel()
+        zsum = float(zl.abs().sum() + zu.abs().sum() + vl.abs().sum() + vu.abs().sum())
+        s_d = max(100.0, (float(lam.abs().sum()) + zsum) / max(self.m + nz, 1)) / 100.0
+        s_c = max(100.0, zsum / max(nz, 1)) / 100.0
+        e_d = float(torch.cat([rdx, rds]).abs().max())
+        e_p = float((c - s).abs().max()) if self.m else 0.0
+        e_c = float(comp.abs().max()) if nz else 0.0
+        return max(e_d / s_d, e_p, e_c / s_c)
+
+    def _assemble_factor(self, hv, jv, Sx, Ss, rhs, delta0):
+        torch = _torch()
+        n = self.n
+        K = self.K
+        K.zero_()
+        K.index_add_(0, self.h_dst, hv[self.h_src])
+        K.index_add_(0, self.p_dst, Ss[self.p_row] * jv[self.p_a] * jv[self.p_b])
+        Kd = K.view(n, n)
+        Kd.diagonal().add_(Sx)
+        delta = delta0
+        while True:
+            if delta > 0:
+                Kd.diagonal().add_(delta)
+            L, info = torch.linalg.cholesky_ex(Kd)
+            self.counts["factorizations"] += 1
+            if int(info) == 0:
+                break
+            if delta > 0:
+                Kd.diagonal().sub_(delta)
+            delta = 1e-8 if delta == 0.0 else 8.0 * delta
+            if delta > 1e40:
+                raise FloatingPointError("ipm: no regularisation makes the condensed matrix positive definite")
+        return torch.cholesky_solve(rhs[:, None], L)[:, 0], delta
+
+    # ---------------------------------------------------------------- solve
+    def solve(self, x0=None) -> dict:
+        """Run the iteration from x0 (default: the model's start point).
+
+        Returns a dict: x, s, lam (constraint multipliers), zl, zu (bound
+        duals of x), f, status ("solved", "max_iter" or "stalled" after five
+        line searches in a row that found no acceptable step), iterations,
+        kkt (final scaled KKT error), cvio (largest violation of the
+        unrelaxed constraint bounds), mu, times (seconds by part), counts.
+        """
+        torch = _torch()
+        m = self.m
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        t_start = time.perf_counter()
+        for k in self.times:
+            self.times[k] = 0.0
+        for k in self.counts:
+            self.counts[k] = 0
+        x = self._interior((self.x0 if x0 is None else x0).to(**f64).clone(), self.lv, self.uv, self.hxl, self.hxu)
+        lam = torch.zeros(m, **f64)
+        f, g, c, jv, hv = self._timed("callbacks", self._eval, x, lam)
+        s = self._interior(c.clone(), self.lc, self.uc, self.hsl, self.hsu)
+        zl, zu = self.hxl.to(torch.float64), self.hxu.to(torch.float64)
+        vl, vu = self.hsl.to(torch.float64), self.hsu.to(torch.float64)
+        mu, nu, delta = self.mu0, 1.0, 0.0
+        status, kkt, fails, it = "max_iter", float("inf"), 0, 0
+        for it in range(self.max_iter + 1):
+            t0 = time.perf_counter()
+            z = (zl, zu, vl, vu)
+            kkt = self._kkt(0.0, g, c, jv, x, s, lam, z)
+            if self.verbose:
+                print(f"[ipm] it {it:3d} f {float(f):.10g} kkt {kkt:.3e} mu {mu:.1e} delta {delta:.1e}", flush=True)
+            if kkt <= self.tol or it == self.max_iter:
+                status = "solved" if kkt <= self.tol else status
+                self.times["other"] += time.perf_counter() - t0
+                break
+            while mu > self.tol / 10 and self._kkt(mu, g, c, jv, x, s, lam, z) <= 10.0 * mu:
+                mu = max(self.tol / 10, min(0.2 * mu, mu ** 1.5))
+            dlx, dux, dls, dus = self._dist(x, s)
+            Sx = torch.where(self.hxl, zl / dlx, 0.0) + torch.where(self.hxu, zu / dux, 0.0)
+            Ss = torch.where(self.hsl, vl / dls, 0.0) + torch.where(self.hsu, vu / dus, 0.0)
+            Jt_lam = self._jt(jv, lam)
+            bx = -torch.where(self.hxl, mu / dlx, 0.0) + torch.where(self.hxu, mu / dux, 0.0)
+            bs = -torch.where(self.hsl, mu / dls, 0.0) + torch.where(self.hsu, mu / dus, 0.0)
+            rx = g + Jt_lam + bx
+            rs = bs - lam
+            rc = c - s
+            self.times["other"] += time.perf_counter() - t0
+
+            def newton():
+                rhs = -(rx + self._jt(jv, Ss * rc + rs))
+                d0 = 0.0 if delta == 0.0 else max(1e-20, delta / 3.0)
+                dx, dlt = self._assemble_factor(hv, jv, Sx, Ss, rhs, d0)
+                ds = torch.zeros(m, **f64).index_add_(0, self.jr, jv * dx[self.jc]) + rc
+                return dx, ds, dlt
+
+            dx, ds, delta = self._timed("linear_algebra", newton)
+            t0 = time.perf_counter()
+            dlam = Ss * ds + rs
+            dzl = torch.where(self.hxl, (mu - zl * dx) / dlx - zl, 0.0)
+            dzu = torch.where(self.hxu, (mu + zu * dx) / dux - zu, 0.0)
+            dvl = torch.where(self.hsl, (mu - vl * ds) / dls - vl, 0.0)
+            dvu = torch.where(self.hsu, (mu + vu * ds) / dus - vu, 0.0)
+            tau = max(0.99, 1.0 - mu)
+
+            def max_step(d, dd, has):
+                # largest a in (0, 1] with d + a dd >= (1 - tau) d wherever has
+                bad = has & (dd < 0)
+                if not bool(bad.any()):
+                    return 1.0
+                return min(1.0, float((-tau * d[bad] / dd[bad]).min()))
+
+            a_p = min(max_step(dlx, dx, self.hxl), max_step(dux, -dx, self.hxu),
+                      max_step(dls, ds, self.hsl), max_step(dus, -ds, self.hsu))
+            a_d = min(max_step(zl, dzl, self.hxl), max_step(zu, dzu, self.hxu),
+                      max_step(vl, dvl, self.hsl), max_step(vu, dvu, self.hsu))
+            if m:
+                nu = max(nu, 1.1 * float((lam + dlam).abs().max()))
+            has = (self.hxl, self.hxu, self.hsl, self.hsu)
+
+            def merit(f_, x_, s_, c_):
+                lg = sum(float(torch.log(d[h]).sum()) for d, h in zip(self._dist(x_, s_), has))
+                return float(f_) - mu * lg + nu * float((c_ - s_).abs().sum())
+
+            phi0 = merit(f, x, s, c)
+            # directional derivative of the merit function along (dx, ds)
+            dphi = float((g + bx) @ dx) + float(bs @ ds) - nu * float(rc.abs().sum())
+            self.times["other"] += time.perf_counter() - t0
+            alpha, accepted = a_p, False
+            for _ in range(40):
+                xt, st = x + alpha * dx, s + alpha * ds
+                ft, ct = self._timed("callbacks", self._obj_cons, xt)
+                t0 = time.perf_counter()
+                phit = merit(ft, xt, st, ct)
+                self.times["other"] += time.perf_counter() - t0
+                if math.isfinite(phit) and phit <= phi0 + 1e-4 * alpha * min(dphi, 0.0):
+                    accepted = True
+                    break
+                alpha *= 0.5
+            fails = 0 if accepted else fails + 1
+            if fails >= 5:
+                status = "stalled"
+                break
+            t0 = time.perf_counter()
+            x, s = x + alpha * dx, s + alpha * ds
+            lam = lam + alpha * dlam
+            dlx, dux, dls, dus = self._dist(x, s)
+
+            def keep(zz, dzz, d, h):
+                # bound dual step, then kept within a factor 1e10 of mu / distance
+                zz = zz + a_d * dzz
+                return torch.where(h, torch.maximum(torch.minimum(zz, 1e10 * mu / d), mu / (1e10 * d)), 0.0)
+
+            zl, zu = keep(zl, dzl, dlx, self.hxl), keep(zu, dzu, dux, self.hxu)
+            vl, vu = keep(vl, dvl, dls, self.hsl), keep(vu, dvu, dus, self.hsu)
+            self.times["other"] += time.perf_counter() - t0
+            f, g, c, jv, hv = self._timed("callbacks", self._eval, x, lam)
+        cvio = 0.0
+        if m:
+            cvio = float(torch.maximum(torch.clamp(self.lc0 - c, min=0.0), torch.clamp(c - self.uc0, min=0.0)).max())
+        return dict(x=x, s=s, lam=lam, zl=zl, zu=zu, f=float(f), status=status, iterations=it, kkt=kkt, cvio=cvio,
+                    mu=mu, times=dict(self.times, total=time.perf_counter() - t_start), counts=dict(self.counts))
