@@ -15,7 +15,8 @@ Also measured in the same run (the "extra" object): the batched form on the
 64-scenario uneven mix (8 networks of 500 to 20,000 buses x 8 load seeds,
 one persistent launch) against the plain per-instance launches, the
 multi-period model (2,000 buses x 48 periods), the N-1 contingency model
-(1,000 buses + 200 outage copies) and the learned warm-start proxy (300
+(1,000 buses + 200 outage copies), the rectangular form, the interior-point
+consumer of the callbacks (300 buses) and the learned warm-start proxy (300
 buses, batches of 4,096 load samples).
 
 Prints one JSON line.
@@ -562,6 +563,40 @@ def bench_proxy(args, torch, synth, log):
     return out
 
 
+def bench_ipm(torch, opf, synth, log):
+    """The interior-point consumer (condensed LiftedKKT barrier method,
+    dense Cholesky) solving the proxy's 300-bus network from the model's
+    start point: at 0.7x the base loads with the two tolerances of the
+    paper's tables, and at the base loads, where no point within the
+    bounds satisfies the constraints (the run reports that it is not
+    solved).  Time is split into callbacks, linear algebra and the rest."""
+    from paper_2510_12897_amd.ipm import InteriorPoint
+
+    base = synth.network(300, 410, 60, 41)
+    out = {"workload": "300 buses, 410 branches, 60 generators (the proxy's network), solved from the "
+                       "model's start point; dense condensed matrix factored by Cholesky"}
+    for tag, fac, tol, max_iter in (("load0.7_tol1e-4", 0.7, 1e-4, 300), ("load0.7_tol1e-8", 0.7, 1e-8, 300),
+                                    ("load1.0_tol1e-6", 1.0, 1e-6, 100)):
+        cs = dict(base)
+        cs["pd"], cs["qd"] = base["pd"] * fac, base["qd"] * fac
+        model = opf.Model(cs, device=0)
+        try:
+            InteriorPoint(model, tol=tol, max_iter=3).solve()          # warm the libraries
+            r = InteriorPoint(model, tol=tol, max_iter=max_iter).solve()
+        finally:
+            model.close()
+        t, it = r["times"], max(r["iterations"], 1)
+        log(f"ipm {tag}: {r['status']} in {r['iterations']} iterations, f {r['f']:.8g}, cvio {r['cvio']:.2e}, "
+            f"{t['total'] * 1e3:.0f} ms (callbacks {t['callbacks'] * 1e3:.1f}, linear algebra "
+            f"{t['linear_algebra'] * 1e3:.1f}, other {t['other'] * 1e3:.1f})")
+        out[tag] = dict(status=r["status"], iterations=r["iterations"], objective=r["f"], cvio=r["cvio"],
+                        kkt=r["kkt"], n=model.n, m=model.m, seconds=t["total"],
+                        ms_per_iteration=t["total"] / it * 1e3, seconds_callbacks=t["callbacks"],
+                        seconds_linear_algebra=t["linear_algebra"], seconds_other=t["other"],
+                        callback_share=t["callbacks"] / t["total"], counts=r["counts"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -698,6 +733,10 @@ def main():
             extra["points16_10k"] = bench_points(torch, opf, synth, log, B=16)
         except Exception as e:
             extra["points16_10k"] = {"error": repr(e)}
+        try:
+            extra["ipm_300bus"] = bench_ipm(torch, opf, synth, log)
+        except Exception as e:
+            extra["ipm_300bus"] = {"error": repr(e)}
         if args.proxy_steps > 0:
             try:
                 extra["proxy_300bus"] = bench_proxy(args, torch, synth, log)

@@ -208,7 +208,10 @@ class InteriorPoint:
             delta = 1e-8 if delta == 0.0 else 8.0 * delta
             if delta > 1e40:
                 raise FloatingPointError("ipm: no regularisation makes the condensed matrix positive definite")
-        return torch.cholesky_solve(rhs[:, None], L)[:, 0], delta
+        # two triangular solves (rocBLAS trsm): several times faster on
+        # ROCm than cholesky_solve's default path at these sizes
+        w = torch.linalg.solve_triangular(L, rhs[:, None], upper=False)
+        return torch.linalg.solve_triangular(L.mT, w, upper=True)[:, 0], delta
 
     # ---------------------------------------------------------------- solve
     def solve(self, x0=None) -> dict:
