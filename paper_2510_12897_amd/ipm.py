@@ -12,9 +12,8 @@ is assembled on the device (the J^T Sigma_s J products are scattered through
 a pair list built once from the Jacobian pattern) and factored by torch's
 dense Cholesky (rocSOLVER on ROCm).  The paper's GPU configuration factors K
 with a sparse direct solver; without one, this solver is meant for networks
-up to a few thousand buses (``max_dense_n`` variables), and it reports where
-its time goes (callbacks, linear algebra, the rest), the split of the
-paper's Fig. 5.
+up to a few thousand buses (``max_dense_n`` variables).  It reports where
+its time goes: callbacks, linear algebra, and the rest.
 
 The algorithm is a primal-dual barrier method in the form of Waechter and
 Biegler's Ipopt, with the LiftedKKT treatment of equalities (Pacaud and
