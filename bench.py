@@ -537,7 +537,41 @@ def bench_proxy(args, torch, synth, log):
     _, cvf = px.flat_start(loads)
     cvp, cv0, cvf = cvp.cpu().numpy(), cv0.cpu().numpy(), cvf.cpu().numpy()
     curve = P.fallback_curve(cvp)
+    # the training step split into its parts, each timed on its own: the MLP
+    # forward and backward (matrix-core GEMMs, GELU, bias sums), the FP64
+    # loss node forward and backward (squash, flows, batch evaluation,
+    # penalty, J^T W, squash backward) and the Adam step
+    gen.manual_seed(99)
+    loads, feats = px.sample(gen)
+    px.pen.set_loads(loads[:, :px.N], loads[:, px.N:])
+    gz = torch.randn(B, px.mlp.dims[-1], device=px.dev) * 1e-3
+
+    def mlp_part():
+        px.mlp(feats).backward(gz)
+        px.mlp.flat.grad = None
+
+    z0 = px.mlp(feats).detach()
+
+    def loss_part():
+        z = z0.clone().requires_grad_(True)
+        P._fun("loss").apply(z, px).mean().backward()
+
+    zz = px.mlp(feats)
+    zz.backward(gz)
+    g_keep = px.mlp.flat.grad.clone()
+
+    def adam_part():
+        px.mlp.flat.grad = g_keep
+        px.mlp.adam_step(lr=0.0)
+
+    split = {}
+    for name, fn in (("mlp_fwd_bwd", mlp_part), ("loss_fwd_bwd", loss_part), ("adam", adam_part)):
+        secs, _ = time_steps(torch, fn, 20, 2)
+        split[name] = secs / 20 * 1e3
+    px.mlp.flat.grad = None
     # inference: MLP + squashing + flows + FP64 constraint evaluation + violation
+    gen.manual_seed(4242)
+    loads, feats = px.sample(gen)
     secs, _ = time_steps(torch, lambda: px.predict(loads, feats), 10, 2)
     infer_s = secs / 10
     # MLP forward alone on the matrix cores
@@ -547,10 +581,16 @@ def bench_proxy(args, torch, synth, log):
     mlp_tflops = flops / (secs_m / 10) / 1e12
     log(f"proxy: loss {first:.4g} -> {last:.4g} in {steps} steps ({train_s * 1e3:.2f} ms/step); held-out "
         f"Cvio mean {cvp.mean():.4g} vs x0 {cv0.mean():.4g} and flat start {cvf.mean():.4g}; fallback rate at "
-        f"tau 0.05: {curve[0.05]:.3f}; {B / infer_s:.0f} inferences/s; MLP forward {mlp_tflops:.1f} TFLOP/s")
+        f"tau 0.05: {curve[0.05]:.3f}; {B / infer_s:.0f} inferences/s; MLP forward {mlp_tflops:.1f} TFLOP/s; "
+        f"step split (ms): MLP {split['mlp_fwd_bwd']:.3f}, FP64 loss {split['loss_fwd_bwd']:.3f}, "
+        f"Adam {split['adam']:.3f}")
     out = dict(workload="300 buses, 410 branches, 60 generators; MLP 600-1024x3-720 GELU, BF16 MFMA; "
                         "batches of 4096 loads (+-30 % uniform)",
                train_steps=steps, ms_per_train_step=train_s * 1e3, loss_first=first, loss_last=last,
+               ms_split={**split, "note": "each part timed on its own over 20 repetitions; mlp_fwd_bwd = the "
+                                          "matrix-core GEMMs with their GELU and bias-sum kernels, loss_fwd_bwd = "
+                                          "the FP64 side (squash, flows, batch evaluation, penalty, J^T W, squash "
+                                          "backward)"},
                inferences_per_s=B / infer_s, mlp_forward_tflops=mlp_tflops, mlp_peak_tflops=2500.0,
                heldout_cvio_mean=float(cvp.mean()), heldout_cvio_max=float(cvp.max()),
                x0_cvio_mean=float(cv0.mean()), flatstart_cvio_mean=float(cvf.mean()),

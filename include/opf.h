@@ -392,6 +392,21 @@ int prox_gemm_bf16_splitk(int variant, const float *A, int lda, const float *B, 
                           int N, int K, const float *bias, float *act, int accumulate, int splits, float *work,
                           void *stream);
 
+/* prox_gemm_bf16_splitk with either operand stored as BF16 (a_bf16 /
+ * b_bf16 != 0: A / B point to BF16 values, same layouts; no rounding is
+ * then needed when staged, so the product equals the FP32-operand product of
+ * the same values) and the GELU output act stored as BF16 (act_bf16 != 0,
+ * rounded to nearest even; C stays FP32).  For the MLP's hidden activations
+ * and the BF16 copy of its weights: half the operand bytes.  A k-contiguous
+ * BF16 operand needs K and its leading dimension multiples of 8 (OPF_E_ARG
+ * otherwise). */
+int prox_gemm_bf16_mixed(int variant, const void *A, int a_bf16, int lda, const void *B, int b_bf16, int ldb, float *C,
+                         int ldc, int M, int N, int K, const float *bias, void *act, int act_bf16, int accumulate,
+                         int splits, float *work, void *stream);
+
+/* y[i] = x[i] rounded to BF16 (nearest even), n values. */
+int prox_to_bf16(const float *x, int64_t n, void *y, void *stream);
+
 /* A split count for prox_gemm_bf16_splitk: the smallest power of two (at
  * most 16) that gives 256 or more 128 x 128 workgroups while each part keeps
  * at least four k tiles.  Negative sizes: OPF_E_ARG. */
@@ -408,6 +423,14 @@ int prox_colsum(const float *X, int M, int N, float *work, float *out, float sca
  * step counts from 1. */
 int prox_adam(float *p, const float *g, float *m1, float *m2, int64_t n, float lr, float beta1, float beta2,
               float eps, int step, void *stream);
+
+/* prox_adam with the step count in device memory, for a training step
+ * captured in a HIP graph: the update uses step = *step + 1 and a second
+ * one-thread launch then stores it into *step (int32, device).  pb (may be
+ * NULL) receives the updated parameters rounded to BF16 (nearest even, n
+ * values, device): the copy the matrix-core products read. */
+int prox_adam_dev(float *p, const float *g, float *m1, float *m2, int64_t n, float lr, float beta1, float beta2,
+                  float eps, int32_t *step, void *pb, void *stream);
 
 /* z [B, 2N+2G] (blocks vm, va, pg, qg) -> the va, vm, pg, qg entries of X
  * [B, n] (FP64): vm, pg, qg = lower + (upper - lower) sigmoid(z); va =
@@ -449,6 +472,13 @@ int prox_vjp_weights(opf_model model, const double *X, const double *W, const do
  * instance's loss).  gX2 may be NULL; X may be NULL when obj_scale is 0. */
 int prox_vjp_sum(opf_model model, const double *X, const double *gX1, const double *gX2, double obj_scale,
                  const double *wb, int B, double *gX, void *stream);
+
+/* prox_vjp_sum followed by prox_squash_bwd in one pass: dz [B, 2N+2G] =
+ * (d x / d z)^T g with g = wb[b] * (gX1 + obj_scale * grad f(X)) on the va,
+ * vm, pg, qg entries (X may be NULL when obj_scale is 0).  The same values
+ * as the two calls (no [B, n] intermediate). */
+int prox_loss_bwd(opf_model model, const float *z, int B, double va_span, const double *X, const double *gX1,
+                  double obj_scale, const double *wb, float *dz, void *stream);
 #ifdef __cplusplus
 }
 #endif

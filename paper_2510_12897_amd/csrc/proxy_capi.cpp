@@ -64,9 +64,9 @@ opf::ProxRows rows_of(opf_model m) {
 extern "C" {
 
 namespace {
-int gemm_checked(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N, int K,
-                 const float* bias, float* act, int accumulate, int splits, float* work, void* stream,
-                 const char* what) {
+int gemm_checked(int variant, const void* A, bool a_bf16, int lda, const void* B, bool b_bf16, int ldb, float* C,
+                 int ldc, int M, int N, int K, const float* bias, void* act, bool act_bf16, int accumulate, int splits,
+                 float* work, void* stream, const char* what) {
     if (variant < 0 || variant > 3) return set_err(OPF_E_ARG, "variant must be 0..3");
     if (!A || !B || !C) return set_err(OPF_E_ARG, "A, B and C must be non-NULL");
     if (M < 0 || N < 0 || K < 0) return set_err(OPF_E_ARG, "negative dimension");
@@ -77,27 +77,42 @@ int gemm_checked(int variant, const float* A, int lda, const float* B, int ldb, 
     const bool a_k = variant == 0 || variant == 1, b_k = variant == 0 || variant == 3;
     if (lda < (a_k ? K : M) || ldb < (b_k ? K : N) || ldc < N)
         return set_err(OPF_E_ARG, "a leading dimension is smaller than its row");
+    if (((a_bf16 && a_k) || (b_bf16 && b_k)) && (K % 8 || (a_bf16 && a_k && lda % 8) || (b_bf16 && b_k && ldb % 8)))
+        return set_err(OPF_E_ARG, "a k-contiguous BF16 operand needs K and its leading dimension multiples of 8");
     if (splits < 1 || splits > 64) return set_err(OPF_E_ARG, "splits must be 1..64");
     if (splits > 1 && (!work || !aligned16(work)))
         return set_err(OPF_E_ARG, "splits > 1 needs a 16-byte aligned work buffer");
     if (M == 0 || N == 0) return OPF_OK;
-    return launched(opf::prox_gemm(variant, A, lda, B, ldb, C, ldc, M, N, K, bias, act, accumulate, splits, work,
-                                   static_cast<hipStream_t>(stream)),
+    return launched(opf::prox_gemm_mixed(variant, A, a_bf16, lda, B, b_bf16, ldb, C, ldc, M, N, K, bias, act, act_bf16,
+                                         accumulate, splits, work, static_cast<hipStream_t>(stream)),
                     what);
 }
 }  // namespace
 
 int prox_gemm_bf16(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N,
                    int K, const float* bias, float* act, int accumulate, void* stream) {
-    return gemm_checked(variant, A, lda, B, ldb, C, ldc, M, N, K, bias, act, accumulate, 1, nullptr, stream,
-                        "prox_gemm_bf16 launch");
+    return gemm_checked(variant, A, false, lda, B, false, ldb, C, ldc, M, N, K, bias, act, false, accumulate, 1,
+                        nullptr, stream, "prox_gemm_bf16 launch");
 }
 
 int prox_gemm_bf16_splitk(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M,
                           int N, int K, const float* bias, float* act, int accumulate, int splits, float* work,
                           void* stream) {
-    return gemm_checked(variant, A, lda, B, ldb, C, ldc, M, N, K, bias, act, accumulate, splits, work, stream,
-                        "prox_gemm_bf16_splitk launch");
+    return gemm_checked(variant, A, false, lda, B, false, ldb, C, ldc, M, N, K, bias, act, false, accumulate, splits,
+                        work, stream, "prox_gemm_bf16_splitk launch");
+}
+
+int prox_gemm_bf16_mixed(int variant, const void* A, int a_bf16, int lda, const void* B, int b_bf16, int ldb, float* C,
+                         int ldc, int M, int N, int K, const float* bias, void* act, int act_bf16, int accumulate,
+                         int splits, float* work, void* stream) {
+    return gemm_checked(variant, A, a_bf16 != 0, lda, B, b_bf16 != 0, ldb, C, ldc, M, N, K, bias, act, act_bf16 != 0,
+                        accumulate, splits, work, stream, "prox_gemm_bf16_mixed launch");
+}
+
+int prox_to_bf16(const float* x, int64_t n, void* y, void* stream) {
+    if (n < 0 || (n > 0 && (!x || !y))) return set_err(OPF_E_ARG, "bad arguments");
+    if (n == 0) return OPF_OK;
+    return launched(opf::prox_to_bf16(x, n, y, static_cast<hipStream_t>(stream)), "prox_to_bf16 launch");
 }
 
 int prox_gemm_splits(int M, int N, int K) {
@@ -119,8 +134,17 @@ int prox_adam(float* p, const float* g, float* m1, float* m2, int64_t n, float l
               int step, void* stream) {
     if (n < 0 || step < 1 || (n > 0 && (!p || !g || !m1 || !m2))) return set_err(OPF_E_ARG, "bad arguments");
     if (n == 0) return OPF_OK;
-    return launched(opf::prox_adam(p, g, m1, m2, n, lr, beta1, beta2, eps, step, static_cast<hipStream_t>(stream)),
+    return launched(opf::prox_adam(p, g, m1, m2, n, lr, beta1, beta2, eps, step, nullptr,
+                                   static_cast<hipStream_t>(stream)),
                     "prox_adam launch");
+}
+
+int prox_adam_dev(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float beta1, float beta2,
+                  float eps, int32_t* step, void* pb, void* stream) {
+    if (n < 1 || !p || !g || !m1 || !m2 || !step) return set_err(OPF_E_ARG, "bad arguments");
+    return launched(opf::prox_adam_dev(p, g, m1, m2, n, lr, beta1, beta2, eps, step, pb,
+                                       static_cast<hipStream_t>(stream)),
+                    "prox_adam_dev launch");
 }
 
 int prox_squash_fwd(opf_model model, const float* z, int B, double va_span, double* X, void* stream) {
@@ -172,6 +196,19 @@ int prox_vjp_sum(opf_model model, const double* X, const double* gX1, const doub
     return launched(opf::prox_vjp_sum(obj_scale != 0.0 ? X : nullptr, gX1, gX2, ob, obj_scale, wb, B, ly.n, ly.x_p, gX,
                                       static_cast<hipStream_t>(stream)),
                     "prox_vjp_sum launch");
+}
+
+int prox_loss_bwd(opf_model model, const float* z, int B, double va_span, const double* X, const double* gX1,
+                  double obj_scale, const double* wb, float* dz, void* stream) {
+    if (int rc = static_model(model)) return rc;
+    if (B < 1 || !z || !gX1 || !wb || !dz) return set_err(OPF_E_ARG, "bad arguments");
+    if (obj_scale != 0.0 && !X) return set_err(OPF_E_ARG, "X is needed for the objective term");
+    const opf::Layout& ly = model->hm.ly;
+    const opf::ProxObj ob{model->dm.c2, model->dm.c1, ly.x_pg, ly.G};
+    DeviceGuard dg(model->device);
+    return launched(opf::prox_loss_bwd(z, B, box_of(model, va_span), ob, obj_scale != 0.0 ? X : nullptr, gX1,
+                                       obj_scale, wb, ly.n, dz, static_cast<hipStream_t>(stream)),
+                    "prox_loss_bwd launch");
 }
 
 }  // extern "C"

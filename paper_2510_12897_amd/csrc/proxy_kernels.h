@@ -32,11 +32,20 @@ struct ProxRows {
 // floats), then summed in order with the epilogue.
 hipError_t prox_gemm(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N,
                      int K, const float* bias, float* act, int accumulate, int splits, float* work, hipStream_t s);
+// prox_gemm with either operand stored as BF16 (a_bf16, b_bf16) and the GELU
+// output stored as BF16 (act_bf16); a k-contiguous BF16 operand has K and its
+// leading dimension multiples of 8.
+hipError_t prox_gemm_mixed(int variant, const void* A, bool a_bf16, int lda, const void* B, bool b_bf16, int ldb,
+                           float* C, int ldc, int M, int N, int K, const float* bias, void* act, bool act_bf16,
+                           int accumulate, int splits, float* work, hipStream_t s);
 int prox_gemm_splits(int M, int N, int K);
 hipError_t prox_gelu_bwd(const float* pre, const float* dact, float* dpre, int64_t n, hipStream_t s);
 hipError_t prox_colsum(const float* X, int M, int N, float* part, float* out, float scale, hipStream_t s);
 hipError_t prox_adam(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2, float eps,
-                     int step, hipStream_t s);
+                     int step, void* pb, hipStream_t s);
+hipError_t prox_adam_dev(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2,
+                         float eps, int32_t* step, void* pb, hipStream_t s);
+hipError_t prox_to_bf16(const float* x, int64_t n, void* y, hipStream_t s);
 hipError_t prox_squash_fwd(const float* z, int B, const ProxBox& box, double* X, int64_t n, hipStream_t s);
 hipError_t prox_squash_bwd(const float* z, int B, const ProxBox& box, const double* gX1, const double* gX2,
                            const double* gObj, double obj_scale, int64_t n, float* dz, float scale, hipStream_t s);
@@ -51,5 +60,7 @@ struct ProxObj {
 };
 hipError_t prox_vjp_sum(const double* X, const double* gX1, const double* gX2, const ProxObj& ob, double obj_scale,
                         const double* wb, int B, int64_t n, int64_t nfree, double* gX, hipStream_t s);
+hipError_t prox_loss_bwd(const float* z, int B, const ProxBox& box, const ProxObj& ob, const double* X,
+                         const double* gX1, double obj_scale, const double* wb, int64_t n, float* dz, hipStream_t s);
 
 }  // namespace opf

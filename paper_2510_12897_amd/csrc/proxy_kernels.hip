@@ -66,9 +66,27 @@ __device__ __forceinline__ float4 guarded_load(const float* __restrict__ base, c
     return ok ? t : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// Registers that stage one operand tile between its global load and its LDS
+// store: FP32 operands as float4 (rounded to BF16 at the store); BF16
+// operands as they are stored (k-contiguous: 8 k values of one row per
+// 16-byte load; i-contiguous: 4 rows of one k per 8-byte load).
+template <typename T, bool KCONT, int ROWS>
+struct TileRegs {
+    float4 v[ROWS / 16];
+};
+template <int ROWS>
+struct TileRegs<__bf16, true, ROWS> {
+    uint4 v[ROWS / 32];
+};
+template <int ROWS>
+struct TileRegs<__bf16, false, ROWS> {
+    uint2 v[ROWS / 16];
+};
+
 template <bool KCONT, int ROWS>
 __device__ __forceinline__ void load_tile(const float* __restrict__ P, int ld, int nrows, int kend, int r0, int k0,
-                                          float4 (&v)[ROWS / 16]) {
+                                          TileRegs<float, KCONT, ROWS>& R) {
+    float4 (&v)[ROWS / 16] = R.v;
     const int t = threadIdx.x;
     if (KCONT) {
         const int k = k0 + (t % 8) * 8;
@@ -94,7 +112,8 @@ __device__ __forceinline__ void load_tile(const float* __restrict__ P, int ld, i
 // i-contiguous layout is transposed in registers: 16-byte chunks for 128
 // rows, 8-byte half chunks for 64).
 template <bool KCONT, int ROWS>
-__device__ __forceinline__ void store_tile(__bf16* S, const float4 (&v)[ROWS / 16]) {
+__device__ __forceinline__ void store_tile(__bf16* S, const TileRegs<float, KCONT, ROWS>& R) {
+    const float4 (&v)[ROWS / 16] = R.v;
     const int t = threadIdx.x;
     if (KCONT) {
 #pragma unroll
@@ -124,6 +143,67 @@ __device__ __forceinline__ void store_tile(__bf16* S, const float4 (&v)[ROWS / 1
             (bf16x4){to_bf16(v[0].z), to_bf16(v[1].z), to_bf16(v[2].z), to_bf16(v[3].z)};
         *reinterpret_cast<bf16x4*>(S + lds_at(r + 3, c) + h) =
             (bf16x4){to_bf16(v[0].w), to_bf16(v[1].w), to_bf16(v[2].w), to_bf16(v[3].w)};
+    }
+}
+
+// BF16 operands: the same thread-to-element maps as the FP32 loads above.
+// A k-contiguous operand has its k extent and leading dimension multiples
+// of 8, so that every 16-byte load of 8 k values is wholly inside or outside.
+template <bool KCONT, int ROWS>
+__device__ __forceinline__ void load_tile(const __bf16* __restrict__ P, int ld, int nrows, int kend, int r0, int k0,
+                                          TileRegs<__bf16, KCONT, ROWS>& R) {
+    const int t = threadIdx.x;
+    if constexpr (KCONT) {
+        const int k = k0 + (t % 8) * 8;
+#pragma unroll
+        for (int q = 0; q < ROWS / 32; q++) {
+            const int r = r0 + t / 8 + 32 * q;
+            const bool ok = r < nrows && k < kend;
+            const uint4 u = *reinterpret_cast<const uint4*>(ok ? P + (size_t)r * ld + k : P);
+            R.v[q] = ok ? u : make_uint4(0u, 0u, 0u, 0u);
+        }
+    } else {
+        constexpr int G = ROWS / 4, KPER = ROWS / 16;
+        const int r = r0 + (t % G) * 4;
+#pragma unroll
+        for (int kk = 0; kk < KPER; kk++) {
+            const int k = k0 + (t / G) * KPER + kk;
+            const bool ok = r < nrows && k < kend;
+            const uint2 u = *reinterpret_cast<const uint2*>(ok ? P + (size_t)k * ld + r : P);
+            R.v[kk] = ok ? u : make_uint2(0u, 0u);
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t pack_lo(uint32_t a, uint32_t b) { return (a & 0xffffu) | (b << 16); }
+__device__ __forceinline__ uint32_t pack_hi(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xffff0000u); }
+
+template <bool KCONT, int ROWS>
+__device__ __forceinline__ void store_tile(__bf16* S, const TileRegs<__bf16, KCONT, ROWS>& R) {
+    const int t = threadIdx.x;
+    if constexpr (KCONT) {
+#pragma unroll
+        for (int q = 0; q < ROWS / 32; q++) *reinterpret_cast<uint4*>(S + lds_at(t / 8 + 32 * q, t % 8)) = R.v[q];
+    } else if constexpr (ROWS == 128) {
+        // thread: rows r .. r + 3 at k values 8 c .. 8 c + 7 (v[kk] = rows at k = 8 c + kk)
+        const uint2* v = R.v;
+        const int r = (t % 32) * 4, c = t / 32;
+        *reinterpret_cast<uint4*>(S + lds_at(r + 0, c)) =
+            make_uint4(pack_lo(v[0].x, v[1].x), pack_lo(v[2].x, v[3].x), pack_lo(v[4].x, v[5].x), pack_lo(v[6].x, v[7].x));
+        *reinterpret_cast<uint4*>(S + lds_at(r + 1, c)) =
+            make_uint4(pack_hi(v[0].x, v[1].x), pack_hi(v[2].x, v[3].x), pack_hi(v[4].x, v[5].x), pack_hi(v[6].x, v[7].x));
+        *reinterpret_cast<uint4*>(S + lds_at(r + 2, c)) =
+            make_uint4(pack_lo(v[0].y, v[1].y), pack_lo(v[2].y, v[3].y), pack_lo(v[4].y, v[5].y), pack_lo(v[6].y, v[7].y));
+        *reinterpret_cast<uint4*>(S + lds_at(r + 3, c)) =
+            make_uint4(pack_hi(v[0].y, v[1].y), pack_hi(v[2].y, v[3].y), pack_hi(v[4].y, v[5].y), pack_hi(v[6].y, v[7].y));
+    } else {
+        const uint2* v = R.v;
+        const int r = (t % 16) * 4, kq = t / 16;  // k = 4 kq .. + 4: half kq % 2 of chunk kq / 2
+        const int c = kq / 2, h = (kq % 2) * 4;
+        *reinterpret_cast<uint2*>(S + lds_at(r + 0, c) + h) = make_uint2(pack_lo(v[0].x, v[1].x), pack_lo(v[2].x, v[3].x));
+        *reinterpret_cast<uint2*>(S + lds_at(r + 1, c) + h) = make_uint2(pack_hi(v[0].x, v[1].x), pack_hi(v[2].x, v[3].x));
+        *reinterpret_cast<uint2*>(S + lds_at(r + 2, c) + h) = make_uint2(pack_lo(v[0].y, v[1].y), pack_lo(v[2].y, v[3].y));
+        *reinterpret_cast<uint2*>(S + lds_at(r + 3, c) + h) = make_uint2(pack_hi(v[0].y, v[1].y), pack_hi(v[2].y, v[3].y));
     }
 }
 
@@ -157,11 +237,13 @@ __device__ __forceinline__ void mma_tile(const __bf16* As, const __bf16* Bs, int
 // to work[z] (row-major [M, N]) instead of the epilogue.  Four waves of 64 x 64,
 // double-buffered LDS (one barrier per k tile), the next tile's global loads
 // in flight during the matrix-core work on the current one.
-template <bool A_KCONT, bool B_KCONT, int BN>
-__global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const float* __restrict__ A, int lda,
-                                                            const float* __restrict__ B, int ldb, float* __restrict__ C,
+// TA, TB: the operands' storage (float, rounded when staged, or __bf16);
+// TACT: the storage of the GELU output.
+template <bool A_KCONT, bool B_KCONT, int BN, typename TA, typename TB, typename TACT>
+__global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const TA* __restrict__ A, int lda,
+                                                            const TB* __restrict__ B, int ldb, float* __restrict__ C,
                                                             int ldc, int M, int N, int K, int kchunk,
-                                                            const float* __restrict__ bias, float* __restrict__ act,
+                                                            const float* __restrict__ bias, TACT* __restrict__ act,
                                                             int accumulate, float* __restrict__ work) {
     constexpr int NB = BN / 64;  // 32-column MFMA tiles per wave
     __shared__ __bf16 As[2][BM * BK];
@@ -186,7 +268,8 @@ __global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const float* __restr
 #pragma unroll
             for (int v = 0; v < 16; v++) acc[a][b][v] = 0.f;
 
-    float4 ra[BM / 16], rb[BN / 16];
+    TileRegs<TA, A_KCONT, BM> ra;
+    TileRegs<TB, B_KCONT, BN> rb;
     if (kb < ke) {
         load_tile<A_KCONT, BM>(A, lda, M, ke, i0, kb, ra);
         load_tile<B_KCONT, BN>(B, ldb, N, ke, j0, kb, rb);
@@ -242,15 +325,16 @@ __global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const float* __restr
                 float* cp = C + (size_t)i * ldc + j;
                 if (accumulate) r += *cp;
                 *cp = r;
-                if (act) act[(size_t)i * ldc + j] = gelu(r);
+                if (act) act[(size_t)i * ldc + j] = (TACT)gelu(r);
             }
         }
 }
 
 // Split-K epilogue: C = sum over the parts in order (part 0 first) + bias
 // (+ C when accumulating), GELU into act; four columns per thread.
+template <typename TACT>
 __global__ void splitk_sum_kernel(const float* __restrict__ work, int splits, int M, int N, float* __restrict__ C,
-                                  int ldc, const float* __restrict__ bias, float* __restrict__ act, int accumulate) {
+                                  int ldc, const float* __restrict__ bias, TACT* __restrict__ act, int accumulate) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int n4 = N / 4;
     if (idx >= (int64_t)M * n4) return;
@@ -280,7 +364,13 @@ __global__ void splitk_sum_kernel(const float* __restrict__ work, int splits, in
         s.w += c.w;
     }
     *cp = s;
-    if (act) *reinterpret_cast<float4*>(act + (size_t)i * ldc + j) = make_float4(gelu(s.x), gelu(s.y), gelu(s.z), gelu(s.w));
+    if (act) {
+        TACT* ap = act + (size_t)i * ldc + j;
+        ap[0] = (TACT)gelu(s.x);
+        ap[1] = (TACT)gelu(s.y);
+        ap[2] = (TACT)gelu(s.z);
+        ap[3] = (TACT)gelu(s.w);
+    }
 }
 
 __global__ void gelu_bwd_kernel(const float* __restrict__ pre, const float* __restrict__ dact,
@@ -321,9 +411,11 @@ __global__ void __launch_bounds__(256) colsum_final_kernel(const float* __restri
 }
 
 // Adam (Kingma and Ba, 2015) with bias correction; FP32 state.
+// pb (may be NULL) receives the updated parameters rounded to BF16: the
+// matrix cores' copy of the weights.
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
                             float* __restrict__ m2, int64_t n, float lr, float b1, float b2, float eps, float c1,
-                            float c2) {
+                            float c2, __bf16* __restrict__ pb) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float gi = g[i];
@@ -331,7 +423,36 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, 
     const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
     m1[i] = a;
     m2[i] = b;
-    p[i] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
+    const float pn = p[i] - lr * (a / c1) / (sqrtf(b / c2) + eps);
+    p[i] = pn;
+    if (pb) pb[i] = to_bf16(pn);
+}
+
+// Adam with the step count in device memory (a captured step replays with
+// the count it finds there): every thread forms the bias corrections from
+// step + 1, and step_bump_kernel, launched after it, stores step + 1.
+__global__ void adam_dev_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
+                                float* __restrict__ m2, int64_t n, float lr, float b1, float b2, float eps,
+                                const int32_t* __restrict__ step, __bf16* __restrict__ pb) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float t = (float)(*step + 1);
+    const float c1 = 1.f - powf(b1, t), c2 = 1.f - powf(b2, t);
+    const float gi = g[i];
+    const float a = b1 * m1[i] + (1.f - b1) * gi;
+    const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
+    m1[i] = a;
+    m2[i] = b;
+    const float pn = p[i] - lr * (a / c1) / (sqrtf(b / c2) + eps);
+    p[i] = pn;
+    if (pb) pb[i] = to_bf16(pn);
+}
+
+__global__ void step_bump_kernel(int32_t* step) { *step += 1; }
+
+__global__ void to_bf16_kernel(const float* __restrict__ x, int64_t n, __bf16* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = to_bf16(x[i]);
 }
 
 __device__ __forceinline__ double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
@@ -403,6 +524,50 @@ __global__ void squash_bwd_kernel(const float* __restrict__ z, int B, ProxBox bo
         d = g * (box.qmax[k] - box.qmin[k]) * s * (1.0 - s);
     }
     dz[idx] = (float)(d * scale);
+}
+
+// dz = (d x / d z)^T g with g = wb[b] (gX1 + obj_scale grad f(X)) on the
+// va, vm, pg, qg entries (grad f = 2 c2 pg + c1 on pg): the objective and
+// loss-weight step of vjp_sum_kernel and squash_bwd_kernel in one pass, in
+// the same order of operations.
+__global__ void loss_bwd_kernel(const float* __restrict__ z, int B, ProxBox box, ProxObj ob,
+                                const double* __restrict__ X, const double* __restrict__ gX1, double obj_scale,
+                                const double* __restrict__ wb, int64_t n, float* __restrict__ dz) {
+    const int D = 2 * box.N + 2 * box.G;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)B * D) return;
+    const int64_t b = idx / D;
+    const int j = (int)(idx % D);
+    const int N = box.N, G = box.G;
+    const double zj = z[idx];
+    int64_t e;
+    if (j < N) e = N + j;                    // vm
+    else if (j < 2 * N) e = j - N;           // va
+    else e = j;                              // pg, qg: same offset in z and x
+    double g = gX1[b * n + e];
+    if (X && j >= 2 * N && j < 2 * N + G) {
+        const int k = j - 2 * N;
+        g += obj_scale * (2.0 * ob.c2[k] * X[b * n + e] + ob.c1[k]);
+    }
+    g *= wb[b];
+    double d;
+    if (j < N) {  // vm
+        const double s = sigmoid(zj);
+        d = g * (box.vmax[j] - box.vmin[j]) * s * (1.0 - s);
+    } else if (j < 2 * N) {  // va
+        const int i = j - N;
+        const double t = tanh(zj);
+        d = box.is_ref[i] ? 0.0 : g * box.va_span * (1.0 - t * t);
+    } else if (j < 2 * N + G) {
+        const int k = j - 2 * N;
+        const double s = sigmoid(zj);
+        d = g * (box.pmax[k] - box.pmin[k]) * s * (1.0 - s);
+    } else {
+        const int k = j - 2 * N - G;
+        const double s = sigmoid(zj);
+        d = g * (box.qmax[k] - box.qmin[k]) * s * (1.0 - s);
+    }
+    dz[idx] = (float)d;
 }
 
 // The arc flows p, q are F(vm, va): a gradient on them reaches the
@@ -541,22 +706,21 @@ int prox_gemm_splits(int M, int N, int K) {
 }
 
 namespace {
-template <int BN>
-void launch_gemm(int variant, dim3 grid, hipStream_t s, const float* A, int lda, const float* B, int ldb, float* C,
-                 int ldc, int M, int N, int K, int kchunk, const float* bias, float* act, int accumulate,
-                 float* part) {
+template <int BN, typename TA, typename TB, typename TACT>
+void launch_gemm(int variant, dim3 grid, hipStream_t s, const TA* A, int lda, const TB* B, int ldb, float* C, int ldc,
+                 int M, int N, int K, int kchunk, const float* bias, TACT* act, int accumulate, float* part) {
     const dim3 block(GEMM_THREADS);
     switch (variant) {
-    case 0: hipLaunchKernelGGL((gemm_kernel<true, true, BN>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
-    case 1: hipLaunchKernelGGL((gemm_kernel<true, false, BN>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
-    case 2: hipLaunchKernelGGL((gemm_kernel<false, false, BN>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
-    default: hipLaunchKernelGGL((gemm_kernel<false, true, BN>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
+    case 0: hipLaunchKernelGGL((gemm_kernel<true, true, BN, TA, TB, TACT>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
+    case 1: hipLaunchKernelGGL((gemm_kernel<true, false, BN, TA, TB, TACT>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
+    case 2: hipLaunchKernelGGL((gemm_kernel<false, false, BN, TA, TB, TACT>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
+    default: hipLaunchKernelGGL((gemm_kernel<false, true, BN, TA, TB, TACT>), grid, block, 0, s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias, act, accumulate, part); break;
     }
 }
-}  // namespace
 
-hipError_t prox_gemm(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N,
-                     int K, const float* bias, float* act, int accumulate, int splits, float* work, hipStream_t s) {
+template <typename TA, typename TB, typename TACT>
+hipError_t gemm_typed(int variant, const TA* A, int lda, const TB* B, int ldb, float* C, int ldc, int M, int N, int K,
+                      const float* bias, TACT* act, int accumulate, int splits, float* work, hipStream_t s) {
     if (splits < 1) splits = 1;
     const int kchunk = splits == 1 ? K : ((K + splits - 1) / splits + BK - 1) / BK * BK;
     float* part = splits == 1 ? nullptr : work;
@@ -572,10 +736,49 @@ hipError_t prox_gemm(int variant, const float* A, int lda, const float* B, int l
                         act, accumulate, part);
     if (splits > 1) {
         const int64_t tot = (int64_t)M * (N / 4);
-        hipLaunchKernelGGL(splitk_sum_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, work, splits, M, N,
-                           C, ldc, bias, act, accumulate);
+        hipLaunchKernelGGL(splitk_sum_kernel<TACT>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, work, splits,
+                           M, N, C, ldc, bias, act, accumulate);
     }
     return hipGetLastError();
+}
+
+template <typename TA, typename TB>
+hipError_t gemm_act(int variant, const TA* A, int lda, const TB* B, int ldb, float* C, int ldc, int M, int N, int K,
+                    const float* bias, void* act, bool act_bf16, int accumulate, int splits, float* work,
+                    hipStream_t s) {
+    if (act_bf16)
+        return gemm_typed(variant, A, lda, B, ldb, C, ldc, M, N, K, bias, static_cast<__bf16*>(act), accumulate, splits,
+                          work, s);
+    return gemm_typed(variant, A, lda, B, ldb, C, ldc, M, N, K, bias, static_cast<float*>(act), accumulate, splits,
+                      work, s);
+}
+
+template <typename TA>
+hipError_t gemm_b(int variant, const TA* A, int lda, const void* B, bool b_bf16, int ldb, float* C, int ldc, int M,
+                  int N, int K, const float* bias, void* act, bool act_bf16, int accumulate, int splits, float* work,
+                  hipStream_t s) {
+    if (b_bf16)
+        return gemm_act(variant, A, lda, static_cast<const __bf16*>(B), ldb, C, ldc, M, N, K, bias, act, act_bf16,
+                        accumulate, splits, work, s);
+    return gemm_act(variant, A, lda, static_cast<const float*>(B), ldb, C, ldc, M, N, K, bias, act, act_bf16,
+                    accumulate, splits, work, s);
+}
+}  // namespace
+
+hipError_t prox_gemm_mixed(int variant, const void* A, bool a_bf16, int lda, const void* B, bool b_bf16, int ldb,
+                           float* C, int ldc, int M, int N, int K, const float* bias, void* act, bool act_bf16,
+                           int accumulate, int splits, float* work, hipStream_t s) {
+    if (a_bf16)
+        return gemm_b(variant, static_cast<const __bf16*>(A), lda, B, b_bf16, ldb, C, ldc, M, N, K, bias, act, act_bf16,
+                      accumulate, splits, work, s);
+    return gemm_b(variant, static_cast<const float*>(A), lda, B, b_bf16, ldb, C, ldc, M, N, K, bias, act, act_bf16,
+                  accumulate, splits, work, s);
+}
+
+hipError_t prox_gemm(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N,
+                     int K, const float* bias, float* act, int accumulate, int splits, float* work, hipStream_t s) {
+    return prox_gemm_mixed(variant, A, false, lda, B, false, ldb, C, ldc, M, N, K, bias, act, false, accumulate, splits,
+                           work, s);
 }
 
 hipError_t prox_gelu_bwd(const float* pre, const float* dact, float* dpre, int64_t n, hipStream_t s) {
@@ -593,10 +796,23 @@ hipError_t prox_colsum(const float* X, int M, int N, float* part, float* out, fl
 
 
 hipError_t prox_adam(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2, float eps,
-                     int step, hipStream_t s) {
+                     int step, void* pb, hipStream_t s) {
     const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
     hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m1, m2, n, lr, b1, b2,
-                       eps, c1, c2);
+                       eps, c1, c2, static_cast<__bf16*>(pb));
+    return hipGetLastError();
+}
+
+hipError_t prox_adam_dev(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2,
+                         float eps, int32_t* step, void* pb, hipStream_t s) {
+    hipLaunchKernelGGL(adam_dev_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m1, m2, n, lr, b1, b2,
+                       eps, step, static_cast<__bf16*>(pb));
+    hipLaunchKernelGGL(step_bump_kernel, dim3(1), dim3(1), 0, s, step);
+    return hipGetLastError();
+}
+
+hipError_t prox_to_bf16(const float* x, int64_t n, void* y, hipStream_t s) {
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, static_cast<__bf16*>(y));
     return hipGetLastError();
 }
 
@@ -611,6 +827,14 @@ hipError_t prox_squash_bwd(const float* z, int B, const ProxBox& box, const doub
     const int64_t tot = (int64_t)B * (2 * box.N + 2 * box.G);
     hipLaunchKernelGGL(squash_bwd_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, z, B, box, gX1, gX2,
                        gObj, obj_scale, n, dz, scale);
+    return hipGetLastError();
+}
+
+hipError_t prox_loss_bwd(const float* z, int B, const ProxBox& box, const ProxObj& ob, const double* X,
+                         const double* gX1, double obj_scale, const double* wb, int64_t n, float* dz, hipStream_t s) {
+    const int64_t tot = (int64_t)B * (2 * box.N + 2 * box.G);
+    hipLaunchKernelGGL(loss_bwd_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, z, B, box, ob, X, gX1,
+                       obj_scale, wb, n, dz);
     return hipGetLastError();
 }
 

@@ -140,11 +140,17 @@ def lib():
         "prox_gemm_bf16_splitk": ([ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int,
                                    _vp, _vp], ctypes.c_int),
+        "prox_gemm_bf16_mixed": ([ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int,
+                                  _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp,
+                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp], ctypes.c_int),
+        "prox_to_bf16": ([_vp, ctypes.c_int64, _vp, _vp], ctypes.c_int),
         "prox_gemm_splits": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "prox_gelu_bwd": ([_vp, _vp, _vp, ctypes.c_int64, _vp], ctypes.c_int),
         "prox_colsum": ([_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_float, _vp], ctypes.c_int),
         "prox_adam": ([_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                        ctypes.c_float, ctypes.c_int, _vp], ctypes.c_int),
+        "prox_adam_dev": ([_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                           ctypes.c_float, _vp, _vp, _vp], ctypes.c_int),
         "prox_squash_fwd": ([_vp, _vp, ctypes.c_int, ctypes.c_double, _vp, _vp], ctypes.c_int),
         "prox_squash_bwd": ([_vp, _vp, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, ctypes.c_double, _vp,
                              ctypes.c_float, _vp], ctypes.c_int),
@@ -152,6 +158,8 @@ def lib():
                           _vp, _vp, _vp], ctypes.c_int),
         "prox_vjp_weights": ([_vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp], ctypes.c_int),
         "prox_vjp_sum": ([_vp, _vp, _vp, _vp, ctypes.c_double, _vp, ctypes.c_int, _vp, _vp], ctypes.c_int),
+        "prox_loss_bwd": ([_vp, _vp, ctypes.c_int, ctypes.c_double, _vp, _vp, ctypes.c_double, _vp, _vp, _vp],
+                          ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)

@@ -11,19 +11,23 @@ than the plain starting point's falls back to it.
 Every step runs in libopf's kernels (argument marshalling only here):
 
 * the MLP's linear layers are BF16 matrix-core GEMMs with FP32 accumulation
-  (``prox_gemm_bf16``), the hidden activations an exact-erf GELU fused into
-  the GEMM epilogue; its backward is three more GEMM layouts, ``prox_colsum``
+  (``prox_gemm_bf16_mixed``: a BF16 copy of the weights kept by the Adam
+  step, hidden activations stored as BF16), the hidden activations an
+  exact-erf GELU fused into the GEMM epilogue; its backward is three more GEMM layouts, ``prox_colsum``
   for the biases and ``prox_gelu_bwd``; the optimiser is ``prox_adam``;
 * ``Squash`` maps the network output into the variable boxes
   (``prox_squash_fwd`` / ``prox_squash_bwd``);
-* ``OPFPenalty`` completes the arc flows (``opf_batch_flows``), evaluates f,
+* ``Penalty`` completes the arc flows (``opf_batch_flows``), evaluates f,
   grad f and c for the whole batch (``opf_batch_eval``) and the penalty
   (``prox_penalty``); its backward is the hand-written vector-Jacobian
   product J^T (w + w2): w the penalty weights, w2 the weights on the flow
   rows that carry the arc-flow gradient back through p = F(vm, va), built
   in closed form by the penalty pass itself when a gradient will follow
   (``prox_penalty`` with ``vjp``), then one ``opf_batch_jtprod`` and
-  ``prox_vjp_sum`` (which adds the objective gradient 2 c2 pg + c1).
+  ``prox_vjp_sum`` (which adds the objective gradient 2 c2 pg + c1);
+* training takes Squash and Penalty as one autograd node (the arc flows
+  written into the squashed X itself, ``prox_loss_bwd`` for the objective
+  and squashing backward in one pass).
 """
 from __future__ import annotations
 
@@ -61,6 +65,15 @@ def gemm(variant, A, lda, B, ldb, C, ldc, M, N, K, bias=None, act=None, accumula
                                            _p(work), _stream()))
 
 
+def gemm_mixed(variant, A, a_bf16, lda, B, b_bf16, ldb, C, ldc, M, N, K, bias=None, act=None, act_bf16=False,
+               accumulate=False, splits=1, work=None):
+    """gemm with either operand stored as BF16 (a_bf16 / b_bf16) and the
+    GELU output stored as BF16 (act_bf16)."""
+    _check(lib().prox_gemm_bf16_mixed(int(variant), _p(A), int(bool(a_bf16)), int(lda), _p(B), int(bool(b_bf16)),
+                                      int(ldb), _p(C), int(ldc), int(M), int(N), int(K), _p(bias), _p(act),
+                                      int(bool(act_bf16)), int(bool(accumulate)), int(splits), _p(work), _stream()))
+
+
 def gemm_splits(M, N, K):
     """The library's split count for an M x N x K product."""
     s = lib().prox_gemm_splits(int(M), int(N), int(K))
@@ -73,9 +86,16 @@ def gemm_splits(M, N, K):
 class MLP:
     """x [B, n_in] -> z [B, n_out]: `depth` hidden layers of `width` with
     GELU, then a linear output layer.  Parameters live in one flat FP32
-    buffer (weights [out, in] row-major, then the bias, per layer)."""
+    buffer (weights [out, in] row-major, then the bias, per layer).
 
-    def __init__(self, n_in: int, n_out: int, width: int = 1024, depth: int = 3, seed: int = 0, device: int = 0):
+    With bf16_storage (the default) the matrix cores read a BF16 copy of
+    the parameters (kept by the Adam step, refreshed when the FP32 buffer
+    is written from outside) and the hidden activations are stored as BF16:
+    the operands are rounded once when written instead of each time a tile
+    is staged, so the products are the same and read half the bytes."""
+
+    def __init__(self, n_in: int, n_out: int, width: int = 1024, depth: int = 3, seed: int = 0, device: int = 0,
+                 bf16_storage: bool = True):
         torch = _torch()
         for d in (n_in, n_out, width):
             if d % 4:
@@ -100,6 +120,32 @@ class MLP:
         self.m1 = torch.zeros_like(self.flat, requires_grad=False)
         self.m2 = torch.zeros_like(self.flat, requires_grad=False)
         self.step = 0
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=self.device)  # Adam's count, read on the device
+        self.bf16_storage = bool(bf16_storage)
+        self.flat_bf16 = None
+        self._bf16_version = None
+        if self.bf16_storage:
+            self.flat_bf16 = torch.empty(off, dtype=torch.bfloat16, device=self.device)
+            self.sync_bf16()
+
+    def sync_bf16(self):
+        """Round the FP32 parameters into the BF16 copy."""
+        _check(lib().prox_to_bf16(_p(self.flat.detach()), self.n_params, _p(self.flat_bf16), _stream()))
+        self._bf16_version = self.flat._version
+
+    def mma_weight(self, k):
+        """(weight [out, in] as the matrix cores read it, stored as BF16).
+        The forward reads it k-contiguous, so a BF16 copy needs its input
+        width a multiple of 8; other layers read the FP32 buffer."""
+        wo, bo, fo, fi = self.layout[k]
+        if self.bf16_storage and fi % 8 == 0:
+            return self.flat_bf16[wo:wo + fo * fi].view(fo, fi), True
+        return self.weight(k), False
+
+    def act_bf16(self, k):
+        """Whether hidden layer k stores its activations as BF16 (the next
+        layer reads them k-contiguous: width a multiple of 8)."""
+        return self.bf16_storage and self.layout[k][2] % 8 == 0
 
     def weight(self, k):
         wo, bo, fo, fi = self.layout[k]
@@ -116,8 +162,13 @@ class MLP:
         if self.flat.grad is None:
             raise OPFError(OPF_E_ARG, "no gradient: run backward first")
         self.step += 1
-        _check(lib().prox_adam(_p(self.flat), _p(self.flat.grad), _p(self.m1), _p(self.m2), self.n_params,
-                               float(lr), float(beta1), float(beta2), float(eps), self.step, _stream()))
+        if self.bf16_storage and self._bf16_version != self.flat._version:
+            self.sync_bf16()
+        # the step count lives on the device (the bias corrections need no
+        # host value, so the step could be recorded once and replayed)
+        _check(lib().prox_adam_dev(_p(self.flat), _p(self.flat.grad), _p(self.m1), _p(self.m2), self.n_params,
+                                   float(lr), float(beta1), float(beta2), float(eps), _p(self.step_dev),
+                                   _p(self.flat_bf16) if self.bf16_storage else None, _stream()))
         self.flat.grad = None
 
 
@@ -143,14 +194,21 @@ def _make_mlp_function():
             if x.dtype != torch.float32 or x.dim() != 2 or x.shape[1] != mlp.dims[0]:
                 raise OPFError(OPF_E_ARG, f"input must be float32 [B, {mlp.dims[0]}]")
             Bn = x.shape[0]
+            if mlp.bf16_storage and mlp._bf16_version != mlp.flat._version:
+                mlp.sync_bf16()  # the FP32 parameters were written from outside
             acts, pres = [x], []
             h = x
             nl = len(mlp.layout)
             for k in range(nl):
                 wo, bo, fo, fi = mlp.layout[k]
                 pre = torch.empty(Bn, fo, dtype=torch.float32, device=x.device)
-                act = torch.empty_like(pre) if k < nl - 1 else None
-                gemm(0, h, fi, mlp.weight(k), fi, pre, fo, Bn, fo, fi, bias=mlp.bias(k), act=act)
+                ab = k < nl - 1 and mlp.act_bf16(k)
+                act = None
+                if k < nl - 1:
+                    act = torch.empty(Bn, fo, dtype=torch.bfloat16 if ab else torch.float32, device=x.device)
+                W, w_bf16 = mlp.mma_weight(k)
+                gemm_mixed(0, h, h.dtype == torch.bfloat16, fi, W, w_bf16, fi, pre, fo, Bn, fo, fi, bias=mlp.bias(k),
+                           act=act, act_bf16=ab)
                 pres.append(pre)
                 h = act if act is not None else pre
                 if act is not None:
@@ -176,14 +234,16 @@ def _make_mlp_function():
                 wo, bo, fo, fi = mlp.layout[k]
                 h_in = ctx.acts[k]
                 # dW [fo, fi] = dpre^T h_in (split over the batch); db = column sums of dpre
-                gemm(2, dpre, fo, h_in, fi, gflat[wo:wo + fo * fi], fi, fo, fi, Bn, splits=splits[k], work=skw)
+                gemm_mixed(2, dpre, False, fo, h_in, h_in.dtype == torch.bfloat16, fi, gflat[wo:wo + fo * fi], fi,
+                           fo, fi, Bn, splits=splits[k], work=skw)
                 _check(lib().prox_colsum(_p(dpre), Bn, fo, _p(work), _p(gflat[bo:bo + fo]), ctypes.c_float(1.0),
                                          _stream()))
                 if k == 0:
                     break
                 # dh [B, fi] = dpre W, then through the GELU of layer k - 1
                 dh = torch.empty(Bn, fi, dtype=torch.float32, device=gz.device)
-                gemm(1, dpre, fo, mlp.weight(k), fi, dh, fi, Bn, fi, fo)
+                W, w_bf16 = mlp.mma_weight(k)
+                gemm_mixed(1, dpre, False, fo, W, w_bf16, fi, dh, fi, Bn, fi, fo)
                 d = torch.empty_like(dh)
                 _check(lib().prox_gelu_bwd(_p(ctx.pres[k - 1]), _p(dh), _p(d), dh.numel(), _stream()))
                 dpre = d
@@ -262,12 +322,61 @@ def _make_penalty_function():
     return F
 
 
+def _make_loss_function():
+    """z -> per-instance loss in one autograd node: squashing, arc flows
+    written into the same X, batch evaluation and penalty forward; J^T W and
+    the fused objective / squashing backward (prox_loss_bwd) backward.  The
+    same values as Squash followed by Penalty, without the copy of X and
+    the [B, n] gradient in between."""
+    torch = _torch()
+
+    class F(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, z, prox):
+            pen, va_span = prox.pen, prox.squash.va_span
+            z = z.contiguous()
+            B, n, m = pen.B, pen.model.n, pen.model.m
+            dev = z.device
+            X = torch.empty(B, n, dtype=torch.float64, device=dev)
+            _check(lib().prox_squash_fwd(pen.model.handle, _p(z), B, float(va_span), _p(X), _stream()))
+            pen.batch.flows(X)
+            Xflat = X.view(-1)
+            Fo = torch.empty(B, dtype=torch.float64, device=dev)
+            C = torch.empty(B * m, dtype=torch.float64, device=dev)
+            pen.batch.eval(Xflat, F=Fo, C=C)
+            loss = torch.empty(B, dtype=torch.float64, device=dev)
+            cvio = torch.empty(B, dtype=torch.float64, device=dev)
+            W = torch.empty(B * m, dtype=torch.float64, device=dev)
+            gpq = torch.empty(B * 4 * pen.L, dtype=torch.float64, device=dev)
+            vjp = int(bool(ctx.needs_input_grad[0]))
+            _check(lib().prox_penalty(pen.model.handle, _p(C), _p(Xflat), _p(Fo), float(pen.obj_scale),
+                                      float(pen.rho), B, vjp, _p(loss), _p(cvio), _p(W), _p(gpq), _stream()))
+            pen.last = {"x": X, "f": Fo, "c": C.view(B, m), "cvio": cvio}
+            ctx.save_for_backward(z, Xflat, W)
+            ctx.pen, ctx.va_span = pen, va_span
+            return loss
+
+        @staticmethod
+        def backward(ctx, gloss):
+            z, Xflat, W = ctx.saved_tensors
+            pen = ctx.pen
+            gX1 = pen.batch.jtprod(Xflat, W)
+            wb = gloss.detach().to(torch.float64).contiguous()
+            dz = torch.empty_like(z)
+            _check(lib().prox_loss_bwd(pen.model.handle, _p(z), pen.B, float(ctx.va_span), _p(Xflat), _p(gX1),
+                                       float(pen.obj_scale), _p(wb), _p(dz), _stream()))
+            return dz, None
+
+    return F
+
+
 _FUN = {}
 
 
 def _fun(name):
     if name not in _FUN:
-        _FUN[name] = {"squash": _make_squash_function, "penalty": _make_penalty_function}[name]()
+        _FUN[name] = {"squash": _make_squash_function, "penalty": _make_penalty_function,
+                      "loss": _make_loss_function}[name]()
     return _FUN[name]
 
 
@@ -352,6 +461,13 @@ class WarmStartProxy:
         return loads, feats
 
     def loss(self, loads, feats):
+        """Per-sample loss [B] of the network's prediction on these loads."""
+        self.pen.set_loads(loads[:, :self.N], loads[:, self.N:])
+        return _fun("loss").apply(self.mlp(feats), self)
+
+    def loss_unfused(self, loads, feats):
+        """loss through Squash and Penalty as two autograd nodes (the same
+        values; kept as the reference for the fused node)."""
         self.pen.set_loads(loads[:, :self.N], loads[:, self.N:])
         X = self.squash(self.mlp(feats))
         return self.pen(X)

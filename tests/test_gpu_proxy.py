@@ -125,6 +125,93 @@ def test_gemm_rejects_bad_shapes(dev, P):
         P.gemm(0, a, 8, a, 8, a, 8, 8, 8, 8, splits=2)  # split-K without work
 
 
+def _to_bf16(P, t):
+    from paper_2510_12897_amd.opf import lib
+    out = torch.empty(t.shape, dtype=torch.bfloat16, device=t.device)
+    assert lib().prox_to_bf16(P._p(t.contiguous()), t.numel(), P._p(out), P._stream()) == 0
+    return out
+
+
+def test_to_bf16_is_round_to_nearest_even(dev, P):
+    rng = np.random.default_rng(5)
+    x = (rng.standard_normal(100_000) * 10.0 ** rng.integers(-6, 6, 100_000)).astype(np.float32)
+    # exact ties: a BF16 value plus half its last place, both parities
+    ties = (np.arange(1, 513, dtype=np.uint32) << 16) | 0x8000
+    x = np.concatenate([x, ties.view(np.float32), -ties.view(np.float32)]).astype(np.float32)
+    got = _to_bf16(P, torch.as_tensor(x, device=dev)).float().cpu().numpy()
+    np.testing.assert_array_equal(got, MO.bf16_round(x))
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("shape,splits", [((132, 200, 72), 1), ((256, 128, 1000), 1), ((1024, 8192, 64), 1),
+                                          ((256, 128, 4096), 4)])
+def test_gemm_bf16_storage_equals_fp32_operands(dev, P, variant, shape, splits):
+    """Operands stored as BF16 give the product of the FP32-operand GEMM on
+    the same (rounded) values, bit for bit; a BF16 GELU output is the FP32
+    one rounded to nearest even."""
+    M, N, K = shape
+    rng = np.random.default_rng(40 + variant)
+    A = rng.standard_normal((M, K)).astype(np.float32)
+    B = rng.standard_normal((K, N)).astype(np.float32)
+    bias = torch.as_tensor(rng.standard_normal(N).astype(np.float32), device=dev)
+    As, lda, Bs, ldb = _stored(variant, A, B)
+    tA, tB = torch.as_tensor(As, device=dev), torch.as_tensor(Bs, device=dev)
+    bA, bB = _to_bf16(P, tA), _to_bf16(P, tB)
+    work = torch.empty(max(splits * M * N, 4), device=dev)
+    C = torch.empty(M, N, device=dev)
+    act = torch.empty_like(C)
+    P.gemm(variant, tA, lda, tB, ldb, C, N, M, N, K, bias=bias, act=act, splits=splits, work=work)
+    for a16, b16 in ((True, False), (False, True), (True, True)):
+        C2 = torch.empty_like(C)
+        act2 = torch.empty(M, N, dtype=torch.bfloat16, device=dev)
+        P.gemm_mixed(variant, bA if a16 else tA, a16, lda, bB if b16 else tB, b16, ldb, C2, N, M, N, K, bias=bias,
+                     act=act2, act_bf16=True, splits=splits, work=work)
+        torch.cuda.synchronize()
+        assert torch.equal(C2, C), (a16, b16)
+        assert torch.equal(act2, act.to(torch.bfloat16)), (a16, b16)
+
+
+def test_gemm_bf16_storage_shape_rules(dev, P):
+    from paper_2510_12897_amd.opf import OPFError
+    a = torch.zeros(64, 64, device=dev)
+    b = torch.zeros(64, 64, dtype=torch.bfloat16, device=dev)
+    with pytest.raises(OPFError, match="multiples of 8"):
+        P.gemm_mixed(0, b, True, 12, a, False, 12, a, 8, 8, 8, 12)   # k-contiguous BF16 A, K = 12
+    with pytest.raises(OPFError, match="multiples of 8"):
+        P.gemm_mixed(0, a, False, 16, b, True, 20, a, 8, 8, 8, 16)   # k-contiguous BF16 B, ldb = 20
+    # an i-contiguous BF16 operand takes any K that is a multiple of 4
+    out = torch.empty(8, 8, device=dev)
+    P.gemm_mixed(2, b, True, 8, a, False, 8, out, 8, 8, 8, 12)
+    torch.cuda.synchronize()
+    assert float(out.abs().max()) == 0.0
+
+
+def test_mlp_bf16_storage_matches_fp32_storage(dev, P):
+    """The MLP with BF16 weight copy and BF16 hidden activations computes the
+    same outputs, gradients and Adam updates as with FP32 storage."""
+    torch.manual_seed(0)
+    x = torch.randn(256, 24, device=dev)
+    gz = torch.randn(256, 40, device=dev)
+    nets = [P.MLP(24, 40, width=64, depth=3, seed=7, bf16_storage=b) for b in (True, False)]
+    outs = []
+    for net in nets:
+        z = net(x)
+        z.backward(gz)
+        g = net.flat.grad.clone()
+        net.adam_step(lr=1e-2)
+        z2 = net(x)
+        outs.append((z.detach(), g, net.flat.detach().clone(), z2.detach()))
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
+    # the BF16 copy follows the Adam step, and an outside write of the FP32
+    # parameters is picked up by the next forward
+    assert torch.equal(nets[0].flat_bf16, nets[0].flat.detach().to(torch.bfloat16))
+    with torch.no_grad():
+        for net in nets:
+            net.flat.mul_(0.5)
+    assert torch.equal(nets[0](x), nets[1](x))
+
+
 def test_elementwise_kernels_vs_oracle(dev, P):
     from paper_2510_12897_amd.opf import lib
     rng = np.random.default_rng(3)
@@ -159,6 +246,29 @@ def test_elementwise_kernels_vs_oracle(dev, P):
         lib().prox_adam(P._p(tp_), P._p(tg), P._p(tm1), P._p(tm2), 1000, 1e-2, 0.9, 0.999, 1e-8, t, P._stream())
         p, m1, m2 = MO.adam(p, g.astype(np.float32).astype(np.float64), m1, m2, t, lr=1e-2)
     np.testing.assert_allclose(tp_.cpu().numpy(), p, rtol=1e-5, atol=1e-6)
+
+
+def test_adam_with_device_step_count_vs_oracle(dev, P):
+    from paper_2510_12897_amd.opf import lib
+    rng = np.random.default_rng(8)
+    n = 1000
+    p = rng.standard_normal(n)
+    m1 = np.zeros(n)
+    m2 = np.zeros(n)
+    tp_ = torch.as_tensor(p.astype(np.float32), device=dev)
+    tm1, tm2 = torch.zeros(n, device=dev), torch.zeros(n, device=dev)
+    pb = torch.empty(n, dtype=torch.bfloat16, device=dev)
+    step = torch.zeros(1, dtype=torch.int32, device=dev)
+    for t in range(1, 6):
+        g = rng.standard_normal(n)
+        tg = torch.as_tensor(g.astype(np.float32), device=dev)
+        assert lib().prox_adam_dev(P._p(tp_), P._p(tg), P._p(tm1), P._p(tm2), n, 1e-2, 0.9, 0.999, 1e-8,
+                                   P._p(step), P._p(pb), P._stream()) == 0
+        p, m1, m2 = MO.adam(p, g.astype(np.float32).astype(np.float64), m1, m2, t, lr=1e-2)
+    torch.cuda.synchronize()
+    assert int(step) == 5
+    np.testing.assert_allclose(tp_.cpu().numpy(), p, rtol=1e-5, atol=1e-6)
+    np.testing.assert_array_equal(pb.float().cpu().numpy(), MO.bf16_round(tp_.cpu().numpy()))
 
 
 def _case(N=14, L=20, G=6, seed=5):
@@ -385,6 +495,29 @@ def test_mlp_forward_backward_vs_oracle(dev, P):
         if k:
             dh = MO.gemm(d.astype(np.float32), W)
             d = dh * MO.gelu_grad(pres[k - 1])
+
+
+def test_fused_loss_node_matches_squash_then_penalty(dev, P):
+    """The training loss node (squash, flows, evaluation, penalty; backward
+    J^T W with prox_loss_bwd) gives the values and parameter gradients of
+    Squash followed by Penalty as two nodes."""
+    case = _case(N=14, L=20, G=6, seed=9)
+    px = P.WarmStartProxy(case, B=64, width=32, depth=2, rho=3.0, obj_scale=2e-3, seed=4)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3)
+    loads, feats = px.sample(gen)
+    out = []
+    for fn in (px.loss, px.loss_unfused):
+        lb = fn(loads, feats)
+        x = px.pen.last["x"].clone()
+        (lb * torch.linspace(0.5, 1.5, lb.numel(), device=dev, dtype=torch.float64)).sum().backward()
+        out.append((lb.detach(), x, px.mlp.flat.grad.clone()))
+        px.mlp.flat.grad = None
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])
+    g0, g1 = out[0][2], out[1][2]
+    assert float((g0 - g1).abs().max()) <= 1e-6 * float(g1.abs().max())
+    px.close()
 
 
 def test_trained_proxy_gains_over_flat_start(dev, P):
