@@ -428,16 +428,22 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, 
     if (pb) pb[i] = to_bf16(pn);
 }
 
-// Adam with the step count in device memory (a captured step replays with
-// the count it finds there): every thread forms the bias corrections from
+// Adam with the step count in device memory (a recorded step replays with
+// the count it finds there): each workgroup forms the bias corrections from
 // step + 1, and step_bump_kernel, launched after it, stores step + 1.
 __global__ void adam_dev_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
                                 float* __restrict__ m2, int64_t n, float lr, float b1, float b2, float eps,
                                 const int32_t* __restrict__ step, __bf16* __restrict__ pb) {
+    __shared__ float corr[2];  // the bias corrections, formed once per workgroup
+    if (threadIdx.x == 0) {
+        const float t = (float)(*step + 1);
+        corr[0] = 1.f - powf(b1, t);
+        corr[1] = 1.f - powf(b2, t);
+    }
+    __syncthreads();
+    const float c1 = corr[0], c2 = corr[1];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float t = (float)(*step + 1);
-    const float c1 = 1.f - powf(b1, t), c2 = 1.f - powf(b2, t);
     const float gi = g[i];
     const float a = b1 * m1[i] + (1.f - b1) * gi;
     const float b = b2 * m2[i] + (1.f - b2) * gi * gi;

@@ -8,8 +8,9 @@ on the model's device.  The linear algebra is dense: the condensed matrix
 
     K = W + Sigma_x + J^T Sigma_s J  (+ delta I)
 
-is assembled on the device (the J^T Sigma_s J products are scattered through
-a pair list built once from the Jacobian pattern) and factored by torch's
+is assembled on the device (the J^T Sigma_s J products through a pair list
+built once from the Jacobian pattern; every sum through the fixed pattern
+in a fixed order, so a solve repeats bit for bit) and factored by torch's
 dense Cholesky (rocSOLVER on ROCm).  The paper's GPU configuration factors K
 with a sparse direct solver; without one, this solver is meant for networks
 up to a few thousand buses (``max_dense_n`` variables).  It reports where
@@ -33,6 +34,10 @@ Shin, condensed-space interior-point methods):
 * fraction-to-the-boundary rule with tau = max(0.99, 1 - mu), separate
   primal and bound-dual step lengths, backtracking on the l1 merit function
   f - mu sum log(distances) + nu |c(x) - s|_1 with an Armijo condition;
+  when the first trial point is rejected, up to four second-order
+  corrections (Ipopt's: the constraint residual of the trial point added to
+  the right-hand side, solved with the same factorization) before
+  backtracking;
 * monotone barrier update mu <- max(tol / 10, min(0.2 mu, mu^1.5)) once the
   barrier problem is solved to 10 mu; bound duals are kept within a factor
   1e10 of mu / distance; stop when the scaled KKT error is at most tol.
@@ -53,6 +58,32 @@ import numpy as np
 def _torch():
     import torch
     return torch
+
+
+class _SegSum:
+    """out[idx[k]] = sum of values[perm] over segment k, in a fixed order:
+    a reduction through a sparsity pattern fixed once, without atomics, so
+    that the solver's iterates repeat bit for bit from run to run."""
+
+    def __init__(self, dst: np.ndarray, size: int, device):
+        torch = _torch()
+        perm = np.argsort(dst, kind="stable")
+        sd = dst[perm]
+        idx, lengths = np.unique(sd, return_counts=True)
+        self.perm = torch.from_numpy(perm).to(device)
+        self.idx = torch.from_numpy(idx.astype(np.int64)).to(device)
+        self.lengths = torch.from_numpy(lengths.astype(np.int64)).to(device)
+        self.size = int(size)
+
+    def __call__(self, values, out=None):
+        torch = _torch()
+        sums = torch.segment_reduce(values[self.perm], "sum", lengths=self.lengths)
+        if out is None:
+            out = torch.zeros(self.size, dtype=values.dtype, device=values.device)
+        else:
+            out.zero_()
+        out[self.idx] = sums
+        return out
 
 
 class InteriorPoint:
@@ -81,16 +112,24 @@ class InteriorPoint:
         jr, jc = (t.long() for t in model.jac_structure())
         hr, hc = (t.long() for t in model.hess_structure())
         self.jr, self.jc = jr, jc
+        jr_h, jc_h = jr.cpu().numpy(), jc.cpu().numpy()
+        hr_h, hc_h = hr.cpu().numpy(), hc.cpu().numpy()
+        # J^T v (sums by column) and J v (sums by row) in a fixed order
+        self.sum_cols = _SegSum(jc_h, n, self.dev)
+        self.sum_rows = _SegSum(jr_h, m, self.dev)
         # K index of every Hessian value, both triangles
-        off = hr != hc
-        self.h_src = torch.cat([torch.arange(hr.numel(), device=self.dev), torch.nonzero(off)[:, 0]])
-        self.h_dst = torch.cat([hr * n + hc, (hc * n + hr)[off]])
+        off_h = hr_h != hc_h
+        self.h_src = torch.from_numpy(np.concatenate([np.arange(hr_h.size), np.nonzero(off_h)[0]])).to(self.dev)
+        h_dst = np.concatenate([hr_h * n + hc_h, (hc_h * n + hr_h)[off_h]])
         # ordered pairs (a, b) of Jacobian entries in one row r:
         # K[col a, col b] += Sigma_s[r] J_a J_b
-        self.p_a, self.p_b, self.p_row, self.p_dst = self._pairs(jr.cpu().numpy(), jc.cpu().numpy(), n)
+        self.p_a, self.p_b, self.p_row, p_dst = self._pairs(jr_h, jc_h, n)
+        # every contribution to K (Hessian values, then pair products) summed
+        # per entry in a fixed order
+        self.sum_k = _SegSum(np.concatenate([h_dst, p_dst]), n * n, self.dev)
         self.K = torch.empty(n * n, dtype=torch.float64, device=self.dev)
         self.times = {"callbacks": 0.0, "linear_algebra": 0.0, "other": 0.0}
-        self.counts = {"eval_set": 0, "obj_cons": 0, "factorizations": 0}
+        self.counts = {"eval_set": 0, "obj_cons": 0, "factorizations": 0, "soc": 0}
 
     def _pairs(self, jr, jc, n):
         torch = _torch()
@@ -116,7 +155,7 @@ class InteriorPoint:
 
         def dev(v):
             return torch.from_numpy(v).to(self.dev)
-        return dev(a), dev(b), dev(r), dev(dst)
+        return dev(a), dev(b), dev(r), dst
 
     # ---------------------------------------------------------------- helpers
     def _sync(self):
@@ -163,8 +202,12 @@ class InteriorPoint:
                 torch.where(self.hsl, s - self.lc, one), torch.where(self.hsu, self.uc - s, one))
 
     def _jt(self, jv, v):
-        torch = _torch()
-        return torch.zeros(self.n, dtype=torch.float64, device=self.dev).index_add_(0, self.jc, jv * v[self.jr])
+        """J^T v."""
+        return self.sum_cols(jv * v[self.jr])
+
+    def _jv(self, jv, v):
+        """J v."""
+        return self.sum_rows(jv * v[self.jc])
 
     def _kkt(self, mu, g, c, jv, x, s, lam, z):
         """Scaled KKT error of the barrier problem at mu (Ipopt's E_mu with
@@ -189,9 +232,7 @@ class InteriorPoint:
         torch = _torch()
         n = self.n
         K = self.K
-        K.zero_()
-        K.index_add_(0, self.h_dst, hv[self.h_src])
-        K.index_add_(0, self.p_dst, Ss[self.p_row] * jv[self.p_a] * jv[self.p_b])
+        self.sum_k(torch.cat([hv[self.h_src], Ss[self.p_row] * jv[self.p_a] * jv[self.p_b]]), out=K)
         Kd = K.view(n, n)
         Kd.diagonal().add_(Sx)
         delta = delta0
@@ -207,10 +248,15 @@ class InteriorPoint:
             delta = 1e-8 if delta == 0.0 else 8.0 * delta
             if delta > 1e40:
                 raise FloatingPointError("ipm: no regularisation makes the condensed matrix positive definite")
-        # two triangular solves (rocBLAS trsm): several times faster on
-        # ROCm than cholesky_solve's default path at these sizes
+        return self._solve(L, rhs), delta, L
+
+    @staticmethod
+    def _solve(L, rhs):
+        """K^-1 rhs from the Cholesky factor: two triangular solves (several
+        times faster on ROCm than cholesky_solve's default path here)."""
+        torch = _torch()
         w = torch.linalg.solve_triangular(L, rhs[:, None], upper=False)
-        return torch.linalg.solve_triangular(L.mT, w, upper=True)[:, 0], delta
+        return torch.linalg.solve_triangular(L.mT, w, upper=True)[:, 0]
 
     # ---------------------------------------------------------------- solve
     def solve(self, x0=None) -> dict:
@@ -238,12 +284,14 @@ class InteriorPoint:
         vl, vu = self.hsl.to(torch.float64), self.hsu.to(torch.float64)
         mu, nu, delta = self.mu0, 1.0, 0.0
         status, kkt, fails, it = "max_iter", float("inf"), 0, 0
+        last_step = "-"
         for it in range(self.max_iter + 1):
             t0 = time.perf_counter()
             z = (zl, zu, vl, vu)
             kkt = self._kkt(0.0, g, c, jv, x, s, lam, z)
             if self.verbose:
-                print(f"[ipm] it {it:3d} f {float(f):.10g} kkt {kkt:.3e} mu {mu:.1e} delta {delta:.1e}", flush=True)
+                print(f"[ipm] it {it:3d} f {float(f):.10g} kkt {kkt:.3e} mu {mu:.1e} delta {delta:.1e} "
+                      f"step {last_step}", flush=True)
             if kkt <= self.tol or it == self.max_iter:
                 status = "solved" if kkt <= self.tol else status
                 self.times["other"] += time.perf_counter() - t0
@@ -264,58 +312,93 @@ class InteriorPoint:
             def newton():
                 rhs = -(rx + self._jt(jv, Ss * rc + rs))
                 d0 = 0.0 if delta == 0.0 else max(1e-20, delta / 3.0)
-                dx, dlt = self._assemble_factor(hv, jv, Sx, Ss, rhs, d0)
-                ds = torch.zeros(m, **f64).index_add_(0, self.jr, jv * dx[self.jc]) + rc
-                return dx, ds, dlt
+                dx, dlt, L = self._assemble_factor(hv, jv, Sx, Ss, rhs, d0)
+                ds = self._jv(jv, dx) + rc
+                return dx, ds, dlt, L
 
-            dx, ds, delta = self._timed("linear_algebra", newton)
+            dx, ds, delta, L = self._timed("linear_algebra", newton)
+            t0 = time.perf_counter()
+            tau = max(0.99, 1.0 - mu)
+            has = (self.hxl, self.hxu, self.hsl, self.hsu)
+
+            def max_step(d, dd, h):
+                # largest a in (0, 1] with d + a dd >= (1 - tau) d wherever h
+                bad = h & (dd < 0)
+                if not bool(bad.any()):
+                    return 1.0
+                return min(1.0, float((-tau * d[bad] / dd[bad]).min()))
+
+            def primal_step(dx_, ds_):
+                return min(max_step(dlx, dx_, self.hxl), max_step(dux, -dx_, self.hxu),
+                           max_step(dls, ds_, self.hsl), max_step(dus, -ds_, self.hsu))
+
+            def merit(f_, x_, s_, c_):
+                lg = sum(float(torch.log(d[h]).sum()) for d, h in zip(self._dist(x_, s_), has))
+                return float(f_) - mu * lg + nu * float((c_ - s_).abs().sum())
+
+            a_p = primal_step(dx, ds)
+            if m:
+                nu = max(nu, 1.1 * float((lam + Ss * ds + rs).abs().max()))
+            phi0 = merit(f, x, s, c)
+            # directional derivative of the merit function along (dx, ds)
+            dphi = float((g + bx) @ dx) + float(bs @ ds) - nu * float(rc.abs().sum())
+            self.times["other"] += time.perf_counter() - t0
+
+            def trial(a, dx_, ds_):
+                xt, st = x + a * dx_, s + a * ds_
+                ft, ct = self._timed("callbacks", self._obj_cons, xt)
+                t1 = time.perf_counter()
+                phit = merit(ft, xt, st, ct)
+                ok = math.isfinite(phit) and phit <= phi0 + 1e-4 * a_p * min(dphi, 0.0) * (a / a_p)
+                self.times["other"] += time.perf_counter() - t1
+                return ok, ct - st
+
+            alpha, accepted, soc = a_p, False, 0
+            ok, rt = trial(alpha, dx, ds)
+            if ok:
+                accepted = True
+            elif m:
+                # second-order correction (Ipopt's): the step that also
+                # removes the trial point's constraint residual to first
+                # order, from the same factorization; at most 4 rounds while
+                # the residual keeps falling
+                rc_soc, theta = a_p * rc + rt, float(rt.abs().sum())
+                for _ in range(4):
+                    soc += 1
+                    dx_s = self._timed("linear_algebra", lambda: self._solve(L, -(rx + self._jt(jv, Ss * rc_soc + rs))))
+                    ds_s = self._jv(jv, dx_s) + rc_soc
+                    a_s = primal_step(dx_s, ds_s)
+                    ok_s, rt_s = trial(a_s, dx_s, ds_s)
+                    if ok_s and math.isfinite(a_s):
+                        # Armijo against the original step, then take the corrected one
+                        dx, ds, alpha, accepted = dx_s, ds_s, a_s, True
+                        break
+                    theta_s = float(rt_s.abs().sum())
+                    if not theta_s < 0.99 * theta:
+                        break
+                    rc_soc, theta = a_s * rc_soc + rt_s, theta_s
+            if not accepted:
+                alpha = a_p
+                for _ in range(40):
+                    alpha *= 0.5
+                    ok, _ = trial(alpha, dx, ds)
+                    if ok:
+                        accepted = True
+                        break
+            fails = 0 if accepted else fails + 1
+            self.counts["soc"] = self.counts.get("soc", 0) + soc
+            if fails >= 5:
+                status = "stalled"
+                break
             t0 = time.perf_counter()
             dlam = Ss * ds + rs
             dzl = torch.where(self.hxl, (mu - zl * dx) / dlx - zl, 0.0)
             dzu = torch.where(self.hxu, (mu + zu * dx) / dux - zu, 0.0)
             dvl = torch.where(self.hsl, (mu - vl * ds) / dls - vl, 0.0)
             dvu = torch.where(self.hsu, (mu + vu * ds) / dus - vu, 0.0)
-            tau = max(0.99, 1.0 - mu)
-
-            def max_step(d, dd, has):
-                # largest a in (0, 1] with d + a dd >= (1 - tau) d wherever has
-                bad = has & (dd < 0)
-                if not bool(bad.any()):
-                    return 1.0
-                return min(1.0, float((-tau * d[bad] / dd[bad]).min()))
-
-            a_p = min(max_step(dlx, dx, self.hxl), max_step(dux, -dx, self.hxu),
-                      max_step(dls, ds, self.hsl), max_step(dus, -ds, self.hsu))
             a_d = min(max_step(zl, dzl, self.hxl), max_step(zu, dzu, self.hxu),
                       max_step(vl, dvl, self.hsl), max_step(vu, dvu, self.hsu))
-            if m:
-                nu = max(nu, 1.1 * float((lam + dlam).abs().max()))
-            has = (self.hxl, self.hxu, self.hsl, self.hsu)
-
-            def merit(f_, x_, s_, c_):
-                lg = sum(float(torch.log(d[h]).sum()) for d, h in zip(self._dist(x_, s_), has))
-                return float(f_) - mu * lg + nu * float((c_ - s_).abs().sum())
-
-            phi0 = merit(f, x, s, c)
-            # directional derivative of the merit function along (dx, ds)
-            dphi = float((g + bx) @ dx) + float(bs @ ds) - nu * float(rc.abs().sum())
-            self.times["other"] += time.perf_counter() - t0
-            alpha, accepted = a_p, False
-            for _ in range(40):
-                xt, st = x + alpha * dx, s + alpha * ds
-                ft, ct = self._timed("callbacks", self._obj_cons, xt)
-                t0 = time.perf_counter()
-                phit = merit(ft, xt, st, ct)
-                self.times["other"] += time.perf_counter() - t0
-                if math.isfinite(phit) and phit <= phi0 + 1e-4 * alpha * min(dphi, 0.0):
-                    accepted = True
-                    break
-                alpha *= 0.5
-            fails = 0 if accepted else fails + 1
-            if fails >= 5:
-                status = "stalled"
-                break
-            t0 = time.perf_counter()
+            last_step = f"a_p {a_p:.2e} alpha {alpha:.2e} a_d {a_d:.2e} soc {soc} nu {nu:.1e}"
             x, s = x + alpha * dx, s + alpha * ds
             lam = lam + alpha * dlam
             dlx, dux, dls, dus = self._dist(x, s)

@@ -57,3 +57,22 @@ def test_multiperiod_storage_solve_matches():
     rg, rc = _pair(case, 1e-6, **opts)
     assert rg["status"] == rc["status"] == "solved"
     assert abs(rg["f"] - rc["f"]) <= 1e-7 * abs(rc["f"])
+
+
+def test_solve_repeats_bit_for_bit():
+    """Every reduction of the solver goes through the fixed pattern in a
+    fixed order (no atomics): two solves take the same iterations and end
+    at the same point, bit for bit."""
+    case = dict(synth.network(300, 410, 60, 41))
+    case["pd"], case["qd"] = case["pd"] * 0.7, case["qd"] * 0.7
+    m = opf.Model(case, 0)
+    try:
+        r1 = InteriorPoint(m, tol=1e-8).solve()
+        r2 = InteriorPoint(m, tol=1e-8).solve()
+    finally:
+        m.close()
+    say(f"[ipm] repeat: {r1['status']} {r1['iterations']} / {r2['status']} {r2['iterations']}")
+    assert r1["status"] == r2["status"] == "solved"
+    assert r1["iterations"] == r2["iterations"]
+    assert r1["f"] == r2["f"]
+    assert bool((r1["x"] == r2["x"]).all())

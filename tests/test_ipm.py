@@ -128,7 +128,7 @@ def test_condensed_matrix_matches_dense_products():
     Sx = torch.from_numpy(rng.uniform(0, 2, mdl.n))
     Ss = torch.from_numpy(rng.uniform(0, 2, mdl.m))
     rhs = torch.from_numpy(rng.normal(size=mdl.n))
-    dx, delta = ip._assemble_factor(torch.from_numpy(ev["hval"]), torch.from_numpy(ev["jval"]), Sx, Ss, rhs, 0.0)
+    dx, delta, _ = ip._assemble_factor(torch.from_numpy(ev["hval"]), torch.from_numpy(ev["jval"]), Sx, Ss, rhs, 0.0)
     J = orc.dense_jacobian(ev)
     K = orc.dense_hessian(ev) + np.diag(Sx.numpy()) + J.T @ np.diag(Ss.numpy()) @ J + delta * np.eye(mdl.n)
     np.testing.assert_allclose(K @ dx.numpy(), rhs.numpy(), rtol=0, atol=1e-8 * np.abs(K).max() * np.abs(dx.numpy()).max())
