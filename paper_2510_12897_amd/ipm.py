@@ -10,11 +10,14 @@ on the model's device.  The linear algebra is dense: the condensed matrix
 
 is assembled on the device (the J^T Sigma_s J products through a pair list
 built once from the Jacobian pattern; every sum through the fixed pattern
-in a fixed order, so a solve repeats bit for bit) and factored by torch's
-dense Cholesky (rocSOLVER on ROCm).  The paper's GPU configuration factors K
-with a sparse direct solver; without one, this solver is meant for networks
-up to a few thousand buses (``max_dense_n`` variables).  It reports where
-its time goes: callbacks, linear algebra, and the rest.
+in a fixed order, so a solve repeats bit for bit) and factored either as a
+sparse matrix on the GPU (``linear_solver="sparse"``, the default on a GPU:
+``sparse_chol.SparseCholesky``, rocSOLVER's sparse Cholesky
+re-factorization with a minimum-degree ordering, as the paper's GPU
+configuration factors K with a sparse direct solver) or dense
+(``"dense"``: torch's Cholesky, the CPU path, up to ``max_dense_n``
+variables).  It reports where its time goes: callbacks, linear algebra,
+and the rest.
 
 The algorithm is a primal-dual barrier method in the form of Waechter and
 Biegler's Ipopt, with the LiftedKKT treatment of equalities (Pacaud and
@@ -90,20 +93,27 @@ class InteriorPoint:
     """Solve min f(x) s.t. lcon <= c(x) <= ucon, lvar <= x <= uvar."""
 
     def __init__(self, model, tol: float = 1e-6, relax: float | None = None, max_iter: int = 300,
-                 mu0: float = 0.1, max_dense_n: int = 40000, verbose: bool = False):
+                 mu0: float = 0.1, max_dense_n: int = 40000, linear_solver: str = "auto", verbose: bool = False):
         torch = _torch()
         self.model = model
         self.tol = float(tol)
         self.relax = self.tol if relax is None else float(relax)
         self.max_iter, self.mu0, self.verbose = int(max_iter), float(mu0), verbose
         n, m = int(model.n), int(model.m)
-        if n > max_dense_n:
-            raise ValueError(f"ipm: {n} variables exceed the dense limit max_dense_n = {max_dense_n}")
         self.n, self.m = n, m
         b = model.bounds()
         self.lv, self.uv, self.x0 = b["lvar"], b["uvar"], b["x0"]
         self.lc0, self.uc0 = b["lcon"], b["ucon"]
         self.dev = self.lv.device
+        if linear_solver == "auto":
+            linear_solver = "sparse" if self.dev.type == "cuda" else "dense"
+        if linear_solver not in ("dense", "sparse"):
+            raise ValueError(f"ipm: linear_solver must be 'dense', 'sparse' or 'auto', not {linear_solver!r}")
+        if linear_solver == "sparse" and self.dev.type != "cuda":
+            raise ValueError("ipm: the sparse factorization runs on the GPU only")
+        if linear_solver == "dense" and n > max_dense_n:
+            raise ValueError(f"ipm: {n} variables exceed the dense limit max_dense_n = {max_dense_n}")
+        self.linear_solver = linear_solver
         eq = self.lc0 == self.uc0
         self.lc = torch.where(eq, self.lc0 - self.relax, self.lc0)
         self.uc = torch.where(eq, self.uc0 + self.relax, self.uc0)
@@ -117,22 +127,38 @@ class InteriorPoint:
         # J^T v (sums by column) and J v (sums by row) in a fixed order
         self.sum_cols = _SegSum(jc_h, n, self.dev)
         self.sum_rows = _SegSum(jr_h, m, self.dev)
-        # K index of every Hessian value, both triangles
-        off_h = hr_h != hc_h
-        self.h_src = torch.from_numpy(np.concatenate([np.arange(hr_h.size), np.nonzero(off_h)[0]])).to(self.dev)
-        h_dst = np.concatenate([hr_h * n + hc_h, (hc_h * n + hr_h)[off_h]])
         # ordered pairs (a, b) of Jacobian entries in one row r:
         # K[col a, col b] += Sigma_s[r] J_a J_b
-        self.p_a, self.p_b, self.p_row, p_dst = self._pairs(jr_h, jc_h, n)
+        p_a, p_b, p_row = self._pairs(jr_h, jc_h)
+        if linear_solver == "dense":
+            # K index of every Hessian value, both triangles, and of every pair
+            off_h = hr_h != hc_h
+            h_src = np.concatenate([np.arange(hr_h.size), np.nonzero(off_h)[0]])
+            h_dst = np.concatenate([hr_h * n + hc_h, (hc_h * n + hr_h)[off_h]])
+            p_dst = jc_h[p_a] * n + jc_h[p_b]
+            size = n * n
+            self.K = torch.empty(n * n, dtype=torch.float64, device=self.dev)
+        else:
+            from .sparse_chol import SparseCholesky
+            # the lower triangle only: Hessian values as given (lower), pairs
+            # with col a >= col b
+            keep = jc_h[p_a] >= jc_h[p_b]
+            p_a, p_b, p_row = p_a[keep], p_b[keep], p_row[keep]
+            self.chol = SparseCholesky(np.concatenate([hr_h, jc_h[p_a]]), np.concatenate([hc_h, jc_h[p_b]]), n,
+                                       self.dev)
+            h_src = np.arange(hr_h.size)
+            h_dst = np.searchsorted(self.chol.src, np.maximum(hr_h, hc_h) * n + np.minimum(hr_h, hc_h))
+            p_dst = np.searchsorted(self.chol.src, jc_h[p_a] * n + jc_h[p_b])
+            size = self.chol.src.size
+        dev_t = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to(self.dev)   # noqa: E731
+        self.h_src, self.p_a, self.p_b, self.p_row = dev_t(h_src), dev_t(p_a), dev_t(p_b), dev_t(p_row)
         # every contribution to K (Hessian values, then pair products) summed
         # per entry in a fixed order
-        self.sum_k = _SegSum(np.concatenate([h_dst, p_dst]), n * n, self.dev)
-        self.K = torch.empty(n * n, dtype=torch.float64, device=self.dev)
+        self.sum_k = _SegSum(np.concatenate([h_dst, p_dst]), size, self.dev)
         self.times = {"callbacks": 0.0, "linear_algebra": 0.0, "other": 0.0}
         self.counts = {"eval_set": 0, "obj_cons": 0, "factorizations": 0, "soc": 0}
 
-    def _pairs(self, jr, jc, n):
-        torch = _torch()
+    def _pairs(self, jr, jc):
         order = np.argsort(jr, kind="stable")
         starts = np.searchsorted(jr[order], np.arange(self.m + 1))
         cnt = np.diff(starts)
@@ -151,11 +177,13 @@ class InteriorPoint:
             b[pos:pos + w] = np.tile(ent, (1, c)).ravel()
             r[pos:pos + w] = np.repeat(sel, c * c)
             pos += w
-        dst = jc[a].astype(np.int64) * n + jc[b]
+        return a, b, r
 
-        def dev(v):
-            return torch.from_numpy(v).to(self.dev)
-        return dev(a), dev(b), dev(r), dst
+    def close(self):
+        """Release the sparse factorization's library handles."""
+        if getattr(self, "chol", None) is not None:
+            self.chol.close()
+            self.chol = None
 
     # ---------------------------------------------------------------- helpers
     def _sync(self):
@@ -229,10 +257,30 @@ class InteriorPoint:
         return max(e_d / s_d, e_p, e_c / s_c)
 
     def _assemble_factor(self, hv, jv, Sx, Ss, rhs, delta0):
+        """Assemble K, factor it (raising delta until it factors) and solve
+        K dx = rhs: (dx, delta, solve) with solve(r) = K^-1 r from the same
+        factorization."""
         torch = _torch()
         n = self.n
+        contrib = torch.cat([hv[self.h_src], Ss[self.p_row] * jv[self.p_a] * jv[self.p_b]])
+        if self.linear_solver == "sparse":
+            vals = self.sum_k(contrib)
+            vals[self.chol.diag] += Sx
+            delta = delta0
+            while True:
+                v = vals
+                if delta > 0:
+                    v = vals.clone()
+                    v[self.chol.diag] += delta
+                self.counts["factorizations"] += 1
+                if self.chol.factor(v):
+                    break
+                delta = 1e-8 if delta == 0.0 else 8.0 * delta
+                if delta > 1e40:
+                    raise FloatingPointError("ipm: no regularisation makes the condensed matrix positive definite")
+            return self.chol.solve(rhs), delta, self.chol.solve
         K = self.K
-        self.sum_k(torch.cat([hv[self.h_src], Ss[self.p_row] * jv[self.p_a] * jv[self.p_b]]), out=K)
+        self.sum_k(contrib, out=K)
         Kd = K.view(n, n)
         Kd.diagonal().add_(Sx)
         delta = delta0
@@ -248,7 +296,7 @@ class InteriorPoint:
             delta = 1e-8 if delta == 0.0 else 8.0 * delta
             if delta > 1e40:
                 raise FloatingPointError("ipm: no regularisation makes the condensed matrix positive definite")
-        return self._solve(L, rhs), delta, L
+        return self._solve(L, rhs), delta, lambda r: self._solve(L, r)
 
     @staticmethod
     def _solve(L, rhs):
@@ -312,11 +360,11 @@ class InteriorPoint:
             def newton():
                 rhs = -(rx + self._jt(jv, Ss * rc + rs))
                 d0 = 0.0 if delta == 0.0 else max(1e-20, delta / 3.0)
-                dx, dlt, L = self._assemble_factor(hv, jv, Sx, Ss, rhs, d0)
+                dx, dlt, solve_k = self._assemble_factor(hv, jv, Sx, Ss, rhs, d0)
                 ds = self._jv(jv, dx) + rc
-                return dx, ds, dlt, L
+                return dx, ds, dlt, solve_k
 
-            dx, ds, delta, L = self._timed("linear_algebra", newton)
+            dx, ds, delta, solve_k = self._timed("linear_algebra", newton)
             t0 = time.perf_counter()
             tau = max(0.99, 1.0 - mu)
             has = (self.hxl, self.hxu, self.hsl, self.hsu)
@@ -365,7 +413,7 @@ class InteriorPoint:
                 rc_soc, theta = a_p * rc + rt, float(rt.abs().sum())
                 for _ in range(4):
                     soc += 1
-                    dx_s = self._timed("linear_algebra", lambda: self._solve(L, -(rx + self._jt(jv, Ss * rc_soc + rs))))
+                    dx_s = self._timed("linear_algebra", lambda: solve_k(-(rx + self._jt(jv, Ss * rc_soc + rs))))
                     ds_s = self._jv(jv, dx_s) + rc_soc
                     a_s = primal_step(dx_s, ds_s)
                     ok_s, rt_s = trial(a_s, dx_s, ds_s)

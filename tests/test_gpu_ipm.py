@@ -76,3 +76,83 @@ def test_solve_repeats_bit_for_bit():
     assert r1["iterations"] == r2["iterations"]
     assert r1["f"] == r2["f"]
     assert bool((r1["x"] == r2["x"]).all())
+
+
+def _ipm_pattern(case):
+    """The condensed matrix's pattern of a model: Hessian plus J^T J."""
+    m = opf.Model(case, 0)
+    try:
+        jr, jc = (t.cpu().numpy() for t in m.jac_structure())
+        hr, hc = (t.cpu().numpy() for t in m.hess_structure())
+        n = m.n
+    finally:
+        m.close()
+    pr, pc = [hr], [hc]
+    order = np.argsort(jr, kind="stable")
+    starts = np.searchsorted(jr[order], np.arange(jr.max() + 2))
+    for r in range(jr.max() + 1):
+        cols = jc[order[starts[r]:starts[r + 1]]]
+        a, b = np.meshgrid(cols, cols)
+        pr.append(a.ravel())
+        pc.append(b.ravel())
+    return np.concatenate(pr), np.concatenate(pc), n
+
+
+def test_sparse_cholesky_factors_and_solves():
+    """rocSOLVER's sparse re-factorization with the library's ordering and
+    symbolic factor: two matrices of the interior-point pattern (the first
+    through the analysis, the second re-factored) solve like a dense
+    solve; a matrix that is not positive definite is reported."""
+    import torch
+    from paper_2510_12897_amd.sparse_chol import SparseCholesky
+    case = synth.network(300, 410, 60, 41)
+    rows, cols, n = _ipm_pattern(case)
+    dev = torch.device("cuda", 0)
+    ch = SparseCholesky(rows, cols, n, dev)
+    say(f"[sparse] n {n}, lower nnz {ch.src.size}, factor nnz {ch.nnzT}")
+    rng = np.random.default_rng(2)
+    rr, cc = ch.src // n, ch.src % n
+    try:
+        for trial in range(3):
+            v = rng.uniform(-1.0, 1.0, ch.src.size)
+            A = np.zeros((n, n))
+            A[rr, cc] = v
+            A = np.tril(A, -1)
+            A = A + A.T
+            d = np.abs(A).sum(1) + 1.0 + trial
+            A += np.diag(d)
+            v[rr == cc] = d
+            assert ch.factor(torch.as_tensor(v, device=dev))
+            b = rng.standard_normal(n)
+            x = ch.solve(torch.as_tensor(b, device=dev)).cpu().numpy()
+            ref = np.linalg.solve(A, b)
+            err = np.abs(x - ref).max() / np.abs(ref).max()
+            say(f"[sparse] trial {trial}: max relative error {err:.2e}")
+            assert err < 1e-12
+        # an indefinite matrix of the pattern fails to factor
+        v = np.zeros(ch.src.size)
+        v[rr == cc] = -1.0
+        assert not ch.factor(torch.as_tensor(v, device=dev))
+    finally:
+        ch.close()
+
+
+def test_sparse_and_dense_linear_solvers_reach_one_optimum():
+    case = dict(synth.network(300, 410, 60, 41))
+    case["pd"], case["qd"] = case["pd"] * 0.7, case["qd"] * 0.7
+    m = opf.Model(case, 0)
+    try:
+        ips = InteriorPoint(m, tol=1e-8, linear_solver="sparse")
+        rs = ips.solve()
+        ips.close()
+        rd = InteriorPoint(m, tol=1e-8, linear_solver="dense").solve()
+    finally:
+        m.close()
+    say(f"[ipm] sparse {rs['status']} it {rs['iterations']} f {rs['f']:.12g} la {rs['times']['linear_algebra']:.3f} s | "
+        f"dense {rd['status']} it {rd['iterations']} f {rd['f']:.12g} la {rd['times']['linear_algebra']:.3f} s")
+    assert rs["status"] == rd["status"] == "solved"
+    # the equality rows are relaxed by the tolerance (LiftedKKT): two
+    # solutions agree to about tol * sum |lam|
+    slack = 1e-8 * float(rd["lam"].abs().sum())
+    assert abs(rs["f"] - rd["f"]) <= 2 * slack + 1e-10 * abs(rd["f"])
+    assert rs["cvio"] <= 1.01e-8
