@@ -174,9 +174,16 @@ class SparseCholesky:
     (``src`` holds each entry's flat index row * n + col, ``diag`` the
     diagonal's positions)."""
 
+    # the first factorization (which seeds the analysis) is a dense one: n^2
+    # doubles on the device
+    MAX_SETUP_N = 40000
+
     def __init__(self, rows, cols, n: int, device):
         torch = _torch()
         self.n = int(n)
+        if self.n > self.MAX_SETUP_N:
+            raise ValueError(f"sparse Cholesky: the dense first factorization limits n to {self.MAX_SETUP_N} "
+                             f"(got {self.n})")
         self.dev = device
         self.ptr, self.ind, self.src = lower_csr(rows, cols, self.n)
         self.q = minimum_degree_order(self.ptr, self.ind, self.n)
