@@ -119,6 +119,7 @@ class InteriorPoint:
         self.uc = torch.where(eq, self.uc0 + self.relax, self.uc0)
         self.hxl, self.hxu = torch.isfinite(self.lv), torch.isfinite(self.uv)
         self.hsl, self.hsu = torch.isfinite(self.lc), torch.isfinite(self.uc)
+        self.n_bounds = int(self.hxl.sum() + self.hxu.sum() + self.hsl.sum() + self.hsu.sum())
         jr, jc = (t.long() for t in model.jac_structure())
         hr, hc = (t.long() for t in model.hess_structure())
         self.jr, self.jc = jr, jc
@@ -239,22 +240,23 @@ class InteriorPoint:
 
     def _kkt(self, mu, g, c, jv, x, s, lam, z):
         """Scaled KKT error of the barrier problem at mu (Ipopt's E_mu with
-        s_max = 100)."""
+        s_max = 100), as a 0-d device tensor (no host synchronization)."""
         torch = _torch()
         zl, zu, vl, vu = z
         dlx, dux, dls, dus = self._dist(x, s)
         rdx = g + self._jt(jv, lam) - zl + zu
         rds = -lam - vl + vu
-        comp = torch.cat([(dlx * zl - mu)[self.hxl], (dux * zu - mu)[self.hxu],
-                          (dls * vl - mu)[self.hsl], (dus * vu - mu)[self.hsu]])
-        nz = comp.numel()
-        zsum = float(zl.abs().sum() + zu.abs().sum() + vl.abs().sum() + vu.abs().sum())
-        s_d = max(100.0, (float(lam.abs().sum()) + zsum) / max(self.m + nz, 1)) / 100.0
-        s_c = max(100.0, zsum / max(nz, 1)) / 100.0
-        e_d = float(torch.cat([rdx, rds]).abs().max())
-        e_p = float((c - s).abs().max()) if self.m else 0.0
-        e_c = float(comp.abs().max()) if nz else 0.0
-        return max(e_d / s_d, e_p, e_c / s_c)
+        comp = torch.stack([torch.where(self.hxl, dlx * zl - mu, 0.0).abs().max(),
+                            torch.where(self.hxu, dux * zu - mu, 0.0).abs().max(),
+                            torch.where(self.hsl, dls * vl - mu, 0.0).abs().max() if self.m else rdx.new_zeros(()),
+                            torch.where(self.hsu, dus * vu - mu, 0.0).abs().max() if self.m else rdx.new_zeros(())]).max()
+        nz = self.n_bounds
+        zsum = zl.abs().sum() + zu.abs().sum() + vl.abs().sum() + vu.abs().sum()
+        s_d = torch.clamp((lam.abs().sum() + zsum) / max(self.m + nz, 1), min=100.0) / 100.0
+        s_c = torch.clamp(zsum / max(nz, 1), min=100.0) / 100.0
+        e_d = torch.maximum(rdx.abs().max(), rds.abs().max()) if self.m else rdx.abs().max()
+        e_p = (c - s).abs().max() if self.m else rdx.new_zeros(())
+        return torch.stack([e_d / s_d, e_p, comp / s_c]).max()
 
     def _assemble_factor(self, hv, jv, Sx, Ss, rhs, delta0):
         """Assemble K, factor it (raising delta until it factors) and solve
@@ -336,7 +338,7 @@ class InteriorPoint:
         for it in range(self.max_iter + 1):
             t0 = time.perf_counter()
             z = (zl, zu, vl, vu)
-            kkt = self._kkt(0.0, g, c, jv, x, s, lam, z)
+            kkt = float(self._kkt(0.0, g, c, jv, x, s, lam, z))
             if self.verbose:
                 print(f"[ipm] it {it:3d} f {float(f):.10g} kkt {kkt:.3e} mu {mu:.1e} delta {delta:.1e} "
                       f"step {last_step}", flush=True)
@@ -344,7 +346,7 @@ class InteriorPoint:
                 status = "solved" if kkt <= self.tol else status
                 self.times["other"] += time.perf_counter() - t0
                 break
-            while mu > self.tol / 10 and self._kkt(mu, g, c, jv, x, s, lam, z) <= 10.0 * mu:
+            while mu > self.tol / 10 and float(self._kkt(mu, g, c, jv, x, s, lam, z)) <= 10.0 * mu:
                 mu = max(self.tol / 10, min(0.2 * mu, mu ** 1.5))
             dlx, dux, dls, dus = self._dist(x, s)
             Sx = torch.where(self.hxl, zl / dlx, 0.0) + torch.where(self.hxu, zu / dux, 0.0)
@@ -369,27 +371,28 @@ class InteriorPoint:
             tau = max(0.99, 1.0 - mu)
             has = (self.hxl, self.hxu, self.hsl, self.hsu)
 
+            inf = torch.full((), float("inf"), **f64)
+
             def max_step(d, dd, h):
-                # largest a in (0, 1] with d + a dd >= (1 - tau) d wherever h
-                bad = h & (dd < 0)
-                if not bool(bad.any()):
-                    return 1.0
-                return min(1.0, float((-tau * d[bad] / dd[bad]).min()))
+                # largest a with d + a dd >= (1 - tau) d wherever h (device scalar)
+                return torch.where(h & (dd < 0), -tau * d / dd, inf).min() if d.numel() else inf
 
             def primal_step(dx_, ds_):
-                return min(max_step(dlx, dx_, self.hxl), max_step(dux, -dx_, self.hxu),
-                           max_step(dls, ds_, self.hsl), max_step(dus, -ds_, self.hsu))
+                return min(1.0, float(torch.stack([max_step(dlx, dx_, self.hxl), max_step(dux, -dx_, self.hxu),
+                                                   max_step(dls, ds_, self.hsl),
+                                                   max_step(dus, -ds_, self.hsu)]).min()))
 
             def merit(f_, x_, s_, c_):
-                lg = sum(float(torch.log(d[h]).sum()) for d, h in zip(self._dist(x_, s_), has))
-                return float(f_) - mu * lg + nu * float((c_ - s_).abs().sum())
+                # device scalar
+                lg = sum(torch.where(h, torch.log(d), 0.0).sum() for d, h in zip(self._dist(x_, s_), has))
+                return f_ - mu * lg + nu * (c_ - s_).abs().sum()
 
             a_p = primal_step(dx, ds)
             if m:
                 nu = max(nu, 1.1 * float((lam + Ss * ds + rs).abs().max()))
             phi0 = merit(f, x, s, c)
             # directional derivative of the merit function along (dx, ds)
-            dphi = float((g + bx) @ dx) + float(bs @ ds) - nu * float(rc.abs().sum())
+            dphi = torch.clamp((g + bx) @ dx + bs @ ds - nu * rc.abs().sum(), max=0.0)
             self.times["other"] += time.perf_counter() - t0
 
             def trial(a, dx_, ds_):
@@ -397,7 +400,7 @@ class InteriorPoint:
                 ft, ct = self._timed("callbacks", self._obj_cons, xt)
                 t1 = time.perf_counter()
                 phit = merit(ft, xt, st, ct)
-                ok = math.isfinite(phit) and phit <= phi0 + 1e-4 * a_p * min(dphi, 0.0) * (a / a_p)
+                ok = bool(torch.isfinite(phit) & (phit <= phi0 + 1e-4 * a * dphi))
                 self.times["other"] += time.perf_counter() - t1
                 return ok, ct - st
 
@@ -444,8 +447,8 @@ class InteriorPoint:
             dzu = torch.where(self.hxu, (mu + zu * dx) / dux - zu, 0.0)
             dvl = torch.where(self.hsl, (mu - vl * ds) / dls - vl, 0.0)
             dvu = torch.where(self.hsu, (mu + vu * ds) / dus - vu, 0.0)
-            a_d = min(max_step(zl, dzl, self.hxl), max_step(zu, dzu, self.hxu),
-                      max_step(vl, dvl, self.hsl), max_step(vu, dvu, self.hsu))
+            a_d = min(1.0, float(torch.stack([max_step(zl, dzl, self.hxl), max_step(zu, dzu, self.hxu),
+                                              max_step(vl, dvl, self.hsl), max_step(vu, dvu, self.hsu)]).min()))
             last_step = f"a_p {a_p:.2e} alpha {alpha:.2e} a_d {a_d:.2e} soc {soc} nu {nu:.1e}"
             x, s = x + alpha * dx, s + alpha * ds
             lam = lam + alpha * dlam
