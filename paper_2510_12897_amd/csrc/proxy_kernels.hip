@@ -2,16 +2,20 @@
 // that maps bus loads to (vm, va, pg, qg), trained with a penalty on the
 // FP64 constraint violation that the callback kernels compute.
 //
-//  - prox_gemm: C[M,N] = A[M,K] B[K,N] on the matrix cores
-//    (v_mfma_f32_32x32x16_bf16): operands are FP32 in memory, rounded to
-//    BF16 (nearest even) when staged into LDS, accumulated in FP32; optional
-//    fused epilogue bias + exact GELU.  128x128 or 128x64 block tile, BK = 64, four
-//    waves of 64x64 or 64x32, global loads of the next K tile overlapped with the
-//    matrix-core work on the current one.
+//  - prox_gemm / prox_gemm_mixed: C[M,N] = A[M,K] B[K,N] on the matrix
+//    cores (v_mfma_f32_32x32x16_bf16), FP32 accumulation: each operand is
+//    either FP32 in memory, rounded to BF16 (nearest even) when staged into
+//    LDS, or already BF16 (the MLP's weight copy and hidden activations);
+//    optional fused epilogue bias + exact GELU (FP32 or BF16 output), staged
+//    through LDS for whole-row vector stores.  128x128 or 128x64 block tile,
+//    BK = 64, four waves of 64x64 or 64x32, global loads of the next K tile
+//    overlapped with the matrix-core work on the current one.
 //  - elementwise / reduction kernels: GELU backward, deterministic column
-//    sums (bias gradient), Adam, output squashing into the variable bounds
-//    and its backward, the penalty loss with its constraint weights, and the
-//    chain weights that carry the arc-flow gradient back to the voltages.
+//    sums (bias gradient), Adam (also with its step count on the device and
+//    a BF16 copy of the parameters), output squashing into the variable
+//    bounds and its backward (also fused with the objective and loss-weight
+//    step), the penalty loss with its constraint weights, and the chain
+//    weights that carry the arc-flow gradient back to the voltages.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
