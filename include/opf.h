@@ -438,6 +438,11 @@ int prox_adam_dev(float *p, const float *g, float *m1, float *m2, int64_t n, flo
  * (OPF_E_ARG otherwise). */
 int prox_squash_fwd(opf_model model, const float *z, int B, double va_span, double *X, void *stream);
 
+/* prox_squash_fwd that leaves the arc variables p, q of X as they are (for
+ * a caller that writes them next, as opf_batch_flows does): 2N + 2G entries
+ * per instance written instead of n. */
+int prox_squash_fwd_vars(opf_model model, const float *z, int B, double va_span, double *X, void *stream);
+
 /* dz [B, 2N+2G] = scale * (d x / d z)^T g for the va, vm, pg, qg entries of
  * g = gX1 + gX2 + obj_scale * gObj ([B, n] FP64 each; gX2 and gObj may be
  * NULL). */
@@ -451,7 +456,9 @@ int prox_squash_bwd(opf_model model, const float *z, int B, double va_span, cons
  * paper's Cvio, Sec. IV-A5); W [B, m] = d pen / d c on the non-flow rows;
  * gpq [B, 4L] = d pen / d (p, q).  The flow rows of W receive 0, or with
  * vjp != 0 the weights of prox_vjp_weights (computed in the same pass), so
- * that J^T W is the whole constraint part of the gradient. */
+ * that J^T W is the whole constraint part of the gradient.  With vjp != 0
+ * and 4L <= 7680, gpq may be NULL: d pen / d (p, q), needed only by those
+ * weights, then stays on chip (OPF_E_ARG for a NULL gpq otherwise). */
 int prox_penalty(opf_model model, const double *C, const double *X, const double *F, double obj_scale, double rho,
                  int B, int vjp, double *pen, double *cvio, double *W, double *gpq, void *stream);
 

@@ -151,9 +151,18 @@ int prox_squash_fwd(opf_model model, const float* z, int B, double va_span, doub
     if (int rc = static_model(model)) return rc;
     if (B < 1 || !z || !X) return set_err(OPF_E_ARG, "bad arguments");
     DeviceGuard dg(model->device);
-    return launched(opf::prox_squash_fwd(z, B, box_of(model, va_span), X, model->hm.ly.n,
+    return launched(opf::prox_squash_fwd(z, B, box_of(model, va_span), X, model->hm.ly.n, true,
                                          static_cast<hipStream_t>(stream)),
                     "prox_squash_fwd launch");
+}
+
+int prox_squash_fwd_vars(opf_model model, const float* z, int B, double va_span, double* X, void* stream) {
+    if (int rc = static_model(model)) return rc;
+    if (B < 1 || !z || !X) return set_err(OPF_E_ARG, "bad arguments");
+    DeviceGuard dg(model->device);
+    return launched(opf::prox_squash_fwd(z, B, box_of(model, va_span), X, model->hm.ly.n, false,
+                                         static_cast<hipStream_t>(stream)),
+                    "prox_squash_fwd_vars launch");
 }
 
 int prox_squash_bwd(opf_model model, const float* z, int B, double va_span, const double* gX1, const double* gX2,
@@ -169,7 +178,12 @@ int prox_squash_bwd(opf_model model, const float* z, int B, double va_span, cons
 int prox_penalty(opf_model model, const double* C, const double* X, const double* F, double obj_scale, double rho,
                  int B, int vjp, double* pen, double* cvio, double* W, double* gpq, void* stream) {
     if (int rc = static_model(model)) return rc;
-    if (B < 1 || !C || !X || !pen || !cvio || !W || !gpq) return set_err(OPF_E_ARG, "bad arguments");
+    if (B < 1 || !C || !X || !pen || !cvio || !W) return set_err(OPF_E_ARG, "bad arguments");
+    // without gpq the gradient on p, q stays in the workgroup's LDS: only
+    // with vjp (its one reader) and when it fits
+    constexpr int32_t kMaxOnChip = 7680;  // 60 KiB of doubles beside the 4 KiB of reduction arrays
+    if (!gpq && (!vjp || model->hm.ly.L * 4 > kMaxOnChip))
+        return set_err(OPF_E_ARG, "gpq may be NULL only with vjp and at most %d arc variables", kMaxOnChip);
     DeviceGuard dg(model->device);
     return launched(opf::prox_penalty(C, X, F, obj_scale, rows_of(model), rho, B, pen, cvio, W, gpq, vjp ? 1 : 0,
                                       static_cast<hipStream_t>(stream)),

@@ -46,7 +46,8 @@ hipError_t prox_adam(float* p, const float* g, float* m1, float* m2, int64_t n, 
 hipError_t prox_adam_dev(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2,
                          float eps, int32_t* step, void* pb, hipStream_t s);
 hipError_t prox_to_bf16(const float* x, int64_t n, void* y, hipStream_t s);
-hipError_t prox_squash_fwd(const float* z, int B, const ProxBox& box, double* X, int64_t n, hipStream_t s);
+// arcs: also set the arc variables p, q to 0 (else they are left as they are)
+hipError_t prox_squash_fwd(const float* z, int B, const ProxBox& box, double* X, int64_t n, bool arcs, hipStream_t s);
 hipError_t prox_squash_bwd(const float* z, int B, const ProxBox& box, const double* gX1, const double* gX2,
                            const double* gObj, double obj_scale, int64_t n, float* dz, float scale, hipStream_t s);
 hipError_t prox_penalty(const double* C, const double* X, const double* F, double obj_scale, const ProxRows& rows,

@@ -504,11 +504,11 @@ __device__ __forceinline__ double sigmoid(double z) { return 1.0 / (1.0 + exp(-z
 
 // z [B, 2N + 2G] (vm, va, pg, qg blocks, FP32) -> the first 2N + 2G entries
 // of each instance's x [B, n] (va, vm, pg, qg, FP64); p and q are zeroed.
+// per = n writes every entry (p, q = 0); per = 2N + 2G leaves p, q as they are.
 __global__ void squash_fwd_kernel(const float* __restrict__ z, int B, ProxBox box, double* __restrict__ X,
-                                  int64_t n) {
+                                  int64_t n, int64_t per) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int N = box.N, G = box.G;
-    const int64_t per = n;
     if (idx >= (int64_t)B * per) return;
     const int64_t b = idx / per;
     const int64_t e = idx % per;
@@ -528,7 +528,7 @@ __global__ void squash_fwd_kernel(const float* __restrict__ z, int B, ProxBox bo
     } else {
         v = 0.0;
     }
-    X[idx] = v;
+    X[b * n + e] = v;
 }
 
 // dz from dL/dx = gX + gX2 + obj_scale * gObj on the (va, vm, pg, qg)
@@ -646,11 +646,12 @@ __global__ void __launch_bounds__(256) penalty_kernel(const double* __restrict__
                                                       ProxRows rows, double rho, double* __restrict__ pen,
                                                       double* __restrict__ cvio, double* W, double* gpq, int vjp) {
     __shared__ double s_pen[256], s_vio[256];
+    extern __shared__ double s_gq[];  // d pen / d (p, q) when gpq is NULL (vjp only)
     const int64_t b = blockIdx.x;
     const double* c = C + b * rows.m;
     const double* x = X + b * rows.n;
     double* w = W + b * rows.m;
-    double* gq = gpq + b * rows.npq;
+    double* gq = gpq ? gpq + b * rows.npq : s_gq;
     double sp = 0.0, sv = 0.0;
     for (int r = threadIdx.x; r < rows.m; r += 256) {
         const double cr = c[r];
@@ -861,9 +862,10 @@ hipError_t prox_to_bf16(const float* x, int64_t n, void* y, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t prox_squash_fwd(const float* z, int B, const ProxBox& box, double* X, int64_t n, hipStream_t s) {
-    const int64_t tot = (int64_t)B * n;
-    hipLaunchKernelGGL(squash_fwd_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, z, B, box, X, n);
+hipError_t prox_squash_fwd(const float* z, int B, const ProxBox& box, double* X, int64_t n, bool arcs, hipStream_t s) {
+    const int64_t per = arcs ? n : 2 * (int64_t)box.N + 2 * box.G;
+    const int64_t tot = (int64_t)B * per;
+    hipLaunchKernelGGL(squash_fwd_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, z, B, box, X, n, per);
     return hipGetLastError();
 }
 
@@ -885,7 +887,9 @@ hipError_t prox_loss_bwd(const float* z, int B, const ProxBox& box, const ProxOb
 
 hipError_t prox_penalty(const double* C, const double* X, const double* F, double obj_scale, const ProxRows& rows,
                         double rho, int B, double* pen, double* cvio, double* W, double* gpq, int vjp, hipStream_t s) {
-    hipLaunchKernelGGL(penalty_kernel, dim3(B), dim3(256), 0, s, C, X, F, obj_scale, rows, rho, pen, cvio, W, gpq, vjp);
+    const size_t lds = gpq ? 0 : sizeof(double) * (size_t)rows.npq;
+    hipLaunchKernelGGL(penalty_kernel, dim3(B), dim3(256), lds, s, C, X, F, obj_scale, rows, rho, pen, cvio, W, gpq,
+                       vjp);
     return hipGetLastError();
 }
 

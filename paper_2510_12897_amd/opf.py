@@ -152,6 +152,7 @@ def lib():
         "prox_adam_dev": ([_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                            ctypes.c_float, _vp, _vp, _vp], ctypes.c_int),
         "prox_squash_fwd": ([_vp, _vp, ctypes.c_int, ctypes.c_double, _vp, _vp], ctypes.c_int),
+        "prox_squash_fwd_vars": ([_vp, _vp, ctypes.c_int, ctypes.c_double, _vp, _vp], ctypes.c_int),
         "prox_squash_bwd": ([_vp, _vp, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, ctypes.c_double, _vp,
                              ctypes.c_float, _vp], ctypes.c_int),
         "prox_penalty": ([_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, _vp, _vp,

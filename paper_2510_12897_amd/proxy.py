@@ -338,7 +338,8 @@ def _make_loss_function():
             B, n, m = pen.B, pen.model.n, pen.model.m
             dev = z.device
             X = torch.empty(B, n, dtype=torch.float64, device=dev)
-            _check(lib().prox_squash_fwd(pen.model.handle, _p(z), B, float(va_span), _p(X), _stream()))
+            # the arc variables are left for the flows, which write every one
+            _check(lib().prox_squash_fwd_vars(pen.model.handle, _p(z), B, float(va_span), _p(X), _stream()))
             pen.batch.flows(X)
             Xflat = X.view(-1)
             Fo = torch.empty(B, dtype=torch.float64, device=dev)
@@ -347,8 +348,9 @@ def _make_loss_function():
             loss = torch.empty(B, dtype=torch.float64, device=dev)
             cvio = torch.empty(B, dtype=torch.float64, device=dev)
             W = torch.empty(B * m, dtype=torch.float64, device=dev)
-            gpq = torch.empty(B * 4 * pen.L, dtype=torch.float64, device=dev)
             vjp = int(bool(ctx.needs_input_grad[0]))
+            # with a gradient to come, d pen / d (p, q) stays on chip when it fits
+            gpq = None if vjp and 4 * pen.L <= 7680 else torch.empty(B * 4 * pen.L, dtype=torch.float64, device=dev)
             _check(lib().prox_penalty(pen.model.handle, _p(C), _p(Xflat), _p(Fo), float(pen.obj_scale),
                                       float(pen.rho), B, vjp, _p(loss), _p(cvio), _p(W), _p(gpq), _stream()))
             pen.last = {"x": X, "f": Fo, "c": C.view(B, m), "cvio": cvio}

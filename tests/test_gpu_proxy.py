@@ -418,7 +418,40 @@ def test_penalty_fused_vjp_weights(dev, P):
     for a, b in zip(outs[0][:2] + outs[0][3:], outs[1][:2] + outs[1][3:]):
         assert torch.equal(a, b)
     assert torch.equal(outs[1][2], Wt)
+    # with vjp, d pen / d (p, q) may stay on chip (gpq NULL): the same loss,
+    # Cvio and weights
+    o = [torch.empty(B, dtype=torch.float64, device=dev) for _ in range(2)] + [
+        torch.full((B * m,), float("nan"), dtype=torch.float64, device=dev)]
+    assert lib().prox_penalty(pen.model.handle, P._p(C), P._p(X), P._p(F), 1e-3, 4.0, B, 1, *[P._p(t) for t in o],
+                              None, P._stream()) == 0
+    torch.cuda.synchronize()
+    for a, b in zip(o, outs[1][:3]):
+        assert torch.equal(a, b)
+    # without vjp a NULL gpq is refused
+    from paper_2510_12897_amd.opf import OPFError, _check
+    with pytest.raises(OPFError, match="gpq may be NULL"):
+        _check(lib().prox_penalty(pen.model.handle, P._p(C), P._p(X), P._p(F), 1e-3, 4.0, B, 0,
+                                  *[P._p(t) for t in o], None, P._stream()))
     pen.close()
+
+
+def test_squash_without_arc_variables(dev, P):
+    """prox_squash_fwd_vars writes the va, vm, pg, qg entries of
+    prox_squash_fwd and leaves p, q as they were."""
+    from paper_2510_12897_amd.opf import lib
+    case = _case()
+    B = 5
+    m = P.Penalty(case, B)
+    n, D = m.model.n, 2 * case["n_bus"] + 2 * case["n_gen"]
+    z = torch.randn(B, D, device=dev)
+    X1 = torch.full((B, n), 7.0, dtype=torch.float64, device=dev)
+    X2 = torch.full((B, n), 7.0, dtype=torch.float64, device=dev)
+    assert lib().prox_squash_fwd(m.model.handle, P._p(z), B, 0.3, P._p(X1), P._stream()) == 0
+    assert lib().prox_squash_fwd_vars(m.model.handle, P._p(z), B, 0.3, P._p(X2), P._stream()) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(X1[:, :D], X2[:, :D])
+    assert bool((X1[:, D:] == 0).all()) and bool((X2[:, D:] == 7.0).all())
+    m.close()
 
 
 def test_penalty_vjp_vs_finite_differences(dev, P):
