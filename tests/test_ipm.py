@@ -132,3 +132,24 @@ def test_condensed_matrix_matches_dense_products():
     J = orc.dense_jacobian(ev)
     K = orc.dense_hessian(ev) + np.diag(Sx.numpy()) + J.T @ np.diag(Ss.numpy()) @ J + delta * np.eye(mdl.n)
     np.testing.assert_allclose(K @ dx.numpy(), rhs.numpy(), rtol=0, atol=1e-8 * np.abs(K).max() * np.abs(dx.numpy()).max())
+
+
+def test_linear_solver_choice_is_checked():
+    mdl = OracleModel(case0())
+    assert InteriorPoint(mdl).linear_solver == "dense"          # the CPU default
+    with pytest.raises(ValueError, match="GPU only"):
+        InteriorPoint(mdl, linear_solver="sparse")
+    with pytest.raises(ValueError, match="linear_solver"):
+        InteriorPoint(mdl, linear_solver="qr")
+
+
+def test_warm_start_from_the_optimum_takes_few_iterations():
+    """Started at a solution, the method stops after few iterations at the
+    same optimum (the primal start is used as given, pushed inside its
+    bounds)."""
+    mdl = OracleModel(case0())
+    r = InteriorPoint(mdl, tol=1e-6).solve()
+    rw = InteriorPoint(mdl, tol=1e-6).solve(r["x"].clone())
+    assert rw["status"] == "solved"
+    assert rw["iterations"] < r["iterations"]
+    assert abs(rw["f"] - r["f"]) <= 1e-6 * abs(r["f"])
