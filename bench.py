@@ -711,6 +711,10 @@ def main():
     ap.add_argument("--inputs", type=int, default=256, help="distinct pre-generated (x, y) pairs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle timing budget (0 = skip)")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / multi-period / N-1 legs")
+    ap.add_argument("--legs", default="all",
+                    help="comma-separated extra legs to run (batch64, multiperiod_2k_x48, "
+                         "multiperiod_storage_2k_x48, contingency_1k_x201, rect_10k, points16_10k, ipm_300bus, "
+                         "proxy_300bus, proxy_warm_start_300bus, cpu_oracle_batch64; default all)")
     ap.add_argument("--batch-reps", type=int, default=20)
     ap.add_argument("--proxy-steps", type=int, default=1500, help="training steps of the proxy leg (0 = skip)")
     ap.add_argument("--eager", action="store_true", help="launch the headline sets without a HIP graph")
@@ -791,72 +795,61 @@ def main():
             "frac_of_copy": achieved / copy_gbs,
         },
     }
+    def leg_multiperiod():
+        cs = synth.network(2000, 2700, 400, 2)
+        pd_t, qd_t = synth.mp_loads(cs, 48, 202)
+        return bench_model(torch, opf, synth, cs, dict(n_periods=48, pd_t=pd_t, qd_t=qd_t, ramp_ratio=0.2), 24, 8, 24,
+                           log, "multi-period", T=48, mp_loads=True)
+
+    def leg_multiperiod_storage():
+        # storage at the largest 10 % of loads (1.5x energy ratings) and 100
+        # electrolyzer-like devices, 30-minute periods
+        cs = synth.network(2000, 2700, 400, 2)
+        pd_t, qd_t = synth.mp_loads(cs, 48, 202)
+        r = bench_model(torch, opf, synth, cs, dict(n_periods=48, pd_t=pd_t, qd_t=qd_t, ramp_ratio=0.2,
+                                                    storage=synth.storage(cs, 203), stor_dt=0.5,
+                                                    devices=synth.devices(cs, 100, 204)), 24, 8, 24,
+                        log, "multi-period with storage and devices", T=48, mp_loads=True)
+        r["workload"] = "2000 buses x 48 periods, 200 storage units at the largest loads, 100 devices"
+        return r
+
+    def leg_contingency():
+        cs = synth.network(1000, 1350, 200, 31)
+        out = synth.outages(cs, 200, 32)
+        return bench_model(torch, opf, synth, cs, dict(n_cont=200, outaged=out), 16, 6, 24, log, "N-1 copies", K=200)
+
+    def leg_rect():
+        cs = synth.network(10000, 13500, 2000, 1)
+        r = bench_model(torch, opf, synth, cs, dict(form="rect"), 256, 64, 500, log, "rectangular 10k", seed=101)
+        r["workload"] = "plain rectangular-form callback sets, 10000-bus network, HIP graph of back-to-back launches"
+        return r
+
+    legs = [("batch64", lambda: bench_batch(args, torch, opf, synth, log)),
+            ("multiperiod_2k_x48", leg_multiperiod),
+            ("multiperiod_storage_2k_x48", leg_multiperiod_storage),
+            ("contingency_1k_x201", leg_contingency),
+            ("rect_10k", leg_rect),
+            ("points16_10k", lambda: bench_points(torch, opf, synth, log, B=16)),
+            ("ipm_300bus", lambda: bench_ipm(torch, opf, synth, log))]
+    if args.proxy_steps > 0:
+        legs += [("proxy_300bus", lambda: bench_proxy(args, torch, synth, log)),
+                 ("proxy_warm_start_300bus", lambda: bench_warm_start(torch, opf, synth, log))]
+    wanted = None if args.legs == "all" else set(args.legs.split(","))
     if not args.no_extra:
         extra = {}
-        try:
-            extra["batch64"] = bench_batch(args, torch, opf, synth, log)
-        except Exception as e:  # a failing leg must not hide the headline line
-            extra["batch64"] = {"error": repr(e)}
-        try:
-            cs = synth.network(2000, 2700, 400, 2)
-            pd_t, qd_t = synth.mp_loads(cs, 48, 202)
-            extra["multiperiod_2k_x48"] = bench_model(
-                torch, opf, synth, cs, dict(n_periods=48, pd_t=pd_t, qd_t=qd_t, ramp_ratio=0.2), 24, 8, 24,
-                log, "multi-period", T=48, mp_loads=True)
-        except Exception as e:
-            extra["multiperiod_2k_x48"] = {"error": repr(e)}
-        try:
-            # storage at the largest 10 % of loads (1.5x energy ratings) and
-            # 100 electrolyzer-like devices, 30-minute periods
-            cs = synth.network(2000, 2700, 400, 2)
-            pd_t, qd_t = synth.mp_loads(cs, 48, 202)
-            extra["multiperiod_storage_2k_x48"] = bench_model(
-                torch, opf, synth, cs, dict(n_periods=48, pd_t=pd_t, qd_t=qd_t, ramp_ratio=0.2,
-                                            storage=synth.storage(cs, 203), stor_dt=0.5,
-                                            devices=synth.devices(cs, 100, 204)), 24, 8, 24,
-                log, "multi-period with storage and devices", T=48, mp_loads=True)
-            extra["multiperiod_storage_2k_x48"]["workload"] = (
-                "2000 buses x 48 periods, 200 storage units at the largest loads, 100 devices")
-        except Exception as e:
-            extra["multiperiod_storage_2k_x48"] = {"error": repr(e)}
-        try:
-            cs = synth.network(1000, 1350, 200, 31)
-            out = synth.outages(cs, 200, 32)
-            extra["contingency_1k_x201"] = bench_model(
-                torch, opf, synth, cs, dict(n_cont=200, outaged=out), 16, 6, 24, log, "N-1 copies", K=200)
-        except Exception as e:
-            extra["contingency_1k_x201"] = {"error": repr(e)}
-        try:
-            cs = synth.network(10000, 13500, 2000, 1)
-            extra["rect_10k"] = bench_model(torch, opf, synth, cs, dict(form="rect"), 256, 64, 500, log,
-                                            "rectangular 10k", seed=101)
-            extra["rect_10k"]["workload"] = ("plain rectangular-form callback sets, 10000-bus network, "
-                                             "HIP graph of back-to-back launches")
-        except Exception as e:
-            extra["rect_10k"] = {"error": repr(e)}
-        try:
-            extra["points16_10k"] = bench_points(torch, opf, synth, log, B=16)
-        except Exception as e:
-            extra["points16_10k"] = {"error": repr(e)}
-        try:
-            extra["ipm_300bus"] = bench_ipm(torch, opf, synth, log)
-        except Exception as e:
-            extra["ipm_300bus"] = {"error": repr(e)}
-        if args.proxy_steps > 0:
+        for name, fn in legs:
+            if wanted is not None and name not in wanted:
+                continue
             try:
-                extra["proxy_300bus"] = bench_proxy(args, torch, synth, log)
-            except Exception as e:
-                extra["proxy_300bus"] = {"error": repr(e)}
-            try:
-                extra["proxy_warm_start_300bus"] = bench_warm_start(torch, opf, synth, log)
-            except Exception as e:
-                extra["proxy_warm_start_300bus"] = {"error": repr(e)}
+                extra[name] = fn()
+            except Exception as e:  # a failing leg must not hide the headline line
+                extra[name] = {"error": repr(e)}
         result["extra"] = extra
     if args.cpu_seconds > 0:
         from oracle import oracle
 
         result["cpu_baseline"] = bench_cpu_baseline(h, synth, oracle, args.cpu_seconds, log)
-        if not args.no_extra:
+        if not args.no_extra and (wanted is None or "cpu_oracle_batch64" in wanted):
             try:
                 result.setdefault("extra", {})["cpu_oracle_batch64"] = bench_cpu_batch64(synth, oracle, log)
             except Exception as e:
