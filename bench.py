@@ -539,11 +539,9 @@ def bench_proxy(args, torch, synth, log):
     curve = P.fallback_curve(cvp)
     # the training step split into its parts, each timed on its own: the MLP
     # forward and backward (matrix-core GEMMs, GELU, bias sums), the FP64
-    # loss node forward and backward (squash, flows, batch evaluation,
-    # penalty, J^T W, squash backward) and the Adam step
+    # loss node forward and backward and the Adam step
     gen.manual_seed(99)
     loads, feats = px.sample(gen)
-    px.pen.set_loads(loads[:, :px.N], loads[:, px.N:])
     gz = torch.randn(B, px.mlp.dims[-1], device=px.dev) * 1e-3
 
     def mlp_part():
@@ -554,7 +552,7 @@ def bench_proxy(args, torch, synth, log):
 
     def loss_part():
         z = z0.clone().requires_grad_(True)
-        P._fun("loss").apply(z, px).mean().backward()
+        P._fun("loss").apply(z, px, loads, False).mean().backward()
 
     zz = px.mlp(feats)
     zz.backward(gz)
@@ -589,8 +587,10 @@ def bench_proxy(args, torch, synth, log):
                train_steps=steps, ms_per_train_step=train_s * 1e3, loss_first=first, loss_last=last,
                ms_split={**split, "note": "each part timed on its own over 20 repetitions; mlp_fwd_bwd = the "
                                           "matrix-core GEMMs with their GELU and bias-sum kernels, loss_fwd_bwd = "
-                                          "the FP64 side (squash, flows, batch evaluation, penalty, J^T W, squash "
-                                          "backward)"},
+                                          "the FP64 side: with fused_loss, one launch (squashing, flows, rows, "
+                                          "penalty, d loss / d z in LDS) and the gradient scaling; else squash, "
+                                          "flows, batch evaluation, penalty, J^T W, squash backward"},
+               fused_loss=bool(px.pen.fused),
                inferences_per_s=B / infer_s, mlp_forward_tflops=mlp_tflops, mlp_peak_tflops=2500.0,
                heldout_cvio_mean=float(cvp.mean()), heldout_cvio_max=float(cvp.max()),
                x0_cvio_mean=float(cv0.mean()), flatstart_cvio_mean=float(cvf.mean()),

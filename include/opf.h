@@ -486,6 +486,37 @@ int prox_vjp_sum(opf_model model, const double *X, const double *gX1, const doub
  * as the two calls (no [B, n] intermediate). */
 int prox_loss_bwd(opf_model model, const float *z, int B, double va_span, const double *X, const double *gX1,
                   double obj_scale, const double *wb, float *dz, void *stream);
+
+/* The proxy's whole FP64 loss side in one launch, one workgroup per sample
+ * with the sample's working set in LDS: squashing of z [B, 2N+2G] (FP32,
+ * vm, va, pg, qg blocks) into the variable boxes, arc flows p, q := F(vm, va)
+ * (Sec. III-C, the branch flow terms), the non-flow rows at loads [B, 2N]
+ * (each sample's pd then qd, FP64), and
+ *   loss[b] = rho * (squared violations of the non-flow rows and of the p, q
+ *             bounds) + obj_scale * f(x_b),
+ *   cvio[b] = largest violation over every row and the p, q bounds (Cvio,
+ *             Sec. IV-A5),
+ * the values of prox_squash_fwd_vars, opf_batch_flows, opf_batch_eval and
+ * prox_penalty in sequence.  gz [B, 2N+2G] (FP64, z's layout) receives
+ * d loss[b] / d z_b, the chain of prox_penalty (vjp), opf_batch_jtprod and
+ * prox_loss_bwd at wb = 1 (NULL: not computed).  X [B, n] and C [B, m]
+ * receive x (with the arc flows) and c(x) when non-NULL.  The arc values,
+ * the thermal and angle rows and X equal those launches' bits; the balance
+ * rows, loss and gz are summed in another fixed order (rounding-level
+ * differences; the same bits on every run).  Takes a static polar model
+ * without storage units or devices (prox_loss_fused_fits); OPF_E_ARG
+ * otherwise.  Buffers are device memory the caller owns. */
+int prox_loss_fused(opf_model model, const float *z, int B, double va_span, const double *loads, double rho,
+                    double obj_scale, double *loss, double *cvio, double *gz, double *X, double *C, void *stream);
+
+/* 1 when prox_loss_fused takes this model: static, polar, no storage units
+ * or devices, and one sample's working set (4N + 2G + 9L doubles) within
+ * 64 KiB of LDS; 0 when not; OPF_E_STATE for an invalid handle. */
+int prox_loss_fused_fits(opf_model model);
+
+/* dz [B, D] = (float)(wb[b] * gz[b, j]): the backward of prox_loss_fused's
+ * loss under an incoming gradient wb [B] (device FP64). */
+int prox_scale_rows(const double *gz, const double *wb, int B, int D, float *dz, void *stream);
 #ifdef __cplusplus
 }
 #endif

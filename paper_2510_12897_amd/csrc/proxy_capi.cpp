@@ -59,6 +59,18 @@ opf::ProxRows rows_of(opf_model m) {
     return r;
 }
 
+// The fused loss kernel's conditions beyond a static polar model: no storage
+// units or devices, x in the order (va, vm, pg, qg, p, q), and one sample's
+// working set within 64 KiB of LDS.
+constexpr size_t kFusedLdsMax = 65536;
+bool fused_fits(opf_model m) {
+    const opf::Layout& ly = m->hm.ly;
+    const int64_t N = ly.N, G = ly.G, L = ly.L;
+    return ly.nrep == 1 && !ly.rect && ly.S == 0 && ly.D == 0 && ly.x_va == 0 && ly.x_vm == N &&
+           ly.x_pg == 2 * N && ly.x_qg == 2 * N + G && ly.x_p == 2 * N + 2 * G && ly.x_q == ly.x_p + 2 * L &&
+           opf::prox_loss_fused_lds(ly.N, ly.L, ly.G) <= kFusedLdsMax;
+}
+
 }  // namespace
 
 extern "C" {
@@ -223,6 +235,31 @@ int prox_loss_bwd(opf_model model, const float* z, int B, double va_span, const 
     return launched(opf::prox_loss_bwd(z, B, box_of(model, va_span), ob, obj_scale != 0.0 ? X : nullptr, gX1,
                                        obj_scale, wb, ly.n, dz, static_cast<hipStream_t>(stream)),
                     "prox_loss_bwd launch");
+}
+
+
+int prox_loss_fused_fits(opf_model model) {
+    if (!valid_model(model)) return set_err(OPF_E_STATE, "invalid or destroyed model handle");
+    return fused_fits(model) ? 1 : 0;
+}
+
+int prox_loss_fused(opf_model model, const float* z, int B, double va_span, const double* loads, double rho,
+                    double obj_scale, double* loss, double* cvio, double* gz, double* X, double* C, void* stream) {
+    if (int rc = static_model(model)) return rc;
+    if (B < 1 || !z || !loads || !loss || !cvio) return set_err(OPF_E_ARG, "bad arguments");
+    if (!fused_fits(model))
+        return set_err(OPF_E_ARG, "the fused loss takes a model without storage or devices whose sample fits "
+                                  "%zu bytes of LDS",
+                       kFusedLdsMax);
+    DeviceGuard dg(model->device);
+    return launched(opf::prox_loss_fused(model->dm, box_of(model, va_span), rows_of(model), z, loads, B, rho,
+                                         obj_scale, loss, cvio, gz, X, C, static_cast<hipStream_t>(stream)),
+                    "prox_loss_fused launch");
+}
+
+int prox_scale_rows(const double* gz, const double* wb, int B, int D, float* dz, void* stream) {
+    if (B < 1 || D < 1 || !gz || !wb || !dz) return set_err(OPF_E_ARG, "bad arguments");
+    return launched(opf::prox_scale_rows(gz, wb, B, D, dz, static_cast<hipStream_t>(stream)), "prox_scale_rows launch");
 }
 
 }  // extern "C"

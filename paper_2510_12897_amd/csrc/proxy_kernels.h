@@ -7,6 +7,8 @@
 
 namespace opf {
 
+struct DevModel;
+
 // Variable boxes of one model (device pointers) for the output squashing.
 struct ProxBox {
     int32_t N, G;
@@ -63,5 +65,17 @@ hipError_t prox_vjp_sum(const double* X, const double* gX1, const double* gX2, c
                         const double* wb, int B, int64_t n, int64_t nfree, double* gX, hipStream_t s);
 hipError_t prox_loss_bwd(const float* z, int B, const ProxBox& box, const ProxObj& ob, const double* X,
                          const double* gX1, double obj_scale, const double* wb, int64_t n, float* dz, hipStream_t s);
+
+// The fused FP64 loss of B samples of one static polar model (one
+// workgroup each, the sample's working set in prox_loss_fused_lds bytes of
+// LDS): loss, cvio [B]; gz [B, 2N+2G] = d loss_b / d z_b (NULL: not
+// computed); X [B, n], C [B, m] on request (NULL: not written).  loads [B, 2N]
+// holds each sample's pd then qd.
+size_t prox_loss_fused_lds(int N, int L, int G);
+hipError_t prox_loss_fused(const DevModel& m, const ProxBox& box, const ProxRows& rows, const float* z,
+                           const double* loads, int B, double rho, double obj_scale, double* loss, double* cvio,
+                           double* gz, double* X, double* C, hipStream_t s);
+// dz [B, D] = (float)(wb[b] * gz[b, j])
+hipError_t prox_scale_rows(const double* gz, const double* wb, int B, int D, float* dz, hipStream_t s);
 
 }  // namespace opf

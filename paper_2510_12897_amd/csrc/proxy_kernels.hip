@@ -20,6 +20,7 @@
 
 #include <cstdint>
 
+#include "dev_model.h"
 #include "proxy_kernels.h"
 
 namespace opf {
@@ -502,33 +503,35 @@ __global__ void to_bf16_kernel(const float* __restrict__ x, int64_t n, __bf16* _
 
 __device__ __forceinline__ double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
 
+// Entry e < 2N + 2G (va, vm, pg, qg blocks of x) of the squashed network
+// output zb (vm, va, pg, qg blocks, FP32): the squashing kernel and the fused
+// loss kernel both call it, so both write the same bits.
+__device__ __forceinline__ double squash_entry(const ProxBox& box, const float* zb, int e) {
+    const int N = box.N, G = box.G;
+    if (e < N) return box.is_ref[e] ? 0.0 : box.va_span * tanh((double)zb[N + e]);  // va
+    if (e < 2 * N) {                                                                 // vm
+        const int i = e - N;
+        return box.vmin[i] + (box.vmax[i] - box.vmin[i]) * sigmoid((double)zb[i]);
+    }
+    if (e < 2 * N + G) {
+        const int k = e - 2 * N;
+        return box.pmin[k] + (box.pmax[k] - box.pmin[k]) * sigmoid((double)zb[2 * N + k]);
+    }
+    const int k = e - 2 * N - G;
+    return box.qmin[k] + (box.qmax[k] - box.qmin[k]) * sigmoid((double)zb[2 * N + G + k]);
+}
+
 // z [B, 2N + 2G] (vm, va, pg, qg blocks, FP32) -> the first 2N + 2G entries
 // of each instance's x [B, n] (va, vm, pg, qg, FP64); p and q are zeroed.
 // per = n writes every entry (p, q = 0); per = 2N + 2G leaves p, q as they are.
 __global__ void squash_fwd_kernel(const float* __restrict__ z, int B, ProxBox box, double* __restrict__ X,
                                   int64_t n, int64_t per) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int N = box.N, G = box.G;
+    const int D = 2 * box.N + 2 * box.G;
     if (idx >= (int64_t)B * per) return;
     const int64_t b = idx / per;
     const int64_t e = idx % per;
-    const float* zb = z + b * (2 * (int64_t)N + 2 * G);
-    double v;
-    if (e < N) {  // va
-        v = box.is_ref[e] ? 0.0 : box.va_span * tanh((double)zb[N + e]);
-    } else if (e < 2 * N) {  // vm
-        const int i = (int)(e - N);
-        v = box.vmin[i] + (box.vmax[i] - box.vmin[i]) * sigmoid((double)zb[i]);
-    } else if (e < 2 * N + G) {
-        const int k = (int)(e - 2 * N);
-        v = box.pmin[k] + (box.pmax[k] - box.pmin[k]) * sigmoid((double)zb[2 * N + k]);
-    } else if (e < 2 * N + 2 * G) {
-        const int k = (int)(e - 2 * N - G);
-        v = box.qmin[k] + (box.qmax[k] - box.qmin[k]) * sigmoid((double)zb[2 * N + G + k]);
-    } else {
-        v = 0.0;
-    }
-    X[b * n + e] = v;
+    X[b * n + e] = e < D ? squash_entry(box, z + b * D, (int)e) : 0.0;
 }
 
 // dz from dL/dx = gX + gX2 + obj_scale * gObj on the (va, vm, pg, qg)
@@ -733,6 +736,269 @@ __global__ void vjp_sum_kernel(const double* __restrict__ X, const double* __res
     gX[idx] = g;
 }
 
+// ------------------------------------------------------------ fused loss
+// The whole FP64 side of the training loss in one launch, one workgroup per
+// sample, every intermediate in LDS: squashing, the arc flows p, q := F(vm,
+// va), the non-flow rows (reference, angle, balance, thermal), the penalty,
+// the largest violation and, when asked, d loss / d z.  Only z, the loads
+// and the model's read-only arrays are read, and only the loss, Cvio and
+// d loss / d z are written (X and C on request): about 14 KB per 300-bus
+// sample, where the chain of batch launches moves [B, n] and [B, m] arrays
+// through HBM several times.
+//
+// The gradient is the same chain as the penalty VJP (J^T of the row
+// weights, carried to the voltages through the flows), written per branch
+// and summed per bus over the bus's half-edges in adjacency order (no
+// atomics: the same bits on every run).
+//
+// Flow, thermal-row and objective-term arithmetic is not contracted, as in
+// the callback kernels, so the arc flows, thermal rows and X equal those of
+// the batch launches bit for bit; the per-bus and per-sample sums are
+// ordered differently (rounding-level differences in the balance rows, the
+// loss and the gradient).
+constexpr int kFuseThreads = 256;
+
+// F = al u^2 + be w^2 + u w (a C + b S) and its derivatives in u, w and the
+// angle difference (the expression of the callback kernels' flow terms).
+struct PFlow {
+    double F, Fu, Fw, Ft;
+};
+__device__ __forceinline__ PFlow pflow(double al, double be, double a, double b, double u, double w, double C,
+                                       double S) {
+#pragma clang fp contract(off)
+    const double k1 = a * C + b * S;
+    const double k2 = b * C - a * S;
+    const double uw = u * w;
+    PFlow r;
+    r.F = al * u * u + be * w * w + uw * k1;
+    r.Fu = 2.0 * al * u + w * k1;
+    r.Fw = 2.0 * be * w + u * k1;
+    r.Ft = uw * k2;
+    return r;
+}
+
+__device__ __forceinline__ double viol(double v, double lo, double hi) {
+    return v < lo ? v - lo : (v > hi ? v - hi : 0.0);
+}
+
+__device__ __forceinline__ double wave_sum64(double v) {
+    for (int s = 32; s > 0; s >>= 1) v += __shfl_down(v, s, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max64(double v) {
+    for (int s = 32; s > 0; s >>= 1) v = fmax(v, __shfl_down(v, s, 64));
+    return v;
+}
+
+// The four flows of branch l at the voltages in LDS: p_f, q_f, p_t, q_t.
+struct BranchFlows {
+    PFlow pf, qf, pt, qt;
+    int fb, tb;
+};
+__device__ __forceinline__ BranchFlows branch_flows(const DevModel& m, int l, const double* s_va,
+                                                    const double* s_vm) {
+    const int L = m.L;
+    BranchFlows r;
+    r.fb = m.f_bus[l];
+    r.tb = m.t_bus[l];
+    const double* k = m.coef + l;  // Gff Bff Gft Bft Gtt Btt Gtf Btf, L apart
+    const double Gff = k[0], Bff = k[L], Gft = k[2 * L], Bft = k[3 * L];
+    const double Gtt = k[4 * L], Btt = k[5 * L], Gtf = k[6 * L], Btf = k[7 * L];
+    const double u = s_vm[r.fb], w = s_vm[r.tb];
+    double S, C;
+    sincos(s_va[r.fb] - s_va[r.tb], &S, &C);
+    r.pf = pflow(Gff, 0.0, Gft, Bft, u, w, C, S);
+    r.qf = pflow(-Bff, 0.0, -Bft, Gft, u, w, C, S);
+    r.pt = pflow(0.0, Gtt, Gtf, -Btf, u, w, C, S);
+    r.qt = pflow(0.0, -Btt, -Btf, -Gtf, u, w, C, S);
+    return r;
+}
+
+// LDS (doubles): va, vm [N each], pg, qg [G each] (x's order), the arc
+// values [4L] (p_f, p_t, q_f, q_t: x's order; later the half-edge gradient
+// terms d/dva_f, d/dva_t, d/dvm_f, d/dvm_t), d loss / d arc without the
+// balance rows [4L], the angle-row weights [L], the balance-row weights
+// [2N], three partials per wave.
+__global__ void __launch_bounds__(kFuseThreads) loss_fused_kernel(DevModel m, ProxBox box, ProxRows rows,
+                                                                  const float* __restrict__ z,
+                                                                  const double* __restrict__ loads, double rho,
+                                                                  double obj_scale, double* __restrict__ loss,
+                                                                  double* __restrict__ cvio, double* __restrict__ gz,
+                                                                  double* __restrict__ X, double* __restrict__ C) {
+#pragma clang fp contract(off)
+    extern __shared__ double lds[];
+    const int N = m.N, L = m.L, G = m.G, D = 2 * N + 2 * G;
+    double* s_va = lds;
+    double* s_vm = s_va + N;
+    double* s_pg = s_vm + N;
+    double* s_qg = s_pg + G;
+    double* s_pq = s_qg + G;
+    double* s_ap = s_pq + 4 * L;
+    double* s_wa = s_ap + 4 * L;
+    double* s_wb = s_wa + L;
+    double* s_red = s_wb + 2 * N;
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const float* zb = z + b * D;
+    double* xb = X ? X + b * rows.n : nullptr;
+    double* cb = C ? C + b * rows.m : nullptr;
+    const double* pdb = loads + b * 2 * N;
+    double pen = 0.0, fobj = 0.0, vio = 0.0;
+
+    for (int e = tid; e < D; e += kFuseThreads) {
+        const double v = squash_entry(box, zb, e);
+        lds[e] = v;
+        if (xb) xb[e] = v;
+    }
+    __syncthreads();
+
+    // branches: arc flows, angle and thermal rows, arc bounds
+    for (int l = tid; l < L; l += kFuseThreads) {
+        const BranchFlows f = branch_flows(m, l, s_va, s_vm);
+        const double arc[4] = {f.pf.F, f.pt.F, f.qf.F, f.qt.F};
+        const double rate2 = m.rate2[l];
+        const double cf = arc[0] * arc[0] + arc[2] * arc[2] - rate2;
+        const double ct = arc[1] * arc[1] + arc[3] * arc[3] - rate2;
+        const double ca = s_va[f.fb] - s_va[f.tb];
+        const double dvf = viol(cf, rows.lcon[m.c_thf + l], rows.ucon[m.c_thf + l]);
+        const double dvt = viol(ct, rows.lcon[m.c_tht + l], rows.ucon[m.c_tht + l]);
+        const double dva = viol(ca, rows.lcon[m.c_ang + l], rows.ucon[m.c_ang + l]);
+        pen += dvf * dvf;
+        pen += dvt * dvt;
+        pen += dva * dva;
+        vio = fmax(vio, fmax(fabs(dvf), fmax(fabs(dvt), fabs(dva))));
+        s_wa[l] = 2.0 * rho * dva;
+        const double wth[2] = {2.0 * rho * dvf, 2.0 * rho * dvt};
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+            const int e = rows.pq0 + a * L + l;
+            const double dq = viol(arc[a], rows.lvar[e], rows.uvar[e]);
+            pen += dq * dq;
+            vio = fmax(vio, fabs(dq));
+            s_pq[a * L + l] = arc[a];
+            s_ap[a * L + l] = 2.0 * arc[a] * wth[a & 1] + 2.0 * rho * dq;
+            if (xb) xb[e] = arc[a];
+        }
+        if (cb) {  // flow rows: p - F(v) with p := F(v), exactly 0
+            cb[m.c_pfr + l] = 0.0;
+            cb[m.c_qfr + l] = 0.0;
+            cb[m.c_pto + l] = 0.0;
+            cb[m.c_qto + l] = 0.0;
+            cb[m.c_ang + l] = ca;
+            cb[m.c_thf + l] = cf;
+            cb[m.c_tht + l] = ct;
+        }
+    }
+    // objective terms and reference rows
+    for (int k = tid; k < G; k += kFuseThreads) {
+        const double pg = s_pg[k];
+        fobj += m.c2[k] * pg * pg + m.c1[k] * pg + m.c0[k];
+    }
+    for (int q = tid; q < m.R; q += kFuseThreads) {
+        const double c = s_va[m.ref_bus[q]];
+        const double dv = viol(c, rows.lcon[m.c_ref + q], rows.ucon[m.c_ref + q]);
+        pen += dv * dv;
+        vio = fmax(vio, fabs(dv));
+        if (cb) cb[m.c_ref + q] = c;
+    }
+    __syncthreads();
+
+    // buses: balance rows over the half-edges in adjacency order
+    for (int i = tid; i < N; i += kFuseThreads) {
+        const double vm = s_vm[i], v2 = vm * vm;
+        double sp = 0.0, sq = 0.0;
+        for (int h = m.adj_ptr[i]; h < m.adj_ptr[i + 1]; h++) {
+            const int code = m.he[h];
+            const int a = (code >> 1) + ((code & 1) ? 0 : L);  // the arc at bus i: from or to side
+            sp += s_pq[a];
+            sq += s_pq[2 * L + a];
+        }
+        double cp = pdb[i] + m.gs[i] * v2 + sp, cq = pdb[N + i] - m.bs[i] * v2 + sq;
+        for (int q = m.gen_ptr[i]; q < m.gen_ptr[i + 1]; q++) {
+            const int k = m.gen_list[q];
+            cp -= s_pg[k];
+            cq -= s_qg[k];
+        }
+        const double dvp = viol(cp, rows.lcon[m.c_balp + i], rows.ucon[m.c_balp + i]);
+        const double dvq = viol(cq, rows.lcon[m.c_balq + i], rows.ucon[m.c_balq + i]);
+        pen += dvp * dvp;
+        pen += dvq * dvq;
+        vio = fmax(vio, fmax(fabs(dvp), fabs(dvq)));
+        s_wb[i] = 2.0 * rho * dvp;
+        s_wb[N + i] = 2.0 * rho * dvq;
+        if (cb) {
+            cb[m.c_balp + i] = cp;
+            cb[m.c_balq + i] = cq;
+        }
+    }
+    pen = wave_sum64(pen);
+    fobj = wave_sum64(fobj);
+    vio = wave_max64(vio);
+    if ((tid & 63) == 0) {
+        s_red[3 * (tid >> 6)] = pen;
+        s_red[3 * (tid >> 6) + 1] = fobj;
+        s_red[3 * (tid >> 6) + 2] = vio;
+    }
+    __syncthreads();  // also: every balance weight written, every arc value read
+    if (tid == 0) {
+        double P = 0.0, F = 0.0, V = 0.0;
+        for (int w = 0; w < kFuseThreads / 64; w++) {
+            P += s_red[3 * w];
+            F += s_red[3 * w + 1];
+            V = fmax(V, s_red[3 * w + 2]);
+        }
+        loss[b] = rho * P + obj_scale * F;
+        cvio[b] = V;
+    }
+    if (!gz) return;
+
+    // branches: d loss / d arc (with the balance rows) carried through
+    // p = F(v) to the branch's four voltage entries, per half-edge
+    for (int l = tid; l < L; l += kFuseThreads) {
+        const BranchFlows f = branch_flows(m, l, s_va, s_vm);
+        const double tpf = s_ap[l] + s_wb[f.fb], tpt = s_ap[L + l] + s_wb[f.tb];
+        const double tqf = s_ap[2 * L + l] + s_wb[N + f.fb], tqt = s_ap[3 * L + l] + s_wb[N + f.tb];
+        const double gt = tpf * f.pf.Ft + tqf * f.qf.Ft + tpt * f.pt.Ft + tqt * f.qt.Ft;
+        s_pq[l] = gt + s_wa[l];
+        s_pq[L + l] = -(gt + s_wa[l]);
+        s_pq[2 * L + l] = tpf * f.pf.Fu + tqf * f.qf.Fu + tpt * f.pt.Fu + tqt * f.qt.Fu;
+        s_pq[3 * L + l] = tpf * f.pf.Fw + tqf * f.qf.Fw + tpt * f.pt.Fw + tqt * f.qt.Fw;
+    }
+    __syncthreads();
+    double* gzb = gz + b * D;
+    for (int i = tid; i < N; i += kFuseThreads) {
+        double ga = 0.0, gm = 0.0;
+        for (int h = m.adj_ptr[i]; h < m.adj_ptr[i + 1]; h++) {
+            const int code = m.he[h];
+            const int a = (code >> 1) + ((code & 1) ? 0 : L);
+            ga += s_pq[a];
+            gm += s_pq[2 * L + a];
+        }
+        const double vm = s_vm[i];
+        gm += 2.0 * m.gs[i] * vm * s_wb[i] - 2.0 * m.bs[i] * vm * s_wb[N + i];
+        const double s = sigmoid((double)zb[i]);
+        gzb[i] = gm * (box.vmax[i] - box.vmin[i]) * s * (1.0 - s);
+        const double t = tanh((double)zb[N + i]);
+        gzb[N + i] = box.is_ref[i] ? 0.0 : ga * box.va_span * (1.0 - t * t);
+    }
+    for (int k = tid; k < G; k += kFuseThreads) {
+        const int bus = m.gen_bus[k];
+        const double gp = -s_wb[bus] + obj_scale * (2.0 * m.c2[k] * s_pg[k] + m.c1[k]);
+        const double gq = -s_wb[N + bus];
+        const double sp = sigmoid((double)zb[2 * N + k]), sq = sigmoid((double)zb[2 * N + G + k]);
+        gzb[2 * N + k] = gp * (box.pmax[k] - box.pmin[k]) * sp * (1.0 - sp);
+        gzb[2 * N + G + k] = gq * (box.qmax[k] - box.qmin[k]) * sq * (1.0 - sq);
+    }
+}
+
+// dz [B, D] = (float)(wb[b] * gz[b, j])
+__global__ void scale_rows_kernel(const double* __restrict__ gz, const double* __restrict__ wb, int B, int D,
+                                  float* __restrict__ dz) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)B * D) return;
+    dz[idx] = (float)(wb[idx / D] * gz[idx]);
+}
+
 }  // namespace
 
 hipError_t prox_vjp_sum(const double* X, const double* gX1, const double* gX2, const ProxObj& ob, double obj_scale,
@@ -903,6 +1169,25 @@ hipError_t prox_vjp_weights(const double* X, const double* W, const double* gpq,
     if (nfl > 0)
         hipLaunchKernelGGL(vjp_weights_kernel, dim3((unsigned)((nfl + 255) / 256)), dim3(256), 0, s, X, W, gpq, rows,
                            B, Wt);
+    return hipGetLastError();
+}
+
+
+size_t prox_loss_fused_lds(int N, int L, int G) {
+    return sizeof(double) * ((size_t)4 * N + 2 * (size_t)G + 9 * (size_t)L + 3 * (kFuseThreads / 64));
+}
+
+hipError_t prox_loss_fused(const DevModel& m, const ProxBox& box, const ProxRows& rows, const float* z,
+                           const double* loads, int B, double rho, double obj_scale, double* loss, double* cvio,
+                           double* gz, double* X, double* C, hipStream_t s) {
+    hipLaunchKernelGGL(loss_fused_kernel, dim3(B), dim3(kFuseThreads), prox_loss_fused_lds(m.N, m.L, m.G), s, m, box,
+                       rows, z, loads, rho, obj_scale, loss, cvio, gz, X, C);
+    return hipGetLastError();
+}
+
+hipError_t prox_scale_rows(const double* gz, const double* wb, int B, int D, float* dz, hipStream_t s) {
+    const int64_t tot = (int64_t)B * D;
+    hipLaunchKernelGGL(scale_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, gz, wb, B, D, dz);
     return hipGetLastError();
 }
 

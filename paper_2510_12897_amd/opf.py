@@ -161,6 +161,10 @@ def lib():
         "prox_vjp_sum": ([_vp, _vp, _vp, _vp, ctypes.c_double, _vp, ctypes.c_int, _vp, _vp], ctypes.c_int),
         "prox_loss_bwd": ([_vp, _vp, ctypes.c_int, ctypes.c_double, _vp, _vp, ctypes.c_double, _vp, _vp, _vp],
                           ctypes.c_int),
+        "prox_loss_fused": ([_vp, _vp, ctypes.c_int, ctypes.c_double, _vp, ctypes.c_double, ctypes.c_double, _vp,
+                             _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+        "prox_loss_fused_fits": ([_vp], ctypes.c_int),
+        "prox_scale_rows": ([_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)

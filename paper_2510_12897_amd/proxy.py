@@ -323,20 +323,41 @@ def _make_penalty_function():
 
 
 def _make_loss_function():
-    """z -> per-instance loss in one autograd node: squashing, arc flows
-    written into the same X, batch evaluation and penalty forward; J^T W and
-    the fused objective / squashing backward (prox_loss_bwd) backward.  The
-    same values as Squash followed by Penalty, without the copy of X and
-    the [B, n] gradient in between."""
+    """z -> per-instance loss in one autograd node.  On a model that
+    prox_loss_fused takes, one launch computes the loss, Cvio and d loss / d z
+    with each sample in one workgroup's LDS, and the backward scales that
+    gradient by the incoming one (prox_scale_rows).  Otherwise: squashing, arc
+    flows written into the same X, batch evaluation and penalty forward; J^T W
+    and the fused objective / squashing backward (prox_loss_bwd) backward.
+    Both give the values of Squash followed by Penalty (to rounding) without
+    the copy of X and the [B, n] gradient in between.  keep: also leave x and
+    c(x) of every sample in pen.last."""
     torch = _torch()
 
     class F(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, z, prox):
+        def forward(ctx, z, prox, loads, keep):
             pen, va_span = prox.pen, prox.squash.va_span
             z = z.contiguous()
             B, n, m = pen.B, pen.model.n, pen.model.m
             dev = z.device
+            vjp = bool(ctx.needs_input_grad[0])
+            loss = torch.empty(B, dtype=torch.float64, device=dev)
+            cvio = torch.empty(B, dtype=torch.float64, device=dev)
+            ctx.fused = pen.fused
+            if pen.fused:
+                loads = loads.to(torch.float64).contiguous()
+                gz = torch.empty(z.shape, dtype=torch.float64, device=dev) if vjp else None
+                X = torch.empty(B, n, dtype=torch.float64, device=dev) if keep else None
+                C = torch.empty(B, m, dtype=torch.float64, device=dev) if keep else None
+                _check(lib().prox_loss_fused(pen.model.handle, _p(z), B, float(va_span), _p(loads), float(pen.rho),
+                                             float(pen.obj_scale), _p(loss), _p(cvio), _p(gz), _p(X), _p(C),
+                                             _stream()))
+                pen.last = {"x": X, "f": None, "c": C, "cvio": cvio}
+                if vjp:
+                    ctx.save_for_backward(gz)
+                return loss
+            pen.set_loads(loads[:, :pen.N], loads[:, pen.N:])
             X = torch.empty(B, n, dtype=torch.float64, device=dev)
             # the arc variables are left for the flows, which write every one
             _check(lib().prox_squash_fwd_vars(pen.model.handle, _p(z), B, float(va_span), _p(X), _stream()))
@@ -345,14 +366,11 @@ def _make_loss_function():
             Fo = torch.empty(B, dtype=torch.float64, device=dev)
             C = torch.empty(B * m, dtype=torch.float64, device=dev)
             pen.batch.eval(Xflat, F=Fo, C=C)
-            loss = torch.empty(B, dtype=torch.float64, device=dev)
-            cvio = torch.empty(B, dtype=torch.float64, device=dev)
             W = torch.empty(B * m, dtype=torch.float64, device=dev)
-            vjp = int(bool(ctx.needs_input_grad[0]))
             # with a gradient to come, d pen / d (p, q) stays on chip when it fits
             gpq = None if vjp and 4 * pen.L <= 7680 else torch.empty(B * 4 * pen.L, dtype=torch.float64, device=dev)
             _check(lib().prox_penalty(pen.model.handle, _p(C), _p(Xflat), _p(Fo), float(pen.obj_scale),
-                                      float(pen.rho), B, vjp, _p(loss), _p(cvio), _p(W), _p(gpq), _stream()))
+                                      float(pen.rho), B, int(vjp), _p(loss), _p(cvio), _p(W), _p(gpq), _stream()))
             pen.last = {"x": X, "f": Fo, "c": C.view(B, m), "cvio": cvio}
             ctx.save_for_backward(z, Xflat, W)
             ctx.pen, ctx.va_span = pen, va_span
@@ -360,14 +378,20 @@ def _make_loss_function():
 
         @staticmethod
         def backward(ctx, gloss):
+            wb = gloss.detach().to(torch.float64).contiguous()
+            if ctx.fused:
+                (gz,) = ctx.saved_tensors
+                B, D = gz.shape
+                dz = torch.empty(B, D, dtype=torch.float32, device=gz.device)
+                _check(lib().prox_scale_rows(_p(gz), _p(wb), B, D, _p(dz), _stream()))
+                return dz, None, None, None
             z, Xflat, W = ctx.saved_tensors
             pen = ctx.pen
             gX1 = pen.batch.jtprod(Xflat, W)
-            wb = gloss.detach().to(torch.float64).contiguous()
             dz = torch.empty_like(z)
             _check(lib().prox_loss_bwd(pen.model.handle, _p(z), pen.B, float(ctx.va_span), _p(Xflat), _p(gX1),
                                        float(pen.obj_scale), _p(wb), _p(dz), _stream()))
-            return dz, None
+            return dz, None, None, None
 
     return F
 
@@ -407,6 +431,11 @@ class Penalty:
         pd = np.tile(np.asarray(case["pd"], np.float64), self.B)
         qd = np.tile(np.asarray(case["qd"], np.float64), self.B)
         self.batch = opf.Batch([self.model], np.zeros(self.B, np.int32), pd, qd)
+        fits = lib().prox_loss_fused_fits(self.model.handle)
+        _check(min(fits, 0))
+        # the loss node's one-launch form (prox_loss_fused) when the model
+        # has what it takes; else the chain of batch launches
+        self.fused = fits == 1
         self.last = None
 
     def set_loads(self, pd, qd):
@@ -462,10 +491,10 @@ class WarmStartProxy:
         feats = ((loads - self.base[None, :]) * self.inv_scale[None, :]).to(torch.float32)
         return loads, feats
 
-    def loss(self, loads, feats):
-        """Per-sample loss [B] of the network's prediction on these loads."""
-        self.pen.set_loads(loads[:, :self.N], loads[:, self.N:])
-        return _fun("loss").apply(self.mlp(feats), self)
+    def loss(self, loads, feats, keep=False):
+        """Per-sample loss [B] of the network's prediction on these loads
+        (keep: also leave x and c(x) in pen.last)."""
+        return _fun("loss").apply(self.mlp(feats), self, loads, keep)
 
     def loss_unfused(self, loads, feats):
         """loss through Squash and Penalty as two autograd nodes (the same
@@ -485,7 +514,7 @@ class WarmStartProxy:
         """(x with p, q := flows, largest violation per sample) under no grad."""
         torch = _torch()
         with torch.no_grad():
-            self.loss(loads, feats)
+            self.loss(loads, feats, keep=True)
         return self.pen.last["x"], self.pen.last["cvio"]
 
     def baseline(self, loads):

@@ -16,6 +16,10 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
+def say(msg):
+    print(msg, flush=True)
+
+
 @pytest.fixture(scope="module")
 def dev():
     if not torch.cuda.is_available():
@@ -531,26 +535,183 @@ def test_mlp_forward_backward_vs_oracle(dev, P):
 
 
 def test_fused_loss_node_matches_squash_then_penalty(dev, P):
-    """The training loss node (squash, flows, evaluation, penalty; backward
-    J^T W with prox_loss_bwd) gives the values and parameter gradients of
-    Squash followed by Penalty as two nodes."""
+    """The training loss node, in both forms (one fused launch; squash,
+    flows, evaluation, penalty with J^T W and prox_loss_bwd backward), gives
+    the values and parameter gradients of Squash followed by Penalty as two
+    nodes: the chain bit for bit on the loss, the fused launch to rounding
+    (its balance rows and sums run in another order); x bit for bit in both."""
     case = _case(N=14, L=20, G=6, seed=9)
     px = P.WarmStartProxy(case, B=64, width=32, depth=2, rho=3.0, obj_scale=2e-3, seed=4)
+    assert px.pen.fused
     gen = torch.Generator(device=dev)
     gen.manual_seed(3)
     loads, feats = px.sample(gen)
-    out = []
-    for fn in (px.loss, px.loss_unfused):
+    wb = torch.linspace(0.5, 1.5, 64, device=dev, dtype=torch.float64)
+
+    def run(fn):
         lb = fn(loads, feats)
         x = px.pen.last["x"].clone()
-        (lb * torch.linspace(0.5, 1.5, lb.numel(), device=dev, dtype=torch.float64)).sum().backward()
-        out.append((lb.detach(), x, px.mlp.flat.grad.clone()))
+        (lb * wb).sum().backward()
+        g = px.mlp.flat.grad.clone()
         px.mlp.flat.grad = None
-    assert torch.equal(out[0][0], out[1][0])
-    assert torch.equal(out[0][1], out[1][1])
-    g0, g1 = out[0][2], out[1][2]
-    assert float((g0 - g1).abs().max()) <= 1e-6 * float(g1.abs().max())
+        return lb.detach(), x, g
+
+    ref = run(px.loss_unfused)
+    for fused in (False, True):
+        px.pen.fused = fused
+        lb, x, g = run(lambda a, b: px.loss(a, b, keep=True))
+        say(f"[fused loss node] fused={fused}: max |loss diff| {float((lb - ref[0]).abs().max()):.3g}, "
+            f"max |grad diff| {float((g - ref[2]).abs().max()):.3g} of {float(ref[2].abs().max()):.3g}")
+        if fused:
+            assert torch.allclose(lb, ref[0], rtol=1e-12, atol=0)
+        else:
+            assert torch.equal(lb, ref[0])
+        assert torch.equal(x, ref[1])
+        assert float((g - ref[2]).abs().max()) <= 1e-6 * float(ref[2].abs().max())
     px.close()
+
+
+def _fused(P, pen, z, loads, va_span, grad=True, keep=True):
+    """prox_loss_fused through the C-ABI: (loss, cvio, gz, X, C) as numpy."""
+    from paper_2510_12897_amd.opf import _check, lib
+    B, D = z.shape
+    d = dict(dtype=torch.float64, device=z.device)
+    out = [torch.empty(B, **d), torch.empty(B, **d), torch.empty(B, D, **d) if grad else None,
+           torch.empty(B, pen.model.n, **d) if keep else None, torch.empty(B, pen.model.m, **d) if keep else None]
+    _check(lib().prox_loss_fused(pen.model.handle, P._p(z), B, va_span, P._p(loads), pen.rho, pen.obj_scale,
+                                 *[P._p(t) for t in out], P._stream()))
+    torch.cuda.synchronize()
+    return [None if t is None else t.cpu().numpy() for t in out]
+
+
+def test_fused_loss_kernel_vs_oracle(dev, P):
+    """prox_loss_fused against the oracle: x (squashing, then p, q := the
+    flows of the oracle's flow rows), c(x) row by row, the loss and Cvio of
+    the oracle's penalty, and d loss / d z against central differences of
+    the oracle's loss chained through the oracle's squashing derivative."""
+    case = _case()
+    N, L, G = case["n_bus"], case["n_branch"], case["n_gen"]
+    B, D, nf = 3, 2 * N + 2 * G, 2 * N + 2 * G
+    rho, osc, span = 6.0, 2e-3, 0.5
+    pen = P.Penalty(case, B, rho=rho, obj_scale=osc)
+    rng = np.random.default_rng(12)
+    z = rng.standard_normal((B, D)).astype(np.float32)
+    pd, qd = synth.perturbed_loads(case, B, 13)
+    loads = np.concatenate([pd, qd], axis=1)
+    loss, cvio, gz, X, C = _fused(P, pen, torch.as_tensor(z, device=dev), torch.as_tensor(loads, device=dev), span)
+    va, vm, pg, qg = MO.squash(z.astype(np.float64), _box(case), span)
+    np.testing.assert_allclose(X[:, :nf], np.concatenate([va, vm, pg, qg], axis=1), rtol=1e-13, atol=1e-15)
+    for b in range(B):
+        ref, rv, xr = _oracle_loss(case, pd[b], qd[b], X[b, :nf], rho, osc)
+        np.testing.assert_allclose(X[b], xr, rtol=1e-12, atol=1e-14)
+        c2 = dict(case)
+        c2["pd"], c2["qd"] = pd[b], qd[b]
+        cr = OR.evaluate(c2, xr, want=OR.W_CONS)["c"]
+        np.testing.assert_allclose(C[b], cr, rtol=1e-12, atol=1e-13)
+        assert loss[b] == pytest.approx(ref, rel=1e-12, abs=1e-14)
+        assert cvio[b] == pytest.approx(rv, rel=1e-12, abs=1e-14)
+    # the gradient: d loss / d (va, vm, pg, qg) by central differences of the
+    # oracle's loss, then (d x / d z)^T of the oracle's squashing
+    h = 1e-6
+    for b in range(2):
+        x0 = X[b, :nf].copy()
+        noise = 16 * np.finfo(float).eps * abs(_oracle_loss(case, pd[b], qd[b], x0, rho, osc)[0]) / h
+        gx = np.zeros(nf)
+        for e in range(nf):
+            xp, xm = x0.copy(), x0.copy()
+            xp[e] += h
+            xm[e] -= h
+            gx[e] = (_oracle_loss(case, pd[b], qd[b], xp, rho, osc)[0] -
+                     _oracle_loss(case, pd[b], qd[b], xm, rho, osc)[0]) / (2 * h)
+        ref = MO.squash_grad(z[b:b + 1].astype(np.float64), _box(case), span, gx[None, :N], gx[None, N:2 * N],
+                             gx[None, 2 * N:2 * N + G], gx[None, 2 * N + G:])[0]
+        err = np.abs(gz[b] - ref)
+        tol = 1e-6 * np.maximum(1.0, np.abs(ref)) + 4 * noise
+        say(f"[fused loss] sample {b}: max |gz - fd| {err.max():.3g} (noise {noise:.3g})")
+        assert np.all(err <= tol), (b, int(np.argmax(err - tol)))
+    pen.close()
+
+
+def test_fused_loss_at_benchmark_size_matches_the_launch_chain(dev, P):
+    """The benchmarked proxy's shape (300 buses, 410 branches, 60 generators,
+    4,096 samples): prox_loss_fused against the chain of batch launches on
+    the same z and loads.  x, the arc flows and the thermal and angle rows
+    bit for bit; balance rows, loss and Cvio to rounding; dz (FP32) to FP32
+    rounding; two fused runs give the same bits."""
+    case = synth.network(300, 410, 60, 41)
+    px = P.WarmStartProxy(case, B=4096, width=64, depth=1, rho=10.0, obj_scale=1e-3, seed=2)
+    assert px.pen.fused
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    loads, feats = px.sample(gen)
+    D = 2 * px.N + 2 * px.G
+    z = (torch.randn(4096, D, generator=gen, device=dev) * 1.5).requires_grad_(True)
+    wb = torch.rand(4096, generator=gen, device=dev, dtype=torch.float64) + 0.5
+    fun = P._fun("loss")
+    out = {}
+    for fused in (True, False, True):
+        px.pen.fused = fused
+        z.grad = None
+        lb = fun.apply(z, px, loads, True)
+        (lb * wb).sum().backward()
+        out.setdefault(fused, []).append((lb.detach().clone(), px.pen.last["x"].clone(), px.pen.last["c"].clone(),
+                                          px.pen.last["cvio"].clone(), z.grad.clone()))
+    (l1, x1, c1, v1, g1), (l1b, x1b, c1b, v1b, g1b) = out[True]
+    l0, x0, c0, v0, g0 = out[False][0]
+    for a, b in zip(out[True][0], out[True][1]):
+        assert torch.equal(a, b)
+    assert torch.equal(x1, x0)
+    m = px.pen.model
+    ex = torch.zeros(m.m, dtype=torch.bool, device=dev)
+    for blk in ("p_fr", "q_fr", "p_to", "q_to", "angle", "thermal_fr", "thermal_to", "ref"):
+        o, k = m.block(blk)
+        ex[o:o + k] = True
+    assert torch.equal(c1[:, ex], c0.view(4096, -1)[:, ex])
+    scale = float(c0.abs().max())
+    dc = float((c1 - c0.view(4096, -1)).abs().max())
+    dl = float(((l1 - l0).abs() / l0.abs()).max())
+    dg = float((g1 - g0).abs().max()) / float(g0.abs().max())
+    say(f"[fused loss 300-bus] max |dc| {dc:.3g} (scale {scale:.3g}), max rel loss diff {dl:.3g}, "
+        f"max dz diff / max |dz| {dg:.3g}")
+    assert dc <= 1e-13 * scale
+    assert dl <= 1e-12
+    assert torch.allclose(v1, v0, rtol=1e-12, atol=1e-15)
+    assert dg <= 1e-6
+    px.close()
+
+
+def test_fused_loss_model_conditions(dev, P):
+    """prox_loss_fused_fits and the refusals: multi-period and storage models
+    and a network whose sample does not fit 64 KiB of LDS are refused with
+    OPF_E_ARG; the proxy then takes the chain of launches."""
+    from paper_2510_12897_amd import opf
+    from paper_2510_12897_amd.opf import OPFError, _check, lib
+    small = _case()
+    pdt, qdt = synth.mp_loads(small, 2, 1)
+    mp = opf.Model(small, n_periods=2, pd_t=pdt, qd_t=qdt)
+    st = opf.Model(small, storage=synth.storage(small, 2, frac=0.3))
+    big = synth.network(1000, 1400, 100, 3)  # 4N + 2G + 9L = 16,800 doubles
+    bm = opf.Model(big)
+    ok = opf.Model(small)
+    try:
+        assert lib().prox_loss_fused_fits(ok.handle) == 1
+        assert lib().prox_loss_fused_fits(bm.handle) == 0
+        assert lib().prox_loss_fused_fits(st.handle) == 0
+        z = torch.zeros(2, 2 * big["n_bus"] + 2 * big["n_gen"], device=dev)
+        loads = torch.zeros(2, 2 * big["n_bus"], dtype=torch.float64, device=dev)
+        o = [torch.empty(2, dtype=torch.float64, device=dev) for _ in range(2)]
+        with pytest.raises(OPFError, match="LDS"):
+            _check(lib().prox_loss_fused(bm.handle, P._p(z), 2, 0.3, P._p(loads), 1.0, 0.0, P._p(o[0]), P._p(o[1]),
+                                         None, None, None, P._stream()))
+        with pytest.raises(OPFError, match="static model"):
+            _check(lib().prox_loss_fused(mp.handle, P._p(z), 2, 0.3, P._p(loads), 1.0, 0.0, P._p(o[0]), P._p(o[1]),
+                                         None, None, None, P._stream()))
+    finally:
+        for m in (mp, st, bm, ok):
+            m.close()
+    pen = P.Penalty(big, 2)
+    assert not pen.fused
+    pen.close()
 
 
 def test_trained_proxy_gains_over_flat_start(dev, P):
