@@ -510,7 +510,7 @@ int prox_loss_fused(opf_model model, const float *z, int B, double va_span, cons
                     double obj_scale, double *loss, double *cvio, double *gz, double *X, double *C, void *stream);
 
 /* 1 when prox_loss_fused takes this model: static, polar, no storage units
- * or devices, and one sample's working set (4N + 2G + 9L doubles) within
+ * or devices, and one sample's working set (4N + 2G + 4L doubles) within
  * 64 KiB of LDS; 0 when not; OPF_E_STATE for an invalid handle. */
 int prox_loss_fused_fits(opf_model model);
 

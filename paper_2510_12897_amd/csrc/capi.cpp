@@ -303,6 +303,13 @@ int opf_model_create(const opf_case* cs, const opf_opts* opts, int device, opf_m
         const size_t ob_lc = pk.reserve(sizeof(double) * ly.m()), ob_uc = pk.reserve(sizeof(double) * ly.m());
         const size_t ob_x0 = pk.reserve(sizeof(double) * ly.n);
         const size_t o_isref = pk.add(m->hm.is_ref);
+        std::vector<int32_t> he_pos(2 * (size_t)ly.L), gen_pos(ly.G);
+        for (size_t h = 0; h < m->hm.he.size(); h++) {
+            const int32_t code = m->hm.he[h];
+            he_pos[((code & 1) ? 0 : ly.L) + (code >> 1)] = (int32_t)h;
+        }
+        for (size_t q = 0; q < m->hm.gen_list.size(); q++) gen_pos[m->hm.gen_list[q]] = (int32_t)q;
+        const size_t o_hepos = pk.add(he_pos), o_genpos = pk.add(gen_pos);
         opf::fill_bounds(cs, opts, m->hm, reinterpret_cast<double*>(pk.at(ob_lv)),
                          reinterpret_cast<double*>(pk.at(ob_uv)), reinterpret_cast<double*>(pk.at(ob_lc)),
                          reinterpret_cast<double*>(pk.at(ob_uc)), reinterpret_cast<double*>(pk.at(ob_x0)));
@@ -336,6 +343,8 @@ int opf_model_create(const opf_case* cs, const opf_opts* opts, int device, opf_m
         m->ucon = reinterpret_cast<const double*>(base + ob_uc);
         m->x0 = reinterpret_cast<const double*>(base + ob_x0);
         m->is_ref = reinterpret_cast<const int32_t*>(base + o_isref);
+        m->he_pos = reinterpret_cast<const int32_t*>(base + o_hepos);
+        m->gen_pos = reinterpret_cast<const int32_t*>(base + o_genpos);
     } catch (const std::bad_alloc&) {
         delete m;
         return set_err(OPF_E_NOMEM, "host allocation failed");

@@ -92,6 +92,10 @@ struct opf_model_s {
     const int32_t *jrow = nullptr, *jcol = nullptr, *hrow = nullptr, *hcol = nullptr;
     const double *lvar = nullptr, *uvar = nullptr, *lcon = nullptr, *ucon = nullptr, *x0 = nullptr;
     const int32_t* is_ref = nullptr;
+    // inverse orders for the proxy's fused loss: he_pos [2L] = position of
+    // (side, branch) in the bus-ordered half-edge list he (from sides first),
+    // gen_pos [G] = position of generator k in the bus-ordered gen_list
+    const int32_t *he_pos = nullptr, *gen_pos = nullptr;
 };
 
 inline bool valid_model(const opf_model_s* m) { return m && m->magic == opf_internal::kModelMagic; }

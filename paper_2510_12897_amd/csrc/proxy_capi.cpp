@@ -252,7 +252,8 @@ int prox_loss_fused(opf_model model, const float* z, int B, double va_span, cons
                                   "%zu bytes of LDS",
                        kFusedLdsMax);
     DeviceGuard dg(model->device);
-    return launched(opf::prox_loss_fused(model->dm, box_of(model, va_span), rows_of(model), z, loads, B, rho,
+    const opf::ProxPerm pm{model->he_pos, model->gen_pos};
+    return launched(opf::prox_loss_fused(model->dm, box_of(model, va_span), rows_of(model), pm, z, loads, B, rho,
                                          obj_scale, loss, cvio, gz, X, C, static_cast<hipStream_t>(stream)),
                     "prox_loss_fused launch");
 }

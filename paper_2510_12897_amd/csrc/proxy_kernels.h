@@ -71,10 +71,14 @@ hipError_t prox_loss_bwd(const float* z, int B, const ProxBox& box, const ProxOb
 // LDS): loss, cvio [B]; gz [B, 2N+2G] = d loss_b / d z_b (NULL: not
 // computed); X [B, n], C [B, m] on request (NULL: not written).  loads [B, 2N]
 // holds each sample's pd then qd.
+struct ProxPerm {
+    const int32_t* he_pos;   // [2L] position of (side, branch) in the bus-ordered half-edge list, from sides first
+    const int32_t* gen_pos;  // [G] position of generator k in the bus-ordered generator list
+};
 size_t prox_loss_fused_lds(int N, int L, int G);
-hipError_t prox_loss_fused(const DevModel& m, const ProxBox& box, const ProxRows& rows, const float* z,
-                           const double* loads, int B, double rho, double obj_scale, double* loss, double* cvio,
-                           double* gz, double* X, double* C, hipStream_t s);
+hipError_t prox_loss_fused(const DevModel& m, const ProxBox& box, const ProxRows& rows, const ProxPerm& pm,
+                           const float* z, const double* loads, int B, double rho, double obj_scale, double* loss,
+                           double* cvio, double* gz, double* X, double* C, hipStream_t s);
 // dz [B, D] = (float)(wb[b] * gz[b, j])
 hipError_t prox_scale_rows(const double* gz, const double* wb, int B, int D, float* dz, hipStream_t s);
 

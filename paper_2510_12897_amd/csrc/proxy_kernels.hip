@@ -504,21 +504,28 @@ __global__ void to_bf16_kernel(const float* __restrict__ x, int64_t n, __bf16* _
 __device__ __forceinline__ double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
 
 // Entry e < 2N + 2G (va, vm, pg, qg blocks of x) of the squashed network
-// output zb (vm, va, pg, qg blocks, FP32): the squashing kernel and the fused
-// loss kernel both call it, so both write the same bits.
-__device__ __forceinline__ double squash_entry(const ProxBox& box, const float* zb, int e) {
+// output zb (vm, va, pg, qg blocks, FP32), and in act the activation it
+// came from (tanh for va, the sigmoid otherwise): the squashing kernel and
+// the fused loss kernel both call it, so both write the same bits.
+__device__ __forceinline__ double squash_entry(const ProxBox& box, const float* zb, int e, double& act) {
     const int N = box.N, G = box.G;
-    if (e < N) return box.is_ref[e] ? 0.0 : box.va_span * tanh((double)zb[N + e]);  // va
-    if (e < 2 * N) {                                                                 // vm
+    if (e < N) {  // va
+        act = tanh((double)zb[N + e]);
+        return box.is_ref[e] ? 0.0 : box.va_span * act;
+    }
+    if (e < 2 * N) {  // vm
         const int i = e - N;
-        return box.vmin[i] + (box.vmax[i] - box.vmin[i]) * sigmoid((double)zb[i]);
+        act = sigmoid((double)zb[i]);
+        return box.vmin[i] + (box.vmax[i] - box.vmin[i]) * act;
     }
     if (e < 2 * N + G) {
         const int k = e - 2 * N;
-        return box.pmin[k] + (box.pmax[k] - box.pmin[k]) * sigmoid((double)zb[2 * N + k]);
+        act = sigmoid((double)zb[2 * N + k]);
+        return box.pmin[k] + (box.pmax[k] - box.pmin[k]) * act;
     }
     const int k = e - 2 * N - G;
-    return box.qmin[k] + (box.qmax[k] - box.qmin[k]) * sigmoid((double)zb[2 * N + G + k]);
+    act = sigmoid((double)zb[2 * N + G + k]);
+    return box.qmin[k] + (box.qmax[k] - box.qmin[k]) * act;
 }
 
 // z [B, 2N + 2G] (vm, va, pg, qg blocks, FP32) -> the first 2N + 2G entries
@@ -531,7 +538,8 @@ __global__ void squash_fwd_kernel(const float* __restrict__ z, int B, ProxBox bo
     if (idx >= (int64_t)B * per) return;
     const int64_t b = idx / per;
     const int64_t e = idx % per;
-    X[b * n + e] = e < D ? squash_entry(box, z + b * D, (int)e) : 0.0;
+    double act;
+    X[b * n + e] = e < D ? squash_entry(box, z + b * D, (int)e, act) : 0.0;
 }
 
 // dz from dL/dx = gX + gX2 + obj_scale * gObj on the (va, vm, pg, qg)
@@ -790,13 +798,16 @@ __device__ __forceinline__ double wave_max64(double v) {
     return v;
 }
 
-// The four flows of branch l at the voltages in LDS: p_f, q_f, p_t, q_t.
+// The four flows of branch l at the voltages in LDS: p_f, q_f, p_t, q_t,
+// with cos and sin of the angle difference in C, S (computed here when
+// TRIG, else taken as given).
 struct BranchFlows {
     PFlow pf, qf, pt, qt;
     int fb, tb;
 };
-__device__ __forceinline__ BranchFlows branch_flows(const DevModel& m, int l, const double* s_va,
-                                                    const double* s_vm) {
+template <bool TRIG>
+__device__ __forceinline__ BranchFlows branch_flows(const DevModel& m, int l, const double* s_va, const double* s_vm,
+                                                    double& C, double& S) {
     const int L = m.L;
     BranchFlows r;
     r.fb = m.f_bus[l];
@@ -805,8 +816,7 @@ __device__ __forceinline__ BranchFlows branch_flows(const DevModel& m, int l, co
     const double Gff = k[0], Bff = k[L], Gft = k[2 * L], Bft = k[3 * L];
     const double Gtt = k[4 * L], Btt = k[5 * L], Gtf = k[6 * L], Btf = k[7 * L];
     const double u = s_vm[r.fb], w = s_vm[r.tb];
-    double S, C;
-    sincos(s_va[r.fb] - s_va[r.tb], &S, &C);
+    if (TRIG) sincos(s_va[r.fb] - s_va[r.tb], &S, &C);
     r.pf = pflow(Gff, 0.0, Gft, Bft, u, w, C, S);
     r.qf = pflow(-Bff, 0.0, -Bft, Gft, u, w, C, S);
     r.pt = pflow(0.0, Gtt, Gtf, -Btf, u, w, C, S);
@@ -814,13 +824,61 @@ __device__ __forceinline__ BranchFlows branch_flows(const DevModel& m, int l, co
     return r;
 }
 
-// LDS (doubles): va, vm [N each], pg, qg [G each] (x's order), the arc
-// values [4L] (p_f, p_t, q_f, q_t: x's order; later the half-edge gradient
-// terms d/dva_f, d/dva_t, d/dvm_f, d/dvm_t), d loss / d arc without the
-// balance rows [4L], the angle-row weights [L], the balance-row weights
-// [2N], three partials per wave.
+// What one branch reads of the model and contributes to the penalty: its
+// flows at the voltages in LDS, the thermal, angle and arc-bound
+// violations, and d loss / d arc without the balance rows.  The forward and
+// the gradient pass both call it (the gradient pass recomputes rather than
+// keeping 5 values per branch in LDS).
+struct BranchPen {
+    BranchFlows f;
+    double arc[4];  // p_f, p_t, q_f, q_t (x's order)
+    double cf, ct, ca, dvf, dvt, dva, dq[4];
+    int hf, ht;     // positions of the from / to half-edge in the bus-ordered list
+};
+template <bool TRIG>
+__device__ __forceinline__ BranchPen branch_pen(const DevModel& m, const ProxRows& rows, const ProxPerm& pm, int l,
+                                                const double* s_va, const double* s_vm, double& C, double& S) {
+#pragma clang fp contract(off)
+    const int L = m.L;
+    BranchPen r;
+    r.hf = pm.he_pos[l];
+    r.ht = pm.he_pos[L + l];
+    const double rate2 = m.rate2[l];
+    const double lf = rows.lcon[m.c_thf + l], uf = rows.ucon[m.c_thf + l];
+    const double lt = rows.lcon[m.c_tht + l], ut = rows.ucon[m.c_tht + l];
+    const double la = rows.lcon[m.c_ang + l], ua = rows.ucon[m.c_ang + l];
+    double lo[4], hi[4];
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        lo[a] = rows.lvar[rows.pq0 + a * L + l];
+        hi[a] = rows.uvar[rows.pq0 + a * L + l];
+    }
+    r.f = branch_flows<TRIG>(m, l, s_va, s_vm, C, S);
+    r.arc[0] = r.f.pf.F;
+    r.arc[1] = r.f.pt.F;
+    r.arc[2] = r.f.qf.F;
+    r.arc[3] = r.f.qt.F;
+    r.cf = r.arc[0] * r.arc[0] + r.arc[2] * r.arc[2] - rate2;
+    r.ct = r.arc[1] * r.arc[1] + r.arc[3] * r.arc[3] - rate2;
+    r.ca = s_va[r.f.fb] - s_va[r.f.tb];
+    r.dvf = viol(r.cf, lf, uf);
+    r.dvt = viol(r.ct, lt, ut);
+    r.dva = viol(r.ca, la, ua);
+#pragma unroll
+    for (int a = 0; a < 4; a++) r.dq[a] = viol(r.arc[a], lo[a], hi[a]);
+    return r;
+}
+
+// LDS (doubles): va, vm [N each]; pg, qg [G each] in the bus-ordered
+// generator list's order; p and q of each half-edge [2L each] in the
+// bus-ordered half-edge list's order (later the half-edge gradient terms
+// d/dva and d/dvm), so that a bus sums one contiguous range; the
+// balance-row weights [2N]; the squashing activations [2N + 2G] (z's order)
+// and cos, sin of each branch's angle difference [2L], which the gradient
+// pass reuses; three partials per wave.  Sums run in the adjacency and
+// generator-list orders.
 __global__ void __launch_bounds__(kFuseThreads) loss_fused_kernel(DevModel m, ProxBox box, ProxRows rows,
-                                                                  const float* __restrict__ z,
+                                                                  ProxPerm pm, const float* __restrict__ z,
                                                                   const double* __restrict__ loads, double rho,
                                                                   double obj_scale, double* __restrict__ loss,
                                                                   double* __restrict__ cvio, double* __restrict__ gz,
@@ -832,11 +890,12 @@ __global__ void __launch_bounds__(kFuseThreads) loss_fused_kernel(DevModel m, Pr
     double* s_vm = s_va + N;
     double* s_pg = s_vm + N;
     double* s_qg = s_pg + G;
-    double* s_pq = s_qg + G;
-    double* s_ap = s_pq + 4 * L;
-    double* s_wa = s_ap + 4 * L;
-    double* s_wb = s_wa + L;
-    double* s_red = s_wb + 2 * N;
+    double* s_hp = s_qg + G;
+    double* s_hq = s_hp + 2 * L;
+    double* s_wb = s_hq + 2 * L;
+    double* s_act = s_wb + 2 * N;
+    double* s_cs = s_act + D;
+    double* s_red = s_cs + 2 * L;
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
     const float* zb = z + b * D;
@@ -846,52 +905,49 @@ __global__ void __launch_bounds__(kFuseThreads) loss_fused_kernel(DevModel m, Pr
     double pen = 0.0, fobj = 0.0, vio = 0.0;
 
     for (int e = tid; e < D; e += kFuseThreads) {
-        const double v = squash_entry(box, zb, e);
-        lds[e] = v;
+        const int pos = e < 2 * N ? e : (e < 2 * N + G ? 2 * N + pm.gen_pos[e - 2 * N]
+                                                       : 2 * N + G + pm.gen_pos[e - 2 * N - G]);
+        double act;
+        const double v = squash_entry(box, zb, e, act);
+        lds[pos] = v;
+        s_act[e < N ? N + e : (e < 2 * N ? e - N : e)] = act;
         if (xb) xb[e] = v;
     }
     __syncthreads();
 
     // branches: arc flows, angle and thermal rows, arc bounds
     for (int l = tid; l < L; l += kFuseThreads) {
-        const BranchFlows f = branch_flows(m, l, s_va, s_vm);
-        const double arc[4] = {f.pf.F, f.pt.F, f.qf.F, f.qt.F};
-        const double rate2 = m.rate2[l];
-        const double cf = arc[0] * arc[0] + arc[2] * arc[2] - rate2;
-        const double ct = arc[1] * arc[1] + arc[3] * arc[3] - rate2;
-        const double ca = s_va[f.fb] - s_va[f.tb];
-        const double dvf = viol(cf, rows.lcon[m.c_thf + l], rows.ucon[m.c_thf + l]);
-        const double dvt = viol(ct, rows.lcon[m.c_tht + l], rows.ucon[m.c_tht + l]);
-        const double dva = viol(ca, rows.lcon[m.c_ang + l], rows.ucon[m.c_ang + l]);
-        pen += dvf * dvf;
-        pen += dvt * dvt;
-        pen += dva * dva;
-        vio = fmax(vio, fmax(fabs(dvf), fmax(fabs(dvt), fabs(dva))));
-        s_wa[l] = 2.0 * rho * dva;
-        const double wth[2] = {2.0 * rho * dvf, 2.0 * rho * dvt};
+        double Cc, Sc;
+        const BranchPen r = branch_pen<true>(m, rows, pm, l, s_va, s_vm, Cc, Sc);
+        s_cs[l] = Cc;
+        s_cs[L + l] = Sc;
+        pen += r.dvf * r.dvf;
+        pen += r.dvt * r.dvt;
+        pen += r.dva * r.dva;
+        vio = fmax(vio, fmax(fabs(r.dvf), fmax(fabs(r.dvt), fabs(r.dva))));
 #pragma unroll
         for (int a = 0; a < 4; a++) {
-            const int e = rows.pq0 + a * L + l;
-            const double dq = viol(arc[a], rows.lvar[e], rows.uvar[e]);
-            pen += dq * dq;
-            vio = fmax(vio, fabs(dq));
-            s_pq[a * L + l] = arc[a];
-            s_ap[a * L + l] = 2.0 * arc[a] * wth[a & 1] + 2.0 * rho * dq;
-            if (xb) xb[e] = arc[a];
+            pen += r.dq[a] * r.dq[a];
+            vio = fmax(vio, fabs(r.dq[a]));
+            if (xb) xb[rows.pq0 + a * L + l] = r.arc[a];
         }
+        s_hp[r.hf] = r.arc[0];
+        s_hp[r.ht] = r.arc[1];
+        s_hq[r.hf] = r.arc[2];
+        s_hq[r.ht] = r.arc[3];
         if (cb) {  // flow rows: p - F(v) with p := F(v), exactly 0
             cb[m.c_pfr + l] = 0.0;
             cb[m.c_qfr + l] = 0.0;
             cb[m.c_pto + l] = 0.0;
             cb[m.c_qto + l] = 0.0;
-            cb[m.c_ang + l] = ca;
-            cb[m.c_thf + l] = cf;
-            cb[m.c_tht + l] = ct;
+            cb[m.c_ang + l] = r.ca;
+            cb[m.c_thf + l] = r.cf;
+            cb[m.c_tht + l] = r.ct;
         }
     }
     // objective terms and reference rows
     for (int k = tid; k < G; k += kFuseThreads) {
-        const double pg = s_pg[k];
+        const double pg = s_pg[pm.gen_pos[k]];
         fobj += m.c2[k] * pg * pg + m.c1[k] * pg + m.c0[k];
     }
     for (int q = tid; q < m.R; q += kFuseThreads) {
@@ -903,24 +959,24 @@ __global__ void __launch_bounds__(kFuseThreads) loss_fused_kernel(DevModel m, Pr
     }
     __syncthreads();
 
-    // buses: balance rows over the half-edges in adjacency order
+    // buses: balance rows, summed over contiguous half-edge and generator ranges
     for (int i = tid; i < N; i += kFuseThreads) {
+        const int h0 = m.adj_ptr[i], h1 = m.adj_ptr[i + 1], g0 = m.gen_ptr[i], g1 = m.gen_ptr[i + 1];
+        const double gs = m.gs[i], bs = m.bs[i], pd = pdb[i], qd = pdb[N + i];
+        const double lp = rows.lcon[m.c_balp + i], up = rows.ucon[m.c_balp + i];
+        const double lq = rows.lcon[m.c_balq + i], uq = rows.ucon[m.c_balq + i];
         const double vm = s_vm[i], v2 = vm * vm;
         double sp = 0.0, sq = 0.0;
-        for (int h = m.adj_ptr[i]; h < m.adj_ptr[i + 1]; h++) {
-            const int code = m.he[h];
-            const int a = (code >> 1) + ((code & 1) ? 0 : L);  // the arc at bus i: from or to side
-            sp += s_pq[a];
-            sq += s_pq[2 * L + a];
+        for (int h = h0; h < h1; h++) {
+            sp += s_hp[h];
+            sq += s_hq[h];
         }
-        double cp = pdb[i] + m.gs[i] * v2 + sp, cq = pdb[N + i] - m.bs[i] * v2 + sq;
-        for (int q = m.gen_ptr[i]; q < m.gen_ptr[i + 1]; q++) {
-            const int k = m.gen_list[q];
-            cp -= s_pg[k];
-            cq -= s_qg[k];
+        double cp = pd + gs * v2 + sp, cq = qd - bs * v2 + sq;
+        for (int q = g0; q < g1; q++) {
+            cp -= s_pg[q];
+            cq -= s_qg[q];
         }
-        const double dvp = viol(cp, rows.lcon[m.c_balp + i], rows.ucon[m.c_balp + i]);
-        const double dvq = viol(cq, rows.lcon[m.c_balq + i], rows.ucon[m.c_balq + i]);
+        const double dvp = viol(cp, lp, up), dvq = viol(cq, lq, uq);
         pen += dvp * dvp;
         pen += dvq * dvq;
         vio = fmax(vio, fmax(fabs(dvp), fabs(dvq)));
@@ -939,7 +995,7 @@ __global__ void __launch_bounds__(kFuseThreads) loss_fused_kernel(DevModel m, Pr
         s_red[3 * (tid >> 6) + 1] = fobj;
         s_red[3 * (tid >> 6) + 2] = vio;
     }
-    __syncthreads();  // also: every balance weight written, every arc value read
+    __syncthreads();  // also: every balance weight written, every half-edge value read
     if (tid == 0) {
         double P = 0.0, F = 0.0, V = 0.0;
         for (int w = 0; w < kFuseThreads / 64; w++) {
@@ -955,37 +1011,46 @@ __global__ void __launch_bounds__(kFuseThreads) loss_fused_kernel(DevModel m, Pr
     // branches: d loss / d arc (with the balance rows) carried through
     // p = F(v) to the branch's four voltage entries, per half-edge
     for (int l = tid; l < L; l += kFuseThreads) {
-        const BranchFlows f = branch_flows(m, l, s_va, s_vm);
-        const double tpf = s_ap[l] + s_wb[f.fb], tpt = s_ap[L + l] + s_wb[f.tb];
-        const double tqf = s_ap[2 * L + l] + s_wb[N + f.fb], tqt = s_ap[3 * L + l] + s_wb[N + f.tb];
+        double Cc = s_cs[l], Sc = s_cs[L + l];
+        const BranchPen r = branch_pen<false>(m, rows, pm, l, s_va, s_vm, Cc, Sc);
+        const BranchFlows& f = r.f;
+        const double wth[2] = {2.0 * rho * r.dvf, 2.0 * rho * r.dvt};
+        double ap[4];
+#pragma unroll
+        for (int a = 0; a < 4; a++) ap[a] = 2.0 * r.arc[a] * wth[a & 1] + 2.0 * rho * r.dq[a];
+        const double wa = 2.0 * rho * r.dva;
+        const double tpf = ap[0] + s_wb[f.fb], tpt = ap[1] + s_wb[f.tb];
+        const double tqf = ap[2] + s_wb[N + f.fb], tqt = ap[3] + s_wb[N + f.tb];
         const double gt = tpf * f.pf.Ft + tqf * f.qf.Ft + tpt * f.pt.Ft + tqt * f.qt.Ft;
-        s_pq[l] = gt + s_wa[l];
-        s_pq[L + l] = -(gt + s_wa[l]);
-        s_pq[2 * L + l] = tpf * f.pf.Fu + tqf * f.qf.Fu + tpt * f.pt.Fu + tqt * f.qt.Fu;
-        s_pq[3 * L + l] = tpf * f.pf.Fw + tqf * f.qf.Fw + tpt * f.pt.Fw + tqt * f.qt.Fw;
+        s_hp[r.hf] = gt + wa;
+        s_hp[r.ht] = -(gt + wa);
+        s_hq[r.hf] = tpf * f.pf.Fu + tqf * f.qf.Fu + tpt * f.pt.Fu + tqt * f.qt.Fu;
+        s_hq[r.ht] = tpf * f.pf.Fw + tqf * f.qf.Fw + tpt * f.pt.Fw + tqt * f.qt.Fw;
     }
     __syncthreads();
     double* gzb = gz + b * D;
     for (int i = tid; i < N; i += kFuseThreads) {
+        const int h0 = m.adj_ptr[i], h1 = m.adj_ptr[i + 1];
+        const double gs = m.gs[i], bs = m.bs[i];
+        const double span_v = box.vmax[i] - box.vmin[i];
+        const int ref = box.is_ref[i];
         double ga = 0.0, gm = 0.0;
-        for (int h = m.adj_ptr[i]; h < m.adj_ptr[i + 1]; h++) {
-            const int code = m.he[h];
-            const int a = (code >> 1) + ((code & 1) ? 0 : L);
-            ga += s_pq[a];
-            gm += s_pq[2 * L + a];
+        for (int h = h0; h < h1; h++) {
+            ga += s_hp[h];
+            gm += s_hq[h];
         }
         const double vm = s_vm[i];
-        gm += 2.0 * m.gs[i] * vm * s_wb[i] - 2.0 * m.bs[i] * vm * s_wb[N + i];
-        const double s = sigmoid((double)zb[i]);
-        gzb[i] = gm * (box.vmax[i] - box.vmin[i]) * s * (1.0 - s);
-        const double t = tanh((double)zb[N + i]);
-        gzb[N + i] = box.is_ref[i] ? 0.0 : ga * box.va_span * (1.0 - t * t);
+        gm += 2.0 * gs * vm * s_wb[i] - 2.0 * bs * vm * s_wb[N + i];
+        const double s = s_act[i];
+        gzb[i] = gm * span_v * s * (1.0 - s);
+        const double t = s_act[N + i];
+        gzb[N + i] = ref ? 0.0 : ga * box.va_span * (1.0 - t * t);
     }
     for (int k = tid; k < G; k += kFuseThreads) {
-        const int bus = m.gen_bus[k];
-        const double gp = -s_wb[bus] + obj_scale * (2.0 * m.c2[k] * s_pg[k] + m.c1[k]);
+        const int bus = m.gen_bus[k], q = pm.gen_pos[k];
+        const double gp = -s_wb[bus] + obj_scale * (2.0 * m.c2[k] * s_pg[q] + m.c1[k]);
         const double gq = -s_wb[N + bus];
-        const double sp = sigmoid((double)zb[2 * N + k]), sq = sigmoid((double)zb[2 * N + G + k]);
+        const double sp = s_act[2 * N + k], sq = s_act[2 * N + G + k];
         gzb[2 * N + k] = gp * (box.pmax[k] - box.pmin[k]) * sp * (1.0 - sp);
         gzb[2 * N + G + k] = gq * (box.qmax[k] - box.qmin[k]) * sq * (1.0 - sq);
     }
@@ -1174,14 +1239,14 @@ hipError_t prox_vjp_weights(const double* X, const double* W, const double* gpq,
 
 
 size_t prox_loss_fused_lds(int N, int L, int G) {
-    return sizeof(double) * ((size_t)4 * N + 2 * (size_t)G + 9 * (size_t)L + 3 * (kFuseThreads / 64));
+    return sizeof(double) * ((size_t)6 * N + 4 * (size_t)G + 6 * (size_t)L + 3 * (kFuseThreads / 64));
 }
 
-hipError_t prox_loss_fused(const DevModel& m, const ProxBox& box, const ProxRows& rows, const float* z,
-                           const double* loads, int B, double rho, double obj_scale, double* loss, double* cvio,
-                           double* gz, double* X, double* C, hipStream_t s) {
+hipError_t prox_loss_fused(const DevModel& m, const ProxBox& box, const ProxRows& rows, const ProxPerm& pm,
+                           const float* z, const double* loads, int B, double rho, double obj_scale, double* loss,
+                           double* cvio, double* gz, double* X, double* C, hipStream_t s) {
     hipLaunchKernelGGL(loss_fused_kernel, dim3(B), dim3(kFuseThreads), prox_loss_fused_lds(m.N, m.L, m.G), s, m, box,
-                       rows, z, loads, rho, obj_scale, loss, cvio, gz, X, C);
+                       rows, pm, z, loads, rho, obj_scale, loss, cvio, gz, X, C);
     return hipGetLastError();
 }
 

@@ -690,7 +690,7 @@ def test_fused_loss_model_conditions(dev, P):
     pdt, qdt = synth.mp_loads(small, 2, 1)
     mp = opf.Model(small, n_periods=2, pd_t=pdt, qd_t=qdt)
     st = opf.Model(small, storage=synth.storage(small, 2, frac=0.3))
-    big = synth.network(1000, 1400, 100, 3)  # 4N + 2G + 9L = 16,800 doubles
+    big = synth.network(1000, 1400, 100, 3)  # 4N + 2G + 4L = 9,800 doubles
     bm = opf.Model(big)
     ok = opf.Model(small)
     try:
