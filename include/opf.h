@@ -407,6 +407,25 @@ int prox_gemm_bf16_mixed(int variant, const void *A, int a_bf16, int lda, const 
 /* y[i] = x[i] rounded to BF16 (nearest even), n values. */
 int prox_to_bf16(const float *x, int64_t n, void *y, void *stream);
 
+/* The proxy MLP's backward through a hidden layer in one product: out [M, N]
+ * (BF16, leading dimension ldo) = (A B) * gelu'(pre) elementwise, for
+ * row-major A [M, K] and B [K, N] (each FP32 or BF16 as a_bf16, b_bf16, as
+ * prox_gemm_bf16_mixed's variant 1) and pre [M, N] (FP32, the layer's
+ * pre-activation; gelu' of the exact GELU); part [ceil(M / 128), N] (FP32)
+ * receives the column sums of each 128-row block of the FP32 product before
+ * its rounding to BF16, in prox_colsum's first-pass order, so that
+ * prox_colsum_parts gives the bias gradient.  The values equal the product,
+ * prox_gelu_bwd and prox_colsum's first pass in sequence bit for bit.
+ * Dimensions and leading dimensions are multiples of 4 (a BF16 A: K and lda
+ * multiples of 8); A, B, pre 16-byte aligned, out 8-byte aligned.  Buffers
+ * are device memory the caller owns; OPF_E_ARG for a violated rule. */
+int prox_gemm_gelu_bwd(const void *A, int a_bf16, int lda, const void *B, int b_bf16, int ldb, const float *pre,
+                       int ldp, void *out, int ldo, int M, int N, int K, float *part, void *stream);
+
+/* out [N] = scale * column sums of part [chunks, N]: prox_colsum's second
+ * pass over partial sums that prox_gemm_gelu_bwd left. */
+int prox_colsum_parts(const float *part, int chunks, int N, float *out, float scale, void *stream);
+
 /* A split count for prox_gemm_bf16_splitk: the smallest power of two (at
  * most 16) that gives 256 or more 128 x 128 workgroups while each part keeps
  * at least four k tiles.  Negative sizes: OPF_E_ARG. */

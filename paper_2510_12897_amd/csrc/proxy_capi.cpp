@@ -121,6 +121,29 @@ int prox_gemm_bf16_mixed(int variant, const void* A, int a_bf16, int lda, const 
                         accumulate, splits, work, stream, "prox_gemm_bf16_mixed launch");
 }
 
+int prox_gemm_gelu_bwd(const void* A, int a_bf16, int lda, const void* B, int b_bf16, int ldb, const float* pre,
+                       int ldp, void* out, int ldo, int M, int N, int K, float* part, void* stream) {
+    if (!A || !B || !pre || !out || !part) return set_err(OPF_E_ARG, "A, B, pre, out and part must be non-NULL");
+    if (M < 0 || N < 0 || K < 0) return set_err(OPF_E_ARG, "negative dimension");
+    if (!mult4(M) || !mult4(N) || !mult4(K) || !mult4(lda) || !mult4(ldb) || !mult4(ldp) || !mult4(ldo))
+        return set_err(OPF_E_ARG, "dimensions and leading dimensions must be multiples of 4");
+    if (!aligned16(A) || !aligned16(B) || !aligned16(pre) || (reinterpret_cast<uintptr_t>(out) & 7u))
+        return set_err(OPF_E_ARG, "A, B and pre must be 16-byte aligned, out 8-byte aligned");
+    if (lda < K || ldb < N || ldp < N || ldo < N) return set_err(OPF_E_ARG, "a leading dimension is smaller than its row");
+    if (a_bf16 && (K % 8 || lda % 8))
+        return set_err(OPF_E_ARG, "a BF16 A needs K and its leading dimension multiples of 8");
+    if (M == 0 || N == 0) return OPF_OK;
+    return launched(opf::prox_gemm_gelu_bwd(A, a_bf16 != 0, lda, B, b_bf16 != 0, ldb, pre, ldp, out, ldo, M, N, K,
+                                            part, static_cast<hipStream_t>(stream)),
+                    "prox_gemm_gelu_bwd launch");
+}
+
+int prox_colsum_parts(const float* part, int chunks, int N, float* out, float scale, void* stream) {
+    if (chunks < 1 || N < 1 || !part || !out) return set_err(OPF_E_ARG, "bad arguments");
+    return launched(opf::prox_colsum_parts(part, chunks, N, out, scale, static_cast<hipStream_t>(stream)),
+                    "prox_colsum_parts launch");
+}
+
 int prox_to_bf16(const float* x, int64_t n, void* y, void* stream) {
     if (n < 0 || (n > 0 && (!x || !y))) return set_err(OPF_E_ARG, "bad arguments");
     if (n == 0) return OPF_OK;

@@ -41,6 +41,14 @@ hipError_t prox_gemm_mixed(int variant, const void* A, bool a_bf16, int lda, con
                            float* C, int ldc, int M, int N, int K, const float* bias, void* act, bool act_bf16,
                            int accumulate, int splits, float* work, hipStream_t s);
 int prox_gemm_splits(int M, int N, int K);
+// out [M, N] (BF16) = (A B) * gelu'(pre) for row-major A [M, K], B [K, N]
+// (either BF16), pre [M, N]; part [ceil(M / 128), N] = the column sums of
+// each 128-row block of the FP32 product (prox_colsum's first pass).
+hipError_t prox_gemm_gelu_bwd(const void* A, bool a_bf16, int lda, const void* B, bool b_bf16, int ldb,
+                              const float* pre, int ldp, void* out, int ldo, int M, int N, int K, float* part,
+                              hipStream_t s);
+// out [N] = scale * the column sums of part [chunks, N] (prox_colsum's second pass)
+hipError_t prox_colsum_parts(const float* part, int chunks, int N, float* out, float scale, hipStream_t s);
 hipError_t prox_gelu_bwd(const float* pre, const float* dact, float* dpre, int64_t n, hipStream_t s);
 hipError_t prox_colsum(const float* X, int M, int N, float* part, float* out, float scale, hipStream_t s);
 hipError_t prox_adam(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2, float eps,

@@ -244,30 +244,34 @@ __device__ __forceinline__ void mma_tile(const __bf16* As, const __bf16* Bs, int
 // in flight during the matrix-core work on the current one.
 // TA, TB: the operands' storage (float, rounded when staged, or __bf16);
 // TACT: the storage of the GELU output.
-template <bool A_KCONT, bool B_KCONT, int BN, typename TA, typename TB, typename TACT>
-__global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const TA* __restrict__ A, int lda,
-                                                            const TB* __restrict__ B, int ldb, float* __restrict__ C,
-                                                            int ldc, int M, int N, int K, int kchunk,
-                                                            const float* __restrict__ bias, TACT* __restrict__ act,
-                                                            int accumulate, float* __restrict__ work) {
+// The operand tiles in LDS, and after the k loop the epilogue's staging tile.
+template <int BN>
+constexpr int gemm_smem_bytes() {
+    return (2 * BM * BK + 2 * BN * BK) * (int)sizeof(__bf16);
+}
+
+// The k loop of one output tile: the XCD-aware tile of this workgroup
+// (i0, j0, k part kz) and its accumulators.  Workgroups are dealt to the
+// XCDs round-robin; they are renumbered so that each XCD takes one
+// contiguous range of tiles (n fastest, then m, then the k part): its rows of
+// A and the shared B stay in its own L2.
+template <bool A_KCONT, bool B_KCONT, int BN, typename TA, typename TB>
+__device__ __forceinline__ void gemm_mainloop(const TA* __restrict__ A, int lda, const TB* __restrict__ B, int ldb,
+                                              int M, int N, int K, int kchunk, char* smem, int& i0, int& j0, int& kz,
+                                              f32x16 (&acc)[2][BN / 64]) {
     constexpr int NB = BN / 64;  // 32-column MFMA tiles per wave
-    // the operand tiles, and after the k loop the epilogue's staging tile
-    __shared__ __align__(16) char smem[(2 * BM * BK + 2 * BN * BK) * sizeof(__bf16)];
     __bf16 (*As)[BM * BK] = reinterpret_cast<__bf16 (*)[BM * BK]>(smem);
     __bf16 (*Bs)[BN * BK] = reinterpret_cast<__bf16 (*)[BN * BK]>(smem + 2 * BM * BK * sizeof(__bf16));
-    // Workgroups are dealt to the XCDs round-robin; renumber them so that
-    // each XCD takes one contiguous range of tiles (n fastest, then m, then
-    // the k part): its rows of A and the shared B stay in its own L2.
     const int nx = gridDim.x, ny = gridDim.y, nb = nx * ny * gridDim.z;
     const int bl = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
     const int q = nb / kXcd, rem = nb % kXcd, xcd = bl % kXcd;
     const int tile = xcd * q + min(xcd, rem) + bl / kXcd;
-    const int i0 = (tile / nx) % ny * BM, j0 = tile % nx * BN;
-    const int kz = tile / (nx * ny);
+    i0 = (tile / nx) % ny * BM;
+    j0 = tile % nx * BN;
+    kz = tile / (nx * ny);
     const int kb = kz * kchunk, ke = min(K, kb + kchunk);
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const int wi = (wave / 2) * 64, wj = (wave % 2) * (BN / 2);
-    f32x16 acc[2][NB];
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
@@ -299,6 +303,21 @@ __global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const TA* __restrict
         __syncthreads();
         cur ^= 1;
     }
+}
+
+template <bool A_KCONT, bool B_KCONT, int BN, typename TA, typename TB, typename TACT>
+__global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const TA* __restrict__ A, int lda,
+                                                            const TB* __restrict__ B, int ldb, float* __restrict__ C,
+                                                            int ldc, int M, int N, int K, int kchunk,
+                                                            const float* __restrict__ bias, TACT* __restrict__ act,
+                                                            int accumulate, float* __restrict__ work) {
+    constexpr int NB = BN / 64;  // 32-column MFMA tiles per wave
+    __shared__ __align__(16) char smem[gemm_smem_bytes<BN>()];
+    int i0, j0, kz;
+    f32x16 acc[2][NB];
+    gemm_mainloop<A_KCONT, B_KCONT, BN>(A, lda, B, ldb, M, N, K, kchunk, smem, i0, j0, kz, acc);
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int wi = (wave / 2) * 64, wj = (wave % 2) * (BN / 2);
     // Lane holds column lane % 32 of each 32x32 tile, rows (v / 4) * 8 +
     // (lane / 32) * 4 + v % 4.
     // Epilogue through LDS, in two halves of 64 rows: the a = 0 (then
@@ -368,6 +387,62 @@ __global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const TA* __restrict
         }
         __syncthreads();
     }
+}
+
+// dgrad with the GELU backward of the layer below in the epilogue (64-column
+// tiles): d = (A B) * gelu'(pre), stored as BF16 (the operand rounding every
+// later product applies anyway), and the column sums of each 128-row block of
+// d in FP32 (the bias gradient's first pass), summed in the order of
+// colsum_partial_kernel (rows g, g + 4, ... for g = 0..3, then the four
+// groups in order), so the values equal the GEMM, gelu_bwd and colsum
+// kernels in sequence bit for bit.
+template <bool A_KCONT, bool B_KCONT, typename TA, typename TB>
+__global__ void __launch_bounds__(GEMM_THREADS) gemm_gelu_bwd_kernel(const TA* __restrict__ A, int lda,
+                                                                     const TB* __restrict__ B, int ldb,
+                                                                     const float* __restrict__ pre, int ldp,
+                                                                     __bf16* __restrict__ out, int ldo, int M, int N,
+                                                                     int K, float* __restrict__ part) {
+    constexpr int BN = 64, SROW = BN + 4, C4 = BN / 4;
+    // the whole 128 x 64 FP32 tile (padded rows) and the column-sum groups fit the operand tiles' LDS
+    static_assert(BM * SROW * 4 + 4 * 64 * 4 <= gemm_smem_bytes<BN>(), "staging tile");
+    __shared__ __align__(16) char smem[gemm_smem_bytes<BN>()];
+    int i0, j0, kz;
+    f32x16 acc[2][1];
+    gemm_mainloop<A_KCONT, B_KCONT, BN>(A, lda, B, ldb, M, N, K, K, smem, i0, j0, kz, acc);
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int wi = (wave / 2) * 64, wj = (wave % 2) * (BN / 2);
+    float* stage = reinterpret_cast<float*>(smem);
+    float (*sg)[64] = reinterpret_cast<float (*)[64]>(smem + BM * SROW * 4);
+    // Lane holds column lane % 32 of each 32x32 tile, rows (v / 4) * 8 +
+    // (lane / 32) * 4 + v % 4; the last k-loop barrier freed the operand tiles.
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int v = 0; v < 16; v++)
+            stage[(wi + a * 32 + (v / 4) * 8 + (lane / 32) * 4 + v % 4) * SROW + wj + lane % 32] = acc[a][0][v];
+    __syncthreads();
+    for (int e = threadIdx.x; e < BM * C4; e += GEMM_THREADS) {
+        const int lr = e / C4, c4 = e % C4;
+        const int i = i0 + lr, j = j0 + c4 * 4;
+        if (i >= M || j >= N) continue;
+        float4* sp = reinterpret_cast<float4*>(stage + lr * SROW + c4 * 4);
+        const float4 dh = *sp;
+        const float4 pr = *reinterpret_cast<const float4*>(pre + (size_t)i * ldp + j);
+        const float4 d = make_float4(dh.x * gelu_grad(pr.x), dh.y * gelu_grad(pr.y), dh.z * gelu_grad(pr.z),
+                                     dh.w * gelu_grad(pr.w));
+        *reinterpret_cast<bf16x4*>(out + (size_t)i * ldo + j) =
+            (bf16x4){to_bf16(d.x), to_bf16(d.y), to_bf16(d.z), to_bf16(d.w)};
+        *sp = d;
+    }
+    __syncthreads();
+    const int c = threadIdx.x % 64, g = threadIdx.x / 64, j = j0 + c;
+    const int rows = min(BM, M - i0);
+    float s = 0.f;
+    if (j < N)
+        for (int r = g; r < rows; r += 4) s += stage[r * SROW + c];
+    sg[g][c] = s;
+    __syncthreads();
+    if (g == 0 && j < N) part[(size_t)(i0 / BM) * N + j] = ((sg[0][c] + sg[1][c]) + sg[2][c]) + sg[3][c];
 }
 
 // Split-K epilogue: C = sum over the parts in order (part 0 first) + bias
@@ -824,25 +899,24 @@ __device__ __forceinline__ BranchFlows branch_flows(const DevModel& m, int l, co
     return r;
 }
 
-// What one branch reads of the model and contributes to the penalty: its
-// flows at the voltages in LDS, the thermal, angle and arc-bound
-// violations, and d loss / d arc without the balance rows.  The forward and
-// the gradient pass both call it (the gradient pass recomputes rather than
-// keeping 5 values per branch in LDS).
-struct BranchPen {
-    BranchFlows f;
+// What one branch contributes to the penalty, from its arc values in LDS
+// (half-edge positions hf, ht): the thermal, angle and arc-bound
+// violations.  A pass over the branches in two loops, the flows first (with
+// the trigonometry) and then this, holds fewer registers than one loop
+// doing both, so more workgroups fit per compute unit.
+struct ArcPen {
     double arc[4];  // p_f, p_t, q_f, q_t (x's order)
     double cf, ct, ca, dvf, dvt, dva, dq[4];
     int hf, ht;     // positions of the from / to half-edge in the bus-ordered list
 };
-template <bool TRIG>
-__device__ __forceinline__ BranchPen branch_pen(const DevModel& m, const ProxRows& rows, const ProxPerm& pm, int l,
-                                                const double* s_va, const double* s_vm, double& C, double& S) {
+__device__ __forceinline__ ArcPen arc_pen(const DevModel& m, const ProxRows& rows, const ProxPerm& pm, int l,
+                                          const double* s_va, const double* s_hp, const double* s_hq) {
 #pragma clang fp contract(off)
     const int L = m.L;
-    BranchPen r;
+    ArcPen r;
     r.hf = pm.he_pos[l];
     r.ht = pm.he_pos[L + l];
+    const int fb = m.f_bus[l], tb = m.t_bus[l];
     const double rate2 = m.rate2[l];
     const double lf = rows.lcon[m.c_thf + l], uf = rows.ucon[m.c_thf + l];
     const double lt = rows.lcon[m.c_tht + l], ut = rows.ucon[m.c_tht + l];
@@ -853,14 +927,13 @@ __device__ __forceinline__ BranchPen branch_pen(const DevModel& m, const ProxRow
         lo[a] = rows.lvar[rows.pq0 + a * L + l];
         hi[a] = rows.uvar[rows.pq0 + a * L + l];
     }
-    r.f = branch_flows<TRIG>(m, l, s_va, s_vm, C, S);
-    r.arc[0] = r.f.pf.F;
-    r.arc[1] = r.f.pt.F;
-    r.arc[2] = r.f.qf.F;
-    r.arc[3] = r.f.qt.F;
+    r.arc[0] = s_hp[r.hf];
+    r.arc[1] = s_hp[r.ht];
+    r.arc[2] = s_hq[r.hf];
+    r.arc[3] = s_hq[r.ht];
     r.cf = r.arc[0] * r.arc[0] + r.arc[2] * r.arc[2] - rate2;
     r.ct = r.arc[1] * r.arc[1] + r.arc[3] * r.arc[3] - rate2;
-    r.ca = s_va[r.f.fb] - s_va[r.f.tb];
+    r.ca = s_va[fb] - s_va[tb];
     r.dvf = viol(r.cf, lf, uf);
     r.dvt = viol(r.ct, lt, ut);
     r.dva = viol(r.ca, la, ua);
@@ -915,12 +988,27 @@ __global__ void __launch_bounds__(kFuseThreads) loss_fused_kernel(DevModel m, Pr
     }
     __syncthreads();
 
-    // branches: arc flows, angle and thermal rows, arc bounds
+    // branches: arc flows (and cos, sin for the gradient pass), then the
+    // angle and thermal rows and the arc bounds
     for (int l = tid; l < L; l += kFuseThreads) {
         double Cc, Sc;
-        const BranchPen r = branch_pen<true>(m, rows, pm, l, s_va, s_vm, Cc, Sc);
+        const BranchFlows f = branch_flows<true>(m, l, s_va, s_vm, Cc, Sc);
+        const int hf = pm.he_pos[l], ht = pm.he_pos[L + l];
         s_cs[l] = Cc;
         s_cs[L + l] = Sc;
+        s_hp[hf] = f.pf.F;
+        s_hp[ht] = f.pt.F;
+        s_hq[hf] = f.qf.F;
+        s_hq[ht] = f.qt.F;
+        if (xb) {
+            xb[rows.pq0 + l] = f.pf.F;
+            xb[rows.pq0 + L + l] = f.pt.F;
+            xb[rows.pq0 + 2 * L + l] = f.qf.F;
+            xb[rows.pq0 + 3 * L + l] = f.qt.F;
+        }
+    }
+    for (int l = tid; l < L; l += kFuseThreads) {  // the same thread's branches: no barrier needed
+        const ArcPen r = arc_pen(m, rows, pm, l, s_va, s_hp, s_hq);
         pen += r.dvf * r.dvf;
         pen += r.dvt * r.dvt;
         pen += r.dva * r.dva;
@@ -929,12 +1017,7 @@ __global__ void __launch_bounds__(kFuseThreads) loss_fused_kernel(DevModel m, Pr
         for (int a = 0; a < 4; a++) {
             pen += r.dq[a] * r.dq[a];
             vio = fmax(vio, fabs(r.dq[a]));
-            if (xb) xb[rows.pq0 + a * L + l] = r.arc[a];
         }
-        s_hp[r.hf] = r.arc[0];
-        s_hp[r.ht] = r.arc[1];
-        s_hq[r.hf] = r.arc[2];
-        s_hq[r.ht] = r.arc[3];
         if (cb) {  // flow rows: p - F(v) with p := F(v), exactly 0
             cb[m.c_pfr + l] = 0.0;
             cb[m.c_qfr + l] = 0.0;
@@ -1008,24 +1091,33 @@ __global__ void __launch_bounds__(kFuseThreads) loss_fused_kernel(DevModel m, Pr
     }
     if (!gz) return;
 
-    // branches: d loss / d arc (with the balance rows) carried through
+    // branches: d loss / d arc without the balance rows, in place of each
+    // branch's own arc values; then with the balance rows, carried through
     // p = F(v) to the branch's four voltage entries, per half-edge
     for (int l = tid; l < L; l += kFuseThreads) {
-        double Cc = s_cs[l], Sc = s_cs[L + l];
-        const BranchPen r = branch_pen<false>(m, rows, pm, l, s_va, s_vm, Cc, Sc);
-        const BranchFlows& f = r.f;
+        const ArcPen r = arc_pen(m, rows, pm, l, s_va, s_hp, s_hq);
         const double wth[2] = {2.0 * rho * r.dvf, 2.0 * rho * r.dvt};
         double ap[4];
 #pragma unroll
         for (int a = 0; a < 4; a++) ap[a] = 2.0 * r.arc[a] * wth[a & 1] + 2.0 * rho * r.dq[a];
-        const double wa = 2.0 * rho * r.dva;
-        const double tpf = ap[0] + s_wb[f.fb], tpt = ap[1] + s_wb[f.tb];
-        const double tqf = ap[2] + s_wb[N + f.fb], tqt = ap[3] + s_wb[N + f.tb];
+        s_hp[r.hf] = ap[0];
+        s_hp[r.ht] = ap[1];
+        s_hq[r.hf] = ap[2];
+        s_hq[r.ht] = ap[3];
+    }
+    for (int l = tid; l < L; l += kFuseThreads) {
+        double Cc = s_cs[l], Sc = s_cs[L + l];
+        const BranchFlows f = branch_flows<false>(m, l, s_va, s_vm, Cc, Sc);
+        const int hf = pm.he_pos[l], ht = pm.he_pos[L + l];
+        const double la = rows.lcon[m.c_ang + l], ua = rows.ucon[m.c_ang + l];
+        const double wa = 2.0 * rho * viol(s_va[f.fb] - s_va[f.tb], la, ua);
+        const double tpf = s_hp[hf] + s_wb[f.fb], tpt = s_hp[ht] + s_wb[f.tb];
+        const double tqf = s_hq[hf] + s_wb[N + f.fb], tqt = s_hq[ht] + s_wb[N + f.tb];
         const double gt = tpf * f.pf.Ft + tqf * f.qf.Ft + tpt * f.pt.Ft + tqt * f.qt.Ft;
-        s_hp[r.hf] = gt + wa;
-        s_hp[r.ht] = -(gt + wa);
-        s_hq[r.hf] = tpf * f.pf.Fu + tqf * f.qf.Fu + tpt * f.pt.Fu + tqt * f.qt.Fu;
-        s_hq[r.ht] = tpf * f.pf.Fw + tqf * f.qf.Fw + tpt * f.pt.Fw + tqt * f.qt.Fw;
+        s_hp[hf] = gt + wa;
+        s_hp[ht] = -(gt + wa);
+        s_hq[hf] = tpf * f.pf.Fu + tqf * f.qf.Fu + tpt * f.pt.Fu + tqt * f.qt.Fu;
+        s_hq[ht] = tpf * f.pf.Fw + tqf * f.qf.Fw + tpt * f.pt.Fw + tqt * f.qt.Fw;
     }
     __syncthreads();
     double* gzb = gz + b * D;
@@ -1141,6 +1233,37 @@ hipError_t gemm_b(int variant, const TA* A, int lda, const void* B, bool b_bf16,
                     accumulate, splits, work, s);
 }
 }  // namespace
+
+namespace {
+template <typename TA, typename TB>
+hipError_t gelu_bwd_typed(const TA* A, int lda, const TB* B, int ldb, const float* pre, int ldp, __bf16* out, int ldo,
+                          int M, int N, int K, float* part, hipStream_t s) {
+    hipLaunchKernelGGL((gemm_gelu_bwd_kernel<true, false, TA, TB>), dim3((N + 63) / 64, (M + BM - 1) / BM, 1),
+                       dim3(GEMM_THREADS), 0, s, A, lda, B, ldb, pre, ldp, out, ldo, M, N, K, part);
+    return hipGetLastError();
+}
+template <typename TA>
+hipError_t gelu_bwd_b(const TA* A, int lda, const void* B, bool b_bf16, int ldb, const float* pre, int ldp, __bf16* out,
+                      int ldo, int M, int N, int K, float* part, hipStream_t s) {
+    if (b_bf16)
+        return gelu_bwd_typed(A, lda, static_cast<const __bf16*>(B), ldb, pre, ldp, out, ldo, M, N, K, part, s);
+    return gelu_bwd_typed(A, lda, static_cast<const float*>(B), ldb, pre, ldp, out, ldo, M, N, K, part, s);
+}
+}  // namespace
+
+hipError_t prox_gemm_gelu_bwd(const void* A, bool a_bf16, int lda, const void* B, bool b_bf16, int ldb,
+                              const float* pre, int ldp, void* out, int ldo, int M, int N, int K, float* part,
+                              hipStream_t s) {
+    __bf16* o = static_cast<__bf16*>(out);
+    if (a_bf16)
+        return gelu_bwd_b(static_cast<const __bf16*>(A), lda, B, b_bf16, ldb, pre, ldp, o, ldo, M, N, K, part, s);
+    return gelu_bwd_b(static_cast<const float*>(A), lda, B, b_bf16, ldb, pre, ldp, o, ldo, M, N, K, part, s);
+}
+
+hipError_t prox_colsum_parts(const float* part, int chunks, int N, float* out, float scale, hipStream_t s) {
+    hipLaunchKernelGGL(colsum_final_kernel, dim3((N + 63) / 64), dim3(256), 0, s, part, chunks, N, out, scale);
+    return hipGetLastError();
+}
 
 hipError_t prox_gemm_mixed(int variant, const void* A, bool a_bf16, int lda, const void* B, bool b_bf16, int ldb,
                            float* C, int ldc, int M, int N, int K, const float* bias, void* act, bool act_bf16,

@@ -147,6 +147,9 @@ def lib():
         "prox_gemm_splits": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "prox_gelu_bwd": ([_vp, _vp, _vp, ctypes.c_int64, _vp], ctypes.c_int),
         "prox_colsum": ([_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_float, _vp], ctypes.c_int),
+        "prox_colsum_parts": ([_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_float, _vp], ctypes.c_int),
+        "prox_gemm_gelu_bwd": ([_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int,
+                                _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp], ctypes.c_int),
         "prox_adam": ([_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                        ctypes.c_float, ctypes.c_int, _vp], ctypes.c_int),
         "prox_adam_dev": ([_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,

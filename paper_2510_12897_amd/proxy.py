@@ -74,6 +74,13 @@ def gemm_mixed(variant, A, a_bf16, lda, B, b_bf16, ldb, C, ldc, M, N, K, bias=No
                                       int(bool(act_bf16)), int(bool(accumulate)), int(splits), _p(work), _stream()))
 
 
+def gemm_gelu_bwd(A, a_bf16, lda, B, b_bf16, ldb, pre, ldp, out, ldo, M, N, K, part):
+    """out (BF16) = (A B) * gelu'(pre) for row-major A [M, K], B [K, N], and
+    the 128-row column partial sums of the product in part."""
+    _check(lib().prox_gemm_gelu_bwd(_p(A), int(bool(a_bf16)), int(lda), _p(B), int(bool(b_bf16)), int(ldb), _p(pre),
+                                    int(ldp), _p(out), int(ldo), int(M), int(N), int(K), _p(part), _stream()))
+
+
 def gemm_splits(M, N, K):
     """The library's split count for an M x N x K product."""
     s = lib().prox_gemm_splits(int(M), int(N), int(K))
@@ -230,22 +237,36 @@ def _make_mlp_function():
             splits = [gemm_splits(fo, fi, Bn) for (_, _, fo, fi) in mlp.layout]
             sk = max(s * fo * fi if s > 1 else 0 for s, (_, _, fo, fi) in zip(splits, mlp.layout))
             skw = torch.empty(max(sk, 4), dtype=torch.float32, device=gz.device)
+            parts = False  # work holds the first column-sum pass of dpre
             for k in range(nl - 1, -1, -1):
                 wo, bo, fo, fi = mlp.layout[k]
                 h_in = ctx.acts[k]
+                d_bf16 = dpre.dtype == torch.bfloat16
                 # dW [fo, fi] = dpre^T h_in (split over the batch); db = column sums of dpre
-                gemm_mixed(2, dpre, False, fo, h_in, h_in.dtype == torch.bfloat16, fi, gflat[wo:wo + fo * fi], fi,
+                gemm_mixed(2, dpre, d_bf16, fo, h_in, h_in.dtype == torch.bfloat16, fi, gflat[wo:wo + fo * fi], fi,
                            fo, fi, Bn, splits=splits[k], work=skw)
-                _check(lib().prox_colsum(_p(dpre), Bn, fo, _p(work), _p(gflat[bo:bo + fo]), ctypes.c_float(1.0),
-                                         _stream()))
+                if parts:
+                    _check(lib().prox_colsum_parts(_p(work), chunks, fo, _p(gflat[bo:bo + fo]), ctypes.c_float(1.0),
+                                                   _stream()))
+                else:
+                    _check(lib().prox_colsum(_p(dpre), Bn, fo, _p(work), _p(gflat[bo:bo + fo]), ctypes.c_float(1.0),
+                                             _stream()))
                 if k == 0:
                     break
-                # dh [B, fi] = dpre W, then through the GELU of layer k - 1
-                dh = torch.empty(Bn, fi, dtype=torch.float32, device=gz.device)
                 W, w_bf16 = mlp.mma_weight(k)
-                gemm_mixed(1, dpre, False, fo, W, w_bf16, fi, dh, fi, Bn, fi, fo)
-                d = torch.empty_like(dh)
-                _check(lib().prox_gelu_bwd(_p(ctx.pres[k - 1]), _p(dh), _p(d), dh.numel(), _stream()))
+                if fi % 8 == 0:  # the BF16 result is the next product's k-contiguous operand
+                    # dpre of layer k - 1 = (dpre W) * gelu'(pre of k - 1), in BF16 (the rounding every
+                    # product applies to it), with its column sums' first pass in work
+                    d = torch.empty(Bn, fi, dtype=torch.bfloat16, device=gz.device)
+                    gemm_gelu_bwd(dpre, d_bf16, fo, W, w_bf16, fi, ctx.pres[k - 1], fi, d, fi, Bn, fi, fo, work)
+                    parts = True
+                else:
+                    # dh [B, fi] = dpre W, then through the GELU of layer k - 1
+                    dh = torch.empty(Bn, fi, dtype=torch.float32, device=gz.device)
+                    gemm_mixed(1, dpre, d_bf16, fo, W, w_bf16, fi, dh, fi, Bn, fi, fo)
+                    d = torch.empty_like(dh)
+                    _check(lib().prox_gelu_bwd(_p(ctx.pres[k - 1]), _p(dh), _p(d), dh.numel(), _stream()))
+                    parts = False
                 dpre = d
             return None, gflat, None
 

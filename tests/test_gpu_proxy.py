@@ -190,6 +190,42 @@ def test_gemm_bf16_storage_shape_rules(dev, P):
     assert float(out.abs().max()) == 0.0
 
 
+@pytest.mark.parametrize("shape", [(200, 72, 40), (4096, 1024, 1024), (128, 4, 8)])
+@pytest.mark.parametrize("a_bf16,b_bf16", [(False, False), (True, True), (False, True)])
+def test_gemm_gelu_bwd_equals_the_three_kernels(dev, P, shape, a_bf16, b_bf16):
+    """prox_gemm_gelu_bwd against the product (prox_gemm_bf16_mixed, variant
+    1), prox_gelu_bwd and prox_colsum in sequence: the BF16 output is the
+    rounding of their FP32 result, the 128-row column partial sums and the
+    final column sums (prox_colsum_parts) are theirs, all bit for bit; ragged
+    row and column tiles included."""
+    from paper_2510_12897_amd.opf import lib
+    M, N, K = shape
+    g = torch.Generator(device=dev)
+    g.manual_seed(M + N + K)
+    A = torch.randn(M, K, generator=g, device=dev)
+    B = torch.randn(K, N, generator=g, device=dev) / math.sqrt(K)
+    pre = torch.randn(M, N, generator=g, device=dev) * 2.0
+    As = A.to(torch.bfloat16) if a_bf16 else A
+    Bs = B.to(torch.bfloat16) if b_bf16 else B
+    dh = torch.empty(M, N, device=dev)
+    P.gemm_mixed(1, As, a_bf16, K, Bs, b_bf16, N, dh, N, M, N, K)
+    d = torch.empty_like(dh)
+    assert lib().prox_gelu_bwd(P._p(pre), P._p(dh), P._p(d), M * N, P._stream()) == 0
+    chunks = (M + 127) // 128
+    work = torch.empty(chunks * N, device=dev)
+    db = torch.empty(N, device=dev)
+    assert lib().prox_colsum(P._p(d), M, N, P._p(work), P._p(db), 1.0, P._stream()) == 0
+    out = torch.empty(M, N, dtype=torch.bfloat16, device=dev)
+    part = torch.full((chunks * N,), float("nan"), device=dev)
+    P.gemm_gelu_bwd(As, a_bf16, K, Bs, b_bf16, N, pre, N, out, N, M, N, K, part)
+    db2 = torch.empty(N, device=dev)
+    assert lib().prox_colsum_parts(P._p(part), chunks, N, P._p(db2), 1.0, P._stream()) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(out, d.to(torch.bfloat16))
+    assert torch.equal(part, work)
+    assert torch.equal(db2, db)
+
+
 def test_mlp_bf16_storage_matches_fp32_storage(dev, P):
     """The MLP with BF16 weight copy and BF16 hidden activations computes the
     same outputs, gradients and Adam updates as with FP32 storage."""
