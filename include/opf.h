@@ -536,6 +536,45 @@ int prox_loss_fused_fits(opf_model model);
 /* dz [B, D] = (float)(wb[b] * gz[b, j]): the backward of prox_loss_fused's
  * loss under an incoming gradient wb [B] (device FP64). */
 int prox_scale_rows(const double *gz, const double *wb, int B, int D, float *dz, void *stream);
+
+/* The proxy MLP's parameters and optimizer state, all device memory the
+ * caller owns: n_layers layers of widths dims[0..n_layers] (host array,
+ * multiples of 4), GELU after every layer but the last.  flat holds per
+ * layer the weight [out, in] row-major then the bias (FP32); flat_bf16 is
+ * its BF16 copy that the products read where the input width is a multiple
+ * of 8 (NULL: FP32 operands and activations throughout); m1, m2 are Adam's
+ * moments; step is Adam's step count (int32, on the device). */
+typedef struct prox_mlp_desc {
+    int32_t n_layers;
+    const int32_t *dims;
+    float *flat;
+    void *flat_bf16;
+    float *m1;
+    float *m2;
+    int32_t *step;
+} prox_mlp_desc;
+
+/* Bytes of the workspace prox_train_step needs for a batch of B samples. */
+int prox_train_step_bytes(const prox_mlp_desc *mlp, int B, int64_t *bytes);
+
+/* One training step of the warm-start proxy (the learned start of the
+ * related-work proxies, Sec. I; Cvio of Sec. IV-A5), every launch issued
+ * here: the MLP forward on feats [B, dims[0]] (FP32) with the hidden
+ * activations stored BF16 where flat_bf16 is given and the width a multiple
+ * of 8; prox_loss_fused on its output at loads [B, 2N]; the gradient of the
+ * mean loss (weight 1/B); the MLP backward (split-K weight gradients, bias
+ * column sums, the GELU backward in the dh product as prox_gemm_gelu_bwd);
+ * and prox_adam_dev (lr, beta1, beta2, eps).  The same kernels in the same
+ * order as those calls made one by one, so the parameters after a step are
+ * theirs bit for bit.  loss, cvio [B] receive the per-sample loss and Cvio
+ * before the update.  work: work_bytes of device memory (16-byte aligned,
+ * at least prox_train_step_bytes) that the step uses as scratch; the model
+ * is one prox_loss_fused takes and the MLP's output width is 2N + 2G;
+ * OPF_E_ARG otherwise.  Calls on one stream run in order; concurrent calls
+ * sharing a workspace race. */
+int prox_train_step(opf_model model, const prox_mlp_desc *mlp, const float *feats, const double *loads, int B,
+                    double va_span, double rho, double obj_scale, float lr, float beta1, float beta2, float eps,
+                    void *work, int64_t work_bytes, double *loss, double *cvio, void *stream);
 #ifdef __cplusplus
 }
 #endif

@@ -1,5 +1,6 @@
 // C-ABI of the warm-start proxy kernels (declared in include/opf.h).
 #include <cstdint>
+#include <vector>
 
 #include "internal.h"
 #include "proxy_kernels.h"
@@ -71,9 +72,172 @@ bool fused_fits(opf_model m) {
            opf::prox_loss_fused_lds(ly.N, ly.L, ly.G) <= kFusedLdsMax;
 }
 
+
+// The training step's workspace: every buffer of one step carved from the
+// caller's block (256-byte aligned), and the per-layer operand choices of
+// the autograd path (BF16 weights where a BF16 copy is kept and the input
+// width is a multiple of 8; BF16 hidden activations where the width is).
+struct TrainPlan {
+    int nl = 0, B = 0, D = 0, chunks = 0, maxd = 0;
+    std::vector<int64_t> wo, bo;                  // weight and bias offsets (floats)
+    std::vector<int> fo, fi, splits;
+    std::vector<bool> w_bf16, act_bf16;
+    std::vector<size_t> pre, act;                 // byte offsets of each layer's pre-activation and activation
+    size_t gz = 0, dz = 0, gflat = 0, cwork = 0, skw = 0, d0 = 0, d1 = 0, dh = 0, total = 0;
+    int64_t n_params = 0;
+};
+
+int make_plan(const prox_mlp_desc* mlp, int B, TrainPlan& P) {
+    if (!mlp || mlp->n_layers < 1 || !mlp->dims) return set_err(OPF_E_ARG, "bad MLP descriptor");
+    if (B < 4 || B % 4) return set_err(OPF_E_ARG, "the batch must be a positive multiple of 4");
+    P.nl = mlp->n_layers;
+    P.B = B;
+    P.chunks = (B + 127) / 128;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    };
+    int64_t par = 0;
+    for (int k = 0; k <= P.nl; k++) {
+        const int d = mlp->dims[k];
+        if (d < 4 || d % 4) return set_err(OPF_E_ARG, "layer widths must be positive multiples of 4");
+        P.maxd = std::max(P.maxd, d);
+    }
+    size_t sk = 4;
+    for (int k = 0; k < P.nl; k++) {
+        const int fi = mlp->dims[k], fo = mlp->dims[k + 1];
+        P.fi.push_back(fi);
+        P.fo.push_back(fo);
+        P.wo.push_back(par);
+        P.bo.push_back(par + (int64_t)fo * fi);
+        par += (int64_t)fo * fi + fo;
+        P.w_bf16.push_back(mlp->flat_bf16 != nullptr && fi % 8 == 0);
+        if (P.w_bf16.back() && (P.wo.back() % 8 || !aligned16(mlp->flat_bf16)))  // the products' 16-byte loads
+            return set_err(OPF_E_ARG, "layer %d's BF16 weights are not 16-byte aligned", k);
+        P.act_bf16.push_back(k < P.nl - 1 && mlp->flat_bf16 != nullptr && fo % 8 == 0);
+        const int sp = opf::prox_gemm_splits(fo, fi, B);
+        P.splits.push_back(sp);
+        if (sp > 1) sk = std::max(sk, (size_t)sp * fo * fi);
+        P.pre.push_back(take(sizeof(float) * (size_t)B * fo));
+        P.act.push_back(k < P.nl - 1 ? take((P.act_bf16.back() ? 2 : 4) * (size_t)B * fo) : 0);
+    }
+    P.n_params = par;
+    P.D = mlp->dims[P.nl];
+    P.gz = take(sizeof(double) * (size_t)B * P.D);
+    P.dz = take(sizeof(float) * (size_t)B * P.D);
+    P.gflat = take(sizeof(float) * (size_t)par);
+    P.cwork = take(sizeof(float) * (size_t)P.chunks * P.maxd);
+    P.skw = take(sizeof(float) * sk);
+    P.d0 = take(sizeof(float) * (size_t)B * P.maxd);
+    P.d1 = take(sizeof(float) * (size_t)B * P.maxd);
+    P.dh = take(sizeof(float) * (size_t)B * P.maxd);
+    P.total = off;
+    return OPF_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int prox_train_step_bytes(const prox_mlp_desc* mlp, int B, int64_t* bytes) {
+    TrainPlan P;
+    if (int rc = make_plan(mlp, B, P)) return rc;
+    if (!bytes) return set_err(OPF_E_ARG, "bytes must be non-NULL");
+    *bytes = (int64_t)P.total;
+    return OPF_OK;
+}
+
+int prox_train_step(opf_model model, const prox_mlp_desc* mlp, const float* feats, const double* loads, int B,
+                    double va_span, double rho, double obj_scale, float lr, float beta1, float beta2, float eps,
+                    void* work, int64_t work_bytes, double* loss, double* cvio, void* stream) {
+    if (int rc = static_model(model)) return rc;
+    if (!fused_fits(model)) return set_err(OPF_E_ARG, "the training step takes a model that prox_loss_fused takes");
+    TrainPlan P;
+    if (int rc = make_plan(mlp, B, P)) return rc;
+    const opf::Layout& ly = model->hm.ly;
+    if (P.D != 2 * ly.N + 2 * ly.G) return set_err(OPF_E_ARG, "the MLP's output width must be 2N + 2G");
+    if (!feats || !loads || !loss || !cvio || !work || !mlp->flat || !mlp->m1 || !mlp->m2 || !mlp->step)
+        return set_err(OPF_E_ARG, "bad arguments");
+    if (!aligned16(feats) || !aligned16(work) || !aligned16(mlp->flat) || (mlp->flat_bf16 && !aligned16(mlp->flat_bf16)))
+        return set_err(OPF_E_ARG, "feats, work and the parameters must be 16-byte aligned");
+    if (work_bytes < (int64_t)P.total) return set_err(OPF_E_ARG, "work holds %lld bytes, the step needs %zu",
+                                                      (long long)work_bytes, P.total);
+    DeviceGuard dg(model->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    char* W = static_cast<char*>(work);
+    const float* flat = mlp->flat;
+    const __bf16* fb = static_cast<const __bf16*>(mlp->flat_bf16);
+    auto weight = [&](int k) -> const void* { return P.w_bf16[k] ? (const void*)(fb + P.wo[k]) : (const void*)(flat + P.wo[k]); };
+    hipError_t e = hipSuccess;
+    auto ok = [&](hipError_t r) { if (e == hipSuccess) e = r; return r == hipSuccess; };
+    // forward: x W^T + b with GELU on the hidden layers (the activations BF16 where chosen)
+    const void* h = feats;
+    bool h_bf16 = false;
+    for (int k = 0; k < P.nl; k++) {
+        const bool hidden = k < P.nl - 1;
+        if (!ok(opf::prox_gemm_mixed(0, h, h_bf16, P.fi[k], weight(k), P.w_bf16[k], P.fi[k],
+                                     reinterpret_cast<float*>(W + P.pre[k]), P.fo[k], B, P.fo[k], P.fi[k],
+                                     flat + P.bo[k], hidden ? W + P.act[k] : nullptr, hidden && P.act_bf16[k], 0, 1,
+                                     nullptr, s)))
+            return hip_err(e, "prox_train_step forward");
+        if (hidden) {
+            h = W + P.act[k];
+            h_bf16 = P.act_bf16[k];
+        }
+    }
+    // the loss with d loss / d z, then the mean's weight 1/B
+    const float* z = reinterpret_cast<const float*>(W + P.pre[P.nl - 1]);
+    double* gz = reinterpret_cast<double*>(W + P.gz);
+    float* dz = reinterpret_cast<float*>(W + P.dz);
+    const opf::ProxPerm pm{model->he_pos, model->gen_pos};
+    if (!ok(opf::prox_loss_fused(model->dm, box_of(model, va_span), rows_of(model), pm, z, loads, B, rho, obj_scale,
+                                 loss, cvio, gz, nullptr, nullptr, s)) ||
+        !ok(opf::prox_scale_colsum(gz, 1.0 / B, B, P.D, dz, reinterpret_cast<float*>(W + P.cwork), s)))
+        return hip_err(e, "prox_train_step loss");
+    // backward: weight gradients (split over the batch), bias column sums and
+    // the GELU backward of the layer below in the dh product
+    float* gflat = reinterpret_cast<float*>(W + P.gflat);
+    float* cwork = reinterpret_cast<float*>(W + P.cwork);
+    float* skw = reinterpret_cast<float*>(W + P.skw);
+    const void* dpre = dz;
+    bool d_bf16 = false, parts = true;  // the top layer's column sums' first pass came with dz
+    char* dbuf[2] = {W + P.d0, W + P.d1};
+    for (int k = P.nl - 1; k >= 0; k--) {
+        const int fo = P.fo[k], fi = P.fi[k];
+        const void* h_in = k == 0 ? (const void*)feats : (const void*)(W + P.act[k - 1]);
+        const bool h_in_bf16 = k > 0 && P.act_bf16[k - 1];
+        if (!ok(opf::prox_gemm_mixed(2, dpre, d_bf16, fo, h_in, h_in_bf16, fi, gflat + P.wo[k], fi, fo, fi, B, nullptr,
+                                     nullptr, false, 0, P.splits[k], skw, s)))
+            return hip_err(e, "prox_train_step weight gradient");
+        if (!ok(parts ? opf::prox_colsum_parts(cwork, P.chunks, fo, gflat + P.bo[k], 1.0f, s)
+                      : opf::prox_colsum(static_cast<const float*>(dpre), B, fo, cwork, gflat + P.bo[k], 1.0f, s)))
+            return hip_err(e, "prox_train_step bias gradient");
+        if (k == 0) break;
+        const float* pre_below = reinterpret_cast<const float*>(W + P.pre[k - 1]);
+        char* d = dbuf[k & 1];
+        if (fi % 8 == 0) {
+            if (!ok(opf::prox_gemm_gelu_bwd(dpre, d_bf16, fo, weight(k), P.w_bf16[k], fi, pre_below, fi, d, fi, B, fi,
+                                            fo, cwork, s)))
+                return hip_err(e, "prox_train_step dh");
+            d_bf16 = parts = true;
+        } else {
+            float* dh = reinterpret_cast<float*>(W + P.dh);
+            if (!ok(opf::prox_gemm_mixed(1, dpre, d_bf16, fo, weight(k), P.w_bf16[k], fi, dh, fi, B, fi, fo, nullptr,
+                                         nullptr, false, 0, 1, nullptr, s)) ||
+                !ok(opf::prox_gelu_bwd(pre_below, dh, reinterpret_cast<float*>(d), (int64_t)B * fi, s)))
+                return hip_err(e, "prox_train_step dh");
+            d_bf16 = parts = false;
+        }
+        dpre = d;
+    }
+    if (!ok(opf::prox_adam_dev(mlp->flat, gflat, mlp->m1, mlp->m2, P.n_params, lr, beta1, beta2, eps, mlp->step,
+                               mlp->flat_bf16, s)))
+        return hip_err(e, "prox_train_step Adam");
+    return OPF_OK;
+}
+
 
 namespace {
 int gemm_checked(int variant, const void* A, bool a_bf16, int lda, const void* B, bool b_bf16, int ldb, float* C,
@@ -283,7 +447,8 @@ int prox_loss_fused(opf_model model, const float* z, int B, double va_span, cons
 
 int prox_scale_rows(const double* gz, const double* wb, int B, int D, float* dz, void* stream) {
     if (B < 1 || D < 1 || !gz || !wb || !dz) return set_err(OPF_E_ARG, "bad arguments");
-    return launched(opf::prox_scale_rows(gz, wb, B, D, dz, static_cast<hipStream_t>(stream)), "prox_scale_rows launch");
+    return launched(opf::prox_scale_rows(gz, wb, 0.0, B, D, dz, static_cast<hipStream_t>(stream)),
+                    "prox_scale_rows launch");
 }
 
 }  // extern "C"

@@ -87,7 +87,10 @@ size_t prox_loss_fused_lds(int N, int L, int G);
 hipError_t prox_loss_fused(const DevModel& m, const ProxBox& box, const ProxRows& rows, const ProxPerm& pm,
                            const float* z, const double* loads, int B, double rho, double obj_scale, double* loss,
                            double* cvio, double* gz, double* X, double* C, hipStream_t s);
-// dz [B, D] = (float)(wb[b] * gz[b, j])
-hipError_t prox_scale_rows(const double* gz, const double* wb, int B, int D, float* dz, hipStream_t s);
+// dz [B, D] = (float)(w * gz[b, j]) and part [ceil(B / 128), D] = the first
+// pass of dz's column sums (prox_colsum's)
+hipError_t prox_scale_colsum(const double* gz, double w, int B, int D, float* dz, float* part, hipStream_t s);
+// dz [B, D] = (float)(w_b * gz[b, j]), w_b = wb[b] or, with wb NULL, w
+hipError_t prox_scale_rows(const double* gz, const double* wb, double w, int B, int D, float* dz, hipStream_t s);
 
 }  // namespace opf

@@ -18,6 +18,7 @@
 //    weights that carry the arc-flow gradient back to the voltages.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "dev_model.h"
@@ -528,19 +529,30 @@ __global__ void __launch_bounds__(256) colsum_final_kernel(const float* __restri
 // Adam (Kingma and Ba, 2015) with bias correction; FP32 state.
 // pb (may be NULL) receives the updated parameters rounded to BF16: the
 // matrix cores' copy of the weights.
+// One parameter's Adam update (Kingma and Ba, Algorithm 1, with the bias
+// corrections c1, c2).  No contraction, so that every kernel below rounds
+// each operation alike whatever the compiler would fuse in its context.
+__device__ __forceinline__ void adam_one(float& p, float g, float& m1, float& m2, float lr, float b1, float b2,
+                                         float eps, float c1, float c2) {
+#pragma clang fp contract(off)
+    const float a = b1 * m1 + (1.f - b1) * g;
+    const float b = b2 * m2 + (1.f - b2) * g * g;
+    m1 = a;
+    m2 = b;
+    p = p - lr * (a / c1) / (sqrtf(b / c2) + eps);
+}
+
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
                             float* __restrict__ m2, int64_t n, float lr, float b1, float b2, float eps, float c1,
                             float c2, __bf16* __restrict__ pb) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float gi = g[i];
-    const float a = b1 * m1[i] + (1.f - b1) * gi;
-    const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
-    m1[i] = a;
-    m2[i] = b;
-    const float pn = p[i] - lr * (a / c1) / (sqrtf(b / c2) + eps);
-    p[i] = pn;
-    if (pb) pb[i] = to_bf16(pn);
+    float pi = p[i], ai = m1[i], bi = m2[i];
+    adam_one(pi, g[i], ai, bi, lr, b1, b2, eps, c1, c2);
+    m1[i] = ai;
+    m2[i] = bi;
+    p[i] = pi;
+    if (pb) pb[i] = to_bf16(pi);
 }
 
 // Adam with the step count in device memory (a recorded step replays with
@@ -559,14 +571,53 @@ __global__ void adam_dev_kernel(float* __restrict__ p, const float* __restrict__
     const float c1 = corr[0], c2 = corr[1];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float gi = g[i];
-    const float a = b1 * m1[i] + (1.f - b1) * gi;
-    const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
-    m1[i] = a;
-    m2[i] = b;
-    const float pn = p[i] - lr * (a / c1) / (sqrtf(b / c2) + eps);
-    p[i] = pn;
-    if (pb) pb[i] = to_bf16(pn);
+    float pi = p[i], ai = m1[i], bi = m2[i];
+    adam_one(pi, g[i], ai, bi, lr, b1, b2, eps, c1, c2);
+    m1[i] = ai;
+    m2[i] = bi;
+    p[i] = pi;
+    if (pb) pb[i] = to_bf16(pi);
+}
+
+// adam_dev_kernel over 4 consecutive parameters per thread (16-byte
+// accesses) in a grid-stride loop: the same arithmetic per parameter, the
+// bias corrections formed once per workgroup for many more parameters.
+__global__ void __launch_bounds__(256) adam_dev4_kernel(float* __restrict__ p, const float* __restrict__ g,
+                                                        float* __restrict__ m1, float* __restrict__ m2, int64_t n,
+                                                        float lr, float b1, float b2, float eps,
+                                                        const int32_t* __restrict__ step, __bf16* __restrict__ pb) {
+    __shared__ float corr[2];
+    if (threadIdx.x == 0) {
+        const float t = (float)(*step + 1);
+        corr[0] = 1.f - powf(b1, t);
+        corr[1] = 1.f - powf(b2, t);
+    }
+    __syncthreads();
+    const float c1 = corr[0], c2 = corr[1];
+    const int64_t n4 = n / 4, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n4; q += stride) {
+        float4 pv = reinterpret_cast<float4*>(p)[q];
+        float4 av = reinterpret_cast<float4*>(m1)[q];
+        float4 bv = reinterpret_cast<float4*>(m2)[q];
+        const float4 gv = reinterpret_cast<const float4*>(g)[q];
+        adam_one(pv.x, gv.x, av.x, bv.x, lr, b1, b2, eps, c1, c2);
+        adam_one(pv.y, gv.y, av.y, bv.y, lr, b1, b2, eps, c1, c2);
+        adam_one(pv.z, gv.z, av.z, bv.z, lr, b1, b2, eps, c1, c2);
+        adam_one(pv.w, gv.w, av.w, bv.w, lr, b1, b2, eps, c1, c2);
+        reinterpret_cast<float4*>(m1)[q] = av;
+        reinterpret_cast<float4*>(m2)[q] = bv;
+        reinterpret_cast<float4*>(p)[q] = pv;
+        if (pb)
+            reinterpret_cast<bf16x4*>(pb)[q] = (bf16x4){to_bf16(pv.x), to_bf16(pv.y), to_bf16(pv.z), to_bf16(pv.w)};
+    }
+    for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        float pi = p[i], ai = m1[i], bi = m2[i];
+        adam_one(pi, g[i], ai, bi, lr, b1, b2, eps, c1, c2);
+        m1[i] = ai;
+        m2[i] = bi;
+        p[i] = pi;
+        if (pb) pb[i] = to_bf16(pi);
+    }
 }
 
 __global__ void step_bump_kernel(int32_t* step) { *step += 1; }
@@ -1148,12 +1199,33 @@ __global__ void __launch_bounds__(kFuseThreads) loss_fused_kernel(DevModel m, Pr
     }
 }
 
-// dz [B, D] = (float)(wb[b] * gz[b, j])
-__global__ void scale_rows_kernel(const double* __restrict__ gz, const double* __restrict__ wb, int B, int D,
-                                  float* __restrict__ dz) {
+// dz [B, D] = (float)(w * gz) and the first pass of dz's column sums
+// (colsum_partial_kernel's chunks, rows and order), in one pass over gz.
+__global__ void __launch_bounds__(256) scale_colsum_kernel(const double* __restrict__ gz, double w, int B, int D,
+                                                           float* __restrict__ dz, float* __restrict__ part) {
+    __shared__ float sg[4][64];
+    const int c = threadIdx.x % 64, g = threadIdx.x / 64;
+    const int j = blockIdx.x * 64 + c;
+    const int i0 = blockIdx.y * COLSUM_ROWS, i1 = min(i0 + COLSUM_ROWS, B);
+    float acc = 0.f;
+    if (j < D)
+        for (int i = i0 + g; i < i1; i += 4) {
+            const float v = (float)(w * gz[(size_t)i * D + j]);
+            dz[(size_t)i * D + j] = v;
+            acc += v;
+        }
+    sg[g][c] = acc;
+    __syncthreads();
+    if (g == 0 && j < D) part[(size_t)blockIdx.y * D + j] = ((sg[0][c] + sg[1][c]) + sg[2][c]) + sg[3][c];
+}
+
+// dz [B, D] = (float)(w_b * gz[b, j]) with w_b = wb[b], or the constant w
+// when wb is NULL
+__global__ void scale_rows_kernel(const double* __restrict__ gz, const double* __restrict__ wb, double w, int B,
+                                  int D, float* __restrict__ dz) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)B * D) return;
-    dz[idx] = (float)(wb[idx / D] * gz[idx]);
+    dz[idx] = (float)((wb ? wb[idx / D] : w) * gz[idx]);
 }
 
 }  // namespace
@@ -1305,8 +1377,15 @@ hipError_t prox_adam(float* p, const float* g, float* m1, float* m2, int64_t n, 
 
 hipError_t prox_adam_dev(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2,
                          float eps, int32_t* step, void* pb, hipStream_t s) {
-    hipLaunchKernelGGL(adam_dev_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m1, m2, n, lr, b1, b2,
-                       eps, step, static_cast<__bf16*>(pb));
+    auto a16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+    if (a16(p) && a16(g) && a16(m1) && a16(m2) && (reinterpret_cast<uintptr_t>(pb) & 7u) == 0) {
+        const int64_t blocks = std::min<int64_t>((n / 4 + 255) / 256, 2048);
+        hipLaunchKernelGGL(adam_dev4_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, s, p, g, m1,
+                           m2, n, lr, b1, b2, eps, step, static_cast<__bf16*>(pb));
+    } else {
+        hipLaunchKernelGGL(adam_dev_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m1, m2, n, lr,
+                           b1, b2, eps, step, static_cast<__bf16*>(pb));
+    }
     hipLaunchKernelGGL(step_bump_kernel, dim3(1), dim3(1), 0, s, step);
     return hipGetLastError();
 }
@@ -1373,9 +1452,15 @@ hipError_t prox_loss_fused(const DevModel& m, const ProxBox& box, const ProxRows
     return hipGetLastError();
 }
 
-hipError_t prox_scale_rows(const double* gz, const double* wb, int B, int D, float* dz, hipStream_t s) {
+hipError_t prox_scale_colsum(const double* gz, double w, int B, int D, float* dz, float* part, hipStream_t s) {
+    hipLaunchKernelGGL(scale_colsum_kernel, dim3((D + 63) / 64, (B + COLSUM_ROWS - 1) / COLSUM_ROWS), dim3(256), 0, s,
+                       gz, w, B, D, dz, part);
+    return hipGetLastError();
+}
+
+hipError_t prox_scale_rows(const double* gz, const double* wb, double w, int B, int D, float* dz, hipStream_t s) {
     const int64_t tot = (int64_t)B * D;
-    hipLaunchKernelGGL(scale_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, gz, wb, B, D, dz);
+    hipLaunchKernelGGL(scale_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, gz, wb, w, B, D, dz);
     return hipGetLastError();
 }
 

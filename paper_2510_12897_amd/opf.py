@@ -75,6 +75,12 @@ class _Devices(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("bus", _ip)] + [(k, _dp) for k in DEV_FIELDS]
 
 
+class MlpDesc(ctypes.Structure):
+    """prox_mlp_desc: the proxy MLP's device buffers (include/opf.h)."""
+    _fields_ = [("n_layers", ctypes.c_int32), ("dims", ctypes.POINTER(ctypes.c_int32)), ("flat", _vp),
+                ("flat_bf16", _vp), ("m1", _vp), ("m2", _vp), ("step", _vp)]
+
+
 class _Opts(ctypes.Structure):
     _fields_ = [
         ("n_periods", ctypes.c_int32), ("pd_t", _dp), ("qd_t", _dp),
@@ -168,6 +174,10 @@ def lib():
                              _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
         "prox_loss_fused_fits": ([_vp], ctypes.c_int),
         "prox_scale_rows": ([_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp], ctypes.c_int),
+        "prox_train_step_bytes": ([P(MlpDesc), ctypes.c_int, _i64p], ctypes.c_int),
+        "prox_train_step": ([_vp, P(MlpDesc), _vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_double, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp,
+                             ctypes.c_int64, _vp, _vp, _vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)

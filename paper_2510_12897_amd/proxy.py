@@ -165,6 +165,15 @@ class MLP:
     def __call__(self, x):
         return _MLPFunction.apply(x, self.flat, self)
 
+    def desc(self):
+        """The prox_mlp_desc of this MLP (its buffers stay owned here)."""
+        if getattr(self, "_desc", None) is None:
+            dims = (ctypes.c_int32 * len(self.dims))(*self.dims)
+            self._desc = (opf.MlpDesc(len(self.dims) - 1, dims, self.flat.data_ptr(),
+                                      self.flat_bf16.data_ptr() if self.bf16_storage else None,
+                                      self.m1.data_ptr(), self.m2.data_ptr(), self.step_dev.data_ptr()), dims)
+        return self._desc[0]
+
     def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         if self.flat.grad is None:
             raise OPFError(OPF_E_ARG, "no gradient: run backward first")
@@ -502,6 +511,8 @@ class WarmStartProxy:
         self.inv_scale = torch.as_tensor(np.where(scale > 0, 1.0 / np.maximum(scale, 1e-300), 0.0), device=self.dev)
         b = self.pen.model.bounds()
         self.x0 = b["x0"]
+        self.native = True  # train_step through prox_train_step where it applies
+        self._ws = None
 
     # -- data: seeded +-spread uniform scalings of the base loads (one factor per bus)
     def sample(self, gen):
@@ -525,11 +536,43 @@ class WarmStartProxy:
         return self.pen(X)
 
     def train_step(self, loads, feats, lr=3e-4):
+        """One step on the mean loss: forward, backward and Adam.  On a model
+        that the fused loss takes, one library call issues every launch
+        (prox_train_step); else the autograd path.  Both give the same
+        parameters bit for bit."""
+        B = feats.shape[0]
+        if self.native and self.pen.fused and B % 4 == 0:
+            return self._train_step_native(loads, feats, lr)
+        return self.train_step_autograd(loads, feats, lr)
+
+    def train_step_autograd(self, loads, feats, lr=3e-4):
         lb = self.loss(loads, feats)
         loss = lb.mean()
         loss.backward()
         self.mlp.adam_step(lr=lr)
         return loss.detach()
+
+    def _train_step_native(self, loads, feats, lr):
+        torch = _torch()
+        mlp = self.mlp
+        B = feats.shape[0]
+        if self._ws is None or self._ws[0] != B:
+            nbytes = ctypes.c_int64()
+            _check(lib().prox_train_step_bytes(ctypes.byref(mlp.desc()), B, ctypes.byref(nbytes)))
+            self._ws = (B, torch.empty(nbytes.value, dtype=torch.uint8, device=self.dev),
+                        torch.empty(B, dtype=torch.float64, device=self.dev),
+                        torch.empty(B, dtype=torch.float64, device=self.dev))
+        _, ws, lb, cv = self._ws
+        mlp.step += 1
+        if mlp.bf16_storage and mlp._bf16_version != mlp.flat._version:
+            mlp.sync_bf16()  # the FP32 parameters were written from outside
+        feats = feats.to(torch.float32).contiguous()
+        loads = loads.to(torch.float64).contiguous()
+        _check(lib().prox_train_step(self.pen.model.handle, ctypes.byref(mlp.desc()), _p(feats), _p(loads), B,
+                                     float(self.squash.va_span), float(self.pen.rho), float(self.pen.obj_scale),
+                                     float(lr), 0.9, 0.999, 1e-8, _p(ws), ws.numel(), _p(lb), _p(cv), _stream()))
+        self.pen.last = {"x": None, "f": None, "c": None, "cvio": cv}
+        return lb.mean()
 
     def predict(self, loads, feats):
         """(x with p, q := flows, largest violation per sample) under no grad."""

@@ -311,6 +311,36 @@ def test_adam_with_device_step_count_vs_oracle(dev, P):
     np.testing.assert_array_equal(pb.float().cpu().numpy(), MO.bf16_round(tp_.cpu().numpy()))
 
 
+def test_adam_vector_and_scalar_forms_agree(dev, P):
+    """prox_adam_dev takes 16-byte accesses when every buffer allows them
+    and the one-parameter kernel otherwise (here: buffers one element off
+    alignment); both give the same bits, a ragged tail (1,003 parameters)
+    included."""
+    from paper_2510_12897_amd.opf import lib
+    n = 1003
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    init = torch.randn(n, generator=g, device=dev)
+    bufs = []
+    for off in (0, 1):  # off = 1: storage 4 bytes past a 16-byte boundary
+        t = [torch.zeros(n + 1, device=dev) for _ in range(3)]
+        t[0][off:off + n] = init
+        pb = torch.zeros(n + 1, dtype=torch.bfloat16, device=dev)
+        bufs.append(([x[off:off + n] for x in t], pb[off:off + n], torch.zeros(1, dtype=torch.int32, device=dev)))
+    for t in range(3):
+        grad = torch.randn(n, generator=g, device=dev)
+        for (p_, m1, m2), pb, step in bufs:
+            gg = torch.zeros(n + 1, device=dev)
+            gv = gg[1:] if p_.data_ptr() % 16 else gg[:n]
+            gv.copy_(grad)
+            assert lib().prox_adam_dev(P._p(p_), P._p(gv), P._p(m1), P._p(m2), n, 1e-2, 0.9, 0.999, 1e-8,
+                                       P._p(step), P._p(pb), P._stream()) == 0
+    torch.cuda.synchronize()
+    (a, b) = bufs
+    for x, y in zip(a[0] + [a[1], a[2]], b[0] + [b[1], b[2]]):
+        assert torch.equal(x, y)
+
+
 def _case(N=14, L=20, G=6, seed=5):
     return synth.network(N, L, G, seed)
 
@@ -748,6 +778,70 @@ def test_fused_loss_model_conditions(dev, P):
     pen = P.Penalty(big, 2)
     assert not pen.fused
     pen.close()
+
+
+def _twin_proxies(P, case, B, width, depth, bf16):
+    out = []
+    for native in (True, False):
+        px = P.WarmStartProxy(case, B=B, width=width, depth=depth, rho=3.0, obj_scale=2e-3, seed=4)
+        if not bf16:
+            px.mlp = P.MLP(2 * px.N, 2 * px.N + 2 * px.G, width=width, depth=depth, seed=4, bf16_storage=False)
+        px.native = native
+        out.append(px)
+    return out
+
+
+@pytest.mark.parametrize("width,bf16", [(64, True), (64, False), (68, True)])
+def test_native_training_step_equals_the_autograd_step(dev, P, width, bf16):
+    """prox_train_step (every launch of a step issued by the library)
+    against the autograd path (the same kernels called one by one): the
+    mean loss of every step and, after three steps, the parameters, their
+    BF16 copy, Adam's moments and step count, bit for bit.  Width 68 takes
+    the dh product without the fused GELU backward (68 is not a multiple of
+    8) and FP32 hidden activations."""
+    case = _case(N=14, L=20, G=6, seed=9)
+    a, b = _twin_proxies(P, case, 64, width, 2, bf16)
+    gen = torch.Generator(device=dev)
+    for step in range(3):
+        gen.manual_seed(100 + step)
+        loads, feats = a.sample(gen)
+        la = a.train_step(loads, feats, lr=1e-3)
+        lb = b.train_step(loads, feats, lr=1e-3)
+        assert a.mlp.flat.grad is None and b.mlp.flat.grad is None
+        assert torch.equal(la, lb), (step, float(la), float(lb))
+    torch.cuda.synchronize()
+    for t0, t1 in ((a.mlp.flat.detach(), b.mlp.flat.detach()), (a.mlp.m1, b.mlp.m1), (a.mlp.m2, b.mlp.m2),
+                   (a.mlp.step_dev, b.mlp.step_dev)):
+        assert torch.equal(t0, t1)
+    if bf16:
+        assert torch.equal(a.mlp.flat_bf16, b.mlp.flat_bf16)
+    assert int(a.mlp.step_dev) == 3 and a.mlp.step == 3
+    a.close()
+    b.close()
+
+
+def test_native_training_step_at_benchmark_size(dev, P):
+    """The benchmarked proxy (300 buses, MLP 600 -> 3 x 1024 -> 720, 4,096
+    samples): two native steps equal two autograd steps bit for bit, and
+    the native step refuses a workspace that is too small."""
+    from paper_2510_12897_amd.opf import OPFError, _check, lib
+    case = synth.network(300, 410, 60, 41)
+    a, b = _twin_proxies(P, case, 4096, 1024, 3, True)
+    gen = torch.Generator(device=dev)
+    for step in range(2):
+        gen.manual_seed(7 + step)
+        loads, feats = a.sample(gen)
+        assert torch.equal(a.train_step(loads, feats), b.train_step(loads, feats))
+    torch.cuda.synchronize()
+    assert torch.equal(a.mlp.flat.detach(), b.mlp.flat.detach())
+    assert torch.equal(a.mlp.m2, b.mlp.m2)
+    _, ws, lb, cv = a._ws
+    with pytest.raises(OPFError, match="work holds"):
+        _check(lib().prox_train_step(a.pen.model.handle, P.ctypes.byref(a.mlp.desc()), P._p(feats),
+                                     P._p(loads), 4096, 0.3, 3.0, 2e-3, 1e-3, 0.9, 0.999, 1e-8, P._p(ws),
+                                     ws.numel() - 256, P._p(lb), P._p(cv), P._stream()))
+    a.close()
+    b.close()
 
 
 def test_trained_proxy_gains_over_flat_start(dev, P):
