@@ -585,11 +585,15 @@ def bench_proxy(args, torch, synth, log):
     out = dict(workload="300 buses, 410 branches, 60 generators; MLP 600-1024x3-720 GELU, BF16 MFMA; "
                         "batches of 4096 loads (+-30 % uniform)",
                train_steps=steps, ms_per_train_step=train_s * 1e3, loss_first=first, loss_last=last,
-               ms_split={**split, "note": "each part timed on its own over 20 repetitions; mlp_fwd_bwd = the "
-                                          "matrix-core GEMMs with their GELU and bias-sum kernels, loss_fwd_bwd = "
-                                          "the FP64 side: with fused_loss, one launch (squashing, flows, rows, "
-                                          "penalty, d loss / d z in LDS) and the gradient scaling; else squash, "
-                                          "flows, batch evaluation, penalty, J^T W, squash backward"},
+               ms_split={**split, "note": "each part issued from Python through the autograd path and timed on "
+                                          "its own over 20 repetitions, so a part whose host issue outlasts its "
+                                          "GPU work is host-bound here (the training step issues everything in "
+                                          "one library call); mlp_fwd_bwd = the matrix-core GEMMs with their "
+                                          "GELU and bias-sum kernels, loss_fwd_bwd = the FP64 side: with "
+                                          "fused_loss, one launch (squashing, flows, rows, penalty, d loss / d z "
+                                          "in LDS) and the gradient scaling; else squash, flows, batch "
+                                          "evaluation, penalty, J^T W, squash backward"},
+               native_step=bool(px.native and px.pen.fused),
                fused_loss=bool(px.pen.fused),
                inferences_per_s=B / infer_s, mlp_forward_tflops=mlp_tflops, mlp_peak_tflops=2500.0,
                heldout_cvio_mean=float(cvp.mean()), heldout_cvio_max=float(cvp.max()),

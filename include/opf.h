@@ -537,6 +537,15 @@ int prox_loss_fused_fits(opf_model model);
  * loss under an incoming gradient wb [B] (device FP64). */
 int prox_scale_rows(const double *gz, const double *wb, int B, int D, float *dz, void *stream);
 
+/* The proxy's synthetic training samples (a uniform spread of every bus's
+ * load around the base case): from uniform draws r [B, N] in [0, 1), bus i
+ * of sample b has both pd and qd scaled by 1 + spread (2 r[b, i] - 1);
+ * loads [B, 2N] (FP64, pd then qd) = base [2N] times that factor, feats
+ * [B, 2N] (FP32) = (loads - base) * inv_scale [2N].  Each operation rounds
+ * as written (no contraction).  Device buffers the caller owns. */
+int prox_sample_loads(const double *r, const double *base, const double *inv_scale, double spread, int B, int N,
+                      double *loads, float *feats, void *stream);
+
 /* The proxy MLP's parameters and optimizer state, all device memory the
  * caller owns: n_layers layers of widths dims[0..n_layers] (host array,
  * multiples of 4), GELU after every layer but the last.  flat holds per

@@ -445,6 +445,14 @@ int prox_loss_fused(opf_model model, const float* z, int B, double va_span, cons
                     "prox_loss_fused launch");
 }
 
+int prox_sample_loads(const double* r, const double* base, const double* inv_scale, double spread, int B, int N,
+                      double* loads, float* feats, void* stream) {
+    if (B < 1 || N < 1 || !r || !base || !inv_scale || !loads || !feats) return set_err(OPF_E_ARG, "bad arguments");
+    return launched(opf::prox_sample_loads(r, base, inv_scale, spread, B, N, loads, feats,
+                                           static_cast<hipStream_t>(stream)),
+                    "prox_sample_loads launch");
+}
+
 int prox_scale_rows(const double* gz, const double* wb, int B, int D, float* dz, void* stream) {
     if (B < 1 || D < 1 || !gz || !wb || !dz) return set_err(OPF_E_ARG, "bad arguments");
     return launched(opf::prox_scale_rows(gz, wb, 0.0, B, D, dz, static_cast<hipStream_t>(stream)),

@@ -87,6 +87,10 @@ size_t prox_loss_fused_lds(int N, int L, int G);
 hipError_t prox_loss_fused(const DevModel& m, const ProxBox& box, const ProxRows& rows, const ProxPerm& pm,
                            const float* z, const double* loads, int B, double rho, double obj_scale, double* loss,
                            double* cvio, double* gz, double* X, double* C, hipStream_t s);
+// loads [B, 2N] and FP32 features [B, 2N] of the proxy's samples from
+// uniform draws r [B, N] (prox_sample_loads)
+hipError_t prox_sample_loads(const double* r, const double* base, const double* inv_scale, double spread, int B,
+                             int N, double* loads, float* feats, hipStream_t s);
 // dz [B, D] = (float)(w * gz[b, j]) and part [ceil(B / 128), D] = the first
 // pass of dz's column sums (prox_colsum's)
 hipError_t prox_scale_colsum(const double* gz, double w, int B, int D, float* dz, float* part, hipStream_t s);

@@ -870,6 +870,26 @@ __global__ void vjp_sum_kernel(const double* __restrict__ X, const double* __res
     gX[idx] = g;
 }
 
+// The proxy's training samples from uniform draws r [B, N] in [0, 1): bus
+// i's pd and qd both scaled by 1 + spread (2 r - 1); loads [B, 2N] (pd then
+// qd) and the network's features (loads - base) * inv_scale as FP32.  The
+// operations of the host formula one by one, uncontracted.
+__global__ void sample_loads_kernel(const double* __restrict__ r, const double* __restrict__ base,
+                                    const double* __restrict__ inv_scale, double spread, int B, int N,
+                                    double* __restrict__ loads, float* __restrict__ feats) {
+#pragma clang fp contract(off)
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)B * 2 * N;
+    if (idx >= tot) return;
+    const int64_t b = idx / (2 * N);
+    const int j = (int)(idx % (2 * N)), i = j < N ? j : j - N;
+    const double u = r[b * N + i] * 2.0 - 1.0;
+    const double fac = 1.0 + spread * u;
+    const double l = base[j] * fac;
+    loads[idx] = l;
+    feats[idx] = (float)((l - base[j]) * inv_scale[j]);
+}
+
 // ------------------------------------------------------------ fused loss
 // The whole FP64 side of the training loss in one launch, one workgroup per
 // sample, every intermediate in LDS: squashing, the arc flows p, q := F(vm,
@@ -1449,6 +1469,14 @@ hipError_t prox_loss_fused(const DevModel& m, const ProxBox& box, const ProxRows
                            double* cvio, double* gz, double* X, double* C, hipStream_t s) {
     hipLaunchKernelGGL(loss_fused_kernel, dim3(B), dim3(kFuseThreads), prox_loss_fused_lds(m.N, m.L, m.G), s, m, box,
                        rows, pm, z, loads, rho, obj_scale, loss, cvio, gz, X, C);
+    return hipGetLastError();
+}
+
+hipError_t prox_sample_loads(const double* r, const double* base, const double* inv_scale, double spread, int B,
+                             int N, double* loads, float* feats, hipStream_t s) {
+    const int64_t tot = (int64_t)B * 2 * N;
+    hipLaunchKernelGGL(sample_loads_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, r, base, inv_scale,
+                       spread, B, N, loads, feats);
     return hipGetLastError();
 }
 

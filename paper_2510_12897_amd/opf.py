@@ -174,6 +174,8 @@ def lib():
                              _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
         "prox_loss_fused_fits": ([_vp], ctypes.c_int),
         "prox_scale_rows": ([_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp], ctypes.c_int),
+        "prox_sample_loads": ([_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp],
+                              ctypes.c_int),
         "prox_train_step_bytes": ([P(MlpDesc), ctypes.c_int, _i64p], ctypes.c_int),
         "prox_train_step": ([_vp, P(MlpDesc), _vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                              ctypes.c_double, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp,

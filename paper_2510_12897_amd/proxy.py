@@ -516,6 +516,19 @@ class WarmStartProxy:
 
     # -- data: seeded +-spread uniform scalings of the base loads (one factor per bus)
     def sample(self, gen):
+        """(loads [B, 2N] FP64, features [B, 2N] FP32) from B uniform draws
+        per bus of gen (prox_sample_loads: the values of sample_reference in
+        one launch)."""
+        torch = _torch()
+        r = torch.rand(self.B, self.N, generator=gen, device=self.dev, dtype=torch.float64)
+        loads = torch.empty(self.B, 2 * self.N, dtype=torch.float64, device=self.dev)
+        feats = torch.empty(self.B, 2 * self.N, dtype=torch.float32, device=self.dev)
+        _check(lib().prox_sample_loads(_p(r), _p(self.base), _p(self.inv_scale), float(self.spread), self.B, self.N,
+                                       _p(loads), _p(feats), _stream()))
+        return loads, feats
+
+    def sample_reference(self, gen):
+        """sample as torch operations (the tests' reference)."""
         torch = _torch()
         u = torch.rand(self.B, self.N, generator=gen, device=self.dev, dtype=torch.float64) * 2.0 - 1.0
         fac = 1.0 + self.spread * torch.cat([u, u], dim=1)

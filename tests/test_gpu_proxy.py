@@ -780,6 +780,20 @@ def test_fused_loss_model_conditions(dev, P):
     pen.close()
 
 
+def test_sample_loads_equals_the_torch_formula(dev, P):
+    """prox_sample_loads gives the loads and features of the torch formula
+    on the same draws, bit for bit (300-bus network, 4,096 samples)."""
+    case = synth.network(300, 410, 60, 41)
+    px = P.WarmStartProxy(case, B=4096, width=64, depth=1, seed=2)
+    g1, g2 = torch.Generator(device=dev), torch.Generator(device=dev)
+    g1.manual_seed(11)
+    g2.manual_seed(11)
+    l1, f1 = px.sample(g1)
+    l2, f2 = px.sample_reference(g2)
+    assert torch.equal(l1, l2) and torch.equal(f1, f2)
+    px.close()
+
+
 def _twin_proxies(P, case, B, width, depth, bf16):
     out = []
     for native in (True, False):
