@@ -166,12 +166,13 @@ class MLP:
         return _MLPFunction.apply(x, self.flat, self)
 
     def desc(self):
-        """The prox_mlp_desc of this MLP (its buffers stay owned here)."""
-        if getattr(self, "_desc", None) is None:
+        """The prox_mlp_desc of this MLP (its buffers stay owned here; built
+        again whenever a buffer's address changed)."""
+        ptrs = (self.flat.data_ptr(), self.flat_bf16.data_ptr() if self.bf16_storage else None,
+                self.m1.data_ptr(), self.m2.data_ptr(), self.step_dev.data_ptr())
+        if getattr(self, "_desc", None) is None or self._desc[2] != ptrs:
             dims = (ctypes.c_int32 * len(self.dims))(*self.dims)
-            self._desc = (opf.MlpDesc(len(self.dims) - 1, dims, self.flat.data_ptr(),
-                                      self.flat_bf16.data_ptr() if self.bf16_storage else None,
-                                      self.m1.data_ptr(), self.m2.data_ptr(), self.step_dev.data_ptr()), dims)
+            self._desc = (opf.MlpDesc(len(self.dims) - 1, dims, *ptrs), dims, ptrs)
         return self._desc[0]
 
     def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
