@@ -746,6 +746,52 @@ def test_fused_loss_at_benchmark_size_matches_the_launch_chain(dev, P):
     px.close()
 
 
+def _with_isolated_bus(cs):
+    """A copy of a case with one more bus that no branch or generator touches."""
+    c = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in cs.items()}
+    for k, val in (("pd", 0.1), ("qd", 0.03), ("gs", 0.01), ("bs", 0.02), ("vmin", 0.9), ("vmax", 1.1)):
+        c[k] = np.append(c[k], val)
+    c["n_bus"] += 1
+    return c
+
+
+@pytest.mark.parametrize("name", ["hubs", "isolated"])
+def test_fused_loss_on_hub_and_isolated_networks(dev, P, name):
+    """prox_loss_fused where the bus sums are long or empty: hubs of degree
+    62-120 with a parallel branch and two generators at one bus, and a bus
+    with no branch or generator (odd bus count, through the C-ABI directly).
+    Against Squash then Penalty (the chain of launches): x bit for bit, loss
+    and Cvio to rounding, d loss / d z against the chain's autograd gradient
+    (FP32)."""
+    from helpers import hub_network
+    case = hub_network() if name == "hubs" else _with_isolated_bus(synth.network(14, 20, 6, 5))
+    N, G = case["n_bus"], case["n_gen"]
+    B, D, span = 6, 2 * N + 2 * G, 0.4
+    pen = P.Penalty(case, B, rho=5.0, obj_scale=1e-3)
+    assert pen.fused
+    g = torch.Generator(device=dev)
+    g.manual_seed(3)
+    z = torch.randn(B, D, generator=g, device=dev)
+    pd, qd = synth.perturbed_loads(case, B, 9)
+    loads = torch.as_tensor(np.concatenate([pd, qd], axis=1), device=dev)
+    loss, cvio, gz, X, C = _fused(P, pen, z, loads, span)
+    sq = P.Squash(pen.model, span)
+    tz = z.clone().requires_grad_(True)
+    pen.set_loads(loads[:, :N], loads[:, N:])
+    lref = pen(sq(tz))
+    lref.sum().backward()
+    xr, cr, vr = (pen.last[k].cpu().numpy() for k in ("x", "c", "cvio"))
+    lr = lref.detach().cpu().numpy()
+    say(f"[fused loss {name}] max rel loss diff {np.max(np.abs(loss - lr) / np.abs(lr)):.3g}")
+    assert np.array_equal(X, xr)
+    np.testing.assert_allclose(C, cr.reshape(B, -1), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(loss, lr, rtol=1e-12)
+    np.testing.assert_allclose(cvio, vr, rtol=1e-12, atol=1e-15)
+    gref = tz.grad.cpu().numpy()
+    assert np.max(np.abs(gz.astype(np.float32) - gref)) <= 1e-6 * np.max(np.abs(gref))
+    pen.close()
+
+
 def test_fused_loss_model_conditions(dev, P):
     """prox_loss_fused_fits and the refusals: multi-period and storage models
     and a network whose sample does not fit 64 KiB of LDS are refused with
