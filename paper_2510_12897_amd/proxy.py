@@ -362,7 +362,7 @@ def _make_loss_function():
     and the fused objective / squashing backward (prox_loss_bwd) backward.
     Both give the values of Squash followed by Penalty (to rounding) without
     the copy of X and the [B, n] gradient in between.  keep: also leave x and
-    c(x) of every sample in pen.last."""
+    c(x) of every sample in pen.last ("x": x only, in the one-launch form)."""
     torch = _torch()
 
     class F(torch.autograd.Function):
@@ -380,7 +380,7 @@ def _make_loss_function():
                 loads = loads.to(torch.float64).contiguous()
                 gz = torch.empty(z.shape, dtype=torch.float64, device=dev) if vjp else None
                 X = torch.empty(B, n, dtype=torch.float64, device=dev) if keep else None
-                C = torch.empty(B, m, dtype=torch.float64, device=dev) if keep else None
+                C = torch.empty(B, m, dtype=torch.float64, device=dev) if keep and keep != "x" else None
                 _check(lib().prox_loss_fused(pen.model.handle, _p(z), B, float(va_span), _p(loads), float(pen.rho),
                                              float(pen.obj_scale), _p(loss), _p(cvio), _p(gz), _p(X), _p(C),
                                              _stream()))
@@ -539,7 +539,8 @@ class WarmStartProxy:
 
     def loss(self, loads, feats, keep=False):
         """Per-sample loss [B] of the network's prediction on these loads
-        (keep: also leave x and c(x) in pen.last)."""
+        (keep: also leave x and c(x) in pen.last; "x": x only where the loss
+        runs as one launch)."""
         return _fun("loss").apply(self.mlp(feats), self, loads, keep)
 
     def loss_unfused(self, loads, feats):
@@ -592,7 +593,7 @@ class WarmStartProxy:
         """(x with p, q := flows, largest violation per sample) under no grad."""
         torch = _torch()
         with torch.no_grad():
-            self.loss(loads, feats, keep=True)
+            self.loss(loads, feats, keep="x")
         return self.pen.last["x"], self.pen.last["cvio"]
 
     def baseline(self, loads):
