@@ -571,6 +571,11 @@ class WarmStartProxy:
         torch = _torch()
         mlp = self.mlp
         B = feats.shape[0]
+        # the library reads these through raw pointers: their shapes are checked here
+        if tuple(feats.shape) != (B, mlp.dims[0]) or tuple(loads.shape) != (B, 2 * self.N):
+            raise OPFError(OPF_E_ARG, f"feats must be [B, {mlp.dims[0]}] and loads [B, {2 * self.N}]")
+        if feats.device != self.dev or loads.device != self.dev:
+            raise OPFError(OPF_E_ARG, "feats and loads must be on the proxy's device")
         if self._ws is None or self._ws[0] != B:
             nbytes = ctypes.c_int64()
             _check(lib().prox_train_step_bytes(ctypes.byref(mlp.desc()), B, ctypes.byref(nbytes)))
