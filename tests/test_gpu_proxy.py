@@ -851,16 +851,16 @@ def _twin_proxies(P, case, B, width, depth, bf16):
     return out
 
 
-@pytest.mark.parametrize("width,bf16", [(64, True), (64, False), (68, True)])
-def test_native_training_step_equals_the_autograd_step(dev, P, width, bf16):
+@pytest.mark.parametrize("width,depth,bf16", [(64, 2, True), (64, 2, False), (68, 2, True), (64, 0, True)])
+def test_native_training_step_equals_the_autograd_step(dev, P, width, depth, bf16):
     """prox_train_step (every launch of a step issued by the library)
     against the autograd path (the same kernels called one by one): the
     mean loss of every step and, after three steps, the parameters, their
     BF16 copy, Adam's moments and step count, bit for bit.  Width 68 takes
     the dh product without the fused GELU backward (68 is not a multiple of
-    8) and FP32 hidden activations."""
+    8) and FP32 hidden activations; depth 0 is a single linear layer."""
     case = _case(N=14, L=20, G=6, seed=9)
-    a, b = _twin_proxies(P, case, 64, width, 2, bf16)
+    a, b = _twin_proxies(P, case, 64, width, depth, bf16)
     gen = torch.Generator(device=dev)
     for step in range(3):
         gen.manual_seed(100 + step)
