@@ -595,11 +595,14 @@ def bench_proxy(args, torch, synth, log):
                                           "evaluation, penalty, J^T W, squash backward"},
                native_step=bool(px.native and px.pen.fused),
                fused_loss=bool(px.pen.fused),
-               inferences_per_s=B / infer_s, mlp_forward_tflops=mlp_tflops, mlp_peak_tflops=2500.0,
+               inferences_per_s=B / infer_s, mlp_forward_inferences_per_s=B / (secs_m / 10),
+               mlp_forward_tflops=mlp_tflops, mlp_peak_tflops=2500.0,
                heldout_cvio_mean=float(cvp.mean()), heldout_cvio_max=float(cvp.max()),
                x0_cvio_mean=float(cv0.mean()), flatstart_cvio_mean=float(cvf.mean()),
                fallback_tau=0.05, fallback_rate=curve[0.05],
                fallback_curve={str(k): v for k, v in curve.items()},
+               flatstart_fallback_curve={str(k): v for k, v in P.fallback_curve(cvf).items()},
+               x0_fallback_curve={str(k): v for k, v in P.fallback_curve(cv0).items()},
                fallback_definition="share of held-out samples whose Cvio (largest violation over every row and "
                                    "bound, p.u.) exceeds tau",
                beats_flatstart_rate=float(np.mean(cvp < cvf)), beats_x0_rate=float(np.mean(cvp < cv0)))
