@@ -537,35 +537,53 @@ def bench_proxy(args, torch, synth, log):
     _, cvf = px.flat_start(loads)
     cvp, cv0, cvf = cvp.cpu().numpy(), cv0.cpu().numpy(), cvf.cpu().numpy()
     curve = P.fallback_curve(cvp)
-    # the training step split into its parts, each timed on its own: the MLP
-    # forward and backward (matrix-core GEMMs, GELU, bias sums), the FP64
-    # loss node forward and backward and the Adam step
+    # the training step split into its parts: with the library-issued step,
+    # the GPU time of its phases from events on its stream (20 steps, mean);
+    # else each part issued from Python through the autograd path and timed
+    # on its own
     gen.manual_seed(99)
     loads, feats = px.sample(gen)
-    gz = torch.randn(B, px.mlp.dims[-1], device=px.dev) * 1e-3
-
-    def mlp_part():
-        px.mlp(feats).backward(gz)
-        px.mlp.flat.grad = None
-
-    z0 = px.mlp(feats).detach()
-
-    def loss_part():
-        z = z0.clone().requires_grad_(True)
-        P._fun("loss").apply(z, px, loads, False).mean().backward()
-
-    zz = px.mlp(feats)
-    zz.backward(gz)
-    g_keep = px.mlp.flat.grad.clone()
-
-    def adam_part():
-        px.mlp.flat.grad = g_keep
-        px.mlp.adam_step(lr=0.0)
-
     split = {}
-    for name, fn in (("mlp_fwd_bwd", mlp_part), ("loss_fwd_bwd", loss_part), ("adam", adam_part)):
-        secs, _ = time_steps(torch, fn, 20, 2)
-        split[name] = secs / 20 * 1e3
+    if px.native and px.pen.fused:
+        acc = {}
+        for _ in range(20):
+            _, ph = px.train_step_phases(loads, feats, lr=0.0)
+            for k, v in ph.items():
+                acc[k] = acc.get(k, 0.0) + v / 20
+        split = {"forward": acc["forward"], "loss_fwd_bwd": acc["loss"], "backward": acc["backward"],
+                 "adam": acc["adam"], "mlp_fwd_bwd": acc["forward"] + acc["backward"]}
+        split_note = ("GPU time of each phase of the library-issued step (events on its stream, mean of 20 steps): "
+                      "forward = the MLP's matrix-core products with bias and GELU; loss_fwd_bwd = the fused FP64 "
+                      "loss kernel with d loss / d z and its scaling by 1/B; backward = the weight-gradient and dh "
+                      "products with the GELU backward and bias sums; mlp_fwd_bwd = forward + backward")
+    else:
+        gz = torch.randn(B, px.mlp.dims[-1], device=px.dev) * 1e-3
+
+        def mlp_part():
+            px.mlp(feats).backward(gz)
+            px.mlp.flat.grad = None
+
+        z0 = px.mlp(feats).detach()
+
+        def loss_part():
+            z = z0.clone().requires_grad_(True)
+            P._fun("loss").apply(z, px, loads, False).mean().backward()
+
+        zz = px.mlp(feats)
+        zz.backward(gz)
+        g_keep = px.mlp.flat.grad.clone()
+
+        def adam_part():
+            px.mlp.flat.grad = g_keep
+            px.mlp.adam_step(lr=0.0)
+
+        for name, fn in (("mlp_fwd_bwd", mlp_part), ("loss_fwd_bwd", loss_part), ("adam", adam_part)):
+            secs, _ = time_steps(torch, fn, 20, 2)
+            split[name] = secs / 20 * 1e3
+        split_note = ("each part issued from Python through the autograd path and timed on its own over 20 "
+                      "repetitions (host issue included where it outlasts the GPU work); mlp_fwd_bwd = the "
+                      "matrix-core GEMMs with their GELU and bias-sum kernels, loss_fwd_bwd = the FP64 side "
+                      "(squash, flows, batch evaluation, penalty, J^T W, squash backward)")
     px.mlp.flat.grad = None
     # inference: MLP + squashing + flows + FP64 constraint evaluation + violation
     gen.manual_seed(4242)
@@ -585,14 +603,7 @@ def bench_proxy(args, torch, synth, log):
     out = dict(workload="300 buses, 410 branches, 60 generators; MLP 600-1024x3-720 GELU, BF16 MFMA; "
                         "batches of 4096 loads (+-30 % uniform)",
                train_steps=steps, ms_per_train_step=train_s * 1e3, loss_first=first, loss_last=last,
-               ms_split={**split, "note": "each part issued from Python through the autograd path and timed on "
-                                          "its own over 20 repetitions, so a part whose host issue outlasts its "
-                                          "GPU work is host-bound here (the training step issues everything in "
-                                          "one library call); mlp_fwd_bwd = the matrix-core GEMMs with their "
-                                          "GELU and bias-sum kernels, loss_fwd_bwd = the FP64 side: with "
-                                          "fused_loss, one launch (squashing, flows, rows, penalty, d loss / d z "
-                                          "in LDS) and the gradient scaling; else squash, flows, batch "
-                                          "evaluation, penalty, J^T W, squash backward"},
+               ms_split={**split, "note": split_note},
                native_step=bool(px.native and px.pen.fused),
                fused_loss=bool(px.pen.fused),
                inferences_per_s=B / infer_s, mlp_forward_inferences_per_s=B / (secs_m / 10),

@@ -580,10 +580,13 @@ int prox_train_step_bytes(const prox_mlp_desc *mlp, int B, int64_t *bytes);
  * at least prox_train_step_bytes) that the step uses as scratch; the model
  * is one prox_loss_fused takes and the MLP's output width is 2N + 2G;
  * OPF_E_ARG otherwise.  Calls on one stream run in order; concurrent calls
- * sharing a workspace race. */
+ * sharing a workspace race.  phase_ms: NULL, or a host array of 4 floats
+ * that receives the GPU time of the forward, the loss (with its gradient
+ * scaling), the backward and the Adam step, from events on the stream; the
+ * call then waits for the step to finish. */
 int prox_train_step(opf_model model, const prox_mlp_desc *mlp, const float *feats, const double *loads, int B,
                     double va_span, double rho, double obj_scale, float lr, float beta1, float beta2, float eps,
-                    void *work, int64_t work_bytes, double *loss, double *cvio, void *stream);
+                    void *work, int64_t work_bytes, double *loss, double *cvio, float *phase_ms, void *stream);
 #ifdef __cplusplus
 }
 #endif

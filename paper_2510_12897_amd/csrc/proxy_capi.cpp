@@ -149,9 +149,30 @@ int prox_train_step_bytes(const prox_mlp_desc* mlp, int B, int64_t* bytes) {
     return OPF_OK;
 }
 
+namespace {
+// GPU-side phase marks of one training step (phase_ms != NULL only)
+struct PhaseEvents {
+    hipEvent_t ev[5] = {};
+    int n = 0;
+    bool on = false;
+    explicit PhaseEvents(bool want) : on(want) {
+        if (!on) return;
+        for (; n < 5; n++)
+            if (hipEventCreate(&ev[n]) != hipSuccess) break;
+        on = n == 5;
+    }
+    void mark(int i, hipStream_t s) {
+        if (on) hipEventRecord(ev[i], s);
+    }
+    ~PhaseEvents() {
+        for (int i = 0; i < n; i++) hipEventDestroy(ev[i]);
+    }
+};
+}  // namespace
+
 int prox_train_step(opf_model model, const prox_mlp_desc* mlp, const float* feats, const double* loads, int B,
                     double va_span, double rho, double obj_scale, float lr, float beta1, float beta2, float eps,
-                    void* work, int64_t work_bytes, double* loss, double* cvio, void* stream) {
+                    void* work, int64_t work_bytes, double* loss, double* cvio, float* phase_ms, void* stream) {
     if (int rc = static_model(model)) return rc;
     if (!fused_fits(model)) return set_err(OPF_E_ARG, "the training step takes a model that prox_loss_fused takes");
     TrainPlan P;
@@ -166,6 +187,9 @@ int prox_train_step(opf_model model, const prox_mlp_desc* mlp, const float* feat
                                                       (long long)work_bytes, P.total);
     DeviceGuard dg(model->device);
     const hipStream_t s = static_cast<hipStream_t>(stream);
+    PhaseEvents pe(phase_ms != nullptr);
+    if (phase_ms && !pe.on) return set_err(OPF_E_STATE, "could not create the phase events");
+    pe.mark(0, s);
     char* W = static_cast<char*>(work);
     const float* flat = mlp->flat;
     const __bf16* fb = static_cast<const __bf16*>(mlp->flat_bf16);
@@ -187,6 +211,7 @@ int prox_train_step(opf_model model, const prox_mlp_desc* mlp, const float* feat
             h_bf16 = P.act_bf16[k];
         }
     }
+    pe.mark(1, s);
     // the loss with d loss / d z, then the mean's weight 1/B
     const float* z = reinterpret_cast<const float*>(W + P.pre[P.nl - 1]);
     double* gz = reinterpret_cast<double*>(W + P.gz);
@@ -196,6 +221,7 @@ int prox_train_step(opf_model model, const prox_mlp_desc* mlp, const float* feat
                                  loss, cvio, gz, nullptr, nullptr, s)) ||
         !ok(opf::prox_scale_colsum(gz, 1.0 / B, B, P.D, dz, reinterpret_cast<float*>(W + P.cwork), s)))
         return hip_err(e, "prox_train_step loss");
+    pe.mark(2, s);
     // backward: weight gradients (split over the batch), bias column sums and
     // the GELU backward of the layer below in the dh product
     float* gflat = reinterpret_cast<float*>(W + P.gflat);
@@ -232,9 +258,17 @@ int prox_train_step(opf_model model, const prox_mlp_desc* mlp, const float* feat
         }
         dpre = d;
     }
+    pe.mark(3, s);
     if (!ok(opf::prox_adam_dev(mlp->flat, gflat, mlp->m1, mlp->m2, P.n_params, lr, beta1, beta2, eps, mlp->step,
                                mlp->flat_bf16, s)))
         return hip_err(e, "prox_train_step Adam");
+    if (phase_ms) {
+        pe.mark(4, s);
+        if (hipError_t r = hipEventSynchronize(pe.ev[4])) return hip_err(r, "prox_train_step phase events");
+        for (int i = 0; i < 4; i++)
+            if (hipError_t r = hipEventElapsedTime(&phase_ms[i], pe.ev[i], pe.ev[i + 1]))
+                return hip_err(r, "prox_train_step phase events");
+    }
     return OPF_OK;
 }
 

@@ -179,7 +179,7 @@ def lib():
         "prox_train_step_bytes": ([P(MlpDesc), ctypes.c_int, _i64p], ctypes.c_int),
         "prox_train_step": ([_vp, P(MlpDesc), _vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                              ctypes.c_double, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp,
-                             ctypes.c_int64, _vp, _vp, _vp], ctypes.c_int),
+                             ctypes.c_int64, _vp, _vp, P(ctypes.c_float), _vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)

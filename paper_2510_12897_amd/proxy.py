@@ -567,7 +567,14 @@ class WarmStartProxy:
         self.mlp.adam_step(lr=lr)
         return loss.detach()
 
-    def _train_step_native(self, loads, feats, lr):
+    def train_step_phases(self, loads, feats, lr=3e-4):
+        """The library-issued step with the GPU time of its phases (ms):
+        (mean loss, {forward, loss, backward, adam}); waits for the step."""
+        ph = (ctypes.c_float * 4)()
+        loss = self._train_step_native(loads, feats, lr, ph)
+        return loss, dict(zip(("forward", "loss", "backward", "adam"), (float(v) for v in ph)))
+
+    def _train_step_native(self, loads, feats, lr, phases=None):
         torch = _torch()
         mlp = self.mlp
         B = feats.shape[0]
@@ -590,7 +597,8 @@ class WarmStartProxy:
         loads = loads.to(torch.float64).contiguous()
         _check(lib().prox_train_step(self.pen.model.handle, ctypes.byref(mlp.desc()), _p(feats), _p(loads), B,
                                      float(self.squash.va_span), float(self.pen.rho), float(self.pen.obj_scale),
-                                     float(lr), 0.9, 0.999, 1e-8, _p(ws), ws.numel(), _p(lb), _p(cv), _stream()))
+                                     float(lr), 0.9, 0.999, 1e-8, _p(ws), ws.numel(), _p(lb), _p(cv), phases,
+                                     _stream()))
         self.pen.last = {"x": None, "f": None, "c": None, "cvio": cv}
         return lb.mean()
 

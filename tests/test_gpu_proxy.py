@@ -899,7 +899,14 @@ def test_native_training_step_at_benchmark_size(dev, P):
     with pytest.raises(OPFError, match="work holds"):
         _check(lib().prox_train_step(a.pen.model.handle, P.ctypes.byref(a.mlp.desc()), P._p(feats),
                                      P._p(loads), 4096, 0.3, 3.0, 2e-3, 1e-3, 0.9, 0.999, 1e-8, P._p(ws),
-                                     ws.numel() - 256, P._p(lb), P._p(cv), P._stream()))
+                                     ws.numel() - 256, P._p(lb), P._p(cv), None, P._stream()))
+    # the phase times: four positive GPU durations, and the step itself unchanged
+    gen.manual_seed(20)
+    loads, feats = a.sample(gen)
+    la, ph = a.train_step_phases(loads, feats)
+    lb_ = b.train_step(loads, feats)
+    assert torch.equal(la, lb_)
+    assert set(ph) == {"forward", "loss", "backward", "adam"} and all(v > 0 for v in ph.values())
     a.close()
     b.close()
 
