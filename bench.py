@@ -749,7 +749,7 @@ def main():
             print("[bench]", *a, file=sys.stderr, flush=True)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build evaluates each model on a single MI355X "
+        print("bench.py measures one GPU: each model is evaluated on a single MI355X "
               "(multi-GPU sharding is a design note, not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

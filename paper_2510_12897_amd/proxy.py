@@ -3,10 +3,11 @@
 callback kernels compute.
 
 The paper names learned proxies for OPF as related work whose feasibility is
-the open problem (Sec. I); here the FP64 constraint evaluator is the judge:
+the open problem (Sec. I); here the FP64 constraint evaluator decides it:
 every prediction is completed (arc flows p, q := F(vm, va)) and scored by
-the constraint kernels, and a prediction whose largest violation is worse
-than the plain starting point's falls back to it.
+the constraint kernels, and a prediction whose largest violation (Cvio,
+Sec. IV-A5) exceeds a threshold tau is discarded, the solver then starting
+without it (fallback_curve gives that share for several tau).
 
 Every step runs in libopf's kernels (argument marshalling only here):
 
