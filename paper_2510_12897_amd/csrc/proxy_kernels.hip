@@ -10,9 +10,14 @@
 //    through LDS for whole-row vector stores.  128x128 or 128x64 block tile,
 //    BK = 64, four waves of 64x64 or 64x32, global loads of the next K tile
 //    overlapped with the matrix-core work on the current one.
+//  - prox_gemm_gelu_bwd: the dh product with the GELU backward of the layer
+//    below and the bias gradient's first column-sum pass in its epilogue.
+//  - the fused loss (prox_loss_fused): the whole FP64 side of a sample in one
+//    workgroup's LDS (squashing, arc flows, rows, penalty, Cvio, d loss / d z).
 //  - elementwise / reduction kernels: GELU backward, deterministic column
 //    sums (bias gradient), Adam (also with its step count on the device and
-//    a BF16 copy of the parameters), output squashing into the variable
+//    a BF16 copy of the parameters, 16-byte accesses where aligned), the
+//    samples' loads and features, output squashing into the variable
 //    bounds and its backward (also fused with the objective and loss-weight
 //    step), the penalty loss with its constraint weights, and the chain
 //    weights that carry the arc-flow gradient back to the voltages.
