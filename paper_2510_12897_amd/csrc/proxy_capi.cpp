@@ -234,12 +234,22 @@ int prox_train_step(opf_model model, const prox_mlp_desc* mlp, const float* feat
         const int fo = P.fo[k], fi = P.fi[k];
         const void* h_in = k == 0 ? (const void*)feats : (const void*)(W + P.act[k - 1]);
         const bool h_in_bf16 = k > 0 && P.act_bf16[k - 1];
-        if (!ok(opf::prox_gemm_mixed(2, dpre, d_bf16, fo, h_in, h_in_bf16, fi, gflat + P.wo[k], fi, fo, fi, B, nullptr,
-                                     nullptr, false, 0, P.splits[k], skw, s)))
-            return hip_err(e, "prox_train_step weight gradient");
-        if (!ok(parts ? opf::prox_colsum_parts(cwork, P.chunks, fo, gflat + P.bo[k], 1.0f, s)
-                      : opf::prox_colsum(static_cast<const float*>(dpre), B, fo, cwork, gflat + P.bo[k], 1.0f, s)))
-            return hip_err(e, "prox_train_step bias gradient");
+        if (P.splits[k] > 1 && parts) {
+            // the split-K parts, then their sum and the bias sums' second pass in one launch
+            if (!ok(opf::prox_gemm_split_parts(2, dpre, d_bf16, fo, h_in, h_in_bf16, fi, fo, fi, B, P.splits[k], skw,
+                                               s)) ||
+                !ok(opf::prox_wgrad_finish(skw, P.splits[k], fo, fi, gflat + P.wo[k], fi, cwork, P.chunks, fo,
+                                           gflat + P.bo[k], s)))
+                return hip_err(e, "prox_train_step weight and bias gradients");
+        } else {
+            if (!ok(opf::prox_gemm_mixed(2, dpre, d_bf16, fo, h_in, h_in_bf16, fi, gflat + P.wo[k], fi, fo, fi, B,
+                                         nullptr, nullptr, false, 0, P.splits[k], skw, s)))
+                return hip_err(e, "prox_train_step weight gradient");
+            if (!ok(parts ? opf::prox_colsum_parts(cwork, P.chunks, fo, gflat + P.bo[k], 1.0f, s)
+                          : opf::prox_colsum(static_cast<const float*>(dpre), B, fo, cwork, gflat + P.bo[k], 1.0f,
+                                             s)))
+                return hip_err(e, "prox_train_step bias gradient");
+        }
         if (k == 0) break;
         const float* pre_below = reinterpret_cast<const float*>(W + P.pre[k - 1]);
         char* d = dbuf[k & 1];

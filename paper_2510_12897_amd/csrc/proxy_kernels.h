@@ -41,6 +41,14 @@ hipError_t prox_gemm_mixed(int variant, const void* A, bool a_bf16, int lda, con
                            float* C, int ldc, int M, int N, int K, const float* bias, void* act, bool act_bf16,
                            int accumulate, int splits, float* work, hipStream_t s);
 int prox_gemm_splits(int M, int N, int K);
+// The split-K parts only (splits >= 2) of prox_gemm_mixed without bias,
+// activation or accumulation: work receives splits * M * N floats.
+hipError_t prox_gemm_split_parts(int variant, const void* A, bool a_bf16, int lda, const void* B, bool b_bf16, int ldb,
+                                 int M, int N, int K, int splits, float* work, hipStream_t s);
+// C [M, N] = the split-K parts summed in order, and bias_out [NB] = the
+// column sums of part [chunks, NB] (prox_colsum's second pass), one launch.
+hipError_t prox_wgrad_finish(const float* work, int splits, int M, int N, float* C, int ldc, const float* part,
+                             int chunks, int NB, float* bias_out, hipStream_t s);
 // out [M, N] (BF16) = (A B) * gelu'(pre) for row-major A [M, K], B [K, N]
 // (either BF16), pre [M, N]; part [ceil(M / 128), N] = the column sums of
 // each 128-row block of the FP32 product (prox_colsum's first pass).

@@ -531,6 +531,44 @@ __global__ void __launch_bounds__(256) colsum_final_kernel(const float* __restri
     if (g == 0 && j < N) out[j] = (((s[0][c] + s[1][c]) + s[2][c]) + s[3][c]) * scale;
 }
 
+// The end of a weight gradient in one launch: blocks [0, nsum) sum the
+// split-K parts into C [M, N] in part order (splitk_sum_kernel without
+// epilogue); the remaining blocks do the bias gradient's second column-sum
+// pass over part [chunks, NB] (colsum_final_kernel, scale 1).  The same
+// values as those two kernels, one launch fewer.
+__global__ void __launch_bounds__(256) wgrad_finish_kernel(const float* __restrict__ work, int splits, int M, int N,
+                                                           float* __restrict__ C, int ldc, int nsum,
+                                                           const float* __restrict__ part, int chunks, int NB,
+                                                           float* __restrict__ bias_out) {
+    if ((int)blockIdx.x < nsum) {
+        const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const int n4 = N / 4;
+        if (idx >= (int64_t)M * n4) return;
+        const int i = (int)(idx / n4), j = (int)(idx % n4) * 4;
+        const size_t mn = (size_t)M * N;
+        const float* w = work + (size_t)i * N + j;
+        float4 sv = *reinterpret_cast<const float4*>(w);
+        for (int z = 1; z < splits; z++) {
+            const float4 t = *reinterpret_cast<const float4*>(w + z * mn);
+            sv.x += t.x;
+            sv.y += t.y;
+            sv.z += t.z;
+            sv.w += t.w;
+        }
+        *reinterpret_cast<float4*>(C + (size_t)i * ldc + j) = sv;
+        return;
+    }
+    __shared__ float sg[4][64];
+    const int c = threadIdx.x % 64, g = threadIdx.x / 64;
+    const int j = ((int)blockIdx.x - nsum) * 64 + c;
+    float acc = 0.f;
+    if (j < NB)
+        for (int k = g; k < chunks; k += 4) acc += part[(size_t)k * NB + j];
+    sg[g][c] = acc;
+    __syncthreads();
+    if (g == 0 && j < NB) bias_out[j] = (((sg[0][c] + sg[1][c]) + sg[2][c]) + sg[3][c]) * 1.0f;
+}
+
 // Adam (Kingma and Ba, 2015) with bias correction; FP32 state.
 // pb (may be NULL) receives the updated parameters rounded to BF16: the
 // matrix cores' copy of the weights.
@@ -1286,7 +1324,8 @@ void launch_gemm(int variant, dim3 grid, hipStream_t s, const TA* A, int lda, co
 
 template <typename TA, typename TB, typename TACT>
 hipError_t gemm_typed(int variant, const TA* A, int lda, const TB* B, int ldb, float* C, int ldc, int M, int N, int K,
-                      const float* bias, TACT* act, int accumulate, int splits, float* work, hipStream_t s) {
+                      const float* bias, TACT* act, int accumulate, int splits, float* work, hipStream_t s,
+                      bool finish = true) {
     if (splits < 1) splits = 1;
     const int kchunk = splits == 1 ? K : ((K + splits - 1) / splits + BK - 1) / BK * BK;
     float* part = splits == 1 ? nullptr : work;
@@ -1300,7 +1339,7 @@ hipError_t gemm_typed(int variant, const TA* A, int lda, const TB* B, int ldb, f
     else
         launch_gemm<64>(variant, dim3((N + 63) / 64, my, splits), s, A, lda, B, ldb, C, ldc, M, N, K, kchunk, bias,
                         act, accumulate, part);
-    if (splits > 1) {
+    if (splits > 1 && finish) {
         const int64_t tot = (int64_t)M * (N / 4);
         hipLaunchKernelGGL(splitk_sum_kernel<TACT>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, work, splits,
                            M, N, C, ldc, bias, act, accumulate);
@@ -1311,23 +1350,23 @@ hipError_t gemm_typed(int variant, const TA* A, int lda, const TB* B, int ldb, f
 template <typename TA, typename TB>
 hipError_t gemm_act(int variant, const TA* A, int lda, const TB* B, int ldb, float* C, int ldc, int M, int N, int K,
                     const float* bias, void* act, bool act_bf16, int accumulate, int splits, float* work,
-                    hipStream_t s) {
+                    hipStream_t s, bool finish = true) {
     if (act_bf16)
         return gemm_typed(variant, A, lda, B, ldb, C, ldc, M, N, K, bias, static_cast<__bf16*>(act), accumulate, splits,
-                          work, s);
+                          work, s, finish);
     return gemm_typed(variant, A, lda, B, ldb, C, ldc, M, N, K, bias, static_cast<float*>(act), accumulate, splits,
-                      work, s);
+                      work, s, finish);
 }
 
 template <typename TA>
 hipError_t gemm_b(int variant, const TA* A, int lda, const void* B, bool b_bf16, int ldb, float* C, int ldc, int M,
                   int N, int K, const float* bias, void* act, bool act_bf16, int accumulate, int splits, float* work,
-                  hipStream_t s) {
+                  hipStream_t s, bool finish = true) {
     if (b_bf16)
         return gemm_act(variant, A, lda, static_cast<const __bf16*>(B), ldb, C, ldc, M, N, K, bias, act, act_bf16,
-                        accumulate, splits, work, s);
+                        accumulate, splits, work, s, finish);
     return gemm_act(variant, A, lda, static_cast<const float*>(B), ldb, C, ldc, M, N, K, bias, act, act_bf16,
-                    accumulate, splits, work, s);
+                    accumulate, splits, work, s, finish);
 }
 }  // namespace
 
@@ -1370,6 +1409,23 @@ hipError_t prox_gemm_mixed(int variant, const void* A, bool a_bf16, int lda, con
                       accumulate, splits, work, s);
     return gemm_b(variant, static_cast<const float*>(A), lda, B, b_bf16, ldb, C, ldc, M, N, K, bias, act, act_bf16,
                   accumulate, splits, work, s);
+}
+
+hipError_t prox_gemm_split_parts(int variant, const void* A, bool a_bf16, int lda, const void* B, bool b_bf16, int ldb,
+                                 int M, int N, int K, int splits, float* work, hipStream_t s) {
+    if (a_bf16)
+        return gemm_b(variant, static_cast<const __bf16*>(A), lda, B, b_bf16, ldb, nullptr, N, M, N, K, nullptr, nullptr,
+                      false, 0, splits, work, s, false);
+    return gemm_b(variant, static_cast<const float*>(A), lda, B, b_bf16, ldb, nullptr, N, M, N, K, nullptr, nullptr,
+                  false, 0, splits, work, s, false);
+}
+
+hipError_t prox_wgrad_finish(const float* work, int splits, int M, int N, float* C, int ldc, const float* part,
+                             int chunks, int NB, float* bias_out, hipStream_t s) {
+    const int nsum = (int)(((int64_t)M * (N / 4) + 255) / 256);
+    hipLaunchKernelGGL(wgrad_finish_kernel, dim3((unsigned)(nsum + (NB + 63) / 64)), dim3(256), 0, s, work, splits, M,
+                       N, C, ldc, nsum, part, chunks, NB, bias_out);
+    return hipGetLastError();
 }
 
 hipError_t prox_gemm(int variant, const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N,
