@@ -83,7 +83,7 @@ struct TrainPlan {
     std::vector<int> fo, fi, splits;
     std::vector<bool> w_bf16, act_bf16;
     std::vector<size_t> pre, act;                 // byte offsets of each layer's pre-activation and activation
-    size_t gz = 0, dz = 0, gflat = 0, cwork = 0, skw = 0, d0 = 0, d1 = 0, dh = 0, total = 0;
+    size_t gz = 0, dz = 0, gflat = 0, cwork = 0, skw = 0, d0 = 0, d1 = 0, dt0 = 0, dt1 = 0, dh = 0, total = 0;
     int64_t n_params = 0;
 };
 
@@ -132,6 +132,8 @@ int make_plan(const prox_mlp_desc* mlp, int B, TrainPlan& P) {
     P.skw = take(sizeof(float) * sk);
     P.d0 = take(sizeof(float) * (size_t)B * P.maxd);
     P.d1 = take(sizeof(float) * (size_t)B * P.maxd);
+    P.dt0 = take(2 * (size_t)B * P.maxd);  // BF16, dpre transposed
+    P.dt1 = take(2 * (size_t)B * P.maxd);
     P.dh = take(sizeof(float) * (size_t)B * P.maxd);
     P.total = off;
     return OPF_OK;
@@ -228,21 +230,29 @@ int prox_train_step(opf_model model, const prox_mlp_desc* mlp, const float* feat
     float* cwork = reinterpret_cast<float*>(W + P.cwork);
     float* skw = reinterpret_cast<float*>(W + P.skw);
     const void* dpre = dz;
+    const void* dpreT = nullptr;  // dpre transposed (BF16, [fo, B]) when the dh product wrote it
     bool d_bf16 = false, parts = true;  // the top layer's column sums' first pass came with dz
     char* dbuf[2] = {W + P.d0, W + P.d1};
+    char* dtbuf[2] = {W + P.dt0, W + P.dt1};
     for (int k = P.nl - 1; k >= 0; k--) {
         const int fo = P.fo[k], fi = P.fi[k];
         const void* h_in = k == 0 ? (const void*)feats : (const void*)(W + P.act[k - 1]);
         const bool h_in_bf16 = k > 0 && P.act_bf16[k - 1];
+        // dW = dpre^T h_in reads dpre k-contiguous from its transposed copy where there is one (the same
+        // products in the same order, a faster operand load)
+        const bool tr = dpreT != nullptr;
+        const int wv = tr ? 1 : 2, wlda = tr ? B : fo;
+        const void* wa = tr ? dpreT : dpre;
+        const bool wa_bf16 = tr || d_bf16;
         if (P.splits[k] > 1 && parts) {
             // the split-K parts, then their sum and the bias sums' second pass in one launch
-            if (!ok(opf::prox_gemm_split_parts(2, dpre, d_bf16, fo, h_in, h_in_bf16, fi, fo, fi, B, P.splits[k], skw,
+            if (!ok(opf::prox_gemm_split_parts(wv, wa, wa_bf16, wlda, h_in, h_in_bf16, fi, fo, fi, B, P.splits[k], skw,
                                                s)) ||
                 !ok(opf::prox_wgrad_finish(skw, P.splits[k], fo, fi, gflat + P.wo[k], fi, cwork, P.chunks, fo,
                                            gflat + P.bo[k], s)))
                 return hip_err(e, "prox_train_step weight and bias gradients");
         } else {
-            if (!ok(opf::prox_gemm_mixed(2, dpre, d_bf16, fo, h_in, h_in_bf16, fi, gflat + P.wo[k], fi, fo, fi, B,
+            if (!ok(opf::prox_gemm_mixed(wv, wa, wa_bf16, wlda, h_in, h_in_bf16, fi, gflat + P.wo[k], fi, fo, fi, B,
                                          nullptr, nullptr, false, 0, P.splits[k], skw, s)))
                 return hip_err(e, "prox_train_step weight gradient");
             if (!ok(parts ? opf::prox_colsum_parts(cwork, P.chunks, fo, gflat + P.bo[k], 1.0f, s)
@@ -254,11 +264,14 @@ int prox_train_step(opf_model model, const prox_mlp_desc* mlp, const float* feat
         const float* pre_below = reinterpret_cast<const float*>(W + P.pre[k - 1]);
         char* d = dbuf[k & 1];
         if (fi % 8 == 0) {
+            char* dt = B % 8 == 0 ? dtbuf[k & 1] : nullptr;  // the transposed copy's rows need 16-byte stores
             if (!ok(opf::prox_gemm_gelu_bwd(dpre, d_bf16, fo, weight(k), P.w_bf16[k], fi, pre_below, fi, d, fi, B, fi,
-                                            fo, cwork, s)))
+                                            fo, cwork, s, dt, B)))
                 return hip_err(e, "prox_train_step dh");
             d_bf16 = parts = true;
+            dpreT = dt;
         } else {
+            dpreT = nullptr;
             float* dh = reinterpret_cast<float*>(W + P.dh);
             if (!ok(opf::prox_gemm_mixed(1, dpre, d_bf16, fo, weight(k), P.w_bf16[k], fi, dh, fi, B, fi, fo, nullptr,
                                          nullptr, false, 0, 1, nullptr, s)) ||

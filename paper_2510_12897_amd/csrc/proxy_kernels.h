@@ -51,10 +51,12 @@ hipError_t prox_wgrad_finish(const float* work, int splits, int M, int N, float*
                              int chunks, int NB, float* bias_out, hipStream_t s);
 // out [M, N] (BF16) = (A B) * gelu'(pre) for row-major A [M, K], B [K, N]
 // (either BF16), pre [M, N]; part [ceil(M / 128), N] = the column sums of
-// each 128-row block of the FP32 product (prox_colsum's first pass).
+// each 128-row block of the FP32 product (prox_colsum's first pass); outT
+// (optional) = out transposed, [N, M] with leading dimension ldT (a
+// multiple of 8, outT 16-byte aligned).
 hipError_t prox_gemm_gelu_bwd(const void* A, bool a_bf16, int lda, const void* B, bool b_bf16, int ldb,
                               const float* pre, int ldp, void* out, int ldo, int M, int N, int K, float* part,
-                              hipStream_t s);
+                              hipStream_t s, void* outT = nullptr, int ldT = 0);
 // out [N] = scale * the column sums of part [chunks, N] (prox_colsum's second pass)
 hipError_t prox_colsum_parts(const float* part, int chunks, int N, float* out, float scale, hipStream_t s);
 hipError_t prox_gelu_bwd(const float* pre, const float* dact, float* dpre, int64_t n, hipStream_t s);

@@ -402,12 +402,16 @@ __global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const TA* __restrict
 // colsum_partial_kernel (rows g, g + 4, ... for g = 0..3, then the four
 // groups in order), so the values equal the GEMM, gelu_bwd and colsum
 // kernels in sequence bit for bit.
+// outT (may be NULL) receives d transposed, [N, M] BF16 with leading
+// dimension ldT (a multiple of 8): the k-contiguous operand of the next
+// weight-gradient product.
 template <bool A_KCONT, bool B_KCONT, typename TA, typename TB>
 __global__ void __launch_bounds__(GEMM_THREADS) gemm_gelu_bwd_kernel(const TA* __restrict__ A, int lda,
                                                                      const TB* __restrict__ B, int ldb,
                                                                      const float* __restrict__ pre, int ldp,
                                                                      __bf16* __restrict__ out, int ldo, int M, int N,
-                                                                     int K, float* __restrict__ part) {
+                                                                     int K, float* __restrict__ part,
+                                                                     __bf16* __restrict__ outT, int ldT) {
     constexpr int BN = 64, SROW = BN + 4, C4 = BN / 4;
     // the whole 128 x 64 FP32 tile (padded rows) and the column-sum groups fit the operand tiles' LDS
     static_assert(BM * SROW * 4 + 4 * 64 * 4 <= gemm_smem_bytes<BN>(), "staging tile");
@@ -443,6 +447,19 @@ __global__ void __launch_bounds__(GEMM_THREADS) gemm_gelu_bwd_kernel(const TA* _
     __syncthreads();
     const int c = threadIdx.x % 64, g = threadIdx.x / 64, j = j0 + c;
     const int rows = min(BM, M - i0);
+    if (outT && j < N) {  // 8 consecutive rows of column j per 16-byte store
+        __bf16* tcol = outT + (size_t)j * ldT + i0;
+        for (int r0 = g * 8; r0 < rows; r0 += 32) {
+            if (r0 + 8 <= rows) {
+                bf16x8 v;
+#pragma unroll
+                for (int q = 0; q < 8; q++) v[q] = to_bf16(stage[(r0 + q) * SROW + c]);
+                *reinterpret_cast<bf16x8*>(tcol + r0) = v;
+            } else {
+                for (int q = r0; q < rows; q++) tcol[q] = to_bf16(stage[q * SROW + c]);
+            }
+        }
+    }
     float s = 0.f;
     if (j < N)
         for (int r = g; r < rows; r += 4) s += stage[r * SROW + c];
@@ -1373,27 +1390,31 @@ hipError_t gemm_b(int variant, const TA* A, int lda, const void* B, bool b_bf16,
 namespace {
 template <typename TA, typename TB>
 hipError_t gelu_bwd_typed(const TA* A, int lda, const TB* B, int ldb, const float* pre, int ldp, __bf16* out, int ldo,
-                          int M, int N, int K, float* part, hipStream_t s) {
+                          int M, int N, int K, float* part, __bf16* outT, int ldT, hipStream_t s) {
     hipLaunchKernelGGL((gemm_gelu_bwd_kernel<true, false, TA, TB>), dim3((N + 63) / 64, (M + BM - 1) / BM, 1),
-                       dim3(GEMM_THREADS), 0, s, A, lda, B, ldb, pre, ldp, out, ldo, M, N, K, part);
+                       dim3(GEMM_THREADS), 0, s, A, lda, B, ldb, pre, ldp, out, ldo, M, N, K, part, outT, ldT);
     return hipGetLastError();
 }
 template <typename TA>
 hipError_t gelu_bwd_b(const TA* A, int lda, const void* B, bool b_bf16, int ldb, const float* pre, int ldp, __bf16* out,
-                      int ldo, int M, int N, int K, float* part, hipStream_t s) {
+                      int ldo, int M, int N, int K, float* part, __bf16* outT, int ldT, hipStream_t s) {
     if (b_bf16)
-        return gelu_bwd_typed(A, lda, static_cast<const __bf16*>(B), ldb, pre, ldp, out, ldo, M, N, K, part, s);
-    return gelu_bwd_typed(A, lda, static_cast<const float*>(B), ldb, pre, ldp, out, ldo, M, N, K, part, s);
+        return gelu_bwd_typed(A, lda, static_cast<const __bf16*>(B), ldb, pre, ldp, out, ldo, M, N, K, part, outT,
+                              ldT, s);
+    return gelu_bwd_typed(A, lda, static_cast<const float*>(B), ldb, pre, ldp, out, ldo, M, N, K, part, outT, ldT,
+                          s);
 }
 }  // namespace
 
 hipError_t prox_gemm_gelu_bwd(const void* A, bool a_bf16, int lda, const void* B, bool b_bf16, int ldb,
                               const float* pre, int ldp, void* out, int ldo, int M, int N, int K, float* part,
-                              hipStream_t s) {
+                              hipStream_t s, void* outT, int ldT) {
     __bf16* o = static_cast<__bf16*>(out);
+    __bf16* oT = static_cast<__bf16*>(outT);
     if (a_bf16)
-        return gelu_bwd_b(static_cast<const __bf16*>(A), lda, B, b_bf16, ldb, pre, ldp, o, ldo, M, N, K, part, s);
-    return gelu_bwd_b(static_cast<const float*>(A), lda, B, b_bf16, ldb, pre, ldp, o, ldo, M, N, K, part, s);
+        return gelu_bwd_b(static_cast<const __bf16*>(A), lda, B, b_bf16, ldb, pre, ldp, o, ldo, M, N, K, part, oT, ldT,
+                          s);
+    return gelu_bwd_b(static_cast<const float*>(A), lda, B, b_bf16, ldb, pre, ldp, o, ldo, M, N, K, part, oT, ldT, s);
 }
 
 hipError_t prox_colsum_parts(const float* part, int chunks, int N, float* out, float scale, hipStream_t s) {
