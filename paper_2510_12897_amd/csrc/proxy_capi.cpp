@@ -83,7 +83,7 @@ struct TrainPlan {
     std::vector<int> fo, fi, splits;
     std::vector<bool> w_bf16, act_bf16;
     std::vector<size_t> pre, act;                 // byte offsets of each layer's pre-activation and activation
-    size_t gz = 0, dz = 0, gflat = 0, cwork = 0, skw = 0, d0 = 0, d1 = 0, dt0 = 0, dt1 = 0, dh = 0, total = 0;
+    size_t dz = 0, gflat = 0, cwork = 0, skw = 0, d0 = 0, d1 = 0, dt0 = 0, dt1 = 0, dh = 0, total = 0;
     int64_t n_params = 0;
 };
 
@@ -125,7 +125,6 @@ int make_plan(const prox_mlp_desc* mlp, int B, TrainPlan& P) {
     }
     P.n_params = par;
     P.D = mlp->dims[P.nl];
-    P.gz = take(sizeof(double) * (size_t)B * P.D);
     P.dz = take(sizeof(float) * (size_t)B * P.D);
     P.gflat = take(sizeof(float) * (size_t)par);
     P.cwork = take(sizeof(float) * (size_t)P.chunks * P.maxd);
@@ -216,12 +215,13 @@ int prox_train_step(opf_model model, const prox_mlp_desc* mlp, const float* feat
     pe.mark(1, s);
     // the loss with d loss / d z, then the mean's weight 1/B
     const float* z = reinterpret_cast<const float*>(W + P.pre[P.nl - 1]);
-    double* gz = reinterpret_cast<double*>(W + P.gz);
     float* dz = reinterpret_cast<float*>(W + P.dz);
     const opf::ProxPerm pm{model->he_pos, model->gen_pos};
+    // d loss / d z scaled by the mean's 1/B and rounded to FP32 by the loss kernel itself, then the top
+    // layer's bias sums' first pass over it
     if (!ok(opf::prox_loss_fused(model->dm, box_of(model, va_span), rows_of(model), pm, z, loads, B, rho, obj_scale,
-                                 loss, cvio, gz, nullptr, nullptr, s)) ||
-        !ok(opf::prox_scale_colsum(gz, 1.0 / B, B, P.D, dz, reinterpret_cast<float*>(W + P.cwork), s)))
+                                 loss, cvio, nullptr, nullptr, nullptr, s, dz, 1.0 / B)) ||
+        !ok(opf::prox_colsum_first(dz, B, P.D, reinterpret_cast<float*>(W + P.cwork), s)))
         return hip_err(e, "prox_train_step loss");
     pe.mark(2, s);
     // backward: weight gradients (split over the batch), bias column sums and

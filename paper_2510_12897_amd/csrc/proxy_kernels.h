@@ -61,6 +61,8 @@ hipError_t prox_gemm_gelu_bwd(const void* A, bool a_bf16, int lda, const void* B
 hipError_t prox_colsum_parts(const float* part, int chunks, int N, float* out, float scale, hipStream_t s);
 hipError_t prox_gelu_bwd(const float* pre, const float* dact, float* dpre, int64_t n, hipStream_t s);
 hipError_t prox_colsum(const float* X, int M, int N, float* part, float* out, float scale, hipStream_t s);
+// prox_colsum's first pass only: part [ceil(M / 128), N]
+hipError_t prox_colsum_first(const float* X, int M, int N, float* part, hipStream_t s);
 hipError_t prox_adam(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2, float eps,
                      int step, void* pb, hipStream_t s);
 hipError_t prox_adam_dev(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2,
@@ -94,9 +96,11 @@ struct ProxPerm {
     const int32_t* gen_pos;  // [G] position of generator k in the bus-ordered generator list
 };
 size_t prox_loss_fused_lds(int N, int L, int G);
+// dz (optional, in place of gz) = (float)(w * d loss_b / d z_b).
 hipError_t prox_loss_fused(const DevModel& m, const ProxBox& box, const ProxRows& rows, const ProxPerm& pm,
                            const float* z, const double* loads, int B, double rho, double obj_scale, double* loss,
-                           double* cvio, double* gz, double* X, double* C, hipStream_t s);
+                           double* cvio, double* gz, double* X, double* C, hipStream_t s, float* dz = nullptr,
+                           double w = 0.0);
 // loads [B, 2N] and FP32 features [B, 2N] of the proxy's samples from
 // uniform draws r [B, N] (prox_sample_loads)
 hipError_t prox_sample_loads(const double* r, const double* base, const double* inv_scale, double spread, int B,

@@ -1086,7 +1086,8 @@ __global__ void __launch_bounds__(kFuseThreads) loss_fused_kernel(DevModel m, Pr
                                                                   const double* __restrict__ loads, double rho,
                                                                   double obj_scale, double* __restrict__ loss,
                                                                   double* __restrict__ cvio, double* __restrict__ gz,
-                                                                  double* __restrict__ X, double* __restrict__ C) {
+                                                                  double* __restrict__ X, double* __restrict__ C,
+                                                                  float* __restrict__ dz, double w) {
 #pragma clang fp contract(off)
     extern __shared__ double lds[];
     const int N = m.N, L = m.L, G = m.G, D = 2 * N + 2 * G;
@@ -1220,7 +1221,7 @@ __global__ void __launch_bounds__(kFuseThreads) loss_fused_kernel(DevModel m, Pr
         loss[b] = rho * P + obj_scale * F;
         cvio[b] = V;
     }
-    if (!gz) return;
+    if (!gz && !dz) return;
 
     // branches: d loss / d arc without the balance rows, in place of each
     // branch's own arc values; then with the balance rows, carried through
@@ -1251,7 +1252,14 @@ __global__ void __launch_bounds__(kFuseThreads) loss_fused_kernel(DevModel m, Pr
         s_hq[ht] = tpf * f.pf.Fw + tqf * f.qf.Fw + tpt * f.pt.Fw + tqt * f.qt.Fw;
     }
     __syncthreads();
-    double* gzb = gz + b * D;
+    // d loss / d z in FP64, or (dz) as (float)(w * d loss / d z): the scaling
+    // pass's value written here directly
+    auto put = [&](int j, double v) {
+        if (dz)
+            dz[b * D + j] = (float)(w * v);
+        else
+            gz[b * D + j] = v;
+    };
     for (int i = tid; i < N; i += kFuseThreads) {
         const int h0 = m.adj_ptr[i], h1 = m.adj_ptr[i + 1];
         const double gs = m.gs[i], bs = m.bs[i];
@@ -1265,17 +1273,17 @@ __global__ void __launch_bounds__(kFuseThreads) loss_fused_kernel(DevModel m, Pr
         const double vm = s_vm[i];
         gm += 2.0 * gs * vm * s_wb[i] - 2.0 * bs * vm * s_wb[N + i];
         const double s = s_act[i];
-        gzb[i] = gm * span_v * s * (1.0 - s);
+        put(i, gm * span_v * s * (1.0 - s));
         const double t = s_act[N + i];
-        gzb[N + i] = ref ? 0.0 : ga * box.va_span * (1.0 - t * t);
+        put(N + i, ref ? 0.0 : ga * box.va_span * (1.0 - t * t));
     }
     for (int k = tid; k < G; k += kFuseThreads) {
         const int bus = m.gen_bus[k], q = pm.gen_pos[k];
         const double gp = -s_wb[bus] + obj_scale * (2.0 * m.c2[k] * s_pg[q] + m.c1[k]);
         const double gq = -s_wb[N + bus];
         const double sp = s_act[2 * N + k], sq = s_act[2 * N + G + k];
-        gzb[2 * N + k] = gp * (box.pmax[k] - box.pmin[k]) * sp * (1.0 - sp);
-        gzb[2 * N + G + k] = gq * (box.qmax[k] - box.qmin[k]) * sq * (1.0 - sq);
+        put(2 * N + k, gp * (box.pmax[k] - box.pmin[k]) * sp * (1.0 - sp));
+        put(2 * N + G + k, gq * (box.qmax[k] - box.qmin[k]) * sq * (1.0 - sq));
     }
 }
 
@@ -1461,6 +1469,12 @@ hipError_t prox_gelu_bwd(const float* pre, const float* dact, float* dpre, int64
     return hipGetLastError();
 }
 
+hipError_t prox_colsum_first(const float* X, int M, int N, float* part, hipStream_t s) {
+    const int chunks = (M + COLSUM_ROWS - 1) / COLSUM_ROWS;
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3((N + 63) / 64, chunks), dim3(256), 0, s, X, M, N, part);
+    return hipGetLastError();
+}
+
 hipError_t prox_colsum(const float* X, int M, int N, float* part, float* out, float scale, hipStream_t s) {
     const int chunks = (M + COLSUM_ROWS - 1) / COLSUM_ROWS;
     hipLaunchKernelGGL(colsum_partial_kernel, dim3((N + 63) / 64, chunks), dim3(256), 0, s, X, M, N, part);
@@ -1548,9 +1562,9 @@ size_t prox_loss_fused_lds(int N, int L, int G) {
 
 hipError_t prox_loss_fused(const DevModel& m, const ProxBox& box, const ProxRows& rows, const ProxPerm& pm,
                            const float* z, const double* loads, int B, double rho, double obj_scale, double* loss,
-                           double* cvio, double* gz, double* X, double* C, hipStream_t s) {
+                           double* cvio, double* gz, double* X, double* C, hipStream_t s, float* dz, double w) {
     hipLaunchKernelGGL(loss_fused_kernel, dim3(B), dim3(kFuseThreads), prox_loss_fused_lds(m.N, m.L, m.G), s, m, box,
-                       rows, pm, z, loads, rho, obj_scale, loss, cvio, gz, X, C);
+                       rows, pm, z, loads, rho, obj_scale, loss, cvio, gz, X, C, dz, w);
     return hipGetLastError();
 }
 

@@ -28,10 +28,10 @@ def test_train_step_workspace_grows_with_the_batch():
     rc1, b1 = _bytes(dims, 4096)
     rc2, b2 = _bytes(dims, 8192)
     assert rc1 == rc2 == 0
-    # at least the FP32 pre-activations, the FP64 loss gradient and the
+    # at least the FP32 pre-activations, the FP32 loss gradient and the
     # parameter gradient of a 4,096-sample step
     n_params = sum(fo * fi + fo for fi, fo in zip(dims[:-1], dims[1:]))
-    assert b1 >= 4 * 4096 * sum(dims[1:]) + 8 * 4096 * 720 + 4 * n_params
+    assert b1 >= 4 * 4096 * sum(dims[1:]) + 4 * 4096 * 720 + 4 * n_params
     assert b2 > b1 and b1 % 256 == 0
 
 
