@@ -105,9 +105,6 @@ hipError_t prox_loss_fused(const DevModel& m, const ProxBox& box, const ProxRows
 // uniform draws r [B, N] (prox_sample_loads)
 hipError_t prox_sample_loads(const double* r, const double* base, const double* inv_scale, double spread, int B,
                              int N, double* loads, float* feats, hipStream_t s);
-// dz [B, D] = (float)(w * gz[b, j]) and part [ceil(B / 128), D] = the first
-// pass of dz's column sums (prox_colsum's)
-hipError_t prox_scale_colsum(const double* gz, double w, int B, int D, float* dz, float* part, hipStream_t s);
 // dz [B, D] = (float)(w_b * gz[b, j]), w_b = wb[b] or, with wb NULL, w
 hipError_t prox_scale_rows(const double* gz, const double* wb, double w, int B, int D, float* dz, hipStream_t s);
 

@@ -1287,26 +1287,6 @@ __global__ void __launch_bounds__(kFuseThreads) loss_fused_kernel(DevModel m, Pr
     }
 }
 
-// dz [B, D] = (float)(w * gz) and the first pass of dz's column sums
-// (colsum_partial_kernel's chunks, rows and order), in one pass over gz.
-__global__ void __launch_bounds__(256) scale_colsum_kernel(const double* __restrict__ gz, double w, int B, int D,
-                                                           float* __restrict__ dz, float* __restrict__ part) {
-    __shared__ float sg[4][64];
-    const int c = threadIdx.x % 64, g = threadIdx.x / 64;
-    const int j = blockIdx.x * 64 + c;
-    const int i0 = blockIdx.y * COLSUM_ROWS, i1 = min(i0 + COLSUM_ROWS, B);
-    float acc = 0.f;
-    if (j < D)
-        for (int i = i0 + g; i < i1; i += 4) {
-            const float v = (float)(w * gz[(size_t)i * D + j]);
-            dz[(size_t)i * D + j] = v;
-            acc += v;
-        }
-    sg[g][c] = acc;
-    __syncthreads();
-    if (g == 0 && j < D) part[(size_t)blockIdx.y * D + j] = ((sg[0][c] + sg[1][c]) + sg[2][c]) + sg[3][c];
-}
-
 // dz [B, D] = (float)(w_b * gz[b, j]) with w_b = wb[b], or the constant w
 // when wb is NULL
 __global__ void scale_rows_kernel(const double* __restrict__ gz, const double* __restrict__ wb, double w, int B,
@@ -1573,12 +1553,6 @@ hipError_t prox_sample_loads(const double* r, const double* base, const double* 
     const int64_t tot = (int64_t)B * 2 * N;
     hipLaunchKernelGGL(sample_loads_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, r, base, inv_scale,
                        spread, B, N, loads, feats);
-    return hipGetLastError();
-}
-
-hipError_t prox_scale_colsum(const double* gz, double w, int B, int D, float* dz, float* part, hipStream_t s) {
-    hipLaunchKernelGGL(scale_colsum_kernel, dim3((D + 63) / 64, (B + COLSUM_ROWS - 1) / COLSUM_ROWS), dim3(256), 0, s,
-                       gz, w, B, D, dz, part);
     return hipGetLastError();
 }
 
