@@ -703,7 +703,8 @@ def test_fused_loss_at_benchmark_size_matches_the_launch_chain(dev, P):
     4,096 samples): prox_loss_fused against the chain of batch launches on
     the same z and loads.  x, the arc flows and the thermal and angle rows
     bit for bit; balance rows, loss and Cvio to rounding; dz (FP32) to FP32
-    rounding; two fused runs give the same bits."""
+    rounding; two fused runs give the same bits; sampled instances' x, loss
+    and Cvio against the oracle."""
     case = synth.network(300, 410, 60, 41)
     px = P.WarmStartProxy(case, B=4096, width=64, depth=1, rho=10.0, obj_scale=1e-3, seed=2)
     assert px.pen.fused
@@ -743,6 +744,15 @@ def test_fused_loss_at_benchmark_size_matches_the_launch_chain(dev, P):
     assert dl <= 1e-12
     assert torch.allclose(v1, v0, rtol=1e-12, atol=1e-15)
     assert dg <= 1e-6
+    # sampled instances against the oracle itself, at the GPU's squashed point
+    N, G = px.N, px.G
+    xs, ls, vs = x1.cpu().numpy(), l1.cpu().numpy(), v1.cpu().numpy()
+    ld = loads.cpu().numpy()
+    for b in (0, 1234, 4095):
+        ref, rv, xr = _oracle_loss(case, ld[b, :N], ld[b, N:], xs[b, :2 * N + 2 * G], 10.0, 1e-3)
+        np.testing.assert_allclose(xs[b], xr, rtol=1e-12, atol=1e-14)
+        assert ls[b] == pytest.approx(ref, rel=1e-12)
+        assert vs[b] == pytest.approx(rv, rel=1e-12, abs=1e-15)
     px.close()
 
 
