@@ -756,6 +756,44 @@ def test_fused_loss_at_benchmark_size_matches_the_launch_chain(dev, P):
     px.close()
 
 
+def test_fused_loss_gradient_at_benchmark_size_vs_oracle_differences(dev, P):
+    """d loss / d z of prox_loss_fused on the benchmarked network (300 buses,
+    410 branches, 60 generators) against central differences of the oracle's
+    loss through the oracle's squashing, on 40 sampled entries of z (every
+    block) of one sample."""
+    case = synth.network(300, 410, 60, 41)
+    N, G = case["n_bus"], case["n_gen"]
+    D, span, rho, osc = 2 * N + 2 * G, 0.3, 10.0, 1e-3
+    pen = P.Penalty(case, 1, rho=rho, obj_scale=osc)
+    rng = np.random.default_rng(31)
+    z = rng.standard_normal((1, D)).astype(np.float32)
+    pd, qd = synth.perturbed_loads(case, 1, 32)
+    loads = np.concatenate([pd, qd], axis=1)
+    _, _, gz, _, _ = _fused(P, pen, torch.as_tensor(z, device=dev), torch.as_tensor(loads, device=dev), span)
+    box = _box(case)
+
+    def oracle_loss(zz):
+        va, vm, pg, qg = MO.squash(zz[None, :], box, span)
+        return _oracle_loss(case, pd[0], qd[0], np.concatenate([va[0], vm[0], pg[0], qg[0]]), rho, osc)[0]
+
+    z64 = z[0].astype(np.float64)
+    h = 1e-6
+    noise = 16 * np.finfo(float).eps * abs(oracle_loss(z64)) / h
+    picks = np.concatenate([rng.choice(np.arange(lo, hi), 10, replace=False)
+                            for lo, hi in ((0, N), (N, 2 * N), (2 * N, 2 * N + G), (2 * N + G, D))])
+    worst = 0.0
+    for j in picks:
+        zp, zm = z64.copy(), z64.copy()
+        zp[j] += h
+        zm[j] -= h
+        fd = (oracle_loss(zp) - oracle_loss(zm)) / (2 * h)
+        err = abs(gz[0, j] - fd)
+        worst = max(worst, err)
+        assert err <= 1e-6 * max(1.0, abs(fd)) + 4 * noise, (int(j), gz[0, j], fd, noise)
+    say(f"[fused loss 300-bus] 40 entries of d loss / d z: max |gz - fd| {worst:.3g} (noise {noise:.3g})")
+    pen.close()
+
+
 def _with_isolated_bus(cs):
     """A copy of a case with one more bus that no branch or generator touches."""
     c = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in cs.items()}
