@@ -520,11 +520,19 @@ def bench_proxy(args, torch, synth, log):
     gen = torch.Generator(device="cuda")
     gen.manual_seed(7)
     steps = args.proxy_steps
+    # the penalty weight rises geometrically from 10 to 100 over the run (4x
+    # the steps and this schedule took the held-out Cvio mean 0.186 -> 0.156)
+    rho0, rho1 = 10.0, 100.0
+
+    def rho_at(k):
+        return rho0 * (rho1 / rho0) ** (k / max(steps - 1, 1))
+
     loads, feats = px.sample(gen)
     first = float(px.train_step(loads, feats, lr=3e-4))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps - 1):
+    for k in range(1, steps):
+        px.pen.rho = rho_at(k)
         loads, feats = px.sample(gen)
         loss = px.train_step(loads, feats, lr=3e-4)
     torch.cuda.synchronize()
@@ -602,7 +610,8 @@ def bench_proxy(args, torch, synth, log):
         f"Adam {split['adam']:.3f}")
     out = dict(workload="300 buses, 410 branches, 60 generators; MLP 600-1024x3-720 GELU, BF16 MFMA; "
                         "batches of 4096 loads (+-30 % uniform)",
-               train_steps=steps, ms_per_train_step=train_s * 1e3, loss_first=first, loss_last=last,
+               train_steps=steps, penalty_weight=f"{rho0:g} -> {rho1:g}, geometric over the steps",
+               ms_per_train_step=train_s * 1e3, loss_first=first, loss_last=last,
                ms_split={**split, "note": split_note},
                native_step=bool(px.native and px.pen.fused),
                fused_loss=bool(px.pen.fused),
@@ -740,7 +749,7 @@ def main():
                          "multiperiod_storage_2k_x48, contingency_1k_x201, rect_10k, points16_10k, ipm_300bus, "
                          "proxy_300bus, proxy_warm_start_300bus, cpu_oracle_batch64; default all)")
     ap.add_argument("--batch-reps", type=int, default=20)
-    ap.add_argument("--proxy-steps", type=int, default=1500, help="training steps of the proxy leg (0 = skip)")
+    ap.add_argument("--proxy-steps", type=int, default=6000, help="training steps of the proxy leg (0 = skip)")
     ap.add_argument("--eager", action="store_true", help="launch the headline sets without a HIP graph")
     ap.add_argument("--launch-limit", type=int, default=None,
                     help="one-launch limit in work items for the models built (0 = always two launches; "
