@@ -399,7 +399,10 @@ int prox_gemm_bf16_splitk(int variant, const float *A, int lda, const float *B, 
  * rounded to nearest even; C stays FP32).  For the MLP's hidden activations
  * and the BF16 copy of its weights: half the operand bytes.  A k-contiguous
  * BF16 operand needs K and its leading dimension multiples of 8 (OPF_E_ARG
- * otherwise). */
+ * otherwise).  C may be NULL when act is given, accumulate is 0 and splits
+ * is 1: act is then the only output (an MLP forward that no backward will
+ * follow needs no pre-activations); OPF_E_ARG for a NULL C otherwise.  The
+ * same rule holds for prox_gemm_bf16 and prox_gemm_bf16_splitk. */
 int prox_gemm_bf16_mixed(int variant, const void *A, int a_bf16, int lda, const void *B, int b_bf16, int ldb, float *C,
                          int ldc, int M, int N, int K, const float *bias, void *act, int act_bf16, int accumulate,
                          int splits, float *work, void *stream);

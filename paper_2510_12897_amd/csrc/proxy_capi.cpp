@@ -301,11 +301,13 @@ int gemm_checked(int variant, const void* A, bool a_bf16, int lda, const void* B
                  int ldc, int M, int N, int K, const float* bias, void* act, bool act_bf16, int accumulate, int splits,
                  float* work, void* stream, const char* what) {
     if (variant < 0 || variant > 3) return set_err(OPF_E_ARG, "variant must be 0..3");
-    if (!A || !B || !C) return set_err(OPF_E_ARG, "A, B and C must be non-NULL");
+    if (!A || !B) return set_err(OPF_E_ARG, "A and B must be non-NULL");
+    if (!C && (!act || accumulate || splits != 1))
+        return set_err(OPF_E_ARG, "C may be NULL only with act, no accumulate and one split");
     if (M < 0 || N < 0 || K < 0) return set_err(OPF_E_ARG, "negative dimension");
     if (!mult4(M) || !mult4(N) || !mult4(K) || !mult4(lda) || !mult4(ldb) || !mult4(ldc))
         return set_err(OPF_E_ARG, "dimensions and leading dimensions must be multiples of 4");
-    if (!aligned16(A) || !aligned16(B) || !aligned16(C) || (act && !aligned16(act)))
+    if (!aligned16(A) || !aligned16(B) || (C && !aligned16(C)) || (act && !aligned16(act)))
         return set_err(OPF_E_ARG, "buffers must be 16-byte aligned");
     const bool a_k = variant == 0 || variant == 1, b_k = variant == 0 || variant == 3;
     if (lda < (a_k ? K : M) || ldb < (b_k ? K : N) || ldc < N)

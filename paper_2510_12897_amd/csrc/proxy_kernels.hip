@@ -373,15 +373,17 @@ __global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel(const TA* __restrict
                 r.z += bias[j + 2];
                 r.w += bias[j + 3];
             }
-            float4* cp = reinterpret_cast<float4*>(C + (size_t)i * ldc + j);
-            if (accumulate) {
-                const float4 c0 = *cp;
-                r.x += c0.x;
-                r.y += c0.y;
-                r.z += c0.z;
-                r.w += c0.w;
+            if (C) {  // NULL: act is the only output (the host allows it without accumulate)
+                float4* cp = reinterpret_cast<float4*>(C + (size_t)i * ldc + j);
+                if (accumulate) {
+                    const float4 c0 = *cp;
+                    r.x += c0.x;
+                    r.y += c0.y;
+                    r.z += c0.z;
+                    r.w += c0.w;
+                }
+                *cp = r;
             }
-            *cp = r;
             if (act) {
                 TACT* ap = act + (size_t)i * ldc + j;
                 if constexpr (sizeof(TACT) == 2)

@@ -164,7 +164,11 @@ class MLP:
         return self.flat.detach()[bo:bo + fo]
 
     def __call__(self, x):
-        return _MLPFunction.apply(x, self.flat, self)
+        # without a backward to come (no grad mode, or nothing requiring a
+        # gradient) the hidden layers store only their activations
+        torch = _torch()
+        keep = torch.is_grad_enabled() and (x.requires_grad or self.flat.requires_grad)
+        return _MLPFunction.apply(x, self.flat, self, keep)
 
     def desc(self):
         """The prox_mlp_desc of this MLP (its buffers stay owned here; built
@@ -196,10 +200,10 @@ class _MLPFunction:
     _cls = None
 
     @classmethod
-    def apply(cls, x, flat, mlp):
+    def apply(cls, x, flat, mlp, keep=True):
         if cls._cls is None:
             cls._cls = _make_mlp_function()
-        return cls._cls.apply(x, flat, mlp)
+        return cls._cls.apply(x, flat, mlp, keep)
 
 
 def _make_mlp_function():
@@ -207,7 +211,7 @@ def _make_mlp_function():
 
     class F(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, x, flat, mlp):
+        def forward(ctx, x, flat, mlp, keep):
             x = x.contiguous()
             if x.dtype != torch.float32 or x.dim() != 2 or x.shape[1] != mlp.dims[0]:
                 raise OPFError(OPF_E_ARG, f"input must be float32 [B, {mlp.dims[0]}]")
@@ -219,7 +223,8 @@ def _make_mlp_function():
             nl = len(mlp.layout)
             for k in range(nl):
                 wo, bo, fo, fi = mlp.layout[k]
-                pre = torch.empty(Bn, fo, dtype=torch.float32, device=x.device)
+                # a hidden layer's FP32 pre-activation serves only the backward
+                pre = torch.empty(Bn, fo, dtype=torch.float32, device=x.device) if keep or k == nl - 1 else None
                 ab = k < nl - 1 and mlp.act_bf16(k)
                 act = None
                 if k < nl - 1:
@@ -279,7 +284,7 @@ def _make_mlp_function():
                     _check(lib().prox_gelu_bwd(_p(ctx.pres[k - 1]), _p(dh), _p(d), dh.numel(), _stream()))
                     parts = False
                 dpre = d
-            return None, gflat, None
+            return None, gflat, None, None
 
     return F
 

@@ -173,6 +173,12 @@ def test_gemm_bf16_storage_equals_fp32_operands(dev, P, variant, shape, splits):
         torch.cuda.synchronize()
         assert torch.equal(C2, C), (a16, b16)
         assert torch.equal(act2, act.to(torch.bfloat16)), (a16, b16)
+        if splits == 1:  # no C: the activations alone, the same values
+            act3 = torch.full((M, N), float("nan"), dtype=torch.bfloat16, device=dev)
+            P.gemm_mixed(variant, bA if a16 else tA, a16, lda, bB if b16 else tB, b16, ldb, None, N, M, N, K,
+                         bias=bias, act=act3, act_bf16=True)
+            torch.cuda.synchronize()
+            assert torch.equal(act3, act2), (a16, b16)
 
 
 def test_gemm_bf16_storage_shape_rules(dev, P):
@@ -183,6 +189,15 @@ def test_gemm_bf16_storage_shape_rules(dev, P):
         P.gemm_mixed(0, b, True, 12, a, False, 12, a, 8, 8, 8, 12)   # k-contiguous BF16 A, K = 12
     with pytest.raises(OPFError, match="multiples of 8"):
         P.gemm_mixed(0, a, False, 16, b, True, 20, a, 8, 8, 8, 16)   # k-contiguous BF16 B, ldb = 20
+    # C may be left out only when act is the output, without accumulate or splits
+    act = torch.empty(8, 8, device=dev)
+    work = torch.empty(2 * 64, device=dev)
+    with pytest.raises(OPFError, match="C may be NULL"):
+        P.gemm_mixed(0, a, False, 64, a, False, 64, None, 8, 8, 8, 8)
+    with pytest.raises(OPFError, match="C may be NULL"):
+        P.gemm_mixed(0, a, False, 64, a, False, 64, None, 8, 8, 8, 8, act=act, accumulate=True)
+    with pytest.raises(OPFError, match="C may be NULL"):
+        P.gemm_mixed(0, a, False, 64, a, False, 64, None, 8, 8, 8, 8, act=act, splits=2, work=work)
     # an i-contiguous BF16 operand takes any K that is a multiple of 4
     out = torch.empty(8, 8, device=dev)
     P.gemm_mixed(2, b, True, 8, a, False, 8, out, 8, 8, 8, 12)
@@ -250,6 +265,24 @@ def test_mlp_bf16_storage_matches_fp32_storage(dev, P):
         for net in nets:
             net.flat.mul_(0.5)
     assert torch.equal(nets[0](x), nets[1](x))
+
+
+@pytest.mark.parametrize("bf16", [True, False])
+def test_mlp_forward_without_backward_equals_the_training_forward(dev, P, bf16):
+    """A forward that no backward follows (no grad mode) skips the hidden
+    layers' FP32 pre-activations and gives the training forward's output bit
+    for bit; a training forward after it still has its gradient."""
+    torch.manual_seed(1)
+    x = torch.randn(300, 24, device=dev)
+    net = P.MLP(24, 40, width=64, depth=3, seed=5, bf16_storage=bf16)
+    with torch.no_grad():
+        net.flat.add_(0.05 * torch.randn_like(net.flat))
+        z_ng = net(x)
+    z = net(x)
+    assert z.requires_grad and not z_ng.requires_grad
+    assert torch.equal(z.detach(), z_ng)
+    z.sum().backward()
+    assert net.flat.grad is not None and bool(torch.isfinite(net.flat.grad).all())
 
 
 def test_elementwise_kernels_vs_oracle(dev, P):
