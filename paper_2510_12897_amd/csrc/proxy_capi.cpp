@@ -156,6 +156,7 @@ struct PhaseEvents {
     hipEvent_t ev[5] = {};
     int n = 0;
     bool on = false;
+    hipError_t err = hipSuccess;  // the first failed record, reported when the times are read
     explicit PhaseEvents(bool want) : on(want) {
         if (!on) return;
         for (; n < 5; n++)
@@ -163,10 +164,10 @@ struct PhaseEvents {
         on = n == 5;
     }
     void mark(int i, hipStream_t s) {
-        if (on) hipEventRecord(ev[i], s);
+        if (on && err == hipSuccess) err = hipEventRecord(ev[i], s);
     }
     ~PhaseEvents() {
-        for (int i = 0; i < n; i++) hipEventDestroy(ev[i]);
+        for (int i = 0; i < n; i++) (void)hipEventDestroy(ev[i]);  // nothing to report from a destructor
     }
 };
 }  // namespace
@@ -287,6 +288,7 @@ int prox_train_step(opf_model model, const prox_mlp_desc* mlp, const float* feat
         return hip_err(e, "prox_train_step Adam");
     if (phase_ms) {
         pe.mark(4, s);
+        if (pe.err != hipSuccess) return hip_err(pe.err, "prox_train_step phase events");
         if (hipError_t r = hipEventSynchronize(pe.ev[4])) return hip_err(r, "prox_train_step phase events");
         for (int i = 0; i < 4; i++)
             if (hipError_t r = hipEventElapsedTime(&phase_ms[i], pe.ev[i], pe.ev[i + 1]))
