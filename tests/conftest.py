@@ -11,18 +11,34 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: full-size parity cases")
 
 
-def pytest_sessionfinish(session, exitstatus):
-    """Record the strict-form violation counts of the parity checks (values
-    outside 1e-12 |v*| + 1e-14 but inside the scale-aware tolerance)."""
-    import json
-
+def _strict_totals():
     try:
         from helpers import STRICT_COUNTS
     except ImportError:
-        return
-    out = os.path.join(ROOT, "gpurun_out")
-    if STRICT_COUNTS and os.path.isdir(out):
-        tot = sum(v["strict_violations"] for v in STRICT_COUNTS.values())
-        n = sum(v["compared"] for v in STRICT_COUNTS.values())
-        with open(os.path.join(out, "parity_strict_counts.json"), "w") as fh:
-            json.dump(dict(total_strict_violations=tot, total_compared=n, cases=STRICT_COUNTS), fh, indent=1)
+        return None
+    if not STRICT_COUNTS:
+        return None
+    tot = sum(v["strict_violations"] for v in STRICT_COUNTS.values())
+    n = sum(v["compared"] for v in STRICT_COUNTS.values())
+    return tot, n, STRICT_COUNTS
+
+
+def pytest_terminal_summary(terminalreporter, exitstatus, config):
+    """Print the strict-form violation counts of the parity checks (values
+    outside 1e-12 |v*| + 1e-14 but inside the scale-aware tolerance)."""
+    t = _strict_totals()
+    if t:
+        terminalreporter.write_line(f"parity strict form: {t[0]} of {t[1]} compared values outside "
+                                    f"1e-12 |v*| + 1e-14, over {len(t[2])} cases")
+
+
+def pytest_sessionfinish(session, exitstatus):
+    """Also write those counts, per case, as JSON to the file that the
+    environment variable OPF_PARITY_RECORD names (if set)."""
+    import json
+
+    path = os.environ.get("OPF_PARITY_RECORD")
+    t = _strict_totals()
+    if t and path:
+        with open(path, "w") as fh:
+            json.dump(dict(total_strict_violations=t[0], total_compared=t[1], cases=t[2]), fh, indent=1)

@@ -92,8 +92,8 @@ def strict_violations(v, ref, rtol=RTOL, atol=ATOL) -> int:
 
 
 # Strict-form counts of the parity checks of this session, by case tag:
-# written to gpurun_out/parity_strict_counts.json at the end of the session
-# when that folder exists (tests/conftest.py).
+# printed in the session's summary and written as JSON to the file named by
+# OPF_PARITY_RECORD, if set (tests/conftest.py).
 STRICT_COUNTS = {}
 
 
